@@ -1,0 +1,248 @@
+"""CPU oracle for Spiking Neural Dedispersion -- TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of ``bench.py``
+may import this package.  The product library never loads it, and the oracle never
+loads the product library.  The arithmetic lives in ``snd_oracle.c`` (plain C, IEEE
+double); this module only marshals numpy arrays through ctypes, plus two closed-form
+noise statistics written in Python (``cascade`` and ``binary_snr``).
+
+Parity status of each function (what pins it) is recorded in the tests and the design doc.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "snd_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+BINARY, GRADED, FLOAT = 0, 1, 2
+MODES = {"binary": BINARY, "graded": GRADED, "float": FLOAT}
+_IN_U8, _IN_F32, _IN_F64 = 0, 1, 2
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (no fused multiply-add, generic x86-64)."""
+    if force or not os.path.exists(_LIB):
+        cmd = ["gcc", "-O3", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
+               "-Wall", "-Wno-unused-function", "-o", _LIB, _SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+    return _LIB
+
+
+class _Params(C.Structure):
+    _fields_ = [("mode", C.c_int32), ("cluster", C.c_int32), ("branching", C.c_int32),
+                ("k_leaf", C.c_int32), ("k_int", C.c_int32), ("cap", C.c_int32), ("root_norm", C.c_int32)]
+
+
+class _Cand(C.Structure):
+    _fields_ = [("k", C.c_int32), ("widx", C.c_int32), ("t", C.c_int64), ("snr", C.c_double),
+                ("npix", C.c_int64)]
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=True)
+        lib = C.CDLL(_LIB)
+        P = C.c_void_p
+        lib.orc_delays.argtypes = [C.c_int32, P, C.c_double, C.c_double, C.c_int32, P, P]
+        lib.orc_tree_shape.argtypes = [C.c_int32, P, C.c_int32, C.c_int32, P, C.c_int32]
+        common = [C.POINTER(_Params), C.c_int32, P, C.c_int64, P, C.c_int32, C.c_int32, P]
+        lib.orc_snd_points.argtypes = common + [C.c_int64, P, P, P]
+        lib.orc_snd_recursive.argtypes = common + [P]
+        lib.orc_snd_dedup.argtypes = common + [P, P, C.c_int32]
+        lib.orc_bruteforce.argtypes = [C.c_int32, C.c_int32, C.c_int64, P, C.c_int32, C.c_int32, P, P]
+        lib.orc_encode.argtypes = [C.c_int64, P, C.c_int32, P, P]
+        lib.orc_encode.restype = None
+        lib.orc_matched_filter.argtypes = [C.c_int32, C.c_int64, C.c_int64, P, C.c_int32, P, C.c_double,
+                                           P, P, P, P]
+        lib.orc_candidates.argtypes = [C.c_int64, C.c_int64, P, P, C.c_double, C.c_int32, C.c_int64,
+                                       C.POINTER(_Cand), C.c_int64]
+        lib.orc_candidates.restype = C.c_int64
+        _lib = lib
+    return _lib
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def _input(x: np.ndarray):
+    x = np.ascontiguousarray(x)
+    if x.dtype == np.uint8:
+        return x, _IN_U8
+    if x.dtype == np.float32:
+        return x, _IN_F32
+    return np.ascontiguousarray(x, dtype=np.float64), _IN_F64
+
+
+def delays(freqs, dms, tsamp_s: float, fref: float = 0.0) -> np.ndarray:
+    """int32 [ndm][nchan] integer channel delays in samples."""
+    lib = _load()
+    f = np.ascontiguousarray(freqs, dtype=np.float64)
+    d = np.ascontiguousarray(dms, dtype=np.float64)
+    out = np.empty((d.size, f.size), dtype=np.int32)
+    rc = lib.orc_delays(f.size, _ptr(f), tsamp_s, fref, d.size, _ptr(d), _ptr(out))
+    if rc:
+        raise ValueError("reference frequency below the highest channel frequency")
+    return out
+
+
+def tree_shape(freqs, cluster: int, branching: int) -> list:
+    lib = _load()
+    f = np.ascontiguousarray(freqs, dtype=np.float64)
+    buf = np.zeros(64, dtype=np.int32)
+    n = lib.orc_tree_shape(f.size, _ptr(f), cluster, branching, _ptr(buf), 64)
+    if n < 0:
+        raise ValueError("bad tree parameters")
+    return [int(v) for v in buf[:n]]
+
+
+def _params(mode, cluster, branching, k_leaf, k_int, cap, root_norm):
+    return _Params(MODES[mode] if isinstance(mode, str) else int(mode), cluster, branching, k_leaf, k_int, cap,
+                   int(root_norm))
+
+
+def snd_recursive(x, freqs, delay, *, mode="float", cluster=4, branching=2, k_leaf=2, k_int=2, cap=255,
+                  root_norm=False) -> np.ndarray:
+    """DM-time plane by the per-DM reference recursion (no sharing)."""
+    lib = _load()
+    xx, xt = _input(x)
+    f = np.ascontiguousarray(freqs, dtype=np.float64)
+    dl = np.ascontiguousarray(delay, dtype=np.int32)
+    nout = xx.shape[1] - int(dl.max())
+    y = np.empty((dl.shape[0], nout), dtype=np.float64)
+    p = _params(mode, cluster, branching, k_leaf, k_int, cap, root_norm)
+    rc = lib.orc_snd_recursive(C.byref(p), f.size, _ptr(f), xx.shape[1], _ptr(xx), xt, dl.shape[0], _ptr(dl), _ptr(y))
+    if rc:
+        raise ValueError("oracle recursion rejected its arguments")
+    return y
+
+
+def snd_points(x, freqs, delay, ks, ts, *, mode="float", cluster=4, branching=2, k_leaf=2, k_int=2, cap=255,
+               root_norm=False) -> np.ndarray:
+    """Selected outputs y[k_i, t_i] by the reference recursion."""
+    lib = _load()
+    xx, xt = _input(x)
+    f = np.ascontiguousarray(freqs, dtype=np.float64)
+    dl = np.ascontiguousarray(delay, dtype=np.int32)
+    k = np.ascontiguousarray(ks, dtype=np.int32)
+    t = np.ascontiguousarray(ts, dtype=np.int64)
+    out = np.empty(k.size, dtype=np.float64)
+    p = _params(mode, cluster, branching, k_leaf, k_int, cap, root_norm)
+    rc = lib.orc_snd_points(C.byref(p), f.size, _ptr(f), xx.shape[1], _ptr(xx), xt, dl.shape[0], _ptr(dl), k.size,
+                            _ptr(k), _ptr(t), _ptr(out))
+    if rc:
+        raise ValueError("oracle point query out of range")
+    return out
+
+
+def snd_dedup(x, freqs, delay, *, mode="float", cluster=4, branching=2, k_leaf=2, k_int=2, cap=255,
+              root_norm=False):
+    """(plane, counts) by the shared-pattern tree; counts[l] = (neurons, synapses) at level l."""
+    lib = _load()
+    xx, xt = _input(x)
+    f = np.ascontiguousarray(freqs, dtype=np.float64)
+    dl = np.ascontiguousarray(delay, dtype=np.int32)
+    nout = xx.shape[1] - int(dl.max())
+    y = np.empty((dl.shape[0], nout), dtype=np.float64)
+    counts = np.zeros(128, dtype=np.int64)
+    p = _params(mode, cluster, branching, k_leaf, k_int, cap, root_norm)
+    nl = lib.orc_snd_dedup(C.byref(p), f.size, _ptr(f), xx.shape[1], _ptr(xx), xt, dl.shape[0], _ptr(dl), _ptr(y),
+                           _ptr(counts), 64)
+    if nl < 0:
+        raise ValueError("oracle dedup rejected its arguments")
+    return y, [(int(counts[2 * i]), int(counts[2 * i + 1])) for i in range(nl)]
+
+
+def bruteforce(x, delay, *, mode="float") -> np.ndarray:
+    lib = _load()
+    xx, xt = _input(x)
+    dl = np.ascontiguousarray(delay, dtype=np.int32)
+    nout = xx.shape[1] - int(dl.max())
+    y = np.empty((dl.shape[0], nout), dtype=np.float64)
+    rc = lib.orc_bruteforce(MODES[mode], xx.shape[0], xx.shape[1], _ptr(xx), xt, dl.shape[0], _ptr(dl), _ptr(y))
+    if rc:
+        raise ValueError("no valid output samples")
+    return y
+
+
+def encode(z: np.ndarray, thresholds) -> np.ndarray:
+    """uint8 level = number of thresholds exceeded (z > theta), compared in float32."""
+    lib = _load()
+    zz = np.ascontiguousarray(z, dtype=np.float32)
+    th = np.ascontiguousarray(thresholds, dtype=np.float32)
+    out = np.empty(zz.shape, dtype=np.uint8)
+    lib.orc_encode(zz.size, _ptr(zz), th.size, _ptr(th), _ptr(out))
+    return out
+
+
+def matched_filter(y, widths, *, integer_plane: bool, sigma_min: float = 0.0):
+    """(snr, width_index, mu, sigma) for a DM-time plane y[ndm][nout]."""
+    lib = _load()
+    yy = np.ascontiguousarray(y, dtype=np.float64)
+    w = np.ascontiguousarray(widths, dtype=np.int32)
+    snr = np.empty(yy.shape, dtype=np.float64)
+    widx = np.empty(yy.shape, dtype=np.int32)
+    mu = np.empty(yy.shape[0], dtype=np.float64)
+    sg = np.empty(yy.shape[0], dtype=np.float64)
+    rc = lib.orc_matched_filter(int(integer_plane), yy.shape[0], yy.shape[1], _ptr(yy), w.size, _ptr(w), sigma_min,
+                                _ptr(snr), _ptr(widx), _ptr(mu), _ptr(sg))
+    if rc:
+        raise ValueError("widths must be positive and strictly increasing")
+    return snr, widx, mu, sg
+
+
+def candidates(snr, widx, theta: float, radius: int = 4, n_min: int = 10):
+    """List of dicts {k, t, widx, snr, npix}, ordered by (k, t) of the peak pixel."""
+    lib = _load()
+    s = np.ascontiguousarray(snr, dtype=np.float64)
+    w = np.ascontiguousarray(widx, dtype=np.int32)
+    cap = 1 << 16
+    buf = (_Cand * cap)()
+    n = lib.orc_candidates(s.shape[0], s.shape[1], _ptr(s), _ptr(w), theta, radius, n_min, buf, cap)
+    if n < 0:
+        raise ValueError("candidate extraction failed")
+    return [dict(k=buf[i].k, t=buf[i].t, widx=buf[i].widx, snr=buf[i].snr, npix=buf[i].npix)
+            for i in range(min(n, cap))]
+
+
+# --------------------------------------------------------------------------------------
+# Closed forms from the paper's noise analysis (Results, "Spike encoding statistics and
+# cascade noise analysis").
+# --------------------------------------------------------------------------------------
+def fire_probability(theta: float) -> float:
+    """Per-sample fire probability of the delta encoder on N(0,1) input: erfc(theta/sqrt 2)/2."""
+    return 0.5 * math.erfc(theta / math.sqrt(2.0))
+
+
+def _binom_tail(n: int, p: float, k: int) -> float:
+    """P(Bin(n, p) >= k)."""
+    if k <= 0:
+        return 1.0
+    return sum(math.comb(n, i) * p ** i * (1.0 - p) ** (n - i) for i in range(k, n + 1))
+
+
+def cascade(p0: float, fanins, k_leaf: int, k_int: int) -> list:
+    """Noise fire rate per level (Eq. cascade): p1 = P(Bin(C, p0) >= K_L),
+    p_{l+1} = P(Bin(B_l, p_l) >= K_I).  fanins = [C, B_1, ..., B_root]."""
+    rates = [_binom_tail(fanins[0], p0, k_leaf)]
+    for b in fanins[1:]:
+        rates.append(_binom_tail(b, rates[-1], k_int))
+    return rates
+
+
+def binary_snr(width: float, p_sig: float, p_noise: float) -> float:
+    """Predicted boxcar S/N of a Bernoulli root output (Eq. snr_A)."""
+    return math.sqrt(width) * (p_sig - p_noise) / math.sqrt(p_noise * (1.0 - p_noise))

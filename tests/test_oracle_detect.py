@@ -1,0 +1,119 @@
+"""Pins for the oracle's matched filter and candidate extraction."""
+
+import math
+
+import numpy as np
+import pytest
+from scipy import ndimage
+
+import synth
+
+
+def test_noise_floor_closed_forms(orc):
+    # Methods, matched filtering: with sigma_min = 0.15 a single fire in a W = 64 boxcar
+    # gives S/N ~0.8 and a cluster of ~25 fires gives ~21 (row mean ~0 on a sparse plane).
+    n = 100000
+    y = np.zeros((2, n))
+    y[0, 5000] = 1
+    y[1, 5000:5025] = 1
+    snr, widx, mu, sg = orc.matched_filter(y, [64], integer_plane=True, sigma_min=0.15)
+    assert np.all(sg == 0.15)
+    assert abs(snr[0].max() - 0.8) < 0.05
+    assert abs(snr[1].max() - 21.0) < 0.3
+    assert snr[0].argmax() == 5000 - 63
+
+
+def test_gaussian_noise_snr_statistics(orc):
+    # On N(0,1) rows the W-boxcar S/N at any fixed t is N(0,1) (sum of W unit normals scaled
+    # by sqrt(W)), so per width the mean is ~0 and the spread ~1.
+    rng = synth.make_rng(4)
+    y = rng.standard_normal((4, 20000))
+    for w in (1, 4, 16):
+        snr, _, mu, sg = orc.matched_filter(y, [w], integer_plane=False)
+        valid = snr[:, : y.shape[1] - w + 1]
+        assert abs(valid.mean()) < 0.05
+        assert abs(valid.std() - 1.0) < 0.05
+    np.testing.assert_allclose(mu, y.mean(axis=1), rtol=0, atol=1e-12)
+    np.testing.assert_allclose(sg, y.std(axis=1), rtol=1e-12)
+
+
+def test_boxcar_matched_width_is_optimal(orc):
+    # A rectangular pulse of width 8 on a quiet row peaks at its start with W = 8.
+    y = np.zeros((1, 4096))
+    rng = synth.make_rng(5)
+    y[0] = rng.standard_normal(4096) * 0.01
+    y[0, 1000:1008] += 1.0
+    snr, widx, _, _ = orc.matched_filter(y, [1, 2, 4, 8, 16, 32], integer_plane=False)
+    assert int(snr[0].argmax()) == 1000
+    assert widx[0, 1000] == 3
+    assert widx[0, -1] == 0 and widx[0, -40] >= 0  # only W = 1 fits at the last sample
+
+
+def test_constant_row_has_zero_snr(orc):
+    y = np.full((2, 300), 3.0)
+    snr, widx, mu, sg = orc.matched_filter(y, [1, 2], integer_plane=True)
+    assert np.all(snr == 0) and np.all(sg == 0) and np.all(mu == 3.0)
+    with pytest.raises(ValueError):
+        orc.matched_filter(y, [2, 2], integer_plane=True)
+
+
+def _scipy_islands(mask, r):
+    pad = 2 * r
+    m = np.pad(mask, pad)
+    se = np.ones((2 * r + 1, 2 * r + 1), bool)
+    closed = ndimage.binary_erosion(ndimage.binary_dilation(m, se), se)[pad:-pad, pad:-pad]
+    lab, n = ndimage.label(closed, structure=np.ones((3, 3), bool))
+    return lab, n
+
+
+def test_closing_merges_row_pairs_up_to_gap_nine(orc):
+    for gap, expect in ((9, 1), (10, 2)):
+        snr = np.zeros((20, 60))
+        snr[10, 20] = 8.0
+        snr[10, 20 + gap] = 9.0
+        widx = np.zeros(snr.shape, np.int32)
+        c = orc.candidates(snr, widx, 7.0, radius=4, n_min=1)
+        assert len(c) == expect
+        if expect == 1:
+            assert c[0]["npix"] == gap + 1 and c[0]["t"] == 20 + gap and c[0]["snr"] == 9.0
+
+
+def test_closing_keeps_diagonal_pairs_apart(orc):
+    for d in (2, 3, 5, 8):
+        snr = np.zeros((30, 30))
+        snr[5, 5] = 8.0
+        snr[5 + d, 5 + d] = 8.0
+        c = orc.candidates(snr, np.zeros(snr.shape, np.int32), 7.0, radius=4, n_min=1)
+        assert len(c) == 2 and all(x["npix"] == 1 for x in c)
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_candidates_match_scipy_closing_and_labelling(orc, seed):
+    rng = synth.make_rng(100 + seed)
+    snr = rng.standard_normal((40, 300)) * 2.0
+    snr[12:15, 100:140] += 9.0
+    snr[0:2, 0:5] += 9.0            # touches the plane border
+    widx = rng.integers(0, 5, size=snr.shape).astype(np.int32)
+    theta = 5.0
+    lab, n = _scipy_islands(snr >= theta, 4)
+    for n_min in (1, 10):
+        got = orc.candidates(snr, widx, theta, radius=4, n_min=n_min)
+        want = []
+        for i in range(1, n + 1):
+            pix = np.argwhere(lab == i)
+            if len(pix) < n_min:
+                continue
+            vals = snr[pix[:, 0], pix[:, 1]]
+            best = vals.max()
+            sel = pix[vals == best]
+            k, t = min(map(tuple, sel))
+            want.append(dict(k=int(k), t=int(t), widx=int(widx[k, t]), snr=float(best), npix=len(pix)))
+        want.sort(key=lambda c: (c["k"], c["t"]))
+        assert got == want
+
+
+def test_binary_snr_prediction_limits(orc):
+    # Eq. snr_A grows as sqrt(W) and vanishes when signal and noise rates are equal.
+    assert orc.binary_snr(4, 0.5, 0.1) == pytest.approx(2 * orc.binary_snr(1, 0.5, 0.1))
+    assert orc.binary_snr(16, 0.2, 0.2) == 0.0
+    assert math.isclose(orc.binary_snr(1, 1.0, 0.5), 1.0)
