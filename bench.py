@@ -1,0 +1,183 @@
+"""Benchmark of the SND hot path on one MI355X.
+
+Default workload: one Northern-Cross-shaped beam (1024 channels, 400-416 MHz, 0.138 ms,
+2^17 samples, 16 injected pulses), 4096 trial DMs uniform over 0-2000, branching factor 4,
+float32 mode.  One step = one full pass of the path over that block: the SND tree (leaf
+stage + fused upper-tree stage) followed by the boxcar S/N and candidate stage.  Inputs
+are resident in device memory before timing starts.
+
+Prints one JSON line (see the repository's benchmark contract).
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--mode", default="float", choices=["float", "graded", "binary"])
+    ap.add_argument("--node-dtype", default=None)
+    ap.add_argument("--stage-levels", type=lambda s: int(s, 0), default=0)
+    ap.add_argument("--no-detect", action="store_true", help="time the tree only")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=2048, help="output samples in the oracle's timed sample")
+    return ap.parse_args()
+
+
+def cpu_baseline(spec, mode, n_sample):
+    """The oracle's shared-pattern tree timed on the host on a bounded slice of the same beam."""
+    import numpy as np
+    import oracle
+    d = oracle.delays(spec.freqs, spec.dms, spec.tsamp_s)
+    nsamp = int(d.max()) + n_sample
+    z = spec.filterbank(nsamp)
+    x = z if mode == "float" else oracle.encode(z, [1.0, 2.0, 3.0, 4.0] if mode == "graded" else [2.0])
+    t = time.perf_counter()
+    y, _ = oracle.snd_dedup(x, spec.freqs, d, mode=mode, cluster=4, branching=spec.branching,
+                            k_leaf=2, k_int=1, cap=255)
+    dt = time.perf_counter() - t
+    return dict(value=float(spec.dms.size * n_sample / dt), unit="DM-time samples/s", cores=1, kind="oracle",
+                sample=f"shared-pattern SND tree (C, FP64, 1 thread) over all {spec.dms.size} DMs x {n_sample} "
+                       f"output samples of the same 1024-channel beam; {dt:.1f} s",
+                seconds=round(dt, 2)), np.asarray(y).shape
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build measures one GPU only; run with --gpus 1"}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_2606_15361_amd as snd
+    import synth
+
+    dev = torch.device("cuda:0")
+    spec = synth.workload(2)
+    mode = args.mode
+    log(f"[bench] generating the 1024 x {spec.nsamp} filterbank")
+    z = spec.filterbank()
+    zt = torch.from_numpy(z).to(dev)
+    if mode == "float":
+        x = zt
+    else:
+        x = snd.encode(zt, [1.0, 2.0, 3.0, 4.0] if mode == "graded" else [2.0])
+    node = args.node_dtype
+    in_dtype = None
+    if mode == "float" and node in ("bf16", "f16"):
+        in_dtype = node
+        x = snd.cast(zt, node)
+    del zt
+    plan = snd.Plan(spec.freqs, spec.dms, spec.tsamp_s, spec.nsamp, mode=mode, branching=spec.branching,
+                    cluster=spec.cluster, k_leaf=2, k_int=1, cap=255, node_dtype=node, in_dtype=in_dtype,
+                    stage_levels=args.stage_levels)
+    info = plan.info
+    log(f"[bench] plan: {info['n_neurons']} neurons, {info['n_synapses']} synapses, stages {info['stage_rows']}, "
+        f"workspace {info['workspace_bytes'] / 2**30:.2f} GiB, built in {info['build_seconds']:.2f} s")
+    plan.upload(dev)
+    ws = plan.workspace(dev)
+    out = plan.empty_output(dev)
+    detector = None
+    if not args.no_detect and hasattr(snd, "Detector"):
+        detector = snd.Detector(plan, widths=spec.widths, threshold=7.0, device=dev)
+    nst = info["n_stages"]
+    stream = torch.cuda.current_stream(dev)
+
+    def step(evs=None):
+        for s in range(nst):
+            plan.execute(x, out=out, workspace=ws, stage=s)
+            if evs is not None:
+                evs[s + 1].record(stream)
+        if detector is not None:
+            cands = detector.run(out)
+            if evs is not None:
+                evs[nst + 1].record(stream)
+            return cands
+        return None
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    nev = nst + 2
+    events = [[torch.cuda.Event(enable_timing=True) for _ in range(nev)] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ncand = 0
+    for k in range(args.steps):
+        events[k][0].record(stream)
+        c = step(events[k])
+        if c is not None:
+            ncand = len(c)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    stage_ms = np.zeros(nst)
+    det_ms = 0.0
+    for k in range(args.steps):
+        for s in range(nst):
+            stage_ms[s] += events[k][s].elapsed_time(events[k][s + 1])
+        if detector is not None:
+            det_ms += events[k][nst].elapsed_time(events[k][nst + 1])
+    stage_ms /= args.steps
+    det_ms /= args.steps
+    ms_step = wall * 1e3 / args.steps
+    samples = spec.dms.size * plan.n_out
+    value = samples / (wall / args.steps)
+    dom = int(np.argmax(stage_ms))
+    alg = info["stage_alg_bytes"][dom]
+    achieved = alg / (stage_ms[dom] * 1e-3) / 1e9
+    dtype_name = {"float": node or "f32", "graded": "u8", "binary": "u8"}[mode]
+    result = {
+        "metric": "dedispersed DM x time samples/s (1024 ch, 4096 DM) + %HBM peak; p99 chunk latency",
+        "value": value,
+        "unit": "DM-time samples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if mode == "float" and dtype_name == "f32" else dtype_name,
+        "data": "synthetic",
+        "config": {"workload": "single NC-shaped beam: 1024 ch 400-416 MHz, 0.138 ms, 2^17 samples, 16 pulses; "
+                               "4096 DMs 0-2000; B=4, C=4",
+                   "mode": mode, "node_dtype": node or ("f32" if mode == "float" else "u8"),
+                   "n_out": plan.n_out, "stages": nst, "detect": detector is not None},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": f"k_stage (stage {dom} of {nst})"},
+        "stage_ms": [round(v, 4) for v in stage_ms],
+        "stage_alg_gb": [round(b / 1e9, 3) for b in info["stage_alg_bytes"]],
+        "detect_ms": round(det_ms, 4),
+        "candidates": ncand,
+        "plan": {"neurons": info["n_neurons"], "synapses": info["n_synapses"],
+                 "workspace_gib": round(info["workspace_bytes"] / 2**30, 3)},
+    }
+    if not args.no_cpu_baseline:
+        log("[bench] timing the oracle on a bounded sample")
+        cb, _ = cpu_baseline(spec, mode, args.cpu_sample)
+        result["cpu_baseline"] = cb
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

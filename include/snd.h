@@ -1,0 +1,188 @@
+/*
+ * snd.h -- C ABI of the MI355X Spiking Neural Dedispersion (SND) library.
+ *
+ * SND (arXiv 2606.15361, Methods "The Spiking Neural Dedispersion algorithm") dedisperses
+ * a spike-encoded filterbank over an arbitrary trial-DM grid with a hierarchical
+ * delay-and-add tree: contiguous clusters of C channels form the leaves, B-ary levels
+ * combine adjacent sub-bands, and at every node the DMs that share an integer delay
+ * pattern share one "neuron" (one row of partial sums).
+ *
+ * Conventions for every entry point:
+ *   - Return value: SND_OK (0) or a negative snd_status.  Nothing throws across the ABI.
+ *     snd_last_error() returns a thread-local message for the last failure.
+ *   - "d_" pointers are device (HIP) memory owned by the caller; "h_" pointers are host
+ *     memory owned by the caller.  The library never allocates device memory.
+ *   - "stream" is a hipStream_t passed as void* (NULL = the null stream).  Device work is
+ *     enqueued asynchronously on it unless a function says it synchronises.
+ *   - Pitches are in elements of the array's own type.  Row-major [rows][pitch].
+ *   - A plan is immutable after snd_plan_create; one plan may be executed concurrently on
+ *     several streams provided each call has its own workspace.
+ */
+#ifndef SND_H
+#define SND_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SND_MAX_LEVELS 32
+#define SND_STAGE_NONE 0x80000000u
+
+typedef enum {
+    SND_OK = 0,
+    SND_ERR_INVALID = -1,     /* malformed argument or descriptor */
+    SND_ERR_UNSUPPORTED = -2, /* valid but not implemented combination (e.g. dtype/mode) */
+    SND_ERR_NOMEM = -3,       /* host allocation failed or a caller buffer is too small */
+    SND_ERR_HIP = -4,         /* a HIP runtime call failed */
+    SND_ERR_CAPACITY = -5,    /* admission beyond the configured device-memory budget */
+    SND_ERR_STATE = -6,       /* call out of order (e.g. execute before upload) */
+    SND_ERR_GAP = -7          /* streaming: a chunk index was skipped or repeated */
+} snd_status;
+
+/* Tree activation modes (Methods, "Tree activation modes"). */
+typedef enum {
+    SND_MODE_BINARY = 0, /* Mode A: node emits 1 when its active-input count >= K (K_L leaf, K_I above) */
+    SND_MODE_GRADED = 1, /* Mode B: node emits its integer sum clipped to [0, cap] */
+    SND_MODE_FLOAT = 2   /* Mode C: FP32 accumulation at every node */
+} snd_mode;
+
+typedef enum {
+    SND_DT_U8 = 1,
+    SND_DT_U16 = 2,
+    SND_DT_F32 = 3,
+    SND_DT_BF16 = 4,
+    SND_DT_F16 = 5
+} snd_dtype;
+
+/*
+ * Plan descriptor (Methods, SND: "accepts an arbitrary trial-DM grid as input and
+ * constructs a dedispersion plan").
+ *
+ * Delays: delta_c(d) = round_half_even(K_DM * d * (f_c^-2 - f_ref^-2) / tsamp_ms) with
+ * K_DM = 4.148808e6 MHz^2 ms, evaluated in FP64 as ((K_DM * d) * (1/(f_c f_c) -
+ * 1/(f_ref f_ref))) / tsamp_ms (Methods, "Incoherent dedispersion").
+ * Output: y_k(t) = tree value of DM k at reference time t, for t in [0, n_out) with
+ * n_out = nsamp - max_{k,c} delta_c(d_k); in the linear modes y_k(t) = sum_c x_c(t + delta_c(d_k)).
+ * Tree: leaves are consecutive groups of `cluster` channels, each higher level groups
+ * `branching` consecutive nodes; the last group of a level may be smaller.  A node's
+ * reference channel is its highest-frequency channel; node shifts are differences of
+ * the global channel delays.
+ */
+typedef struct {
+    int32_t nchan;           /* N_f >= 1 */
+    const double *freq_mhz;  /* [nchan] channel centre frequencies, > 0, any order (host) */
+    double tsamp_s;          /* sampling interval, > 0 */
+    double fref_mhz;         /* reference frequency; <= 0 selects max(freq); must be >= max(freq) */
+    int32_t ndm;             /* N_DM >= 1 */
+    const double *dm;        /* [ndm] trial DMs >= 0, any order, duplicates allowed (host) */
+    int32_t branching;       /* B >= 2 */
+    int32_t cluster;         /* C >= 1 */
+    int32_t mode;            /* snd_mode */
+    int32_t k_leaf;          /* binary quorum at leaves, >= 1 (ignored otherwise) */
+    int32_t k_int;           /* binary quorum at every higher node incl. the root, >= 1 */
+    int32_t cap;             /* graded clip N, 1..65535 (ignored otherwise) */
+    int32_t in_dtype;        /* input samples: U8 for binary/graded (binary: non-zero = spike);
+                                F32, BF16 or F16 for float */
+    int32_t node_dtype;      /* storage of materialised tree rows: U8 for binary; U8 (cap <= 255)
+                                or U16 for graded; F32, BF16 or F16 for float (FP32 accumulate) */
+    int32_t root_norm;       /* float: divide the output by sqrt(nchan) (Methods, Mode C) */
+    int64_t nsamp;           /* input samples per channel per execute */
+    uint32_t stage_levels;   /* bit l (l below the root level) set: tree level l is written to
+                                device memory and read by the next stage.  0 = library default
+                                (leaves only); SND_STAGE_NONE = no level written (the whole tree is
+                                evaluated from the input in one stage).  The output is identical
+                                for every choice. */
+    int32_t reserved[8];     /* must be zero */
+} snd_plan_desc;
+
+typedef struct snd_plan_s *snd_plan;
+
+typedef struct {
+    int64_t n_out;                          /* valid output samples per DM row */
+    int64_t max_delay;                      /* max_{k,c} delta_c(d_k) */
+    int32_t n_levels;                       /* tree levels, leaf .. root */
+    int32_t n_stages;                       /* kernel stages per execute */
+    int32_t out_dtype;                      /* U8 (binary, graded cap <= 255), U16, or F32 */
+    int32_t pad0;
+    int64_t n_neurons;                      /* shared-pattern neurons over all levels */
+    int64_t n_synapses;                     /* inputs of those neurons */
+    int64_t neurons_per_level[SND_MAX_LEVELS];
+    int64_t synapses_per_level[SND_MAX_LEVELS];
+    int64_t nodes_per_level[SND_MAX_LEVELS];
+    int64_t table_bytes;                    /* device bytes needed by snd_plan_upload */
+    int64_t workspace_bytes;                /* device bytes needed by snd_execute */
+    int64_t alg_bytes;                      /* algorithmic device-memory bytes of one execute:
+                                               every stage reads its source rows once and writes
+                                               its output rows once */
+    int64_t stage_alg_bytes[SND_MAX_LEVELS];/* the same per stage (last = final stage) */
+    int64_t stage_rows[SND_MAX_LEVELS];     /* output rows per stage */
+    int64_t stage_entries[SND_MAX_LEVELS];  /* (row, shift) inputs summed per stage per time sample */
+    double build_seconds;                   /* host time of snd_plan_create */
+} snd_plan_info;
+
+/* Build a plan on the host (no device work).  INVALID on a malformed descriptor (n_out <= 0,
+ * negative DM, f_ref < max frequency, B < 2, C < 1, bad quorum or cap), UNSUPPORTED for a
+ * dtype/mode pair that is not provided.  On success *out owns host tables until destroy. */
+snd_status snd_plan_create(const snd_plan_desc *desc, snd_plan *out);
+
+snd_status snd_plan_query(snd_plan plan, snd_plan_info *out);
+
+/* Copy the integer delay table int32 [ndm][nchan] into h_delays (host). */
+snd_status snd_plan_delays(snd_plan plan, int32_t *h_delays, int64_t count);
+
+/* Copy the plan's device tables into caller memory d_tables of at least table_bytes bytes
+ * (256-byte aligned) and remember that address for later executes.  Synchronises the
+ * stream.  Re-uploading moves the plan to the new address. */
+snd_status snd_plan_upload(snd_plan plan, void *d_tables, int64_t bytes, void *stream);
+
+snd_status snd_plan_destroy(snd_plan plan);
+
+/*
+ * One plain-form pass (Methods, SND; pipeline stage 2): dedisperse nsamp input samples
+ * d_in [nchan][in_pitch] (in_dtype) into d_out [ndm][out_pitch] (out_dtype), rows in the
+ * order of desc->dm, n_out valid samples per row.  d_workspace: workspace_bytes device
+ * bytes, 256-byte aligned, contents irrelevant on entry.  Asynchronous on stream.
+ * STATE before snd_plan_upload; INVALID for pitches smaller than nsamp / n_out.
+ */
+snd_status snd_execute(snd_plan plan, const void *d_in, int64_t in_pitch, void *d_out, int64_t out_pitch,
+                       void *d_workspace, int64_t workspace_bytes, void *stream);
+
+/*
+ * One stage of snd_execute (0 <= stage < n_stages), for callers that time or interleave the
+ * stages: stage 0 reads d_in, every later stage reads the workspace written by the stage
+ * before it, the last stage writes d_out.  Running stages 0 .. n_stages-1 in order on one
+ * stream is exactly snd_execute.  Same arguments and errors as snd_execute.
+ */
+snd_status snd_execute_stage(snd_plan plan, int32_t stage, const void *d_in, int64_t in_pitch, void *d_out,
+                             int64_t out_pitch, void *d_workspace, int64_t workspace_bytes, void *stream);
+
+/*
+ * Delta encoder (Methods, "Input encoding": x = 1[z > theta]).  With several thresholds the
+ * output level is the number of thresholds exceeded (thresholds compared in FP32).
+ * d_z: float32, channel-major [nchan][z_pitch] or, with time_major = 1, [nsamp][z_pitch]
+ * (one row per sample); d_out: uint8 [nchan][out_pitch] channel-major in both cases.
+ * h_thresholds: host float[nthr], 1 <= nthr <= 8.  Asynchronous on stream.
+ */
+snd_status snd_encode(const float *d_z, int64_t z_pitch, int32_t time_major, int32_t nchan, int64_t nsamp,
+                      const float *h_thresholds, int32_t nthr, uint8_t *d_out, int64_t out_pitch, void *stream);
+
+/* Float32 -> BF16 or F16 cast with round-to-nearest-even (input staging for the reduced-
+ * precision float mode).  d_src [rows][src_pitch] float32, d_dst [rows][dst_pitch] of
+ * dst_dtype.  Asynchronous on stream. */
+snd_status snd_cast(const float *d_src, int64_t src_pitch, int64_t rows, int64_t cols, void *d_dst,
+                    int64_t dst_pitch, int32_t dst_dtype, void *stream);
+
+/* Thread-local message describing the last failure in this thread ("" if none). */
+const char *snd_last_error(void);
+
+/* Library version string. */
+const char *snd_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SND_H */

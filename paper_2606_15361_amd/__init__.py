@@ -1,0 +1,12 @@
+"""MI355X-native Spiking Neural Dedispersion (SND).
+
+The compute path is libsnd.so: a C-ABI library (include/snd.h) whose plan builder runs on
+the host and whose tree, encoder and detection stages are hand-written HIP kernels for
+gfx950.  This package is the thin Python binding used by the tests and the benchmark;
+PyTorch only provides device memory and HIP streams.
+"""
+
+from ._capi import SndError, LIB_PATH  # noqa: F401
+from .plan import Plan, encode, cast  # noqa: F401
+
+__all__ = ["Plan", "encode", "cast", "SndError", "LIB_PATH"]

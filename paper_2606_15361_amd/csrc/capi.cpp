@@ -1,0 +1,199 @@
+// C ABI entry points (include/snd.h).  Argument checking, error reporting and the stage
+// schedule of one execute; all device arithmetic is in the HIP kernels.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "snd_internal.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+snd_status fail(snd_status s, const std::string &msg)
+{
+    g_err = msg;
+    return s;
+}
+
+snd_status hip_fail(int code, const char *what)
+{
+    g_err = std::string(what) + ": " + hipGetErrorString((hipError_t)code);
+    return SND_ERR_HIP;
+}
+
+bool aligned256(const void *p) { return ((uintptr_t)p & 255u) == 0; }
+
+}  // namespace
+
+extern "C" {
+
+const char *snd_last_error(void) { return g_err.c_str(); }
+
+const char *snd_version(void) { return "snd-mi355x 0.1 (gfx950)"; }
+
+snd_status snd_plan_create(const snd_plan_desc *desc, snd_plan *out)
+{
+    if (!desc || !out) return fail(SND_ERR_INVALID, "null descriptor or output handle");
+    *out = nullptr;
+    snd_plan p = new (std::nothrow) snd_plan_s;
+    if (!p) return fail(SND_ERR_NOMEM, "host allocation failed");
+    std::string err;
+    snd_status s;
+    try {
+        s = snd::build_plan(*desc, p->impl, err);
+    } catch (const std::bad_alloc &) {
+        s = SND_ERR_NOMEM;
+        err = "host allocation failed while building the plan";
+    }
+    if (s != SND_OK) {
+        delete p;
+        return fail(s, err);
+    }
+    *out = p;
+    return SND_OK;
+}
+
+snd_status snd_plan_query(snd_plan plan, snd_plan_info *out)
+{
+    if (!plan || !out) return fail(SND_ERR_INVALID, "null plan or output");
+    *out = plan->impl.info;
+    return SND_OK;
+}
+
+snd_status snd_plan_delays(snd_plan plan, int32_t *h_delays, int64_t count)
+{
+    if (!plan || !h_delays) return fail(SND_ERR_INVALID, "null plan or buffer");
+    const auto &d = plan->impl.delay;
+    if (count < (int64_t)d.size()) return fail(SND_ERR_NOMEM, "delay buffer smaller than ndm * nchan");
+    std::memcpy(h_delays, d.data(), d.size() * sizeof(int32_t));
+    return SND_OK;
+}
+
+snd_status snd_plan_upload(snd_plan plan, void *d_tables, int64_t bytes, void *stream)
+{
+    if (!plan || !d_tables) return fail(SND_ERR_INVALID, "null plan or table buffer");
+    auto &P = plan->impl;
+    if (bytes < (int64_t)P.table.size()) return fail(SND_ERR_NOMEM, "table buffer smaller than table_bytes");
+    if (!aligned256(d_tables)) return fail(SND_ERR_INVALID, "table buffer must be 256-byte aligned");
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e = hipMemcpyAsync(d_tables, P.table.data(), P.table.size(), hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(tables)");
+    e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize(tables)");
+    P.d_table = d_tables;
+    return SND_OK;
+}
+
+snd_status snd_plan_destroy(snd_plan plan)
+{
+    delete plan;
+    return SND_OK;
+}
+
+namespace {
+
+snd_status check_exec(snd_plan plan, const void *d_in, int64_t in_pitch, void *d_out, int64_t out_pitch,
+                      void *d_workspace, int64_t workspace_bytes)
+{
+    if (!plan || !d_in || !d_out) return fail(SND_ERR_INVALID, "null plan, input or output");
+    auto &P = plan->impl;
+    if (!P.d_table) return fail(SND_ERR_STATE, "plan tables not uploaded");
+    if (in_pitch < P.nsamp) return fail(SND_ERR_INVALID, "input pitch smaller than nsamp");
+    if (out_pitch < P.n_out) return fail(SND_ERR_INVALID, "output pitch smaller than n_out");
+    if (P.workspace_bytes > 0 && (!d_workspace || workspace_bytes < P.workspace_bytes))
+        return fail(SND_ERR_NOMEM, "workspace smaller than workspace_bytes");
+    if (P.workspace_bytes > 0 && !aligned256(d_workspace)) return fail(SND_ERR_INVALID, "workspace must be 256-byte aligned");
+    return SND_OK;
+}
+
+snd_status run_stage(snd::PlanImpl &P, size_t si, const void *d_in, int64_t in_pitch, void *d_out, int64_t out_pitch,
+                     void *d_workspace, void *stream)
+{
+    const uint8_t *tb = static_cast<const uint8_t *>(P.d_table);
+    uint8_t *ws = static_cast<uint8_t *>(d_workspace);
+    const snd::Stage &S = P.stages[si];
+    snd::StageArgs a{};
+    if (si == 0) {
+        a.src = d_in;
+        a.src_pitch = in_pitch;
+    } else {
+        const snd::Stage &Q = P.stages[si - 1];
+        a.src = ws + Q.ws_off;
+        a.src_pitch = Q.pitch;
+    }
+    if (S.final_stage) {
+        a.dst = d_out;
+        a.dst_pitch = out_pitch;
+    } else {
+        a.dst = ws + S.ws_off;
+        a.dst_pitch = S.pitch;
+    }
+    a.row_ptr = reinterpret_cast<const uint32_t *>(tb + S.off_row_ptr);
+    a.row_len = reinterpret_cast<const int32_t *>(tb + S.off_row_len);
+    a.ent = reinterpret_cast<const snd::Entry *>(tb + S.off_ent);
+    a.rows = (int32_t)S.rows;
+    a.depth = S.depth;
+    a.src_is_input = S.src_level < 0;
+    a.k_leaf = P.desc.k_leaf;
+    a.k_int = P.desc.k_int;
+    a.cap = P.desc.cap;
+    a.scale = (S.final_stage && P.desc.mode == SND_MODE_FLOAT && P.desc.root_norm)
+                  ? (float)(1.0 / std::sqrt((double)P.nchan))
+                  : 1.0f;
+    int e = snd::launch_stage(P.desc.mode, S.src_dtype, S.dst_dtype, a, S.max_len, stream);
+    if (e) return hip_fail(e, "stage launch");
+    return SND_OK;
+}
+
+}  // namespace
+
+snd_status snd_execute(snd_plan plan, const void *d_in, int64_t in_pitch, void *d_out, int64_t out_pitch,
+                       void *d_workspace, int64_t workspace_bytes, void *stream)
+{
+    snd_status s = check_exec(plan, d_in, in_pitch, d_out, out_pitch, d_workspace, workspace_bytes);
+    if (s != SND_OK) return s;
+    for (size_t si = 0; si < plan->impl.stages.size(); ++si) {
+        s = run_stage(plan->impl, si, d_in, in_pitch, d_out, out_pitch, d_workspace, stream);
+        if (s != SND_OK) return s;
+    }
+    return SND_OK;
+}
+
+snd_status snd_execute_stage(snd_plan plan, int32_t stage, const void *d_in, int64_t in_pitch, void *d_out,
+                             int64_t out_pitch, void *d_workspace, int64_t workspace_bytes, void *stream)
+{
+    snd_status s = check_exec(plan, d_in, in_pitch, d_out, out_pitch, d_workspace, workspace_bytes);
+    if (s != SND_OK) return s;
+    if (stage < 0 || stage >= (int32_t)plan->impl.stages.size()) return fail(SND_ERR_INVALID, "stage index out of range");
+    return run_stage(plan->impl, (size_t)stage, d_in, in_pitch, d_out, out_pitch, d_workspace, stream);
+}
+
+snd_status snd_encode(const float *d_z, int64_t z_pitch, int32_t time_major, int32_t nchan, int64_t nsamp,
+                      const float *h_thresholds, int32_t nthr, uint8_t *d_out, int64_t out_pitch, void *stream)
+{
+    if (!d_z || !d_out || !h_thresholds) return fail(SND_ERR_INVALID, "null pointer");
+    if (nchan < 1 || nsamp < 1 || nthr < 1 || nthr > 8) return fail(SND_ERR_INVALID, "bad nchan, nsamp or nthr (1..8)");
+    if (z_pitch < (time_major ? nchan : nsamp) || out_pitch < nsamp) return fail(SND_ERR_INVALID, "pitch too small");
+    if (!time_major && nchan > 65535) return fail(SND_ERR_INVALID, "too many channels");
+    int e = snd::launch_encode(d_z, z_pitch, time_major, nchan, nsamp, h_thresholds, nthr, d_out, out_pitch, stream);
+    if (e) return hip_fail(e, "encode launch");
+    return SND_OK;
+}
+
+snd_status snd_cast(const float *d_src, int64_t src_pitch, int64_t rows, int64_t cols, void *d_dst, int64_t dst_pitch,
+                    int32_t dst_dtype, void *stream)
+{
+    if (!d_src || !d_dst) return fail(SND_ERR_INVALID, "null pointer");
+    if (rows < 1 || cols < 1 || rows > 65535 || src_pitch < cols || dst_pitch < cols)
+        return fail(SND_ERR_INVALID, "bad shape or pitch");
+    if (dst_dtype != SND_DT_BF16 && dst_dtype != SND_DT_F16) return fail(SND_ERR_UNSUPPORTED, "cast target must be BF16 or F16");
+    int e = snd::launch_cast(d_src, src_pitch, rows, cols, d_dst, dst_pitch, dst_dtype, stream);
+    if (e) return hip_fail(e, "cast launch");
+    return SND_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,165 @@
+"""Python view of an SND plan: marshals arguments to the C ABI; torch supplies device memory
+and the HIP stream.  Every step of the dedispersion path runs in libsnd's HIP kernels."""
+
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+
+from . import _capi as capi
+
+MODES = {"binary": capi.MODE_BINARY, "graded": capi.MODE_GRADED, "float": capi.MODE_FLOAT}
+DTYPES = {"u8": capi.DT_U8, "u16": capi.DT_U16, "f32": capi.DT_F32, "bf16": capi.DT_BF16, "f16": capi.DT_F16}
+DTYPE_NAMES = {v: k for k, v in DTYPES.items()}
+
+
+def torch_dtype(dt: int):
+    import torch
+    return {capi.DT_U8: torch.uint8, capi.DT_U16: torch.uint16, capi.DT_F32: torch.float32,
+            capi.DT_BF16: torch.bfloat16, capi.DT_F16: torch.float16}[dt]
+
+
+def _stream_handle(stream, device):
+    import torch
+    s = torch.cuda.current_stream(device) if stream is None else stream
+    return C.c_void_p(s.cuda_stream)
+
+
+class Plan:
+    """An SND dedispersion plan (host tables, built by snd_plan_create)."""
+
+    def __init__(self, freqs, dms, tsamp_s: float, nsamp: int, *, mode: str = "float", branching: int = 4,
+                 cluster: int = 4, k_leaf: int = 2, k_int: int = 2, cap: int = 255, in_dtype: str | None = None,
+                 node_dtype: str | None = None, root_norm: bool = False, fref: float = 0.0, stage_levels: int = 0):
+        L = capi.lib()
+        self._freq = np.ascontiguousarray(freqs, dtype=np.float64)
+        self._dm = np.ascontiguousarray(dms, dtype=np.float64)
+        if in_dtype is None:
+            in_dtype = "f32" if mode == "float" else "u8"
+        if node_dtype is None:
+            node_dtype = "f32" if mode == "float" else ("u8" if mode == "binary" or cap <= 255 else "u16")
+        d = capi.PlanDesc()
+        d.nchan = self._freq.size
+        d.freq_mhz = self._freq.ctypes.data_as(C.POINTER(C.c_double))
+        d.tsamp_s = tsamp_s
+        d.fref_mhz = fref
+        d.ndm = self._dm.size
+        d.dm = self._dm.ctypes.data_as(C.POINTER(C.c_double))
+        d.branching, d.cluster, d.mode = branching, cluster, MODES[mode]
+        d.k_leaf, d.k_int, d.cap = k_leaf, k_int, cap
+        d.in_dtype, d.node_dtype = DTYPES[in_dtype], DTYPES[node_dtype]
+        d.root_norm = int(root_norm)
+        d.nsamp = int(nsamp)
+        d.stage_levels = int(stage_levels)
+        h = C.c_void_p()
+        capi.check(L.snd_plan_create(C.byref(d), C.byref(h)))
+        self._h = h
+        self.mode, self.nsamp, self.nchan, self.ndm = mode, int(nsamp), self._freq.size, self._dm.size
+        self.in_dtype, self.node_dtype = in_dtype, node_dtype
+        self.params = dict(mode=mode, branching=branching, cluster=cluster, k_leaf=k_leaf, k_int=k_int, cap=cap,
+                           root_norm=root_norm)
+        info = capi.PlanInfo()
+        capi.check(L.snd_plan_query(h, C.byref(info)))
+        nl, ns = info.n_levels, info.n_stages
+        self.info = dict(
+            n_out=info.n_out, max_delay=info.max_delay, n_levels=nl, n_stages=ns, out_dtype=info.out_dtype,
+            n_neurons=info.n_neurons, n_synapses=info.n_synapses,
+            neurons_per_level=list(info.neurons_per_level[:nl]), synapses_per_level=list(info.synapses_per_level[:nl]),
+            nodes_per_level=list(info.nodes_per_level[:nl]), table_bytes=info.table_bytes,
+            workspace_bytes=info.workspace_bytes, alg_bytes=info.alg_bytes,
+            stage_alg_bytes=list(info.stage_alg_bytes[:ns]), stage_rows=list(info.stage_rows[:ns]),
+            stage_entries=list(info.stage_entries[:ns]), build_seconds=info.build_seconds)
+        self.n_out = info.n_out
+        self._tables = None
+        self._ws = None
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            try:
+                capi.lib().snd_plan_destroy(h)
+            except Exception:
+                pass
+            self._h = None
+
+    @property
+    def handle(self):
+        return self._h
+
+    def delays(self) -> np.ndarray:
+        out = np.empty((self.ndm, self.nchan), dtype=np.int32)
+        capi.check(capi.lib().snd_plan_delays(self._h, out.ctypes.data_as(C.c_void_p), out.size))
+        return out
+
+    @property
+    def out_dtype(self):
+        return torch_dtype(self.info["out_dtype"])
+
+    def upload(self, device="cuda", stream=None):
+        import torch
+        dev = torch.device(device)
+        self._tables = torch.empty(max(256, self.info["table_bytes"]), dtype=torch.uint8, device=dev)
+        capi.check(capi.lib().snd_plan_upload(self._h, C.c_void_p(self._tables.data_ptr()), self._tables.numel(),
+                                              _stream_handle(stream, dev)))
+        return self
+
+    def workspace(self, device="cuda"):
+        import torch
+        if self._ws is None or self._ws.device != torch.device(device):
+            self._ws = torch.empty(max(256, self.info["workspace_bytes"]), dtype=torch.uint8, device=device)
+        return self._ws
+
+    def empty_output(self, device="cuda"):
+        import torch
+        return torch.empty((self.ndm, self.n_out), dtype=self.out_dtype, device=device)
+
+    def execute(self, x, out=None, workspace=None, stream=None, stage=None):
+        """Dedisperse x [nchan][>= nsamp] (device tensor of the input dtype) into out [ndm][>= n_out].
+        With ``stage`` set, run only that stage of the schedule (see snd_execute_stage)."""
+        import torch
+        if self._tables is None:
+            self.upload(x.device, stream)
+        if x.dim() != 2 or x.shape[0] != self.nchan or x.shape[1] < self.nsamp or x.stride(1) != 1:
+            raise ValueError(f"input must be [{self.nchan}][>= {self.nsamp}] with unit time stride")
+        want = torch_dtype(DTYPES[self.in_dtype])
+        if x.dtype != want:
+            raise TypeError(f"input dtype {x.dtype}, plan expects {want}")
+        if out is None:
+            out = self.empty_output(x.device)
+        if out.dim() != 2 or out.shape[0] != self.ndm or out.shape[1] < self.n_out or out.stride(1) != 1 \
+                or out.dtype != self.out_dtype:
+            raise ValueError("bad output tensor")
+        ws = self.workspace(x.device) if workspace is None else workspace
+        args = (C.c_void_p(x.data_ptr()), x.stride(0), C.c_void_p(out.data_ptr()), out.stride(0),
+                C.c_void_p(ws.data_ptr()), ws.numel(), _stream_handle(stream, x.device))
+        if stage is None:
+            capi.check(capi.lib().snd_execute(self._h, *args))
+        else:
+            capi.check(capi.lib().snd_execute_stage(self._h, int(stage), *args))
+        return out
+
+
+def encode(z, thresholds, time_major: bool = False, out=None, stream=None):
+    """Delta encoder on the GPU: uint8 level = number of thresholds exceeded by z (float32)."""
+    import torch
+    th = np.ascontiguousarray(thresholds, dtype=np.float32)
+    if z.dtype != torch.float32 or z.stride(1) != 1:
+        raise TypeError("z must be float32 with unit inner stride")
+    nchan, nsamp = (z.shape[1], z.shape[0]) if time_major else (z.shape[0], z.shape[1])
+    if out is None:
+        out = torch.empty((nchan, nsamp), dtype=torch.uint8, device=z.device)
+    capi.check(capi.lib().snd_encode(C.c_void_p(z.data_ptr()), z.stride(0), int(time_major), nchan, nsamp,
+                                     th.ctypes.data_as(C.c_void_p), th.size, C.c_void_p(out.data_ptr()),
+                                     out.stride(0), _stream_handle(stream, z.device)))
+    return out
+
+
+def cast(x, dtype: str, stream=None):
+    """float32 [rows][cols] -> bf16/f16 with round-to-nearest-even, on the GPU."""
+    import torch
+    dt = DTYPES[dtype]
+    out = torch.empty(x.shape, dtype=torch_dtype(dt), device=x.device)
+    capi.check(capi.lib().snd_cast(C.c_void_p(x.data_ptr()), x.stride(0), x.shape[0], x.shape[1],
+                                   C.c_void_p(out.data_ptr()), out.stride(0), dt, _stream_handle(stream, x.device)))
+    return out

@@ -1,0 +1,116 @@
+"""Host-side checks of libsnd: it loads, exports every declared symbol, and its plan
+(delays, shared-pattern counts, validation) agrees with the oracle.  No device calls."""
+
+import ctypes as C
+import os
+
+import numpy as np
+import pytest
+
+import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def snd():
+    import paper_2606_15361_amd as m
+    return m
+
+
+def test_library_exports_every_declared_symbol(snd):
+    from paper_2606_15361_amd import _capi
+    names = _capi.declared_symbols(os.path.join(ROOT, "include", "snd.h"))
+    assert "snd_execute" in names and "snd_plan_create" in names
+    L = _capi.lib()
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+
+
+@pytest.mark.parametrize("nchan,ndm,C_,B,dmax", [(64, 64, 4, 2, 300.0), (37, 29, 3, 3, 40.0), (24, 17, 5, 4, 30.0),
+                                                 (9, 5, 4, 8, 10.0), (3, 4, 4, 2, 10.0), (1, 3, 1, 2, 50.0)])
+def test_plan_matches_oracle_counts(snd, orc, nchan, ndm, C_, B, dmax):
+    f = synth.channel_freqs(nchan)
+    rng = synth.make_rng(nchan + ndm)
+    dms = rng.uniform(0, dmax, ndm)
+    dms[-1] = dms[0]
+    od = orc.delays(f, dms, 0.138e-3)
+    nsamp = int(od.max()) + 50
+    for mode in ("binary", "graded", "float"):
+        p = snd.Plan(f, dms, 0.138e-3, nsamp, mode=mode, branching=B, cluster=C_)
+        assert np.array_equal(p.delays(), od)
+        assert p.n_out == nsamp - od.max()
+        x = np.zeros((nchan, nsamp), np.uint8)
+        _, counts = orc.snd_dedup(x, f, od, mode=mode, cluster=C_, branching=B)
+        assert p.info["neurons_per_level"] == [c[0] for c in counts]
+        assert p.info["synapses_per_level"] == [c[1] for c in counts]
+        assert p.info["nodes_per_level"] == orc.tree_shape(f, C_, B)
+
+
+def test_config2_plan_shape(snd):
+    spec = synth.workload(2)
+    p = snd.Plan(spec.freqs, spec.dms, spec.tsamp_s, spec.nsamp, mode="float", branching=4)
+    assert p.info["neurons_per_level"] == [49722, 207270, 65356, 16384, 4096]
+    assert p.info["n_synapses"] == 1371312
+    assert p.n_out == 102748
+    assert p.info["n_stages"] == 2
+    assert p.info["build_seconds"] < 2.0
+    every = snd.Plan(spec.freqs, spec.dms, spec.tsamp_s, 40000, mode="graded", branching=4, stage_levels=0b1111)
+    assert every.info["n_stages"] == 5 and every.info["stage_rows"] == [49722, 207270, 65356, 16384, 4096]
+
+
+def test_plan_validation_errors(snd):
+    from paper_2606_15361_amd import SndError, _capi
+    f = synth.channel_freqs(16)
+    dms = np.array([0.0, 5.0])
+    ok = dict(mode="graded", branching=2, cluster=4)
+    snd.Plan(f, dms, 0.138e-3, 500, **ok)
+    bad = [
+        (dict(dms=np.array([-1.0])), _capi.ERR_INVALID),
+        (dict(nsamp=10), _capi.ERR_INVALID),
+        (dict(fref=410.0), _capi.ERR_INVALID),
+        (dict(branching=1), _capi.ERR_INVALID),
+        (dict(cluster=0), _capi.ERR_INVALID),
+        (dict(mode="binary", k_leaf=0), _capi.ERR_INVALID),
+        (dict(cap=0), _capi.ERR_INVALID),
+        (dict(cap=70000), _capi.ERR_INVALID),
+        (dict(mode="float", in_dtype="u8"), _capi.ERR_UNSUPPORTED),
+        (dict(node_dtype="f32"), _capi.ERR_UNSUPPORTED),
+        (dict(cap=300, node_dtype="u8"), _capi.ERR_UNSUPPORTED),
+        (dict(stage_levels=1 << 3), _capi.ERR_INVALID),
+    ]
+    for kw, code in bad:
+        args = dict(ok)
+        dd = kw.pop("dms", dms)
+        ns = kw.pop("nsamp", 500)
+        args.update(kw)
+        with pytest.raises(SndError) as ei:
+            snd.Plan(f, dd, 0.138e-3, ns, **args)
+        assert ei.value.status == code, kw
+
+
+def test_stage_variants_are_consistent_plans(snd):
+    f = synth.channel_freqs(64)
+    dms = synth.dm_linear(40, 0, 60)
+    base = snd.Plan(f, dms, 0.138e-3, 2000, mode="float", branching=2)
+    top = base.info["n_levels"] - 1
+    none = snd.Plan(f, dms, 0.138e-3, 2000, mode="float", branching=2, stage_levels=0x80000000)
+    assert none.info["n_stages"] == 1 and none.info["workspace_bytes"] == 0
+    assert none.info["stage_entries"] == [40 * 64]
+    every = snd.Plan(f, dms, 0.138e-3, 2000, mode="float", branching=2, stage_levels=(1 << top) - 1)
+    assert every.info["n_stages"] == top + 1
+    # per-level schedule: every stage input is one synapse of the shared-pattern tree
+    assert every.info["stage_entries"][:-1] == every.info["synapses_per_level"][:-1]
+    assert base.info["stage_entries"] == [base.info["synapses_per_level"][0], 40 * base.info["nodes_per_level"][0]]
+
+
+def test_execute_requires_upload(snd):
+    from paper_2606_15361_amd import SndError, _capi
+    p = snd.Plan(synth.channel_freqs(8), [0.0, 1.0], 0.138e-3, 100, mode="float", branching=2)
+    buf = (C.c_uint8 * 1024)()
+    rc = _capi.lib().snd_execute(p.handle, C.cast(buf, C.c_void_p), 100, C.cast(buf, C.c_void_p), 100,
+                                 None, 0, None)
+    assert rc == _capi.ERR_STATE
+    assert "upload" in _capi.lib().snd_last_error().decode()
+    with pytest.raises(SndError):
+        _capi.check(rc)

@@ -1,0 +1,264 @@
+"""GPU parity of the SND tree (libsnd through its C ABI) against the CPU oracle.
+
+Integer modes must be bit-exact; float32 within rel-RMS 1e-5 of the FP64 oracle (bit-exact on
+small-integer inputs); BF16/FP16 storage within rel-RMS 1e-2 of the FP64 oracle on the
+original float32 input.
+"""
+
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+STAGE_NONE = 0x80000000
+FP32_TOL = 1e-5
+REDUCED_TOL = 1e-2
+
+
+@pytest.fixture(scope="module")
+def snd():
+    assert torch.cuda.is_available(), "GPU tests need a visible MI355X"
+    import paper_2606_15361_amd as m
+    return m
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def to_np(y):
+    if y.dtype == torch.uint16:
+        y = y.view(torch.int16).to(torch.int32) & 0xFFFF
+    elif y.dtype in (torch.bfloat16, torch.float16):
+        y = y.float()
+    return y.cpu().numpy()
+
+
+def gpu_run(plan, x, stage_by_stage=False):
+    xt = torch.from_numpy(np.ascontiguousarray(x)).cuda()
+    if stage_by_stage:
+        out = plan.empty_output(xt.device)
+        for s in range(plan.info["n_stages"]):
+            plan.execute(xt, out=out, stage=s)
+        y = out
+    else:
+        y = plan.execute(xt)
+    torch.cuda.synchronize()
+    return to_np(y)
+
+
+def rel_rms(a, b):
+    return float(np.sqrt(np.mean((a - b) ** 2)) / max(np.sqrt(np.mean(b ** 2)), 1e-300))
+
+
+def _inputs(rng, mode, nchan, nsamp):
+    if mode == "binary":
+        return synth.random_spikes(rng, nchan, nsamp, 0.3)
+    if mode == "graded":
+        return synth.random_levels(rng, nchan, nsamp, 4)
+    return synth.noise_filterbank(rng, nchan, nsamp)
+
+
+def _case(nchan, ndm, seed, extra=1037):
+    rng = synth.make_rng(seed)
+    f = synth.channel_freqs(nchan)
+    dms = rng.uniform(0, 40.0, ndm)
+    dms[-1] = dms[0]
+    dms[0] = 0.0
+    return rng, f, dms, extra
+
+
+SHAPES = [(64, 4, 2), (37, 3, 3), (24, 5, 4), (16, 1, 2), (9, 4, 8), (3, 4, 2), (1, 1, 2)]
+
+
+@pytest.mark.parametrize("nchan,C_,B", SHAPES)
+@pytest.mark.parametrize("mode,kw", [("binary", dict(k_leaf=2, k_int=2)), ("binary", dict(k_leaf=1, k_int=2)),
+                                     ("graded", dict(cap=255)), ("graded", dict(cap=7)), ("float", {})])
+def test_parity_small(snd, orc, nchan, C_, B, mode, kw):
+    rng, f, dms, extra = _case(nchan, 33, nchan * 31 + B)
+    d = orc.delays(f, dms, 0.138e-3)
+    nsamp = int(d.max()) + extra
+    x = _inputs(rng, mode, nchan, nsamp)
+    want, _ = orc.snd_dedup(x, f, d, mode=mode, cluster=C_, branching=B, **kw)
+    ys = []
+    nlev = len(orc.tree_shape(f, C_, B))
+    variants = [0, STAGE_NONE] + ([(1 << (nlev - 1)) - 1] if nlev > 2 else [])
+    for sl in variants:
+        _say(f"case nchan={nchan} C={C_} B={B} mode={mode} {kw} stage_levels={sl:#x}")
+        p = snd.Plan(f, dms, 0.138e-3, nsamp, mode=mode, cluster=C_, branching=B, stage_levels=sl, **kw)
+        y = gpu_run(p, x, stage_by_stage=(sl == 0))
+        assert y.shape == want.shape
+        if mode == "float":
+            assert rel_rms(y, want) <= FP32_TOL
+        else:
+            assert np.array_equal(y, want.astype(y.dtype))
+        ys.append(y)
+    for y in ys[1:]:
+        assert np.array_equal(y, ys[0])  # identical whatever levels are materialised
+
+
+def test_float_small_integer_input_is_exact(snd, orc):
+    rng, f, dms, extra = _case(48, 40, 7)
+    d = orc.delays(f, dms, 0.138e-3)
+    x = synth.random_levels(rng, 48, int(d.max()) + extra, 3).astype(np.float32)
+    want, _ = orc.snd_dedup(x, f, d, mode="float", cluster=4, branching=4)
+    p = snd.Plan(f, dms, 0.138e-3, x.shape[1], mode="float", branching=4)
+    assert np.array_equal(gpu_run(p, x), want.astype(np.float32))
+    pn = snd.Plan(f, dms, 0.138e-3, x.shape[1], mode="float", branching=4, root_norm=True)
+    wn, _ = orc.snd_dedup(x, f, d, mode="float", cluster=4, branching=4, root_norm=True)
+    assert rel_rms(gpu_run(pn, x), wn) <= FP32_TOL
+
+
+def test_encoder_parity(snd, orc):
+    spec = synth.workload(1)
+    z = spec.filterbank()
+    zt = torch.from_numpy(z).cuda()
+    for thr in ([2.0], [1.0, 2.0, 3.0, 4.0], [0.75]):
+        _say(f"encode thresholds={thr}")
+        a = to_np(snd.encode(zt, thr))
+        b = to_np(snd.encode(zt.t().contiguous(), thr, time_major=True))
+        want = orc.encode(z, thr)
+        assert np.array_equal(a, want) and np.array_equal(b, want)
+
+
+@pytest.mark.parametrize("kl,ki", [(2, 2), (2, 1)])
+def test_config1_binary_exact(snd, orc, kl, ki):
+    spec = synth.workload(1)
+    z = spec.filterbank()
+    x = to_np(snd.encode(torch.from_numpy(z).cuda(), list(spec.enc_thresholds)))
+    d = orc.delays(spec.freqs, spec.dms, spec.tsamp_s)
+    want, counts = orc.snd_dedup(x, spec.freqs, d, mode="binary", cluster=4, branching=2, k_leaf=kl, k_int=ki)
+    p = snd.Plan(spec.freqs, spec.dms, spec.tsamp_s, spec.nsamp, mode="binary", branching=2, k_leaf=kl, k_int=ki)
+    assert p.info["n_neurons"] == sum(c[0] for c in counts) == 1984
+    assert np.array_equal(gpu_run(p, x), want.astype(np.uint8))
+
+
+@pytest.mark.parametrize("B", [2, 4, 8])
+@pytest.mark.parametrize("mode", ["binary", "graded", "float"])
+def test_config3_modes_exact(snd, orc, B, mode):
+    # the 64-channel geometric 3000-trial grid, n_out shortened to keep the oracle fast
+    spec = synth.workload(3, mode=mode, branching=B)
+    d = orc.delays(spec.freqs, spec.dms, spec.tsamp_s)
+    nsamp = int(d.max()) + 1500
+    z = spec.filterbank(nsamp)
+    if mode == "float":
+        x = z
+    else:
+        x = orc.encode(z, list(spec.enc_thresholds))
+    kw = dict(k_leaf=spec.k_leaf, k_int=spec.k_int) if mode == "binary" else {}
+    for cap in ((255, 15) if mode == "graded" else (255,)):
+        _say(f"config3 mode={mode} B={B} cap={cap}")
+        want, _ = orc.snd_dedup(x, spec.freqs, d, mode=mode, cluster=4, branching=B, cap=cap, **kw)
+        p = snd.Plan(spec.freqs, spec.dms, spec.tsamp_s, nsamp, mode=mode, branching=B, cap=cap, **kw)
+        y = gpu_run(p, x)
+        if mode == "float":
+            assert rel_rms(y, want) <= FP32_TOL
+        else:
+            assert np.array_equal(y, want.astype(y.dtype))
+
+
+@pytest.mark.parametrize("node,inp", [("bf16", "f32"), ("f16", "f32"), ("bf16", "bf16"), ("f16", "f16")])
+def test_reduced_precision_storage(snd, orc, node, inp):
+    rng, f, dms, extra = _case(64, 50, 99)
+    d = orc.delays(f, dms, 0.138e-3)
+    z = synth.noise_filterbank(rng, 64, int(d.max()) + extra)
+    want, _ = orc.snd_dedup(z, f, d, mode="float", cluster=4, branching=4)
+    p = snd.Plan(f, dms, 0.138e-3, z.shape[1], mode="float", branching=4, in_dtype=inp, node_dtype=node)
+    zt = torch.from_numpy(z).cuda()
+    xin = zt if inp == "f32" else snd.cast(zt, inp)
+    if inp != "f32":
+        ref = xin.float().cpu() if inp == "bf16" else xin.float().cpu()
+        cpu_cast = zt.cpu().to(torch.bfloat16 if inp == "bf16" else torch.float16).float()
+        assert torch.equal(ref, cpu_cast)  # round-to-nearest-even like torch's own cast
+    y = p.execute(xin)
+    torch.cuda.synchronize()
+    err = rel_rms(to_np(y), want)
+    _say(f"storage node={node} in={inp} rel_rms={err:.3e}")
+    assert err <= REDUCED_TOL
+
+
+def test_edge_cases(snd, orc):
+    f = synth.channel_freqs(40)
+    rng = synth.make_rng(5)
+    # all-zero DM grid: no delay, n_out = nsamp; duplicate rows identical
+    x = synth.random_levels(rng, 40, 300, 4)
+    p = snd.Plan(f, [0.0, 0.0, 0.0], 0.138e-3, 300, mode="graded", branching=2, cap=6)
+    y = gpu_run(p, x)
+    assert y.shape == (3, 300)
+    assert np.array_equal(y[0], np.minimum(x.sum(0), 6)) and np.array_equal(y[0], y[2])
+    # single DM, single channel
+    p1 = snd.Plan([400.0], [100.0], 0.138e-3, 70, mode="float", branching=2, cluster=1)
+    x1 = rng.standard_normal((1, 70)).astype(np.float32)
+    assert np.array_equal(gpu_run(p1, x1), x1[:, :70])
+    # unsorted DMs: rows follow the caller's order
+    dms = np.array([30.0, 0.0, 15.0, 30.0])
+    d = orc.delays(f, dms, 0.138e-3)
+    x2 = synth.random_spikes(rng, 40, int(d.max()) + 600, 0.4)
+    p2 = snd.Plan(f, dms, 0.138e-3, x2.shape[1], mode="binary", branching=3, k_leaf=1, k_int=2)
+    want, _ = orc.snd_dedup(x2, f, d, mode="binary", cluster=4, branching=3, k_leaf=1, k_int=2)
+    y2 = gpu_run(p2, x2)
+    assert np.array_equal(y2, want.astype(np.uint8)) and np.array_equal(y2[0], y2[3])
+    # a pitched input (extra columns) gives the same answer
+    xt = torch.zeros((40, x2.shape[1] + 77), dtype=torch.uint8, device="cuda")
+    xt[:, : x2.shape[1]] = torch.from_numpy(x2).cuda()
+    y3 = to_np(p2.execute(xt))
+    assert np.array_equal(y3, y2)
+
+
+def test_bad_arguments_raise(snd):
+    p = snd.Plan(synth.channel_freqs(8), [0.0, 2.0], 0.138e-3, 200, mode="float", branching=2)
+    with pytest.raises(ValueError):
+        p.execute(torch.zeros((8, 100), device="cuda"))
+    with pytest.raises(TypeError):
+        p.execute(torch.zeros((8, 200), dtype=torch.uint8, device="cuda"))
+
+
+def test_determinism(snd):
+    rng, f, dms, extra = _case(128, 64, 3)
+    p = snd.Plan(f, dms, 0.138e-3, 4000, mode="float", branching=4)
+    z = synth.noise_filterbank(rng, 128, 4000)
+    a = gpu_run(p, z)
+    b = gpu_run(p, z)
+    assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("mode", ["float", "graded"])
+def test_config2_full_size_sampled(snd, orc, mode):
+    # The benchmarked workload (1024 ch, 4096 DM, 2^17 samples, B = 4) at full size, checked
+    # on sampled outputs against the oracle's per-point recursion.
+    spec = synth.workload(2)
+    _say(f"config2 full size mode={mode}: generating input")
+    z = spec.filterbank()
+    d = orc.delays(spec.freqs, spec.dms, spec.tsamp_s)
+    zt = torch.from_numpy(z).cuda()
+    if mode == "float":
+        x, xin = z, zt
+    else:
+        xin = snd.encode(zt, [1.0, 2.0, 3.0, 4.0])
+        x = to_np(xin)
+    p = snd.Plan(spec.freqs, spec.dms, spec.tsamp_s, spec.nsamp, mode=mode, branching=4)
+    _say(f"config2 mode={mode}: executing on the GPU")
+    y = p.execute(xin)
+    torch.cuda.synchronize()
+    rng = synth.make_rng(77)
+    n = 3000
+    ks = rng.integers(0, spec.dms.size, n)
+    ts = rng.integers(0, p.n_out, n)
+    ks[:4] = [0, spec.dms.size - 1, 0, spec.dms.size - 1]
+    ts[:4] = [0, 0, p.n_out - 1, p.n_out - 1]
+    got = to_np(y[torch.from_numpy(ks).cuda(), torch.from_numpy(ts).cuda()])
+    want = orc.snd_points(x, spec.freqs, d, ks, ts, mode=mode, cluster=4, branching=4)
+    if mode == "float":
+        assert rel_rms(got, want) <= FP32_TOL
+    else:
+        assert np.array_equal(got, want.astype(got.dtype))
+    # DM 0 row is the plain channel sum
+    if mode == "graded":
+        row0 = to_np(y[0, :2000])
+        assert np.array_equal(row0, np.minimum(x[:, :2000].astype(np.int64).sum(0), 255))
