@@ -439,8 +439,10 @@ void orc_encode(int64_t n, const float *z, int32_t nthr, const float *thr, uint8
  * every width W that fits, SNR(k,t,W) = (sum_{t'=t}^{t+W-1} y - mu W) / (sigma sqrt W).
  * The plane holds the maximum over widths (first width on ties; widths must increase)
  * and the index of that width; cells where no width fits hold 0 and -1.  A row with
- * sigma = 0 has S/N 0.  integer_plane = 1 takes mu and sigma from exact integer sums:
- * mu = S1/n, sigma = sqrt(n S2 - S1^2) / n.
+ * sigma = 0 has S/N 0.  integer_plane = 1 takes mu and sigma from the exact integer sums
+ * S1 = sum y, S2 = sum y^2 through one fixed FP64 expression: mu = S1/n,
+ * sigma = sqrt(n*S2 - S1*S1)/n with each product and the difference rounded once (exact
+ * for 8-bit planes, where every term is an integer below 2^53).
  * ---------------------------------------------------------------------------------- */
 int orc_matched_filter(int32_t integer_plane, int64_t ndm, int64_t nout, const double *y, int32_t nw,
                        const int32_t *widths, double sigma_min, double *snr, int32_t *widx, double *mu_out,
@@ -459,8 +461,8 @@ int orc_matched_filter(int32_t integer_plane, int64_t ndm, int64_t nout, const d
                 s2 += v * v;
             }
             mu = (double)s1 / (double)nout;
-            int64_t num = nout * s2 - s1 * s1;
-            sigma = sqrt((double)num) / (double)nout;
+            double num = (double)nout * (double)s2 - (double)s1 * (double)s1;
+            sigma = num > 0.0 ? sqrt(num) / (double)nout : 0.0;
         } else {
             double s = 0.0;
             for (int64_t t = 0; t < nout; ++t) s += row[t];
