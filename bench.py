@@ -39,6 +39,8 @@ def parse():
     ap.add_argument("--no-detect", action="store_true", help="time the tree only")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=2048, help="output samples in the oracle's timed sample")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run one plain 1 GiB device copy first (scale reference for HBM counters)")
     return ap.parse_args()
 
 
@@ -72,6 +74,15 @@ def main():
     import synth
 
     dev = torch.device("cuda:0")
+    if args.copy_calibration:
+        a = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        a.fill_(1.0)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log("[bench] calibration copy: 1 GiB read + 1 GiB written")
+        del a, b
     spec = synth.workload(2)
     mode = args.mode
     log(f"[bench] generating the 1024 x {spec.nsamp} filterbank")

@@ -175,6 +175,60 @@ snd_status snd_encode(const float *d_z, int64_t z_pitch, int32_t time_major, int
 snd_status snd_cast(const float *d_src, int64_t src_pitch, int64_t rows, int64_t cols, void *d_dst,
                     int64_t dst_pitch, int32_t dst_dtype, void *stream);
 
+/* ------------------------------------------------------------------------------------
+ * Matched filter and candidates (Methods, "Matched filtering" and "Candidate detection").
+ * Per DM row k of a plane produced by snd_execute: mu_k and sigma_k are the mean and the
+ * population standard deviation of the n_out valid samples (integer planes: from the exact
+ * sums S1, S2 as mu = S1/n, sigma = sqrt(n*S2 - S1*S1)/n in FP64; float planes: two-pass FP64),
+ * sigma_k is raised to sigma_min when smaller; for every width W that fits,
+ *     SNR(k, t, W) = (sum_{t'=t}^{t+W-1} y_k(t') - mu_k W) / (sigma_k sqrt W),
+ * the S/N plane is the maximum over widths (first width on ties; 0 and width index -1 where
+ * no width fits; 0 on rows with sigma = 0).  Candidates: cells with S/N >= threshold, binary
+ * closing with a (2r+1)^2 square on the zero-extended plane, 8-connected islands, islands
+ * with fewer than n_min closed pixels dropped, one candidate per island at its peak cell
+ * (highest S/N, then lowest DM index, then earliest sample), ordered by (dm_index, t).
+ * ---------------------------------------------------------------------------------- */
+#define SND_MAX_WIDTHS 32
+#define SND_MAX_WIDTH 1024
+
+typedef struct {
+    const int32_t *widths;  /* host [nwidths], strictly increasing, 1..SND_MAX_WIDTH */
+    int32_t nwidths;        /* 1..SND_MAX_WIDTHS */
+    int32_t closing_radius; /* r >= 0; 4 gives the paper's 9 x 9 closing */
+    double threshold;       /* > 0, compared with the FP64 S/N */
+    double sigma_min;       /* >= 0; the paper floors sigma of binary planes (0.15-0.20) */
+    int32_t n_min;          /* >= 1; the paper uses 10 */
+    int32_t reserved;       /* must be zero */
+    int64_t max_pixels;     /* capacity of the device list of thresholded cells, >= 1 */
+} snd_detect_desc;
+
+typedef struct {
+    int32_t dm_index; /* row of the peak cell (index into the plan's DM list) */
+    int32_t width;    /* boxcar width of the peak, samples */
+    int64_t t;        /* first sample of the peak boxcar */
+    double snr;       /* S/N of the peak cell */
+    double dm;        /* trial DM of the peak row */
+    int64_t npix;     /* pixels of the closed island */
+} snd_candidate;
+
+/* Device workspace bytes needed by snd_detect / snd_snr_plane for this plan and descriptor. */
+snd_status snd_detect_workspace(snd_plan plan, const snd_detect_desc *desc, int64_t *bytes);
+
+/* Full S/N plane: d_snr float [ndm][snr_pitch] and d_widx int8 [ndm][widx_pitch] (width index,
+ * -1 where none fits) for the plane d_plane [ndm][plane_pitch] of the plan's output dtype.
+ * d_workspace: snd_detect_workspace bytes, 256-byte aligned; its first 2*ndm doubles (after a
+ * 256-byte header) hold (mu_k, sigma_k) afterwards.  Asynchronous on stream. */
+snd_status snd_snr_plane(snd_plan plan, const void *d_plane, int64_t plane_pitch, const snd_detect_desc *desc,
+                         float *d_snr, int64_t snr_pitch, int8_t *d_widx, int64_t widx_pitch, void *d_workspace,
+                         int64_t workspace_bytes, void *stream);
+
+/* Candidates of the plane d_plane.  Synchronises the stream.  Writes up to cap candidates to
+ * h_out, the number of candidates to *h_count and the number of thresholded cells to
+ * *h_npixels.  CAPACITY (and no candidates) when the thresholded cells exceed max_pixels. */
+snd_status snd_detect(snd_plan plan, const void *d_plane, int64_t plane_pitch, const snd_detect_desc *desc,
+                      void *d_workspace, int64_t workspace_bytes, snd_candidate *h_out, int64_t cap,
+                      int64_t *h_count, int64_t *h_npixels, void *stream);
+
 /* Thread-local message describing the last failure in this thread ("" if none). */
 const char *snd_last_error(void);
 

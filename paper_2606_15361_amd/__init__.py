@@ -8,5 +8,6 @@ PyTorch only provides device memory and HIP streams.
 
 from ._capi import SndError, LIB_PATH  # noqa: F401
 from .plan import Plan, encode, cast  # noqa: F401
+from .detect import Detector  # noqa: F401
 
-__all__ = ["Plan", "encode", "cast", "SndError", "LIB_PATH"]
+__all__ = ["Plan", "Detector", "encode", "cast", "SndError", "LIB_PATH"]

@@ -47,6 +47,17 @@ class PlanInfo(C.Structure):
     ]
 
 
+class DetectDesc(C.Structure):
+    _fields_ = [("widths", C.POINTER(C.c_int32)), ("nwidths", C.c_int32), ("closing_radius", C.c_int32),
+                ("threshold", C.c_double), ("sigma_min", C.c_double), ("n_min", C.c_int32),
+                ("reserved", C.c_int32), ("max_pixels", C.c_int64)]
+
+
+class Candidate(C.Structure):
+    _fields_ = [("dm_index", C.c_int32), ("width", C.c_int32), ("t", C.c_int64), ("snr", C.c_double),
+                ("dm", C.c_double), ("npix", C.c_int64)]
+
+
 _lib = None
 
 
@@ -82,12 +93,13 @@ def lib() -> C.CDLL:
         "snd_last_error": ([], C.c_char_p),
         "snd_version": ([], C.c_char_p),
     }
-    optional = {
-        "snd_detect_query": ([P, P, P], I32),
-        "snd_detect": ([P, P, I64, P, P, I64, P, I32, P, P, P], I32),
-        "snd_snr_plane": ([P, P, I64, P, P, I64, P, P, I64, P], I32),
-        "snd_stream_create": ([P, P, I32, I64, P], I32),
-    }
+    D = C.POINTER(DetectDesc)
+    sig.update({
+        "snd_detect_workspace": ([P, D, C.POINTER(I64)], I32),
+        "snd_snr_plane": ([P, P, I64, D, P, I64, P, I64, P, I64, P], I32),
+        "snd_detect": ([P, P, I64, D, P, I64, C.POINTER(Candidate), I64, C.POINTER(I64), C.POINTER(I64), P], I32),
+    })
+    optional = {}
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
         fn.argtypes = args

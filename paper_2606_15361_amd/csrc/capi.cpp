@@ -29,6 +29,10 @@ bool aligned256(const void *p) { return ((uintptr_t)p & 255u) == 0; }
 
 }  // namespace
 
+namespace snd {
+void set_error(const std::string &msg) { g_err = msg; }
+}  // namespace snd
+
 extern "C" {
 
 const char *snd_last_error(void) { return g_err.c_str(); }

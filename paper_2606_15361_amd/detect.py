@@ -1,0 +1,71 @@
+"""Matched filter and candidate stage (snd_snr_plane / snd_detect) from Python."""
+
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+
+from . import _capi as capi
+from .plan import _stream_handle
+
+
+class Detector:
+    """Boxcar S/N and candidate extraction for the DM-time planes of one plan."""
+
+    def __init__(self, plan, widths=(1, 2, 4, 8, 16, 32, 64), threshold: float = 7.0, sigma_min: float = 0.0,
+                 closing_radius: int = 4, n_min: int = 10, max_pixels: int = 1 << 20, device="cuda"):
+        import torch
+        self.plan = plan
+        self._w = np.ascontiguousarray(widths, dtype=np.int32)
+        d = capi.DetectDesc()
+        d.widths = self._w.ctypes.data_as(C.POINTER(C.c_int32))
+        d.nwidths = self._w.size
+        d.threshold = threshold
+        d.sigma_min = sigma_min
+        d.closing_radius = closing_radius
+        d.n_min = n_min
+        d.reserved = 0
+        d.max_pixels = max_pixels
+        self.desc = d
+        nb = C.c_int64()
+        capi.check(capi.lib().snd_detect_workspace(plan.handle, C.byref(d), C.byref(nb)))
+        self.ws = torch.empty(nb.value, dtype=torch.uint8, device=device)
+        self.widths = [int(w) for w in self._w]
+        self.npixels = 0
+        self._cap = 1 << 16
+        self._buf = (capi.Candidate * self._cap)()
+
+    def row_stats(self):
+        """(mu, sigma) per DM row from the last run (float64 tensors on the device)."""
+        n = self.plan.ndm
+        v = self.ws[256:256 + 16 * n].view(__import__("torch").float64).view(n, 2)
+        return v[:, 0], v[:, 1]
+
+    def snr_plane(self, plane, stream=None):
+        """(snr float32 [ndm][n_out], width index int8 [ndm][n_out])."""
+        import torch
+        n = self.plan.n_out
+        snr = torch.empty((self.plan.ndm, n), dtype=torch.float32, device=plane.device)
+        widx = torch.empty((self.plan.ndm, n), dtype=torch.int8, device=plane.device)
+        capi.check(capi.lib().snd_snr_plane(self.plan.handle, C.c_void_p(plane.data_ptr()), plane.stride(0),
+                                            C.byref(self.desc), C.c_void_p(snr.data_ptr()), snr.stride(0),
+                                            C.c_void_p(widx.data_ptr()), widx.stride(0),
+                                            C.c_void_p(self.ws.data_ptr()), self.ws.numel(),
+                                            _stream_handle(stream, plane.device)))
+        return snr, widx
+
+    def run(self, plane, stream=None):
+        """Candidates of a plane, as dicts ordered by (k, t) of the peak.  Synchronises the stream."""
+        cnt, npx = C.c_int64(), C.c_int64()
+        capi.check(capi.lib().snd_detect(self.plan.handle, C.c_void_p(plane.data_ptr()), plane.stride(0),
+                                         C.byref(self.desc), C.c_void_p(self.ws.data_ptr()), self.ws.numel(),
+                                         self._buf, self._cap, C.byref(cnt), C.byref(npx),
+                                         _stream_handle(stream, plane.device)))
+        self.npixels = npx.value
+        out = []
+        for i in range(min(cnt.value, self._cap)):
+            c = self._buf[i]
+            out.append(dict(k=c.dm_index, t=c.t, width=c.width, widx=self.widths.index(c.width), snr=c.snr,
+                            dm=c.dm, npix=c.npix))
+        return out
