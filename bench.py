@@ -37,6 +37,7 @@ def parse():
     ap.add_argument("--node-dtype", default=None)
     ap.add_argument("--stage-levels", type=lambda s: int(s, 0), default=0)
     ap.add_argument("--no-detect", action="store_true", help="time the tree only")
+    ap.add_argument("--generic-kernels", action="store_true", help="run every stage on the generic stage kernel")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=2048, help="output samples in the oracle's timed sample")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -100,7 +101,7 @@ def main():
     del zt
     plan = snd.Plan(spec.freqs, spec.dms, spec.tsamp_s, spec.nsamp, mode=mode, branching=spec.branching,
                     cluster=spec.cluster, k_leaf=2, k_int=1, cap=255, node_dtype=node, in_dtype=in_dtype,
-                    stage_levels=args.stage_levels)
+                    stage_levels=args.stage_levels, generic_kernels=args.generic_kernels)
     info = plan.info
     log(f"[bench] plan: {info['n_neurons']} neurons, {info['n_synapses']} synapses, stages {info['stage_rows']}, "
         f"workspace {info['workspace_bytes'] / 2**30:.2f} GiB, built in {info['build_seconds']:.2f} s")

@@ -95,7 +95,9 @@ typedef struct {
                                 (leaves only); SND_STAGE_NONE = no level written (the whole tree is
                                 evaluated from the input in one stage).  The output is identical
                                 for every choice. */
-    int32_t reserved[8];     /* must be zero */
+    int32_t generic_kernels; /* 1: run every stage on the generic stage kernel instead of the
+                                LDS-staged kernels (same results; for cross-checks) */
+    int32_t reserved[7];     /* must be zero */
 } snd_plan_desc;
 
 typedef struct snd_plan_s *snd_plan;
@@ -121,6 +123,13 @@ typedef struct {
     int64_t stage_rows[SND_MAX_LEVELS];     /* output rows per stage */
     int64_t stage_entries[SND_MAX_LEVELS];  /* (row, shift) inputs summed per stage per time sample */
     double build_seconds;                   /* host time of snd_plan_create */
+    int32_t stage_kernel[SND_MAX_LEVELS];   /* kernel per stage: 0 generic, 1 LDS row groups,
+                                               2 input-anchored, 3 LDS row groups specialised for
+                                               regular level-1 nodes */
+    int64_t stage_staged[SND_MAX_LEVELS];   /* LDS row groups: source elements staged per time
+                                               tile summed over groups (0 otherwise) */
+    int64_t stage_batches[SND_MAX_LEVELS];  /* LDS row groups: batches summed over groups */
+    int64_t stage_windows[SND_MAX_LEVELS];  /* LDS row groups: staged windows summed over groups */
 } snd_plan_info;
 
 /* Build a plan on the host (no device work).  INVALID on a malformed descriptor (n_out <= 0,

@@ -31,7 +31,7 @@ class PlanDesc(C.Structure):
         ("branching", C.c_int32), ("cluster", C.c_int32), ("mode", C.c_int32), ("k_leaf", C.c_int32),
         ("k_int", C.c_int32), ("cap", C.c_int32), ("in_dtype", C.c_int32), ("node_dtype", C.c_int32),
         ("root_norm", C.c_int32), ("nsamp", C.c_int64), ("stage_levels", C.c_uint32),
-        ("reserved", C.c_int32 * 8),
+        ("generic_kernels", C.c_int32), ("reserved", C.c_int32 * 7),
     ]
 
 
@@ -43,7 +43,9 @@ class PlanInfo(C.Structure):
         ("nodes_per_level", C.c_int64 * MAX_LEVELS), ("table_bytes", C.c_int64), ("workspace_bytes", C.c_int64),
         ("alg_bytes", C.c_int64), ("stage_alg_bytes", C.c_int64 * MAX_LEVELS),
         ("stage_rows", C.c_int64 * MAX_LEVELS), ("stage_entries", C.c_int64 * MAX_LEVELS),
-        ("build_seconds", C.c_double),
+        ("build_seconds", C.c_double), ("stage_kernel", C.c_int32 * MAX_LEVELS),
+        ("stage_staged", C.c_int64 * MAX_LEVELS), ("stage_batches", C.c_int64 * MAX_LEVELS),
+        ("stage_windows", C.c_int64 * MAX_LEVELS),
     ]
 
 

@@ -16,7 +16,8 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsnd.so")
 BUILD = os.path.join(HERE, "_build")
 
-HIP_SOURCES = ["kernels.hip", "detect.hip", "stream.hip"]
+HIP_SOURCES = ["kernels.hip", "kernels_lds.hip", "kernels_fast_binary.hip", "kernels_fast_graded.hip",
+               "kernels_fast_float.hip", "detect.hip", "stream.hip"]
 CXX_SOURCES = ["plan.cpp", "capi.cpp", "detect_host.cpp", "stream_host.cpp"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function", "-ffp-contract=off",
@@ -34,6 +35,8 @@ def hipcc() -> str:
 
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
+    if os.path.exists(LIB):  # a failed build must not leave an older library behind
+        os.remove(LIB)
     cc = hipcc()
     objs = []
     jobs = []

@@ -139,6 +139,57 @@ snd_status run_stage(snd::PlanImpl &P, size_t si, const void *d_in, int64_t in_p
     a.row_ptr = reinterpret_cast<const uint32_t *>(tb + S.off_row_ptr);
     a.row_len = reinterpret_cast<const int32_t *>(tb + S.off_row_len);
     a.ent = reinterpret_cast<const snd::Entry *>(tb + S.off_ent);
+    const float scale = (S.final_stage && P.desc.mode == SND_MODE_FLOAT && P.desc.root_norm)
+                            ? (float)(1.0 / std::sqrt((double)P.nchan))
+                            : 1.0f;
+    if (S.kernel == snd::kKernelGroupLds) {
+        snd::GroupArgs g{};
+        g.src = a.src;
+        g.src_pitch = a.src_pitch;
+        g.dst = a.dst;
+        g.dst_pitch = a.dst_pitch;
+        g.grp_rows = reinterpret_cast<const int32_t *>(tb + S.off_grp_rows);
+        g.batch_ptr = reinterpret_cast<const int32_t *>(tb + S.off_batch_ptr);
+        g.batches = reinterpret_cast<const int32_t *>(tb + S.off_batches);
+        g.slots = reinterpret_cast<const int32_t *>(tb + S.off_slots);
+        g.ldsb = reinterpret_cast<const uint32_t *>(tb + S.off_ldsb);
+        g.ngroups = (int32_t)S.ngroups;
+        g.n_entries = S.n_entries;
+        g.buf_elems = S.lds_buf_elems;
+        g.f1 = S.group_f1;
+        g.n_out = (int32_t)P.n_out;
+        g.depth = S.depth;
+        g.src_is_input = S.src_level < 0;
+        g.k_leaf = P.desc.k_leaf;
+        g.k_int = P.desc.k_int;
+        g.cap = P.desc.cap;
+        g.scale = scale;
+        int e = snd::launch_group(P.desc.mode, S.src_dtype, S.dst_dtype, g, P.n_out, S.lds_bytes, stream);
+        if (e) return hip_fail(e, "stage launch (LDS groups)");
+        return SND_OK;
+    }
+    if (S.kernel == snd::kKernelAnchored) {
+        snd::AnchorArgs g{};
+        g.src = a.src;
+        g.src_pitch = a.src_pitch;
+        g.src_len = P.nsamp;
+        g.dst = a.dst;
+        g.dst_pitch = a.dst_pitch;
+        g.row_ptr = a.row_ptr;
+        g.row_len = a.row_len;
+        g.ent = a.ent;
+        g.nodes = reinterpret_cast<const int32_t *>(tb + S.off_nodes);
+        g.tiles = reinterpret_cast<const int32_t *>(tb + S.off_tiles);
+        g.row_lo = reinterpret_cast<const int32_t *>(tb + S.off_row_lo);
+        g.depth = S.depth;
+        g.k_leaf = P.desc.k_leaf;
+        g.k_int = P.desc.k_int;
+        g.cap = P.desc.cap;
+        g.scale = scale;
+        int e = snd::launch_anchored(P.desc.mode, S.src_dtype, S.dst_dtype, g, S.ntiles, S.lds_bytes, stream);
+        if (e) return hip_fail(e, "stage launch (input-anchored)");
+        return SND_OK;
+    }
     a.rows = (int32_t)S.rows;
     a.depth = S.depth;
     a.src_is_input = S.src_level < 0;

@@ -60,6 +60,40 @@ void fill_args(const snd_detect_desc *d, snd::SnrArgs &a)
 }
 
 // ---- host closing + labelling on the sparse thresholded cells ----
+// The thresholded cells are turned into runs of consecutive samples per DM row.  The square
+// closing is separable: dilation along time (runs widened by r and merged), dilation along
+// DM (union of the 2r+1 neighbouring rows), erosion along DM (intersection of the 2r+1
+// neighbouring rows) and erosion along time (runs narrowed by r).  All of it works on runs, so
+// the cost grows with the number of runs, not with the area of the islands.  Rows outside the
+// plane are empty, which is the zero-extended plane.
+struct Run {
+    int64_t a, b;  // inclusive
+};
+using Rows = std::vector<std::vector<Run>>;
+
+void merge_sorted(std::vector<Run> &v)
+{
+    if (v.empty()) return;
+    size_t w = 0;
+    for (size_t i = 1; i < v.size(); ++i) {
+        if (v[i].a <= v[w].b + 1) v[w].b = std::max(v[w].b, v[i].b);
+        else v[++w] = v[i];
+    }
+    v.resize(w + 1);
+}
+
+void intersect(const std::vector<Run> &x, const std::vector<Run> &y, std::vector<Run> &out)
+{
+    out.clear();
+    size_t i = 0, j = 0;
+    while (i < x.size() && j < y.size()) {
+        const int64_t a = std::max(x[i].a, y[j].a), b = std::min(x[i].b, y[j].b);
+        if (a <= b) out.push_back({a, b});
+        if (x[i].b < y[j].b) ++i;
+        else ++j;
+    }
+}
+
 struct UF {
     std::vector<int32_t> p;
     explicit UF(size_t n) : p(n) { std::iota(p.begin(), p.end(), 0); }
@@ -84,150 +118,90 @@ snd_status candidates_from_pixels(std::vector<snd::Pixel> &px, const snd::PlanIm
         return a.k != b.k ? a.k < b.k : a.t < b.t;
     });
     const int64_t r = d->closing_radius;
-    const int64_t reach = 2 * r + 1;  // two dilation squares touch (8-connected) within this distance
-    const size_t n = px.size();
-    // row starts in the sorted list
-    UF uf(n);
-    size_t rs = 0;
-    std::vector<std::pair<int32_t, size_t>> rows;  // (k, first index)
-    for (size_t i = 0; i < n; ++i)
-        if (i == 0 || px[i].k != px[i - 1].k) rows.push_back({px[i].k, i});
-    rows.push_back({INT32_MAX, n});
-    for (size_t ri = 0; ri + 1 < rows.size(); ++ri) {
-        const int32_t k = rows[ri].first;
-        for (size_t rj = ri; rj + 1 < rows.size() && rows[rj].first <= k + reach; ++rj) {
-            size_t b0 = rows[rj].second, b1 = rows[rj + 1].second;
-            for (size_t i = rows[ri].second; i < rows[ri + 1].second; ++i) {
-                const int64_t t = px[i].t;
-                auto lo = std::lower_bound(px.begin() + b0, px.begin() + b1, t - reach,
-                                           [](const snd::Pixel &a, int64_t v) { return a.t < v; });
-                for (auto it = lo; it != px.begin() + b1 && it->t <= t + reach; ++it) uf.u((int32_t)i, (int32_t)(it - px.begin()));
-            }
+    const int64_t kmin = px.front().k, kmax = px.back().k;
+    // rows are indexed relative to K0 = kmin - 2r so every dilated/eroded row has a slot
+    const int64_t K0 = kmin - 2 * r, NR = kmax - kmin + 4 * r + 1;
+    Rows dt((size_t)NR);  // thresholded runs widened along time
+    for (size_t i = 0; i < px.size();) {
+        size_t j = i;
+        const int64_t k = px[i].k;
+        std::vector<Run> &row = dt[(size_t)(k - K0)];
+        while (j < px.size() && px[j].k == k) {
+            int64_t a = px[j].t, b = a;
+            while (j + 1 < px.size() && px[j + 1].k == k && px[j + 1].t == b + 1) { ++j; ++b; }
+            row.push_back({a - r, b + r});
+            ++j;
+        }
+        merge_sorted(row);
+        i = j;
+    }
+    Rows dil((size_t)NR);  // dilation along DM
+    for (int64_t k = 0; k < NR; ++k) {
+        std::vector<Run> &row = dil[(size_t)k];
+        for (int64_t q = std::max<int64_t>(0, k - r); q <= std::min<int64_t>(NR - 1, k + r); ++q)
+            row.insert(row.end(), dt[(size_t)q].begin(), dt[(size_t)q].end());
+        std::sort(row.begin(), row.end(), [](const Run &x, const Run &y) { return x.a < y.a; });
+        merge_sorted(row);
+    }
+    dt.clear();
+    Rows cl((size_t)NR);  // erosion along DM, then along time
+    std::vector<Run> tmp;
+    for (int64_t k = 0; k < NR; ++k) {
+        if (k - r < 0 || k + r >= NR) continue;  // a neighbouring row is outside the dilation: empty
+        std::vector<Run> cur = dil[(size_t)(k - r)];
+        for (int64_t q = k - r + 1; q <= k + r && !cur.empty(); ++q) {
+            intersect(cur, dil[(size_t)q], tmp);
+            cur.swap(tmp);
+        }
+        for (const Run &x : cur)
+            if (x.a + r <= x.b - r) cl[(size_t)k].push_back({x.a + r, x.b - r});
+    }
+    dil.clear();
+    // 8-connected labelling of the closed runs
+    std::vector<int64_t> first((size_t)NR + 1, 0);
+    for (int64_t k = 0; k < NR; ++k) first[(size_t)k + 1] = first[(size_t)k] + (int64_t)cl[(size_t)k].size();
+    UF uf((size_t)first[(size_t)NR]);
+    for (int64_t k = 0; k + 1 < NR; ++k) {
+        const std::vector<Run> &x = cl[(size_t)k], &y = cl[(size_t)k + 1];
+        size_t i = 0, j = 0;
+        while (i < x.size() && j < y.size()) {
+            if (y[j].a <= x[i].b + 1 && x[i].a <= y[j].b + 1)
+                uf.u((int32_t)(first[(size_t)k] + (int64_t)i), (int32_t)(first[(size_t)k + 1] + (int64_t)j));
+            if (x[i].b < y[j].b) ++i;
+            else ++j;
         }
     }
-    (void)rs;
-    // group pixels by component
-    std::vector<int32_t> comp(n);
-    for (size_t i = 0; i < n; ++i) comp[i] = uf.f((int32_t)i);
-    std::vector<int32_t> order(n);
-    std::iota(order.begin(), order.end(), 0);
-    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return comp[a] < comp[b]; });
-    std::vector<uint8_t> A, Bm;
-    std::vector<int32_t> lab;
-    std::vector<int64_t> stack;
-    for (size_t s = 0; s < n;) {
-        size_t e = s;
-        while (e < n && comp[order[e]] == comp[order[s]]) ++e;
-        int64_t kmin = INT64_MAX, kmax = INT64_MIN, tmin = INT64_MAX, tmax = INT64_MIN;
-        for (size_t i = s; i < e; ++i) {
-            const snd::Pixel &q = px[order[i]];
-            kmin = std::min<int64_t>(kmin, q.k); kmax = std::max<int64_t>(kmax, q.k);
-            tmin = std::min<int64_t>(tmin, q.t); tmax = std::max<int64_t>(tmax, q.t);
+    const size_t nruns = (size_t)first[(size_t)NR];
+    std::vector<int64_t> npix(nruns, 0);
+    std::vector<int32_t> peak(nruns, -1);
+    for (int64_t k = 0; k < NR; ++k)
+        for (size_t i = 0; i < cl[(size_t)k].size(); ++i) {
+            const Run &x = cl[(size_t)k][i];
+            npix[(size_t)uf.f((int32_t)(first[(size_t)k] + (int64_t)i))] += x.b - x.a + 1;
         }
-        const int64_t k0 = kmin - 2 * r, t0 = tmin - 2 * r;
-        const int64_t H = kmax - kmin + 4 * r + 1, W = tmax - tmin + 4 * r + 1;
-        if (H * W > (int64_t)1 << 31) { snd::set_error("candidate island too large for host labelling"); return SND_ERR_CAPACITY; }
-        A.assign((size_t)(H * W), 0);
-        Bm.assign((size_t)(H * W), 0);
-        for (size_t i = s; i < e; ++i) {
-            const snd::Pixel &q = px[order[i]];
-            A[(size_t)((q.k - k0) * W + (q.t - t0))] = 1;
-        }
-        // dilation (square): along t, then along k, with running counts
-        for (int64_t i = 0; i < H; ++i) {
-            const uint8_t *a = &A[(size_t)(i * W)];
-            uint8_t *b = &Bm[(size_t)(i * W)];
-            int64_t cnt = 0;
-            for (int64_t j = 0; j < std::min<int64_t>(r, W); ++j) cnt += a[j];
-            for (int64_t j = 0; j < W; ++j) {
-                if (j + r < W) cnt += a[j + r];
-                if (j - r - 1 >= 0) cnt -= a[j - r - 1];
-                b[j] = cnt > 0;
-            }
-        }
-        for (int64_t j = 0; j < W; ++j) {
-            int64_t cnt = 0;
-            for (int64_t i = 0; i < std::min<int64_t>(r, H); ++i) cnt += Bm[(size_t)(i * W + j)];
-            for (int64_t i = 0; i < H; ++i) {
-                if (i + r < H) cnt += Bm[(size_t)((i + r) * W + j)];
-                if (i - r - 1 >= 0) cnt -= Bm[(size_t)((i - r - 1) * W + j)];
-                A[(size_t)(i * W + j)] = cnt > 0;
-            }
-        }
-        // erosion (square); cells outside the grid are empty (the grid spans the dilation + r)
-        const int64_t full = 2 * r + 1;
-        for (int64_t i = 0; i < H; ++i) {
-            const uint8_t *a = &A[(size_t)(i * W)];
-            uint8_t *b = &Bm[(size_t)(i * W)];
-            int64_t cnt = 0;
-            for (int64_t j = 0; j < std::min<int64_t>(r, W); ++j) cnt += a[j];
-            for (int64_t j = 0; j < W; ++j) {
-                if (j + r < W) cnt += a[j + r];
-                if (j - r - 1 >= 0) cnt -= a[j - r - 1];
-                b[j] = (j - r >= 0 && j + r < W && cnt == full);
-            }
-        }
-        for (int64_t j = 0; j < W; ++j) {
-            int64_t cnt = 0;
-            for (int64_t i = 0; i < std::min<int64_t>(r, H); ++i) cnt += Bm[(size_t)(i * W + j)];
-            for (int64_t i = 0; i < H; ++i) {
-                if (i + r < H) cnt += Bm[(size_t)((i + r) * W + j)];
-                if (i - r - 1 >= 0) cnt -= Bm[(size_t)((i - r - 1) * W + j)];
-                A[(size_t)(i * W + j)] = (i - r >= 0 && i + r < H && cnt == full);
-            }
-        }
-        // the closed set lies inside the bounding box of the thresholded cells, hence inside
-        // the plane; label it with 8-connectivity
-        lab.assign((size_t)(H * W), -1);
-        int32_t nlab = 0;
-        std::vector<int64_t> npix;
-        for (int64_t i = 0; i < H; ++i)
-            for (int64_t j = 0; j < W; ++j) {
-                const size_t c = (size_t)(i * W + j);
-                if (!A[c] || lab[c] >= 0) continue;
-                int64_t cntp = 0;
-                stack.clear();
-                stack.push_back((int64_t)c);
-                lab[c] = nlab;
-                while (!stack.empty()) {
-                    const int64_t q = stack.back();
-                    stack.pop_back();
-                    ++cntp;
-                    const int64_t qi = q / W, qj = q % W;
-                    for (int64_t di = -1; di <= 1; ++di)
-                        for (int64_t dj = -1; dj <= 1; ++dj) {
-                            const int64_t ni = qi + di, nj = qj + dj;
-                            if (ni < 0 || ni >= H || nj < 0 || nj >= W) continue;
-                            const size_t nc = (size_t)(ni * W + nj);
-                            if (A[nc] && lab[nc] < 0) { lab[nc] = nlab; stack.push_back((int64_t)nc); }
-                        }
-                }
-                npix.push_back(cntp);
-                ++nlab;
-            }
-        std::vector<int32_t> peak(nlab, -1);
-        for (size_t i = s; i < e; ++i) {  // thresholded cells, visited in (k, t) order
-            const int32_t pi = order[i];
-            const snd::Pixel &q = px[pi];
-            const int32_t l = lab[(size_t)((q.k - k0) * W + (q.t - t0))];
-            if (l < 0) continue;  // cannot happen: closing keeps every original cell
-            if (peak[l] < 0) { peak[l] = pi; continue; }
-            const snd::Pixel &b = px[peak[l]];
-            if (q.snr > b.snr || (q.snr == b.snr && (q.k < b.k || (q.k == b.k && q.t < b.t)))) peak[l] = pi;
-        }
-        for (int32_t l = 0; l < nlab; ++l) {
-            if (npix[l] < d->n_min || peak[l] < 0) continue;
-            const snd::Pixel &q = px[peak[l]];
-            snd_candidate c{};
-            c.dm_index = q.k;
-            c.width = d->widths[q.widx];
-            c.t = q.t;
-            c.snr = q.snr;
-            c.dm = P.dm[q.k];
-            c.npix = npix[l];
-            out.push_back(c);
-        }
-        s = e;
+    for (size_t pi = 0; pi < px.size(); ++pi) {  // thresholded cells in (k, t) order
+        const snd::Pixel &q = px[pi];
+        const std::vector<Run> &row = cl[(size_t)(q.k - K0)];
+        auto it = std::upper_bound(row.begin(), row.end(), (int64_t)q.t, [](int64_t v, const Run &x) { return v < x.a; });
+        if (it == row.begin()) continue;  // cannot happen: closing keeps every thresholded cell
+        --it;
+        if (q.t > it->b) continue;
+        const int32_t c = uf.f((int32_t)(first[(size_t)(q.k - K0)] + (it - row.begin())));
+        if (peak[(size_t)c] < 0) { peak[(size_t)c] = (int32_t)pi; continue; }
+        const snd::Pixel &b = px[(size_t)peak[(size_t)c]];
+        if (q.snr > b.snr) peak[(size_t)c] = (int32_t)pi;  // ties keep the earlier (k, t) cell
+    }
+    for (size_t c = 0; c < nruns; ++c) {
+        if (uf.f((int32_t)c) != (int32_t)c || peak[c] < 0 || npix[c] < d->n_min) continue;
+        const snd::Pixel &q = px[(size_t)peak[c]];
+        snd_candidate cand{};
+        cand.dm_index = q.k;
+        cand.width = d->widths[q.widx];
+        cand.t = q.t;
+        cand.snr = q.snr;
+        cand.dm = P.dm[q.k];
+        cand.npix = npix[c];
+        out.push_back(cand);
     }
     std::sort(out.begin(), out.end(), [](const snd_candidate &a, const snd_candidate &b) {
         return a.dm_index != b.dm_index ? a.dm_index < b.dm_index : a.t < b.t;

@@ -1,0 +1,143 @@
+// Specialised LDS row-group kernel for final stages whose level-1 nodes all have F1 inputs
+// (regular trees) and whose depth D is known at compile time.  Same staging pipeline as the
+// general row-group kernel; the sums differ only in how the work is scheduled: the F1 inputs
+// of a level-1 node are summed directly (the first one assigned, no zeroing), the node is
+// activated, and levels 2..D are closed with compile-time control.  The node arithmetic, its
+// order and its association are the tree's, so results equal every other schedule.
+#pragma once
+
+#include "group_common.h"
+
+namespace snd {
+
+template <int MODE, typename TI, typename TO, int F1, int D>
+__global__ __launch_bounds__(1024) void k_group_fast(GroupArgs s)
+{
+    using A = typename Acc<MODE>::type;
+    constexpr int T = kGroupTileFast;
+    constexpr int V = T / 64;          // samples per lane
+    constexpr int SC = F1 < 4 ? F1 : 4;  // inputs whose reads are issued together
+    constexpr int NS = D > 1 ? D - 1 : 1;
+    extern __shared__ __align__(16) unsigned char smem[];
+    TI *lds = reinterpret_cast<TI *>(smem);
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const uint32_t L = xcd_remap(blockIdx.x, gridDim.x);
+    const int g = (int)(L % (uint32_t)s.ngroups);
+    const int t0 = (int)(L / (uint32_t)s.ngroups) * T;
+    const int vt = s.n_out - t0 < T ? s.n_out - t0 : T;
+    const int row = __builtin_amdgcn_readfirstlane(as_const(s.grp_rows)[g * kGroupRows + wave]);
+    const_ptr<uint32_t> lb = as_const(s.ldsb) + (int64_t)(g * kGroupRows + wave) * s.n_entries;
+    const unsigned char *srcb = static_cast<const unsigned char *>(s.src);
+    const_ptr<int32_t> batches = as_const(s.batches);
+    const_ptr<int32_t> slots = as_const(s.slots);
+
+    A stk[NS][V];  // stk[j - 2]: partial sum of the open level-j node, j = 2 .. D
+    A out[V];
+#pragma unroll
+    for (int j = 0; j < NS; ++j)
+#pragma unroll
+        for (int v = 0; v < V; ++v) stk[j][v] = 0;
+#pragma unroll
+    for (int v = 0; v < V; ++v) out[v] = 0;
+
+    const int b0 = as_const(s.batch_ptr)[g], b1 = as_const(s.batch_ptr)[g + 1];
+    int n1 = 0, n2 = 0;  // copies outstanding for batches b+1 and b+2
+    if (b0 < b1) issue_windows<TI>(batches, slots, b0, wave, lane, srcb, s.src_pitch, t0, vt, lds);
+    if (b0 + 1 < b1) n1 = issue_windows<TI>(batches, slots, b0 + 1, wave, lane, srcb, s.src_pitch, t0, vt, lds + s.buf_elems);
+    int buf = 0;
+    for (int b = b0; b < b1; ++b) {
+        wait_vmcnt(n1);   // this wave's copies of batch b have landed
+        __syncthreads();  // everyone's have; everyone is done reading batch b - 1
+        n2 = 0;
+        if (b + 2 < b1)
+            n2 = issue_windows<TI>(batches, slots, b + 2, wave, lane, srcb, s.src_pitch, t0, vt,
+                                   lds + (buf == 0 ? 2 : buf - 1) * s.buf_elems);
+        if (row >= 0) {
+            const int ex = batches[4 * b], ey = batches[4 * b + 1];
+            const TI *base = lds + buf * s.buf_elems + lane;
+            for (int c0 = ex; c0 < ey; c0 += F1) {  // one level-1 node per step
+                uint32_t x[F1];
+#pragma unroll
+                for (int u = 0; u < F1; ++u) x[u] = lb[c0 + u];
+                A a1[V];
+#pragma unroll
+                for (int u0 = 0; u0 < F1; u0 += SC) {
+                    A val[SC][V];
+#pragma unroll
+                    for (int u = 0; u < SC; ++u) {
+                        const TI *p = base + (x[u0 + u] & kRowMask);
+#pragma unroll
+                        for (int v = 0; v < V; ++v) {
+                            A y = (A)Load<TI>::get(p + 64 * v);
+                            if constexpr (MODE == SND_MODE_BINARY) y = y != 0;
+                            val[u][v] = y;
+                        }
+                    }
+#pragma unroll
+                    for (int u = 0; u < SC; ++u)
+#pragma unroll
+                        for (int v = 0; v < V; ++v) {
+                            if (u0 + u == 0) a1[v] = val[u][v];
+                            else a1[v] += val[u][v];
+                        }
+                }
+#pragma unroll
+                for (int v = 0; v < V; ++v) {
+                    const A y = activate<MODE>(a1[v], 1, s.src_is_input, s.k_leaf, s.k_int, s.cap);
+                    if constexpr (D == 1) out[v] = y;
+                    else stk[0][v] += y;
+                }
+                const int c = (int)(x[F1 - 1] >> 24);  // levels completed by this node's last input
+#pragma unroll
+                for (int j = 2; j <= D; ++j) {
+                    if (j <= c) {
+#pragma unroll
+                        for (int v = 0; v < V; ++v) {
+                            const A y = activate<MODE>(stk[j - 2][v], j, s.src_is_input, s.k_leaf, s.k_int, s.cap);
+                            stk[j - 2][v] = 0;
+                            if (j == D) out[v] = y;
+                            else stk[(j - 1) < NS ? (j - 1) : 0][v] += y;  // index is j - 1 here
+                        }
+                    }
+                }
+            }
+        }
+        n1 = n2;
+        buf = buf == 2 ? 0 : buf + 1;
+    }
+    if (row >= 0) {
+        TO *dst = static_cast<TO *>(s.dst) + (int64_t)row * s.dst_pitch + t0 + lane;
+#pragma unroll
+        for (int v = 0; v < V; ++v)
+            if (lane + 64 * v < vt) {
+                if constexpr (MODE == SND_MODE_FLOAT) Store<TO>::put(dst + 64 * v, out[v] * s.scale);
+                else Store<TO>::put(dst + 64 * v, out[v]);
+            }
+    }
+}
+
+template <int MODE, typename TI, typename TO, int F1, int D>
+int launch_fast_shape(const GroupArgs &a, int64_t n_out, int lds, hipStream_t st)
+{
+    const int64_t ntt = (n_out + kGroupTileFast - 1) / kGroupTileFast;
+    const int64_t nb = (int64_t)a.ngroups * ntt;
+    if (nb <= 0) return 0;
+    if (nb > 0x7fffffffLL) return (int)hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_group_fast<MODE, TI, TO, F1, D>), dim3((uint32_t)nb), dim3(1024), lds, st, a);
+    return (int)hipGetLastError();
+}
+
+// Every (F1, depth) pair listed by group_fast_supported().
+template <int MODE, typename TI, typename TO>
+int launch_fast_typed(const GroupArgs &a, int64_t n_out, int lds, hipStream_t st)
+{
+#define SND_FAST(F, DD) if (a.f1 == F && a.depth == DD) return launch_fast_shape<MODE, TI, TO, F, DD>(a, n_out, lds, st);
+    SND_FAST(2, 1) SND_FAST(2, 2) SND_FAST(2, 3) SND_FAST(2, 4) SND_FAST(2, 5) SND_FAST(2, 6) SND_FAST(2, 7) SND_FAST(2, 8)
+    SND_FAST(4, 1) SND_FAST(4, 2) SND_FAST(4, 3) SND_FAST(4, 4) SND_FAST(4, 5)
+    SND_FAST(8, 1) SND_FAST(8, 2) SND_FAST(8, 3) SND_FAST(8, 4)
+#undef SND_FAST
+    return (int)hipErrorInvalidValue;
+}
+
+}  // namespace snd

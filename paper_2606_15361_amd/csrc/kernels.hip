@@ -15,6 +15,7 @@
 #include <cstdint>
 
 #include "snd_internal.h"
+#include "stage_common.h"
 
 namespace snd {
 namespace {
@@ -23,76 +24,6 @@ constexpr int kWaves = 4;      // output rows per workgroup (one per wave)
 constexpr int kV = 4;          // time samples per lane (strided by 64)
 constexpr int kTile = 64 * kV; // time samples per wave
 constexpr int kUnroll = 8;     // entries whose loads are issued together
-
-template <typename T> struct Load;
-template <> struct Load<uint8_t> {
-    using acc = int;
-    __device__ static int get(const uint8_t *p) { return *p; }
-};
-template <> struct Load<uint16_t> {
-    __device__ static int get(const uint16_t *p) { return *p; }
-};
-template <> struct Load<float> {
-    __device__ static float get(const float *p) { return *p; }
-};
-struct bf16_t { uint16_t bits; };
-struct f16_t { _Float16 v; };
-template <> struct Load<bf16_t> {
-    __device__ static float get(const bf16_t *p) { return __uint_as_float((uint32_t)p->bits << 16); }
-};
-template <> struct Load<f16_t> {
-    __device__ static float get(const f16_t *p) { return (float)p->v; }
-};
-
-__device__ inline uint16_t f32_to_bf16_rne(float f)
-{
-    uint32_t u = __float_as_uint(f);
-    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);  // quiet NaN
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
-}
-
-template <typename T> struct Store;
-template <> struct Store<uint8_t> {
-    template <typename A> __device__ static void put(uint8_t *p, A v) { *p = (uint8_t)v; }
-};
-template <> struct Store<uint16_t> {
-    template <typename A> __device__ static void put(uint16_t *p, A v) { *p = (uint16_t)v; }
-};
-template <> struct Store<float> {
-    template <typename A> __device__ static void put(float *p, A v) { *p = (float)v; }
-};
-template <> struct Store<bf16_t> {
-    template <typename A> __device__ static void put(bf16_t *p, A v) { p->bits = f32_to_bf16_rne((float)v); }
-};
-template <> struct Store<f16_t> {
-    template <typename A> __device__ static void put(f16_t *p, A v) { p->v = (_Float16)(float)v; }
-};
-
-template <int MODE> struct Acc { using type = int; };
-template <> struct Acc<SND_MODE_FLOAT> { using type = float; };
-
-// Node activation at relative level j of the stage (Methods, "Tree activation modes").
-template <int MODE, typename A>
-__device__ inline A activate(A a, int j, const StageArgs &s)
-{
-    if constexpr (MODE == SND_MODE_BINARY) {
-        int k = (j == 1 && s.src_is_input) ? s.k_leaf : s.k_int;
-        return a >= k ? 1 : 0;
-    } else if constexpr (MODE == SND_MODE_GRADED) {
-        return a < s.cap ? a : s.cap;
-    } else {
-        return a;
-    }
-}
-
-// Blocks are dealt round-robin to the 8 XCDs; remap so that each XCD (own L2) works on a
-// contiguous range of logical tiles, which share source rows.
-__device__ inline uint32_t xcd_remap(uint32_t b, uint32_t nb)
-{
-    uint32_t x = b & 7u, i = b >> 3, q = nb >> 3, r = nb & 7u;
-    return x * q + (x < r ? x : r) + i;
-}
 
 template <int MODE, typename TI, typename TO, int MAXD>
 __global__ __launch_bounds__(256) void k_stage(StageArgs s)
@@ -126,48 +57,45 @@ __global__ __launch_bounds__(256) void k_stage(StageArgs s)
     for (int v = 0; v < kV; ++v) out[v] = 0;
 
     const TI *src = static_cast<const TI *>(s.src);
-    for (uint32_t e0 = beg; e0 < end; e0 += kUnroll) {
-        const int n = (int)(end - e0) < kUnroll ? (int)(end - e0) : kUnroll;
+    uint32_t e0 = beg;
+    // full chunks: all table entries, then all loads, then the sums (no per-entry guards, so the
+    // loads of a chunk are in flight together)
+    for (; e0 + kUnroll <= end; e0 += kUnroll) {
+        Entry en[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) en[u] = s.ent[e0 + u];
         A val[kUnroll][kV];
-        int cl[kUnroll];
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
-            cl[u] = 0;
+            const TI *p = src + (int64_t)(en[u].rowc & kRowMask) * s.src_pitch + en[u].off + t0 + lane;
 #pragma unroll
-            for (int v = 0; v < kV; ++v) val[u][v] = 0;
-            if (u < n) {
-                const Entry en = s.ent[e0 + u];
-                cl[u] = (int)(en.rowc >> 24);
-                const TI *p = src + (int64_t)(en.rowc & kRowMask) * s.src_pitch + en.off + t0 + lane;
-#pragma unroll
-                for (int v = 0; v < kV; ++v)
-                    if (ok[v]) {
-                        A x = (A)Load<TI>::get(p + 64 * v);
-                        if constexpr (MODE == SND_MODE_BINARY) x = x != 0;
-                        val[u][v] = x;
-                    }
+            for (int v = 0; v < kV; ++v) {
+                A x = 0;
+                if (ok[v]) x = (A)Load<TI>::get(p + 64 * v);
+                if constexpr (MODE == SND_MODE_BINARY) x = x != 0;
+                val[u][v] = x;
             }
         }
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
-            if (u < n) {
 #pragma unroll
-                for (int v = 0; v < kV; ++v) acc[0][v] += val[u][v];
-                const int c = cl[u];
-#pragma unroll
-                for (int j = 1; j <= MAXD; ++j) {
-                    if (j <= c) {
-#pragma unroll
-                        for (int v = 0; v < kV; ++v) {
-                            A y = activate<MODE>(acc[j - 1][v], j, s);
-                            acc[j - 1][v] = 0;
-                            if (j == depth) out[v] = y;
-                            else if (j < MAXD) acc[j][v] += y;
-                        }
-                    }
-                }
-            }
+            for (int v = 0; v < kV; ++v) acc[0][v] += val[u][v];
+            close_levels<MODE, A, MAXD, kV>(acc, out, (int)(en[u].rowc >> 24), depth, s.src_is_input, s.k_leaf,
+                                            s.k_int, s.cap);
         }
+    }
+    for (; e0 < end; ++e0) {
+        const Entry en = s.ent[e0];
+        const TI *p = src + (int64_t)(en.rowc & kRowMask) * s.src_pitch + en.off + t0 + lane;
+#pragma unroll
+        for (int v = 0; v < kV; ++v) {
+            A x = 0;
+            if (ok[v]) x = (A)Load<TI>::get(p + 64 * v);
+            if constexpr (MODE == SND_MODE_BINARY) x = x != 0;
+            acc[0][v] += x;
+        }
+        close_levels<MODE, A, MAXD, kV>(acc, out, (int)(en.rowc >> 24), depth, s.src_is_input, s.k_leaf, s.k_int,
+                                        s.cap);
     }
 
     TO *dst = static_cast<TO *>(s.dst) + (int64_t)row * s.dst_pitch + t0 + lane;
@@ -199,16 +127,14 @@ int launch_typed(const StageArgs &a, int64_t max_len, hipStream_t st)
     return (int)hipGetLastError();
 }
 
-template <typename TI>
-int launch_float_out(int dst_dt, const StageArgs &a, int64_t max_len, hipStream_t st)
-{
-    switch (dst_dt) {
-    case SND_DT_F32: return launch_typed<SND_MODE_FLOAT, TI, float>(a, max_len, st);
-    case SND_DT_BF16: return launch_typed<SND_MODE_FLOAT, TI, bf16_t>(a, max_len, st);
-    case SND_DT_F16: return launch_typed<SND_MODE_FLOAT, TI, f16_t>(a, max_len, st);
+struct StageLauncher {
+    const StageArgs &a;
+    int64_t max_len;
+    template <int MODE, typename TI, typename TO> int run(hipStream_t st) const
+    {
+        return launch_typed<MODE, TI, TO>(a, max_len, st);
     }
-    return (int)hipErrorInvalidValue;
-}
+};
 
 // ---------------------------------------------------------------------------------------
 // Delta encoder (Methods, "Input encoding"): level = number of thresholds z exceeds.
@@ -267,22 +193,7 @@ __global__ __launch_bounds__(256) void k_cast(const float *src, int64_t sp, int6
 
 int launch_stage(int mode, int src_dt, int dst_dt, const StageArgs &a, int64_t max_len, void *stream)
 {
-    hipStream_t st = (hipStream_t)stream;
-    if (mode == SND_MODE_BINARY) {
-        if (src_dt == SND_DT_U8 && dst_dt == SND_DT_U8) return launch_typed<SND_MODE_BINARY, uint8_t, uint8_t>(a, max_len, st);
-    } else if (mode == SND_MODE_GRADED) {
-        if (src_dt == SND_DT_U8 && dst_dt == SND_DT_U8) return launch_typed<SND_MODE_GRADED, uint8_t, uint8_t>(a, max_len, st);
-        if (src_dt == SND_DT_U8 && dst_dt == SND_DT_U16) return launch_typed<SND_MODE_GRADED, uint8_t, uint16_t>(a, max_len, st);
-        if (src_dt == SND_DT_U16 && dst_dt == SND_DT_U16) return launch_typed<SND_MODE_GRADED, uint16_t, uint16_t>(a, max_len, st);
-        if (src_dt == SND_DT_U16 && dst_dt == SND_DT_U8) return launch_typed<SND_MODE_GRADED, uint16_t, uint8_t>(a, max_len, st);
-    } else if (mode == SND_MODE_FLOAT) {
-        switch (src_dt) {
-        case SND_DT_F32: return launch_float_out<float>(dst_dt, a, max_len, st);
-        case SND_DT_BF16: return launch_float_out<bf16_t>(dst_dt, a, max_len, st);
-        case SND_DT_F16: return launch_float_out<f16_t>(dst_dt, a, max_len, st);
-        }
-    }
-    return (int)hipErrorInvalidValue;
+    return dispatch_types(mode, src_dt, dst_dt, StageLauncher{a, max_len}, (hipStream_t)stream);
 }
 
 int launch_encode(const float *z, int64_t zp, int time_major, int nchan, int64_t nsamp, const float *thr, int nthr,

@@ -1,0 +1,13 @@
+// Instances of the specialised LDS row-group kernel for the binary tree mode.
+#include "group_fast.h"
+
+namespace snd {
+
+int launch_group_fast_binary(int src_dt, int dst_dt, const GroupArgs &a, int64_t n_out, int lds, void *stream)
+{
+    hipStream_t st = (hipStream_t)stream;
+    if (src_dt == SND_DT_U8 && dst_dt == SND_DT_U8) return launch_fast_typed<SND_MODE_BINARY, uint8_t, uint8_t>(a, n_out, lds, st);
+    return (int)hipErrorInvalidValue;
+}
+
+}  // namespace snd

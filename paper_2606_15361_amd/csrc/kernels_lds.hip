@@ -1,0 +1,291 @@
+// LDS-staged SND stage kernels for gfx950.
+//
+// k_group (final stage): a 1024-thread workgroup evaluates kGroupRows DMs adjacent in value
+// over kGroupTile samples.  Adjacent DMs use the same lower-level neuron rows at nearly the
+// same shifts, so for each batch of entries the workgroup stages one window per distinct
+// (source row, offset cluster) in LDS, then every wave walks its DM's entries reading the
+// shifted samples from LDS and evaluates the sub-tree in registers exactly as the generic
+// stage kernel does (same node arithmetic, order and association).  Windows are copied from
+// global memory straight into LDS (global_load_lds) two batches ahead into a ring of three
+// buffers, so every copy has two batches of sums to land and one barrier per batch suffices.
+//
+// k_anchored (first stage from the input): one 256-thread workgroup per (tree node, window of
+// kAnchorTile reference samples).  Every neuron row of a node is anchored at its own smallest
+// reference delay, so the neurons of one node read the node's channels at widely different
+// offsets; staging the node's channels over the absolute window once and producing the
+// overlapping segment of every neuron row reads each input sample once instead of once per
+// neuron.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "group_common.h"
+
+namespace snd {
+namespace {
+
+template <int MODE, typename TI, typename TO, int MAXD>
+__global__ __launch_bounds__(1024) void k_group(GroupArgs s)
+{
+    using A = typename Acc<MODE>::type;
+    constexpr int V = kGroupTile / 64;  // samples per lane
+    constexpr int KS = kGroupSlotsPerWave;
+    constexpr int EU = MAXD <= 8 ? 8 : 4;  // entries per step
+    constexpr int ES = (int)sizeof(TI);
+    constexpr int EPD = 4 / ES;  // elements per dword
+    extern __shared__ __align__(16) unsigned char smem[];
+    TI *lds = reinterpret_cast<TI *>(smem);
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const uint32_t L = xcd_remap(blockIdx.x, gridDim.x);
+    const int g = (int)(L % (uint32_t)s.ngroups);
+    const int t0 = (int)(L / (uint32_t)s.ngroups) * kGroupTile;
+    const int vt = s.n_out - t0 < kGroupTile ? s.n_out - t0 : kGroupTile;
+    const int row = __builtin_amdgcn_readfirstlane(as_const(s.grp_rows)[g * kGroupRows + wave]);
+    const_ptr<uint32_t> lb = as_const(s.ldsb) + (int64_t)(g * kGroupRows + wave) * s.n_entries;
+    const unsigned char *srcb = static_cast<const unsigned char *>(s.src);
+    const_ptr<int32_t> batches = as_const(s.batches);  // 4 ints per batch
+    const_ptr<int32_t> slots = as_const(s.slots);      // 4 ints per window
+
+    A acc[MAXD][V];
+    A out[V];
+#pragma unroll
+    for (int j = 0; j < MAXD; ++j)
+#pragma unroll
+        for (int v = 0; v < V; ++v) acc[j][v] = 0;
+#pragma unroll
+    for (int v = 0; v < V; ++v) out[v] = 0;
+
+    // asynchronous copy of this wave's windows of batch b into LDS buffer buf
+    auto issue = [&](int b, int buf) {
+        return issue_windows<TI>(batches, slots, b, wave, lane, srcb, s.src_pitch, t0, vt, lds + buf * s.buf_elems);
+    };
+
+    const int b0 = as_const(s.batch_ptr)[g], b1 = as_const(s.batch_ptr)[g + 1];
+    int n1 = 0, n2 = 0;  // copies outstanding for batches b+1 and b+2
+    if (b0 < b1) issue(b0, 0);
+    if (b0 + 1 < b1) n1 = issue(b0 + 1, 1);
+    int buf = 0;
+    for (int b = b0; b < b1; ++b) {
+        wait_vmcnt(n1);   // this wave's copies of batch b have landed
+        __syncthreads();  // everyone's have; everyone is done reading batch b - 1
+        n2 = 0;
+        if (b + 2 < b1) n2 = issue(b + 2, buf == 0 ? 2 : buf - 1);  // the buffer of batch b - 1
+        if (row >= 0) {
+            const int ex = batches[4 * b], ey = batches[4 * b + 1];
+            const TI *base = lds + buf * s.buf_elems + lane;
+            int e0 = ex;
+            // full chunks: all table words, then all LDS reads, then the sums
+            for (; e0 + EU <= ey; e0 += EU) {
+                uint32_t x[EU];
+#pragma unroll
+                for (int u = 0; u < EU; ++u) x[u] = lb[e0 + u];
+                A val[EU][V];
+#pragma unroll
+                for (int u = 0; u < EU; ++u) {
+                    const TI *p = base + (x[u] & kRowMask);
+#pragma unroll
+                    for (int v = 0; v < V; ++v) {
+                        A y = (A)Load<TI>::get(p + 64 * v);
+                        if constexpr (MODE == SND_MODE_BINARY) y = y != 0;
+                        val[u][v] = y;
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < EU; ++u) {
+#pragma unroll
+                    for (int v = 0; v < V; ++v) acc[0][v] += val[u][v];
+                    close_levels<MODE, A, MAXD, V>(acc, out, (int)(x[u] >> 24), s.depth, s.src_is_input, s.k_leaf,
+                                                   s.k_int, s.cap);
+                }
+            }
+            for (; e0 < ey; ++e0) {
+                const uint32_t x = lb[e0];
+                const TI *p = base + (x & kRowMask);
+#pragma unroll
+                for (int v = 0; v < V; ++v) {
+                    A y = (A)Load<TI>::get(p + 64 * v);
+                    if constexpr (MODE == SND_MODE_BINARY) y = y != 0;
+                    acc[0][v] += y;
+                }
+                close_levels<MODE, A, MAXD, V>(acc, out, (int)(x >> 24), s.depth, s.src_is_input, s.k_leaf, s.k_int,
+                                               s.cap);
+            }
+        }
+        n1 = n2;
+        buf = buf == 2 ? 0 : buf + 1;
+    }
+    if (row >= 0) {
+        TO *dst = static_cast<TO *>(s.dst) + (int64_t)row * s.dst_pitch + t0 + lane;
+#pragma unroll
+        for (int v = 0; v < V; ++v)
+            if (lane + 64 * v < vt) {
+                if constexpr (MODE == SND_MODE_FLOAT) Store<TO>::put(dst + 64 * v, out[v] * s.scale);
+                else Store<TO>::put(dst + 64 * v, out[v]);
+            }
+    }
+}
+
+template <int MODE, typename TI, typename TO, int MAXD>
+__global__ __launch_bounds__(256) void k_anchored(AnchorArgs s)
+{
+    using A = typename Acc<MODE>::type;
+    constexpr int V = kAnchorTile / 64;
+    constexpr int EU = 4;
+    extern __shared__ __align__(16) unsigned char smem[];
+    TI *lds = reinterpret_cast<TI *>(smem);
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int node = s.tiles[2 * blockIdx.x];
+    const int tau0 = s.tiles[2 * blockIdx.x + 1];
+    const int *nd = s.nodes + 6 * node;
+    const int r0 = nd[0], r1 = nd[1], c0 = nd[2], c1 = nd[3], rho_max = nd[4];
+    const int wst = kAnchorTile + rho_max;
+    const TI *src = static_cast<const TI *>(s.src);
+    for (int c = c0; c < c1; ++c) {  // stage the node's channels over [tau0, tau0 + wst)
+        const TI *p = src + (int64_t)c * s.src_pitch;
+        TI *l = lds + (c - c0) * wst;
+        for (int j0 = 0; j0 < wst; j0 += 4 * 256) {
+            TI tmp[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int j = j0 + tid + 256 * u;
+                const int64_t idx = (int64_t)tau0 + j;
+                tmp[u] = (j < wst && idx < s.src_len) ? p[idx] : Zero<TI>::get();
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int j = j0 + tid + 256 * u;
+                if (j < wst) l[j] = tmp[u];
+            }
+        }
+    }
+    __syncthreads();
+    for (int r = r0 + wave; r < r1; r += 4) {
+        const int lo = s.row_lo[r], len = s.row_len[r];
+        const int i0 = tau0 - lo;  // output index at the window start
+        if (i0 >= len || i0 + kAnchorTile <= 0) continue;
+        A acc[MAXD][V];
+        A out[V];
+#pragma unroll
+        for (int j = 0; j < MAXD; ++j)
+#pragma unroll
+            for (int v = 0; v < V; ++v) acc[j][v] = 0;
+#pragma unroll
+        for (int v = 0; v < V; ++v) out[v] = 0;
+        const uint32_t eb = s.row_ptr[r], ee = s.row_ptr[r + 1];
+        uint32_t e0 = eb;
+        for (; e0 + EU <= ee; e0 += EU) {  // full chunks: table words, then LDS reads, then sums
+            Entry en[EU];
+#pragma unroll
+            for (int u = 0; u < EU; ++u) en[u] = s.ent[e0 + u];
+            A val[EU][V];
+#pragma unroll
+            for (int u = 0; u < EU; ++u) {
+                const TI *p = lds + ((int)(en[u].rowc & kRowMask) - c0) * wst + (en[u].off - lo) + lane;
+#pragma unroll
+                for (int v = 0; v < V; ++v) {
+                    A y = (A)Load<TI>::get(p + 64 * v);
+                    if constexpr (MODE == SND_MODE_BINARY) y = y != 0;
+                    val[u][v] = y;
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < EU; ++u) {
+#pragma unroll
+                for (int v = 0; v < V; ++v) acc[0][v] += val[u][v];
+                close_levels<MODE, A, MAXD, V>(acc, out, (int)(en[u].rowc >> 24), s.depth, 1, s.k_leaf, s.k_int,
+                                               s.cap);
+            }
+        }
+        for (; e0 < ee; ++e0) {
+            const Entry en = s.ent[e0];
+            const TI *p = lds + ((int)(en.rowc & kRowMask) - c0) * wst + (en.off - lo) + lane;
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                A y = (A)Load<TI>::get(p + 64 * v);
+                if constexpr (MODE == SND_MODE_BINARY) y = y != 0;
+                acc[0][v] += y;
+            }
+            close_levels<MODE, A, MAXD, V>(acc, out, (int)(en.rowc >> 24), s.depth, 1, s.k_leaf, s.k_int, s.cap);
+        }
+        TO *dst = static_cast<TO *>(s.dst) + (int64_t)r * s.dst_pitch + i0 + lane;
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            const int i = i0 + lane + 64 * v;
+            if (i >= 0 && i < len) {
+                if constexpr (MODE == SND_MODE_FLOAT) Store<TO>::put(dst + 64 * v, out[v] * s.scale);
+                else Store<TO>::put(dst + 64 * v, out[v]);
+            }
+        }
+    }
+}
+
+template <int MODE, typename TI, typename TO>
+int launch_group_typed(const GroupArgs &a, int64_t n_out, int lds, hipStream_t st)
+{
+    const int64_t ntt = (n_out + kGroupTile - 1) / kGroupTile;
+    const int64_t nb = (int64_t)a.ngroups * ntt;
+    if (nb <= 0) return 0;
+    if (nb > 0x7fffffffLL) return (int)hipErrorInvalidValue;
+    dim3 grid((uint32_t)nb), block(1024);
+    if (a.depth <= 1) hipLaunchKernelGGL((k_group<MODE, TI, TO, 1>), grid, block, lds, st, a);
+    else if (a.depth <= 2) hipLaunchKernelGGL((k_group<MODE, TI, TO, 2>), grid, block, lds, st, a);
+    else if (a.depth <= 4) hipLaunchKernelGGL((k_group<MODE, TI, TO, 4>), grid, block, lds, st, a);
+    else if (a.depth <= 8) hipLaunchKernelGGL((k_group<MODE, TI, TO, 8>), grid, block, lds, st, a);
+    else hipLaunchKernelGGL((k_group<MODE, TI, TO, 16>), grid, block, lds, st, a);
+    return (int)hipGetLastError();
+}
+
+template <int MODE, typename TI, typename TO>
+int launch_anchored_typed(const AnchorArgs &a, int64_t ntiles, int lds, hipStream_t st)
+{
+    if (ntiles <= 0) return 0;
+    if (ntiles > 0x7fffffffLL || a.depth > 8) return (int)hipErrorInvalidValue;
+    dim3 grid((uint32_t)ntiles), block(256);
+    if (a.depth <= 1) hipLaunchKernelGGL((k_anchored<MODE, TI, TO, 1>), grid, block, lds, st, a);
+    else if (a.depth <= 2) hipLaunchKernelGGL((k_anchored<MODE, TI, TO, 2>), grid, block, lds, st, a);
+    else if (a.depth <= 4) hipLaunchKernelGGL((k_anchored<MODE, TI, TO, 4>), grid, block, lds, st, a);
+    else hipLaunchKernelGGL((k_anchored<MODE, TI, TO, 8>), grid, block, lds, st, a);
+    return (int)hipGetLastError();
+}
+
+struct GroupLauncher {
+    const GroupArgs &a;
+    int64_t n_out;
+    int lds;
+    template <int MODE, typename TI, typename TO> int run(hipStream_t st) const
+    {
+        return launch_group_typed<MODE, TI, TO>(a, n_out, lds, st);
+    }
+};
+
+struct AnchorLauncher {
+    const AnchorArgs &a;
+    int64_t ntiles;
+    int lds;
+    template <int MODE, typename TI, typename TO> int run(hipStream_t st) const
+    {
+        return launch_anchored_typed<MODE, TI, TO>(a, ntiles, lds, st);
+    }
+};
+
+}  // namespace
+
+int launch_group(int mode, int src_dt, int dst_dt, const GroupArgs &a, int64_t n_out, int lds_bytes, void *stream)
+{
+    if (a.f1 > 0) {
+        if (mode == SND_MODE_BINARY) return launch_group_fast_binary(src_dt, dst_dt, a, n_out, lds_bytes, stream);
+        if (mode == SND_MODE_GRADED) return launch_group_fast_graded(src_dt, dst_dt, a, n_out, lds_bytes, stream);
+        if (mode == SND_MODE_FLOAT) return launch_group_fast_float(src_dt, dst_dt, a, n_out, lds_bytes, stream);
+        return (int)hipErrorInvalidValue;
+    }
+    return dispatch_types(mode, src_dt, dst_dt, GroupLauncher{a, n_out, lds_bytes}, (hipStream_t)stream);
+}
+
+int launch_anchored(int mode, int src_dt, int dst_dt, const AnchorArgs &a, int64_t ntiles, int lds_bytes, void *stream)
+{
+    return dispatch_types(mode, src_dt, dst_dt, AnchorLauncher{a, ntiles, lds_bytes}, (hipStream_t)stream);
+}
+
+}  // namespace snd

@@ -96,6 +96,192 @@ bool valid_dtype_pair(int mode, int in_dt, int node_dt, int cap)
     return false;
 }
 
+// Final stage in LDS groups: kGroupRows rows (DMs adjacent in value) per workgroup share one
+// staged window per distinct source row of each entry.  Every row of the final stage walks the
+// same tree, so all rows have the same entry count and closing pattern.  Returns false (and
+// leaves the stage on the generic kernel) when one entry alone does not fit the LDS budget.
+bool build_group_lds(const PlanImpl &p, Stage &S, bool allow_fast)
+{
+    const int64_t rows = S.rows;
+    if (rows < 1) return false;
+    const int32_t ne = (int32_t)(S.row_ptr[1] - S.row_ptr[0]);
+    for (int64_t r = 0; r < rows; ++r) {
+        if ((int32_t)(S.row_ptr[r + 1] - S.row_ptr[r]) != ne || S.row_len[r] != S.row_len[0]) return false;
+        for (int32_t e = 0; e < ne; ++e)
+            if ((S.ent[S.row_ptr[r] + e].rowc >> 24) != (S.ent[e].rowc >> 24)) return false;
+    }
+    // Regular level-1 nodes (every f1-th input closes a node, nothing else does) allow the
+    // specialised kernel, which sums each level-1 node's inputs directly.
+    int32_t f1 = 0;
+    {
+        int32_t first = -1;
+        for (int32_t e = 0; e < ne && first < 0; ++e)
+            if ((S.ent[e].rowc >> 24) >= 1) first = e;
+        f1 = first + 1;
+        bool reg = f1 > 0 && ne % f1 == 0;
+        for (int32_t e = 0; e < ne && reg; ++e)
+            if (((S.ent[e].rowc >> 24) >= 1) != ((e + 1) % f1 == 0)) reg = false;
+        if (!allow_fast || !reg || !group_fast_supported(f1, S.depth) ||
+            !group_fast_types(p.desc.mode, S.src_dtype, S.dst_dtype))
+            f1 = 0;
+    }
+    const int tile = f1 ? kGroupTileFast : kGroupTile;
+    const int unit = f1 ? f1 : 1;  // batches end on level-1 node boundaries
+    const int es = dtype_size(S.src_dtype);
+    const int64_t budget = (f1 ? kGroupFastLdsBytes : kGroupLdsBytes) / es;
+    const int32_t epd = 16 / es;  // elements per 16-byte copy unit
+    // LDS elements of one window: its span plus one tile, from a 16-byte boundary, whole units
+    auto slot_elems = [&](int32_t lo, int32_t span) {
+        return (int64_t)round_up((int64_t)(lo % epd) + span + tile, epd);
+    };
+    std::vector<int32_t> order(rows);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return p.dm[a] < p.dm[b]; });
+    const int64_t ng = (rows + kGroupRows - 1) / kGroupRows;
+    std::vector<int32_t> grp_rows((size_t)(ng * kGroupRows), -1);
+    for (int64_t i = 0; i < rows; ++i) grp_rows[(size_t)i] = order[(size_t)i];
+    std::vector<int32_t> batch_ptr(1, 0), batches, slots;
+    std::vector<uint32_t> ldsb((size_t)(ng * kGroupRows * ne), 0);
+    int64_t max_elems = 0;
+    const int32_t max_slots = kGroupRows * kGroupSlotsPerWave;
+    // windows of one entry: the group's (source row, offset) reads, clustered per source row
+    // so that each window spans at most kGroupMaxSpan offsets
+    struct Rd { uint32_t row; int32_t off; int w; };
+    struct Src { uint32_t row; int32_t lo, hi; };
+    std::vector<Rd> rd;
+    std::vector<Src> srcs;
+    std::vector<int32_t> slot_of(kGroupRows);
+    std::vector<Src> unit_srcs;
+    std::vector<int32_t> unit_nsrc;
+    for (int64_t g = 0; g < ng; ++g) {
+        int32_t e0 = 0, s0 = (int32_t)(slots.size() / 4);
+        int64_t elems = 0;
+        for (int32_t eu = 0; eu < ne; eu += unit) {
+        // windows of every input of this unit, then one decision where the batch ends
+        unit_srcs.clear();
+        unit_nsrc.clear();
+        std::vector<std::vector<int32_t>> unit_slot_of;
+        for (int32_t e = eu; e < eu + unit; ++e) {
+            rd.clear();
+            for (int w = 0; w < kGroupRows; ++w) {
+                const int32_t r = grp_rows[(size_t)(g * kGroupRows + w)];
+                if (r < 0) continue;
+                const Entry &en = S.ent[S.row_ptr[r] + e];
+                rd.push_back({en.rowc & kRowMask, en.off, w});
+            }
+            std::sort(rd.begin(), rd.end(), [](const Rd &a, const Rd &b) {
+                return a.row != b.row ? a.row < b.row : a.off < b.off;
+            });
+            srcs.clear();
+            for (const Rd &x : rd) {
+                if (srcs.empty() || srcs.back().row != x.row || x.off - srcs.back().lo > kGroupMaxSpan)
+                    srcs.push_back({x.row, x.off, x.off});
+                srcs.back().hi = x.off;
+                slot_of[x.w] = (int32_t)srcs.size() - 1;
+            }
+            unit_nsrc.push_back((int32_t)srcs.size());
+            unit_srcs.insert(unit_srcs.end(), srcs.begin(), srcs.end());
+            unit_slot_of.push_back(slot_of);
+        }
+        int64_t need = 0;
+        for (const Src &s : unit_srcs) need += slot_elems(s.lo, s.hi - s.lo);
+        if (need > budget || (int32_t)unit_srcs.size() > max_slots) return false;
+        const int32_t nslot_batch = (int32_t)(slots.size() / 4) - s0;
+        if (elems + need > budget || nslot_batch + (int32_t)unit_srcs.size() > max_slots) {  // close the batch
+            batches.insert(batches.end(), {e0, eu, s0, (int32_t)(slots.size() / 4)});
+            max_elems = std::max(max_elems, elems);
+            e0 = eu;
+            s0 = (int32_t)(slots.size() / 4);
+            elems = 0;
+        }
+        size_t si0 = 0;
+        for (int32_t e = eu; e < eu + unit; ++e) {
+            const int32_t ns = unit_nsrc[(size_t)(e - eu)];
+            std::vector<int32_t> slot_lds((size_t)ns);
+            for (int32_t i = 0; i < ns; ++i) {
+                const Src &sr = unit_srcs[si0 + (size_t)i];
+                // 16-byte aligned footprint; the window starts `head` elements into it so that
+                // the kernel can copy whole 16-byte units from the (16-byte aligned) source row
+                const int32_t head = sr.lo % epd;
+                slot_lds[(size_t)i] = (int32_t)elems + head;
+                slots.insert(slots.end(), {(int32_t)sr.row, sr.lo, sr.hi - sr.lo, slot_lds[(size_t)i]});
+                elems += slot_elems(sr.lo, sr.hi - sr.lo);
+            }
+            const std::vector<int32_t> &so = unit_slot_of[(size_t)(e - eu)];
+            for (int w = 0; w < kGroupRows; ++w) {
+                const int32_t r = grp_rows[(size_t)(g * kGroupRows + w)];
+                if (r < 0) continue;
+                const Entry &en = S.ent[S.row_ptr[r] + e];
+                const Src &sr = unit_srcs[si0 + (size_t)so[(size_t)w]];
+                const uint32_t base = (uint32_t)(slot_lds[(size_t)so[(size_t)w]] + (en.off - sr.lo));
+                const uint32_t closes = S.ent[e].rowc & ~kRowMask;  // identical for every row
+                ldsb[(size_t)((g * kGroupRows + w) * ne + e)] = base | closes;
+            }
+            si0 += (size_t)ns;
+        }
+        }
+        batches.insert(batches.end(), {e0, ne, s0, (int32_t)(slots.size() / 4)});
+        max_elems = std::max(max_elems, elems);
+        batch_ptr.push_back((int32_t)(batches.size() / 4));
+    }
+    if (max_elems > budget || max_elems >= (1 << 24)) return false;
+    S.kernel = kKernelGroupLds;
+    S.ngroups = ng;
+    S.n_entries = ne;
+    S.group_f1 = f1;
+    S.group_tile = tile;
+    S.lds_buf_elems = (int32_t)(round_up(max_elems * es, 16) / es);
+    S.lds_bytes = kGroupBuffers * S.lds_buf_elems * es;  // batches b+1, b+2 land while b is read
+    S.grp_rows = std::move(grp_rows);
+    S.batch_ptr = std::move(batch_ptr);
+    S.batches = std::move(batches);
+    S.slots = std::move(slots);
+    S.ldsb = std::move(ldsb);
+    return true;
+}
+
+// First stage anchored on the input: one workgroup per (node, window of kAnchorTile reference
+// samples) stages the node's channels once and produces the overlapping segment of every
+// neuron row of that node.  Needs all entries of a node's rows to read that node's channels
+// and the node's staged window to fit the LDS budget.
+bool build_anchored(const PlanImpl &p, Stage &S)
+{
+    const Level &D = p.lev[S.dst_level];
+    const int es = dtype_size(S.src_dtype);
+    if (S.depth > 8) return false;
+    std::vector<int32_t> nodes, tiles;
+    int64_t lds_max = 0;
+    for (int q = 0; q < D.nnodes; ++q) {
+        const int64_t r0 = D.row_base[q], r1 = r0 + D.nneu[q];
+        const int32_t c0 = D.chlo[q], c1 = D.chhi[q];
+        int32_t rho_max = 0;
+        int64_t tlo = INT64_MAX, thi = INT64_MIN;
+        for (int64_t r = r0; r < r1; ++r) {
+            for (uint32_t e = S.row_ptr[r]; e < S.row_ptr[r + 1]; ++e) {
+                const int32_t c = (int32_t)(S.ent[e].rowc & kRowMask);
+                const int32_t rho = S.ent[e].off - D.lo[r];
+                if (c < c0 || c >= c1 || rho < 0) return false;
+                rho_max = std::max(rho_max, rho);
+            }
+            tlo = std::min<int64_t>(tlo, D.lo[r]);
+            thi = std::max<int64_t>(thi, D.lo[r] + S.row_len[r]);
+        }
+        const int64_t lds = (int64_t)(c1 - c0) * (kAnchorTile + rho_max) * es;
+        if (lds > kAnchorLdsBytes) return false;
+        lds_max = std::max(lds_max, lds);
+        const int32_t ni = (int32_t)(nodes.size() / 6);
+        nodes.insert(nodes.end(), {(int32_t)r0, (int32_t)r1, c0, c1, rho_max, 0});
+        for (int64_t t = tlo; t < thi; t += kAnchorTile) tiles.insert(tiles.end(), {ni, (int32_t)t});
+    }
+    S.kernel = kKernelAnchored;
+    S.lds_bytes = (int32_t)round_up(lds_max, 16);
+    S.nodes = std::move(nodes);
+    S.ntiles = (int64_t)(tiles.size() / 2);
+    S.tiles = std::move(tiles);
+    S.row_lo.assign(D.lo.begin(), D.lo.end());
+    return true;
+}
+
 }  // namespace
 
 snd_status build_plan(const snd_plan_desc &d, PlanImpl &p, std::string &err)
@@ -106,7 +292,7 @@ snd_status build_plan(const snd_plan_desc &d, PlanImpl &p, std::string &err)
         err = "nchan, ndm, nsamp must be >= 1, tsamp_s > 0 and freq/dm non-null";
         return SND_ERR_INVALID;
     }
-    for (int i = 0; i < 8; ++i)
+    for (int i = 0; i < 7; ++i)
         if (d.reserved[i]) { err = "reserved descriptor fields must be zero"; return SND_ERR_INVALID; }
     if (d.branching < 2 || d.cluster < 1) { err = "branching must be >= 2 and cluster >= 1"; return SND_ERR_INVALID; }
     if (d.mode < SND_MODE_BINARY || d.mode > SND_MODE_FLOAT) { err = "unknown mode"; return SND_ERR_INVALID; }
@@ -354,18 +540,50 @@ snd_status build_plan(const snd_plan_desc &d, PlanImpl &p, std::string &err)
         src = dsts[si];
     }
 
+    // ---------------- kernel choice per stage ----------------
+    for (Stage &S : p.stages) {
+        S.kernel = kKernelGeneric;
+        if (d.generic_kernels) continue;
+        if (S.final_stage && (build_group_lds(p, S, true) || build_group_lds(p, S, false))) continue;
+        if (!S.final_stage && S.src_level < 0) build_anchored(p, S);
+    }
+
     // ---------------- table image and workspace layout ----------------
     int64_t off = 0;
+    auto reserve = [&](int64_t bytes) {
+        int64_t o = off;
+        off = round_up(off + bytes, 256);
+        return o;
+    };
     for (Stage &S : p.stages) {
-        S.off_row_ptr = off; off = round_up(off + (int64_t)S.row_ptr.size() * 4, 256);
-        S.off_row_len = off; off = round_up(off + (int64_t)S.row_len.size() * 4, 256);
-        S.off_ent = off; off = round_up(off + (int64_t)S.ent.size() * 8, 256);
+        S.off_row_ptr = reserve((int64_t)S.row_ptr.size() * 4);
+        S.off_row_len = reserve((int64_t)S.row_len.size() * 4);
+        S.off_ent = reserve((int64_t)S.ent.size() * 8);
+        S.off_grp_rows = reserve((int64_t)S.grp_rows.size() * 4);
+        S.off_batch_ptr = reserve((int64_t)S.batch_ptr.size() * 4);
+        S.off_batches = reserve((int64_t)S.batches.size() * 4);
+        S.off_slots = reserve((int64_t)S.slots.size() * 4);
+        S.off_ldsb = reserve((int64_t)S.ldsb.size() * 4);
+        S.off_nodes = reserve((int64_t)S.nodes.size() * 4);
+        S.off_tiles = reserve((int64_t)S.tiles.size() * 4);
+        S.off_row_lo = reserve((int64_t)S.row_lo.size() * 4);
     }
     p.table.assign((size_t)off, 0);
+    auto put = [&](int64_t o, const void *src, size_t bytes) {
+        if (bytes) std::memcpy(&p.table[(size_t)o], src, bytes);
+    };
     for (Stage &S : p.stages) {
-        std::memcpy(&p.table[S.off_row_ptr], S.row_ptr.data(), S.row_ptr.size() * 4);
-        std::memcpy(&p.table[S.off_row_len], S.row_len.data(), S.row_len.size() * 4);
-        std::memcpy(&p.table[S.off_ent], S.ent.data(), S.ent.size() * 8);
+        put(S.off_row_ptr, S.row_ptr.data(), S.row_ptr.size() * 4);
+        put(S.off_row_len, S.row_len.data(), S.row_len.size() * 4);
+        put(S.off_ent, S.ent.data(), S.ent.size() * 8);
+        put(S.off_grp_rows, S.grp_rows.data(), S.grp_rows.size() * 4);
+        put(S.off_batch_ptr, S.batch_ptr.data(), S.batch_ptr.size() * 4);
+        put(S.off_batches, S.batches.data(), S.batches.size() * 4);
+        put(S.off_slots, S.slots.data(), S.slots.size() * 4);
+        put(S.off_ldsb, S.ldsb.data(), S.ldsb.size() * 4);
+        put(S.off_nodes, S.nodes.data(), S.nodes.size() * 4);
+        put(S.off_tiles, S.tiles.data(), S.tiles.size() * 4);
+        put(S.off_row_lo, S.row_lo.data(), S.row_lo.size() * 4);
     }
     int64_t ws = 0;
     for (Stage &S : p.stages) {
@@ -412,6 +630,14 @@ snd_status build_plan(const snd_plan_desc &d, PlanImpl &p, std::string &err)
         I.stage_alg_bytes[si] = S.alg_bytes;
         I.stage_rows[si] = S.rows;
         I.stage_entries[si] = (int64_t)S.ent.size();
+        I.stage_kernel[si] = (S.kernel == kKernelGroupLds && S.group_f1 > 0) ? 3 : S.kernel;
+        if (S.kernel == kKernelGroupLds) {
+            int64_t staged = 0;
+            for (size_t i = 0; i < S.slots.size(); i += 4) staged += S.slots[i + 2] + S.group_tile;
+            I.stage_staged[si] = staged;
+            I.stage_batches[si] = (int64_t)(S.batches.size() / 4);
+            I.stage_windows[si] = (int64_t)(S.slots.size() / 4);
+        }
     }
     I.alg_bytes = alg;
     I.build_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();

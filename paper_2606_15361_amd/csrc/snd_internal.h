@@ -42,7 +42,57 @@ struct Stage {
     int64_t off_row_ptr = 0, off_row_len = 0, off_ent = 0;  // byte offsets in the table image
     int64_t ws_off = 0;            // byte offset of the output plane in the workspace
     int64_t alg_bytes = 0;
+
+    // Kernel chosen for the stage.
+    int kernel = 0;  // kKernelGeneric, kKernelGroupLds or kKernelAnchored
+
+    // kKernelGroupLds: rows in groups of kGroupRows sharing LDS-staged source windows.
+    int64_t ngroups = 0;
+    int32_t n_entries = 0;          // entries per row (identical for every row)
+    int32_t lds_bytes = 0;          // dynamic LDS per workgroup
+    int32_t lds_buf_elems = 0;      // elements per LDS buffer (group kernel)
+    int32_t group_f1 = 0;           // inputs per level-1 node when regular (specialised kernel), else 0
+    int32_t group_tile = 0;         // time samples per workgroup
+    std::vector<int32_t> grp_rows;  // [ngroups * kGroupRows], -1 = padding
+    std::vector<int32_t> batch_ptr; // [ngroups + 1] into batches
+    std::vector<int32_t> batches;   // 4 ints per batch: entry begin, entry end, slot begin, slot end
+    std::vector<int32_t> slots;     // 4 ints per slot: source row, start offset, span, LDS element offset
+    std::vector<uint32_t> ldsb;     // [ngroups][n_entries][kGroupRows]: LDS base | closes << 24
+    int64_t off_grp_rows = 0, off_batch_ptr = 0, off_batches = 0, off_slots = 0, off_ldsb = 0;
+
+    // kKernelAnchored: one workgroup per (node, window of kAnchorTile reference samples).
+    std::vector<int32_t> nodes;     // 6 ints per node: row begin, row end, channel begin, channel end, rho max, 0
+    std::vector<int32_t> tiles;     // 2 ints per workgroup: node index, window start
+    std::vector<int32_t> row_lo;    // [rows]
+    int64_t off_nodes = 0, off_tiles = 0, off_row_lo = 0;
+    int64_t ntiles = 0;
 };
+
+constexpr int kKernelGeneric = 0;
+constexpr int kKernelGroupLds = 1;
+constexpr int kKernelAnchored = 2;
+constexpr int kGroupRows = 16;       // rows (waves) per LDS-group workgroup
+constexpr int kGroupTile = 256;      // time samples per LDS-group workgroup
+constexpr int kGroupLdsBytes = 20480;  // per LDS buffer
+constexpr int kGroupBuffers = 3;       // batches b, b+1, b+2 in LDS at once
+// Specialised group kernel: regular level-1 nodes of f1 inputs, compile-time depth.
+constexpr int kGroupTileFast = 512;
+constexpr int kGroupFastLdsBytes = 49152;
+inline bool group_fast_types(int mode, int src_dt, int dst_dt)
+{
+    if (mode == SND_MODE_BINARY) return src_dt == SND_DT_U8 && dst_dt == SND_DT_U8;
+    if (mode == SND_MODE_GRADED) return src_dt == dst_dt && (src_dt == SND_DT_U8 || src_dt == SND_DT_U16);
+    return dst_dt == SND_DT_F32;
+}
+inline bool group_fast_supported(int f1, int depth)
+{
+    return (f1 == 2 && depth >= 1 && depth <= 8) || (f1 == 4 && depth >= 1 && depth <= 5) ||
+           (f1 == 8 && depth >= 1 && depth <= 4);
+}
+constexpr int kGroupMaxSpan = 256;   // offset spread of one staged window (window <= span + tile)
+constexpr int kGroupSlotsPerWave = 4;  // staged windows per wave per batch
+constexpr int kAnchorTile = 512;     // reference samples per anchored workgroup
+constexpr int kAnchorLdsBytes = 65536;
 
 struct Level {
     int nnodes = 0;
@@ -97,6 +147,47 @@ struct StageArgs {
 
 // Enqueue one stage; returns 0 or a HIP error code.
 int launch_stage(int mode, int src_dtype, int dst_dtype, const StageArgs &a, int64_t max_len, void *stream);
+
+struct GroupArgs {
+    const void *src;
+    int64_t src_pitch;
+    void *dst;
+    int64_t dst_pitch;
+    const int32_t *grp_rows;
+    const int32_t *batch_ptr;
+    const int32_t *batches;  // 4 ints per batch
+    const int32_t *slots;    // 4 ints per slot
+    const uint32_t *ldsb;
+    int32_t ngroups;
+    int32_t n_entries;
+    int32_t buf_elems;
+    int32_t f1;  // > 0: specialised kernel with level-1 nodes of f1 inputs
+    int32_t n_out;
+    int32_t depth;
+    int32_t src_is_input;
+    int32_t k_leaf, k_int, cap;
+    float scale;
+};
+int launch_group(int mode, int src_dtype, int dst_dtype, const GroupArgs &a, int64_t n_out, int lds_bytes, void *stream);
+
+struct AnchorArgs {
+    const void *src;
+    int64_t src_pitch;
+    int64_t src_len;  // valid samples per source row
+    void *dst;
+    int64_t dst_pitch;
+    const uint32_t *row_ptr;
+    const int32_t *row_len;
+    const Entry *ent;
+    const int32_t *nodes;
+    const int32_t *tiles;    // 2 ints per workgroup
+    const int32_t *row_lo;
+    int32_t depth;
+    int32_t k_leaf, k_int, cap;
+    float scale;
+};
+int launch_anchored(int mode, int src_dtype, int dst_dtype, const AnchorArgs &a, int64_t ntiles, int lds_bytes,
+                    void *stream);
 int launch_encode(const float *z, int64_t z_pitch, int time_major, int nchan, int64_t nsamp, const float *thr,
                   int nthr, uint8_t *out, int64_t out_pitch, void *stream);
 int launch_cast(const float *src, int64_t src_pitch, int64_t rows, int64_t cols, void *dst, int64_t dst_pitch,

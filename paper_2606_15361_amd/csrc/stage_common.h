@@ -1,0 +1,133 @@
+// Device helpers shared by the SND stage kernels: storage types, node activation, the
+// level-closing step of the in-register sub-tree evaluation, the XCD-aware block remap and
+// the (mode, source type, destination type) dispatch.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "snd.h"
+
+namespace snd {
+
+// Plan tables are never written while a kernel runs: read them through the constant address
+// space so that wave-uniform reads become scalar loads (counted apart from vector memory).
+template <typename T> using const_ptr = const __attribute__((address_space(4))) T *;
+template <typename T> __device__ inline const_ptr<T> as_const(const T *p) { return (const_ptr<T>)p; }
+
+struct bf16_t { uint16_t bits; };
+struct f16_t { _Float16 v; };
+
+template <typename T> struct Load;
+template <> struct Load<uint8_t> { __device__ static int get(const uint8_t *p) { return *p; } };
+template <> struct Load<uint16_t> { __device__ static int get(const uint16_t *p) { return *p; } };
+template <> struct Load<float> { __device__ static float get(const float *p) { return *p; } };
+template <> struct Load<bf16_t> {
+    __device__ static float get(const bf16_t *p) { return __uint_as_float((uint32_t)p->bits << 16); }
+};
+template <> struct Load<f16_t> { __device__ static float get(const f16_t *p) { return (float)p->v; } };
+
+template <typename T> struct Zero { __device__ static T get() { return T{}; } };
+
+__device__ inline uint16_t f32_to_bf16_rne(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);  // quiet NaN
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+template <typename T> struct Store;
+template <> struct Store<uint8_t> {
+    template <typename A> __device__ static void put(uint8_t *p, A v) { *p = (uint8_t)v; }
+};
+template <> struct Store<uint16_t> {
+    template <typename A> __device__ static void put(uint16_t *p, A v) { *p = (uint16_t)v; }
+};
+template <> struct Store<float> {
+    template <typename A> __device__ static void put(float *p, A v) { *p = (float)v; }
+};
+template <> struct Store<bf16_t> {
+    template <typename A> __device__ static void put(bf16_t *p, A v) { p->bits = f32_to_bf16_rne((float)v); }
+};
+template <> struct Store<f16_t> {
+    template <typename A> __device__ static void put(f16_t *p, A v) { p->v = (_Float16)(float)v; }
+};
+
+template <int MODE> struct Acc { using type = int; };
+template <> struct Acc<SND_MODE_FLOAT> { using type = float; };
+
+// Node activation at relative level j of a stage (Methods, "Tree activation modes"): binary
+// quorum (K_L for the leaf level, K_I above), graded clip, or identity.
+template <int MODE, typename A>
+__device__ inline A activate(A a, int j, int src_is_input, int k_leaf, int k_int, int cap)
+{
+    if constexpr (MODE == SND_MODE_BINARY) {
+        const int k = (j == 1 && src_is_input) ? k_leaf : k_int;
+        return a >= k ? 1 : 0;
+    } else if constexpr (MODE == SND_MODE_GRADED) {
+        return a < cap ? a : cap;
+    } else {
+        return a;
+    }
+}
+
+// After an input that completes c sub-tree levels: activate each completed node in turn and
+// add its output to the parent's partial sum; the stage's own level goes to `out`.
+template <int MODE, typename A, int MAXD, int V>
+__device__ inline void close_levels(A (&acc)[MAXD][V], A (&out)[V], int c, int depth, int src_is_input, int k_leaf,
+                                    int k_int, int cap)
+{
+#pragma unroll
+    for (int j = 1; j <= MAXD; ++j) {
+        if (j <= c) {
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                const A y = activate<MODE>(acc[j - 1][v], j, src_is_input, k_leaf, k_int, cap);
+                acc[j - 1][v] = 0;
+                if (j == depth) out[v] = y;
+                else if (j < MAXD) acc[j][v] += y;
+            }
+        }
+    }
+}
+
+// Workgroups are dealt round-robin to the 8 XCDs; remap so that each XCD (own L2) works on a
+// contiguous range of logical tiles, which share source rows.
+__device__ inline uint32_t xcd_remap(uint32_t b, uint32_t nb)
+{
+    const uint32_t x = b & 7u, i = b >> 3, q = nb >> 3, r = nb & 7u;
+    return x * q + (x < r ? x : r) + i;
+}
+
+// Calls f.template run<MODE, TI, TO>(stream) for the supported storage combinations.
+template <typename F>
+int dispatch_types(int mode, int src_dt, int dst_dt, const F &f, hipStream_t st)
+{
+    if (mode == SND_MODE_BINARY) {
+        if (src_dt == SND_DT_U8 && dst_dt == SND_DT_U8) return f.template run<SND_MODE_BINARY, uint8_t, uint8_t>(st);
+    } else if (mode == SND_MODE_GRADED) {
+        if (src_dt == SND_DT_U8 && dst_dt == SND_DT_U8) return f.template run<SND_MODE_GRADED, uint8_t, uint8_t>(st);
+        if (src_dt == SND_DT_U8 && dst_dt == SND_DT_U16) return f.template run<SND_MODE_GRADED, uint8_t, uint16_t>(st);
+        if (src_dt == SND_DT_U16 && dst_dt == SND_DT_U16) return f.template run<SND_MODE_GRADED, uint16_t, uint16_t>(st);
+        if (src_dt == SND_DT_U16 && dst_dt == SND_DT_U8) return f.template run<SND_MODE_GRADED, uint16_t, uint8_t>(st);
+    } else if (mode == SND_MODE_FLOAT) {
+#define SND_FLOAT_DST(TI)                                                                             \
+    switch (dst_dt) {                                                                                 \
+    case SND_DT_F32: return f.template run<SND_MODE_FLOAT, TI, float>(st);                            \
+    case SND_DT_BF16: return f.template run<SND_MODE_FLOAT, TI, bf16_t>(st);                          \
+    case SND_DT_F16: return f.template run<SND_MODE_FLOAT, TI, f16_t>(st);                            \
+    }                                                                                                 \
+    break;
+        switch (src_dt) {
+        case SND_DT_F32: SND_FLOAT_DST(float)
+        case SND_DT_BF16: SND_FLOAT_DST(bf16_t)
+        case SND_DT_F16: SND_FLOAT_DST(f16_t)
+        }
+#undef SND_FLOAT_DST
+    }
+    return (int)hipErrorInvalidValue;
+}
+
+}  // namespace snd

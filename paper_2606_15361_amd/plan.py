@@ -31,7 +31,8 @@ class Plan:
 
     def __init__(self, freqs, dms, tsamp_s: float, nsamp: int, *, mode: str = "float", branching: int = 4,
                  cluster: int = 4, k_leaf: int = 2, k_int: int = 2, cap: int = 255, in_dtype: str | None = None,
-                 node_dtype: str | None = None, root_norm: bool = False, fref: float = 0.0, stage_levels: int = 0):
+                 node_dtype: str | None = None, root_norm: bool = False, fref: float = 0.0, stage_levels: int = 0,
+                 generic_kernels: bool = False):
         L = capi.lib()
         self._freq = np.ascontiguousarray(freqs, dtype=np.float64)
         self._dm = np.ascontiguousarray(dms, dtype=np.float64)
@@ -52,6 +53,7 @@ class Plan:
         d.root_norm = int(root_norm)
         d.nsamp = int(nsamp)
         d.stage_levels = int(stage_levels)
+        d.generic_kernels = int(generic_kernels)
         h = C.c_void_p()
         capi.check(L.snd_plan_create(C.byref(d), C.byref(h)))
         self._h = h
@@ -69,7 +71,10 @@ class Plan:
             nodes_per_level=list(info.nodes_per_level[:nl]), table_bytes=info.table_bytes,
             workspace_bytes=info.workspace_bytes, alg_bytes=info.alg_bytes,
             stage_alg_bytes=list(info.stage_alg_bytes[:ns]), stage_rows=list(info.stage_rows[:ns]),
-            stage_entries=list(info.stage_entries[:ns]), build_seconds=info.build_seconds)
+            stage_entries=list(info.stage_entries[:ns]), build_seconds=info.build_seconds,
+            stage_kernel=[("generic", "group_lds", "anchored", "group_fast")[k] for k in info.stage_kernel[:ns]],
+            stage_staged=list(info.stage_staged[:ns]), stage_batches=list(info.stage_batches[:ns]),
+            stage_windows=list(info.stage_windows[:ns]))
         self.n_out = info.n_out
         self._tables = None
         self._ws = None

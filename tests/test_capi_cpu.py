@@ -54,7 +54,12 @@ def test_config2_plan_shape(snd):
     assert p.info["n_synapses"] == 1371312
     assert p.n_out == 102748
     assert p.info["n_stages"] == 2
-    assert p.info["build_seconds"] < 2.0
+    assert p.info["build_seconds"] < 3.0
+    assert p.info["stage_kernel"] == ["anchored", "group_fast"]
+    b8 = snd.Plan(spec.freqs, spec.dms, spec.tsamp_s, spec.nsamp, mode="float", branching=8)
+    assert b8.info["stage_kernel"] == ["anchored", "group_lds"]  # an 8-input node does not fit the fast layout
+    g = snd.Plan(spec.freqs, spec.dms, spec.tsamp_s, spec.nsamp, mode="float", branching=4, generic_kernels=True)
+    assert g.info["stage_kernel"] == ["generic", "generic"]
     every = snd.Plan(spec.freqs, spec.dms, spec.tsamp_s, 40000, mode="graded", branching=4, stage_levels=0b1111)
     assert every.info["n_stages"] == 5 and every.info["stage_rows"] == [49722, 207270, 65356, 16384, 4096]
 

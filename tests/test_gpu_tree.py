@@ -88,10 +88,16 @@ def test_parity_small(snd, orc, nchan, C_, B, mode, kw):
     want, _ = orc.snd_dedup(x, f, d, mode=mode, cluster=C_, branching=B, **kw)
     ys = []
     nlev = len(orc.tree_shape(f, C_, B))
-    variants = [0, STAGE_NONE] + ([(1 << (nlev - 1)) - 1] if nlev > 2 else [])
-    for sl in variants:
-        _say(f"case nchan={nchan} C={C_} B={B} mode={mode} {kw} stage_levels={sl:#x}")
-        p = snd.Plan(f, dms, 0.138e-3, nsamp, mode=mode, cluster=C_, branching=B, stage_levels=sl, **kw)
+    variants = [(0, False), (0, True), (STAGE_NONE, False)]
+    if nlev > 2:
+        variants += [((1 << (nlev - 1)) - 1, False), ((1 << (nlev - 1)) - 1, True)]
+    for sl, generic in variants:
+        _say(f"case nchan={nchan} C={C_} B={B} mode={mode} {kw} stage_levels={sl:#x} generic={generic}")
+        p = snd.Plan(f, dms, 0.138e-3, nsamp, mode=mode, cluster=C_, branching=B, stage_levels=sl,
+                     generic_kernels=generic, **kw)
+        if not generic and sl == 0 and nlev > 1:
+            assert p.info["stage_kernel"][0] == "anchored", p.info["stage_kernel"]
+            assert p.info["stage_kernel"][1] in ("group_lds", "group_fast"), p.info["stage_kernel"]
         y = gpu_run(p, x, stage_by_stage=(sl == 0))
         assert y.shape == want.shape
         if mode == "float":
@@ -136,6 +142,7 @@ def test_config1_binary_exact(snd, orc, kl, ki):
     want, counts = orc.snd_dedup(x, spec.freqs, d, mode="binary", cluster=4, branching=2, k_leaf=kl, k_int=ki)
     p = snd.Plan(spec.freqs, spec.dms, spec.tsamp_s, spec.nsamp, mode="binary", branching=2, k_leaf=kl, k_int=ki)
     assert p.info["n_neurons"] == sum(c[0] for c in counts) == 1984
+    assert p.info["stage_kernel"] == ["anchored", "group_fast"]
     assert np.array_equal(gpu_run(p, x), want.astype(np.uint8))
 
 
