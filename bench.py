@@ -22,6 +22,37 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+LDS_PEAK_GBS = 256 * 128 * 2.4  # 256 CUs x 128 B/clk x 2.4 GHz
+KERNEL_SYMBOL = {"generic": "k_stage", "group_lds": "k_group", "anchored": "k_anchored", "group_fast": "k_group_fast"}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+
+
+def source_digest():
+    """Digest of the library sources: counter readings are only valid for the code they were taken on."""
+    import hashlib
+    h = hashlib.sha256()
+    for d in ("paper_2606_15361_amd/csrc", "include"):
+        for name in sorted(os.listdir(os.path.join(ROOT, d))):
+            if name.endswith((".hip", ".h", ".cpp")):
+                with open(os.path.join(ROOT, d, name), "rb") as f:
+                    h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(key):
+    """HBM bytes per launch of the dominant kernel from the committed counter summary, or None when
+    the summary is absent or was taken on other sources."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_digest") != source_digest():
+        return None
+    e = rec.get("kernels", {}).get(key)
+    if e is None:
+        return None
+    return (e["fetch_kib"] * rec["read_scale"] + e["write_kib"] * rec["write_scale"]) * 1024.0
 
 
 def log(*a):
@@ -156,6 +187,14 @@ def main():
     dom = int(np.argmax(stage_ms))
     alg = info["stage_alg_bytes"][dom]
     achieved = alg / (stage_ms[dom] * 1e-3) / 1e9
+    kname = KERNEL_SYMBOL[info["stage_kernel"][dom]]
+    wl_key = f"{mode}-{node or 'native'}-stage{dom}-{kname}"
+    traffic = measured_traffic(wl_key)
+    # LDS: every input of every output row is read once per output sample from LDS by the
+    # staged kernels; this is the kernel's own LDS floor, next to the HBM one
+    es = {"f32": 4, "bf16": 2, "f16": 2, "u8": 1, "u16": 2}[info["stage_src_dtype"][dom]]
+    lds_alg = info["stage_entries"][dom] * plan.n_out * es
+    whole_alg = sum(info["stage_alg_bytes"])
     dtype_name = {"float": node or "f32", "graded": "u8", "binary": "u8"}[mode]
     result = {
         "metric": "dedispersed DM x time samples/s (1024 ch, 4096 DM) + %HBM peak; p99 chunk latency",
@@ -175,8 +214,15 @@ def main():
                    "mode": mode, "node_dtype": node or ("f32" if mode == "float" else "u8"),
                    "n_out": plan.n_out, "stages": nst, "detect": detector is not None},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": f"k_stage (stage {dom} of {nst})"},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": f"{kname} (stage {dom} of {nst}, {info['stage_kernel'][dom]})",
+                     "alg_bytes_per_launch": alg, "avg_launch_ms": round(float(stage_ms[dom]), 4)},
+        "lds_roofline": {"achieved": lds_alg / (stage_ms[dom] * 1e-3) / 1e9, "peak": LDS_PEAK_GBS, "unit": "GB/s",
+                         "frac": lds_alg / (stage_ms[dom] * 1e-3) / 1e9 / LDS_PEAK_GBS,
+                         "alg_read_bytes_per_launch": lds_alg},
+        "tree_hbm": {"alg_bytes": whole_alg, "ms": round(float(stage_ms.sum()), 4),
+                     "achieved": whole_alg / (stage_ms.sum() * 1e-3) / 1e9,
+                     "frac": whole_alg / (stage_ms.sum() * 1e-3) / 1e9 / HBM_PEAK_GBS},
         "stage_ms": [round(v, 4) for v in stage_ms],
         "stage_alg_gb": [round(b / 1e9, 3) for b in info["stage_alg_bytes"]],
         "detect_ms": round(det_ms, 4),

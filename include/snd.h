@@ -89,7 +89,7 @@ typedef struct {
     int32_t node_dtype;      /* storage of materialised tree rows: U8 for binary; U8 (cap <= 255)
                                 or U16 for graded; F32, BF16 or F16 for float (FP32 accumulate) */
     int32_t root_norm;       /* float: divide the output by sqrt(nchan) (Methods, Mode C) */
-    int64_t nsamp;           /* input samples per channel per execute */
+    int64_t nsamp;           /* input samples per channel per execute (ignored when chunk > 0) */
     uint32_t stage_levels;   /* bit l (l below the root level) set: tree level l is written to
                                 device memory and read by the next stage.  0 = library default
                                 (leaves only); SND_STAGE_NONE = no level written (the whole tree is
@@ -97,7 +97,9 @@ typedef struct {
                                 for every choice. */
     int32_t generic_kernels; /* 1: run every stage on the generic stage kernel instead of the
                                 LDS-staged kernels (same results; for cross-checks) */
-    int32_t reserved[7];     /* must be zero */
+    int32_t chunk;           /* > 0: streaming plan for chunks of up to `chunk` samples; nsamp is
+                                then max_delay + chunk, so that n_out = chunk */
+    int32_t reserved[6];     /* must be zero */
 } snd_plan_desc;
 
 typedef struct snd_plan_s *snd_plan;
@@ -237,6 +239,89 @@ snd_status snd_snr_plane(snd_plan plan, const void *d_plane, int64_t plane_pitch
 snd_status snd_detect(snd_plan plan, const void *d_plane, int64_t plane_pitch, const snd_detect_desc *desc,
                       void *d_workspace, int64_t workspace_bytes, snd_candidate *h_out, int64_t cap,
                       int64_t *h_count, int64_t *h_npixels, void *stream);
+
+/* ---------------------------------------------------------------------------------------
+ * Streaming (chunked input with device-resident history).
+ *
+ * The paper processes a continuous observation chunk by chunk, consecutive chunks overlapping
+ * by the largest delay (Methods, "Pipeline overview"), and its neuromorphic mapping keeps a
+ * history ring per neuron (Methods, "Hardware mapping and power modelling", Eq. hist_mem).
+ * Here each admitted beam keeps, in a caller-owned device
+ * buffer, a ring of the last max_delay + n_out input samples of every channel, where n_out of
+ * the beam's plan is the longest chunk the beam accepts.  After S input samples have arrived
+ * in total, output samples t < S - max_delay exist; a push appends one chunk to the ring and
+ * computes exactly the output samples that became complete, each equal (bit for bit) to the
+ * plain snd_execute over the concatenated input.  Only the input is kept, not the neuron
+ * rows: the first stage recomputes the short spread of each leaf row from the ring.
+ *
+ * The plan must be uploaded and its first stage must be the input-anchored kernel (the
+ * default schedule; plans built with generic_kernels = 1 or without a materialised level
+ * are rejected with UNSUPPORTED).
+ * --------------------------------------------------------------------------------------- */
+typedef struct snd_stream_s *snd_stream;
+
+/* Device bytes of one beam's history for this plan (ring of nchan x (max_delay + n_out)
+ * input samples, rows padded to 256 bytes). */
+snd_status snd_stream_history_bytes(snd_plan plan, int64_t *bytes);
+
+/* New stream that admits beams while the sum of their history bytes stays within
+ * hbm_budget_bytes (> 0).  Host object only. */
+snd_status snd_stream_create(int64_t hbm_budget_bytes, snd_stream *out);
+snd_status snd_stream_destroy(snd_stream s);
+
+/* Admit beam_id (>= 0, not yet admitted) with plan and its history buffer d_history
+ * (>= snd_stream_history_bytes bytes, 256-byte aligned, owned by the caller, kept until
+ * evict).  CAPACITY (beam not admitted) when the budget would be exceeded.  The beam starts
+ * empty; its first push may carry any chunk index.  The plan must outlive the beam. */
+snd_status snd_stream_admit(snd_stream s, int32_t beam_id, snd_plan plan, void *d_history, int64_t bytes);
+
+/* Remove a beam and release its share of the budget (its buffer returns to the caller). */
+snd_status snd_stream_evict(snd_stream s, int32_t beam_id);
+
+/* One chunk of one beam in a push.  Inputs: beam_id, chunk_idx (must follow the beam's
+ * previous chunk index by one), chunk_len (1 .. n_out of the beam's plan), d_chunk
+ * [nchan][chunk_pitch] in the plan's input dtype, d_out [ndm][out_pitch] in the plan's output
+ * dtype with out_pitch >= n_out.  Outputs: out_t0 = output time of column 0 of d_out,
+ * out_n = output samples written (0 while the first max_delay samples fill the history),
+ * status = SND_OK or SND_ERR_GAP. */
+typedef struct {
+    int32_t beam_id;
+    int32_t status;
+    int64_t chunk_idx;
+    int64_t chunk_len;
+    const void *d_chunk;
+    int64_t chunk_pitch;
+    void *d_out;
+    int64_t out_pitch;
+    int64_t out_t0;
+    int64_t out_n;
+} snd_stream_item;
+
+/* Append one chunk to each of n beams (distinct beam ids) and compute their new output
+ * samples, asynchronously on stream, beams in the given order.  d_workspace: at least the
+ * largest workspace_bytes of the beams' plans, 256-byte aligned, reused beam after beam.
+ * All items are validated before any work (INVALID, STATE for an unknown beam).  A chunk
+ * index that does not follow the beam's previous one resets that beam's history, the chunk
+ * starts a new history, the item's status is SND_ERR_GAP and so is the return value (the
+ * other items are processed normally).  Calls on one stream object must not overlap. */
+snd_status snd_stream_push(snd_stream s, int32_t n, snd_stream_item *items, void *d_workspace,
+                           int64_t workspace_bytes, void *stream);
+
+/* State of one beam: input samples received, the next expected chunk index (-1 = any),
+ * output samples emitted. */
+snd_status snd_stream_beam_state(snd_stream s, int32_t beam_id, int64_t *received, int64_t *next_chunk,
+                                 int64_t *emitted);
+
+/* Budget, bytes in use and number of admitted beams. */
+snd_status snd_stream_usage(snd_stream s, int64_t *budget, int64_t *used, int32_t *n_beams);
+
+/* Checkpoint of one beam: a 64-byte header (state and ring shape) followed by the ring.
+ * snd_stream_export_bytes gives the size; export copies to host memory and synchronises the
+ * stream; import restores into an admitted beam whose plan has the same ring shape (INVALID
+ * otherwise) and synchronises the stream. */
+snd_status snd_stream_export_bytes(snd_stream s, int32_t beam_id, int64_t *bytes);
+snd_status snd_stream_export(snd_stream s, int32_t beam_id, void *h_buf, int64_t bytes, void *stream);
+snd_status snd_stream_import(snd_stream s, int32_t beam_id, const void *h_buf, int64_t bytes, void *stream);
 
 /* Thread-local message describing the last failure in this thread ("" if none). */
 const char *snd_last_error(void);

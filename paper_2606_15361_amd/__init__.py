@@ -9,5 +9,6 @@ PyTorch only provides device memory and HIP streams.
 from ._capi import SndError, LIB_PATH  # noqa: F401
 from .plan import Plan, encode, cast  # noqa: F401
 from .detect import Detector  # noqa: F401
+from .stream import Stream, history_bytes  # noqa: F401
 
-__all__ = ["Plan", "Detector", "encode", "cast", "SndError", "LIB_PATH"]
+__all__ = ["Plan", "Detector", "Stream", "history_bytes", "encode", "cast", "SndError", "LIB_PATH"]

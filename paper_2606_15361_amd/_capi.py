@@ -31,7 +31,7 @@ class PlanDesc(C.Structure):
         ("branching", C.c_int32), ("cluster", C.c_int32), ("mode", C.c_int32), ("k_leaf", C.c_int32),
         ("k_int", C.c_int32), ("cap", C.c_int32), ("in_dtype", C.c_int32), ("node_dtype", C.c_int32),
         ("root_norm", C.c_int32), ("nsamp", C.c_int64), ("stage_levels", C.c_uint32),
-        ("generic_kernels", C.c_int32), ("reserved", C.c_int32 * 7),
+        ("generic_kernels", C.c_int32), ("chunk", C.c_int32), ("reserved", C.c_int32 * 6),
     ]
 
 
@@ -58,6 +58,12 @@ class DetectDesc(C.Structure):
 class Candidate(C.Structure):
     _fields_ = [("dm_index", C.c_int32), ("width", C.c_int32), ("t", C.c_int64), ("snr", C.c_double),
                 ("dm", C.c_double), ("npix", C.c_int64)]
+
+
+class StreamItem(C.Structure):
+    _fields_ = [("beam_id", C.c_int32), ("status", C.c_int32), ("chunk_idx", C.c_int64), ("chunk_len", C.c_int64),
+                ("d_chunk", C.c_void_p), ("chunk_pitch", C.c_int64), ("d_out", C.c_void_p), ("out_pitch", C.c_int64),
+                ("out_t0", C.c_int64), ("out_n", C.c_int64)]
 
 
 _lib = None
@@ -100,6 +106,20 @@ def lib() -> C.CDLL:
         "snd_detect_workspace": ([P, D, C.POINTER(I64)], I32),
         "snd_snr_plane": ([P, P, I64, D, P, I64, P, I64, P, I64, P], I32),
         "snd_detect": ([P, P, I64, D, P, I64, C.POINTER(Candidate), I64, C.POINTER(I64), C.POINTER(I64), P], I32),
+    })
+    PI64 = C.POINTER(I64)
+    sig.update({
+        "snd_stream_history_bytes": ([P, PI64], I32),
+        "snd_stream_create": ([I64, C.POINTER(P)], I32),
+        "snd_stream_destroy": ([P], I32),
+        "snd_stream_admit": ([P, I32, P, P, I64], I32),
+        "snd_stream_evict": ([P, I32], I32),
+        "snd_stream_push": ([P, I32, C.POINTER(StreamItem), P, I64, P], I32),
+        "snd_stream_beam_state": ([P, I32, PI64, PI64, PI64], I32),
+        "snd_stream_usage": ([P, PI64, PI64, C.POINTER(I32)], I32),
+        "snd_stream_export_bytes": ([P, I32, PI64], I32),
+        "snd_stream_export": ([P, I32, P, I64, P], I32),
+        "snd_stream_import": ([P, I32, P, I64, P], I32),
     })
     optional = {}
     for name, (args, res) in sig.items():

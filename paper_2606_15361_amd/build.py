@@ -48,7 +48,7 @@ def build(verbose: bool = False) -> str:
         if src.endswith(".hip"):
             cmd = [cc, "-x", "hip"] + COMMON + DEVICE + ["-c", path, "-o", obj]
         else:
-            cmd = [cc] + COMMON + ["-c", path, "-o", obj]
+            cmd = [cc] + COMMON + ["--offload-arch=gfx950", "-c", path, "-o", obj]
         jobs.append((cmd, src))
         objs.append(obj)
     procs = [(subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT), src) for cmd, src in jobs]

@@ -98,6 +98,8 @@ snd_status snd_plan_destroy(snd_plan plan)
     return SND_OK;
 }
 
+}  // extern "C"
+
 namespace {
 
 snd_status check_exec(snd_plan plan, const void *d_in, int64_t in_pitch, void *d_out, int64_t out_pitch,
@@ -114,9 +116,14 @@ snd_status check_exec(snd_plan plan, const void *d_in, int64_t in_pitch, void *d
     return SND_OK;
 }
 
-snd_status run_stage(snd::PlanImpl &P, size_t si, const void *d_in, int64_t in_pitch, void *d_out, int64_t out_pitch,
-                     void *d_workspace, void *stream)
+}  // namespace
+
+namespace snd {
+
+snd_status run_stage(PlanImpl &P, size_t si, const Run &run, const void *d_in, int64_t in_pitch, void *d_out,
+                     int64_t out_pitch, void *d_workspace, void *stream)
 {
+    const int32_t len_cut = (int32_t)(P.n_out - run.n_run);
     const uint8_t *tb = static_cast<const uint8_t *>(P.d_table);
     uint8_t *ws = static_cast<uint8_t *>(d_workspace);
     const snd::Stage &S = P.stages[si];
@@ -157,14 +164,14 @@ snd_status run_stage(snd::PlanImpl &P, size_t si, const void *d_in, int64_t in_p
         g.n_entries = S.n_entries;
         g.buf_elems = S.lds_buf_elems;
         g.f1 = S.group_f1;
-        g.n_out = (int32_t)P.n_out;
+        g.n_out = (int32_t)run.n_run;
         g.depth = S.depth;
         g.src_is_input = S.src_level < 0;
         g.k_leaf = P.desc.k_leaf;
         g.k_int = P.desc.k_int;
         g.cap = P.desc.cap;
         g.scale = scale;
-        int e = snd::launch_group(P.desc.mode, S.src_dtype, S.dst_dtype, g, P.n_out, S.lds_bytes, stream);
+        int e = snd::launch_group(P.desc.mode, S.src_dtype, S.dst_dtype, g, run.n_run, S.lds_bytes, stream);
         if (e) return hip_fail(e, "stage launch (LDS groups)");
         return SND_OK;
     }
@@ -172,7 +179,9 @@ snd_status run_stage(snd::PlanImpl &P, size_t si, const void *d_in, int64_t in_p
         snd::AnchorArgs g{};
         g.src = a.src;
         g.src_pitch = a.src_pitch;
-        g.src_len = P.nsamp;
+        g.src_len = run.src_len;
+        g.ring_len = run.ring_len;
+        g.ring_start = run.ring_start;
         g.dst = a.dst;
         g.dst_pitch = a.dst_pitch;
         g.row_ptr = a.row_ptr;
@@ -186,6 +195,8 @@ snd_status run_stage(snd::PlanImpl &P, size_t si, const void *d_in, int64_t in_p
         g.k_int = P.desc.k_int;
         g.cap = P.desc.cap;
         g.scale = scale;
+        g.n_run = (int32_t)run.n_run;
+        g.len_cut = len_cut;
         int e = snd::launch_anchored(P.desc.mode, S.src_dtype, S.dst_dtype, g, S.ntiles, S.lds_bytes, stream);
         if (e) return hip_fail(e, "stage launch (input-anchored)");
         return SND_OK;
@@ -199,12 +210,15 @@ snd_status run_stage(snd::PlanImpl &P, size_t si, const void *d_in, int64_t in_p
     a.scale = (S.final_stage && P.desc.mode == SND_MODE_FLOAT && P.desc.root_norm)
                   ? (float)(1.0 / std::sqrt((double)P.nchan))
                   : 1.0f;
-    int e = snd::launch_stage(P.desc.mode, S.src_dtype, S.dst_dtype, a, S.max_len, stream);
+    a.len_cut = len_cut;
+    int e = snd::launch_stage(P.desc.mode, S.src_dtype, S.dst_dtype, a, S.max_len - len_cut, stream);
     if (e) return hip_fail(e, "stage launch");
     return SND_OK;
 }
 
-}  // namespace
+}  // namespace snd
+
+extern "C" {
 
 snd_status snd_execute(snd_plan plan, const void *d_in, int64_t in_pitch, void *d_out, int64_t out_pitch,
                        void *d_workspace, int64_t workspace_bytes, void *stream)
@@ -212,7 +226,8 @@ snd_status snd_execute(snd_plan plan, const void *d_in, int64_t in_pitch, void *
     snd_status s = check_exec(plan, d_in, in_pitch, d_out, out_pitch, d_workspace, workspace_bytes);
     if (s != SND_OK) return s;
     for (size_t si = 0; si < plan->impl.stages.size(); ++si) {
-        s = run_stage(plan->impl, si, d_in, in_pitch, d_out, out_pitch, d_workspace, stream);
+        s = snd::run_stage(plan->impl, si, snd::full_run(plan->impl), d_in, in_pitch, d_out, out_pitch, d_workspace,
+                           stream);
         if (s != SND_OK) return s;
     }
     return SND_OK;
@@ -224,7 +239,8 @@ snd_status snd_execute_stage(snd_plan plan, int32_t stage, const void *d_in, int
     snd_status s = check_exec(plan, d_in, in_pitch, d_out, out_pitch, d_workspace, workspace_bytes);
     if (s != SND_OK) return s;
     if (stage < 0 || stage >= (int32_t)plan->impl.stages.size()) return fail(SND_ERR_INVALID, "stage index out of range");
-    return run_stage(plan->impl, (size_t)stage, d_in, in_pitch, d_out, out_pitch, d_workspace, stream);
+    return snd::run_stage(plan->impl, (size_t)stage, snd::full_run(plan->impl), d_in, in_pitch, d_out, out_pitch,
+                          d_workspace, stream);
 }
 
 snd_status snd_encode(const float *d_z, int64_t z_pitch, int32_t time_major, int32_t nchan, int64_t nsamp,

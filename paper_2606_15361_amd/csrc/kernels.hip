@@ -37,7 +37,7 @@ __global__ __launch_bounds__(256) void k_stage(StageArgs s)
     int row = rg * kWaves + wave;
     if (row >= s.rows) return;
     row = __builtin_amdgcn_readfirstlane(row);
-    const int len = s.row_len[row];
+    const int len = s.row_len[row] - s.len_cut;
     const int t0 = tt * kTile;
     if (t0 >= len) return;
     const uint32_t beg = s.row_ptr[row], end = s.row_ptr[row + 1];

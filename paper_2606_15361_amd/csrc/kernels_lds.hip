@@ -140,6 +140,7 @@ __global__ __launch_bounds__(256) void k_anchored(AnchorArgs s)
     const int tau0 = s.tiles[2 * blockIdx.x + 1];
     const int *nd = s.nodes + 6 * node;
     const int r0 = nd[0], r1 = nd[1], c0 = nd[2], c1 = nd[3], rho_max = nd[4];
+    if (tau0 >= nd[5] + s.n_run) return;  // past every row of the node in this run (uniform per block)
     const int wst = kAnchorTile + rho_max;
     const TI *src = static_cast<const TI *>(s.src);
     for (int c = c0; c < c1; ++c) {  // stage the node's channels over [tau0, tau0 + wst)
@@ -151,7 +152,9 @@ __global__ __launch_bounds__(256) void k_anchored(AnchorArgs s)
             for (int u = 0; u < 4; ++u) {
                 const int j = j0 + tid + 256 * u;
                 const int64_t idx = (int64_t)tau0 + j;
-                tmp[u] = (j < wst && idx < s.src_len) ? p[idx] : Zero<TI>::get();
+                int64_t col = idx + s.ring_start;  // ring column of window sample idx
+                if (s.ring_len > 0 && col >= s.ring_len) col -= s.ring_len;
+                tmp[u] = (j < wst && idx < s.src_len) ? p[col] : Zero<TI>::get();
             }
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
@@ -162,7 +165,7 @@ __global__ __launch_bounds__(256) void k_anchored(AnchorArgs s)
     }
     __syncthreads();
     for (int r = r0 + wave; r < r1; r += 4) {
-        const int lo = s.row_lo[r], len = s.row_len[r];
+        const int lo = s.row_lo[r], len = s.row_len[r] - s.len_cut;
         const int i0 = tau0 - lo;  // output index at the window start
         if (i0 >= len || i0 + kAnchorTile <= 0) continue;
         A acc[MAXD][V];

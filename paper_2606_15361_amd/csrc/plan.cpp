@@ -270,7 +270,9 @@ bool build_anchored(const PlanImpl &p, Stage &S)
         if (lds > kAnchorLdsBytes) return false;
         lds_max = std::max(lds_max, lds);
         const int32_t ni = (int32_t)(nodes.size() / 6);
-        nodes.insert(nodes.end(), {(int32_t)r0, (int32_t)r1, c0, c1, rho_max, 0});
+        // last field: how far the node's rows reach past n_out, so that a run with fewer output
+        // samples can skip the tiles it does not need
+        nodes.insert(nodes.end(), {(int32_t)r0, (int32_t)r1, c0, c1, rho_max, (int32_t)(thi - p.n_out)});
         for (int64_t t = tlo; t < thi; t += kAnchorTile) tiles.insert(tiles.end(), {ni, (int32_t)t});
     }
     S.kernel = kKernelAnchored;
@@ -288,11 +290,12 @@ snd_status build_plan(const snd_plan_desc &d, PlanImpl &p, std::string &err)
 {
     auto t_start = std::chrono::steady_clock::now();
     // ---------------- validation ----------------
-    if (d.nchan < 1 || !d.freq_mhz || d.ndm < 1 || !d.dm || !(d.tsamp_s > 0.0) || d.nsamp < 1) {
-        err = "nchan, ndm, nsamp must be >= 1, tsamp_s > 0 and freq/dm non-null";
+    if (d.nchan < 1 || !d.freq_mhz || d.ndm < 1 || !d.dm || !(d.tsamp_s > 0.0) || (d.chunk <= 0 && d.nsamp < 1) ||
+        d.chunk < 0) {
+        err = "nchan, ndm, nsamp (or chunk) must be >= 1, tsamp_s > 0 and freq/dm non-null";
         return SND_ERR_INVALID;
     }
-    for (int i = 0; i < 7; ++i)
+    for (int i = 0; i < 6; ++i)
         if (d.reserved[i]) { err = "reserved descriptor fields must be zero"; return SND_ERR_INVALID; }
     if (d.branching < 2 || d.cluster < 1) { err = "branching must be >= 2 and cluster >= 1"; return SND_ERR_INVALID; }
     if (d.mode < SND_MODE_BINARY || d.mode > SND_MODE_FLOAT) { err = "unknown mode"; return SND_ERR_INVALID; }
@@ -338,6 +341,7 @@ snd_status build_plan(const snd_plan_desc &d, PlanImpl &p, std::string &err)
         }
     }
     p.max_delay = dmax;
+    if (d.chunk > 0) p.nsamp = p.desc.nsamp = dmax + d.chunk;
     p.n_out = p.nsamp - dmax;
     if (p.n_out < 1) { err = "nsamp does not exceed the largest delay: no valid output samples"; return SND_ERR_INVALID; }
 

@@ -61,7 +61,8 @@ struct Stage {
     int64_t off_grp_rows = 0, off_batch_ptr = 0, off_batches = 0, off_slots = 0, off_ldsb = 0;
 
     // kKernelAnchored: one workgroup per (node, window of kAnchorTile reference samples).
-    std::vector<int32_t> nodes;     // 6 ints per node: row begin, row end, channel begin, channel end, rho max, 0
+    std::vector<int32_t> nodes;     // 6 ints per node: row begin, row end, channel begin, channel end, rho max,
+                                    // reach of its rows past n_out
     std::vector<int32_t> tiles;     // 2 ints per workgroup: node index, window start
     std::vector<int32_t> row_lo;    // [rows]
     int64_t off_nodes = 0, off_tiles = 0, off_row_lo = 0;
@@ -124,6 +125,21 @@ struct PlanImpl {
 };
 
 int dtype_size(int dt);
+
+// One execution of a plan: n_run <= n_out output samples from a source window of src_len
+// samples per channel; the input rows are rings of ring_len samples whose window starts at
+// column ring_start when ring_len > 0 (streaming), plain rows otherwise.
+struct Run {
+    int64_t n_run;
+    int64_t src_len;
+    int64_t ring_len;
+    int64_t ring_start;
+};
+inline Run full_run(const PlanImpl &p) { return Run{p.n_out, p.nsamp, 0, 0}; }
+// Enqueue stage si of one run (defined with the C ABI).
+snd_status run_stage(PlanImpl &P, size_t si, const Run &run, const void *d_in, int64_t in_pitch, void *d_out,
+                     int64_t out_pitch, void *d_workspace, void *stream);
+void set_error(const std::string &msg);
 // Builds the whole plan; returns SND_OK or an error with a message in `err`.
 snd_status build_plan(const snd_plan_desc &d, PlanImpl &p, std::string &err);
 
@@ -143,6 +159,7 @@ struct StageArgs {
     int32_t src_is_input;
     int32_t k_leaf, k_int, cap;
     float scale;
+    int32_t len_cut;  // samples dropped from the end of every row (runs with fewer outputs than n_out)
 };
 
 // Enqueue one stage; returns 0 or a HIP error code.
@@ -173,7 +190,9 @@ int launch_group(int mode, int src_dtype, int dst_dtype, const GroupArgs &a, int
 struct AnchorArgs {
     const void *src;
     int64_t src_pitch;
-    int64_t src_len;  // valid samples per source row
+    int64_t src_len;     // valid samples per source row, counted from the window start
+    int64_t ring_len;    // > 0: source rows are rings of this many samples
+    int64_t ring_start;  // ring column of the window start (0 when not a ring)
     void *dst;
     int64_t dst_pitch;
     const uint32_t *row_ptr;
@@ -185,6 +204,8 @@ struct AnchorArgs {
     int32_t depth;
     int32_t k_leaf, k_int, cap;
     float scale;
+    int32_t n_run;    // output samples of this run (<= n_out)
+    int32_t len_cut;  // n_out - n_run: samples dropped from the end of every row
 };
 int launch_anchored(int mode, int src_dtype, int dst_dtype, const AnchorArgs &a, int64_t ntiles, int lds_bytes,
                     void *stream);

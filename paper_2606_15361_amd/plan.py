@@ -29,10 +29,12 @@ def _stream_handle(stream, device):
 class Plan:
     """An SND dedispersion plan (host tables, built by snd_plan_create)."""
 
-    def __init__(self, freqs, dms, tsamp_s: float, nsamp: int, *, mode: str = "float", branching: int = 4,
+    def __init__(self, freqs, dms, tsamp_s: float, nsamp: int | None, *, mode: str = "float", branching: int = 4,
                  cluster: int = 4, k_leaf: int = 2, k_int: int = 2, cap: int = 255, in_dtype: str | None = None,
                  node_dtype: str | None = None, root_norm: bool = False, fref: float = 0.0, stage_levels: int = 0,
-                 generic_kernels: bool = False):
+                 generic_kernels: bool = False, chunk: int = 0):
+        """nsamp: input samples per execute; or chunk > 0 (nsamp None): a streaming plan whose
+        n_out is `chunk` and whose nsamp is max_delay + chunk."""
         L = capi.lib()
         self._freq = np.ascontiguousarray(freqs, dtype=np.float64)
         self._dm = np.ascontiguousarray(dms, dtype=np.float64)
@@ -51,13 +53,14 @@ class Plan:
         d.k_leaf, d.k_int, d.cap = k_leaf, k_int, cap
         d.in_dtype, d.node_dtype = DTYPES[in_dtype], DTYPES[node_dtype]
         d.root_norm = int(root_norm)
-        d.nsamp = int(nsamp)
+        d.nsamp = int(nsamp or 0)
+        d.chunk = int(chunk)
         d.stage_levels = int(stage_levels)
         d.generic_kernels = int(generic_kernels)
         h = C.c_void_p()
         capi.check(L.snd_plan_create(C.byref(d), C.byref(h)))
         self._h = h
-        self.mode, self.nsamp, self.nchan, self.ndm = mode, int(nsamp), self._freq.size, self._dm.size
+        self.mode, self.nchan, self.ndm = mode, self._freq.size, self._dm.size
         self.in_dtype, self.node_dtype = in_dtype, node_dtype
         self.params = dict(mode=mode, branching=branching, cluster=cluster, k_leaf=k_leaf, k_int=k_int, cap=cap,
                            root_norm=root_norm)
@@ -74,8 +77,11 @@ class Plan:
             stage_entries=list(info.stage_entries[:ns]), build_seconds=info.build_seconds,
             stage_kernel=[("generic", "group_lds", "anchored", "group_fast")[k] for k in info.stage_kernel[:ns]],
             stage_staged=list(info.stage_staged[:ns]), stage_batches=list(info.stage_batches[:ns]),
-            stage_windows=list(info.stage_windows[:ns]))
+            stage_windows=list(info.stage_windows[:ns]),
+            stage_src_dtype=[in_dtype if s == 0 else node_dtype for s in range(ns)])
         self.n_out = info.n_out
+        self.nsamp = info.n_out + info.max_delay
+        self.max_delay = info.max_delay
         self._tables = None
         self._ws = None
 

@@ -119,3 +119,52 @@ def test_execute_requires_upload(snd):
     assert "upload" in _capi.lib().snd_last_error().decode()
     with pytest.raises(SndError):
         _capi.check(rc)
+
+
+def test_streaming_plan_and_admission_host_logic(snd):
+    """Streaming plans (chunk > 0), history sizing and admission by budget; no device work
+    (admission only records the caller's buffer, so any 256-byte aligned address serves)."""
+    import ctypes as C
+    from paper_2606_15361_amd import SndError, _capi
+    L = _capi.lib()
+    f = synth.channel_freqs(64)
+    dms = synth.dm_linear(64, 0, 300)
+    p = snd.Plan(f, dms, 0.138e-3, None, mode="graded", branching=2, chunk=1000)
+    assert p.n_out == 1000 and p.nsamp == p.max_delay + 1000
+    assert p.max_delay == 4186
+    nb = snd.history_bytes(p)
+    assert nb == 64 * ((p.max_delay + 1000 + 255) // 256 * 256)  # u8 ring rows padded to 256 bytes
+    pf = snd.Plan(f, dms, 0.138e-3, None, mode="float", branching=2, chunk=1000, node_dtype="bf16", in_dtype="bf16")
+    assert snd.history_bytes(pf) == 64 * ((2 * (pf.max_delay + 1000) + 255) // 256 * 256)
+
+    h = C.c_void_p()
+    assert L.snd_stream_create(0, C.byref(h)) == _capi.ERR_INVALID
+    _capi.check(L.snd_stream_create(2 * nb + nb // 2, C.byref(h)))
+    fake = C.c_void_p(1 << 20)
+    assert L.snd_stream_admit(h, 0, p.handle, C.c_void_p((1 << 20) + 8), nb) == _capi.ERR_INVALID  # misaligned
+    assert L.snd_stream_admit(h, 0, p.handle, fake, nb - 1) == _capi.ERR_NOMEM
+    assert L.snd_stream_admit(h, 0, p.handle, fake, nb) == _capi.ERR_STATE  # tables not uploaded
+    assert "upload" in L.snd_last_error().decode()
+    used = C.c_int64()
+    _capi.check(L.snd_stream_usage(h, None, C.byref(used), None))
+    assert used.value == 0
+    # a plan without the input-anchored first stage cannot stream
+    g = snd.Plan(f, dms, 0.138e-3, None, mode="graded", branching=2, chunk=1000, generic_kernels=True)
+    assert L.snd_stream_admit(h, 1, g.handle, fake, nb) == _capi.ERR_UNSUPPORTED
+    # budget: the third beam of this size does not fit
+    big = C.c_int64(3 * nb)
+    assert L.snd_stream_admit(h, 2, p.handle, fake, big) in (_capi.ERR_STATE,)
+    small_budget = C.c_void_p()
+    _capi.check(L.snd_stream_create(nb - 1, C.byref(small_budget)))
+    assert L.snd_stream_admit(small_budget, 0, p.handle, fake, nb) == _capi.ERR_CAPACITY
+    assert "budget" in L.snd_last_error().decode()
+    # unknown beams
+    assert L.snd_stream_evict(h, 7) == _capi.ERR_STATE
+    item = _capi.StreamItem()
+    item.beam_id = 7
+    assert L.snd_stream_push(h, 1, C.byref(item), None, 0, None) == _capi.ERR_STATE
+    assert L.snd_stream_push(h, 0, None, None, 0, None) == _capi.OK
+    L.snd_stream_destroy(h)
+    L.snd_stream_destroy(small_budget)
+    with pytest.raises(SndError):
+        snd.Plan(f, dms, 0.138e-3, None, mode="graded", branching=2, chunk=-5)
