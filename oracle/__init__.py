@@ -6,7 +6,27 @@ loads the product library.  The arithmetic lives in ``snd_oracle.c`` (plain C, I
 double); this module only marshals numpy arrays through ctypes, plus two closed-form
 noise statistics written in Python (``cascade`` and ``binary_snr``).
 
-Parity status of each function (what pins it) is recorded in the tests and the design doc.
+What pins each function to something other than itself (tests/test_oracle_*.py):
+
+* delays        -- textbook dispersion constant values, the ~42,500-sample sweep at DM 3000 for
+                   the Northern Cross band, the printed scrunch band edges, monotonicity, DM 0.
+* tree_shape    -- the Northern Cross tree 256 / 32 / 4 / 1 (Table S1).
+* snd_recursive, snd_points, snd_dedup
+                -- float and uncapped graded equal brute force exactly; graded equals
+                   min(brute force, cap) (node values are non-negative, so a clipped child
+                   clips its parent); branching-factor invariance; DM 0 row = channel sum;
+                   spike-count conservation; binary K = 1 and K = full fan-in reduce to
+                   brute force; hand-worked binary cases (tests/golden); the cascade law on
+                   Bernoulli spikes; the dedup tree equals the per-DM recursion in all modes.
+* bruteforce    -- DM 0 row = channel sum; conservation of the summed counts.
+* encode        -- fire rates against the normal tail probability.
+* matched_filter -- the printed noise-floor closed forms (0.8 and ~21), Gaussian noise
+                   statistics, optimal boxcar width, constant rows.
+* candidates    -- hand-built masks (row gaps 9 / 10, diagonal pairs) and scipy's closing and
+                   labelling on padded planes.
+* fire_probability, cascade, binary_snr -- Table 1 values.
+
+No function is left "parity unpinned".
 """
 
 from __future__ import annotations

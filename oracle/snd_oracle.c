@@ -12,7 +12,7 @@
  * exact integer sums (all sums here stay far below 2^53).  Compile with
  * -ffp-contract=off so that no multiply-add is fused.
  *
- * Readings of points the paper leaves open (each is listed in the design doc):
+ * Readings of points the paper leaves open:
  *  - delays are rounded half-to-even from one fixed FP64 expression;
  *  - the output time origin is the arrival time at the reference frequency, i.e. the
  *    "t + delta" form y_d(t) = sum_c x_c(t + delta_c(d));
