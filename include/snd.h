@@ -241,6 +241,31 @@ snd_status snd_detect(snd_plan plan, const void *d_plane, int64_t plane_pitch, c
                       int64_t *h_count, int64_t *h_npixels, void *stream);
 
 /* ---------------------------------------------------------------------------------------
+ * Batched execution.
+ *
+ * Several beams, each with its own uploaded plan (DM grids, lengths, modes and storage types
+ * may all differ), run with one grid per (stage, kernel class) instead of one launch per beam
+ * and stage.  A kernel class is a kernel kind, mode, storage pair and compile-time tree shape.
+ * Each grid reads per-beam argument records and a workgroup prefix table from d_records
+ * (caller-owned device memory, 256-byte aligned, snd_batch_records_bytes bytes, written by
+ * one host-to-device copy per grid on `stream`).  Results equal one snd_execute per beam.
+ * --------------------------------------------------------------------------------------- */
+
+/* Record bytes for a batch of these plans, and the number of grids it launches. */
+snd_status snd_batch_records_bytes(int32_t nbeams, const snd_plan *plans, int64_t *bytes, int32_t *n_launches);
+
+/* Execute beam i of the batch on d_in[i] [nchan][in_pitch[i]] into d_out[i] [ndm][out_pitch[i]]
+ * with its own workspace d_workspace[i] (workspace_bytes[i] >= the plan's, 256-byte aligned,
+ * distinct per beam).  n_run: NULL for every plan's full n_out, else per beam 0..n_out output
+ * samples (a shorter run reads max_delay + n_run[i] input samples), which lets a caller cut a
+ * long beam into time chunks.  Asynchronous on stream; *h_launches (nullable) receives the
+ * number of grids launched.  INVALID / STATE / NOMEM as for snd_execute, per beam. */
+snd_status snd_batch_execute(int32_t nbeams, const snd_plan *plans, const void *const *d_in, const int64_t *in_pitch,
+                             void *const *d_out, const int64_t *out_pitch, void *const *d_workspace,
+                             const int64_t *workspace_bytes, const int64_t *n_run, void *d_records,
+                             int64_t records_bytes, void *stream, int32_t *h_launches);
+
+/* ---------------------------------------------------------------------------------------
  * Streaming (chunked input with device-resident history).
  *
  * The paper processes a continuous observation chunk by chunk, consecutive chunks overlapping

@@ -120,19 +120,25 @@ snd_status check_exec(snd_plan plan, const void *d_in, int64_t in_pitch, void *d
 
 namespace snd {
 
-snd_status run_stage(PlanImpl &P, size_t si, const Run &run, const void *d_in, int64_t in_pitch, void *d_out,
-                     int64_t out_pitch, void *d_workspace, void *stream)
+Prepared prepare_stage(const PlanImpl &P, size_t si, const Run &run, const void *d_in, int64_t in_pitch, void *d_out,
+                       int64_t out_pitch, void *d_workspace)
 {
     const int32_t len_cut = (int32_t)(P.n_out - run.n_run);
     const uint8_t *tb = static_cast<const uint8_t *>(P.d_table);
     uint8_t *ws = static_cast<uint8_t *>(d_workspace);
-    const snd::Stage &S = P.stages[si];
-    snd::StageArgs a{};
+    const Stage &S = P.stages[si];
+    Prepared pr{};
+    pr.kind = S.kernel;
+    pr.mode = P.desc.mode;
+    pr.src_dt = S.src_dtype;
+    pr.dst_dt = S.dst_dtype;
+    pr.lds = S.lds_bytes;
+    StageArgs &a = pr.st;
     if (si == 0) {
         a.src = d_in;
         a.src_pitch = in_pitch;
     } else {
-        const snd::Stage &Q = P.stages[si - 1];
+        const Stage &Q = P.stages[si - 1];
         a.src = ws + Q.ws_off;
         a.src_pitch = Q.pitch;
     }
@@ -145,12 +151,12 @@ snd_status run_stage(PlanImpl &P, size_t si, const Run &run, const void *d_in, i
     }
     a.row_ptr = reinterpret_cast<const uint32_t *>(tb + S.off_row_ptr);
     a.row_len = reinterpret_cast<const int32_t *>(tb + S.off_row_len);
-    a.ent = reinterpret_cast<const snd::Entry *>(tb + S.off_ent);
+    a.ent = reinterpret_cast<const Entry *>(tb + S.off_ent);
     const float scale = (S.final_stage && P.desc.mode == SND_MODE_FLOAT && P.desc.root_norm)
                             ? (float)(1.0 / std::sqrt((double)P.nchan))
                             : 1.0f;
-    if (S.kernel == snd::kKernelGroupLds) {
-        snd::GroupArgs g{};
+    if (S.kernel == kKernelGroupLds) {
+        GroupArgs &g = pr.gr;
         g.src = a.src;
         g.src_pitch = a.src_pitch;
         g.dst = a.dst;
@@ -171,12 +177,14 @@ snd_status run_stage(PlanImpl &P, size_t si, const Run &run, const void *d_in, i
         g.k_int = P.desc.k_int;
         g.cap = P.desc.cap;
         g.scale = scale;
-        int e = snd::launch_group(P.desc.mode, S.src_dtype, S.dst_dtype, g, run.n_run, S.lds_bytes, stream);
-        if (e) return hip_fail(e, "stage launch (LDS groups)");
-        return SND_OK;
+        pr.n_run = run.n_run;
+        pr.shape = stage_shape(S);
+        const int64_t tile = S.group_tile;
+        pr.nblocks = S.ngroups * ((run.n_run + tile - 1) / tile);
+        return pr;
     }
-    if (S.kernel == snd::kKernelAnchored) {
-        snd::AnchorArgs g{};
+    if (S.kernel == kKernelAnchored) {
+        AnchorArgs &g = pr.an;
         g.src = a.src;
         g.src_pitch = a.src_pitch;
         g.src_len = run.src_len;
@@ -197,9 +205,9 @@ snd_status run_stage(PlanImpl &P, size_t si, const Run &run, const void *d_in, i
         g.scale = scale;
         g.n_run = (int32_t)run.n_run;
         g.len_cut = len_cut;
-        int e = snd::launch_anchored(P.desc.mode, S.src_dtype, S.dst_dtype, g, S.ntiles, S.lds_bytes, stream);
-        if (e) return hip_fail(e, "stage launch (input-anchored)");
-        return SND_OK;
+        pr.shape = stage_shape(S);
+        pr.nblocks = S.ntiles;
+        return pr;
     }
     a.rows = (int32_t)S.rows;
     a.depth = S.depth;
@@ -207,13 +215,36 @@ snd_status run_stage(PlanImpl &P, size_t si, const Run &run, const void *d_in, i
     a.k_leaf = P.desc.k_leaf;
     a.k_int = P.desc.k_int;
     a.cap = P.desc.cap;
-    a.scale = (S.final_stage && P.desc.mode == SND_MODE_FLOAT && P.desc.root_norm)
-                  ? (float)(1.0 / std::sqrt((double)P.nchan))
-                  : 1.0f;
+    a.scale = scale;
     a.len_cut = len_cut;
-    int e = snd::launch_stage(P.desc.mode, S.src_dtype, S.dst_dtype, a, S.max_len - len_cut, stream);
-    if (e) return hip_fail(e, "stage launch");
+    pr.max_len = S.max_len - len_cut;
+    pr.shape = stage_shape(S);
+    pr.nblocks = stage_blocks(a, pr.max_len);
+    return pr;
+}
+
+snd_status launch_prepared(const Prepared &pr, void *stream, const Multi &m, int64_t nblocks)
+{
+    int e = 0;
+    const char *what = "stage launch";
+    if (pr.kind == kKernelGroupLds) {
+        e = launch_group(pr.mode, pr.src_dt, pr.dst_dt, pr.gr, pr.n_run, pr.lds, stream, m, nblocks);
+        what = "stage launch (LDS groups)";
+    } else if (pr.kind == kKernelAnchored) {
+        e = launch_anchored(pr.mode, pr.src_dt, pr.dst_dt, pr.an, m.n > 0 ? nblocks : pr.nblocks, pr.lds, stream, m);
+        what = "stage launch (input-anchored)";
+    } else {
+        e = launch_stage(pr.mode, pr.src_dt, pr.dst_dt, pr.st, pr.max_len, stream, m, nblocks);
+    }
+    if (e) return hip_fail(e, what);
     return SND_OK;
+}
+
+snd_status run_stage(PlanImpl &P, size_t si, const Run &run, const void *d_in, int64_t in_pitch, void *d_out,
+                     int64_t out_pitch, void *d_workspace, void *stream)
+{
+    const Prepared pr = prepare_stage(P, si, run, d_in, in_pitch, d_out, out_pitch, d_workspace);
+    return launch_prepared(pr, stream, Multi{nullptr, nullptr, 0}, 0);
 }
 
 }  // namespace snd

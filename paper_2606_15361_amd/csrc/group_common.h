@@ -70,8 +70,11 @@ __device__ inline int issue_windows(const_ptr<int32_t> batches, const_ptr<int32_
     return n_ins;
 }
 
-int launch_group_fast_binary(int src_dt, int dst_dt, const GroupArgs &a, int64_t n_out, int lds, void *stream);
-int launch_group_fast_graded(int src_dt, int dst_dt, const GroupArgs &a, int64_t n_out, int lds, void *stream);
-int launch_group_fast_float(int src_dt, int dst_dt, const GroupArgs &a, int64_t n_out, int lds, void *stream);
+int launch_group_fast_binary(int src_dt, int dst_dt, const GroupArgs &a, int64_t n_out, int lds, void *stream,
+                             const Multi &m, int64_t nblocks);
+int launch_group_fast_graded(int src_dt, int dst_dt, const GroupArgs &a, int64_t n_out, int lds, void *stream,
+                             const Multi &m, int64_t nblocks);
+int launch_group_fast_float(int src_dt, int dst_dt, const GroupArgs &a, int64_t n_out, int lds, void *stream,
+                            const Multi &m, int64_t nblocks);
 
 }  // namespace snd

@@ -11,9 +11,12 @@
 namespace snd {
 
 template <int MODE, typename TI, typename TO, int F1, int D>
-__global__ __launch_bounds__(1024) void k_group_fast(GroupArgs s)
+__global__ __launch_bounds__(1024) void k_group_fast(GroupArgs s0, Multi m)
 {
     using A = typename Acc<MODE>::type;
+    GroupArgs s;
+    uint32_t bid, nblk;
+    select_record(s0, m, s, bid, nblk);
     constexpr int T = kGroupTileFast;
     constexpr int V = T / 64;          // samples per lane
     constexpr int SC = F1 < 4 ? F1 : 4;  // inputs whose reads are issued together
@@ -22,7 +25,7 @@ __global__ __launch_bounds__(1024) void k_group_fast(GroupArgs s)
     TI *lds = reinterpret_cast<TI *>(smem);
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const uint32_t L = xcd_remap(blockIdx.x, gridDim.x);
+    const uint32_t L = xcd_remap(bid, nblk);
     const int g = (int)(L % (uint32_t)s.ngroups);
     const int t0 = (int)(L / (uint32_t)s.ngroups) * T;
     const int vt = s.n_out - t0 < T ? s.n_out - t0 : T;
@@ -118,21 +121,22 @@ __global__ __launch_bounds__(1024) void k_group_fast(GroupArgs s)
 }
 
 template <int MODE, typename TI, typename TO, int F1, int D>
-int launch_fast_shape(const GroupArgs &a, int64_t n_out, int lds, hipStream_t st)
+int launch_fast_shape(const GroupArgs &a, int64_t n_out, int lds, hipStream_t st, const Multi &m, int64_t nb_multi)
 {
     const int64_t ntt = (n_out + kGroupTileFast - 1) / kGroupTileFast;
-    const int64_t nb = (int64_t)a.ngroups * ntt;
+    const int64_t nb = m.n > 0 ? nb_multi : (int64_t)a.ngroups * ntt;
     if (nb <= 0) return 0;
     if (nb > 0x7fffffffLL) return (int)hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_group_fast<MODE, TI, TO, F1, D>), dim3((uint32_t)nb), dim3(1024), lds, st, a);
+    hipLaunchKernelGGL((k_group_fast<MODE, TI, TO, F1, D>), dim3((uint32_t)nb), dim3(1024), lds, st, a, m);
     return (int)hipGetLastError();
 }
 
 // Every (F1, depth) pair listed by group_fast_supported().
 template <int MODE, typename TI, typename TO>
-int launch_fast_typed(const GroupArgs &a, int64_t n_out, int lds, hipStream_t st)
+int launch_fast_typed(const GroupArgs &a, int64_t n_out, int lds, hipStream_t st, const Multi &m, int64_t nb)
 {
-#define SND_FAST(F, DD) if (a.f1 == F && a.depth == DD) return launch_fast_shape<MODE, TI, TO, F, DD>(a, n_out, lds, st);
+#define SND_FAST(F, DD) \
+    if (a.f1 == F && a.depth == DD) return launch_fast_shape<MODE, TI, TO, F, DD>(a, n_out, lds, st, m, nb);
     SND_FAST(2, 1) SND_FAST(2, 2) SND_FAST(2, 3) SND_FAST(2, 4) SND_FAST(2, 5) SND_FAST(2, 6) SND_FAST(2, 7) SND_FAST(2, 8)
     SND_FAST(4, 1) SND_FAST(4, 2) SND_FAST(4, 3) SND_FAST(4, 4) SND_FAST(4, 5)
     SND_FAST(8, 1) SND_FAST(8, 2) SND_FAST(8, 3) SND_FAST(8, 4)

@@ -26,12 +26,15 @@ constexpr int kTile = 64 * kV; // time samples per wave
 constexpr int kUnroll = 8;     // entries whose loads are issued together
 
 template <int MODE, typename TI, typename TO, int MAXD>
-__global__ __launch_bounds__(256) void k_stage(StageArgs s)
+__global__ __launch_bounds__(256) void k_stage(StageArgs s0, Multi m)
 {
     using A = typename Acc<MODE>::type;
+    StageArgs s;
+    uint32_t bid, nblk;
+    select_record(s0, m, s, bid, nblk);
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
-    const uint32_t L = xcd_remap(blockIdx.x, gridDim.x);
+    const uint32_t L = xcd_remap(bid, nblk);
     const int rg = (int)(L % (uint32_t)s.n_rgroups);
     const int tt = (int)(L / (uint32_t)s.n_rgroups);
     int row = rg * kWaves + wave;
@@ -109,30 +112,29 @@ __global__ __launch_bounds__(256) void k_stage(StageArgs s)
 }
 
 template <int MODE, typename TI, typename TO>
-int launch_typed(const StageArgs &a, int64_t max_len, hipStream_t st)
+int launch_typed(const StageArgs &a, int64_t max_len, hipStream_t st, const Multi &m, int64_t nb_multi)
 {
-    const int64_t ntt = (max_len + kTile - 1) / kTile;
     StageArgs s = a;
-    s.n_ttiles = (int32_t)ntt;
-    s.n_rgroups = (a.rows + kWaves - 1) / kWaves;
-    const int64_t nblocks = (int64_t)s.n_rgroups * ntt;
+    const int64_t nblocks = m.n > 0 ? nb_multi : stage_blocks(s, max_len);
     if (nblocks <= 0) return 0;
     if (nblocks > 0x7fffffffLL || max_len > 0x7fffffffLL) return (int)hipErrorInvalidValue;
     dim3 grid((uint32_t)nblocks), block(256);
-    if (a.depth <= 1) hipLaunchKernelGGL((k_stage<MODE, TI, TO, 1>), grid, block, 0, st, s);
-    else if (a.depth <= 2) hipLaunchKernelGGL((k_stage<MODE, TI, TO, 2>), grid, block, 0, st, s);
-    else if (a.depth <= 4) hipLaunchKernelGGL((k_stage<MODE, TI, TO, 4>), grid, block, 0, st, s);
-    else if (a.depth <= 8) hipLaunchKernelGGL((k_stage<MODE, TI, TO, 8>), grid, block, 0, st, s);
-    else hipLaunchKernelGGL((k_stage<MODE, TI, TO, 16>), grid, block, 0, st, s);
+    if (a.depth <= 1) hipLaunchKernelGGL((k_stage<MODE, TI, TO, 1>), grid, block, 0, st, s, m);
+    else if (a.depth <= 2) hipLaunchKernelGGL((k_stage<MODE, TI, TO, 2>), grid, block, 0, st, s, m);
+    else if (a.depth <= 4) hipLaunchKernelGGL((k_stage<MODE, TI, TO, 4>), grid, block, 0, st, s, m);
+    else if (a.depth <= 8) hipLaunchKernelGGL((k_stage<MODE, TI, TO, 8>), grid, block, 0, st, s, m);
+    else hipLaunchKernelGGL((k_stage<MODE, TI, TO, 16>), grid, block, 0, st, s, m);
     return (int)hipGetLastError();
 }
 
 struct StageLauncher {
     const StageArgs &a;
     int64_t max_len;
+    const Multi &m;
+    int64_t nblocks;
     template <int MODE, typename TI, typename TO> int run(hipStream_t st) const
     {
-        return launch_typed<MODE, TI, TO>(a, max_len, st);
+        return launch_typed<MODE, TI, TO>(a, max_len, st, m, nblocks);
     }
 };
 
@@ -191,9 +193,18 @@ __global__ __launch_bounds__(256) void k_cast(const float *src, int64_t sp, int6
 
 }  // namespace
 
-int launch_stage(int mode, int src_dt, int dst_dt, const StageArgs &a, int64_t max_len, void *stream)
+int64_t stage_blocks(StageArgs &a, int64_t max_len)
 {
-    return dispatch_types(mode, src_dt, dst_dt, StageLauncher{a, max_len}, (hipStream_t)stream);
+    const int64_t ntt = (max_len + kTile - 1) / kTile;
+    a.n_ttiles = (int32_t)ntt;
+    a.n_rgroups = (a.rows + kWaves - 1) / kWaves;
+    return (int64_t)a.n_rgroups * ntt;
+}
+
+int launch_stage(int mode, int src_dt, int dst_dt, const StageArgs &a, int64_t max_len, void *stream, const Multi &m,
+                 int64_t nblocks)
+{
+    return dispatch_types(mode, src_dt, dst_dt, StageLauncher{a, max_len, m, nblocks}, (hipStream_t)stream);
 }
 
 int launch_encode(const float *z, int64_t zp, int time_major, int nchan, int64_t nsamp, const float *thr, int nthr,

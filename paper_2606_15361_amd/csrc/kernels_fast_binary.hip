@@ -3,10 +3,11 @@
 
 namespace snd {
 
-int launch_group_fast_binary(int src_dt, int dst_dt, const GroupArgs &a, int64_t n_out, int lds, void *stream)
+int launch_group_fast_binary(int src_dt, int dst_dt, const GroupArgs &a, int64_t n_out, int lds, void *stream,
+                             const Multi &m, int64_t nb)
 {
     hipStream_t st = (hipStream_t)stream;
-    if (src_dt == SND_DT_U8 && dst_dt == SND_DT_U8) return launch_fast_typed<SND_MODE_BINARY, uint8_t, uint8_t>(a, n_out, lds, st);
+    if (src_dt == SND_DT_U8 && dst_dt == SND_DT_U8) return launch_fast_typed<SND_MODE_BINARY, uint8_t, uint8_t>(a, n_out, lds, st, m, nb);
     return (int)hipErrorInvalidValue;
 }
 

@@ -25,9 +25,12 @@ namespace snd {
 namespace {
 
 template <int MODE, typename TI, typename TO, int MAXD>
-__global__ __launch_bounds__(1024) void k_group(GroupArgs s)
+__global__ __launch_bounds__(1024) void k_group(GroupArgs s0, Multi m)
 {
     using A = typename Acc<MODE>::type;
+    GroupArgs s;
+    uint32_t bid, nblk;
+    select_record(s0, m, s, bid, nblk);
     constexpr int V = kGroupTile / 64;  // samples per lane
     constexpr int KS = kGroupSlotsPerWave;
     constexpr int EU = MAXD <= 8 ? 8 : 4;  // entries per step
@@ -37,7 +40,7 @@ __global__ __launch_bounds__(1024) void k_group(GroupArgs s)
     TI *lds = reinterpret_cast<TI *>(smem);
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const uint32_t L = xcd_remap(blockIdx.x, gridDim.x);
+    const uint32_t L = xcd_remap(bid, nblk);
     const int g = (int)(L % (uint32_t)s.ngroups);
     const int t0 = (int)(L / (uint32_t)s.ngroups) * kGroupTile;
     const int vt = s.n_out - t0 < kGroupTile ? s.n_out - t0 : kGroupTile;
@@ -127,17 +130,20 @@ __global__ __launch_bounds__(1024) void k_group(GroupArgs s)
 }
 
 template <int MODE, typename TI, typename TO, int MAXD>
-__global__ __launch_bounds__(256) void k_anchored(AnchorArgs s)
+__global__ __launch_bounds__(256) void k_anchored(AnchorArgs s0, Multi m)
 {
     using A = typename Acc<MODE>::type;
+    AnchorArgs s;
+    uint32_t bid, nblk;
+    select_record(s0, m, s, bid, nblk);
     constexpr int V = kAnchorTile / 64;
     constexpr int EU = 4;
     extern __shared__ __align__(16) unsigned char smem[];
     TI *lds = reinterpret_cast<TI *>(smem);
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int node = s.tiles[2 * blockIdx.x];
-    const int tau0 = s.tiles[2 * blockIdx.x + 1];
+    const int node = s.tiles[2 * bid];
+    const int tau0 = s.tiles[2 * bid + 1];
     const int *nd = s.nodes + 6 * node;
     const int r0 = nd[0], r1 = nd[1], c0 = nd[2], c1 = nd[3], rho_max = nd[4];
     if (tau0 >= nd[5] + s.n_run) return;  // past every row of the node in this run (uniform per block)
@@ -225,31 +231,31 @@ __global__ __launch_bounds__(256) void k_anchored(AnchorArgs s)
 }
 
 template <int MODE, typename TI, typename TO>
-int launch_group_typed(const GroupArgs &a, int64_t n_out, int lds, hipStream_t st)
+int launch_group_typed(const GroupArgs &a, int64_t n_out, int lds, hipStream_t st, const Multi &m, int64_t nb_multi)
 {
     const int64_t ntt = (n_out + kGroupTile - 1) / kGroupTile;
-    const int64_t nb = (int64_t)a.ngroups * ntt;
+    const int64_t nb = m.n > 0 ? nb_multi : (int64_t)a.ngroups * ntt;
     if (nb <= 0) return 0;
     if (nb > 0x7fffffffLL) return (int)hipErrorInvalidValue;
     dim3 grid((uint32_t)nb), block(1024);
-    if (a.depth <= 1) hipLaunchKernelGGL((k_group<MODE, TI, TO, 1>), grid, block, lds, st, a);
-    else if (a.depth <= 2) hipLaunchKernelGGL((k_group<MODE, TI, TO, 2>), grid, block, lds, st, a);
-    else if (a.depth <= 4) hipLaunchKernelGGL((k_group<MODE, TI, TO, 4>), grid, block, lds, st, a);
-    else if (a.depth <= 8) hipLaunchKernelGGL((k_group<MODE, TI, TO, 8>), grid, block, lds, st, a);
-    else hipLaunchKernelGGL((k_group<MODE, TI, TO, 16>), grid, block, lds, st, a);
+    if (a.depth <= 1) hipLaunchKernelGGL((k_group<MODE, TI, TO, 1>), grid, block, lds, st, a, m);
+    else if (a.depth <= 2) hipLaunchKernelGGL((k_group<MODE, TI, TO, 2>), grid, block, lds, st, a, m);
+    else if (a.depth <= 4) hipLaunchKernelGGL((k_group<MODE, TI, TO, 4>), grid, block, lds, st, a, m);
+    else if (a.depth <= 8) hipLaunchKernelGGL((k_group<MODE, TI, TO, 8>), grid, block, lds, st, a, m);
+    else hipLaunchKernelGGL((k_group<MODE, TI, TO, 16>), grid, block, lds, st, a, m);
     return (int)hipGetLastError();
 }
 
 template <int MODE, typename TI, typename TO>
-int launch_anchored_typed(const AnchorArgs &a, int64_t ntiles, int lds, hipStream_t st)
+int launch_anchored_typed(const AnchorArgs &a, int64_t ntiles, int lds, hipStream_t st, const Multi &m)
 {
     if (ntiles <= 0) return 0;
     if (ntiles > 0x7fffffffLL || a.depth > 8) return (int)hipErrorInvalidValue;
     dim3 grid((uint32_t)ntiles), block(256);
-    if (a.depth <= 1) hipLaunchKernelGGL((k_anchored<MODE, TI, TO, 1>), grid, block, lds, st, a);
-    else if (a.depth <= 2) hipLaunchKernelGGL((k_anchored<MODE, TI, TO, 2>), grid, block, lds, st, a);
-    else if (a.depth <= 4) hipLaunchKernelGGL((k_anchored<MODE, TI, TO, 4>), grid, block, lds, st, a);
-    else hipLaunchKernelGGL((k_anchored<MODE, TI, TO, 8>), grid, block, lds, st, a);
+    if (a.depth <= 1) hipLaunchKernelGGL((k_anchored<MODE, TI, TO, 1>), grid, block, lds, st, a, m);
+    else if (a.depth <= 2) hipLaunchKernelGGL((k_anchored<MODE, TI, TO, 2>), grid, block, lds, st, a, m);
+    else if (a.depth <= 4) hipLaunchKernelGGL((k_anchored<MODE, TI, TO, 4>), grid, block, lds, st, a, m);
+    else hipLaunchKernelGGL((k_anchored<MODE, TI, TO, 8>), grid, block, lds, st, a, m);
     return (int)hipGetLastError();
 }
 
@@ -257,9 +263,11 @@ struct GroupLauncher {
     const GroupArgs &a;
     int64_t n_out;
     int lds;
+    const Multi &m;
+    int64_t nblocks;
     template <int MODE, typename TI, typename TO> int run(hipStream_t st) const
     {
-        return launch_group_typed<MODE, TI, TO>(a, n_out, lds, st);
+        return launch_group_typed<MODE, TI, TO>(a, n_out, lds, st, m, nblocks);
     }
 };
 
@@ -267,28 +275,34 @@ struct AnchorLauncher {
     const AnchorArgs &a;
     int64_t ntiles;
     int lds;
+    const Multi &m;
     template <int MODE, typename TI, typename TO> int run(hipStream_t st) const
     {
-        return launch_anchored_typed<MODE, TI, TO>(a, ntiles, lds, st);
+        return launch_anchored_typed<MODE, TI, TO>(a, ntiles, lds, st, m);
     }
 };
 
 }  // namespace
 
-int launch_group(int mode, int src_dt, int dst_dt, const GroupArgs &a, int64_t n_out, int lds_bytes, void *stream)
+int launch_group(int mode, int src_dt, int dst_dt, const GroupArgs &a, int64_t n_out, int lds_bytes, void *stream,
+                 const Multi &m, int64_t nblocks)
 {
     if (a.f1 > 0) {
-        if (mode == SND_MODE_BINARY) return launch_group_fast_binary(src_dt, dst_dt, a, n_out, lds_bytes, stream);
-        if (mode == SND_MODE_GRADED) return launch_group_fast_graded(src_dt, dst_dt, a, n_out, lds_bytes, stream);
-        if (mode == SND_MODE_FLOAT) return launch_group_fast_float(src_dt, dst_dt, a, n_out, lds_bytes, stream);
+        if (mode == SND_MODE_BINARY)
+            return launch_group_fast_binary(src_dt, dst_dt, a, n_out, lds_bytes, stream, m, nblocks);
+        if (mode == SND_MODE_GRADED)
+            return launch_group_fast_graded(src_dt, dst_dt, a, n_out, lds_bytes, stream, m, nblocks);
+        if (mode == SND_MODE_FLOAT)
+            return launch_group_fast_float(src_dt, dst_dt, a, n_out, lds_bytes, stream, m, nblocks);
         return (int)hipErrorInvalidValue;
     }
-    return dispatch_types(mode, src_dt, dst_dt, GroupLauncher{a, n_out, lds_bytes}, (hipStream_t)stream);
+    return dispatch_types(mode, src_dt, dst_dt, GroupLauncher{a, n_out, lds_bytes, m, nblocks}, (hipStream_t)stream);
 }
 
-int launch_anchored(int mode, int src_dt, int dst_dt, const AnchorArgs &a, int64_t ntiles, int lds_bytes, void *stream)
+int launch_anchored(int mode, int src_dt, int dst_dt, const AnchorArgs &a, int64_t ntiles, int lds_bytes, void *stream,
+                    const Multi &m)
 {
-    return dispatch_types(mode, src_dt, dst_dt, AnchorLauncher{a, ntiles, lds_bytes}, (hipStream_t)stream);
+    return dispatch_types(mode, src_dt, dst_dt, AnchorLauncher{a, ntiles, lds_bytes, m}, (hipStream_t)stream);
 }
 
 }  // namespace snd

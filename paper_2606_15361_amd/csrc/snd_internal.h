@@ -139,11 +139,22 @@ inline Run full_run(const PlanImpl &p) { return Run{p.n_out, p.nsamp, 0, 0}; }
 // Enqueue stage si of one run (defined with the C ABI).
 snd_status run_stage(PlanImpl &P, size_t si, const Run &run, const void *d_in, int64_t in_pitch, void *d_out,
                      int64_t out_pitch, void *d_workspace, void *stream);
+// Depth classes of the kernels whose open-level stack is sized at compile time.
+inline int depth_bucket(int d) { return d <= 1 ? 1 : d <= 2 ? 2 : d <= 4 ? 4 : d <= 8 ? 8 : 16; }
 void set_error(const std::string &msg);
 // Builds the whole plan; returns SND_OK or an error with a message in `err`.
 snd_status build_plan(const snd_plan_desc &d, PlanImpl &p, std::string &err);
 
 // ---- device launchers (kernels.hip) ----
+
+// Several stage launches of one kernel class in a single grid: record r (an argument struct of
+// the kernel in device memory) owns the workgroups [prefix[r], prefix[r + 1]).  n == 0 means a
+// plain launch whose arguments are passed by value.
+struct Multi {
+    const void *recs;
+    const int32_t *prefix;
+    int32_t n;
+};
 struct StageArgs {
     const void *src;
     int64_t src_pitch;
@@ -162,8 +173,12 @@ struct StageArgs {
     int32_t len_cut;  // samples dropped from the end of every row (runs with fewer outputs than n_out)
 };
 
-// Enqueue one stage; returns 0 or a HIP error code.
-int launch_stage(int mode, int src_dtype, int dst_dtype, const StageArgs &a, int64_t max_len, void *stream);
+// Workgroups of one generic stage launch; fills a.n_ttiles and a.n_rgroups.
+int64_t stage_blocks(StageArgs &a, int64_t max_len);
+// Enqueue one stage; returns 0 or a HIP error code.  With m.n > 0 the arguments come from the
+// records of m and the grid has `nblocks` workgroups (a is only used to choose the instance).
+int launch_stage(int mode, int src_dtype, int dst_dtype, const StageArgs &a, int64_t max_len, void *stream,
+                 const Multi &m = Multi{nullptr, nullptr, 0}, int64_t nblocks = 0);
 
 struct GroupArgs {
     const void *src;
@@ -185,7 +200,8 @@ struct GroupArgs {
     int32_t k_leaf, k_int, cap;
     float scale;
 };
-int launch_group(int mode, int src_dtype, int dst_dtype, const GroupArgs &a, int64_t n_out, int lds_bytes, void *stream);
+int launch_group(int mode, int src_dtype, int dst_dtype, const GroupArgs &a, int64_t n_out, int lds_bytes, void *stream,
+                 const Multi &m = Multi{nullptr, nullptr, 0}, int64_t nblocks = 0);
 
 struct AnchorArgs {
     const void *src;
@@ -208,11 +224,52 @@ struct AnchorArgs {
     int32_t len_cut;  // n_out - n_run: samples dropped from the end of every row
 };
 int launch_anchored(int mode, int src_dtype, int dst_dtype, const AnchorArgs &a, int64_t ntiles, int lds_bytes,
-                    void *stream);
+                    void *stream, const Multi &m = Multi{nullptr, nullptr, 0});
 int launch_encode(const float *z, int64_t z_pitch, int time_major, int nchan, int64_t nsamp, const float *thr,
                   int nthr, uint8_t *out, int64_t out_pitch, void *stream);
 int launch_cast(const float *src, int64_t src_pitch, int64_t rows, int64_t cols, void *dst, int64_t dst_pitch,
                 int dst_dtype, void *stream);
+
+// Compile-time shape of the kernel instance that runs stage S: the depth class, or, for the
+// specialised row-group kernel, 1000 * (inputs per level-1 node) + depth.
+inline int stage_shape(const Stage &S)
+{
+    if (S.kernel == kKernelGroupLds && S.group_f1 > 0) return 1000 * S.group_f1 + S.depth;
+    return depth_bucket(S.depth);
+}
+
+// One stage launch with its arguments filled in, ready to run alone or as one record of a
+// batched launch.  Launches may share a grid when kind, mode, dtypes and shape agree.
+struct Prepared {
+    int kind, mode, src_dt, dst_dt;
+    int shape;   // compile-time shape of the instance: depth class, or 1000 * f1 + depth
+    int lds;     // dynamic LDS bytes
+    int64_t nblocks;
+    int64_t n_run;    // LDS row groups: output samples of the run
+    int64_t max_len;  // generic: longest row of the run
+    StageArgs st;
+    GroupArgs gr;
+    AnchorArgs an;
+};
+Prepared prepare_stage(const PlanImpl &P, size_t si, const Run &run, const void *d_in, int64_t in_pitch, void *d_out,
+                       int64_t out_pitch, void *d_workspace);
+snd_status launch_prepared(const Prepared &pr, void *stream, const Multi &m, int64_t nblocks);
+
+// One beam of a batched execution: its plan, run and buffers.
+struct Job {
+    const PlanImpl *P;
+    Run run;
+    const void *in;
+    int64_t in_pitch;
+    void *out;
+    int64_t out_pitch;
+    void *ws;
+};
+// Device record bytes a batch of these plans needs, and the number of grids it launches.
+int64_t batch_record_bytes(const std::vector<const PlanImpl *> &plans, int *n_launches);
+// Every stage of every job, one grid per (stage wave, kernel class); records in d_records.
+snd_status run_batch(const std::vector<Job> &jobs, void *d_records, int64_t records_bytes, void *stream,
+                     int *n_launches);
 
 }  // namespace snd
 

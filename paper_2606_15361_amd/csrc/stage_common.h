@@ -8,6 +8,7 @@
 #include <cstdint>
 
 #include "snd.h"
+#include "snd_internal.h"
 
 namespace snd {
 
@@ -99,6 +100,36 @@ __device__ inline uint32_t xcd_remap(uint32_t b, uint32_t nb)
 {
     const uint32_t x = b & 7u, i = b >> 3, q = nb >> 3, r = nb & 7u;
     return x * q + (x < r ? x : r) + i;
+}
+
+// The arguments and the workgroup index of this workgroup: those passed by value for a plain
+// launch, else those of the record whose workgroup range holds blockIdx.x (binary search over
+// the prefix table; every value is wave-uniform, so this is scalar work).
+template <typename A>
+__device__ inline void select_record(const A &a0, const Multi &m, A &a, uint32_t &bid, uint32_t &nblk)
+{
+    if (m.n == 0) {
+        a = a0;
+        bid = blockIdx.x;
+        nblk = gridDim.x;
+        return;
+    }
+    const_ptr<int32_t> pre = as_const(m.prefix);
+    const int32_t b = (int32_t)blockIdx.x;
+    int lo = 0, hi = m.n;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (pre[mid] <= b) lo = mid;
+        else hi = mid;
+    }
+    static_assert(sizeof(A) % 4 == 0, "argument records are copied as dwords");
+    const_ptr<uint32_t> src = as_const(reinterpret_cast<const uint32_t *>(static_cast<const A *>(m.recs) + lo));
+    uint32_t w[sizeof(A) / 4];
+#pragma unroll
+    for (size_t i = 0; i < sizeof(A) / 4; ++i) w[i] = src[i];
+    __builtin_memcpy(&a, w, sizeof(A));
+    bid = (uint32_t)(b - pre[lo]);
+    nblk = (uint32_t)(pre[lo + 1] - pre[lo]);
 }
 
 // Calls f.template run<MODE, TI, TO>(stream) for the supported storage combinations.

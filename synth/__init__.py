@@ -22,7 +22,13 @@ from .filterbank import (  # noqa: F401
     random_pulse_slots,
 )
 from .configs import (  # noqa: F401
+    TSAMP_S,
     WorkloadSpec,
     workload,
     WORKLOADS,
+    batch_beam,
+    stream_beam,
+    arrival_times,
+    chunk_period_s,
+    seed_for,
 )

@@ -168,3 +168,31 @@ def test_streaming_plan_and_admission_host_logic(snd):
     L.snd_stream_destroy(small_budget)
     with pytest.raises(SndError):
         snd.Plan(f, dms, 0.138e-3, None, mode="graded", branching=2, chunk=-5)
+
+
+def test_batch_grouping_and_errors_host_logic(snd):
+    """Batched execution groups stage launches by kernel class; argument errors are caught on
+    the host before any device work."""
+    import ctypes as C
+    from paper_2606_15361_amd import _capi
+    L = _capi.lib()
+    f = synth.channel_freqs(64)
+    mk = lambda n, hi, **kw: snd.Plan(f, synth.dm_linear(n, 0, hi), 0.138e-3, 6000, branching=2, **kw)
+    plans = [mk(40, 100, mode="graded"), mk(64, 300, mode="graded"), mk(20, 50, mode="binary"),
+             mk(33, 120, mode="float"), mk(33, 120, mode="float", node_dtype="bf16", in_dtype="bf16")]
+    # stage 0: anchored graded / binary / float f32 / float bf16 -> 4 classes; final stage the same
+    # split (the two graded plans share one grid per stage)
+    nb, nl = snd.records_bytes(plans)
+    assert nl == 8 and nb % 256 == 0 and nb > 0
+    nb1, nl1 = snd.records_bytes(plans[:1])
+    assert nl1 == 2
+    hs = (C.c_void_p * 1)(plans[0].handle.value)
+    ptr = (C.c_void_p * 1)(1 << 20)
+    pitch = (C.c_int64 * 1)(6000)
+    wsb = (C.c_int64 * 1)(plans[0].info["workspace_bytes"])
+    rc = L.snd_batch_execute(1, hs, ptr, pitch, ptr, pitch, ptr, wsb, None, C.c_void_p(1 << 20), nb1, None, None)
+    assert rc == _capi.ERR_STATE  # tables not uploaded
+    assert L.snd_batch_execute(0, hs, ptr, pitch, ptr, pitch, ptr, wsb, None, C.c_void_p(1 << 20), nb1, None,
+                               None) == _capi.ERR_INVALID
+    assert L.snd_batch_execute(1, hs, ptr, pitch, ptr, pitch, ptr, wsb, None, C.c_void_p((1 << 20) + 4), nb1, None,
+                               None) == _capi.ERR_INVALID  # misaligned records
