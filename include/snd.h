@@ -266,6 +266,30 @@ snd_status snd_batch_execute(int32_t nbeams, const snd_plan *plans, const void *
                              int64_t records_bytes, void *stream, int32_t *h_launches);
 
 /* ---------------------------------------------------------------------------------------
+ * Schedule autotuner.
+ *
+ * A candidate is a stage schedule (which tree levels are written to device memory, see
+ * snd_plan_desc.stage_levels) and a time chunk (0 = the whole block in one run, else runs of
+ * `chunk` output samples, which bounds the workspace).  Every candidate computes the same
+ * output; they differ in speed and memory.  For each candidate the library builds its plan,
+ * uploads the tables to d_tables and times `reps` passes over the block d_in -> d_out with HIP
+ * events on `stream` (after one untimed pass).  A candidate whose tables or workspace exceed
+ * table_bytes / workspace_bytes is skipped (ms = -1).  *h_best receives the index of the
+ * fastest.  Synchronises the stream.  NOMEM when no candidate fits.
+ * --------------------------------------------------------------------------------------- */
+typedef struct {
+    uint32_t stage_levels;     /* in: schedule (as in snd_plan_desc) */
+    int32_t chunk;             /* in: output samples per run, 0 = whole block */
+    double ms;                 /* out: mean milliseconds per pass, -1 when skipped */
+    int64_t workspace_bytes;   /* out: the candidate's workspace */
+    int64_t table_bytes;       /* out: the candidate's tables */
+} snd_tune_candidate;
+
+snd_status snd_autotune(const snd_plan_desc *desc, snd_tune_candidate *cands, int32_t ncand, const void *d_in,
+                        int64_t in_pitch, void *d_out, int64_t out_pitch, void *d_workspace, int64_t workspace_bytes,
+                        void *d_tables, int64_t table_bytes, int32_t reps, int32_t *h_best, void *stream);
+
+/* ---------------------------------------------------------------------------------------
  * Streaming (chunked input with device-resident history).
  *
  * The paper processes a continuous observation chunk by chunk, consecutive chunks overlapping
@@ -331,6 +355,16 @@ typedef struct {
  * other items are processed normally).  Calls on one stream object must not overlap. */
 snd_status snd_stream_push(snd_stream s, int32_t n, snd_stream_item *items, void *d_workspace,
                            int64_t workspace_bytes, void *stream);
+
+/* The same push with the beams' stage launches batched: one grid per (stage, kernel class)
+ * across all items (see snd_batch_execute).  d_workspace holds one share per item, in item
+ * order, each the item plan's workspace_bytes rounded up to 256; d_records is a 256-byte
+ * aligned device buffer.  snd_stream_batch_bytes gives both sizes for a set of beams.  The
+ * outputs equal those of snd_stream_push. */
+snd_status snd_stream_push_batched(snd_stream s, int32_t n, snd_stream_item *items, void *d_workspace,
+                                   int64_t workspace_bytes, void *d_records, int64_t records_bytes, void *stream);
+snd_status snd_stream_batch_bytes(snd_stream s, int32_t n, const int32_t *beam_ids, int64_t *workspace_bytes,
+                                  int64_t *records_bytes);
 
 /* State of one beam: input samples received, the next expected chunk index (-1 = any),
  * output samples emitted. */

@@ -66,6 +66,11 @@ class StreamItem(C.Structure):
                 ("out_t0", C.c_int64), ("out_n", C.c_int64)]
 
 
+class TuneCandidate(C.Structure):
+    _fields_ = [("stage_levels", C.c_uint32), ("chunk", C.c_int32), ("ms", C.c_double),
+                ("workspace_bytes", C.c_int64), ("table_bytes", C.c_int64)]
+
+
 _lib = None
 
 
@@ -110,6 +115,8 @@ def lib() -> C.CDLL:
     PI64 = C.POINTER(I64)
     PP = C.POINTER(P)
     sig.update({
+        "snd_autotune": ([C.POINTER(PlanDesc), C.POINTER(TuneCandidate), I32, P, I64, P, I64, P, I64, P, I64, I32,
+                          C.POINTER(I32), P], I32),
         "snd_batch_records_bytes": ([I32, PP, PI64, C.POINTER(I32)], I32),
         "snd_batch_execute": ([I32, PP, PP, PI64, PP, PI64, PP, PI64, PI64, P, I64, P, C.POINTER(I32)], I32),
         "snd_stream_history_bytes": ([P, PI64], I32),
@@ -118,6 +125,8 @@ def lib() -> C.CDLL:
         "snd_stream_admit": ([P, I32, P, P, I64], I32),
         "snd_stream_evict": ([P, I32], I32),
         "snd_stream_push": ([P, I32, C.POINTER(StreamItem), P, I64, P], I32),
+        "snd_stream_push_batched": ([P, I32, C.POINTER(StreamItem), P, I64, P, I64, P], I32),
+        "snd_stream_batch_bytes": ([P, I32, C.POINTER(I32), PI64, PI64], I32),
         "snd_stream_beam_state": ([P, I32, PI64, PI64, PI64], I32),
         "snd_stream_usage": ([P, PI64, PI64, C.POINTER(I32)], I32),
         "snd_stream_export_bytes": ([P, I32, PI64], I32),

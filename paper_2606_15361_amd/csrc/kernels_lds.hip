@@ -32,10 +32,7 @@ __global__ __launch_bounds__(1024) void k_group(GroupArgs s0, Multi m)
     uint32_t bid, nblk;
     select_record(s0, m, s, bid, nblk);
     constexpr int V = kGroupTile / 64;  // samples per lane
-    constexpr int KS = kGroupSlotsPerWave;
     constexpr int EU = MAXD <= 8 ? 8 : 4;  // entries per step
-    constexpr int ES = (int)sizeof(TI);
-    constexpr int EPD = 4 / ES;  // elements per dword
     extern __shared__ __align__(16) unsigned char smem[];
     TI *lds = reinterpret_cast<TI *>(smem);
     const int tid = threadIdx.x, lane = tid & 63;

@@ -141,13 +141,22 @@ snd_status snd_stream_evict(snd_stream s, int32_t beam_id)
     return SND_OK;
 }
 
-snd_status snd_stream_push(snd_stream s, int32_t n, snd_stream_item *items, void *d_workspace,
-                           int64_t workspace_bytes, void *stream)
+}  // extern "C"
+
+namespace {
+
+// Bytes of one beam's share of a batched push workspace.
+int64_t ws_share(const snd::PlanImpl &P) { return round_up(P.workspace_bytes, 256); }
+
+snd_status push_impl(snd_stream s, int32_t n, snd_stream_item *items, void *d_workspace, int64_t workspace_bytes,
+                     void *d_records, int64_t records_bytes, bool batched, void *stream)
 {
     if (!s || (n > 0 && !items)) return fail(SND_ERR_INVALID, "null stream or items");
     if (n < 0) return fail(SND_ERR_INVALID, "negative item count");
     // validate everything before any work
     std::vector<Beam *> bp((size_t)n);
+    int64_t ws_total = 0;
+    std::vector<const snd::PlanImpl *> plans;
     for (int32_t i = 0; i < n; ++i) {
         snd_stream_item &it = items[i];
         auto f = s->beams.find(it.beam_id);
@@ -162,14 +171,26 @@ snd_status snd_stream_push(snd_stream s, int32_t n, snd_stream_item *items, void
         if (it.chunk_pitch < it.chunk_len) return fail(SND_ERR_INVALID, "item " + std::to_string(i) + ": chunk pitch");
         if (it.out_pitch < P.n_out) return fail(SND_ERR_INVALID, "item " + std::to_string(i) + ": output pitch < n_out");
         if (it.chunk_idx < 0) return fail(SND_ERR_INVALID, "item " + std::to_string(i) + ": negative chunk index");
-        if (P.workspace_bytes > 0 &&
+        ws_total += batched ? ws_share(P) : 0;
+        if (!batched && P.workspace_bytes > 0 &&
             (!d_workspace || workspace_bytes < P.workspace_bytes || ((uintptr_t)d_workspace & 255u)))
             return fail(SND_ERR_NOMEM, "workspace smaller than the plan's workspace_bytes or not 256-byte aligned");
+        plans.push_back(&P);
         bp[(size_t)i] = &b;
+    }
+    if (batched) {
+        if (ws_total > 0 && (!d_workspace || workspace_bytes < ws_total || ((uintptr_t)d_workspace & 255u)))
+            return fail(SND_ERR_NOMEM, "workspace smaller than the batch needs (snd_stream_batch_bytes) or not "
+                                       "256-byte aligned");
+        if (n > 0 && (!d_records || ((uintptr_t)d_records & 255u) ||
+                      records_bytes < snd::batch_record_bytes(plans, nullptr)))
+            return fail(SND_ERR_NOMEM, "record buffer smaller than the batch needs or not 256-byte aligned");
     }
     hipStream_t st = (hipStream_t)stream;
     snd_status ret = SND_OK;
     std::string gap_msg;
+    std::vector<snd::Job> jobs;
+    uint8_t *wsp = static_cast<uint8_t *>(d_workspace);
     for (int32_t i = 0; i < n; ++i) {
         snd_stream_item &it = items[i];
         Beam &b = *bp[(size_t)i];
@@ -203,17 +224,61 @@ snd_status snd_stream_push(snd_stream s, int32_t n, snd_stream_item *items, void
         it.out_n = n_run;
         if (n_run > 0) {
             const snd::Run run{n_run, P.max_delay + n_run, r.ring_len, b.emitted % r.ring_len};
-            for (size_t si = 0; si < P.stages.size(); ++si) {
-                snd_status rs = snd::run_stage(P, si, run, b.ring, r.pitch, it.d_out, it.out_pitch, d_workspace, st);
-                if (rs != SND_OK) return rs;
+            if (batched) {
+                jobs.push_back(snd::Job{&P, run, b.ring, r.pitch, it.d_out, it.out_pitch, wsp});
+                wsp += ws_share(P);
+            } else {
+                for (size_t si = 0; si < P.stages.size(); ++si) {
+                    snd_status rs =
+                        snd::run_stage(P, si, run, b.ring, r.pitch, it.d_out, it.out_pitch, d_workspace, st);
+                    if (rs != SND_OK) return rs;
+                }
             }
         }
         b.received = S1;
         b.emitted = E1;
         b.next_chunk = it.chunk_idx + 1;
     }
+    if (!jobs.empty()) {
+        snd_status rs = snd::run_batch(jobs, d_records, records_bytes, st, nullptr);
+        if (rs != SND_OK) return rs;
+    }
     if (ret != SND_OK) snd::set_error("history reset after a chunk gap: " + gap_msg);
     return ret;
+}
+
+}  // namespace
+
+extern "C" {
+
+snd_status snd_stream_push(snd_stream s, int32_t n, snd_stream_item *items, void *d_workspace,
+                           int64_t workspace_bytes, void *stream)
+{
+    return push_impl(s, n, items, d_workspace, workspace_bytes, nullptr, 0, false, stream);
+}
+
+snd_status snd_stream_push_batched(snd_stream s, int32_t n, snd_stream_item *items, void *d_workspace,
+                                   int64_t workspace_bytes, void *d_records, int64_t records_bytes, void *stream)
+{
+    return push_impl(s, n, items, d_workspace, workspace_bytes, d_records, records_bytes, true, stream);
+}
+
+snd_status snd_stream_batch_bytes(snd_stream s, int32_t n, const int32_t *beam_ids, int64_t *workspace_bytes,
+                                  int64_t *records_bytes)
+{
+    if (!s || n < 0 || (n > 0 && !beam_ids) || !workspace_bytes || !records_bytes)
+        return fail(SND_ERR_INVALID, "null argument or negative count");
+    std::vector<const snd::PlanImpl *> plans;
+    int64_t ws = 0;
+    for (int32_t i = 0; i < n; ++i) {
+        auto f = s->beams.find(beam_ids[i]);
+        if (f == s->beams.end()) return fail(SND_ERR_STATE, "beam not admitted");
+        plans.push_back(&f->second.plan->impl);
+        ws += ws_share(f->second.plan->impl);
+    }
+    *workspace_bytes = ws;
+    *records_bytes = n > 0 ? snd::batch_record_bytes(plans, nullptr) : 0;
+    return SND_OK;
 }
 
 snd_status snd_stream_beam_state(snd_stream s, int32_t beam_id, int64_t *received, int64_t *next_chunk,

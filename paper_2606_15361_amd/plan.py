@@ -26,6 +26,65 @@ def _stream_handle(stream, device):
     return C.c_void_p(s.cuda_stream)
 
 
+def make_desc(freqs, dms, tsamp_s, nsamp, *, mode="float", branching=4, cluster=4, k_leaf=2, k_int=2, cap=255,
+              in_dtype=None, node_dtype=None, root_norm=False, fref=0.0, stage_levels=0, generic_kernels=False,
+              chunk=0):
+    """snd_plan_desc for these parameters; also returns the frequency and DM arrays it points to
+    (keep them alive while the descriptor is used) and the resolved storage types."""
+    freq = np.ascontiguousarray(freqs, dtype=np.float64)
+    dm = np.ascontiguousarray(dms, dtype=np.float64)
+    if in_dtype is None:
+        in_dtype = "f32" if mode == "float" else "u8"
+    if node_dtype is None:
+        node_dtype = "f32" if mode == "float" else ("u8" if mode == "binary" or cap <= 255 else "u16")
+    d = capi.PlanDesc()
+    d.nchan = freq.size
+    d.freq_mhz = freq.ctypes.data_as(C.POINTER(C.c_double))
+    d.tsamp_s = tsamp_s
+    d.fref_mhz = fref
+    d.ndm = dm.size
+    d.dm = dm.ctypes.data_as(C.POINTER(C.c_double))
+    d.branching, d.cluster, d.mode = branching, cluster, MODES[mode]
+    d.k_leaf, d.k_int, d.cap = k_leaf, k_int, cap
+    d.in_dtype, d.node_dtype = DTYPES[in_dtype], DTYPES[node_dtype]
+    d.root_norm = int(root_norm)
+    d.nsamp = int(nsamp or 0)
+    d.chunk = int(chunk)
+    d.stage_levels = int(stage_levels)
+    d.generic_kernels = int(generic_kernels)
+    return d, freq, dm, in_dtype, node_dtype
+
+
+def autotune(freqs, dms, tsamp_s, x, candidates, *, reps=2, out=None, stream=None, **plan_kw):
+    """Time every (stage_levels, chunk) candidate on the block x [nchan][nsamp] with snd_autotune.
+    Returns (index of the fastest, [dict(stage_levels, chunk, ms, workspace_bytes, table_bytes)]).
+    Buffers are sized for the largest candidate that is probed host-side first."""
+    import torch
+    nsamp = x.shape[1]
+    probes = [Plan(freqs, dms, tsamp_s, None if c else nsamp, stage_levels=s, chunk=c, **plan_kw)
+              for s, c in candidates]
+    wsb = max(p.info["workspace_bytes"] for p in probes)
+    tb = max(p.info["table_bytes"] for p in probes)
+    n_out = nsamp - probes[0].max_delay
+    dev = x.device
+    ws = torch.empty(max(256, wsb), dtype=torch.uint8, device=dev)
+    tables = torch.empty(max(256, tb), dtype=torch.uint8, device=dev)
+    if out is None:
+        out = torch.empty((probes[0].ndm, n_out), dtype=probes[0].out_dtype, device=dev)
+    del probes
+    d, _f, _d, _, _ = make_desc(freqs, dms, tsamp_s, nsamp, stage_levels=0, chunk=0, **plan_kw)
+    arr = (capi.TuneCandidate * len(candidates))()
+    for i, (s, c) in enumerate(candidates):
+        arr[i].stage_levels, arr[i].chunk = int(s), int(c)
+    best = C.c_int32()
+    capi.check(capi.lib().snd_autotune(C.byref(d), arr, len(candidates), C.c_void_p(x.data_ptr()), x.stride(0),
+                                       C.c_void_p(out.data_ptr()), out.stride(0), C.c_void_p(ws.data_ptr()),
+                                       ws.numel(), C.c_void_p(tables.data_ptr()), tables.numel(), int(reps),
+                                       C.byref(best), _stream_handle(stream, dev)))
+    return best.value, [dict(stage_levels=a.stage_levels, chunk=a.chunk, ms=a.ms, workspace_bytes=a.workspace_bytes,
+                             table_bytes=a.table_bytes) for a in arr]
+
+
 class Plan:
     """An SND dedispersion plan (host tables, built by snd_plan_create)."""
 
@@ -36,27 +95,10 @@ class Plan:
         """nsamp: input samples per execute; or chunk > 0 (nsamp None): a streaming plan whose
         n_out is `chunk` and whose nsamp is max_delay + chunk."""
         L = capi.lib()
-        self._freq = np.ascontiguousarray(freqs, dtype=np.float64)
-        self._dm = np.ascontiguousarray(dms, dtype=np.float64)
-        if in_dtype is None:
-            in_dtype = "f32" if mode == "float" else "u8"
-        if node_dtype is None:
-            node_dtype = "f32" if mode == "float" else ("u8" if mode == "binary" or cap <= 255 else "u16")
-        d = capi.PlanDesc()
-        d.nchan = self._freq.size
-        d.freq_mhz = self._freq.ctypes.data_as(C.POINTER(C.c_double))
-        d.tsamp_s = tsamp_s
-        d.fref_mhz = fref
-        d.ndm = self._dm.size
-        d.dm = self._dm.ctypes.data_as(C.POINTER(C.c_double))
-        d.branching, d.cluster, d.mode = branching, cluster, MODES[mode]
-        d.k_leaf, d.k_int, d.cap = k_leaf, k_int, cap
-        d.in_dtype, d.node_dtype = DTYPES[in_dtype], DTYPES[node_dtype]
-        d.root_norm = int(root_norm)
-        d.nsamp = int(nsamp or 0)
-        d.chunk = int(chunk)
-        d.stage_levels = int(stage_levels)
-        d.generic_kernels = int(generic_kernels)
+        d, self._freq, self._dm, in_dtype, node_dtype = make_desc(
+            freqs, dms, tsamp_s, nsamp, mode=mode, branching=branching, cluster=cluster, k_leaf=k_leaf, k_int=k_int,
+            cap=cap, in_dtype=in_dtype, node_dtype=node_dtype, root_norm=root_norm, fref=fref,
+            stage_levels=stage_levels, generic_kernels=generic_kernels, chunk=chunk)
         h = C.c_void_p()
         capi.check(L.snd_plan_create(C.byref(d), C.byref(h)))
         self._h = h

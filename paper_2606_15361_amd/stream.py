@@ -60,10 +60,19 @@ class Stream:
     def plan_of(self, beam_id: int) -> Plan:
         return self._beams[int(beam_id)][0]
 
-    def push(self, items, workspace=None, stream=None):
+    def batch_bytes(self, beam_ids):
+        """(workspace bytes, record bytes) of a batched push of these beams."""
+        ids = (C.c_int32 * max(1, len(beam_ids)))(*[int(b) for b in beam_ids])
+        w, r = C.c_int64(), C.c_int64()
+        capi.check(capi.lib().snd_stream_batch_bytes(self._h, len(beam_ids), ids, C.byref(w), C.byref(r)))
+        return w.value, r.value
+
+    def push(self, items, workspace=None, stream=None, batched=False):
         """items: sequence of (beam_id, chunk_idx, chunk [nchan][L] tensor, out [ndm][>= n_out] tensor).
         Returns [(out_t0, out_n, status)] per item; a chunk-index gap resets that beam (status
-        ERR_GAP) and is not raised; every other failure raises SndError."""
+        ERR_GAP) and is not raised; every other failure raises SndError.  batched=True runs the
+        beams' stages in shared grids (snd_stream_push_batched); its workspace and record
+        buffers are kept by this object and grown on demand."""
         n = len(items)
         arr = (capi.StreamItem * max(1, n))()
         ws_need = 0
@@ -78,6 +87,19 @@ class Stream:
             it.d_chunk, it.chunk_pitch = chunk.data_ptr(), chunk.stride(0)
             it.d_out, it.out_pitch = out.data_ptr(), out.stride(0)
             ws_need = max(ws_need, plan.info["workspace_bytes"])
+        if batched:
+            import torch
+            wneed, rneed = self.batch_bytes([it[0] for it in items])
+            if getattr(self, "_bws", None) is None or self._bws.numel() < wneed:
+                self._bws = torch.empty(max(256, wneed), dtype=torch.uint8, device=self.device)
+            if getattr(self, "_brec", None) is None or self._brec.numel() < rneed:
+                self._brec = torch.empty(max(256, rneed), dtype=torch.uint8, device=self.device)
+            rc = capi.lib().snd_stream_push_batched(self._h, n, arr, C.c_void_p(self._bws.data_ptr()),
+                                                    self._bws.numel(), C.c_void_p(self._brec.data_ptr()),
+                                                    self._brec.numel(), _stream_handle(stream, self.device))
+            if rc not in (capi.OK, capi.ERR_GAP):
+                capi.check(rc)
+            return [(arr[i].out_t0, arr[i].out_n, arr[i].status) for i in range(n)]
         if workspace is None and ws_need > 0:
             raise ValueError("a workspace of at least the plans' workspace_bytes is required")
         wsp = C.c_void_p(workspace.data_ptr()) if workspace is not None else None

@@ -196,3 +196,20 @@ def test_batch_grouping_and_errors_host_logic(snd):
                                None) == _capi.ERR_INVALID
     assert L.snd_batch_execute(1, hs, ptr, pitch, ptr, pitch, ptr, wsb, None, C.c_void_p((1 << 20) + 4), nb1, None,
                                None) == _capi.ERR_INVALID  # misaligned records
+
+
+def test_autotune_argument_errors(snd):
+    import ctypes as C
+    from paper_2606_15361_amd import _capi
+    from paper_2606_15361_amd.plan import make_desc
+    L = _capi.lib()
+    f = synth.channel_freqs(16)
+    d, _f, _d, _, _ = make_desc(f, [0.0, 5.0], 0.138e-3, 500, mode="graded", branching=2, chunk=100)
+    c = (_capi.TuneCandidate * 1)()
+    best = C.c_int32()
+    buf = C.c_void_p(1 << 20)
+    rc = L.snd_autotune(C.byref(d), c, 1, buf, 500, buf, 500, buf, 1 << 20, buf, 1 << 20, 1, C.byref(best), None)
+    assert rc == _capi.ERR_INVALID and "whole block" in L.snd_last_error().decode()
+    d.chunk = 0
+    assert L.snd_autotune(C.byref(d), c, 0, buf, 500, buf, 500, buf, 1 << 20, buf, 1 << 20, 1, C.byref(best),
+                          None) == _capi.ERR_INVALID

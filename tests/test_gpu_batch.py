@@ -139,7 +139,7 @@ def test_batch_48_beams_workload(snd):
     rng = synth.make_rng(48)
     for s, p in zip(specs, plans):
         # device-side noise stands in for each beam's filterbank here (the parity of the
-        # encoded path is covered elsewhere); one shared draw per storage type keeps memory low
+        # encoded path is covered elsewhere); drawing on the device keeps the test fast
         z = torch.randn(s.nchan, s.nsamp, device="cuda", generator=None)
         if s.mode == "float":
             xs.append(z if p.in_dtype == "f32" else snd.cast(z, p.in_dtype))
@@ -157,3 +157,22 @@ def test_batch_48_beams_workload(snd):
         ref = plans[b].execute(xs[b], workspace=batch.workspaces[b])
         torch.cuda.synchronize()
         assert torch.equal(y, ref), b
+
+
+def test_autotune_times_candidates_with_identical_results(snd):
+    spec = synth.workload(1)
+    nsamp = 8192
+    x = torch.from_numpy(synth.random_levels(synth.make_rng(21), 64, nsamp, 4)).cuda()
+    plain = snd.Plan(spec.freqs, spec.dms, spec.tsamp_s, nsamp, mode="graded", branching=2)
+    want = plain.execute(x)
+    cands = [(0, 0), (0x80000000, 0), (0, 1000), (0b1111, 0), (0b0101, 1500)]
+    out = torch.zeros_like(want)
+    best, res = snd.autotune(spec.freqs, spec.dms, spec.tsamp_s, x, cands, reps=2, out=out, mode="graded",
+                             branching=2)
+    torch.cuda.synchronize()
+    _say("autotune:", [(r["stage_levels"], r["chunk"], round(r["ms"], 4)) for r in res], "best", best)
+    assert 0 <= best < len(cands)
+    assert all(r["ms"] > 0 for r in res)
+    assert res[best]["ms"] == min(r["ms"] for r in res)
+    assert res[1]["workspace_bytes"] == 0 and res[2]["workspace_bytes"] < res[0]["workspace_bytes"]
+    assert torch.equal(out, want)  # the last candidate (levels 0 and 2, chunks of 1500) wrote the same rows

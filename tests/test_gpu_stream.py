@@ -226,3 +226,51 @@ def test_stream_full_size_graded_chunk(snd):
     assert y.shape[1] == N - plan.max_delay
     plain = snd.Plan(spec.freqs, spec.dms, spec.tsamp_s, N, mode="graded", branching=4)
     assert np.array_equal(y, to_np(plain.execute(x)))
+
+
+def test_batched_push_equals_per_beam_push(snd):
+    """snd_stream_push_batched (shared grids across beams) gives the outputs of the per-beam
+    push, through history fill, steady state and a chunk gap."""
+    spec = synth.workload(1)
+    plans = [snd.Plan(spec.freqs, spec.dms, spec.tsamp_s, None, mode="graded", branching=2, chunk=1024),
+             snd.Plan(spec.freqs, spec.dms[:40], spec.tsamp_s, None, mode="float", branching=4, chunk=1024,
+                      in_dtype="bf16", node_dtype="bf16"),
+             snd.Plan(spec.freqs, spec.dms, spec.tsamp_s, None, mode="binary", branching=2, chunk=800, k_leaf=2,
+                      k_int=1)]
+    rng = synth.make_rng(77)
+    N = 9 * 1024
+    srcs = [torch.from_numpy(synth.random_levels(rng, 64, N, 4)).cuda(),
+            snd.cast(torch.from_numpy(synth.noise_filterbank(rng, 64, N)).cuda(), "bf16"),
+            torch.from_numpy(synth.random_spikes(rng, 64, N, 0.3)).cuda()]
+    a, b = snd.Stream(1 << 34), snd.Stream(1 << 34)
+    for i, p in enumerate(plans):
+        a.admit(10 + i, p)
+        b.admit(10 + i, p)
+    ws = torch.empty(max(p.info["workspace_bytes"] for p in plans), dtype=torch.uint8, device="cuda")
+    oa = [p.empty_output("cuda") for p in plans]
+    ob = [p.empty_output("cuda") for p in plans]
+    idx = [0, 0, 0]
+    pos = [0, 0, 0]
+    gaps = 0
+    for step in range(9):
+        items_a, items_b = [], []
+        for i, p in enumerate(plans):
+            L = min(p.n_out, N - pos[i]) if step % 3 else max(1, p.n_out // 3)
+            if L <= 0:
+                continue
+            if step == 5 and i == 1:
+                idx[i] += 1  # a lost chunk on one beam
+            items_a.append((10 + i, idx[i], srcs[i][:, pos[i]:pos[i] + L], oa[i]))
+            items_b.append((10 + i, idx[i], srcs[i][:, pos[i]:pos[i] + L], ob[i]))
+            idx[i] += 1
+            pos[i] += L
+        ra = a.push(items_a, workspace=ws)
+        rb = b.push(items_b, batched=True)
+        torch.cuda.synchronize()
+        assert ra == rb
+        gaps += sum(1 for _, _, st in ra if st == -7)
+        for (bid, _, _, _), (t0, n, status) in zip(items_a, ra):
+            i = bid - 10
+            if n:
+                assert torch.equal(oa[i][:, :n], ob[i][:, :n]), (step, i)
+    assert gaps == 1
