@@ -22,6 +22,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+METRIC = "dedispersed DM\u00d7time samples/s (1024 ch, 4096 DM) + %HBM peak; p99 chunk latency"
 LDS_PEAK_GBS = 256 * 128 * 2.4  # 256 CUs x 128 B/clk x 2.4 GHz
 KERNEL_SYMBOL = {"generic": "k_stage", "group_lds": "k_group", "anchored": "k_anchored", "group_fast": "k_group_fast"}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic.json")
@@ -73,6 +74,10 @@ def parse():
     ap.add_argument("--cpu-sample", type=int, default=2048, help="output samples in the oracle's timed sample")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one plain 1 GiB device copy first (scale reference for HBM counters)")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default stage schedule")
+    ap.add_argument("--legs", default="batch,serve",
+                    help="extra measurements after the headline: batch (48 beams), serve (streaming loop)")
+    ap.add_argument("--serve-seconds", type=float, default=12.0, help="real-time length of each serving run")
     return ap.parse_args()
 
 
@@ -92,6 +97,216 @@ def cpu_baseline(spec, mode, n_sample):
                 sample=f"shared-pattern SND tree (C, FP64, 1 thread) over all {spec.dms.size} DMs x {n_sample} "
                        f"output samples of the same 1024-channel beam; {dt:.1f} s",
                 seconds=round(dt, 2)), np.asarray(y).shape
+
+
+def batch_leg(snd, synth, torch, dev, reps=3):
+    """48 beams x 1024 ch x 2^16 samples, uneven DM grids (1024-4096 trials, max DM 500-2000), modes
+    rotating binary / graded / float with float storage rotating f32 / bf16 / f16: one batched
+    execute (shared grids) against one execute per beam."""
+    import numpy as np
+    specs = [synth.batch_beam(b) for b in range(48)]
+    t = time.perf_counter()
+    plans = []
+    for s_ in specs:
+        inp = s_.node_dtype if s_.mode == "float" else "u8"
+        plans.append(snd.Plan(s_.freqs, s_.dms, s_.tsamp_s, s_.nsamp, mode=s_.mode, branching=4, k_leaf=s_.k_leaf,
+                              k_int=s_.k_int, node_dtype=s_.node_dtype, in_dtype=inp))
+    t_plan = time.perf_counter() - t
+    xs = []
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(synth.seed_for(4))
+    for s_, p in zip(specs, plans):
+        z = torch.randn(s_.nchan, s_.nsamp, device=dev, generator=gen)
+        if s_.mode == "float":
+            xs.append(z if p.in_dtype == "f32" else snd.cast(z, p.in_dtype))
+        else:
+            xs.append(snd.encode(z, list(s_.enc_thresholds)))
+        del z
+    batch = snd.Batch(plans, dev)
+    outs = [p.empty_output(dev) for p in plans]
+    samples = sum(p.ndm * p.n_out for p in plans)
+    stream = torch.cuda.current_stream(dev)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    ms_batch = timed(lambda: batch.execute(xs, outs))
+    ms_single = timed(lambda: [p.execute(x, out=o, workspace=w)
+                               for p, x, o, w in zip(plans, xs, outs, batch.workspaces)])
+    res = dict(workload="48 beams x 1024 ch x 2^16 samples; DM grids 1024-4096 trials to 500-2000; "
+                        "modes binary/graded/float (f32/bf16/f16); B=4; synthetic N(0,1) encoded on the device",
+               beams=48, grids=batch.n_launches, plan_build_s=round(t_plan, 2),
+               dm_time_samples=int(samples), ms_batched=round(ms_batch, 3), ms_per_beam_launches=round(ms_single, 3),
+               value_batched=samples / (ms_batch * 1e-3), value_per_beam=samples / (ms_single * 1e-3),
+               unit="DM-time samples/s", workspace_gib=round(sum(w.numel() for w in batch.workspaces) / 2**30, 2))
+    del xs, outs, batch
+    torch.cuda.empty_cache()
+    return res
+
+
+class _ChunkSource:
+    """Z-scored 1024-channel chunks on the device for the serving runs: a pool of N(0,1) chunks
+    (reused round-robin, so that drawing a chunk costs one device copy) plus dispersed pulses
+    from a few pre-built templates, placed at random times per beam."""
+
+    def __init__(self, snd, synth, torch, dev, nchan, chunk, nbeams, seconds, pool=12, ntemplates=6):
+        import numpy as np
+        self.torch, self.dev, self.T = torch, dev, chunk
+        gen = torch.Generator(device=dev)
+        gen.manual_seed(synth.seed_for(5))
+        self.pool = [torch.randn(nchan, chunk, device=dev, generator=gen) for _ in range(pool)]
+        rng = synth.make_rng(synth.seed_for(5, 99))
+        freqs = synth.channel_freqs(nchan)
+        self.templates = []
+        for i in range(ntemplates):
+            dm = float(rng.uniform(100.0, 1800.0))
+            width = float(np.exp(rng.uniform(np.log(0.5), np.log(5.0))))
+            sweep = int(synth.KDM_MS * dm * (freqs.min() ** -2 - freqs.max() ** -2) / (synth.TSAMP_S * 1e3))
+            span = sweep + 200
+            z = np.zeros((nchan, span), np.float32)
+            synth.inject_pulses(z, freqs, synth.TSAMP_S, [synth.Pulse(dm=dm, t0=60.0, width_ms=width,
+                                                                      snr=float(rng.uniform(15, 40)))])
+            self.templates.append(torch.from_numpy(z).to(dev))
+        # one pulse every ~8 s per beam at a random template and phase
+        total = int(seconds / (chunk * synth.TSAMP_S) + 2) * chunk
+        self.pulses = {}
+        for b in range(nbeams):
+            n = max(1, int(seconds / 8))
+            starts = np.sort(rng.uniform(0, total, n)).astype(np.int64)
+            self.pulses[b] = [(int(s0), int(rng.integers(ntemplates))) for s0 in starts]
+
+    def __call__(self, beam, idx):
+        z = self.pool[(beam * 7 + idx) % len(self.pool)].clone()
+        lo, hi = idx * self.T, (idx + 1) * self.T
+        for s0, k in self.pulses.get(beam, ()):
+            tpl = self.templates[k]
+            a, b = max(lo, s0), min(hi, s0 + tpl.shape[1])
+            if a < b:
+                z[:, a - lo:b - lo] += tpl[:, a - s0:b - s0]
+        return z
+
+
+class _PlainServer:
+    """The plain per-beam form for comparison: each chunk is appended to an explicit overlap
+    buffer (the previous max_delay samples + the chunk), the buffer is encoded or cast and
+    executed with its own launches, then detected."""
+
+    def __init__(self, snd, torch, kinds, dev):
+        self.snd, self.torch, self.dev, self.kinds = snd, torch, dev, kinds
+        self.kind_of, self.buf, self.filled, self.out, self.nidx = {}, {}, {}, {}, {}
+        self.det = {k: snd.Detector(p, widths=(1, 2, 4, 8, 16, 32, 64), threshold=7.0, device=dev)
+                    for k, (p, _) in kinds.items()}
+        self.ws = torch.empty(max(p.info["workspace_bytes"] for p, _ in kinds.values()), dtype=torch.uint8,
+                              device=dev)
+
+    def admit(self, beam, kind):
+        p = self.kinds[kind][0]
+        self.kind_of[beam] = kind
+        self.buf[beam] = self.torch.zeros(p.nchan, p.nsamp, device=self.dev)
+        self.filled[beam] = 0
+        self.out[beam] = p.empty_output(self.dev)
+        return True
+
+    def evict(self, beam):
+        for d in (self.kind_of, self.buf, self.filled, self.out):
+            d.pop(beam, None)
+
+    def beams(self):
+        return sorted(self.kind_of)
+
+    def next_index(self, beam):
+        return self.nidx.get(beam, 0)
+
+    def process(self, ready):
+        done = []
+        for beam, idx, z in ready:
+            p, thr = self.kinds[self.kind_of[beam]]
+            buf, T, D = self.buf[beam], z.shape[1], p.max_delay
+            self.nidx[beam] = idx + 1
+            buf[:, :D] = buf[:, T:T + D].clone()
+            buf[:, D:D + T] = z
+            self.filled[beam] += T
+            if self.filled[beam] < D + T:
+                done.append((beam, idx, 0, 0, None))
+                continue
+            x = self.snd.encode(buf, thr) if thr is not None else self.snd.cast(buf, p.in_dtype)
+            p.execute(x, out=self.out[beam], workspace=self.ws)
+            done.append((beam, idx, 0, T, self.det[self.kind_of[beam]].run(self.out[beam])))
+        return done
+
+
+def serve_leg(snd, synth, torch, dev, seconds):
+    """Streaming service (48 beams of 1024 ch, 8192-sample chunks = 1.13 s, arrivals at a random
+    phase with inter-arrival 1.13 s x U(0.8, 1.2); half graded (4-level u8), half BF16 float;
+    4096 DMs to 2000, B = 4; history budget for about 44 beams; 40 beams at start, one leaves and
+    one joins every 10 s).  Real-time runs of the batched streaming form and of the plain per-beam
+    form, then a saturation run of each (all chunks ready at once) for capacity."""
+    import numpy as np
+    from paper_2606_15361_amd import serve
+    T = 8192
+    sg, sf = synth.stream_beam(0, T), synth.stream_beam(1, T)
+    pg = snd.Plan(sg.freqs, sg.dms, sg.tsamp_s, None, mode="graded", branching=4, chunk=T)
+    pf = snd.Plan(sf.freqs, sf.dms, sf.tsamp_s, None, mode="float", branching=4, chunk=T, in_dtype="bf16",
+                  node_dtype="bf16")
+    kinds = {"graded": (pg, [1.0, 2.0, 3.0, 4.0]), "bf16": (pf, None)}
+    budget = 22 * snd.history_bytes(pg) + 22 * snd.history_bytes(pf)
+    period = synth.chunk_period_s(T)
+    src = _ChunkSource(snd, synth, torch, dev, 1024, T, 48, max(seconds, 30.0) + 30.0)
+    kind = lambda b: "graded" if b % 2 == 0 else "bf16"
+    out = {}
+    for form in ("batched_stream", "plain_per_beam"):
+        rng = synth.make_rng(synth.seed_for(5, 7))  # the same arrivals for both forms
+        if form == "batched_stream":
+            server = serve.Server(kinds, budget, batched=True, device=dev)
+        else:
+            server = _PlainServer(snd, torch, kinds, dev)
+        for b in range(40):
+            assert server.admit(b, kind(b))
+        arr = {b: a for b, a in enumerate(synth.arrival_times(rng, 48, seconds + 5.0, period))}
+        joins = [(10.0 * (i + 1), 40 + i, kind(40 + i)) for i in range(int(seconds // 10))]
+        leaves = [(10.0 * (i + 1), i) for i in range(int(seconds // 10))]
+        log(f"[bench] serving ({form}) for {seconds:.0f} s")
+        recs, adm = serve.run_schedule(server, arr, src, duration_s=seconds, joins=joins, leaves=leaves, log=log)
+        lat = np.array([r["latency"] for r in recs if r["counted"]])
+        nout = sum(1 for r in recs if r["counted"])
+        out[form] = dict(chunks=len(recs), counted=int(nout),
+                         p50_ms=round(float(np.percentile(lat, 50)) * 1e3, 3) if lat.size else None,
+                         p99_ms=round(float(np.percentile(lat, 99)) * 1e3, 3) if lat.size else None,
+                         candidates_per_s=round(sum(r["candidates"] for r in recs) / seconds, 3),
+                         admissions=[dict(t=a[0], beam=a[1], kind=a[2], admitted=a[3]) for a in adm])
+        # saturation: every beam has a chunk ready at once, rounds back to back (after the
+        # histories are full), outputs counted as produced
+        beams = server.beams()
+        nxt = {b: server.next_index(b) for b in beams}
+        for r in range(4):  # fill the histories of recently joined beams
+            server.process([(b, nxt[b] + r, src(b, nxt[b] + r)) for b in beams])
+        torch.cuda.synchronize()
+        nround, produced = 6, 0
+        t0 = time.perf_counter()
+        for r in range(4, 4 + nround):
+            res = server.process([(b, nxt[b] + r, src(b, nxt[b] + r)) for b in beams])
+            produced += sum(n for _, _, _, n, _ in res)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        out[form]["saturated_beams"] = len(beams)
+        out[form]["saturated_chunks_per_s"] = round(nround * len(beams) / dt, 2)
+        out[form]["saturated_dm_time_samples_per_s"] = produced * pg.ndm / dt
+        del server
+        torch.cuda.empty_cache()
+    out["workload"] = ("48 beams x 1024 ch, 8192-sample chunks (1.1305 s), arrivals period x U(0.8,1.2); half graded "
+                       "u8 / half bf16 float; 4096 DMs to 2000; B=4; history budget ~44 beams; 40 at start, one "
+                       "leaves and one joins every 10 s")
+    out["seconds"] = seconds
+    out["real_time_bound_ms"] = round(period * 1e3, 1)
+    return out
 
 
 def main():
@@ -130,9 +345,18 @@ def main():
         in_dtype = node
         x = snd.cast(zt, node)
     del zt
-    plan = snd.Plan(spec.freqs, spec.dms, spec.tsamp_s, spec.nsamp, mode=mode, branching=spec.branching,
-                    cluster=spec.cluster, k_leaf=2, k_int=1, cap=255, node_dtype=node, in_dtype=in_dtype,
-                    stage_levels=args.stage_levels, generic_kernels=args.generic_kernels)
+    pkw = dict(mode=mode, branching=spec.branching, cluster=spec.cluster, k_leaf=2, k_int=1, cap=255,
+               node_dtype=node, in_dtype=in_dtype, generic_kernels=args.generic_kernels)
+    tuned = None
+    stage_levels = args.stage_levels
+    if not args.no_autotune and not args.stage_levels and not args.generic_kernels:
+        # measured choice of the stage schedule: leaves only, level 2 only, leaves and level 2
+        cands = [(0, 0), (0b0100, 0), (0b0101, 0)]
+        best, tuned = snd.autotune(spec.freqs, spec.dms, spec.tsamp_s, x, cands, reps=1, **pkw)
+        stage_levels = cands[best][0]
+        log(f"[bench] autotune: {[(hex(t['stage_levels']), round(t['ms'], 2)) for t in tuned]} -> {stage_levels:#x}")
+        torch.cuda.empty_cache()
+    plan = snd.Plan(spec.freqs, spec.dms, spec.tsamp_s, spec.nsamp, stage_levels=stage_levels, **pkw)
     info = plan.info
     log(f"[bench] plan: {info['n_neurons']} neurons, {info['n_synapses']} synapses, stages {info['stage_rows']}, "
         f"workspace {info['workspace_bytes'] / 2**30:.2f} GiB, built in {info['build_seconds']:.2f} s")
@@ -197,7 +421,7 @@ def main():
     whole_alg = sum(info["stage_alg_bytes"])
     dtype_name = {"float": node or "f32", "graded": "u8", "binary": "u8"}[mode]
     result = {
-        "metric": "dedispersed DM x time samples/s (1024 ch, 4096 DM) + %HBM peak; p99 chunk latency",
+        "metric": METRIC,
         "value": value,
         "unit": "DM-time samples/s",
         "n_gpus": 1,
@@ -230,6 +454,19 @@ def main():
         "plan": {"neurons": info["n_neurons"], "synapses": info["n_synapses"],
                  "workspace_gib": round(info["workspace_bytes"] / 2**30, 3)},
     }
+    if tuned is not None:
+        result["autotune"] = [dict(stage_levels=hex(t["stage_levels"]), ms=round(t["ms"], 3),
+                                   workspace_gib=round(t["workspace_bytes"] / 2**30, 2)) for t in tuned]
+    result["config"]["stage_levels"] = hex(stage_levels)
+    legs = [l for l in args.legs.split(",") if l]
+    if legs:
+        del x, out, ws, detector, plan
+        torch.cuda.empty_cache()
+    if "batch" in legs:
+        log("[bench] batched leg: 48 beams")
+        result["batch"] = batch_leg(snd, synth, torch, dev)
+    if "serve" in legs:
+        result["serving"] = serve_leg(snd, synth, torch, dev, args.serve_seconds)
     if not args.no_cpu_baseline:
         log("[bench] timing the oracle on a bounded sample")
         cb, _ = cpu_baseline(spec, mode, args.cpu_sample)
