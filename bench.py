@@ -458,7 +458,7 @@ def main():
         result["autotune"] = [dict(stage_levels=hex(t["stage_levels"]), ms=round(t["ms"], 3),
                                    workspace_gib=round(t["workspace_bytes"] / 2**30, 2)) for t in tuned]
     result["config"]["stage_levels"] = hex(stage_levels)
-    legs = [l for l in args.legs.split(",") if l]
+    legs = [l for l in args.legs.split(",") if l and l != "none"]
     if legs:
         del x, out, ws, detector, plan
         torch.cuda.empty_cache()

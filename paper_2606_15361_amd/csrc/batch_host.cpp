@@ -108,6 +108,7 @@ snd_status run_batch(const std::vector<Job> &jobs, void *d_records, int64_t reco
                 merged.lds = std::max(merged.lds, p.lds);
                 merged.max_len = std::max(merged.max_len, p.max_len);
                 merged.n_run = std::max(merged.n_run, p.n_run);
+                merged.bad_pitch = merged.bad_pitch || p.bad_pitch;
             }
             std::memcpy(host.data() + pre_off, prefix.data(), prefix.size() * sizeof(int32_t));
             // pageable source: the copy has consumed it when the call returns

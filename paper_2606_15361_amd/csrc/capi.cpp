@@ -157,6 +157,7 @@ Prepared prepare_stage(const PlanImpl &P, size_t si, const Run &run, const void 
                             : 1.0f;
     if (S.kernel == kKernelGroupLds) {
         GroupArgs &g = pr.gr;
+        pr.bad_pitch = a.src_pitch < 0 || a.src_pitch * dtype_size(S.src_dtype) >= (int64_t(1) << 32);
         g.src = a.src;
         g.src_pitch = a.src_pitch;
         g.dst = a.dst;
@@ -164,7 +165,7 @@ Prepared prepare_stage(const PlanImpl &P, size_t si, const Run &run, const void 
         g.grp_rows = reinterpret_cast<const int32_t *>(tb + S.off_grp_rows);
         g.batch_ptr = reinterpret_cast<const int32_t *>(tb + S.off_batch_ptr);
         g.batches = reinterpret_cast<const int32_t *>(tb + S.off_batches);
-        g.slots = reinterpret_cast<const int32_t *>(tb + S.off_slots);
+        g.instrs = reinterpret_cast<const int32_t *>(tb + S.off_instrs);
         g.ldsb = reinterpret_cast<const uint32_t *>(tb + S.off_ldsb);
         g.ngroups = (int32_t)S.ngroups;
         g.n_entries = S.n_entries;
@@ -228,6 +229,10 @@ snd_status launch_prepared(const Prepared &pr, void *stream, const Multi &m, int
     int e = 0;
     const char *what = "stage launch";
     if (pr.kind == kKernelGroupLds) {
+        if (pr.bad_pitch) {
+            set_error("source row pitch of 4 GiB or more is not supported by the LDS row-group kernels");
+            return SND_ERR_UNSUPPORTED;
+        }
         e = launch_group(pr.mode, pr.src_dt, pr.dst_dt, pr.gr, pr.n_run, pr.lds, stream, m, nblocks);
         what = "stage launch (LDS groups)";
     } else if (pr.kind == kKernelAnchored) {

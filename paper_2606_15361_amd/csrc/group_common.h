@@ -28,46 +28,55 @@ __device__ inline void wait_vmcnt(int n)
 #undef SND_VM
 }
 
-// Copy this wave's windows of batch b (windows wave, wave + kGroupRows, ...) into LDS buffer
-// `dst` in 16-byte units straight from global memory to LDS (1 KB per instruction).  A window
-// is (source row, start offset, span, LDS element offset); it covers span + vt samples from
-// sample t0 + start, and its LDS footprint starts `start mod (elements per 16 bytes)` elements
-// before its offset so that 16-byte copies from the 16-byte aligned source row land every
-// element in place.  Returns the number of copy instructions issued.
+// Asynchronous copy of this wave's windows of batch b (windows wave, wave + kGroupRows, ...)
+// into the LDS buffer `dst`, straight from global memory to LDS in 16-byte units, 64 units (one
+// per lane, 1 KB) per instruction.  A window's descriptor is (source row, element offset of its
+// 16-byte aligned footprint, LDS byte offset of the footprint, head + span); for a tile of vt
+// samples it covers head + span + vt elements.  Returns the number of copy instructions issued.
 template <typename TI>
-__device__ inline int issue_windows(const_ptr<int32_t> batches, const_ptr<int32_t> slots, int b, int wave, int lane,
-                                    const unsigned char *srcb, int64_t src_pitch, int t0, int vt, TI *dst)
+__device__ inline int issue_batch(const_ptr<int32_t> batches, const_ptr<int32_t> instrs, int b, int wave, int lane,
+                                  const unsigned char *srcb, int64_t pitch_bytes, int t0, int vt, TI *dst)
 {
     constexpr int ES = (int)sizeof(TI);
-    constexpr int EPU = 16 / ES;  // elements per 16-byte unit
     const int bz = batches[4 * b + 2], bw = batches[4 * b + 3];
+    unsigned char *ldsb = reinterpret_cast<unsigned char *>(dst);
     int n_ins = 0;
-#pragma unroll
-    for (int k = 0; k < kGroupSlotsPerWave; ++k) {
-        const int si = bz + wave + kGroupRows * k;
-        if (si < bw) {
-            const int srow = slots[4 * si], start = slots[4 * si + 1], span = slots[4 * si + 2];
-            const int lofs = slots[4 * si + 3];
-            const int head = start % EPU;
-            const uint4 *gp =
-                reinterpret_cast<const uint4 *>(srcb + ((int64_t)srow * src_pitch + t0 + start - head) * ES);
-            uint4 *lp = reinterpret_cast<uint4 *>(dst + lofs - head);
-            const int nu = ((head + span + vt) * ES + 15) / 16;  // 16-byte units
+    for (int si = bz + wave; si < bw; si += kGroupRows) {
+        {
+            const int srow = instrs[4 * si], eoff = instrs[4 * si + 1], lbyte = instrs[4 * si + 2];
+            const int hs = instrs[4 * si + 3];
+            // row and offsets are non-negative and a row pitch is below 4 GiB (checked on the host)
+            const uint4 *gp = reinterpret_cast<const uint4 *>(srcb + (uint64_t)(uint32_t)srow * (uint32_t)pitch_bytes +
+                                                              (uint64_t)(uint32_t)(eoff + t0) * ES) + lane;
+            unsigned char *lp = ldsb + lbyte;
+            const int nu = ((hs + vt) * ES + 15) >> 4;  // 16-byte units of the window for this tile
             int u0 = 0;
             for (; u0 + 64 <= nu; u0 += 64) {  // whole instructions, no mask
-                __builtin_amdgcn_global_load_lds(gp + u0 + lane, (__attribute__((address_space(3))) void *)(lp + u0), 16,
+                __builtin_amdgcn_global_load_lds(gp + u0, (__attribute__((address_space(3))) void *)(lp + 16 * u0), 16,
                                                  0, 0);
                 ++n_ins;
             }
             if (u0 < nu) {
                 if (u0 + lane < nu)
-                    __builtin_amdgcn_global_load_lds(gp + u0 + lane, (__attribute__((address_space(3))) void *)(lp + u0),
+                    __builtin_amdgcn_global_load_lds(gp + u0, (__attribute__((address_space(3))) void *)(lp + 16 * u0),
                                                      16, 0, 0);
                 ++n_ins;
             }
         }
     }
     return n_ins;
+}
+
+// Workgroup barrier for the staged kernels.  Every wave has already waited for its own copies
+// into the buffer about to be read (wait_vmcnt), and every LDS read of the buffer about to be
+// refilled has returned (its values were summed), so only the execution barrier is needed:
+// unlike __syncthreads() this does not wait for the copies of the batches still in flight.  The
+// empty asm statements keep the compiler from moving memory accesses across it.
+__device__ inline void stage_barrier()
+{
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
 }
 
 int launch_group_fast_binary(int src_dt, int dst_dt, const GroupArgs &a, int64_t n_out, int lds, void *stream,

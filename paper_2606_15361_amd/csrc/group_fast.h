@@ -18,7 +18,8 @@ __global__ __launch_bounds__(1024) void k_group_fast(GroupArgs s0, Multi m)
     uint32_t bid, nblk;
     select_record(s0, m, s, bid, nblk);
     constexpr int T = kGroupTileFast;
-    constexpr int V = T / 64;          // samples per lane
+    constexpr int V = kFastV;            // samples per lane
+    constexpr int R = kFastRows;         // DM rows per wave
     constexpr int SC = F1 < 4 ? F1 : 4;  // inputs whose reads are issued together
     constexpr int NS = D > 1 ? D - 1 : 1;
     extern __shared__ __align__(16) unsigned char smem[];
@@ -29,93 +30,111 @@ __global__ __launch_bounds__(1024) void k_group_fast(GroupArgs s0, Multi m)
     const int g = (int)(L % (uint32_t)s.ngroups);
     const int t0 = (int)(L / (uint32_t)s.ngroups) * T;
     const int vt = s.n_out - t0 < T ? s.n_out - t0 : T;
-    const int row = __builtin_amdgcn_readfirstlane(as_const(s.grp_rows)[g * kGroupRows + wave]);
-    const_ptr<uint32_t> lb = as_const(s.ldsb) + (int64_t)(g * kGroupRows + wave) * s.n_entries;
+    int row[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q)
+        row[q] = __builtin_amdgcn_readfirstlane(as_const(s.grp_rows)[(g * kGroupRows + wave) * R + q]);
+    // entry e of row q of this wave: lb[e * R + q]
+    const_ptr<uint32_t> lb = as_const(s.ldsb) + (int64_t)(g * kGroupRows + wave) * s.n_entries * R;
     const unsigned char *srcb = static_cast<const unsigned char *>(s.src);
     const_ptr<int32_t> batches = as_const(s.batches);
-    const_ptr<int32_t> slots = as_const(s.slots);
+    const_ptr<int32_t> instrs = as_const(s.instrs);
+    const int64_t pitch_bytes = s.src_pitch * (int64_t)sizeof(TI);
 
-    A stk[NS][V];  // stk[j - 2]: partial sum of the open level-j node, j = 2 .. D
-    A out[V];
+    A stk[NS][R][V];  // stk[j - 2]: partial sums of the open level-j node, j = 2 .. D
+    A out[R][V];
 #pragma unroll
     for (int j = 0; j < NS; ++j)
 #pragma unroll
-        for (int v = 0; v < V; ++v) stk[j][v] = 0;
+        for (int q = 0; q < R; ++q)
 #pragma unroll
-    for (int v = 0; v < V; ++v) out[v] = 0;
+            for (int v = 0; v < V; ++v) stk[j][q][v] = 0;
+#pragma unroll
+    for (int q = 0; q < R; ++q)
+#pragma unroll
+        for (int v = 0; v < V; ++v) out[q][v] = 0;
 
     const int b0 = as_const(s.batch_ptr)[g], b1 = as_const(s.batch_ptr)[g + 1];
-    int n1 = 0, n2 = 0;  // copies outstanding for batches b+1 and b+2
-    if (b0 < b1) issue_windows<TI>(batches, slots, b0, wave, lane, srcb, s.src_pitch, t0, vt, lds);
-    if (b0 + 1 < b1) n1 = issue_windows<TI>(batches, slots, b0 + 1, wave, lane, srcb, s.src_pitch, t0, vt, lds + s.buf_elems);
+    static_assert(kFastBuffers == 2, "the pipeline below double-buffers");
+    if (b0 < b1) issue_batch<TI>(batches, instrs, b0, wave, lane, srcb, pitch_bytes, t0, vt, lds);
     int buf = 0;
     for (int b = b0; b < b1; ++b) {
-        wait_vmcnt(n1);   // this wave's copies of batch b have landed
-        __syncthreads();  // everyone's have; everyone is done reading batch b - 1
-        n2 = 0;
-        if (b + 2 < b1)
-            n2 = issue_windows<TI>(batches, slots, b + 2, wave, lane, srcb, s.src_pitch, t0, vt,
-                                   lds + (buf == 0 ? 2 : buf - 1) * s.buf_elems);
-        if (row >= 0) {
+        __builtin_amdgcn_s_waitcnt(0x0f70);  // vmcnt(0): this wave's copies of batch b have landed
+        stage_barrier();  // everyone's have; everyone is done reading batch b - 1
+        if (b + 1 < b1)   // into the buffer of batch b - 1
+            issue_batch<TI>(batches, instrs, b + 1, wave, lane, srcb, pitch_bytes, t0, vt, lds + (buf ^ 1) * s.buf_elems);
+        if (row[0] >= 0) {
             const int ex = batches[4 * b], ey = batches[4 * b + 1];
             const TI *base = lds + buf * s.buf_elems + lane;
             for (int c0 = ex; c0 < ey; c0 += F1) {  // one level-1 node per step
-                uint32_t x[F1];
+                uint32_t x[F1][R];
 #pragma unroll
-                for (int u = 0; u < F1; ++u) x[u] = lb[c0 + u];
-                A a1[V];
+                for (int u = 0; u < F1; ++u)
+#pragma unroll
+                    for (int q = 0; q < R; ++q) x[u][q] = lb[(c0 + u) * R + q];
+                A a1[R][V];
 #pragma unroll
                 for (int u0 = 0; u0 < F1; u0 += SC) {
-                    A val[SC][V];
-#pragma unroll
-                    for (int u = 0; u < SC; ++u) {
-                        const TI *p = base + (x[u0 + u] & kRowMask);
-#pragma unroll
-                        for (int v = 0; v < V; ++v) {
-                            A y = (A)Load<TI>::get(p + 64 * v);
-                            if constexpr (MODE == SND_MODE_BINARY) y = y != 0;
-                            val[u][v] = y;
-                        }
-                    }
+                    A val[SC][R][V];
 #pragma unroll
                     for (int u = 0; u < SC; ++u)
 #pragma unroll
-                        for (int v = 0; v < V; ++v) {
-                            if (u0 + u == 0) a1[v] = val[u][v];
-                            else a1[v] += val[u][v];
+                        for (int q = 0; q < R; ++q) {
+                            const TI *p = base + (x[u0 + u][q] & kRowMask);
+#pragma unroll
+                            for (int v = 0; v < V; ++v) {
+                                A y = (A)Load<TI>::get(p + 64 * v);
+                                if constexpr (MODE == SND_MODE_BINARY) y = y != 0;
+                                val[u][q][v] = y;
+                            }
                         }
+#pragma unroll
+                    for (int u = 0; u < SC; ++u)
+#pragma unroll
+                        for (int q = 0; q < R; ++q)
+#pragma unroll
+                            for (int v = 0; v < V; ++v) {
+                                if (u0 + u == 0) a1[q][v] = val[u][q][v];
+                                else a1[q][v] += val[u][q][v];
+                            }
                 }
 #pragma unroll
-                for (int v = 0; v < V; ++v) {
-                    const A y = activate<MODE>(a1[v], 1, s.src_is_input, s.k_leaf, s.k_int, s.cap);
-                    if constexpr (D == 1) out[v] = y;
-                    else stk[0][v] += y;
-                }
-                const int c = (int)(x[F1 - 1] >> 24);  // levels completed by this node's last input
+                for (int q = 0; q < R; ++q)
+#pragma unroll
+                    for (int v = 0; v < V; ++v) {
+                        const A y = activate<MODE>(a1[q][v], 1, s.src_is_input, s.k_leaf, s.k_int, s.cap);
+                        if constexpr (D == 1) out[q][v] = y;
+                        else stk[0][q][v] += y;
+                    }
+                const int c = (int)(x[F1 - 1][0] >> 24);  // levels completed by this node's last input
 #pragma unroll
                 for (int j = 2; j <= D; ++j) {
                     if (j <= c) {
 #pragma unroll
-                        for (int v = 0; v < V; ++v) {
-                            const A y = activate<MODE>(stk[j - 2][v], j, s.src_is_input, s.k_leaf, s.k_int, s.cap);
-                            stk[j - 2][v] = 0;
-                            if (j == D) out[v] = y;
-                            else stk[(j - 1) < NS ? (j - 1) : 0][v] += y;  // index is j - 1 here
-                        }
+                        for (int q = 0; q < R; ++q)
+#pragma unroll
+                            for (int v = 0; v < V; ++v) {
+                                const A y =
+                                    activate<MODE>(stk[j - 2][q][v], j, s.src_is_input, s.k_leaf, s.k_int, s.cap);
+                                stk[j - 2][q][v] = 0;
+                                if (j == D) out[q][v] = y;
+                                else stk[(j - 1) < NS ? (j - 1) : 0][q][v] += y;  // index is j - 1 here
+                            }
                     }
                 }
             }
         }
-        n1 = n2;
-        buf = buf == 2 ? 0 : buf + 1;
+        buf ^= 1;
     }
-    if (row >= 0) {
-        TO *dst = static_cast<TO *>(s.dst) + (int64_t)row * s.dst_pitch + t0 + lane;
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+        if (row[q] < 0) continue;
+        TO *dst = static_cast<TO *>(s.dst) + (int64_t)row[q] * s.dst_pitch + t0 + lane;
 #pragma unroll
         for (int v = 0; v < V; ++v)
             if (lane + 64 * v < vt) {
-                if constexpr (MODE == SND_MODE_FLOAT) Store<TO>::put(dst + 64 * v, out[v] * s.scale);
-                else Store<TO>::put(dst + 64 * v, out[v]);
+                if constexpr (MODE == SND_MODE_FLOAT) Store<TO>::put(dst + 64 * v, out[q][v] * s.scale);
+                else Store<TO>::put(dst + 64 * v, out[q][v]);
             }
     }
 }

@@ -45,7 +45,8 @@ __global__ __launch_bounds__(1024) void k_group(GroupArgs s0, Multi m)
     const_ptr<uint32_t> lb = as_const(s.ldsb) + (int64_t)(g * kGroupRows + wave) * s.n_entries;
     const unsigned char *srcb = static_cast<const unsigned char *>(s.src);
     const_ptr<int32_t> batches = as_const(s.batches);  // 4 ints per batch
-    const_ptr<int32_t> slots = as_const(s.slots);      // 4 ints per window
+    const_ptr<int32_t> instrs = as_const(s.instrs);    // 4 ints per copy instruction
+    const int64_t pitch_bytes = s.src_pitch * (int64_t)sizeof(TI);
 
     A acc[MAXD][V];
     A out[V];
@@ -58,7 +59,7 @@ __global__ __launch_bounds__(1024) void k_group(GroupArgs s0, Multi m)
 
     // asynchronous copy of this wave's windows of batch b into LDS buffer buf
     auto issue = [&](int b, int buf) {
-        return issue_windows<TI>(batches, slots, b, wave, lane, srcb, s.src_pitch, t0, vt, lds + buf * s.buf_elems);
+        return issue_batch<TI>(batches, instrs, b, wave, lane, srcb, pitch_bytes, t0, vt, lds + buf * s.buf_elems);
     };
 
     const int b0 = as_const(s.batch_ptr)[g], b1 = as_const(s.batch_ptr)[g + 1];
@@ -68,7 +69,7 @@ __global__ __launch_bounds__(1024) void k_group(GroupArgs s0, Multi m)
     int buf = 0;
     for (int b = b0; b < b1; ++b) {
         wait_vmcnt(n1);   // this wave's copies of batch b have landed
-        __syncthreads();  // everyone's have; everyone is done reading batch b - 1
+        stage_barrier();  // everyone's have; everyone is done reading batch b - 1
         n2 = 0;
         if (b + 2 < b1) n2 = issue(b + 2, buf == 0 ? 2 : buf - 1);  // the buffer of batch b - 1
         if (row >= 0) {

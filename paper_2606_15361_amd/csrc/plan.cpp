@@ -126,6 +126,8 @@ bool build_group_lds(const PlanImpl &p, Stage &S, bool allow_fast)
             f1 = 0;
     }
     const int tile = f1 ? kGroupTileFast : kGroupTile;
+    const int rpw = f1 ? kFastRows : 1;  // rows per wave
+    const int gr = kGroupRows * rpw;     // rows per group
     const int unit = f1 ? f1 : 1;  // batches end on level-1 node boundaries
     const int es = dtype_size(S.src_dtype);
     const int64_t budget = (f1 ? kGroupFastLdsBytes : kGroupLdsBytes) / es;
@@ -137,11 +139,15 @@ bool build_group_lds(const PlanImpl &p, Stage &S, bool allow_fast)
     std::vector<int32_t> order(rows);
     std::iota(order.begin(), order.end(), 0);
     std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return p.dm[a] < p.dm[b]; });
-    const int64_t ng = (rows + kGroupRows - 1) / kGroupRows;
-    std::vector<int32_t> grp_rows((size_t)(ng * kGroupRows), -1);
+    const int64_t ng = (rows + gr - 1) / gr;
+    std::vector<int32_t> grp_rows((size_t)(ng * gr), -1);
     for (int64_t i = 0; i < rows; ++i) grp_rows[(size_t)i] = order[(size_t)i];
     std::vector<int32_t> batch_ptr(1, 0), batches, slots;
-    std::vector<uint32_t> ldsb((size_t)(ng * kGroupRows * ne), 0);
+    std::vector<uint32_t> ldsb((size_t)(ng * gr * ne), 0);
+    // row w of group g (wave w / rpw, row w % rpw of that wave) at entry e
+    auto ldsb_at = [&](int64_t g, int w, int32_t e) -> uint32_t & {
+        return ldsb[(size_t)((((g * kGroupRows + w / rpw) * ne) + e) * rpw + w % rpw)];
+    };
     int64_t max_elems = 0;
     const int32_t max_slots = kGroupRows * kGroupSlotsPerWave;
     // windows of one entry: the group's (source row, offset) reads, clustered per source row
@@ -150,7 +156,7 @@ bool build_group_lds(const PlanImpl &p, Stage &S, bool allow_fast)
     struct Src { uint32_t row; int32_t lo, hi; };
     std::vector<Rd> rd;
     std::vector<Src> srcs;
-    std::vector<int32_t> slot_of(kGroupRows);
+    std::vector<int32_t> slot_of(gr);
     std::vector<Src> unit_srcs;
     std::vector<int32_t> unit_nsrc;
     for (int64_t g = 0; g < ng; ++g) {
@@ -163,8 +169,8 @@ bool build_group_lds(const PlanImpl &p, Stage &S, bool allow_fast)
         std::vector<std::vector<int32_t>> unit_slot_of;
         for (int32_t e = eu; e < eu + unit; ++e) {
             rd.clear();
-            for (int w = 0; w < kGroupRows; ++w) {
-                const int32_t r = grp_rows[(size_t)(g * kGroupRows + w)];
+            for (int w = 0; w < gr; ++w) {
+                const int32_t r = grp_rows[(size_t)(g * gr + w)];
                 if (r < 0) continue;
                 const Entry &en = S.ent[S.row_ptr[r] + e];
                 rd.push_back({en.rowc & kRowMask, en.off, w});
@@ -208,14 +214,17 @@ bool build_group_lds(const PlanImpl &p, Stage &S, bool allow_fast)
                 elems += slot_elems(sr.lo, sr.hi - sr.lo);
             }
             const std::vector<int32_t> &so = unit_slot_of[(size_t)(e - eu)];
-            for (int w = 0; w < kGroupRows; ++w) {
-                const int32_t r = grp_rows[(size_t)(g * kGroupRows + w)];
-                if (r < 0) continue;
+            const uint32_t closes = S.ent[e].rowc & ~kRowMask;  // identical for every row
+            for (int w = 0; w < gr; ++w) {
+                const int32_t r = grp_rows[(size_t)(g * gr + w)];
+                if (r < 0) {
+                    ldsb_at(g, w, e) = closes;  // padding rows read offset 0 of the buffer; never stored
+                    continue;
+                }
                 const Entry &en = S.ent[S.row_ptr[r] + e];
                 const Src &sr = unit_srcs[si0 + (size_t)so[(size_t)w]];
                 const uint32_t base = (uint32_t)(slot_lds[(size_t)so[(size_t)w]] + (en.off - sr.lo));
-                const uint32_t closes = S.ent[e].rowc & ~kRowMask;  // identical for every row
-                ldsb[(size_t)((g * kGroupRows + w) * ne + e)] = base | closes;
+                ldsb_at(g, w, e) = base | closes;
             }
             si0 += (size_t)ns;
         }
@@ -225,17 +234,31 @@ bool build_group_lds(const PlanImpl &p, Stage &S, bool allow_fast)
         batch_ptr.push_back((int32_t)(batches.size() / 4));
     }
     if (max_elems > budget || max_elems >= (1 << 24)) return false;
+    // Copy descriptors of the staged windows, in the batches' slot order: (source row, element
+    // offset of the window's 16-byte aligned footprint, LDS byte offset of the footprint,
+    // elements from the footprint start to the window end without the tile, i.e. head + span).
+    std::vector<int32_t> instrs;
+    instrs.reserve(slots.size());
+    for (size_t si = 0; si < slots.size(); si += 4) {
+        const int32_t srow = slots[si], lo = slots[si + 1], span = slots[si + 2], lofs = slots[si + 3];
+        if (lo < 0) return false;
+        const int32_t head = lo % epd;
+        instrs.insert(instrs.end(), {srow, lo - head, (lofs - head) * es, head + span});
+    }
     S.kernel = kKernelGroupLds;
     S.ngroups = ng;
     S.n_entries = ne;
     S.group_f1 = f1;
     S.group_tile = tile;
+    S.group_rpw = rpw;
     S.lds_buf_elems = (int32_t)(round_up(max_elems * es, 16) / es);
-    S.lds_bytes = kGroupBuffers * S.lds_buf_elems * es;  // batches b+1, b+2 land while b is read
+    // general kernel: batches b+1, b+2 land while b is read; specialised kernel: b+1
+    S.lds_bytes = (f1 ? kFastBuffers : kGroupBuffers) * S.lds_buf_elems * es;
     S.grp_rows = std::move(grp_rows);
     S.batch_ptr = std::move(batch_ptr);
     S.batches = std::move(batches);
     S.slots = std::move(slots);
+    S.instrs = std::move(instrs);
     S.ldsb = std::move(ldsb);
     return true;
 }
@@ -566,7 +589,7 @@ snd_status build_plan(const snd_plan_desc &d, PlanImpl &p, std::string &err)
         S.off_grp_rows = reserve((int64_t)S.grp_rows.size() * 4);
         S.off_batch_ptr = reserve((int64_t)S.batch_ptr.size() * 4);
         S.off_batches = reserve((int64_t)S.batches.size() * 4);
-        S.off_slots = reserve((int64_t)S.slots.size() * 4);
+        S.off_instrs = reserve((int64_t)S.instrs.size() * 4);
         S.off_ldsb = reserve((int64_t)S.ldsb.size() * 4);
         S.off_nodes = reserve((int64_t)S.nodes.size() * 4);
         S.off_tiles = reserve((int64_t)S.tiles.size() * 4);
@@ -583,7 +606,7 @@ snd_status build_plan(const snd_plan_desc &d, PlanImpl &p, std::string &err)
         put(S.off_grp_rows, S.grp_rows.data(), S.grp_rows.size() * 4);
         put(S.off_batch_ptr, S.batch_ptr.data(), S.batch_ptr.size() * 4);
         put(S.off_batches, S.batches.data(), S.batches.size() * 4);
-        put(S.off_slots, S.slots.data(), S.slots.size() * 4);
+        put(S.off_instrs, S.instrs.data(), S.instrs.size() * 4);
         put(S.off_ldsb, S.ldsb.data(), S.ldsb.size() * 4);
         put(S.off_nodes, S.nodes.data(), S.nodes.size() * 4);
         put(S.off_tiles, S.tiles.data(), S.tiles.size() * 4);

@@ -53,12 +53,17 @@ struct Stage {
     int32_t lds_buf_elems = 0;      // elements per LDS buffer (group kernel)
     int32_t group_f1 = 0;           // inputs per level-1 node when regular (specialised kernel), else 0
     int32_t group_tile = 0;         // time samples per workgroup
-    std::vector<int32_t> grp_rows;  // [ngroups * kGroupRows], -1 = padding
+    int32_t group_rpw = 1;          // rows per wave (kFastRows for the specialised kernel)
+    std::vector<int32_t> grp_rows;  // [ngroups * kGroupRows * rows per wave], -1 = padding
     std::vector<int32_t> batch_ptr; // [ngroups + 1] into batches
-    std::vector<int32_t> batches;   // 4 ints per batch: entry begin, entry end, slot begin, slot end
-    std::vector<int32_t> slots;     // 4 ints per slot: source row, start offset, span, LDS element offset
-    std::vector<uint32_t> ldsb;     // [ngroups][n_entries][kGroupRows]: LDS base | closes << 24
-    int64_t off_grp_rows = 0, off_batch_ptr = 0, off_batches = 0, off_slots = 0, off_ldsb = 0;
+    std::vector<int32_t> batches;   // 4 ints per batch: entry begin, entry end, window begin, window end
+    std::vector<int32_t> slots;     // 4 ints per staged window: source row, start offset, span, LDS element
+                                    // offset (host only: plan statistics)
+    std::vector<int32_t> instrs;    // 4 ints per staged window, as copied: source row, element offset of
+                                    // its 16-byte aligned footprint, LDS byte offset of the footprint,
+                                    // head + span (elements from the footprint start, tile excluded)
+    std::vector<uint32_t> ldsb;     // [ngroups][kGroupRows][n_entries][rows per wave]: LDS base | closes << 24
+    int64_t off_grp_rows = 0, off_batch_ptr = 0, off_batches = 0, off_instrs = 0, off_ldsb = 0;
 
     // kKernelAnchored: one workgroup per (node, window of kAnchorTile reference samples).
     std::vector<int32_t> nodes;     // 6 ints per node: row begin, row end, channel begin, channel end, rho max,
@@ -76,9 +81,14 @@ constexpr int kGroupRows = 16;       // rows (waves) per LDS-group workgroup
 constexpr int kGroupTile = 256;      // time samples per LDS-group workgroup
 constexpr int kGroupLdsBytes = 20480;  // per LDS buffer
 constexpr int kGroupBuffers = 3;       // batches b, b+1, b+2 in LDS at once
-// Specialised group kernel: regular level-1 nodes of f1 inputs, compile-time depth.
-constexpr int kGroupTileFast = 512;
-constexpr int kGroupFastLdsBytes = 49152;
+// Specialised group kernel: regular level-1 nodes of f1 inputs, compile-time depth; each wave
+// computes kFastRows DM rows of 64 * kFastV samples, so a workgroup covers kGroupRows *
+// kFastRows rows (more rows share each staged window) and a tile of kGroupTileFast samples.
+constexpr int kFastRows = 2;
+constexpr int kFastV = 4;
+constexpr int kGroupTileFast = 64 * kFastV;
+constexpr int kFastBuffers = 2;           // batch b + 1 lands while b is read
+constexpr int kGroupFastLdsBytes = 73728; // per buffer
 inline bool group_fast_types(int mode, int src_dt, int dst_dt)
 {
     if (mode == SND_MODE_BINARY) return src_dt == SND_DT_U8 && dst_dt == SND_DT_U8;
@@ -91,7 +101,7 @@ inline bool group_fast_supported(int f1, int depth)
            (f1 == 8 && depth >= 1 && depth <= 4);
 }
 constexpr int kGroupMaxSpan = 256;   // offset spread of one staged window (window <= span + tile)
-constexpr int kGroupSlotsPerWave = 4;  // staged windows per wave per batch
+constexpr int kGroupSlotsPerWave = 8;  // staged windows per wave per batch
 constexpr int kAnchorTile = 512;     // reference samples per anchored workgroup
 constexpr int kAnchorLdsBytes = 65536;
 
@@ -188,7 +198,7 @@ struct GroupArgs {
     const int32_t *grp_rows;
     const int32_t *batch_ptr;
     const int32_t *batches;  // 4 ints per batch
-    const int32_t *slots;    // 4 ints per slot
+    const int32_t *instrs;   // 4 ints per staged window (copy descriptor)
     const uint32_t *ldsb;
     int32_t ngroups;
     int32_t n_entries;
@@ -247,6 +257,7 @@ struct Prepared {
     int64_t nblocks;
     int64_t n_run;    // LDS row groups: output samples of the run
     int64_t max_len;  // generic: longest row of the run
+    bool bad_pitch;   // LDS row groups: source pitch the kernel cannot address
     StageArgs st;
     GroupArgs gr;
     AnchorArgs an;
