@@ -34,8 +34,9 @@ __global__ __launch_bounds__(1024) void k_group_fast(GroupArgs s0, Multi m)
 #pragma unroll
     for (int q = 0; q < R; ++q)
         row[q] = __builtin_amdgcn_readfirstlane(as_const(s.grp_rows)[(g * kGroupRows + wave) * R + q]);
-    // entry e of row q of this wave: lb[e * R + q]
+    // LDS byte offset of entry e of row q of this wave: lb[e * R + q]
     const_ptr<uint32_t> lb = as_const(s.ldsb) + (int64_t)(g * kGroupRows + wave) * s.n_entries * R;
+    const_ptr<int32_t> closes = as_const(s.node_closes);
     const unsigned char *srcb = static_cast<const unsigned char *>(s.src);
     const_ptr<int32_t> batches = as_const(s.batches);
     const_ptr<int32_t> instrs = as_const(s.instrs);
@@ -65,7 +66,7 @@ __global__ __launch_bounds__(1024) void k_group_fast(GroupArgs s0, Multi m)
             issue_batch<TI>(batches, instrs, b + 1, wave, lane, srcb, pitch_bytes, t0, vt, lds + (buf ^ 1) * s.buf_elems);
         if (row[0] >= 0) {
             const int ex = batches[4 * b], ey = batches[4 * b + 1];
-            const TI *base = lds + buf * s.buf_elems + lane;
+            const unsigned char *base = reinterpret_cast<const unsigned char *>(lds + buf * s.buf_elems + lane);
             for (int c0 = ex; c0 < ey; c0 += F1) {  // one level-1 node per step
                 uint32_t x[F1][R];
 #pragma unroll
@@ -80,7 +81,7 @@ __global__ __launch_bounds__(1024) void k_group_fast(GroupArgs s0, Multi m)
                     for (int u = 0; u < SC; ++u)
 #pragma unroll
                         for (int q = 0; q < R; ++q) {
-                            const TI *p = base + (x[u0 + u][q] & kRowMask);
+                            const TI *p = reinterpret_cast<const TI *>(base + x[u0 + u][q]);
 #pragma unroll
                             for (int v = 0; v < V; ++v) {
                                 A y = (A)Load<TI>::get(p + 64 * v);
@@ -106,7 +107,7 @@ __global__ __launch_bounds__(1024) void k_group_fast(GroupArgs s0, Multi m)
                         if constexpr (D == 1) out[q][v] = y;
                         else stk[0][q][v] += y;
                     }
-                const int c = (int)(x[F1 - 1][0] >> 24);  // levels completed by this node's last input
+                const int c = closes[c0 / F1];  // levels completed by this node's last input
 #pragma unroll
                 for (int j = 2; j <= D; ++j) {
                     if (j <= c) {

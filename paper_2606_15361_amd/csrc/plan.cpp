@@ -259,6 +259,13 @@ bool build_group_lds(const PlanImpl &p, Stage &S, bool allow_fast)
     S.batches = std::move(batches);
     S.slots = std::move(slots);
     S.instrs = std::move(instrs);
+    if (f1) {
+        // specialised kernel: LDS byte offsets without the closing counts, which are the same for
+        // every row and kept once per level-1 node
+        for (uint32_t &w : ldsb) w = (w & kRowMask) * (uint32_t)es;
+        S.node_closes.resize((size_t)(ne / f1));
+        for (int32_t k = 0; k < ne / f1; ++k) S.node_closes[(size_t)k] = (int32_t)(S.ent[k * f1 + f1 - 1].rowc >> 24);
+    }
     S.ldsb = std::move(ldsb);
     return true;
 }
@@ -591,6 +598,7 @@ snd_status build_plan(const snd_plan_desc &d, PlanImpl &p, std::string &err)
         S.off_batches = reserve((int64_t)S.batches.size() * 4);
         S.off_instrs = reserve((int64_t)S.instrs.size() * 4);
         S.off_ldsb = reserve((int64_t)S.ldsb.size() * 4);
+        S.off_node_closes = reserve((int64_t)S.node_closes.size() * 4);
         S.off_nodes = reserve((int64_t)S.nodes.size() * 4);
         S.off_tiles = reserve((int64_t)S.tiles.size() * 4);
         S.off_row_lo = reserve((int64_t)S.row_lo.size() * 4);
@@ -608,6 +616,7 @@ snd_status build_plan(const snd_plan_desc &d, PlanImpl &p, std::string &err)
         put(S.off_batches, S.batches.data(), S.batches.size() * 4);
         put(S.off_instrs, S.instrs.data(), S.instrs.size() * 4);
         put(S.off_ldsb, S.ldsb.data(), S.ldsb.size() * 4);
+        put(S.off_node_closes, S.node_closes.data(), S.node_closes.size() * 4);
         put(S.off_nodes, S.nodes.data(), S.nodes.size() * 4);
         put(S.off_tiles, S.tiles.data(), S.tiles.size() * 4);
         put(S.off_row_lo, S.row_lo.data(), S.row_lo.size() * 4);

@@ -62,8 +62,11 @@ struct Stage {
     std::vector<int32_t> instrs;    // 4 ints per staged window, as copied: source row, element offset of
                                     // its 16-byte aligned footprint, LDS byte offset of the footprint,
                                     // head + span (elements from the footprint start, tile excluded)
-    std::vector<uint32_t> ldsb;     // [ngroups][kGroupRows][n_entries][rows per wave]: LDS base | closes << 24
+    std::vector<uint32_t> ldsb;     // [ngroups][kGroupRows][n_entries][rows per wave]: LDS element offset |
+                                    // closes << 24 (general kernel) or LDS byte offset (specialised kernel)
+    std::vector<int32_t> node_closes;  // specialised kernel: levels completed by each level-1 node
     int64_t off_grp_rows = 0, off_batch_ptr = 0, off_batches = 0, off_instrs = 0, off_ldsb = 0;
+    int64_t off_node_closes = 0;
 
     // kKernelAnchored: one workgroup per (node, window of kAnchorTile reference samples).
     std::vector<int32_t> nodes;     // 6 ints per node: row begin, row end, channel begin, channel end, rho max,
@@ -200,6 +203,7 @@ struct GroupArgs {
     const int32_t *batches;  // 4 ints per batch
     const int32_t *instrs;   // 4 ints per staged window (copy descriptor)
     const uint32_t *ldsb;
+    const int32_t *node_closes;  // specialised kernel only
     int32_t ngroups;
     int32_t n_entries;
     int32_t buf_elems;
