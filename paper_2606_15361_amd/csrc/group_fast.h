@@ -20,7 +20,8 @@ __global__ __launch_bounds__(1024) void k_group_fast(GroupArgs s0, Multi m)
     constexpr int T = kGroupTileFast;
     constexpr int V = kFastV;            // samples per lane
     constexpr int R = kFastRows;         // DM rows per wave
-    constexpr int SC = F1 < 4 ? F1 : 4;  // inputs whose reads are issued together
+    // inputs whose reads are issued together (fewer when the row registers are many)
+    constexpr int SC = V * R > 8 ? (F1 < 2 ? F1 : 2) : (F1 < 4 ? F1 : 4);
     constexpr int NS = D > 1 ? D - 1 : 1;
     extern __shared__ __align__(16) unsigned char smem[];
     TI *lds = reinterpret_cast<TI *>(smem);

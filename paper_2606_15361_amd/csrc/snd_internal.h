@@ -88,7 +88,7 @@ constexpr int kGroupBuffers = 3;       // batches b, b+1, b+2 in LDS at once
 // computes kFastRows DM rows of 64 * kFastV samples, so a workgroup covers kGroupRows *
 // kFastRows rows (more rows share each staged window) and a tile of kGroupTileFast samples.
 constexpr int kFastRows = 2;
-constexpr int kFastV = 4;
+constexpr int kFastV = 8;
 constexpr int kGroupTileFast = 64 * kFastV;
 constexpr int kFastBuffers = 2;           // batch b + 1 lands while b is read
 constexpr int kGroupFastLdsBytes = 73728; // per buffer
