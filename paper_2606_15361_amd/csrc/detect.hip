@@ -4,12 +4,15 @@
 // k_rowstats: mean and population standard deviation of each DM row over its valid samples.
 //   Integer planes use exact 64-bit sums S1, S2 and sigma = sqrt(n*S2 - S1*S1)/n in one fixed
 //   FP64 expression; float planes use a two-pass FP64 reduction.  A floor sigma_min applies.
-// k_snr: one workgroup per (row, 1024-sample tile).  The tile plus the widest boxcar is
+// k_snr: one workgroup per (row, 4096-sample tile).  The tile plus the widest boxcar is
 //   staged in LDS as an inclusive prefix sum (int32 for integer planes: exact; FP64 for float
 //   planes), every sample then evaluates all widths with two LDS reads each:
 //   SNR(t, W) = (S_W(t) - mu W) / (sigma sqrt W), maximum over widths (first width on ties).
-//   Cells whose S/N reaches the threshold are appended to a global pixel list, or the full
-//   S/N plane and width index are written.
+//   Either the full S/N plane and width index are written, or the cells whose S/N reaches the
+//   threshold are appended to a global pixel list, each workgroup's cells as one segment in
+//   increasing t.  For the list, a bound from multiplying by the reciprocal of the denominator
+//   skips the cells far below the threshold; every cell that can reach it takes the exact
+//   quotient.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -19,7 +22,7 @@
 namespace snd {
 namespace {
 
-constexpr int kSnrTile = 1024;
+constexpr int kSnrTile = 4096;
 constexpr int kThreads = 256;
 
 template <typename T> struct IsInt { static constexpr bool value = true; };
@@ -91,17 +94,24 @@ __global__ __launch_bounds__(kThreads) void k_rowstats(const T *plane, int64_t p
     }
 }
 
-template <typename T>
+// NW > 0: exactly NW widths, known at compile time (per-row constants stay in registers);
+// NW == 0: any number of widths.
+template <typename T, int NW>
 __global__ __launch_bounds__(kThreads) void k_snr(const T *plane, int64_t pitch, int64_t n, const double *stats,
                                                   SnrArgs a)
 {
     using P = typename PrefixType<T>::type;
+    constexpr int kMaxPer = (kSnrTile + kMaxWidth + kThreads - 1) / kThreads;  // elements per thread
+    constexpr int kSlabs = kSnrTile / kThreads;                                // samples per thread
     __shared__ P pre[kSnrTile + kMaxWidth + 1];
-    __shared__ P part[kThreads];
+    __shared__ P wtot[kThreads / 64];
+    __shared__ int slab_off[kSlabs][kThreads / 64];
+    __shared__ unsigned int base_s;
+    __shared__ double muw[kMaxWidths], den[kMaxWidths], rden[kMaxWidths];  // per-row constants
     const int k = blockIdx.y;
     const int64_t t0 = (int64_t)blockIdx.x * kSnrTile;
-    const T *row = plane + (int64_t)k * pitch;
-    const int tid = threadIdx.x;
+    const T *row = plane + (int64_t)k * pitch + t0;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int wmax = a.w[a.nw - 1];
     // elements t0 .. t0 + L - 1 are needed (and exist): L = min(tile + wmax - 1, n - t0)
     int64_t L64 = (int64_t)kSnrTile + wmax - 1;
@@ -109,64 +119,157 @@ __global__ __launch_bounds__(kThreads) void k_snr(const T *plane, int64_t pitch,
     const int L = (int)L64;
     const int per = (L + kThreads - 1) / kThreads;
     const int beg = tid * per;
+    // prefix sums: per-thread chunk totals, wave scan, wave totals through LDS
+    P v[kMaxPer];
     P run = 0;
-    for (int i = 0; i < per; ++i) {
+#pragma unroll
+    for (int i = 0; i < kMaxPer; ++i) {
         const int j = beg + i;
-        if (j < L) run += (P)row[t0 + j];
+        v[i] = (i < per && j < L) ? (P)row[j] : (P)0;
+        run += v[i];
     }
-    part[tid] = run;
+    P inc = run;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const P u = __shfl_up(inc, d, 64);
+        if (lane >= d) inc += u;
+    }
+    if (lane == 63) wtot[wv] = inc;
     __syncthreads();
-    for (int s = 1; s < kThreads; s <<= 1) {  // inclusive scan of the per-thread totals
-        P v = tid >= s ? part[tid - s] : (P)0;
-        __syncthreads();
-        part[tid] += v;
-        __syncthreads();
-    }
-    P acc = tid > 0 ? part[tid - 1] : (P)0;
+    P acc = inc - run;
+    for (int w = 0; w < wv; ++w) acc += wtot[w];
     if (tid == 0) pre[0] = 0;
-    for (int i = 0; i < per; ++i) {
+#pragma unroll
+    for (int i = 0; i < kMaxPer; ++i) {
         const int j = beg + i;
-        if (j < L) {
-            acc += (P)row[t0 + j];
+        if (i < per && j < L) {
+            acc += v[i];
             pre[j + 1] = acc;
         }
     }
-    __syncthreads();
     const double mu = stats[2 * k], sg = stats[2 * k + 1];
-    for (int i = tid; i < kSnrTile; i += kThreads) {
-        const int64_t t = t0 + i;
-        if (t >= n) break;
-        double best = 0.0;
-        int bi = -1;
+    // per-row constants of S/N(t, W) = (S_W(t) - mu W) / (sigma sqrt W)
+    if (tid < a.nw) {
+        muw[tid] = __dmul_rn(mu, (double)a.w[tid]);
+        den[tid] = __dmul_rn(sg, a.sqrtw[tid]);
+        rden[tid] = sg > 0.0 ? 1.0 / den[tid] : 0.0;
+    }
+    __syncthreads();
+    // the exact maximum over widths of sample i (first width on ties)
+    auto exact = [&](int i, int64_t t, double &best, int &bi) {
+        best = 0.0;
+        bi = -1;
         for (int w = 0; w < a.nw; ++w) {
             const int W = a.w[w];
             if (t + W > n) break;
             double val = 0.0;
             if (sg > 0.0) {
                 const double s = (double)(pre[i + W] - pre[i]);
-                const double num = __dsub_rn(s, __dmul_rn(mu, (double)W));
-                const double den = __dmul_rn(sg, a.sqrtw[w]);
-                val = num / den;
+                val = __dsub_rn(s, muw[w]) / den[w];
             }
             if (bi < 0 || val > best) {
                 best = val;
                 bi = w;
             }
         }
-        if (a.snr) {
+    };
+    if (a.snr) {  // the whole S/N plane
+        for (int i = tid; i < kSnrTile; i += kThreads) {
+            const int64_t t = t0 + i;
+            if (t >= n) break;
+            double best;
+            int bi;
+            exact(i, t, best, bi);
             a.snr[(int64_t)k * a.snr_pitch + t] = (float)best;
             a.widx[(int64_t)k * a.widx_pitch + t] = (int8_t)bi;
-        } else if (bi >= 0 && best >= a.threshold) {
-            const unsigned int slot = atomicAdd(a.counter, 1u);
-            if ((int64_t)slot < a.max_pixels) {
-                Pixel px;
-                px.k = k;
-                px.t = (int32_t)t;
-                px.snr = best;
-                px.widx = bi;
-                px.pad = 0;
-                a.pixels[slot] = px;
+        }
+        return;
+    }
+    // compaction: a cheap bound (multiplication by the reciprocal, within a few ulp of the
+    // quotient) rejects the cells far below the threshold; the rest take the exact quotient
+    const double lo = a.threshold * (1.0 - 1e-9);
+    constexpr int RW = NW > 0 ? NW : 1;
+    double rmuw[RW], rrden[RW];
+    int rw[RW];
+    if constexpr (NW > 0) {
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+            rmuw[w] = muw[w];
+            rrden[w] = rden[w];
+            rw[w] = a.w[w];
+        }
+    }
+    // every width fits every sample of the tile: no end-of-row tests
+    const bool interior = t0 + kSnrTile + wmax - 1 <= n;
+    uint32_t flags = 0;
+    double bs[kSlabs];
+    int bw[kSlabs];
+#pragma unroll
+    for (int j = 0; j < kSlabs; ++j) {
+        bs[j] = 0.0;
+        bw[j] = 0;
+        const int i = tid + kThreads * j;
+        const int64_t t = t0 + i;
+        if (t >= n || !(sg > 0.0)) continue;
+        const P p0 = pre[i];
+        double m = -1.0e300;
+        if (NW > 0 && interior) {
+#pragma unroll
+            for (int w = 0; w < RW; ++w) {
+                const double s = (double)(pre[i + rw[w]] - p0);
+                const double approx = (s - rmuw[w]) * rrden[w];
+                m = approx > m ? approx : m;
             }
+        } else {
+            for (int w = 0; w < a.nw; ++w) {
+                if (t + a.w[w] > n) break;
+                const double s = (double)(pre[i + a.w[w]] - p0);
+                const double approx = (s - muw[w]) * rden[w];
+                m = approx > m ? approx : m;
+            }
+        }
+        if (m < lo) continue;
+        double best;
+        int bi;
+        exact(i, t, best, bi);
+        if (bi >= 0 && best >= a.threshold) {
+            flags |= 1u << j;
+            bs[j] = best;
+            bw[j] = bi;
+        }
+    }
+    // ordered output: the block's cells in increasing t (slab by slab, thread by thread)
+    uint64_t masks[kSlabs];
+#pragma unroll
+    for (int j = 0; j < kSlabs; ++j) {
+        masks[j] = __ballot((flags >> j) & 1u);
+        if (lane == 0) slab_off[j][wv] = __popcll(masks[j]);
+    }
+    __syncthreads();
+    if (tid == 0) {
+        int tot = 0;
+        for (int j = 0; j < kSlabs; ++j)
+            for (int w = 0; w < kThreads / 64; ++w) {
+                const int c = slab_off[j][w];
+                slab_off[j][w] = tot;
+                tot += c;
+            }
+        base_s = tot ? atomicAdd(a.counter, (unsigned int)tot) : 0u;
+    }
+    __syncthreads();
+    const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
+#pragma unroll
+    for (int j = 0; j < kSlabs; ++j) {
+        if (!((flags >> j) & 1u)) continue;
+        const int64_t pos = (int64_t)base_s + slab_off[j][wv] + __popcll(masks[j] & below);
+        if (pos < a.max_pixels) {
+            Pixel px;
+            px.k = k;
+            px.t = (int32_t)(t0 + tid + kThreads * j);
+            px.snr = bs[j];
+            px.widx = bw[j];
+            px.pad = 0;
+            a.pixels[pos] = px;
         }
     }
 }
@@ -181,7 +284,12 @@ int launch_typed(const void *plane, int64_t pitch, int ndm, int64_t n, double si
     if (!a.snr) hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(1), 0, st, a.counter);
     hipLaunchKernelGGL((k_rowstats<T>), dim3((uint32_t)ndm), dim3(kThreads), 0, st, p, pitch, n, sigma_min, stats);
     dim3 grid((uint32_t)((n + kSnrTile - 1) / kSnrTile), (uint32_t)ndm);
-    hipLaunchKernelGGL((k_snr<T>), grid, dim3(kThreads), 0, st, p, pitch, n, stats, a);
+    switch (a.nw) {
+#define SND_NW(N) case N: hipLaunchKernelGGL((k_snr<T, N>), grid, dim3(kThreads), 0, st, p, pitch, n, stats, a); break;
+    SND_NW(1) SND_NW(2) SND_NW(3) SND_NW(4) SND_NW(5) SND_NW(6) SND_NW(7) SND_NW(8)
+#undef SND_NW
+    default: hipLaunchKernelGGL((k_snr<T, 0>), grid, dim3(kThreads), 0, st, p, pitch, n, stats, a); break;
+    }
     return (int)hipGetLastError();
 }
 

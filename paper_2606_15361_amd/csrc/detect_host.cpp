@@ -114,9 +114,23 @@ snd_status candidates_from_pixels(std::vector<snd::Pixel> &px, const snd::PlanIm
 {
     out.clear();
     if (px.empty()) return SND_OK;
-    std::sort(px.begin(), px.end(), [](const snd::Pixel &a, const snd::Pixel &b) {
-        return a.k != b.k ? a.k < b.k : a.t < b.t;
-    });
+    {  // (k, t) order: a counting sort by row, then t within a row (each workgroup's cells arrive
+       // as one segment of one row in increasing t, so rows are short runs of sorted segments)
+        int32_t k0 = px[0].k, k1 = px[0].k;
+        for (const snd::Pixel &q : px) { k0 = std::min(k0, q.k); k1 = std::max(k1, q.k); }
+        std::vector<int64_t> at((size_t)(k1 - k0) + 2, 0);
+        for (const snd::Pixel &q : px) ++at[(size_t)(q.k - k0) + 1];
+        for (size_t i = 1; i < at.size(); ++i) at[i] += at[i - 1];
+        std::vector<snd::Pixel> sorted(px.size());
+        std::vector<int64_t> fill(at.begin(), at.end() - 1);
+        for (const snd::Pixel &q : px) sorted[(size_t)fill[(size_t)(q.k - k0)]++] = q;
+        auto by_t = [](const snd::Pixel &a, const snd::Pixel &b) { return a.t < b.t; };
+        for (size_t r = 0; r + 1 < at.size(); ++r) {
+            auto b = sorted.begin() + at[r], e = sorted.begin() + at[r + 1];
+            if (!std::is_sorted(b, e, by_t)) std::sort(b, e, by_t);
+        }
+        px.swap(sorted);
+    }
     const int64_t r = d->closing_radius;
     const int64_t kmin = px.front().k, kmax = px.back().k;
     // rows are indexed relative to K0 = kmin - 2r so every dilated/eroded row has a slot
