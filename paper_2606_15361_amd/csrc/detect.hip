@@ -3,7 +3,8 @@
 //
 // k_rowstats: mean and population standard deviation of each DM row over its valid samples.
 //   Integer planes use exact 64-bit sums S1, S2 and sigma = sqrt(n*S2 - S1*S1)/n in one fixed
-//   FP64 expression; float planes use a two-pass FP64 reduction.  A floor sigma_min applies.
+//   FP64 expression; float planes use one FP64 pass about the row's first sample.  A floor
+//   sigma_min applies.
 // k_snr: one workgroup per (row, 4096-sample tile).  The tile plus the widest boxcar is
 //   staged in LDS as an inclusive prefix sum (int32 for integer planes: exact; FP64 for float
 //   planes), every sample then evaluates all widths with two LDS reads each:
@@ -63,32 +64,33 @@ __global__ __launch_bounds__(kThreads) void k_rowstats(const T *plane, int64_t p
             stats[2 * k + 1] = sg;
         }
     } else {
-        __shared__ double red[kThreads];
-        double a = 0.0;
-        for (int64_t t = tid; t < n; t += kThreads) a += (double)row[t];
-        red[tid] = a;
-        __syncthreads();
-        for (int s = kThreads / 2; s > 0; s >>= 1) {
-            if (tid < s) red[tid] += red[tid + s];
-            __syncthreads();
-        }
-        const double mu = red[0] / (double)n;
-        __syncthreads();
-        double q = 0.0;
+        // one pass in FP64 about a shift c (the row's first sample), so that a large mean does
+        // not cancel: mu = c + S1 / n, sigma^2 = S2 / n - (S1 / n)^2 with S1, S2 the sums of
+        // (y - c) and (y - c)^2
+        __shared__ double r1[kThreads], r2[kThreads];
+        const double c = (double)row[0];
+        double a = 0.0, b = 0.0;
         for (int64_t t = tid; t < n; t += kThreads) {
-            double d = (double)row[t] - mu;
-            q += d * d;
+            const double d = (double)row[t] - c;
+            a += d;
+            b += d * d;
         }
-        red[tid] = q;
+        r1[tid] = a;
+        r2[tid] = b;
         __syncthreads();
         for (int s = kThreads / 2; s > 0; s >>= 1) {
-            if (tid < s) red[tid] += red[tid + s];
+            if (tid < s) {
+                r1[tid] += r1[tid + s];
+                r2[tid] += r2[tid + s];
+            }
             __syncthreads();
         }
         if (tid == 0) {
-            double sg = sqrt(red[0] / (double)n);
+            const double m1 = r1[0] / (double)n;
+            const double var = r2[0] / (double)n - m1 * m1;
+            double sg = var > 0.0 ? sqrt(var) : 0.0;
             if (sg < sigma_min) sg = sigma_min;
-            stats[2 * k] = mu;
+            stats[2 * k] = c + m1;
             stats[2 * k + 1] = sg;
         }
     }

@@ -109,6 +109,28 @@ struct UF {
     }
 };
 
+// Page-locked host memory for read-backs; null when it cannot be had (pageable copy then).
+// The last buffer is deliberately kept until the process ends: freeing it from a thread-exit
+// destructor could run after the HIP runtime has shut down.
+struct PinnedBuffer {
+    void *p = nullptr;
+    size_t n = 0;
+    void *get(size_t bytes)
+    {
+        if (bytes <= n) return p;
+        const size_t want = std::max(bytes, n * 2);
+        if (p) (void)hipHostFree(p);
+        p = nullptr;
+        n = 0;
+        if (hipHostMalloc(&p, want, hipHostMallocDefault) != hipSuccess) {
+            p = nullptr;
+            return nullptr;
+        }
+        n = want;
+        return p;
+    }
+};
+
 snd_status candidates_from_pixels(std::vector<snd::Pixel> &px, const snd::PlanImpl &P, const snd_detect_desc *d,
                                   std::vector<snd_candidate> &out)
 {
@@ -296,9 +318,15 @@ snd_status snd_detect(snd_plan plan, const void *d_plane, int64_t plane_pitch, c
     }
     std::vector<snd::Pixel> px(count);
     if (count) {
-        he = hipMemcpyAsync(px.data(), a.pixels, sizeof(snd::Pixel) * count, hipMemcpyDeviceToHost, st);
+        // through a pinned staging buffer of this thread (grown on demand, kept until exit):
+        // a pageable read-back of ~10^5 cells costs more than the labelling that follows
+        thread_local PinnedBuffer stage;
+        const size_t nb = sizeof(snd::Pixel) * count;
+        void *h = stage.get(nb);
+        he = hipMemcpyAsync(h ? h : px.data(), a.pixels, nb, hipMemcpyDeviceToHost, st);
         if (he == hipSuccess) he = hipStreamSynchronize(st);
         if (he != hipSuccess) { snd::set_error(std::string("detect readback: ") + hipGetErrorString(he)); return SND_ERR_HIP; }
+        if (h) std::memcpy(px.data(), h, nb);
     }
     std::vector<snd_candidate> cands;
     s = candidates_from_pixels(px, P, desc, cands);

@@ -10,6 +10,29 @@
 
 namespace snd {
 
+// Levels J..D of the open sub-tree after an input that completes c levels: when c >= J the
+// level-J node is complete, its activated sum goes to level J + 1 (or is the root's value)
+// and its accumulator restarts at zero; only then can level J + 1 be complete as well.
+template <int MODE, typename A, int J, int D, int NS, int R, int V>
+__device__ inline void close_levels_from(int c, A (&stk)[NS][R][V], A (&out)[R][V], int src_is_input, int k_leaf,
+                                         int k_int, int cap)
+{
+    if constexpr (J <= D) {
+        if (c >= J) {
+#pragma unroll
+            for (int q = 0; q < R; ++q)
+#pragma unroll
+                for (int v = 0; v < V; ++v) {
+                    const A y = activate<MODE>(stk[J - 2][q][v], J, src_is_input, k_leaf, k_int, cap);
+                    stk[J - 2][q][v] = 0;
+                    if constexpr (J == D) out[q][v] = y;
+                    else stk[J - 1][q][v] += y;
+                }
+            close_levels_from<MODE, A, J + 1, D, NS, R, V>(c, stk, out, src_is_input, k_leaf, k_int, cap);
+        }
+    }
+}
+
 template <int MODE, typename TI, typename TO, int F1, int D>
 __global__ __launch_bounds__(1024) void k_group_fast(GroupArgs s0, Multi m)
 {
@@ -69,6 +92,7 @@ __global__ __launch_bounds__(1024) void k_group_fast(GroupArgs s0, Multi m)
             const int ex = batches[4 * b], ey = batches[4 * b + 1];
             const unsigned char *base = reinterpret_cast<const unsigned char *>(lds + buf * s.buf_elems + lane);
             for (int c0 = ex; c0 < ey; c0 += F1) {  // one level-1 node per step
+                const int c = closes[(uint32_t)c0 / F1];  // levels completed by this node's last input
                 uint32_t x[F1][R];
 #pragma unroll
                 for (int u = 0; u < F1; ++u)
@@ -108,22 +132,8 @@ __global__ __launch_bounds__(1024) void k_group_fast(GroupArgs s0, Multi m)
                         if constexpr (D == 1) out[q][v] = y;
                         else stk[0][q][v] += y;
                     }
-                const int c = closes[c0 / F1];  // levels completed by this node's last input
-#pragma unroll
-                for (int j = 2; j <= D; ++j) {
-                    if (j <= c) {
-#pragma unroll
-                        for (int q = 0; q < R; ++q)
-#pragma unroll
-                            for (int v = 0; v < V; ++v) {
-                                const A y =
-                                    activate<MODE>(stk[j - 2][q][v], j, s.src_is_input, s.k_leaf, s.k_int, s.cap);
-                                stk[j - 2][q][v] = 0;
-                                if (j == D) out[q][v] = y;
-                                else stk[(j - 1) < NS ? (j - 1) : 0][q][v] += y;  // index is j - 1 here
-                            }
-                    }
-                }
+                // closing level j implies closing every level below it: nested tests
+                close_levels_from<MODE, A, 2, D, NS, R, V>(c, stk, out, s.src_is_input, s.k_leaf, s.k_int, s.cap);
             }
         }
         buf ^= 1;
