@@ -91,7 +91,7 @@ constexpr int kFastRows = 2;
 constexpr int kFastV = 8;
 constexpr int kGroupTileFast = 64 * kFastV;
 constexpr int kFastBuffers = 2;           // batch b + 1 lands while b is read
-constexpr int kGroupFastLdsBytes = 73728; // per buffer
+constexpr int kGroupFastLdsBytes = 81920; // per buffer (two fill the 160 KB of LDS)
 inline bool group_fast_types(int mode, int src_dt, int dst_dt)
 {
     if (mode == SND_MODE_BINARY) return src_dt == SND_DT_U8 && dst_dt == SND_DT_U8;
