@@ -54,7 +54,9 @@ typedef enum {
     SND_DT_U16 = 2,
     SND_DT_F32 = 3,
     SND_DT_BF16 = 4,
-    SND_DT_F16 = 5
+    SND_DT_F16 = 5,
+    SND_DT_BITS = 6   /* binary tree rows, one bit per sample: bit i of 32-bit word w holds
+                         sample 32 w + i of the row (node storage of binary mode only) */
 } snd_dtype;
 
 /*
@@ -86,8 +88,11 @@ typedef struct {
     int32_t cap;             /* graded clip N, 1..65535 (ignored otherwise) */
     int32_t in_dtype;        /* input samples: U8 for binary/graded (binary: non-zero = spike);
                                 F32, BF16 or F16 for float */
-    int32_t node_dtype;      /* storage of materialised tree rows: U8 for binary; U8 (cap <= 255)
-                                or U16 for graded; F32, BF16 or F16 for float (FP32 accumulate) */
+    int32_t node_dtype;      /* storage of materialised tree rows: BITS or U8 for binary; U8
+                                (cap <= 255) or U16 for graded; F32, BF16 or F16 for float (FP32
+                                accumulate).  BITS needs the default schedule (leaf level
+                                materialised, no generic kernels) and a tree whose level-1 nodes
+                                all have the same fan-in of 2, 4 or 8; UNSUPPORTED otherwise */
     int32_t root_norm;       /* float: divide the output by sqrt(nchan) (Methods, Mode C) */
     int64_t nsamp;           /* input samples per channel per execute (ignored when chunk > 0) */
     uint32_t stage_levels;   /* bit l (l below the root level) set: tree level l is written to
@@ -127,7 +132,7 @@ typedef struct {
     double build_seconds;                   /* host time of snd_plan_create */
     int32_t stage_kernel[SND_MAX_LEVELS];   /* kernel per stage: 0 generic, 1 LDS row groups,
                                                2 input-anchored, 3 LDS row groups specialised for
-                                               regular level-1 nodes */
+                                               regular level-1 nodes, 4 the same on bit rows */
     int64_t stage_staged[SND_MAX_LEVELS];   /* LDS row groups: source elements staged per time
                                                tile summed over groups (0 otherwise) */
     int64_t stage_batches[SND_MAX_LEVELS];  /* LDS row groups: batches summed over groups */

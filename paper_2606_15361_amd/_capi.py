@@ -15,7 +15,7 @@ OK, ERR_INVALID, ERR_UNSUPPORTED, ERR_NOMEM, ERR_HIP, ERR_CAPACITY, ERR_STATE, E
 STATUS_NAMES = {0: "SND_OK", -1: "SND_ERR_INVALID", -2: "SND_ERR_UNSUPPORTED", -3: "SND_ERR_NOMEM",
                 -4: "SND_ERR_HIP", -5: "SND_ERR_CAPACITY", -6: "SND_ERR_STATE", -7: "SND_ERR_GAP"}
 MODE_BINARY, MODE_GRADED, MODE_FLOAT = 0, 1, 2
-DT_U8, DT_U16, DT_F32, DT_BF16, DT_F16 = 1, 2, 3, 4, 5
+DT_U8, DT_U16, DT_F32, DT_BF16, DT_F16, DT_BITS = 1, 2, 3, 4, 5, 6
 
 
 class SndError(RuntimeError):

@@ -1,0 +1,226 @@
+// Final stage of the binary tree on bit rows (Methods, "Tree activation modes", Mode A).
+//
+// The leaf stage stores every leaf neuron's output as one bit per sample.  Here a lane holds 32
+// consecutive samples of a DM row in one 32-bit word, so every tree operation works on 32
+// samples at once with bitwise logic:
+//   - an input is the 32 bits of a staged leaf window at the row's offset, read as two aligned
+//     words from LDS and funnel-shifted;
+//   - a node's input count is kept bit-sliced (plane i holds bit i of every sample's count) and
+//     incremented with a ripple of AND / XOR;
+//   - the quorum count >= K is a bit-sliced comparison with the constant K;
+//   - the root's bits are expanded to the 0/1 bytes of the output plane.
+// Staging, batches, row groups and the closing pattern are those of the specialised row-group
+// kernel (two DM rows per wave), with tiles of 2048 samples.  The counts and quorums are exact
+// integers, so the output equals the byte-row kernels and the oracle bit for bit.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "group_common.h"
+
+namespace snd {
+namespace {
+
+constexpr int kPlanes = 4;  // counts up to 15 (fan-in of any node <= 15 for the supported trees)
+
+// count += x (bit-sliced, one increment per set bit of x)
+__device__ inline void bs_add(uint32_t (&c)[kPlanes], uint32_t x)
+{
+#pragma unroll
+    for (int i = 0; i < kPlanes; ++i) {
+        const uint32_t t = c[i] & x;
+        c[i] ^= x;
+        x = t;
+    }
+}
+
+// bits where count >= k (k uniform, >= 1)
+__device__ inline uint32_t bs_ge(const uint32_t (&c)[kPlanes], int k)
+{
+    if (k >= (1 << kPlanes)) return 0u;
+    uint32_t gt = 0u, eq = ~0u;
+#pragma unroll
+    for (int i = kPlanes - 1; i >= 0; --i) {
+        if ((k >> i) & 1) {
+            eq &= c[i];
+        } else {
+            gt |= eq & c[i];
+            eq &= ~c[i];
+        }
+    }
+    return gt | eq;
+}
+
+// Copy this wave's windows of batch b into LDS: as issue_batch, with elements of one bit (the
+// element offset and the window length are in bits, the copy units are 128 bits).
+__device__ inline void issue_bits(const_ptr<int32_t> batches, const_ptr<int32_t> instrs, int b, int wave, int lane,
+                                  const unsigned char *srcb, int64_t pitch_bytes, int t0, int vt, unsigned char *dst)
+{
+    const int bz = batches[4 * b + 2], bw = batches[4 * b + 3];
+    for (int si = bz + wave; si < bw; si += kGroupRows) {
+        const int srow = instrs[4 * si], eoff = instrs[4 * si + 1], lbyte = instrs[4 * si + 2];
+        const int hs = instrs[4 * si + 3];
+        // eoff and t0 are multiples of 128 bits: the footprint starts on a 16-byte boundary
+        const uint4 *gp = reinterpret_cast<const uint4 *>(srcb + (uint64_t)(uint32_t)srow * (uint32_t)pitch_bytes +
+                                                          ((uint64_t)(uint32_t)(eoff + t0) >> 3)) + lane;
+        unsigned char *lp = dst + lbyte;
+        const int nu = (hs + vt + 127) >> 7;  // 128-bit units of the window for this tile
+        int u0 = 0;
+        for (; u0 + 64 <= nu; u0 += 64)
+            __builtin_amdgcn_global_load_lds(gp + u0, (__attribute__((address_space(3))) void *)(lp + 16 * u0), 16, 0, 0);
+        if (u0 < nu && u0 + lane < nu)
+            __builtin_amdgcn_global_load_lds(gp + u0, (__attribute__((address_space(3))) void *)(lp + 16 * u0), 16, 0, 0);
+    }
+}
+
+// Levels J..D after an input that completes c levels (see the byte-row kernel): the level-J
+// count's quorum goes to level J + 1 (or is the root) and the count restarts at zero.
+template <int J, int D, int NS, int R>
+__device__ inline void close_bits_from(int c, uint32_t (&cnt)[NS][R][kPlanes], uint32_t (&out)[R], int k)
+{
+    if constexpr (J <= D) {
+        if (c >= J) {
+#pragma unroll
+            for (int q = 0; q < R; ++q) {
+                const uint32_t y = bs_ge(cnt[J - 2][q], k);
+#pragma unroll
+                for (int i = 0; i < kPlanes; ++i) cnt[J - 2][q][i] = 0u;
+                if constexpr (J == D) out[q] = y;
+                else bs_add(cnt[J - 1][q], y);
+            }
+            close_bits_from<J + 1, D, NS, R>(c, cnt, out, k);
+        }
+    }
+}
+
+template <int F1, int D>
+__global__ __launch_bounds__(1024) void k_group_bits(GroupArgs s0, Multi m)
+{
+    GroupArgs s;
+    uint32_t bid, nblk;
+    select_record(s0, m, s, bid, nblk);
+    constexpr int T = kGroupTileBits;  // 32 samples per lane
+    constexpr int R = kFastRows;       // DM rows per wave
+    constexpr int NS = D > 1 ? D - 1 : 1;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const uint32_t L = xcd_remap(bid, nblk);
+    const int g = (int)(L % (uint32_t)s.ngroups);
+    const int t0 = (int)(L / (uint32_t)s.ngroups) * T;
+    const int vt = s.n_out - t0 < T ? s.n_out - t0 : T;
+    int row[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q)
+        row[q] = __builtin_amdgcn_readfirstlane(as_const(s.grp_rows)[(g * kGroupRows + wave) * R + q]);
+    // entry e of row q: byte offset of the word holding its first sample | bit offset << 27
+    const_ptr<uint32_t> lb = as_const(s.ldsb) + (int64_t)(g * kGroupRows + wave) * s.n_entries * R;
+    const_ptr<int32_t> closes = as_const(s.node_closes);
+    const unsigned char *srcb = static_cast<const unsigned char *>(s.src);
+    const_ptr<int32_t> batches = as_const(s.batches);
+    const_ptr<int32_t> instrs = as_const(s.instrs);
+    const int64_t pitch_bytes = s.src_pitch / 8;  // row pitch in bits (a multiple of 128)
+    const int buf_bytes = s.buf_elems / 8;
+    const int k1 = s.src_is_input ? s.k_leaf : s.k_int;  // quorum of the level-1 nodes
+
+    uint32_t cnt[NS][R][kPlanes];  // cnt[j - 2]: input count of the open level-j node, j = 2 .. D
+    uint32_t out[R];
+#pragma unroll
+    for (int j = 0; j < NS; ++j)
+#pragma unroll
+        for (int q = 0; q < R; ++q)
+#pragma unroll
+            for (int i = 0; i < kPlanes; ++i) cnt[j][q][i] = 0u;
+#pragma unroll
+    for (int q = 0; q < R; ++q) out[q] = 0u;
+
+    const int b0 = as_const(s.batch_ptr)[g], b1 = as_const(s.batch_ptr)[g + 1];
+    if (b0 < b1) issue_bits(batches, instrs, b0, wave, lane, srcb, pitch_bytes, t0, vt, smem);
+    int buf = 0;
+    for (int b = b0; b < b1; ++b) {
+        __builtin_amdgcn_s_waitcnt(0x0f70);  // vmcnt(0): this wave's copies of batch b have landed
+        stage_barrier();                     // everyone's have; everyone is done reading batch b - 1
+        if (b + 1 < b1) issue_bits(batches, instrs, b + 1, wave, lane, srcb, pitch_bytes, t0, vt, smem + (buf ^ 1) * buf_bytes);
+        if (row[0] >= 0) {
+            const int ex = batches[4 * b], ey = batches[4 * b + 1];
+            const unsigned char *base = smem + buf * buf_bytes + 4 * lane;
+            for (int c0 = ex; c0 < ey; c0 += F1) {  // one level-1 node per step
+                const int c = closes[(uint32_t)c0 / F1];
+                uint32_t x[F1][R];
+#pragma unroll
+                for (int u = 0; u < F1; ++u)
+#pragma unroll
+                    for (int q = 0; q < R; ++q) x[u][q] = lb[(c0 + u) * R + q];
+                uint32_t a[R][kPlanes];
+#pragma unroll
+                for (int q = 0; q < R; ++q)
+#pragma unroll
+                    for (int i = 0; i < kPlanes; ++i) a[q][i] = 0u;
+#pragma unroll
+                for (int u = 0; u < F1; ++u)
+#pragma unroll
+                    for (int q = 0; q < R; ++q) {
+                        const uint32_t w = x[u][q];
+                        const uint32_t *p = reinterpret_cast<const uint32_t *>(base + (w & 0x07ffffffu));
+                        const uint32_t lo = p[0], hi = p[1];
+                        bs_add(a[q], __builtin_amdgcn_alignbit(hi, lo, w >> 27));
+                    }
+#pragma unroll
+                for (int q = 0; q < R; ++q) {
+                    const uint32_t y = bs_ge(a[q], k1);
+                    if constexpr (D == 1) out[q] = y;
+                    else bs_add(cnt[0][q], y);
+                }
+                close_bits_from<2, D, NS, R>(c, cnt, out, s.k_int);
+            }
+        }
+        buf ^= 1;
+    }
+    // root bits -> 0/1 bytes: lane holds samples t0 + 32 lane .. + 31
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+        if (row[q] < 0) continue;
+        uint8_t *dst = static_cast<uint8_t *>(s.dst) + (int64_t)row[q] * s.dst_pitch + t0 + 32 * lane;
+        const int nv = vt - 32 * lane;  // valid samples of this lane
+        if (nv >= 32 && ((uintptr_t)dst & 3u) == 0) {
+            uint32_t wds[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const uint32_t nib = (out[q] >> (4 * k)) & 0xfu;
+                wds[k] = (nib & 1u) | ((nib & 2u) << 7) | ((nib & 4u) << 14) | ((nib & 8u) << 21);
+            }
+            uint32_t *d32 = reinterpret_cast<uint32_t *>(dst);
+#pragma unroll
+            for (int k = 0; k < 8; ++k) d32[k] = wds[k];
+        } else {
+            for (int i = 0; i < 32 && i < nv; ++i) dst[i] = (uint8_t)((out[q] >> i) & 1u);
+        }
+    }
+}
+
+template <int F1, int D>
+int launch_bits_shape(const GroupArgs &a, int64_t n_out, int lds, hipStream_t st, const Multi &m, int64_t nb_multi)
+{
+    const int64_t ntt = (n_out + kGroupTileBits - 1) / kGroupTileBits;
+    const int64_t nb = m.n > 0 ? nb_multi : (int64_t)a.ngroups * ntt;
+    if (nb <= 0) return 0;
+    if (nb > 0x7fffffffLL) return (int)hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_group_bits<F1, D>), dim3((uint32_t)nb), dim3(1024), lds, st, a, m);
+    return (int)hipGetLastError();
+}
+
+}  // namespace
+
+int launch_group_bits(const GroupArgs &a, int64_t n_out, int lds, void *stream, const Multi &m, int64_t nb)
+{
+    hipStream_t st = (hipStream_t)stream;
+#define SND_BITS(F, DD) \
+    if (a.f1 == F && a.depth == DD) return launch_bits_shape<F, DD>(a, n_out, lds, st, m, nb);
+    SND_BITS(2, 1) SND_BITS(2, 2) SND_BITS(2, 3) SND_BITS(2, 4) SND_BITS(2, 5) SND_BITS(2, 6) SND_BITS(2, 7) SND_BITS(2, 8)
+    SND_BITS(4, 1) SND_BITS(4, 2) SND_BITS(4, 3) SND_BITS(4, 4) SND_BITS(4, 5)
+    SND_BITS(8, 1) SND_BITS(8, 2) SND_BITS(8, 3) SND_BITS(8, 4)
+#undef SND_BITS
+    return (int)hipErrorInvalidValue;
+}
+
+}  // namespace snd

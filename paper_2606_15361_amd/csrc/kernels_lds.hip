@@ -18,6 +18,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 
 #include "group_common.h"
 
@@ -216,13 +217,27 @@ __global__ __launch_bounds__(256) void k_anchored(AnchorArgs s0, Multi m)
             }
             close_levels<MODE, A, MAXD, V>(acc, out, (int)(en.rowc >> 24), s.depth, 1, s.k_leaf, s.k_int, s.cap);
         }
-        TO *dst = static_cast<TO *>(s.dst) + (int64_t)r * s.dst_pitch + i0 + lane;
+        if constexpr (std::is_same<TO, bits_t>::value) {
+            // bit rows: i0 is a multiple of 64 (row anchors and tiles are), so the 64 samples
+            // lane + 64 v of a wave are the two words (i0 + 64 v) / 32 and the next; samples
+            // outside the row are zero and words outside it are not written
+            uint32_t *rowp = reinterpret_cast<uint32_t *>(s.dst) + (int64_t)r * (s.dst_pitch / 32);
 #pragma unroll
-        for (int v = 0; v < V; ++v) {
-            const int i = i0 + lane + 64 * v;
-            if (i >= 0 && i < len) {
-                if constexpr (MODE == SND_MODE_FLOAT) Store<TO>::put(dst + 64 * v, out[v] * s.scale);
-                else Store<TO>::put(dst + 64 * v, out[v]);
+            for (int v = 0; v < V; ++v) {
+                const int i = i0 + lane + 64 * v;
+                const uint64_t mask = __ballot(i >= 0 && i < len && out[v] != 0);
+                const int w = ((i0 + 64 * v) >> 5) + (lane & 1);
+                if (lane < 2 && w >= 0 && 32 * w < len) rowp[w] = lane ? (uint32_t)(mask >> 32) : (uint32_t)mask;
+            }
+        } else {
+            TO *dst = static_cast<TO *>(s.dst) + (int64_t)r * s.dst_pitch + i0 + lane;
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                const int i = i0 + lane + 64 * v;
+                if (i >= 0 && i < len) {
+                    if constexpr (MODE == SND_MODE_FLOAT) Store<TO>::put(dst + 64 * v, out[v] * s.scale);
+                    else Store<TO>::put(dst + 64 * v, out[v]);
+                }
             }
         }
     }
@@ -285,6 +300,10 @@ struct AnchorLauncher {
 int launch_group(int mode, int src_dt, int dst_dt, const GroupArgs &a, int64_t n_out, int lds_bytes, void *stream,
                  const Multi &m, int64_t nblocks)
 {
+    if (src_dt == SND_DT_BITS) {
+        if (mode != SND_MODE_BINARY || dst_dt != SND_DT_U8 || a.f1 <= 0) return (int)hipErrorInvalidValue;
+        return launch_group_bits(a, n_out, lds_bytes, stream, m, nblocks);
+    }
     if (a.f1 > 0) {
         if (mode == SND_MODE_BINARY)
             return launch_group_fast_binary(src_dt, dst_dt, a, n_out, lds_bytes, stream, m, nblocks);
@@ -300,6 +319,10 @@ int launch_group(int mode, int src_dt, int dst_dt, const GroupArgs &a, int64_t n
 int launch_anchored(int mode, int src_dt, int dst_dt, const AnchorArgs &a, int64_t ntiles, int lds_bytes, void *stream,
                     const Multi &m)
 {
+    if (dst_dt == SND_DT_BITS) {
+        if (mode != SND_MODE_BINARY || src_dt != SND_DT_U8) return (int)hipErrorInvalidValue;
+        return launch_anchored_typed<SND_MODE_BINARY, uint8_t, bits_t>(a, ntiles, lds_bytes, (hipStream_t)stream, m);
+    }
     return dispatch_types(mode, src_dt, dst_dt, AnchorLauncher{a, ntiles, lds_bytes, m}, (hipStream_t)stream);
 }
 

@@ -32,9 +32,11 @@ int dtype_size(int dt)
     case SND_DT_F32: return 4;
     case SND_DT_BF16: return 2;
     case SND_DT_F16: return 2;
-    default: return 0;
+    default: return 0;  // SND_DT_BITS: less than a byte per element
     }
 }
+
+int64_t dtype_bytes(int dt, int64_t elems) { return dt == SND_DT_BITS ? (elems + 7) / 8 : elems * dtype_size(dt); }
 
 namespace {
 
@@ -86,7 +88,7 @@ int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
 
 bool valid_dtype_pair(int mode, int in_dt, int node_dt, int cap)
 {
-    if (mode == SND_MODE_BINARY) return in_dt == SND_DT_U8 && node_dt == SND_DT_U8;
+    if (mode == SND_MODE_BINARY) return in_dt == SND_DT_U8 && (node_dt == SND_DT_U8 || node_dt == SND_DT_BITS);
     if (mode == SND_MODE_GRADED)
         return in_dt == SND_DT_U8 && (node_dt == SND_DT_U16 || (node_dt == SND_DT_U8 && cap <= 255));
     if (mode == SND_MODE_FLOAT) {
@@ -125,16 +127,19 @@ bool build_group_lds(const PlanImpl &p, Stage &S, bool allow_fast)
             !group_fast_types(p.desc.mode, S.src_dtype, S.dst_dtype))
             f1 = 0;
     }
-    const int tile = f1 ? kGroupTileFast : kGroupTile;
+    const bool bits = S.src_dtype == SND_DT_BITS;
+    if (bits && !f1) return false;  // bit rows: specialised kernel only
+    const int tile = bits ? kGroupTileBits : f1 ? kGroupTileFast : kGroupTile;
     const int rpw = f1 ? kFastRows : 1;  // rows per wave
     const int gr = kGroupRows * rpw;     // rows per group
     const int unit = f1 ? f1 : 1;  // batches end on level-1 node boundaries
-    const int es = dtype_size(S.src_dtype);
-    const int64_t budget = (f1 ? kGroupFastLdsBytes : kGroupLdsBytes) / es;
-    const int32_t epd = 16 / es;  // elements per 16-byte copy unit
+    const int eb = bits ? 1 : 8 * dtype_size(S.src_dtype);  // bits per element
+    const int64_t budget = (int64_t)(f1 ? kGroupFastLdsBytes : kGroupLdsBytes) * 8 / eb;
+    const int32_t epd = 128 / eb;  // elements per 16-byte copy unit
     // LDS elements of one window: its span plus one tile, from a 16-byte boundary, whole units
+    // (bit rows: one more unit, since a lane reads the word after its 32 samples too)
     auto slot_elems = [&](int32_t lo, int32_t span) {
-        return (int64_t)round_up((int64_t)(lo % epd) + span + tile, epd);
+        return (int64_t)round_up((int64_t)(lo % epd) + span + tile, epd) + (bits ? epd : 0);
     };
     std::vector<int32_t> order(rows);
     std::iota(order.begin(), order.end(), 0);
@@ -243,7 +248,7 @@ bool build_group_lds(const PlanImpl &p, Stage &S, bool allow_fast)
         const int32_t srow = slots[si], lo = slots[si + 1], span = slots[si + 2], lofs = slots[si + 3];
         if (lo < 0) return false;
         const int32_t head = lo % epd;
-        instrs.insert(instrs.end(), {srow, lo - head, (lofs - head) * es, head + span});
+        instrs.insert(instrs.end(), {srow, lo - head, (int32_t)((int64_t)(lofs - head) * eb / 8), head + span});
     }
     S.kernel = kKernelGroupLds;
     S.ngroups = ng;
@@ -251,9 +256,10 @@ bool build_group_lds(const PlanImpl &p, Stage &S, bool allow_fast)
     S.group_f1 = f1;
     S.group_tile = tile;
     S.group_rpw = rpw;
-    S.lds_buf_elems = (int32_t)(round_up(max_elems * es, 16) / es);
+    const int64_t buf_bytes = round_up(max_elems * eb / 8, 16);
+    S.lds_buf_elems = (int32_t)(buf_bytes * 8 / eb);
     // general kernel: batches b+1, b+2 land while b is read; specialised kernel: b+1
-    S.lds_bytes = (f1 ? kFastBuffers : kGroupBuffers) * S.lds_buf_elems * es;
+    S.lds_bytes = (int32_t)((f1 ? kFastBuffers : kGroupBuffers) * buf_bytes);
     S.grp_rows = std::move(grp_rows);
     S.batch_ptr = std::move(batch_ptr);
     S.batches = std::move(batches);
@@ -262,7 +268,11 @@ bool build_group_lds(const PlanImpl &p, Stage &S, bool allow_fast)
     if (f1) {
         // specialised kernel: LDS byte offsets without the closing counts, which are the same for
         // every row and kept once per level-1 node
-        for (uint32_t &w : ldsb) w = (w & kRowMask) * (uint32_t)es;
+        // (bit rows: byte offset of the word holding the first sample | bit offset << 27)
+        for (uint32_t &w : ldsb) {
+            const uint32_t o = w & kRowMask;
+            w = bits ? ((o >> 5) << 2) | ((o & 31u) << 27) : o * (uint32_t)(eb / 8);
+        }
         S.node_closes.resize((size_t)(ne / f1));
         for (int32_t k = 0; k < ne / f1; ++k) S.node_closes[(size_t)k] = (int32_t)(S.ent[k * f1 + f1 - 1].rowc >> 24);
     }
@@ -467,6 +477,17 @@ snd_status build_plan(const snd_plan_desc &d, PlanImpl &p, std::string &err)
         }
     }
 
+    // Bit rows: every leaf row starts on a 64-sample boundary (its anchor moves down by at
+    // most 63 samples), so that a leaf-stage tile writes whole words of each row.
+    const bool bits = d.node_dtype == SND_DT_BITS;
+    if (bits) {
+        if (top < 1 || d.generic_kernels || (d.stage_levels != 0 && d.stage_levels != 1u)) {
+            err = "bit rows need the default schedule (leaf level materialised) and the staged kernels";
+            return SND_ERR_UNSUPPORTED;
+        }
+        for (int32_t &v : p.lev[0].lo) v -= v % 64;
+    }
+
     // ---------------- stages ----------------
     uint32_t mask;
     if (d.stage_levels == SND_STAGE_NONE) {
@@ -569,7 +590,8 @@ snd_status build_plan(const snd_plan_desc &d, PlanImpl &p, std::string &err)
                 }
             }
         }
-        S.pitch = S.final_stage ? 0 : round_up(S.max_len, 64);
+        // row pitch in elements: 64, or 128 bits (16 bytes) for bit rows
+        S.pitch = S.final_stage ? 0 : round_up(S.max_len, S.dst_dtype == SND_DT_BITS ? 128 : 64);
         p.stages.push_back(std::move(S));
         src = dsts[si];
     }
@@ -578,8 +600,13 @@ snd_status build_plan(const snd_plan_desc &d, PlanImpl &p, std::string &err)
     for (Stage &S : p.stages) {
         S.kernel = kKernelGeneric;
         if (d.generic_kernels) continue;
-        if (S.final_stage && (build_group_lds(p, S, true) || build_group_lds(p, S, false))) continue;
+        if (S.final_stage && (build_group_lds(p, S, true) || (!bits && build_group_lds(p, S, false)))) continue;
         if (!S.final_stage && S.src_level < 0) build_anchored(p, S);
+    }
+    if (bits && (p.stages.size() != 2 || p.stages[0].kernel != kKernelAnchored ||
+                 p.stages[1].kernel != kKernelGroupLds)) {
+        err = "bit rows need level-1 nodes of equal fan-in (2, 4 or 8) and a leaf stage that fits the staged kernels";
+        return SND_ERR_UNSUPPORTED;
     }
 
     // ---------------- table image and workspace layout ----------------
@@ -625,7 +652,7 @@ snd_status build_plan(const snd_plan_desc &d, PlanImpl &p, std::string &err)
     for (Stage &S : p.stages) {
         if (S.final_stage) continue;
         S.ws_off = ws;
-        ws = round_up(ws + S.rows * S.pitch * dtype_size(S.dst_dtype), 256);
+        ws = round_up(ws + dtype_bytes(S.dst_dtype, S.rows * S.pitch), 256);
     }
     p.workspace_bytes = ws;
 
@@ -651,22 +678,24 @@ snd_status build_plan(const snd_plan_desc &d, PlanImpl &p, std::string &err)
         Stage &S = p.stages[si];
         int64_t in_bytes;
         if (S.src_level < 0) {
-            in_bytes = (int64_t)nc * p.nsamp * dtype_size(S.src_dtype);
+            in_bytes = dtype_bytes(S.src_dtype, (int64_t)nc * p.nsamp);
         } else {
             const Level &SL = p.lev[S.src_level];
             in_bytes = 0;
             for (int64_t r = 0; r < SL.rows; ++r) in_bytes += (p.n_out + SL.hi[r] - SL.lo[r]);
-            in_bytes *= dtype_size(S.src_dtype);
+            in_bytes = dtype_bytes(S.src_dtype, in_bytes);
         }
         int64_t out_bytes = 0;
         for (int64_t r = 0; r < S.rows; ++r) out_bytes += S.row_len[r];
-        out_bytes *= dtype_size(S.dst_dtype);
+        out_bytes = dtype_bytes(S.dst_dtype, out_bytes);
         S.alg_bytes = in_bytes + out_bytes;
         alg += S.alg_bytes;
         I.stage_alg_bytes[si] = S.alg_bytes;
         I.stage_rows[si] = S.rows;
         I.stage_entries[si] = (int64_t)S.ent.size();
-        I.stage_kernel[si] = (S.kernel == kKernelGroupLds && S.group_f1 > 0) ? 3 : S.kernel;
+        I.stage_kernel[si] = S.kernel == kKernelGroupLds && S.src_dtype == SND_DT_BITS ? 4
+                             : (S.kernel == kKernelGroupLds && S.group_f1 > 0) ? 3
+                                                                                : S.kernel;
         if (S.kernel == kKernelGroupLds) {
             int64_t staged = 0;
             for (size_t i = 0; i < S.slots.size(); i += 4) staged += S.slots[i + 2] + S.group_tile;

@@ -92,9 +92,10 @@ constexpr int kFastV = 8;
 constexpr int kGroupTileFast = 64 * kFastV;
 constexpr int kFastBuffers = 2;           // batch b + 1 lands while b is read
 constexpr int kGroupFastLdsBytes = 81920; // per buffer (two fill the 160 KB of LDS)
+constexpr int kGroupTileBits = 2048;  // bit rows: 32 samples (one word) per lane
 inline bool group_fast_types(int mode, int src_dt, int dst_dt)
 {
-    if (mode == SND_MODE_BINARY) return src_dt == SND_DT_U8 && dst_dt == SND_DT_U8;
+    if (mode == SND_MODE_BINARY) return (src_dt == SND_DT_U8 || src_dt == SND_DT_BITS) && dst_dt == SND_DT_U8;
     if (mode == SND_MODE_GRADED) return src_dt == dst_dt && (src_dt == SND_DT_U8 || src_dt == SND_DT_U16);
     return dst_dt == SND_DT_F32;
 }
@@ -138,6 +139,7 @@ struct PlanImpl {
 };
 
 int dtype_size(int dt);
+int64_t dtype_bytes(int dt, int64_t elems);  // storage bytes of elems elements (bit rows: rounded up)
 
 // One execution of a plan: n_run <= n_out output samples from a source window of src_len
 // samples per channel; the input rows are rings of ring_len samples whose window starts at

@@ -19,6 +19,9 @@ template <typename T> __device__ inline const_ptr<T> as_const(const T *p) { retu
 
 struct bf16_t { uint16_t bits; };
 struct f16_t { _Float16 v; };
+// Bit rows (binary mode): one bit per sample in 32-bit words; rows are written word-wise by the
+// leaf stage and read word-wise by the bit-row final stage, never through Load / Store.
+struct bits_t { uint32_t w; };
 
 template <typename T> struct Load;
 template <> struct Load<uint8_t> { __device__ static int get(const uint8_t *p) { return *p; } };

@@ -10,7 +10,8 @@ import numpy as np
 from . import _capi as capi
 
 MODES = {"binary": capi.MODE_BINARY, "graded": capi.MODE_GRADED, "float": capi.MODE_FLOAT}
-DTYPES = {"u8": capi.DT_U8, "u16": capi.DT_U16, "f32": capi.DT_F32, "bf16": capi.DT_BF16, "f16": capi.DT_F16}
+DTYPES = {"u8": capi.DT_U8, "u16": capi.DT_U16, "f32": capi.DT_F32, "bf16": capi.DT_BF16, "f16": capi.DT_F16,
+          "bits": capi.DT_BITS}
 DTYPE_NAMES = {v: k for k, v in DTYPES.items()}
 
 
@@ -36,7 +37,7 @@ def make_desc(freqs, dms, tsamp_s, nsamp, *, mode="float", branching=4, cluster=
     if in_dtype is None:
         in_dtype = "f32" if mode == "float" else "u8"
     if node_dtype is None:
-        node_dtype = "f32" if mode == "float" else ("u8" if mode == "binary" or cap <= 255 else "u16")
+        node_dtype = "f32" if mode == "float" else ("bits" if mode == "binary" else "u8" if cap <= 255 else "u16")
     d = capi.PlanDesc()
     d.nchan = freq.size
     d.freq_mhz = freq.ctypes.data_as(C.POINTER(C.c_double))
@@ -95,12 +96,20 @@ class Plan:
         """nsamp: input samples per execute; or chunk > 0 (nsamp None): a streaming plan whose
         n_out is `chunk` and whose nsamp is max_delay + chunk."""
         L = capi.lib()
+        # binary mode stores tree rows as bits unless asked otherwise; trees and schedules that
+        # bit rows do not support (irregular level-1 nodes, other stage schedules) use bytes
+        auto_bits = mode == "binary" and node_dtype is None
         d, self._freq, self._dm, in_dtype, node_dtype = make_desc(
             freqs, dms, tsamp_s, nsamp, mode=mode, branching=branching, cluster=cluster, k_leaf=k_leaf, k_int=k_int,
             cap=cap, in_dtype=in_dtype, node_dtype=node_dtype, root_norm=root_norm, fref=fref,
             stage_levels=stage_levels, generic_kernels=generic_kernels, chunk=chunk)
         h = C.c_void_p()
-        capi.check(L.snd_plan_create(C.byref(d), C.byref(h)))
+        rc = L.snd_plan_create(C.byref(d), C.byref(h))
+        if rc == capi.ERR_UNSUPPORTED and auto_bits:
+            node_dtype = "u8"
+            d.node_dtype = DTYPES[node_dtype]
+            rc = L.snd_plan_create(C.byref(d), C.byref(h))
+        capi.check(rc)
         self._h = h
         self.mode, self.nchan, self.ndm = mode, self._freq.size, self._dm.size
         self.in_dtype, self.node_dtype = in_dtype, node_dtype
@@ -117,7 +126,8 @@ class Plan:
             workspace_bytes=info.workspace_bytes, alg_bytes=info.alg_bytes,
             stage_alg_bytes=list(info.stage_alg_bytes[:ns]), stage_rows=list(info.stage_rows[:ns]),
             stage_entries=list(info.stage_entries[:ns]), build_seconds=info.build_seconds,
-            stage_kernel=[("generic", "group_lds", "anchored", "group_fast")[k] for k in info.stage_kernel[:ns]],
+            stage_kernel=[("generic", "group_lds", "anchored", "group_fast", "group_bits")[k]
+                          for k in info.stage_kernel[:ns]],
             stage_staged=list(info.stage_staged[:ns]), stage_batches=list(info.stage_batches[:ns]),
             stage_windows=list(info.stage_windows[:ns]),
             stage_src_dtype=[in_dtype if s == 0 else node_dtype for s in range(ns)])

@@ -88,16 +88,18 @@ def test_parity_small(snd, orc, nchan, C_, B, mode, kw):
     want, _ = orc.snd_dedup(x, f, d, mode=mode, cluster=C_, branching=B, **kw)
     ys = []
     nlev = len(orc.tree_shape(f, C_, B))
-    variants = [(0, False), (0, True), (STAGE_NONE, False)]
+    variants = [(0, False, None), (0, True, None), (STAGE_NONE, False, None)]
+    if mode == "binary":
+        variants.append((0, False, "u8"))  # byte rows next to the default bit rows
     if nlev > 2:
-        variants += [((1 << (nlev - 1)) - 1, False), ((1 << (nlev - 1)) - 1, True)]
-    for sl, generic in variants:
-        _say(f"case nchan={nchan} C={C_} B={B} mode={mode} {kw} stage_levels={sl:#x} generic={generic}")
+        variants += [((1 << (nlev - 1)) - 1, False, None), ((1 << (nlev - 1)) - 1, True, None)]
+    for sl, generic, node in variants:
+        _say(f"case nchan={nchan} C={C_} B={B} mode={mode} {kw} stage_levels={sl:#x} generic={generic} node={node}")
         p = snd.Plan(f, dms, 0.138e-3, nsamp, mode=mode, cluster=C_, branching=B, stage_levels=sl,
-                     generic_kernels=generic, **kw)
+                     generic_kernels=generic, node_dtype=node, **kw)
         if not generic and sl == 0 and nlev > 1:
             assert p.info["stage_kernel"][0] == "anchored", p.info["stage_kernel"]
-            assert p.info["stage_kernel"][1] in ("group_lds", "group_fast"), p.info["stage_kernel"]
+            assert p.info["stage_kernel"][1] in ("group_lds", "group_fast", "group_bits"), p.info["stage_kernel"]
         y = gpu_run(p, x, stage_by_stage=(sl == 0))
         assert y.shape == want.shape
         if mode == "float":
@@ -142,8 +144,12 @@ def test_config1_binary_exact(snd, orc, kl, ki):
     want, counts = orc.snd_dedup(x, spec.freqs, d, mode="binary", cluster=4, branching=2, k_leaf=kl, k_int=ki)
     p = snd.Plan(spec.freqs, spec.dms, spec.tsamp_s, spec.nsamp, mode="binary", branching=2, k_leaf=kl, k_int=ki)
     assert p.info["n_neurons"] == sum(c[0] for c in counts) == 1984
-    assert p.info["stage_kernel"] == ["anchored", "group_fast"]
+    assert p.node_dtype == "bits" and p.info["stage_kernel"] == ["anchored", "group_bits"]
     assert np.array_equal(gpu_run(p, x), want.astype(np.uint8))
+    pb = snd.Plan(spec.freqs, spec.dms, spec.tsamp_s, spec.nsamp, mode="binary", branching=2, k_leaf=kl, k_int=ki,
+                  node_dtype="u8")
+    assert pb.info["stage_kernel"] == ["anchored", "group_fast"]
+    assert np.array_equal(gpu_run(pb, x), want.astype(np.uint8))
 
 
 @pytest.mark.parametrize("B", [2, 4, 8])
@@ -235,7 +241,7 @@ def test_determinism(snd):
     assert np.array_equal(a, b)
 
 
-@pytest.mark.parametrize("mode", ["float", "graded"])
+@pytest.mark.parametrize("mode", ["float", "graded", "binary"])
 def test_config2_full_size_sampled(snd, orc, mode):
     # The benchmarked workload (1024 ch, 4096 DM, 2^17 samples, B = 4) at full size, checked
     # on sampled outputs against the oracle's per-point recursion.
@@ -247,9 +253,11 @@ def test_config2_full_size_sampled(snd, orc, mode):
     if mode == "float":
         x, xin = z, zt
     else:
-        xin = snd.encode(zt, [1.0, 2.0, 3.0, 4.0])
+        xin = snd.encode(zt, [1.0, 2.0, 3.0, 4.0] if mode == "graded" else [2.0])
         x = to_np(xin)
     p = snd.Plan(spec.freqs, spec.dms, spec.tsamp_s, spec.nsamp, mode=mode, branching=4)
+    if mode == "binary":
+        assert p.info["stage_kernel"] == ["anchored", "group_bits"]
     _say(f"config2 mode={mode}: executing on the GPU")
     y = p.execute(xin)
     torch.cuda.synchronize()
