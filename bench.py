@@ -24,7 +24,8 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 METRIC = "dedispersed DM\u00d7time samples/s (1024 ch, 4096 DM) + %HBM peak; p99 chunk latency"
 LDS_PEAK_GBS = 256 * 128 * 2.4  # 256 CUs x 128 B/clk x 2.4 GHz
-KERNEL_SYMBOL = {"generic": "k_stage", "group_lds": "k_group", "anchored": "k_anchored", "group_fast": "k_group_fast"}
+KERNEL_SYMBOL = {"generic": "k_stage", "group_lds": "k_group", "anchored": "k_anchored", "group_fast": "k_group_fast",
+                 "group_bits": "k_group_bits", "anchored_bits": "k_anchored_bits"}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic.json")
 
 
@@ -67,6 +68,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--mode", default="float", choices=["float", "graded", "binary"])
     ap.add_argument("--node-dtype", default=None)
+    ap.add_argument("--input", default="auto", choices=["auto", "bytes", "bits"],
+                    help="binary input storage: bit rows (auto) or one byte per sample")
     ap.add_argument("--stage-levels", type=lambda s: int(s, 0), default=0)
     ap.add_argument("--no-detect", action="store_true", help="time the tree only")
     ap.add_argument("--generic-kernels", action="store_true", help="run every stage on the generic stage kernel")
@@ -337,10 +340,13 @@ def main():
     zt = torch.from_numpy(z).to(dev)
     if mode == "float":
         x = zt
-    else:
-        x = snd.encode(zt, [1.0, 2.0, 3.0, 4.0] if mode == "graded" else [2.0])
     node = args.node_dtype
     in_dtype = None
+    if mode == "binary" and args.input != "bytes" and node in (None, "bits"):
+        in_dtype = "bits"  # spikes as bit rows, straight from the encoder
+        x = snd.encode_bits(zt, 2.0)
+    elif mode != "float":
+        x = snd.encode(zt, [1.0, 2.0, 3.0, 4.0] if mode == "graded" else [2.0])
     if mode == "float" and node in ("bf16", "f16"):
         in_dtype = node
         x = snd.cast(zt, node)
@@ -352,7 +358,7 @@ def main():
     if not args.no_autotune and not args.stage_levels and not args.generic_kernels:
         # measured choice of the stage schedule: leaves only, level 2 only, leaves and level 2
         cands = [(0, 0), (0b0100, 0), (0b0101, 0)]
-        best, tuned = snd.autotune(spec.freqs, spec.dms, spec.tsamp_s, x, cands, reps=1, **pkw)
+        best, tuned = snd.autotune(spec.freqs, spec.dms, spec.tsamp_s, x, cands, reps=1, nsamp=spec.nsamp, **pkw)
         stage_levels = cands[best][0]
         log(f"[bench] autotune: {[(hex(t['stage_levels']), round(t['ms'], 2)) for t in tuned]} -> {stage_levels:#x}")
         torch.cuda.empty_cache()
@@ -412,14 +418,17 @@ def main():
     alg = info["stage_alg_bytes"][dom]
     achieved = alg / (stage_ms[dom] * 1e-3) / 1e9
     kname = KERNEL_SYMBOL[info["stage_kernel"][dom]]
-    wl_key = f"{mode}-{node or 'native'}-stage{dom}-{kname}"
+    node = plan.node_dtype
+    wl_key = f"{mode}-{plan.in_dtype}-{node}-stage{dom}-{kname}"
     traffic = measured_traffic(wl_key)
     # LDS: every input of every output row is read once per output sample from LDS by the
     # staged kernels; this is the kernel's own LDS floor, next to the HBM one
-    es = {"f32": 4, "bf16": 2, "f16": 2, "u8": 1, "u16": 2}[info["stage_src_dtype"][dom]]
+    es = {"f32": 4, "bf16": 2, "f16": 2, "u8": 1, "u16": 2, "bits": 0.125}[info["stage_src_dtype"][dom]]
     lds_alg = info["stage_entries"][dom] * plan.n_out * es
     whole_alg = sum(info["stage_alg_bytes"])
-    dtype_name = {"float": node or "f32", "graded": "u8", "binary": "u8"}[mode]
+    # the type the tree arithmetic runs in: float storage types accumulate in FP32; binary bit
+    # rows are evaluated with bitwise logic on 1-bit samples
+    dtype_name = {"float": "f32" if node == "f32" else node, "graded": node, "binary": "u1" if node == "bits" else "u8"}[mode]
     result = {
         "metric": METRIC,
         "value": value,
@@ -431,11 +440,11 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if mode == "float" and dtype_name == "f32" else dtype_name,
+        "dtype": dtype_name,
         "data": "synthetic",
         "config": {"workload": "single NC-shaped beam: 1024 ch 400-416 MHz, 0.138 ms, 2^17 samples, 16 pulses; "
                                "4096 DMs 0-2000; B=4, C=4",
-                   "mode": mode, "node_dtype": node or ("f32" if mode == "float" else "u8"),
+                   "mode": mode, "in_dtype": plan.in_dtype, "node_dtype": node,
                    "n_out": plan.n_out, "stages": nst, "detect": detector is not None},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,

@@ -55,8 +55,9 @@ typedef enum {
     SND_DT_F32 = 3,
     SND_DT_BF16 = 4,
     SND_DT_F16 = 5,
-    SND_DT_BITS = 6   /* binary tree rows, one bit per sample: bit i of 32-bit word w holds
-                         sample 32 w + i of the row (node storage of binary mode only) */
+    SND_DT_BITS = 6   /* binary spikes, one bit per sample: bit i of 32-bit word w holds
+                         sample 32 w + i of the row; pitches of such rows are counted in bits
+                         (binary mode only: input and node storage) */
 } snd_dtype;
 
 /*
@@ -87,7 +88,10 @@ typedef struct {
     int32_t k_int;           /* binary quorum at every higher node incl. the root, >= 1 */
     int32_t cap;             /* graded clip N, 1..65535 (ignored otherwise) */
     int32_t in_dtype;        /* input samples: U8 for binary/graded (binary: non-zero = spike);
-                                F32, BF16 or F16 for float */
+                                F32, BF16 or F16 for float.  Binary also takes BITS input (rows of
+                                bits, in_pitch in bits and a multiple of 32), which needs
+                                node_dtype BITS, cluster <= 15 and a plain (chunk = 0) plan;
+                                UNSUPPORTED otherwise */
     int32_t node_dtype;      /* storage of materialised tree rows: BITS or U8 for binary; U8
                                 (cap <= 255) or U16 for graded; F32, BF16 or F16 for float (FP32
                                 accumulate).  BITS needs the default schedule (leaf level
@@ -132,7 +136,8 @@ typedef struct {
     double build_seconds;                   /* host time of snd_plan_create */
     int32_t stage_kernel[SND_MAX_LEVELS];   /* kernel per stage: 0 generic, 1 LDS row groups,
                                                2 input-anchored, 3 LDS row groups specialised for
-                                               regular level-1 nodes, 4 the same on bit rows */
+                                               regular level-1 nodes, 4 the same on bit rows,
+                                               5 input-anchored on bit input */
     int64_t stage_staged[SND_MAX_LEVELS];   /* LDS row groups: source elements staged per time
                                                tile summed over groups (0 otherwise) */
     int64_t stage_batches[SND_MAX_LEVELS];  /* LDS row groups: batches summed over groups */
@@ -161,7 +166,8 @@ snd_status snd_plan_destroy(snd_plan plan);
  * d_in [nchan][in_pitch] (in_dtype) into d_out [ndm][out_pitch] (out_dtype), rows in the
  * order of desc->dm, n_out valid samples per row.  d_workspace: workspace_bytes device
  * bytes, 256-byte aligned, contents irrelevant on entry.  Asynchronous on stream.
- * STATE before snd_plan_upload; INVALID for pitches smaller than nsamp / n_out.
+ * STATE before snd_plan_upload; INVALID for pitches smaller than nsamp / n_out, or a BITS
+ * in_pitch that is not a multiple of 32.
  */
 snd_status snd_execute(snd_plan plan, const void *d_in, int64_t in_pitch, void *d_out, int64_t out_pitch,
                        void *d_workspace, int64_t workspace_bytes, void *stream);
@@ -184,6 +190,16 @@ snd_status snd_execute_stage(snd_plan plan, int32_t stage, const void *d_in, int
  */
 snd_status snd_encode(const float *d_z, int64_t z_pitch, int32_t time_major, int32_t nchan, int64_t nsamp,
                       const float *h_thresholds, int32_t nthr, uint8_t *d_out, int64_t out_pitch, void *stream);
+
+/*
+ * Delta encoder to bits (Methods, "Input encoding": x = 1[z > theta], one threshold, compared
+ * in FP32): bit i of word w of channel c is 1[z_c(32 w + i) > theta].  d_z as for snd_encode;
+ * d_out: uint32 [nchan][out_pitch / 32] channel-major, out_pitch in bits, a multiple of 32 and
+ * >= nsamp.  Words past the last one holding a sample are not written; bits past nsamp in that
+ * word are zero.  Asynchronous on stream.  The rows are BITS input for a binary plan.
+ */
+snd_status snd_encode_bits(const float *d_z, int64_t z_pitch, int32_t time_major, int32_t nchan, int64_t nsamp,
+                           float threshold, uint32_t *d_out, int64_t out_pitch, void *stream);
 
 /* Float32 -> BF16 or F16 cast with round-to-nearest-even (input staging for the reduced-
  * precision float mode).  d_src [rows][src_pitch] float32, d_dst [rows][dst_pitch] of
@@ -315,7 +331,8 @@ snd_status snd_autotune(const snd_plan_desc *desc, snd_tune_candidate *cands, in
 typedef struct snd_stream_s *snd_stream;
 
 /* Device bytes of one beam's history for this plan (ring of nchan x (max_delay + n_out)
- * input samples, rows padded to 256 bytes). */
+ * input samples, rows padded to 256 bytes).  UNSUPPORTED for BITS input (streams take byte
+ * or float input). */
 snd_status snd_stream_history_bytes(snd_plan plan, int64_t *bytes);
 
 /* New stream that admits beams while the sum of their history bytes stays within

@@ -7,10 +7,10 @@ PyTorch only provides device memory and HIP streams.
 """
 
 from ._capi import SndError, LIB_PATH  # noqa: F401
-from .plan import Plan, autotune, encode, cast  # noqa: F401
+from .plan import Plan, autotune, encode, encode_bits, cast  # noqa: F401
 from .detect import Detector  # noqa: F401
 from .stream import Stream, history_bytes  # noqa: F401
 from .batch import Batch, records_bytes  # noqa: F401
 
-__all__ = ["Plan", "autotune", "Detector", "Stream", "Batch", "history_bytes", "records_bytes", "encode", "cast", "SndError",
+__all__ = ["Plan", "autotune", "Detector", "Stream", "Batch", "history_bytes", "records_bytes", "encode", "encode_bits", "cast", "SndError",
            "LIB_PATH"]

@@ -102,6 +102,7 @@ def lib() -> C.CDLL:
         "snd_execute": ([P, P, I64, P, I64, P, I64, P], I32),
         "snd_execute_stage": ([P, I32, P, I64, P, I64, P, I64, P], I32),
         "snd_encode": ([P, I64, I32, I32, I64, P, I32, P, I64, P], I32),
+        "snd_encode_bits": ([P, I64, I32, I32, I64, C.c_float, P, I64, P], I32),
         "snd_cast": ([P, I64, I64, I64, P, I64, I32, P], I32),
         "snd_last_error": ([], C.c_char_p),
         "snd_version": ([], C.c_char_p),

@@ -6,7 +6,7 @@ from __future__ import annotations
 import ctypes as C
 
 from . import _capi as capi
-from .plan import Plan, _stream_handle
+from .plan import Plan, _stream_handle, row_pitch
 
 
 def _arr(ctype, values):
@@ -49,7 +49,7 @@ class Batch:
                 raise ValueError("output must be [ndm][T] of the plan's output dtype")
         hs = _arr(C.c_void_p, [p.handle.value for p in self.plans])
         ins = _arr(C.c_void_p, [x.data_ptr() for x in inputs])
-        inp = _arr(C.c_int64, [x.stride(0) for x in inputs])
+        inp = _arr(C.c_int64, [row_pitch(x, p.in_dtype) for p, x in zip(self.plans, inputs)])
         outs = _arr(C.c_void_p, [y.data_ptr() for y in outputs])
         outp = _arr(C.c_int64, [y.stride(0) for y in outputs])
         wss = _arr(C.c_void_p, [w.data_ptr() for w in self.workspaces])

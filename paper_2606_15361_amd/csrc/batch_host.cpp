@@ -186,6 +186,10 @@ snd_status snd_batch_execute(int32_t nbeams, const snd_plan *plans, const void *
             snd::set_error(who + "n_run must be in 0..n_out");
             return SND_ERR_INVALID;
         }
+        if (P.desc.in_dtype == SND_DT_BITS && in_pitch[i] % 32 != 0) {
+            snd::set_error(who + "bit input pitch must be a multiple of 32 bits");
+            return SND_ERR_INVALID;
+        }
         if (in_pitch[i] < P.max_delay + nr || out_pitch[i] < nr) {
             snd::set_error(who + "input pitch below max_delay + n_run or output pitch below n_run");
             return SND_ERR_INVALID;

@@ -109,6 +109,8 @@ snd_status check_exec(snd_plan plan, const void *d_in, int64_t in_pitch, void *d
     auto &P = plan->impl;
     if (!P.d_table) return fail(SND_ERR_STATE, "plan tables not uploaded");
     if (in_pitch < P.nsamp) return fail(SND_ERR_INVALID, "input pitch smaller than nsamp");
+    if (P.desc.in_dtype == SND_DT_BITS && in_pitch % 32 != 0)
+        return fail(SND_ERR_INVALID, "bit input pitch must be a multiple of 32 bits");
     if (out_pitch < P.n_out) return fail(SND_ERR_INVALID, "output pitch smaller than n_out");
     if (P.workspace_bytes > 0 && (!d_workspace || workspace_bytes < P.workspace_bytes))
         return fail(SND_ERR_NOMEM, "workspace smaller than workspace_bytes");
@@ -288,6 +290,20 @@ snd_status snd_encode(const float *d_z, int64_t z_pitch, int32_t time_major, int
     if (z_pitch < (time_major ? nchan : nsamp) || out_pitch < nsamp) return fail(SND_ERR_INVALID, "pitch too small");
     if (!time_major && nchan > 65535) return fail(SND_ERR_INVALID, "too many channels");
     int e = snd::launch_encode(d_z, z_pitch, time_major, nchan, nsamp, h_thresholds, nthr, d_out, out_pitch, stream);
+    if (e) return hip_fail(e, "encode launch");
+    return SND_OK;
+}
+
+snd_status snd_encode_bits(const float *d_z, int64_t z_pitch, int32_t time_major, int32_t nchan, int64_t nsamp,
+                           float threshold, uint32_t *d_out, int64_t out_pitch, void *stream)
+{
+    if (!d_z || !d_out) return fail(SND_ERR_INVALID, "null pointer");
+    if (nchan < 1 || nsamp < 1) return fail(SND_ERR_INVALID, "bad nchan or nsamp");
+    if (z_pitch < (time_major ? nchan : nsamp) || out_pitch < nsamp || out_pitch % 32 != 0)
+        return fail(SND_ERR_INVALID, "pitch too small, or output pitch not a multiple of 32 bits");
+    if (nchan > 65535 * (time_major ? 64 : 1) || nsamp > (int64_t)0x7fffffff * 64)
+        return fail(SND_ERR_INVALID, "too many channels or samples");
+    int e = snd::launch_encode_bits(d_z, z_pitch, time_major, nchan, nsamp, threshold, d_out, out_pitch / 32, stream);
     if (e) return hip_fail(e, "encode launch");
     return SND_OK;
 }

@@ -182,6 +182,42 @@ __global__ __launch_bounds__(256) void k_encode_tm(const float *z, int64_t zp, i
     }
 }
 
+// Bits: one wave tests 64 consecutive samples of a channel; the ballot is two output words.
+__global__ __launch_bounds__(256) void k_encode_bits_cm(const float *z, int64_t zp, int64_t nsamp, float th,
+                                                        uint32_t *out, int64_t ow)
+{
+    const int c = blockIdx.y;
+    const int lane = threadIdx.x & 63;
+    const int64_t tb = (int64_t)blockIdx.x * 256 + (threadIdx.x >> 6) * 64;  // first sample of the wave
+    const int64_t t = tb + lane;
+    const uint64_t mask = __ballot(t < nsamp && z[(int64_t)c * zp + t] > th);
+    const int64_t w = (tb >> 5) + lane;
+    if (lane < 2 && 32 * w < nsamp) out[(int64_t)c * ow + w] = lane ? (uint32_t)(mask >> 32) : (uint32_t)mask;
+}
+
+// Bits from time-major input: a 64 x 64 (time, channel) tile through LDS, then one ballot per
+// channel of the tile.
+__global__ __launch_bounds__(256) void k_encode_bits_tm(const float *z, int64_t zp, int nchan, int64_t nsamp,
+                                                        float th, uint32_t *out, int64_t ow)
+{
+    __shared__ uint8_t tile[64][65];
+    const int64_t tb = (int64_t)blockIdx.x * 64;
+    const int cb = blockIdx.y * 64;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    for (int i = ty; i < 64; i += 4) {  // i: time within tile, tx: channel within tile
+        const int64_t t = tb + i;
+        const int c = cb + tx;
+        tile[i][tx] = (t < nsamp && c < nchan) ? (uint8_t)(z[t * zp + c] > th) : (uint8_t)0;
+    }
+    __syncthreads();
+    for (int i = ty; i < 64; i += 4) {  // i: channel within tile, tx: time within tile
+        const uint64_t mask = __ballot(tile[tx][i] != 0);
+        const int c = cb + i;
+        const int64_t w = (tb >> 5) + tx;
+        if (tx < 2 && c < nchan && 32 * w < nsamp) out[(int64_t)c * ow + w] = tx ? (uint32_t)(mask >> 32) : (uint32_t)mask;
+    }
+}
+
 template <typename TO>
 __global__ __launch_bounds__(256) void k_cast(const float *src, int64_t sp, int64_t cols, TO *dst, int64_t dp)
 {
@@ -220,6 +256,20 @@ int launch_encode(const float *z, int64_t zp, int time_major, int nchan, int64_t
     } else {
         dim3 grid((uint32_t)((nsamp + 255) / 256), (uint32_t)nchan);
         hipLaunchKernelGGL(k_encode_cm, grid, dim3(256), 0, st, z, zp, nchan, nsamp, th, out, op);
+    }
+    return (int)hipGetLastError();
+}
+
+int launch_encode_bits(const float *z, int64_t zp, int time_major, int nchan, int64_t nsamp, float thr, uint32_t *out,
+                       int64_t ow, void *stream)
+{
+    hipStream_t st = (hipStream_t)stream;
+    if (time_major) {
+        dim3 grid((uint32_t)((nsamp + 63) / 64), (uint32_t)((nchan + 63) / 64));
+        hipLaunchKernelGGL(k_encode_bits_tm, grid, dim3(256), 0, st, z, zp, nchan, nsamp, thr, out, ow);
+    } else {
+        dim3 grid((uint32_t)((nsamp + 255) / 256), (uint32_t)nchan);
+        hipLaunchKernelGGL(k_encode_bits_cm, grid, dim3(256), 0, st, z, zp, nsamp, thr, out, ow);
     }
     return (int)hipGetLastError();
 }

@@ -1,4 +1,5 @@
-// Final stage of the binary tree on bit rows (Methods, "Tree activation modes", Mode A).
+// Binary tree kernels on bit rows (Methods, "Tree activation modes", Mode A): the final stage
+// and, for bit input, the leaf stage.
 //
 // The leaf stage stores every leaf neuron's output as one bit per sample.  Here a lane holds 32
 // consecutive samples of a DM row in one 32-bit word, so every tree operation works on 32
@@ -198,6 +199,76 @@ __global__ __launch_bounds__(1024) void k_group_bits(GroupArgs s0, Multi m)
     }
 }
 
+// Leaf stage on bit input: one 256-thread workgroup per (leaf node, window of kAnchorTileBits
+// reference samples), as the byte-input anchored kernel.  The node's channel windows are staged
+// in LDS as words (bits past the valid input are cleared); a wave evaluates one leaf neuron row
+// at a time, a lane holding the 32-sample words lane + 64 u of the tile: each input is a funnel
+// shift of two staged words, the count is bit-sliced and the quorum count >= K_L is one
+// bit-sliced comparison.  Row anchors and tiles are 64-aligned, so every output word is whole.
+template <int W>
+__global__ __launch_bounds__(256) void k_anchored_bits(AnchorArgs s0, Multi m)
+{
+    AnchorArgs s;
+    uint32_t bid, nblk;
+    select_record(s0, m, s, bid, nblk);
+    constexpr int T = 64 * 32 * W;
+    extern __shared__ __align__(16) unsigned char smem[];
+    uint32_t *lds = reinterpret_cast<uint32_t *>(smem);
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int node = s.tiles[2 * bid];
+    const int tau0 = s.tiles[2 * bid + 1];
+    const int *nd = s.nodes + 6 * node;
+    const int r0 = nd[0], r1 = nd[1], c0 = nd[2], c1 = nd[3], rho_max = nd[4];
+    if (tau0 >= nd[5] + s.n_run) return;  // past every row of the node in this run (uniform per block)
+    const int nw = 64 * W + (rho_max >> 5) + 1;  // staged words per channel
+    const uint32_t *src = static_cast<const uint32_t *>(s.src);
+    const int64_t wp = s.src_pitch >> 5;  // words per input row
+    const int64_t w0 = tau0 >> 5;         // first staged word
+    const int ntot = (c1 - c0) * nw;
+    for (int j = tid; j < ntot; j += 256) {
+        const int c = j / nw, k = j - c * nw;
+        const int64_t sb = 32 * (w0 + k);  // first sample of the word
+        uint32_t v = 0u;
+        if (sb < s.src_len) {
+            v = src[(int64_t)(c0 + c) * wp + w0 + k];
+            const int64_t left = s.src_len - sb;
+            if (left < 32) v &= (1u << left) - 1u;
+        }
+        lds[j] = v;
+    }
+    __syncthreads();
+    for (int r = r0 + wave; r < r1; r += 4) {
+        const int lo = s.row_lo[r], len = s.row_len[r] - s.len_cut;
+        const int i0 = tau0 - lo;  // output index at the window start (a multiple of 64)
+        if (i0 >= len || i0 + T <= 0) continue;
+        uint32_t cnt[W][kPlanes];
+#pragma unroll
+        for (int u = 0; u < W; ++u)
+#pragma unroll
+            for (int i = 0; i < kPlanes; ++i) cnt[u][i] = 0u;
+        const uint32_t eb = s.row_ptr[r], ee = s.row_ptr[r + 1];
+        for (uint32_t e = eb; e < ee; ++e) {
+            const Entry en = s.ent[e];
+            const int rho = en.off - lo;
+            const uint32_t *p = lds + ((int)(en.rowc & kRowMask) - c0) * nw + (rho >> 5) + lane;
+            const uint32_t sh = (uint32_t)rho & 31u;
+#pragma unroll
+            for (int u = 0; u < W; ++u) bs_add(cnt[u], __builtin_amdgcn_alignbit(p[64 * u + 1], p[64 * u], sh));
+        }
+        uint32_t *rowp = static_cast<uint32_t *>(s.dst) + (int64_t)r * (s.dst_pitch >> 5);
+#pragma unroll
+        for (int u = 0; u < W; ++u) {
+            const int wi = (i0 >> 5) + lane + 64 * u;  // output word of the row
+            if (wi < 0 || 32 * wi >= len) continue;
+            uint32_t y = bs_ge(cnt[u], s.k_leaf);
+            const int left = len - 32 * wi;
+            if (left < 32) y &= (1u << left) - 1u;
+            rowp[wi] = y;
+        }
+    }
+}
+
 template <int F1, int D>
 int launch_bits_shape(const GroupArgs &a, int64_t n_out, int lds, hipStream_t st, const Multi &m, int64_t nb_multi)
 {
@@ -210,6 +281,15 @@ int launch_bits_shape(const GroupArgs &a, int64_t n_out, int lds, hipStream_t st
 }
 
 }  // namespace
+
+int launch_anchored_bits(const AnchorArgs &a, int64_t ntiles, int lds, void *stream, const Multi &m)
+{
+    if (ntiles <= 0) return 0;
+    if (ntiles > 0x7fffffffLL || a.depth != 1 || a.ring_len != 0) return (int)hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_anchored_bits<kAnchorBitsW>), dim3((uint32_t)ntiles), dim3(256), lds, (hipStream_t)stream, a,
+                       m);
+    return (int)hipGetLastError();
+}
 
 int launch_group_bits(const GroupArgs &a, int64_t n_out, int lds, void *stream, const Multi &m, int64_t nb)
 {

@@ -319,6 +319,10 @@ int launch_group(int mode, int src_dt, int dst_dt, const GroupArgs &a, int64_t n
 int launch_anchored(int mode, int src_dt, int dst_dt, const AnchorArgs &a, int64_t ntiles, int lds_bytes, void *stream,
                     const Multi &m)
 {
+    if (src_dt == SND_DT_BITS) {
+        if (mode != SND_MODE_BINARY || dst_dt != SND_DT_BITS) return (int)hipErrorInvalidValue;
+        return launch_anchored_bits(a, ntiles, lds_bytes, stream, m);
+    }
     if (dst_dt == SND_DT_BITS) {
         if (mode != SND_MODE_BINARY || src_dt != SND_DT_U8) return (int)hipErrorInvalidValue;
         return launch_anchored_typed<SND_MODE_BINARY, uint8_t, bits_t>(a, ntiles, lds_bytes, (hipStream_t)stream, m);

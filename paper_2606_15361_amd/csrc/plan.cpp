@@ -88,7 +88,9 @@ int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
 
 bool valid_dtype_pair(int mode, int in_dt, int node_dt, int cap)
 {
-    if (mode == SND_MODE_BINARY) return in_dt == SND_DT_U8 && (node_dt == SND_DT_U8 || node_dt == SND_DT_BITS);
+    if (mode == SND_MODE_BINARY)
+        return (in_dt == SND_DT_U8 && (node_dt == SND_DT_U8 || node_dt == SND_DT_BITS)) ||
+               (in_dt == SND_DT_BITS && node_dt == SND_DT_BITS);
     if (mode == SND_MODE_GRADED)
         return in_dt == SND_DT_U8 && (node_dt == SND_DT_U16 || (node_dt == SND_DT_U8 && cap <= 255));
     if (mode == SND_MODE_FLOAT) {
@@ -288,7 +290,10 @@ bool build_anchored(const PlanImpl &p, Stage &S)
 {
     const Level &D = p.lev[S.dst_level];
     const int es = dtype_size(S.src_dtype);
-    if (S.depth > 8) return false;
+    const bool bits = S.src_dtype == SND_DT_BITS;
+    // bit input: leaf level only, tiles of kAnchorTileBits from 64-aligned row anchors
+    const int tile = bits ? kAnchorTileBits : kAnchorTile;
+    if (S.depth > (bits ? 1 : 8)) return false;
     std::vector<int32_t> nodes, tiles;
     int64_t lds_max = 0;
     for (int q = 0; q < D.nnodes; ++q) {
@@ -306,14 +311,16 @@ bool build_anchored(const PlanImpl &p, Stage &S)
             tlo = std::min<int64_t>(tlo, D.lo[r]);
             thi = std::max<int64_t>(thi, D.lo[r] + S.row_len[r]);
         }
-        const int64_t lds = (int64_t)(c1 - c0) * (kAnchorTile + rho_max) * es;
+        if (bits && tlo % 64 != 0) return false;
+        const int64_t lds = bits ? (int64_t)(c1 - c0) * anchor_bits_words(rho_max) * 4
+                                 : (int64_t)(c1 - c0) * (kAnchorTile + rho_max) * es;
         if (lds > kAnchorLdsBytes) return false;
         lds_max = std::max(lds_max, lds);
         const int32_t ni = (int32_t)(nodes.size() / 6);
         // last field: how far the node's rows reach past n_out, so that a run with fewer output
         // samples can skip the tiles it does not need
         nodes.insert(nodes.end(), {(int32_t)r0, (int32_t)r1, c0, c1, rho_max, (int32_t)(thi - p.n_out)});
-        for (int64_t t = tlo; t < thi; t += kAnchorTile) tiles.insert(tiles.end(), {ni, (int32_t)t});
+        for (int64_t t = tlo; t < thi; t += tile) tiles.insert(tiles.end(), {ni, (int32_t)t});
     }
     S.kernel = kKernelAnchored;
     S.lds_bytes = (int32_t)round_up(lds_max, 16);
@@ -346,6 +353,10 @@ snd_status build_plan(const snd_plan_desc &d, PlanImpl &p, std::string &err)
     if (d.mode == SND_MODE_GRADED && (d.cap < 1 || d.cap > 65535)) { err = "graded cap must be in 1..65535"; return SND_ERR_INVALID; }
     if (!valid_dtype_pair(d.mode, d.in_dtype, d.node_dtype, d.cap)) {
         err = "unsupported input/node dtype for this mode";
+        return SND_ERR_UNSUPPORTED;
+    }
+    if (d.in_dtype == SND_DT_BITS && (d.chunk > 0 || d.cluster > 15)) {
+        err = "bit input needs a plain (chunk = 0) plan and cluster <= 15";
         return SND_ERR_UNSUPPORTED;
     }
     p.desc = d;
@@ -693,7 +704,8 @@ snd_status build_plan(const snd_plan_desc &d, PlanImpl &p, std::string &err)
         I.stage_alg_bytes[si] = S.alg_bytes;
         I.stage_rows[si] = S.rows;
         I.stage_entries[si] = (int64_t)S.ent.size();
-        I.stage_kernel[si] = S.kernel == kKernelGroupLds && S.src_dtype == SND_DT_BITS ? 4
+        I.stage_kernel[si] = S.kernel == kKernelAnchored && S.src_dtype == SND_DT_BITS ? 5
+                             : S.kernel == kKernelGroupLds && S.src_dtype == SND_DT_BITS ? 4
                              : (S.kernel == kKernelGroupLds && S.group_f1 > 0) ? 3
                                                                                 : S.kernel;
         if (S.kernel == kKernelGroupLds) {

@@ -108,6 +108,11 @@ constexpr int kGroupMaxSpan = 256;   // offset spread of one staged window (wind
 constexpr int kGroupSlotsPerWave = 8;  // staged windows per wave per batch
 constexpr int kAnchorTile = 512;     // reference samples per anchored workgroup
 constexpr int kAnchorLdsBytes = 65536;
+constexpr int kAnchorBitsW = 4;                         // bit input: words per lane
+constexpr int kAnchorTileBits = 64 * 32 * kAnchorBitsW;  // bit input: samples per workgroup
+// words of one staged channel window on bit input: the tile, the largest offset, one more word
+// for the funnel shift
+inline int64_t anchor_bits_words(int32_t rho_max) { return 64 * kAnchorBitsW + (rho_max >> 5) + 1; }
 
 struct Level {
     int nnodes = 0;
@@ -243,6 +248,8 @@ int launch_anchored(int mode, int src_dtype, int dst_dtype, const AnchorArgs &a,
                     void *stream, const Multi &m = Multi{nullptr, nullptr, 0});
 int launch_encode(const float *z, int64_t z_pitch, int time_major, int nchan, int64_t nsamp, const float *thr,
                   int nthr, uint8_t *out, int64_t out_pitch, void *stream);
+int launch_encode_bits(const float *z, int64_t z_pitch, int time_major, int nchan, int64_t nsamp, float thr,
+                       uint32_t *out, int64_t out_words, void *stream);
 int launch_cast(const float *src, int64_t src_pitch, int64_t rows, int64_t cols, void *dst, int64_t dst_pitch,
                 int dst_dtype, void *stream);
 

@@ -83,6 +83,7 @@ extern "C" {
 snd_status snd_stream_history_bytes(snd_plan plan, int64_t *bytes)
 {
     if (!plan || !bytes) return fail(SND_ERR_INVALID, "null plan or output");
+    if (plan->impl.desc.in_dtype == SND_DT_BITS) return fail(SND_ERR_UNSUPPORTED, "bit input is not streamed");
     *bytes = ring_shape(plan->impl).bytes;
     return SND_OK;
 }
@@ -111,6 +112,7 @@ snd_status snd_stream_admit(snd_stream s, int32_t beam_id, snd_plan plan, void *
     if (beam_id < 0) return fail(SND_ERR_INVALID, "beam id must be >= 0");
     if (s->beams.count(beam_id)) return fail(SND_ERR_INVALID, "beam already admitted");
     const snd::PlanImpl &P = plan->impl;
+    if (P.desc.in_dtype == SND_DT_BITS) return fail(SND_ERR_UNSUPPORTED, "bit input is not streamed");
     if (P.stages.empty() || P.stages[0].kernel != snd::kKernelAnchored || P.stages[0].final_stage)
         return fail(SND_ERR_UNSUPPORTED,
                     "streaming needs a plan whose first stage is the input-anchored kernel (default schedule)");

@@ -16,9 +16,20 @@ DTYPE_NAMES = {v: k for k, v in DTYPES.items()}
 
 
 def torch_dtype(dt: int):
+    """Tensor dtype holding rows of this storage type (bit rows: int32 words)."""
     import torch
     return {capi.DT_U8: torch.uint8, capi.DT_U16: torch.uint16, capi.DT_F32: torch.float32,
-            capi.DT_BF16: torch.bfloat16, capi.DT_F16: torch.float16}[dt]
+            capi.DT_BF16: torch.bfloat16, capi.DT_F16: torch.float16, capi.DT_BITS: torch.int32}[dt]
+
+
+def row_pitch(x, dtype: str) -> int:
+    """Row pitch of tensor x in elements of the storage type (bit rows: in bits)."""
+    return x.stride(0) * 32 if dtype == "bits" else x.stride(0)
+
+
+def row_samples(x, dtype: str) -> int:
+    """Samples a row of tensor x can hold."""
+    return x.shape[1] * 32 if dtype == "bits" else x.shape[1]
 
 
 def _stream_handle(stream, device):
@@ -56,12 +67,14 @@ def make_desc(freqs, dms, tsamp_s, nsamp, *, mode="float", branching=4, cluster=
     return d, freq, dm, in_dtype, node_dtype
 
 
-def autotune(freqs, dms, tsamp_s, x, candidates, *, reps=2, out=None, stream=None, **plan_kw):
-    """Time every (stage_levels, chunk) candidate on the block x [nchan][nsamp] with snd_autotune.
+def autotune(freqs, dms, tsamp_s, x, candidates, *, reps=2, out=None, stream=None, nsamp=None, **plan_kw):
+    """Time every (stage_levels, chunk) candidate on the block x [nchan][nsamp] with snd_autotune
+    (nsamp defaults to the samples a row of x holds).
     Returns (index of the fastest, [dict(stage_levels, chunk, ms, workspace_bytes, table_bytes)]).
     Buffers are sized for the largest candidate that is probed host-side first."""
     import torch
-    nsamp = x.shape[1]
+    in_dt = plan_kw.get("in_dtype") or ""
+    nsamp = int(nsamp or row_samples(x, in_dt))
     probes = [Plan(freqs, dms, tsamp_s, None if c else nsamp, stage_levels=s, chunk=c, **plan_kw)
               for s, c in candidates]
     wsb = max(p.info["workspace_bytes"] for p in probes)
@@ -78,7 +91,7 @@ def autotune(freqs, dms, tsamp_s, x, candidates, *, reps=2, out=None, stream=Non
     for i, (s, c) in enumerate(candidates):
         arr[i].stage_levels, arr[i].chunk = int(s), int(c)
     best = C.c_int32()
-    capi.check(capi.lib().snd_autotune(C.byref(d), arr, len(candidates), C.c_void_p(x.data_ptr()), x.stride(0),
+    capi.check(capi.lib().snd_autotune(C.byref(d), arr, len(candidates), C.c_void_p(x.data_ptr()), row_pitch(x, in_dt),
                                        C.c_void_p(out.data_ptr()), out.stride(0), C.c_void_p(ws.data_ptr()),
                                        ws.numel(), C.c_void_p(tables.data_ptr()), tables.numel(), int(reps),
                                        C.byref(best), _stream_handle(stream, dev)))
@@ -126,7 +139,7 @@ class Plan:
             workspace_bytes=info.workspace_bytes, alg_bytes=info.alg_bytes,
             stage_alg_bytes=list(info.stage_alg_bytes[:ns]), stage_rows=list(info.stage_rows[:ns]),
             stage_entries=list(info.stage_entries[:ns]), build_seconds=info.build_seconds,
-            stage_kernel=[("generic", "group_lds", "anchored", "group_fast", "group_bits")[k]
+            stage_kernel=[("generic", "group_lds", "anchored", "group_fast", "group_bits", "anchored_bits")[k]
                           for k in info.stage_kernel[:ns]],
             stage_staged=list(info.stage_staged[:ns]), stage_batches=list(info.stage_batches[:ns]),
             stage_windows=list(info.stage_windows[:ns]),
@@ -183,8 +196,8 @@ class Plan:
         import torch
         if self._tables is None:
             self.upload(x.device, stream)
-        if x.dim() != 2 or x.shape[0] != self.nchan or x.shape[1] < self.nsamp or x.stride(1) != 1:
-            raise ValueError(f"input must be [{self.nchan}][>= {self.nsamp}] with unit time stride")
+        if x.dim() != 2 or x.shape[0] != self.nchan or row_samples(x, self.in_dtype) < self.nsamp or x.stride(1) != 1:
+            raise ValueError(f"input must be [{self.nchan}][>= {self.nsamp} samples] with unit time stride")
         want = torch_dtype(DTYPES[self.in_dtype])
         if x.dtype != want:
             raise TypeError(f"input dtype {x.dtype}, plan expects {want}")
@@ -194,7 +207,7 @@ class Plan:
                 or out.dtype != self.out_dtype:
             raise ValueError("bad output tensor")
         ws = self.workspace(x.device) if workspace is None else workspace
-        args = (C.c_void_p(x.data_ptr()), x.stride(0), C.c_void_p(out.data_ptr()), out.stride(0),
+        args = (C.c_void_p(x.data_ptr()), row_pitch(x, self.in_dtype), C.c_void_p(out.data_ptr()), out.stride(0),
                 C.c_void_p(ws.data_ptr()), ws.numel(), _stream_handle(stream, x.device))
         if stage is None:
             capi.check(capi.lib().snd_execute(self._h, *args))
@@ -215,6 +228,23 @@ def encode(z, thresholds, time_major: bool = False, out=None, stream=None):
     capi.check(capi.lib().snd_encode(C.c_void_p(z.data_ptr()), z.stride(0), int(time_major), nchan, nsamp,
                                      th.ctypes.data_as(C.c_void_p), th.size, C.c_void_p(out.data_ptr()),
                                      out.stride(0), _stream_handle(stream, z.device)))
+    return out
+
+
+def encode_bits(z, threshold: float, time_major: bool = False, out=None, stream=None):
+    """Delta encoder to bit rows on the GPU: bit i of word w of channel c = 1[z_c(32 w + i) > threshold].
+    Returns int32 [nchan][words], words a multiple of 4 (row pitch a multiple of 128 bits)."""
+    import torch
+    if z.dtype != torch.float32 or z.stride(1) != 1:
+        raise TypeError("z must be float32 with unit inner stride")
+    nchan, nsamp = (z.shape[1], z.shape[0]) if time_major else (z.shape[0], z.shape[1])
+    if out is None:
+        out = torch.zeros((nchan, (nsamp + 127) // 128 * 4), dtype=torch.int32, device=z.device)
+    if out.dtype != torch.int32 or out.stride(1) != 1 or out.shape[0] != nchan or out.shape[1] * 32 < nsamp:
+        raise ValueError("out must be int32 [nchan][>= nsamp / 32] with unit inner stride")
+    capi.check(capi.lib().snd_encode_bits(C.c_void_p(z.data_ptr()), z.stride(0), int(time_major), nchan, nsamp,
+                                          float(threshold), C.c_void_p(out.data_ptr()), out.stride(0) * 32,
+                                          _stream_handle(stream, z.device)))
     return out
 
 

@@ -88,6 +88,11 @@ def test_plan_validation_errors(snd):
         (dict(node_dtype="f32"), _capi.ERR_UNSUPPORTED),
         (dict(cap=300, node_dtype="u8"), _capi.ERR_UNSUPPORTED),
         (dict(stage_levels=1 << 3), _capi.ERR_INVALID),
+        (dict(in_dtype="bits"), _capi.ERR_UNSUPPORTED),
+        (dict(mode="binary", in_dtype="bits", node_dtype="u8"), _capi.ERR_UNSUPPORTED),
+        (dict(mode="binary", in_dtype="bits", cluster=16), _capi.ERR_UNSUPPORTED),
+        (dict(mode="binary", in_dtype="bits", stage_levels=0x80000000), _capi.ERR_UNSUPPORTED),
+        (dict(mode="binary", in_dtype="bits", generic_kernels=True), _capi.ERR_UNSUPPORTED),
     ]
     for kw, code in bad:
         args = dict(ok)
@@ -97,6 +102,30 @@ def test_plan_validation_errors(snd):
         with pytest.raises(SndError) as ei:
             snd.Plan(f, dd, 0.138e-3, ns, **args)
         assert ei.value.status == code, kw
+
+
+def test_bit_input_plans(snd):
+    """Bit input: leaf stage on bit rows, bit-row final stage, not streamed."""
+    from paper_2606_15361_amd import SndError, _capi
+    f = synth.channel_freqs(64)
+    dms = synth.dm_linear(40, 0, 60)
+    p = snd.Plan(f, dms, 0.138e-3, 2000, mode="binary", branching=4, in_dtype="bits")
+    assert p.info["stage_kernel"] == ["anchored_bits", "group_bits"]
+    assert p.info["stage_src_dtype"] == ["bits", "bits"]
+    u = snd.Plan(f, dms, 0.138e-3, 2000, mode="binary", branching=4)
+    # same tree; the input read is 1/8 of the byte input's
+    assert p.info["n_neurons"] == u.info["n_neurons"] and p.info["stage_entries"] == u.info["stage_entries"]
+    assert u.info["stage_alg_bytes"][0] - p.info["stage_alg_bytes"][0] == 64 * 2000 - 64 * 2000 // 8
+    nb = C.c_int64()
+    assert _capi.lib().snd_stream_history_bytes(p.handle, C.byref(nb)) == _capi.ERR_UNSUPPORTED
+    with pytest.raises(SndError) as ei:
+        snd.Plan(f, dms, 0.138e-3, None, mode="binary", branching=4, in_dtype="bits", chunk=512)
+    assert ei.value.status == _capi.ERR_UNSUPPORTED
+    # bit input pitch must be whole words; encoder pitch likewise
+    buf = (C.c_uint8 * 256)()
+    rc = _capi.lib().snd_encode_bits(C.cast(buf, C.c_void_p), 100, 0, 1, 100, C.c_float(1.0),
+                                     C.cast(buf, C.c_void_p), 112, None)
+    assert rc == _capi.ERR_INVALID
 
 
 def test_stage_variants_are_consistent_plans(snd):

@@ -53,6 +53,17 @@ def gpu_run(plan, x, stage_by_stage=False):
     return to_np(y)
 
 
+def pack_bits(x):
+    """Spike rows [nchan][nsamp] (non-zero = spike) as bit rows: int32 [nchan][words], bit i
+    of word w = sample 32 w + i, words a multiple of 4."""
+    nchan, nsamp = x.shape
+    nw = (nsamp + 127) // 128 * 4
+    b = np.packbits(np.asarray(x) != 0, axis=1, bitorder="little")
+    out = np.zeros((nchan, nw * 4), dtype=np.uint8)
+    out[:, : b.shape[1]] = b
+    return out.view("<u4").view(np.int32)
+
+
 def rel_rms(a, b):
     return float(np.sqrt(np.mean((a - b) ** 2)) / max(np.sqrt(np.mean(b ** 2)), 1e-300))
 
@@ -107,6 +118,20 @@ def test_parity_small(snd, orc, nchan, C_, B, mode, kw):
         else:
             assert np.array_equal(y, want.astype(y.dtype))
         ys.append(y)
+    if mode == "binary":
+        # bit input (rows of bits straight from the encoder) where the tree takes bit rows
+        try:
+            pb = snd.Plan(f, dms, 0.138e-3, nsamp, mode=mode, cluster=C_, branching=B, in_dtype="bits", **kw)
+        except snd.SndError as e:
+            assert e.status == -2 and snd.Plan(f, dms, 0.138e-3, nsamp, mode=mode, cluster=C_, branching=B,
+                                              **kw).node_dtype == "u8"
+        else:
+            _say(f"case nchan={nchan} C={C_} B={B} mode={mode} {kw} bit input")
+            if nlev > 1:
+                assert pb.info["stage_kernel"] == ["anchored_bits", "group_bits"], pb.info["stage_kernel"]
+            y = gpu_run(pb, pack_bits(x), stage_by_stage=True)
+            assert np.array_equal(y, want.astype(y.dtype))
+            ys.append(y)
     for y in ys[1:]:
         assert np.array_equal(y, ys[0])  # identical whatever levels are materialised
 
@@ -135,6 +160,18 @@ def test_encoder_parity(snd, orc):
         assert np.array_equal(a, want) and np.array_equal(b, want)
 
 
+def test_encoder_bits_parity(snd, orc):
+    spec = synth.workload(1)
+    z = spec.filterbank()
+    zt = torch.from_numpy(z).cuda()
+    for thr, n in ((2.0, z.shape[1]), (0.75, z.shape[1]), (1.0, 1000), (1.5, 1)):
+        _say(f"encode_bits threshold={thr} nsamp={n}")
+        want = pack_bits(orc.encode(z[:, :n], [thr]))
+        a = snd.encode_bits(zt[:, :n], thr).cpu().numpy()
+        b = snd.encode_bits(zt[:, :n].t().contiguous(), thr, time_major=True).cpu().numpy()
+        assert np.array_equal(a, want) and np.array_equal(b, want)
+
+
 @pytest.mark.parametrize("kl,ki", [(2, 2), (2, 1)])
 def test_config1_binary_exact(snd, orc, kl, ki):
     spec = synth.workload(1)
@@ -150,6 +187,14 @@ def test_config1_binary_exact(snd, orc, kl, ki):
                   node_dtype="u8")
     assert pb.info["stage_kernel"] == ["anchored", "group_fast"]
     assert np.array_equal(gpu_run(pb, x), want.astype(np.uint8))
+    if len(spec.enc_thresholds) == 1:  # bit input from the bit encoder
+        xb = snd.encode_bits(torch.from_numpy(z).cuda(), spec.enc_thresholds[0])
+        pi = snd.Plan(spec.freqs, spec.dms, spec.tsamp_s, spec.nsamp, mode="binary", branching=2, k_leaf=kl,
+                      k_int=ki, in_dtype="bits")
+        assert pi.info["stage_kernel"] == ["anchored_bits", "group_bits"]
+        y = pi.execute(xb)
+        torch.cuda.synchronize()
+        assert np.array_equal(to_np(y), want.astype(np.uint8))
 
 
 @pytest.mark.parametrize("B", [2, 4, 8])
@@ -241,7 +286,7 @@ def test_determinism(snd):
     assert np.array_equal(a, b)
 
 
-@pytest.mark.parametrize("mode", ["float", "graded", "binary"])
+@pytest.mark.parametrize("mode", ["float", "graded", "binary", "binary-bits"])
 def test_config2_full_size_sampled(snd, orc, mode):
     # The benchmarked workload (1024 ch, 4096 DM, 2^17 samples, B = 4) at full size, checked
     # on sampled outputs against the oracle's per-point recursion.
@@ -250,14 +295,20 @@ def test_config2_full_size_sampled(snd, orc, mode):
     z = spec.filterbank()
     d = orc.delays(spec.freqs, spec.dms, spec.tsamp_s)
     zt = torch.from_numpy(z).cuda()
+    bit_input = mode == "binary-bits"
+    mode = "binary" if bit_input else mode
     if mode == "float":
         x, xin = z, zt
     else:
         xin = snd.encode(zt, [1.0, 2.0, 3.0, 4.0] if mode == "graded" else [2.0])
         x = to_np(xin)
-    p = snd.Plan(spec.freqs, spec.dms, spec.tsamp_s, spec.nsamp, mode=mode, branching=4)
+    if bit_input:
+        xin = snd.encode_bits(zt, 2.0)
+        assert np.array_equal(xin[:, :64].cpu().numpy(), pack_bits(x[:, :2048]))
+    p = snd.Plan(spec.freqs, spec.dms, spec.tsamp_s, spec.nsamp, mode=mode, branching=4,
+                 in_dtype="bits" if bit_input else None)
     if mode == "binary":
-        assert p.info["stage_kernel"] == ["anchored", "group_bits"]
+        assert p.info["stage_kernel"] == ["anchored_bits" if bit_input else "anchored", "group_bits"]
     _say(f"config2 mode={mode}: executing on the GPU")
     y = p.execute(xin)
     torch.cuda.synchronize()
