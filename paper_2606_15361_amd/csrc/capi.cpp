@@ -209,6 +209,7 @@ Prepared prepare_stage(const PlanImpl &P, size_t si, const Run &run, const void 
         g.scale = scale;
         g.n_run = (int32_t)run.n_run;
         g.len_cut = len_cut;
+        g.tile = S.anchor_tile;
         pr.shape = stage_shape(S);
         pr.nblocks = S.ntiles;
         return pr;

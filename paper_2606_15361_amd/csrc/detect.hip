@@ -23,11 +23,48 @@
 namespace snd {
 namespace {
 
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+template <typename T> using global_ptr = __attribute__((address_space(1))) T *;
+template <typename T> __device__ inline global_ptr<const T> as_global(const T *p) { return (global_ptr<const T>)p; }
+
 constexpr int kSnrTile = 4096;
 constexpr int kThreads = 256;
 
 template <typename T> struct IsInt { static constexpr bool value = true; };
 template <> struct IsInt<float> { static constexpr bool value = false; };
+
+// Row sums with 16-byte loads: a scalar head up to the first 16-byte boundary of the row, then
+// 16-byte vectors (four in flight per thread), then a scalar tail.  f(x, j) folds one sample;
+// j is its place in a vector (0 for the scalar head and tail), for independent accumulators.
+template <typename T, typename F>
+__device__ inline void row_fold(const T *row, int64_t n, int tid, F &&f)
+{
+    constexpr int E = 16 / (int)sizeof(T);  // samples per vector
+    int64_t head = (int64_t)(((16u - ((uint32_t)(uintptr_t)row & 15u)) & 15u) / sizeof(T));
+    if (((uintptr_t)row % sizeof(T)) != 0 || head > n) head = n;  // misaligned element type: all scalar
+    if (tid < head) f(row[tid], 0);
+    const int64_t nv = (n - head) / E;
+    const auto vec = as_global(reinterpret_cast<const u32x4 *>(row + head));
+    int64_t i = tid;
+    for (; i + 3 * kThreads < nv; i += 4 * kThreads) {
+        u32x4 q[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) q[u] = vec[i + u * kThreads];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const T *e = reinterpret_cast<const T *>(&q[u]);
+#pragma unroll
+            for (int j = 0; j < E; ++j) f(e[j], j);
+        }
+    }
+    for (; i < nv; i += kThreads) {
+        const u32x4 q = vec[i];
+        const T *e = reinterpret_cast<const T *>(&q);
+#pragma unroll
+        for (int j = 0; j < E; ++j) f(e[j], j);
+    }
+    for (int64_t t = head + nv * E + tid; t < n; t += kThreads) f(row[t], 0);
+}
 
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_rowstats(const T *plane, int64_t pitch, int64_t n, double sigma_min,
@@ -38,12 +75,13 @@ __global__ __launch_bounds__(kThreads) void k_rowstats(const T *plane, int64_t p
     const int tid = threadIdx.x;
     if constexpr (IsInt<T>::value) {
         __shared__ unsigned long long s1[kThreads], s2[kThreads];
+        // per-thread sums stay exact in 64 bits (at most n / kThreads + 1 samples of < 2^16 each)
         unsigned long long a = 0, b = 0;
-        for (int64_t t = tid; t < n; t += kThreads) {
-            unsigned long long v = (unsigned long long)row[t];
+        row_fold(row, n, tid, [&](T x, int) {
+            const unsigned long long v = (unsigned long long)x;
             a += v;
             b += v * v;
-        }
+        });
         s1[tid] = a;
         s2[tid] = b;
         __syncthreads();
@@ -66,17 +104,22 @@ __global__ __launch_bounds__(kThreads) void k_rowstats(const T *plane, int64_t p
     } else {
         // one pass in FP64 about a shift c (the row's first sample), so that a large mean does
         // not cancel: mu = c + S1 / n, sigma^2 = S2 / n - (S1 / n)^2 with S1, S2 the sums of
-        // (y - c) and (y - c)^2
+        // (y - c) and (y - c)^2; two accumulator pairs keep the FP64 adds independent
         __shared__ double r1[kThreads], r2[kThreads];
         const double c = (double)row[0];
-        double a = 0.0, b = 0.0;
-        for (int64_t t = tid; t < n; t += kThreads) {
-            const double d = (double)row[t] - c;
-            a += d;
-            b += d * d;
-        }
-        r1[tid] = a;
-        r2[tid] = b;
+        double a0 = 0.0, b0 = 0.0, a1 = 0.0, b1 = 0.0;
+        row_fold(row, n, tid, [&](T x, int j) {
+            const double d = (double)x - c;
+            if (j & 1) {
+                a1 += d;
+                b1 += d * d;
+            } else {
+                a0 += d;
+                b0 += d * d;
+            }
+        });
+        r1[tid] = a0 + a1;
+        r2[tid] = b0 + b1;
         __syncthreads();
         for (int s = kThreads / 2; s > 0; s >>= 1) {
             if (tid < s) {

@@ -141,7 +141,7 @@ __global__ __launch_bounds__(1024) void k_group_fast(GroupArgs s0, Multi m)
 #pragma unroll
     for (int q = 0; q < R; ++q) {
         if (row[q] < 0) continue;
-        TO *dst = static_cast<TO *>(s.dst) + (int64_t)row[q] * s.dst_pitch + t0 + lane;
+        const auto dst = as_global(static_cast<TO *>(s.dst)) + (int64_t)row[q] * s.dst_pitch + t0 + lane;
 #pragma unroll
         for (int v = 0; v < V; ++v)
             if (lane + 64 * v < vt) {

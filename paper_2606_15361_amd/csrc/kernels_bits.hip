@@ -181,7 +181,7 @@ __global__ __launch_bounds__(1024) void k_group_bits(GroupArgs s0, Multi m)
 #pragma unroll
     for (int q = 0; q < R; ++q) {
         if (row[q] < 0) continue;
-        uint8_t *dst = static_cast<uint8_t *>(s.dst) + (int64_t)row[q] * s.dst_pitch + t0 + 32 * lane;
+        const auto dst = as_global(static_cast<uint8_t *>(s.dst)) + (int64_t)row[q] * s.dst_pitch + t0 + 32 * lane;
         const int nv = vt - 32 * lane;  // valid samples of this lane
         if (nv >= 32 && ((uintptr_t)dst & 3u) == 0) {
             uint32_t wds[8];
@@ -190,7 +190,7 @@ __global__ __launch_bounds__(1024) void k_group_bits(GroupArgs s0, Multi m)
                 const uint32_t nib = (out[q] >> (4 * k)) & 0xfu;
                 wds[k] = (nib & 1u) | ((nib & 2u) << 7) | ((nib & 4u) << 14) | ((nib & 8u) << 21);
             }
-            uint32_t *d32 = reinterpret_cast<uint32_t *>(dst);
+            const auto d32 = reinterpret_cast<global_ptr<uint32_t>>(dst);
 #pragma unroll
             for (int k = 0; k < 8; ++k) d32[k] = wds[k];
         } else {
@@ -216,13 +216,19 @@ __global__ __launch_bounds__(256) void k_anchored_bits(AnchorArgs s0, Multi m)
     uint32_t *lds = reinterpret_cast<uint32_t *>(smem);
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int node = s.tiles[2 * bid];
-    const int tau0 = s.tiles[2 * bid + 1];
-    const int *nd = s.nodes + 6 * node;
-    const int r0 = nd[0], r1 = nd[1], c0 = nd[2], c1 = nd[3], rho_max = nd[4];
+    // every table value below is uniform: scalar loads through the constant address space
+    const int node = __builtin_amdgcn_readfirstlane(as_const(s.tiles)[2 * bid]);
+    const int tau0 = __builtin_amdgcn_readfirstlane(as_const(s.tiles)[2 * bid + 1]);
+    const_ptr<int32_t> nd = as_const(s.nodes) + 6 * node;
+    const int r0 = __builtin_amdgcn_readfirstlane(nd[0]), r1 = __builtin_amdgcn_readfirstlane(nd[1]);
+    const int c0 = __builtin_amdgcn_readfirstlane(nd[2]), c1 = __builtin_amdgcn_readfirstlane(nd[3]);
+    const int rho_max = __builtin_amdgcn_readfirstlane(nd[4]);
     if (tau0 >= nd[5] + s.n_run) return;  // past every row of the node in this run (uniform per block)
+    const_ptr<int32_t> row_lo = as_const(s.row_lo), row_len = as_const(s.row_len);
+    const_ptr<uint32_t> row_ptr = as_const(s.row_ptr);
+    const_ptr<uint32_t> ent = as_const(reinterpret_cast<const uint32_t *>(s.ent));  // (rowc, off) word pairs
     const int nw = 64 * W + (rho_max >> 5) + 1;  // staged words per channel
-    const uint32_t *src = static_cast<const uint32_t *>(s.src);
+    const auto src = as_global(static_cast<const uint32_t *>(s.src));
     const int64_t wp = s.src_pitch >> 5;  // words per input row
     const int64_t w0 = tau0 >> 5;         // first staged word
     const int ntot = (c1 - c0) * nw;
@@ -239,7 +245,7 @@ __global__ __launch_bounds__(256) void k_anchored_bits(AnchorArgs s0, Multi m)
     }
     __syncthreads();
     for (int r = r0 + wave; r < r1; r += 4) {
-        const int lo = s.row_lo[r], len = s.row_len[r] - s.len_cut;
+        const int lo = row_lo[r], len = row_len[r] - s.len_cut;
         const int i0 = tau0 - lo;  // output index at the window start (a multiple of 64)
         if (i0 >= len || i0 + T <= 0) continue;
         uint32_t cnt[W][kPlanes];
@@ -247,16 +253,15 @@ __global__ __launch_bounds__(256) void k_anchored_bits(AnchorArgs s0, Multi m)
         for (int u = 0; u < W; ++u)
 #pragma unroll
             for (int i = 0; i < kPlanes; ++i) cnt[u][i] = 0u;
-        const uint32_t eb = s.row_ptr[r], ee = s.row_ptr[r + 1];
+        const uint32_t eb = row_ptr[r], ee = row_ptr[r + 1];
         for (uint32_t e = eb; e < ee; ++e) {
-            const Entry en = s.ent[e];
-            const int rho = en.off - lo;
-            const uint32_t *p = lds + ((int)(en.rowc & kRowMask) - c0) * nw + (rho >> 5) + lane;
+            const int rho = (int32_t)ent[2 * e + 1] - lo;
+            const uint32_t *p = lds + ((int)(ent[2 * e] & kRowMask) - c0) * nw + (rho >> 5) + lane;
             const uint32_t sh = (uint32_t)rho & 31u;
 #pragma unroll
             for (int u = 0; u < W; ++u) bs_add(cnt[u], __builtin_amdgcn_alignbit(p[64 * u + 1], p[64 * u], sh));
         }
-        uint32_t *rowp = static_cast<uint32_t *>(s.dst) + (int64_t)r * (s.dst_pitch >> 5);
+        const auto rowp = as_global(static_cast<uint32_t *>(s.dst)) + (int64_t)r * (s.dst_pitch >> 5);
 #pragma unroll
         for (int u = 0; u < W; ++u) {
             const int wi = (i0 >> 5) + lane + 64 * u;  // output word of the row

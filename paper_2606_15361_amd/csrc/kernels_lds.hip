@@ -9,8 +9,8 @@
 // global memory straight into LDS (global_load_lds) two batches ahead into a ring of three
 // buffers, so every copy has two batches of sums to land and one barrier per batch suffices.
 //
-// k_anchored (first stage from the input): one 256-thread workgroup per (tree node, window of
-// kAnchorTile reference samples).  Every neuron row of a node is anchored at its own smallest
+// k_anchored (first stage from the input): one workgroup of kAnchorWaves waves per (tree node,
+// window of the stage's anchor tile of reference samples, in sub-tiles of kAnchorTile).  Every neuron row of a node is anchored at its own smallest
 // reference delay, so the neurons of one node read the node's channels at widely different
 // offsets; staging the node's channels over the absolute window once and producing the
 // overlapping segment of every neuron row reads each input sample once instead of once per
@@ -118,7 +118,7 @@ __global__ __launch_bounds__(1024) void k_group(GroupArgs s0, Multi m)
         buf = buf == 2 ? 0 : buf + 1;
     }
     if (row >= 0) {
-        TO *dst = static_cast<TO *>(s.dst) + (int64_t)row * s.dst_pitch + t0 + lane;
+        const auto dst = as_global(static_cast<TO *>(s.dst)) + (int64_t)row * s.dst_pitch + t0 + lane;
 #pragma unroll
         for (int v = 0; v < V; ++v)
             if (lane + 64 * v < vt) {
@@ -129,114 +129,130 @@ __global__ __launch_bounds__(1024) void k_group(GroupArgs s0, Multi m)
 }
 
 template <int MODE, typename TI, typename TO, int MAXD>
-__global__ __launch_bounds__(256) void k_anchored(AnchorArgs s0, Multi m)
+__global__ __launch_bounds__(64 * kAnchorWaves) void k_anchored(AnchorArgs s0, Multi m)
 {
     using A = typename Acc<MODE>::type;
     AnchorArgs s;
     uint32_t bid, nblk;
     select_record(s0, m, s, bid, nblk);
-    constexpr int V = kAnchorTile / 64;
+    constexpr int ST = kAnchorTile;  // samples per sub-tile: V per lane
+    constexpr int V = ST / 64;
     constexpr int EU = 4;
+    constexpr int NT = 64 * kAnchorWaves;
     extern __shared__ __align__(16) unsigned char smem[];
     TI *lds = reinterpret_cast<TI *>(smem);
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int node = s.tiles[2 * bid];
-    const int tau0 = s.tiles[2 * bid + 1];
-    const int *nd = s.nodes + 6 * node;
-    const int r0 = nd[0], r1 = nd[1], c0 = nd[2], c1 = nd[3], rho_max = nd[4];
+    // every table value below is uniform: scalar loads through the constant address space
+    const int node = __builtin_amdgcn_readfirstlane(as_const(s.tiles)[2 * bid]);
+    const int tau0 = __builtin_amdgcn_readfirstlane(as_const(s.tiles)[2 * bid + 1]);
+    const_ptr<int32_t> nd = as_const(s.nodes) + 6 * node;
+    const int r0 = __builtin_amdgcn_readfirstlane(nd[0]), r1 = __builtin_amdgcn_readfirstlane(nd[1]);
+    const int c0 = __builtin_amdgcn_readfirstlane(nd[2]), c1 = __builtin_amdgcn_readfirstlane(nd[3]);
+    const int rho_max = __builtin_amdgcn_readfirstlane(nd[4]);
     if (tau0 >= nd[5] + s.n_run) return;  // past every row of the node in this run (uniform per block)
-    const int wst = kAnchorTile + rho_max;
-    const TI *src = static_cast<const TI *>(s.src);
+    const_ptr<int32_t> row_lo = as_const(s.row_lo), row_len = as_const(s.row_len);
+    const_ptr<uint32_t> row_ptr = as_const(s.row_ptr);
+    const_ptr<uint32_t> ent = as_const(reinterpret_cast<const uint32_t *>(s.ent));  // (rowc, off) word pairs
+    const int T = s.tile;  // a multiple of ST
+    const int wst = T + rho_max;
+    // staged as raw storage words of the element type
+    using RT = typename std::conditional<sizeof(TI) == 1, uint8_t,
+                                         typename std::conditional<sizeof(TI) == 2, uint16_t, uint32_t>::type>::type;
+    static_assert(sizeof(RT) == sizeof(TI), "element storage");
+    const auto src = as_global(static_cast<const RT *>(s.src));
     for (int c = c0; c < c1; ++c) {  // stage the node's channels over [tau0, tau0 + wst)
-        const TI *p = src + (int64_t)c * s.src_pitch;
-        TI *l = lds + (c - c0) * wst;
-        for (int j0 = 0; j0 < wst; j0 += 4 * 256) {
-            TI tmp[4];
+        const auto p = src + (int64_t)c * s.src_pitch;
+        RT *l = reinterpret_cast<RT *>(lds) + (c - c0) * wst;
+        for (int j0 = 0; j0 < wst; j0 += 4 * NT) {
+            RT tmp[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                const int j = j0 + tid + 256 * u;
+                const int j = j0 + tid + NT * u;
                 const int64_t idx = (int64_t)tau0 + j;
                 int64_t col = idx + s.ring_start;  // ring column of window sample idx
                 if (s.ring_len > 0 && col >= s.ring_len) col -= s.ring_len;
-                tmp[u] = (j < wst && idx < s.src_len) ? p[col] : Zero<TI>::get();
+                tmp[u] = (j < wst && idx < s.src_len) ? p[col] : (RT)0;
             }
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                const int j = j0 + tid + 256 * u;
+                const int j = j0 + tid + NT * u;
                 if (j < wst) l[j] = tmp[u];
             }
         }
     }
     __syncthreads();
-    for (int r = r0 + wave; r < r1; r += 4) {
-        const int lo = s.row_lo[r], len = s.row_len[r] - s.len_cut;
-        const int i0 = tau0 - lo;  // output index at the window start
-        if (i0 >= len || i0 + kAnchorTile <= 0) continue;
-        A acc[MAXD][V];
-        A out[V];
+    for (int r = r0 + wave; r < r1; r += kAnchorWaves) {
+        const int lo = row_lo[r], len = row_len[r] - s.len_cut;
+        const uint32_t eb = row_ptr[r], ee = row_ptr[r + 1];
+        for (int sub = 0; sub < T; sub += ST) {  // sub-tiles of the window: the row's table words stay cached
+            const int i0 = tau0 + sub - lo;  // output index at the sub-tile start
+            if (i0 >= len || i0 + ST <= 0) continue;
+            const TI *lsub = lds + sub - lo + lane;
+            A acc[MAXD][V];
+            A out[V];
 #pragma unroll
-        for (int j = 0; j < MAXD; ++j)
+            for (int j = 0; j < MAXD; ++j)
 #pragma unroll
-            for (int v = 0; v < V; ++v) acc[j][v] = 0;
+                for (int v = 0; v < V; ++v) acc[j][v] = 0;
 #pragma unroll
-        for (int v = 0; v < V; ++v) out[v] = 0;
-        const uint32_t eb = s.row_ptr[r], ee = s.row_ptr[r + 1];
-        uint32_t e0 = eb;
-        for (; e0 + EU <= ee; e0 += EU) {  // full chunks: table words, then LDS reads, then sums
-            Entry en[EU];
+            for (int v = 0; v < V; ++v) out[v] = 0;
+            uint32_t e0 = eb;
+            for (; e0 + EU <= ee; e0 += EU) {  // full chunks: table words, then LDS reads, then sums
+                Entry en[EU];
 #pragma unroll
-            for (int u = 0; u < EU; ++u) en[u] = s.ent[e0 + u];
-            A val[EU][V];
+                for (int u = 0; u < EU; ++u) en[u] = Entry{ent[2 * (e0 + u)], (int32_t)ent[2 * (e0 + u) + 1]};
+                A val[EU][V];
 #pragma unroll
-            for (int u = 0; u < EU; ++u) {
-                const TI *p = lds + ((int)(en[u].rowc & kRowMask) - c0) * wst + (en[u].off - lo) + lane;
+                for (int u = 0; u < EU; ++u) {
+                    const TI *p = lsub + ((int)(en[u].rowc & kRowMask) - c0) * wst + en[u].off;
+#pragma unroll
+                    for (int v = 0; v < V; ++v) {
+                        A y = (A)Load<TI>::get(p + 64 * v);
+                        if constexpr (MODE == SND_MODE_BINARY) y = y != 0;
+                        val[u][v] = y;
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < EU; ++u) {
+#pragma unroll
+                    for (int v = 0; v < V; ++v) acc[0][v] += val[u][v];
+                    close_levels<MODE, A, MAXD, V>(acc, out, (int)(en[u].rowc >> 24), s.depth, 1, s.k_leaf, s.k_int,
+                                                   s.cap);
+                }
+            }
+            for (; e0 < ee; ++e0) {
+                const Entry en{ent[2 * e0], (int32_t)ent[2 * e0 + 1]};
+                const TI *p = lsub + ((int)(en.rowc & kRowMask) - c0) * wst + en.off;
 #pragma unroll
                 for (int v = 0; v < V; ++v) {
                     A y = (A)Load<TI>::get(p + 64 * v);
                     if constexpr (MODE == SND_MODE_BINARY) y = y != 0;
-                    val[u][v] = y;
+                    acc[0][v] += y;
                 }
+                close_levels<MODE, A, MAXD, V>(acc, out, (int)(en.rowc >> 24), s.depth, 1, s.k_leaf, s.k_int, s.cap);
             }
+            if constexpr (std::is_same<TO, bits_t>::value) {
+                // bit rows: i0 is a multiple of 64 (row anchors, tiles and sub-tiles are), so the
+                // 64 samples lane + 64 v of a wave are the two words (i0 + 64 v) / 32 and the next;
+                // samples outside the row are zero and words outside it are not written
+                const auto rowp = as_global(reinterpret_cast<uint32_t *>(s.dst)) + (int64_t)r * (s.dst_pitch / 32);
 #pragma unroll
-            for (int u = 0; u < EU; ++u) {
+                for (int v = 0; v < V; ++v) {
+                    const int i = i0 + lane + 64 * v;
+                    const uint64_t mask = __ballot(i >= 0 && i < len && out[v] != 0);
+                    const int w = ((i0 + 64 * v) >> 5) + (lane & 1);
+                    if (lane < 2 && w >= 0 && 32 * w < len) rowp[w] = lane ? (uint32_t)(mask >> 32) : (uint32_t)mask;
+                }
+            } else {
+                const auto dst = as_global(static_cast<TO *>(s.dst)) + (int64_t)r * s.dst_pitch + i0 + lane;
 #pragma unroll
-                for (int v = 0; v < V; ++v) acc[0][v] += val[u][v];
-                close_levels<MODE, A, MAXD, V>(acc, out, (int)(en[u].rowc >> 24), s.depth, 1, s.k_leaf, s.k_int,
-                                               s.cap);
-            }
-        }
-        for (; e0 < ee; ++e0) {
-            const Entry en = s.ent[e0];
-            const TI *p = lds + ((int)(en.rowc & kRowMask) - c0) * wst + (en.off - lo) + lane;
-#pragma unroll
-            for (int v = 0; v < V; ++v) {
-                A y = (A)Load<TI>::get(p + 64 * v);
-                if constexpr (MODE == SND_MODE_BINARY) y = y != 0;
-                acc[0][v] += y;
-            }
-            close_levels<MODE, A, MAXD, V>(acc, out, (int)(en.rowc >> 24), s.depth, 1, s.k_leaf, s.k_int, s.cap);
-        }
-        if constexpr (std::is_same<TO, bits_t>::value) {
-            // bit rows: i0 is a multiple of 64 (row anchors and tiles are), so the 64 samples
-            // lane + 64 v of a wave are the two words (i0 + 64 v) / 32 and the next; samples
-            // outside the row are zero and words outside it are not written
-            uint32_t *rowp = reinterpret_cast<uint32_t *>(s.dst) + (int64_t)r * (s.dst_pitch / 32);
-#pragma unroll
-            for (int v = 0; v < V; ++v) {
-                const int i = i0 + lane + 64 * v;
-                const uint64_t mask = __ballot(i >= 0 && i < len && out[v] != 0);
-                const int w = ((i0 + 64 * v) >> 5) + (lane & 1);
-                if (lane < 2 && w >= 0 && 32 * w < len) rowp[w] = lane ? (uint32_t)(mask >> 32) : (uint32_t)mask;
-            }
-        } else {
-            TO *dst = static_cast<TO *>(s.dst) + (int64_t)r * s.dst_pitch + i0 + lane;
-#pragma unroll
-            for (int v = 0; v < V; ++v) {
-                const int i = i0 + lane + 64 * v;
-                if (i >= 0 && i < len) {
-                    if constexpr (MODE == SND_MODE_FLOAT) Store<TO>::put(dst + 64 * v, out[v] * s.scale);
-                    else Store<TO>::put(dst + 64 * v, out[v]);
+                for (int v = 0; v < V; ++v) {
+                    const int i = i0 + lane + 64 * v;
+                    if (i >= 0 && i < len) {
+                        if constexpr (MODE == SND_MODE_FLOAT) Store<TO>::put(dst + 64 * v, out[v] * s.scale);
+                        else Store<TO>::put(dst + 64 * v, out[v]);
+                    }
                 }
             }
         }
@@ -264,7 +280,8 @@ int launch_anchored_typed(const AnchorArgs &a, int64_t ntiles, int lds, hipStrea
 {
     if (ntiles <= 0) return 0;
     if (ntiles > 0x7fffffffLL || a.depth > 8) return (int)hipErrorInvalidValue;
-    dim3 grid((uint32_t)ntiles), block(256);
+    if (a.tile < kAnchorTile || a.tile % kAnchorTile) return (int)hipErrorInvalidValue;
+    dim3 grid((uint32_t)ntiles), block(64 * kAnchorWaves);
     if (a.depth <= 1) hipLaunchKernelGGL((k_anchored<MODE, TI, TO, 1>), grid, block, lds, st, a, m);
     else if (a.depth <= 2) hipLaunchKernelGGL((k_anchored<MODE, TI, TO, 2>), grid, block, lds, st, a, m);
     else if (a.depth <= 4) hipLaunchKernelGGL((k_anchored<MODE, TI, TO, 4>), grid, block, lds, st, a, m);

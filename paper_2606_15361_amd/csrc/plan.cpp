@@ -282,46 +282,57 @@ bool build_group_lds(const PlanImpl &p, Stage &S, bool allow_fast)
     return true;
 }
 
-// First stage anchored on the input: one workgroup per (node, window of kAnchorTile reference
-// samples) stages the node's channels once and produces the overlapping segment of every
-// neuron row of that node.  Needs all entries of a node's rows to read that node's channels
-// and the node's staged window to fit the LDS budget.
+// First stage anchored on the input: one workgroup per (node, window of reference samples)
+// stages the node's channels once and produces the overlapping segment of every neuron row of
+// that node.  Needs all entries of a node's rows to read that node's channels and the node's
+// staged window to fit the LDS budget.  The window is the largest of 2048, 1024 or 512 samples
+// whose staging keeps four workgroups on a CU (512 only needs the hard LDS limit).
 bool build_anchored(const PlanImpl &p, Stage &S)
 {
     const Level &D = p.lev[S.dst_level];
     const int es = dtype_size(S.src_dtype);
     const bool bits = S.src_dtype == SND_DT_BITS;
-    // bit input: leaf level only, tiles of kAnchorTileBits from 64-aligned row anchors
-    const int tile = bits ? kAnchorTileBits : kAnchorTile;
     if (S.depth > (bits ? 1 : 8)) return false;
-    std::vector<int32_t> nodes, tiles;
-    int64_t lds_max = 0;
+    struct NodeSpan { int64_t r0, r1; int32_t c0, c1, rho_max; int64_t tlo, thi; };
+    std::vector<NodeSpan> ns;
+    int64_t worst = 0;  // largest (channels, rho_max) LDS footprint beyond the window itself
+    int64_t chan_max = 0;
     for (int q = 0; q < D.nnodes; ++q) {
-        const int64_t r0 = D.row_base[q], r1 = r0 + D.nneu[q];
-        const int32_t c0 = D.chlo[q], c1 = D.chhi[q];
-        int32_t rho_max = 0;
-        int64_t tlo = INT64_MAX, thi = INT64_MIN;
-        for (int64_t r = r0; r < r1; ++r) {
+        NodeSpan n{D.row_base[q], D.row_base[q] + D.nneu[q], D.chlo[q], D.chhi[q], 0, INT64_MAX, INT64_MIN};
+        for (int64_t r = n.r0; r < n.r1; ++r) {
             for (uint32_t e = S.row_ptr[r]; e < S.row_ptr[r + 1]; ++e) {
                 const int32_t c = (int32_t)(S.ent[e].rowc & kRowMask);
                 const int32_t rho = S.ent[e].off - D.lo[r];
-                if (c < c0 || c >= c1 || rho < 0) return false;
-                rho_max = std::max(rho_max, rho);
+                if (c < n.c0 || c >= n.c1 || rho < 0) return false;
+                n.rho_max = std::max(n.rho_max, rho);
             }
-            tlo = std::min<int64_t>(tlo, D.lo[r]);
-            thi = std::max<int64_t>(thi, D.lo[r] + S.row_len[r]);
+            n.tlo = std::min<int64_t>(n.tlo, D.lo[r]);
+            n.thi = std::max<int64_t>(n.thi, D.lo[r] + S.row_len[r]);
         }
-        if (bits && tlo % 64 != 0) return false;
-        const int64_t lds = bits ? (int64_t)(c1 - c0) * anchor_bits_words(rho_max) * 4
-                                 : (int64_t)(c1 - c0) * (kAnchorTile + rho_max) * es;
+        if (bits && n.tlo % 64 != 0) return false;
+        worst = std::max<int64_t>(worst, (int64_t)(n.c1 - n.c0) * n.rho_max);
+        chan_max = std::max<int64_t>(chan_max, n.c1 - n.c0);
+        ns.push_back(n);
+    }
+    // bit input: leaf level only, tiles of kAnchorTileBits from 64-aligned row anchors
+    int tile = bits ? kAnchorTileBits : kAnchorTile;
+    if (!bits)
+        for (int t = kAnchorMaxTile; t > kAnchorTile; t /= 2)
+            if ((chan_max * t + worst) * es <= kAnchorLdsTarget) { tile = t; break; }
+    std::vector<int32_t> nodes, tiles;
+    int64_t lds_max = 0;
+    for (const NodeSpan &n : ns) {
+        const int64_t lds = bits ? (int64_t)(n.c1 - n.c0) * anchor_bits_words(n.rho_max) * 4
+                                 : (int64_t)(n.c1 - n.c0) * (tile + n.rho_max) * es;
         if (lds > kAnchorLdsBytes) return false;
         lds_max = std::max(lds_max, lds);
         const int32_t ni = (int32_t)(nodes.size() / 6);
         // last field: how far the node's rows reach past n_out, so that a run with fewer output
         // samples can skip the tiles it does not need
-        nodes.insert(nodes.end(), {(int32_t)r0, (int32_t)r1, c0, c1, rho_max, (int32_t)(thi - p.n_out)});
-        for (int64_t t = tlo; t < thi; t += tile) tiles.insert(tiles.end(), {ni, (int32_t)t});
+        nodes.insert(nodes.end(), {(int32_t)n.r0, (int32_t)n.r1, n.c0, n.c1, n.rho_max, (int32_t)(n.thi - p.n_out)});
+        for (int64_t t = n.tlo; t < n.thi; t += tile) tiles.insert(tiles.end(), {ni, (int32_t)t});
     }
+    S.anchor_tile = tile;
     S.kernel = kKernelAnchored;
     S.lds_bytes = (int32_t)round_up(lds_max, 16);
     S.nodes = std::move(nodes);

@@ -68,11 +68,12 @@ struct Stage {
     int64_t off_grp_rows = 0, off_batch_ptr = 0, off_batches = 0, off_instrs = 0, off_ldsb = 0;
     int64_t off_node_closes = 0;
 
-    // kKernelAnchored: one workgroup per (node, window of kAnchorTile reference samples).
+    // kKernelAnchored: one workgroup per (node, window of anchor_tile reference samples).
     std::vector<int32_t> nodes;     // 6 ints per node: row begin, row end, channel begin, channel end, rho max,
                                     // reach of its rows past n_out
     std::vector<int32_t> tiles;     // 2 ints per workgroup: node index, window start
     std::vector<int32_t> row_lo;    // [rows]
+    int32_t anchor_tile = 0;        // reference samples per workgroup window
     int64_t off_nodes = 0, off_tiles = 0, off_row_lo = 0;
     int64_t ntiles = 0;
 };
@@ -106,8 +107,11 @@ inline bool group_fast_supported(int f1, int depth)
 }
 constexpr int kGroupMaxSpan = 256;   // offset spread of one staged window (window <= span + tile)
 constexpr int kGroupSlotsPerWave = 8;  // staged windows per wave per batch
-constexpr int kAnchorTile = 512;     // reference samples per anchored workgroup
+constexpr int kAnchorTile = 512;     // reference samples per anchored sub-tile (8 per lane)
+constexpr int kAnchorMaxTile = 2048;  // largest anchored window per workgroup
+constexpr int kAnchorWaves = 8;      // waves per anchored workgroup
 constexpr int kAnchorLdsBytes = 65536;
+constexpr int kAnchorLdsTarget = 40960;  // larger windows only while four workgroups fit a CU
 constexpr int kAnchorBitsW = 4;                         // bit input: words per lane
 constexpr int kAnchorTileBits = 64 * 32 * kAnchorBitsW;  // bit input: samples per workgroup
 // words of one staged channel window on bit input: the tile, the largest offset, one more word
@@ -243,6 +247,7 @@ struct AnchorArgs {
     float scale;
     int32_t n_run;    // output samples of this run (<= n_out)
     int32_t len_cut;  // n_out - n_run: samples dropped from the end of every row
+    int32_t tile;     // reference samples per workgroup window (a multiple of kAnchorTile)
 };
 int launch_anchored(int mode, int src_dtype, int dst_dtype, const AnchorArgs &a, int64_t ntiles, int lds_bytes,
                     void *stream, const Multi &m = Multi{nullptr, nullptr, 0});

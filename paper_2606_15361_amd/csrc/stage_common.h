@@ -16,6 +16,12 @@ namespace snd {
 // space so that wave-uniform reads become scalar loads (counted apart from vector memory).
 template <typename T> using const_ptr = const __attribute__((address_space(4))) T *;
 template <typename T> __device__ inline const_ptr<T> as_const(const T *p) { return (const_ptr<T>)p; }
+// Device-memory pointers as global-address-space pointers: loads and stores through them are
+// global_* instructions, which count on the vector-memory counter only (flat ones also count on
+// the LDS counter, so every LDS wait would wait for them too).
+template <typename T> using global_ptr = __attribute__((address_space(1))) T *;
+template <typename T> __device__ inline global_ptr<T> as_global(T *p) { return (global_ptr<T>)p; }
+template <typename T> __device__ inline global_ptr<const T> as_global(const T *p) { return (global_ptr<const T>)p; }
 
 struct bf16_t { uint16_t bits; };
 struct f16_t { _Float16 v; };
@@ -23,14 +29,15 @@ struct f16_t { _Float16 v; };
 // leaf stage and read word-wise by the bit-row final stage, never through Load / Store.
 struct bits_t { uint32_t w; };
 
+// Element access through any pointer type (generic, global or LDS).
 template <typename T> struct Load;
-template <> struct Load<uint8_t> { __device__ static int get(const uint8_t *p) { return *p; } };
-template <> struct Load<uint16_t> { __device__ static int get(const uint16_t *p) { return *p; } };
-template <> struct Load<float> { __device__ static float get(const float *p) { return *p; } };
+template <> struct Load<uint8_t> { template <typename P> __device__ static int get(P p) { return *p; } };
+template <> struct Load<uint16_t> { template <typename P> __device__ static int get(P p) { return *p; } };
+template <> struct Load<float> { template <typename P> __device__ static float get(P p) { return *p; } };
 template <> struct Load<bf16_t> {
-    __device__ static float get(const bf16_t *p) { return __uint_as_float((uint32_t)p->bits << 16); }
+    template <typename P> __device__ static float get(P p) { return __uint_as_float((uint32_t)p->bits << 16); }
 };
-template <> struct Load<f16_t> { __device__ static float get(const f16_t *p) { return (float)p->v; } };
+template <> struct Load<f16_t> { template <typename P> __device__ static float get(P p) { return (float)p->v; } };
 
 template <typename T> struct Zero { __device__ static T get() { return T{}; } };
 
@@ -44,19 +51,19 @@ __device__ inline uint16_t f32_to_bf16_rne(float f)
 
 template <typename T> struct Store;
 template <> struct Store<uint8_t> {
-    template <typename A> __device__ static void put(uint8_t *p, A v) { *p = (uint8_t)v; }
+    template <typename P, typename A> __device__ static void put(P p, A v) { *p = (uint8_t)v; }
 };
 template <> struct Store<uint16_t> {
-    template <typename A> __device__ static void put(uint16_t *p, A v) { *p = (uint16_t)v; }
+    template <typename P, typename A> __device__ static void put(P p, A v) { *p = (uint16_t)v; }
 };
 template <> struct Store<float> {
-    template <typename A> __device__ static void put(float *p, A v) { *p = (float)v; }
+    template <typename P, typename A> __device__ static void put(P p, A v) { *p = (float)v; }
 };
 template <> struct Store<bf16_t> {
-    template <typename A> __device__ static void put(bf16_t *p, A v) { p->bits = f32_to_bf16_rne((float)v); }
+    template <typename P, typename A> __device__ static void put(P p, A v) { p->bits = f32_to_bf16_rne((float)v); }
 };
 template <> struct Store<f16_t> {
-    template <typename A> __device__ static void put(f16_t *p, A v) { p->v = (_Float16)(float)v; }
+    template <typename P, typename A> __device__ static void put(P p, A v) { p->v = (_Float16)(float)v; }
 };
 
 template <int MODE> struct Acc { using type = int; };
