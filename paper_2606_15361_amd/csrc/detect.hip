@@ -11,8 +11,8 @@
 //   SNR(t, W) = (S_W(t) - mu W) / (sigma sqrt W), maximum over widths (first width on ties).
 //   Either the full S/N plane and width index are written, or the cells whose S/N reaches the
 //   threshold are appended to a global pixel list, each workgroup's cells as one segment in
-//   increasing t.  For the list, a bound from multiplying by the reciprocal of the denominator
-//   skips the cells far below the threshold; every cell that can reach it takes the exact
+//   increasing t.  For the list, a per-width bound on the boxcar sum (in the prefix type)
+//   skips the cells that cannot reach the threshold; every cell that can takes the exact
 //   quotient.
 #include <hip/hip_runtime.h>
 
@@ -152,7 +152,8 @@ __global__ __launch_bounds__(kThreads) void k_snr(const T *plane, int64_t pitch,
     __shared__ P wtot[kThreads / 64];
     __shared__ int slab_off[kSlabs][kThreads / 64];
     __shared__ unsigned int base_s;
-    __shared__ double muw[kMaxWidths], den[kMaxWidths], rden[kMaxWidths];  // per-row constants
+    __shared__ double muw[kMaxWidths], den[kMaxWidths];  // per-row constants
+    __shared__ P sthr[kMaxWidths];                       // per-row boxcar-sum bounds
     const int k = blockIdx.y;
     const int64_t t0 = (int64_t)blockIdx.x * kSnrTile;
     const T *row = plane + (int64_t)k * pitch + t0;
@@ -162,16 +163,57 @@ __global__ __launch_bounds__(kThreads) void k_snr(const T *plane, int64_t pitch,
     int64_t L64 = (int64_t)kSnrTile + wmax - 1;
     if (L64 > n - t0) L64 = n - t0;
     const int L = (int)L64;
-    const int per = (L + kThreads - 1) / kThreads;
+    // float tiles on a 16-byte boundary are read as 16-byte vectors: chunks of a multiple of
+    // four samples (at most kMaxPer, since kMaxPer is itself a multiple of four)
+    static_assert(kMaxPer % 4 == 0, "vector chunks");
+    const bool vec4 = !IsInt<T>::value && sizeof(T) == 4 && ((uintptr_t)row & 15u) == 0;
+    const int per = vec4 ? (L + 4 * kThreads - 1) / (4 * kThreads) * 4 : (L + kThreads - 1) / kThreads;
     const int beg = tid * per;
-    // prefix sums: per-thread chunk totals, wave scan, wave totals through LDS
+    // prefix sums: per-thread chunk totals, wave scan, wave totals through LDS.  Integer
+    // tiles are first read with coalesced loads into LDS (in the prefix array's storage, which
+    // is written only after the barrier below); float tiles are read in place (measured faster)
     P v[kMaxPer];
     P run = 0;
+    if constexpr (IsInt<T>::value) {
+        T *raw = reinterpret_cast<T *>(pre);
+        static_assert(sizeof(T) <= sizeof(P), "the staged tile fits the prefix array");
+        const auto grow = as_global(row);
+        for (int j = tid; j < L; j += kThreads) raw[j] = grow[j];
+        __syncthreads();
 #pragma unroll
-    for (int i = 0; i < kMaxPer; ++i) {
-        const int j = beg + i;
-        v[i] = (i < per && j < L) ? (P)row[j] : (P)0;
-        run += v[i];
+        for (int i = 0; i < kMaxPer; ++i) {
+            const int j = beg + i;
+            v[i] = (i < per && j < L) ? (P)raw[j] : (P)0;
+            run += v[i];
+        }
+    } else if (vec4) {
+        typedef float f32x4 __attribute__((ext_vector_type(4)));
+        const auto g4 = as_global(reinterpret_cast<const f32x4 *>(row));
+        const auto grow = as_global(row);
+#pragma unroll
+        for (int i = 0; i < kMaxPer; i += 4) {
+            const int j = beg + i;
+            if (i < per && j + 3 < L) {
+                const f32x4 q = g4[j >> 2];
+                v[i] = (P)q.x;
+                v[i + 1] = (P)q.y;
+                v[i + 2] = (P)q.z;
+                v[i + 3] = (P)q.w;
+            } else {
+#pragma unroll
+                for (int u = 0; u < 4; ++u) v[i + u] = (i < per && j + u < L) ? (P)grow[j + u] : (P)0;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) run += v[i + u];
+        }
+    } else {
+        const auto grow = as_global(row);
+#pragma unroll
+        for (int i = 0; i < kMaxPer; ++i) {
+            const int j = beg + i;
+            v[i] = (i < per && j < L) ? (P)grow[j] : (P)0;
+            run += v[i];
+        }
     }
     P inc = run;
 #pragma unroll
@@ -197,7 +239,17 @@ __global__ __launch_bounds__(kThreads) void k_snr(const T *plane, int64_t pitch,
     if (tid < a.nw) {
         muw[tid] = __dmul_rn(mu, (double)a.w[tid]);
         den[tid] = __dmul_rn(sg, a.sqrtw[tid]);
-        rden[tid] = sg > 0.0 ? 1.0 / den[tid] : 0.0;
+        // S/N >= Theta needs S >= mu W + Theta sigma sqrt W up to the rounding of the exact
+        // quotient (relative 1e-16); the bound takes a relative margin of 1e-9 below that
+        const double b = muw[tid] + a.threshold * den[tid];
+        const double thr = b - 1e-9 * (fabs(muw[tid]) + a.threshold * den[tid]);
+        if constexpr (IsInt<T>::value) {  // integer sums: the largest integer at or below the bound
+            sthr[tid] = thr <= -2147483648.0 ? (P)(-2147483647 - 1)
+                        : thr >= 2147483647.0 ? (P)2147483647
+                                              : (P)floor(thr);
+        } else {
+            sthr[tid] = thr;
+        }
     }
     __syncthreads();
     // the exact maximum over widths of sample i (first width on ties)
@@ -230,17 +282,16 @@ __global__ __launch_bounds__(kThreads) void k_snr(const T *plane, int64_t pitch,
         }
         return;
     }
-    // compaction: a cheap bound (multiplication by the reciprocal, within a few ulp of the
-    // quotient) rejects the cells far below the threshold; the rest take the exact quotient
-    const double lo = a.threshold * (1.0 - 1e-9);
+    // compaction: a cell can reach the threshold at width W only if its boxcar sum reaches
+    // the row's bound for W (one subtraction and one compare per width, in the prefix type);
+    // the cells that do take the exact quotient
     constexpr int RW = NW > 0 ? NW : 1;
-    double rmuw[RW], rrden[RW];
+    P rthr[RW];
     int rw[RW];
     if constexpr (NW > 0) {
 #pragma unroll
         for (int w = 0; w < NW; ++w) {
-            rmuw[w] = muw[w];
-            rrden[w] = rden[w];
+            rthr[w] = sthr[w];
             rw[w] = a.w[w];
         }
     }
@@ -257,23 +308,17 @@ __global__ __launch_bounds__(kThreads) void k_snr(const T *plane, int64_t pitch,
         const int64_t t = t0 + i;
         if (t >= n || !(sg > 0.0)) continue;
         const P p0 = pre[i];
-        double m = -1.0e300;
+        bool maybe = false;
         if (NW > 0 && interior) {
 #pragma unroll
-            for (int w = 0; w < RW; ++w) {
-                const double s = (double)(pre[i + rw[w]] - p0);
-                const double approx = (s - rmuw[w]) * rrden[w];
-                m = approx > m ? approx : m;
-            }
+            for (int w = 0; w < RW; ++w) maybe |= (P)(pre[i + rw[w]] - p0) >= rthr[w];
         } else {
             for (int w = 0; w < a.nw; ++w) {
                 if (t + a.w[w] > n) break;
-                const double s = (double)(pre[i + a.w[w]] - p0);
-                const double approx = (s - muw[w]) * rden[w];
-                m = approx > m ? approx : m;
+                maybe |= (P)(pre[i + a.w[w]] - p0) >= sthr[w];
             }
         }
-        if (m < lo) continue;
+        if (!maybe) continue;
         double best;
         int bi;
         exact(i, t, best, bi);

@@ -185,6 +185,51 @@ __global__ __launch_bounds__(64 * kAnchorWaves) void k_anchored(AnchorArgs s0, M
     for (int r = r0 + wave; r < r1; r += kAnchorWaves) {
         const int lo = row_lo[r], len = row_len[r] - s.len_cut;
         const uint32_t eb = row_ptr[r], ee = row_ptr[r + 1];
+        if constexpr (MAXD == 1 && !std::is_same<TO, bits_t>::value) if (ee - eb == (uint32_t)EU) {
+            // one-level rows of EU inputs (the leaf level of clusters of four channels): table
+            // words once per row, stores without per-sample tests inside the row
+            const TI *p[EU];
+#pragma unroll
+            for (int u = 0; u < EU; ++u)
+                p[u] = lds - lo + lane + ((int)(ent[2 * (eb + u)] & kRowMask) - c0) * wst + (int32_t)ent[2 * (eb + u) + 1];
+            for (int sub = 0; sub < T; sub += ST) {
+                const int i0 = tau0 + sub - lo;  // output index at the sub-tile start
+                if (i0 >= len || i0 + ST <= 0) continue;
+                A val[EU][V];
+#pragma unroll
+                for (int u = 0; u < EU; ++u)
+#pragma unroll
+                    for (int v = 0; v < V; ++v) {
+                        A y = (A)Load<TI>::get(p[u] + sub + 64 * v);
+                        if constexpr (MODE == SND_MODE_BINARY) y = y != 0;
+                        val[u][v] = y;
+                    }
+                A out[V];
+#pragma unroll
+                for (int v = 0; v < V; ++v) {
+                    A a = val[0][v];
+#pragma unroll
+                    for (int u = 1; u < EU; ++u) a += val[u][v];
+                    out[v] = activate<MODE>(a, 1, 1, s.k_leaf, s.k_int, s.cap);
+                }
+                const auto dst = as_global(static_cast<TO *>(s.dst)) + (int64_t)r * s.dst_pitch + i0 + lane;
+                if constexpr (MODE == SND_MODE_FLOAT) {
+#pragma unroll
+                    for (int v = 0; v < V; ++v) out[v] *= s.scale;
+                }
+                if (i0 >= 0 && i0 + ST <= len) {  // uniform: the whole sub-tile is inside the row
+#pragma unroll
+                    for (int v = 0; v < V; ++v) Store<TO>::put(dst + 64 * v, out[v]);
+                } else {
+#pragma unroll
+                    for (int v = 0; v < V; ++v) {
+                        const int i = i0 + lane + 64 * v;
+                        if (i >= 0 && i < len) Store<TO>::put(dst + 64 * v, out[v]);
+                    }
+                }
+            }
+            continue;
+        }
         for (int sub = 0; sub < T; sub += ST) {  // sub-tiles of the window: the row's table words stay cached
             const int i0 = tau0 + sub - lo;  // output index at the sub-tile start
             if (i0 >= len || i0 + ST <= 0) continue;
