@@ -72,6 +72,8 @@ def parse():
                     help="binary input storage: bit rows (auto) or one byte per sample")
     ap.add_argument("--stage-levels", type=lambda s: int(s, 0), default=0)
     ap.add_argument("--no-detect", action="store_true", help="time the tree only")
+    ap.add_argument("--serial-detect", action="store_true",
+                    help="extract each block's candidates before the next block starts (no host/device overlap)")
     ap.add_argument("--generic-kernels", action="store_true", help="run every stage on the generic stage kernel")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=2048, help="output samples in the oracle's timed sample")
@@ -368,27 +370,43 @@ def main():
         f"workspace {info['workspace_bytes'] / 2**30:.2f} GiB, built in {info['build_seconds']:.2f} s")
     plan.upload(dev)
     ws = plan.workspace(dev)
-    out = plan.empty_output(dev)
+    # two output planes: a block's plane stays intact while the next block's tree runs and
+    # the host extracts the block's candidates
+    outs = [plan.empty_output(dev), plan.empty_output(dev)]
     detector = None
     if not args.no_detect and hasattr(snd, "Detector"):
         detector = snd.Detector(plan, widths=spec.widths, threshold=7.0, device=dev)
     nst = info["n_stages"]
     stream = torch.cuda.current_stream(dev)
+    pipeline = detector is not None and not args.serial_detect
 
-    def step(evs=None):
+    def step(k, evs=None, pending=None):
+        """Block k: the tree, then detection.  Pipelined, the detection is only launched here
+        and the previous block's candidates are collected (host work) while this block runs."""
+        out = outs[k % 2]
         for s in range(nst):
             plan.execute(x, out=out, workspace=ws, stage=s)
             if evs is not None:
                 evs[s + 1].record(stream)
-        if detector is not None:
+        if detector is None:
+            return None, None
+        if not pipeline:
             cands = detector.run(out)
             if evs is not None:
                 evs[nst + 1].record(stream)
-            return cands
-        return None
+            return cands, None
+        ticket = detector.launch(out)
+        if evs is not None:
+            evs[nst + 1].record(stream)
+        cands = detector.collect(pending) if pending is not None else None
+        return cands, ticket
 
-    for _ in range(args.warmup):
-        step()
+    pending = None
+    for k in range(args.warmup):
+        _, pending = step(k, pending=pending)
+    if pending is not None:
+        detector.collect(pending)
+        pending = None
     torch.cuda.synchronize()
     nev = nst + 2
     events = [[torch.cuda.Event(enable_timing=True) for _ in range(nev)] for _ in range(args.steps)]
@@ -397,9 +415,11 @@ def main():
     ncand = 0
     for k in range(args.steps):
         events[k][0].record(stream)
-        c = step(events[k])
+        c, pending = step(k, events[k], pending)
         if c is not None:
             ncand = len(c)
+    if pending is not None:
+        ncand = len(detector.collect(pending))
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     stage_ms = np.zeros(nst)
@@ -445,7 +465,8 @@ def main():
         "config": {"workload": "single NC-shaped beam: 1024 ch 400-416 MHz, 0.138 ms, 2^17 samples, 16 pulses; "
                                "4096 DMs 0-2000; B=4, C=4",
                    "mode": mode, "in_dtype": plan.in_dtype, "node_dtype": node,
-                   "n_out": plan.n_out, "stages": nst, "detect": detector is not None},
+                   "n_out": plan.n_out, "stages": nst, "detect": detector is not None,
+                   "detect_host_overlapped": pipeline},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": f"{kname} (stage {dom} of {nst}, {info['stage_kernel'][dom]})",
@@ -460,6 +481,7 @@ def main():
         "stage_alg_gb": [round(b / 1e9, 3) for b in info["stage_alg_bytes"]],
         "detect_ms": round(det_ms, 4),
         "candidates": ncand,
+        "thresholded_cells": detector.npixels if detector is not None else 0,
         "plan": {"neurons": info["n_neurons"], "synapses": info["n_synapses"],
                  "workspace_gib": round(info["workspace_bytes"] / 2**30, 3)},
     }
@@ -469,7 +491,7 @@ def main():
     result["config"]["stage_levels"] = hex(stage_levels)
     legs = [l for l in args.legs.split(",") if l and l != "none"]
     if legs:
-        del x, out, ws, detector, plan
+        del x, outs, ws, detector, plan
         torch.cuda.empty_cache()
     if "batch" in legs:
         log("[bench] batched leg: 48 beams")

@@ -261,6 +261,31 @@ snd_status snd_detect(snd_plan plan, const void *d_plane, int64_t plane_pitch, c
                       void *d_workspace, int64_t workspace_bytes, snd_candidate *h_out, int64_t cap,
                       int64_t *h_count, int64_t *h_npixels, void *stream);
 
+/*
+ * Asynchronous form of snd_detect, for pipelines that overlap the host's candidate extraction
+ * with later device work (for example the next block's tree).
+ *
+ * snd_detect_launch enqueues on stream the kernels of snd_detect and the read-back of the
+ * thresholded-cell count and of up to SND_DETECT_STAGE_CELLS(stage_bytes) cells into h_stage,
+ * a caller-owned host buffer of stage_bytes (page-locked for the copy to be asynchronous;
+ * >= SND_DETECT_STAGE_HEADER bytes; its first 4 bytes receive the count), and returns.  The
+ * copy size is fixed by stage_bytes and max_pixels, not by the count.
+ *
+ * snd_detect_collect, called once that stream work has completed (e.g. after synchronising an
+ * event recorded after snd_detect_launch), turns the staged cells into candidates on the host
+ * without touching the device: same outputs as snd_detect.  CAPACITY (with *h_npixels set and
+ * no candidates) when the count exceeds max_pixels or the cells h_stage holds; the caller can
+ * then run snd_detect on the same plane.  The device workspace may be reused as soon as the
+ * launch's stream work has completed; h_stage must stay untouched until collect returns.
+ */
+#define SND_DETECT_STAGE_HEADER 256
+#define SND_DETECT_STAGE_CELLS(stage_bytes) (((stage_bytes) - SND_DETECT_STAGE_HEADER) / 24)
+snd_status snd_detect_launch(snd_plan plan, const void *d_plane, int64_t plane_pitch, const snd_detect_desc *desc,
+                             void *d_workspace, int64_t workspace_bytes, void *h_stage, int64_t stage_bytes,
+                             void *stream);
+snd_status snd_detect_collect(snd_plan plan, const snd_detect_desc *desc, const void *h_stage, int64_t stage_bytes,
+                              snd_candidate *h_out, int64_t cap, int64_t *h_count, int64_t *h_npixels);
+
 /* ---------------------------------------------------------------------------------------
  * Batched execution.
  *

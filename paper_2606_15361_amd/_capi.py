@@ -18,6 +18,10 @@ MODE_BINARY, MODE_GRADED, MODE_FLOAT = 0, 1, 2
 DT_U8, DT_U16, DT_F32, DT_BF16, DT_F16, DT_BITS = 1, 2, 3, 4, 5, 6
 
 
+DETECT_STAGE_HEADER = 256  # SND_DETECT_STAGE_HEADER
+DETECT_CELL_BYTES = 24    # bytes per staged cell
+
+
 class SndError(RuntimeError):
     def __init__(self, status: int, message: str):
         super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
@@ -112,6 +116,8 @@ def lib() -> C.CDLL:
         "snd_detect_workspace": ([P, D, C.POINTER(I64)], I32),
         "snd_snr_plane": ([P, P, I64, D, P, I64, P, I64, P, I64, P], I32),
         "snd_detect": ([P, P, I64, D, P, I64, C.POINTER(Candidate), I64, C.POINTER(I64), C.POINTER(I64), P], I32),
+        "snd_detect_launch": ([P, P, I64, D, P, I64, P, I64, P], I32),
+        "snd_detect_collect": ([P, D, P, I64, C.POINTER(Candidate), I64, C.POINTER(I64), C.POINTER(I64)], I32),
     })
     PI64 = C.POINTER(I64)
     PP = C.POINTER(P)

@@ -283,6 +283,69 @@ snd_status snd_snr_plane(snd_plan plan, const void *d_plane, int64_t plane_pitch
     return SND_OK;
 }
 
+snd_status snd_detect_launch(snd_plan plan, const void *d_plane, int64_t plane_pitch, const snd_detect_desc *desc,
+                             void *d_workspace, int64_t workspace_bytes, void *h_stage, int64_t stage_bytes,
+                             void *stream)
+{
+    static_assert(sizeof(snd::Pixel) == 24, "staged cell size");
+    if (!plan || !d_plane || !d_workspace || !h_stage) { snd::set_error("null argument"); return SND_ERR_INVALID; }
+    if (stage_bytes < SND_DETECT_STAGE_HEADER) { snd::set_error("stage buffer smaller than its header"); return SND_ERR_INVALID; }
+    const auto &P = plan->impl;
+    snd_status s = check_desc(P, desc);
+    if (s != SND_OK) return s;
+    if (workspace_bytes < workspace_bytes_for(P, desc) || ((uintptr_t)d_workspace & 255u)) {
+        snd::set_error("detect workspace too small or not 256-byte aligned");
+        return SND_ERR_NOMEM;
+    }
+    if (plane_pitch < P.n_out) { snd::set_error("plane pitch smaller than n_out"); return SND_ERR_INVALID; }
+    uint8_t *ws = static_cast<uint8_t *>(d_workspace);
+    snd::SnrArgs a;
+    fill_args(desc, a);
+    a.counter = reinterpret_cast<unsigned int *>(ws);
+    a.pixels = reinterpret_cast<snd::Pixel *>(ws + kHeader + round_up((int64_t)P.ndm * 16, 256));
+    a.max_pixels = desc->max_pixels;
+    double *stats = reinterpret_cast<double *>(ws + kHeader);
+    hipStream_t st = (hipStream_t)stream;
+    int e = snd::launch_detect(P.out_dtype, d_plane, plane_pitch, P.ndm, P.n_out, desc->sigma_min, stats, a, stream);
+    if (e) { snd::set_error(std::string("detect launch: ") + hipGetErrorString((hipError_t)e)); return SND_ERR_HIP; }
+    uint8_t *hs = static_cast<uint8_t *>(h_stage);
+    hipError_t he = hipMemcpyAsync(hs, a.counter, sizeof(unsigned int), hipMemcpyDeviceToHost, st);
+    const int64_t ncells = std::min<int64_t>(SND_DETECT_STAGE_CELLS(stage_bytes), desc->max_pixels);
+    if (he == hipSuccess && ncells > 0)
+        he = hipMemcpyAsync(hs + SND_DETECT_STAGE_HEADER, a.pixels, (size_t)ncells * sizeof(snd::Pixel),
+                            hipMemcpyDeviceToHost, st);
+    if (he != hipSuccess) { snd::set_error(std::string("detect read-back: ") + hipGetErrorString(he)); return SND_ERR_HIP; }
+    return SND_OK;
+}
+
+snd_status snd_detect_collect(snd_plan plan, const snd_detect_desc *desc, const void *h_stage, int64_t stage_bytes,
+                              snd_candidate *h_out, int64_t cap, int64_t *h_count, int64_t *h_npixels)
+{
+    if (!plan || !h_stage || !h_count || (cap > 0 && !h_out)) { snd::set_error("null argument"); return SND_ERR_INVALID; }
+    if (stage_bytes < SND_DETECT_STAGE_HEADER) { snd::set_error("stage buffer smaller than its header"); return SND_ERR_INVALID; }
+    const auto &P = plan->impl;
+    snd_status s = check_desc(P, desc);
+    if (s != SND_OK) return s;
+    const uint8_t *hs = static_cast<const uint8_t *>(h_stage);
+    unsigned int count = 0;
+    std::memcpy(&count, hs, sizeof(count));
+    if (h_npixels) *h_npixels = count;
+    *h_count = 0;
+    const int64_t ncells = std::min<int64_t>(SND_DETECT_STAGE_CELLS(stage_bytes), desc->max_pixels);
+    if ((int64_t)count > desc->max_pixels || (int64_t)count > ncells) {
+        snd::set_error("more thresholded cells than max_pixels or than the stage buffer holds");
+        return SND_ERR_CAPACITY;
+    }
+    std::vector<snd::Pixel> px(count);
+    if (count) std::memcpy(px.data(), hs + SND_DETECT_STAGE_HEADER, sizeof(snd::Pixel) * count);
+    std::vector<snd_candidate> cands;
+    s = candidates_from_pixels(px, P, desc, cands);
+    if (s != SND_OK) return s;
+    *h_count = (int64_t)cands.size();
+    for (int64_t i = 0; i < cap && i < (int64_t)cands.size(); ++i) h_out[i] = cands[i];
+    return SND_OK;
+}
+
 snd_status snd_detect(snd_plan plan, const void *d_plane, int64_t plane_pitch, const snd_detect_desc *desc,
                       void *d_workspace, int64_t workspace_bytes, snd_candidate *h_out, int64_t cap, int64_t *h_count,
                       int64_t *h_npixels, void *stream)

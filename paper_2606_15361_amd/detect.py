@@ -55,6 +55,38 @@ class Detector:
                                             _stream_handle(stream, plane.device)))
         return snr, widx
 
+    def launch(self, plane, stage_cells: int = 1 << 18, stream=None):
+        """Enqueue this plane's detection and the read-back of up to stage_cells thresholded
+        cells into a page-locked host buffer (snd_detect_launch); returns a ticket for
+        collect().  Launches on one stream may follow each other (the workspace is reused in
+        stream order); the plane must stay unchanged until collect() returns, since collect()
+        detects it again with run() when the staged cells do not hold them all."""
+        import torch
+        dev = plane.device
+        nb = capi.DETECT_STAGE_HEADER + capi.DETECT_CELL_BYTES * int(stage_cells)
+        stage = torch.empty(nb, dtype=torch.uint8, pin_memory=True)
+        capi.check(capi.lib().snd_detect_launch(self.plan.handle, C.c_void_p(plane.data_ptr()), plane.stride(0),
+                                                C.byref(self.desc), C.c_void_p(self.ws.data_ptr()), self.ws.numel(),
+                                                C.c_void_p(stage.data_ptr()), nb, _stream_handle(stream, dev)))
+        ev = torch.cuda.Event()
+        ev.record(torch.cuda.current_stream(dev) if stream is None else stream)
+        return (stage, ev, plane)
+
+    def collect(self, ticket):
+        """Candidates of a launched plane: waits for its read-back, then extracts them on the host
+        (snd_detect_collect), while the device may already run later work.  Falls back to run()
+        on the plane when the staged cells do not hold them all."""
+        stage, ev, plane = ticket
+        ev.synchronize()
+        cnt, npx = C.c_int64(), C.c_int64()
+        rc = capi.lib().snd_detect_collect(self.plan.handle, C.byref(self.desc), C.c_void_p(stage.data_ptr()),
+                                           stage.numel(), self._buf, self._cap, C.byref(cnt), C.byref(npx))
+        if rc == capi.ERR_CAPACITY and npx.value <= self.desc.max_pixels:
+            return self.run(plane)
+        capi.check(rc)
+        self.npixels = npx.value
+        return self._candidates(cnt.value)
+
     def run(self, plane, stream=None):
         """Candidates of a plane, as dicts ordered by (k, t) of the peak.  Synchronises the stream."""
         cnt, npx = C.c_int64(), C.c_int64()
@@ -63,8 +95,11 @@ class Detector:
                                          self._buf, self._cap, C.byref(cnt), C.byref(npx),
                                          _stream_handle(stream, plane.device)))
         self.npixels = npx.value
+        return self._candidates(cnt.value)
+
+    def _candidates(self, n):
         out = []
-        for i in range(min(cnt.value, self._cap)):
+        for i in range(min(n, self._cap)):
             c = self._buf[i]
             out.append(dict(k=c.dm_index, t=c.t, width=c.width, widx=self.widths.index(c.width), snr=c.snr,
                             dm=c.dm, npix=c.npix))

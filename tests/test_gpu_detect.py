@@ -94,6 +94,34 @@ def test_float_plane_within_tolerance(snd, orc):
         assert abs(g["snr"] - w["snr"]) <= 0.01 * abs(w["snr"])
 
 
+def test_launch_collect_matches_run(snd, orc):
+    # the asynchronous pair gives the candidates of snd_detect, with later device work queued
+    # between launch and collect; a stage buffer too small for the cells falls back to run()
+    rng = synth.make_rng(21)
+    ndm, n = 40, 6000
+    planes = []
+    for j in range(3):
+        pl = rng.standard_normal((ndm, n)).astype(np.float32)
+        pl[5 + 9 * j:8 + 9 * j, 1000 + 700 * j:1012 + 700 * j] += 5.0
+        planes.append(torch.from_numpy(pl).cuda())
+    p = _plan_for(snd, ndm, n, "float")
+    det = snd.Detector(p, WIDTHS, threshold=6.0)
+    want = [det.run(pl) for pl in planes]
+    npx = []
+    for pl in planes:
+        det.run(pl)
+        npx.append(det.npixels)
+    tickets = [det.launch(pl) for pl in planes]  # three launches queued before any collect
+    got = [det.collect(t) for t in tickets]
+    for g, w, m in zip(got, want, npx):
+        assert g == w and len(w) >= 1
+    o_snr, o_widx, _, _ = orc.matched_filter(planes[0].cpu().numpy().astype(np.float64), WIDTHS,
+                                             integer_plane=False)
+    assert [(c["k"], c["t"]) for c in got[0]] == [(c["k"], c["t"]) for c in orc.candidates(o_snr, o_widx, 6.0)]
+    small = det.launch(planes[1], stage_cells=max(1, npx[1] // 2))
+    assert det.collect(small) == want[1]
+
+
 def test_capacity_error(snd):
     from paper_2606_15361_amd import SndError
     plane = np.full((8, 500), 1.0, np.float32)
