@@ -499,16 +499,16 @@ snd_status build_plan(const snd_plan_desc &d, PlanImpl &p, std::string &err)
         }
     }
 
-    // Bit rows: every leaf row starts on a 64-sample boundary (its anchor moves down by at
-    // most 63 samples), so that a leaf-stage tile writes whole words of each row.
+    // Every leaf row (below a root) starts on a 64-sample boundary (its anchor moves down by at
+    // most 63 samples): the leaf stage's stores of a row are then whole 256-byte (f32) or
+    // 128-byte (16-bit) lines, and bit rows are written in whole words.
     const bool bits = d.node_dtype == SND_DT_BITS;
-    if (bits) {
-        if (top < 1 || d.generic_kernels || (d.stage_levels != 0 && d.stage_levels != 1u)) {
-            err = "bit rows need the default schedule (leaf level materialised) and the staged kernels";
-            return SND_ERR_UNSUPPORTED;
-        }
-        for (int32_t &v : p.lev[0].lo) v -= v % 64;
+    if (bits && (top < 1 || d.generic_kernels || (d.stage_levels != 0 && d.stage_levels != 1u))) {
+        err = "bit rows need the default schedule (leaf level materialised) and the staged kernels";
+        return SND_ERR_UNSUPPORTED;
     }
+    if (top >= 1)
+        for (int32_t &v : p.lev[0].lo) v -= v % 64;
 
     // ---------------- stages ----------------
     uint32_t mask;

@@ -187,8 +187,11 @@ class Plan:
         return self._ws
 
     def empty_output(self, device="cuda"):
+        """[ndm][n_out] view of rows whose pitch is a multiple of 64 samples, so that every row
+        starts on a 256-byte boundary (whole-line stores)."""
         import torch
-        return torch.empty((self.ndm, self.n_out), dtype=self.out_dtype, device=device)
+        pitch = (self.n_out + 63) // 64 * 64
+        return torch.empty((self.ndm, pitch), dtype=self.out_dtype, device=device)[:, : self.n_out]
 
     def execute(self, x, out=None, workspace=None, stream=None, stage=None):
         """Dedisperse x [nchan][>= nsamp] (device tensor of the input dtype) into out [ndm][>= n_out].
