@@ -67,6 +67,64 @@ __device__ inline int issue_batch(const_ptr<int32_t> batches, const_ptr<int32_t>
     return n_ins;
 }
 
+// Copy one window (descriptor as in issue_batch) of the tile into LDS.
+template <typename TI>
+__device__ inline void issue_window(int srow, int eoff, int lbyte, int hs, int lane, const unsigned char *srcb,
+                                    int64_t pitch_bytes, int t0, int vt, unsigned char *ldsb)
+{
+    constexpr int ES = (int)sizeof(TI);
+    // row and offsets are non-negative and a row pitch is below 4 GiB (checked on the host)
+    const uint4 *gp = reinterpret_cast<const uint4 *>(srcb + (uint64_t)(uint32_t)srow * (uint32_t)pitch_bytes +
+                                                      (uint64_t)(uint32_t)(eoff + t0) * ES) + lane;
+    unsigned char *lp = ldsb + lbyte;
+    const int nu = ((hs + vt) * ES + 15) >> 4;  // 16-byte units of the window for this tile
+    int u0 = 0;
+    for (; u0 + 64 <= nu; u0 += 64)  // whole instructions, no mask
+        __builtin_amdgcn_global_load_lds(gp + u0, (__attribute__((address_space(3))) void *)(lp + 16 * u0), 16, 0, 0);
+    if (u0 < nu && u0 + lane < nu)
+        __builtin_amdgcn_global_load_lds(gp + u0, (__attribute__((address_space(3))) void *)(lp + 16 * u0), 16, 0, 0);
+}
+
+// A batch's table words for one wave: its entry range and window range, and the descriptors
+// of the wave's first two windows.  Loaded a batch ahead of use, so that no wave waits for
+// scalar loads between a barrier and its copies or its first LDS reads.
+struct BatchWords {
+    int ex, ey, bz, bw;
+    int d[2][4];
+};
+
+__device__ inline void load_batch_words(const_ptr<int32_t> batches, const_ptr<int32_t> instrs, int b, int wave,
+                                        BatchWords &w)
+{
+    w.ex = batches[4 * b];
+    w.ey = batches[4 * b + 1];
+    w.bz = batches[4 * b + 2];
+    w.bw = batches[4 * b + 3];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const int si = w.bz + wave + j * kGroupRows;
+        if (si < w.bw) {  // uniform; windows past the batch are not read
+#pragma unroll
+            for (int i = 0; i < 4; ++i) w.d[j][i] = instrs[4 * si + i];
+        }
+    }
+}
+
+// issue_batch from preloaded words: the first two windows from w, any further ones loaded here.
+template <typename TI>
+__device__ inline void issue_batch_words(const BatchWords &w, const_ptr<int32_t> instrs, int wave, int lane,
+                                         const unsigned char *srcb, int64_t pitch_bytes, int t0, int vt, TI *dst)
+{
+    unsigned char *ldsb = reinterpret_cast<unsigned char *>(dst);
+    int si = w.bz + wave;
+#pragma unroll
+    for (int j = 0; j < 2; ++j, si += kGroupRows)
+        if (si < w.bw) issue_window<TI>(w.d[j][0], w.d[j][1], w.d[j][2], w.d[j][3], lane, srcb, pitch_bytes, t0, vt, ldsb);
+    for (; si < w.bw; si += kGroupRows)
+        issue_window<TI>(instrs[4 * si], instrs[4 * si + 1], instrs[4 * si + 2], instrs[4 * si + 3], lane, srcb,
+                         pitch_bytes, t0, vt, ldsb);
+}
+
 // Workgroup barrier for the staged kernels.  Every wave has already waited for its own copies
 // into the buffer about to be read (wait_vmcnt), and every LDS read of the buffer about to be
 // refilled has returned (its values were summed), so only the execution barrier is needed:

@@ -81,15 +81,23 @@ __global__ __launch_bounds__(1024) void k_group_fast(GroupArgs s0, Multi m)
 
     const int b0 = as_const(s.batch_ptr)[g], b1 = as_const(s.batch_ptr)[g + 1];
     static_assert(kFastBuffers == 2, "the pipeline below double-buffers");
-    if (b0 < b1) issue_batch<TI>(batches, instrs, b0, wave, lane, srcb, pitch_bytes, t0, vt, lds);
+    // table words of batches b (cur) and b + 1 (nxt); those of b + 2 are loaded during batch b
+    BatchWords cur{}, nxt{};
+    if (b0 < b1) {
+        load_batch_words(batches, instrs, b0, wave, cur);
+        issue_batch_words<TI>(cur, instrs, wave, lane, srcb, pitch_bytes, t0, vt, lds);
+    }
+    if (b0 + 1 < b1) load_batch_words(batches, instrs, b0 + 1, wave, nxt);
     int buf = 0;
     for (int b = b0; b < b1; ++b) {
         __builtin_amdgcn_s_waitcnt(0x0f70);  // vmcnt(0): this wave's copies of batch b have landed
         stage_barrier();  // everyone's have; everyone is done reading batch b - 1
         if (b + 1 < b1)   // into the buffer of batch b - 1
-            issue_batch<TI>(batches, instrs, b + 1, wave, lane, srcb, pitch_bytes, t0, vt, lds + (buf ^ 1) * s.buf_elems);
+            issue_batch_words<TI>(nxt, instrs, wave, lane, srcb, pitch_bytes, t0, vt, lds + (buf ^ 1) * s.buf_elems);
+        const int ex = cur.ex, ey = cur.ey;
+        cur = nxt;
+        if (b + 2 < b1) load_batch_words(batches, instrs, b + 2, wave, nxt);
         if (row[0] >= 0) {
-            const int ex = batches[4 * b], ey = batches[4 * b + 1];
             const unsigned char *base = reinterpret_cast<const unsigned char *>(lds + buf * s.buf_elems + lane);
             for (int c0 = ex; c0 < ey; c0 += F1) {  // one level-1 node per step
                 const int c = closes[(uint32_t)c0 / F1];  // levels completed by this node's last input
