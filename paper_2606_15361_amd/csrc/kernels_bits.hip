@@ -22,13 +22,16 @@
 namespace snd {
 namespace {
 
-constexpr int kPlanes = 4;  // counts up to 15 (fan-in of any node <= 15 for the supported trees)
+constexpr int kPlanes = 4;  // counts up to 15: leaf clusters of at most 15 channels
+// bit planes for counts up to n
+constexpr int planes_for(int n) { return n < 2 ? 1 : n < 4 ? 2 : n < 8 ? 3 : 4; }
 
 // count += x (bit-sliced, one increment per set bit of x)
-__device__ inline void bs_add(uint32_t (&c)[kPlanes], uint32_t x)
+template <int NP>
+__device__ inline void bs_add(uint32_t (&c)[NP], uint32_t x)
 {
 #pragma unroll
-    for (int i = 0; i < kPlanes; ++i) {
+    for (int i = 0; i < NP; ++i) {
         const uint32_t t = c[i] & x;
         c[i] ^= x;
         x = t;
@@ -36,12 +39,13 @@ __device__ inline void bs_add(uint32_t (&c)[kPlanes], uint32_t x)
 }
 
 // bits where count >= k (k uniform, >= 1)
-__device__ inline uint32_t bs_ge(const uint32_t (&c)[kPlanes], int k)
+template <int NP>
+__device__ inline uint32_t bs_ge(const uint32_t (&c)[NP], int k)
 {
-    if (k >= (1 << kPlanes)) return 0u;
+    if (k >= (1 << NP)) return 0u;
     uint32_t gt = 0u, eq = ~0u;
 #pragma unroll
-    for (int i = kPlanes - 1; i >= 0; --i) {
+    for (int i = NP - 1; i >= 0; --i) {
         if ((k >> i) & 1) {
             eq &= c[i];
         } else {
@@ -76,8 +80,8 @@ __device__ inline void issue_bits(const_ptr<int32_t> batches, const_ptr<int32_t>
 
 // Levels J..D after an input that completes c levels (see the byte-row kernel): the level-J
 // count's quorum goes to level J + 1 (or is the root) and the count restarts at zero.
-template <int J, int D, int NS, int R>
-__device__ inline void close_bits_from(int c, uint32_t (&cnt)[NS][R][kPlanes], uint32_t (&out)[R], int k)
+template <int J, int D, int NS, int R, int NP>
+__device__ inline void close_bits_from(int c, uint32_t (&cnt)[NS][R][NP], uint32_t (&out)[R], int k)
 {
     if constexpr (J <= D) {
         if (c >= J) {
@@ -85,11 +89,11 @@ __device__ inline void close_bits_from(int c, uint32_t (&cnt)[NS][R][kPlanes], u
             for (int q = 0; q < R; ++q) {
                 const uint32_t y = bs_ge(cnt[J - 2][q], k);
 #pragma unroll
-                for (int i = 0; i < kPlanes; ++i) cnt[J - 2][q][i] = 0u;
+                for (int i = 0; i < NP; ++i) cnt[J - 2][q][i] = 0u;
                 if constexpr (J == D) out[q] = y;
                 else bs_add(cnt[J - 1][q], y);
             }
-            close_bits_from<J + 1, D, NS, R>(c, cnt, out, k);
+            close_bits_from<J + 1, D, NS, R, NP>(c, cnt, out, k);
         }
     }
 }
@@ -124,14 +128,17 @@ __global__ __launch_bounds__(1024) void k_group_bits(GroupArgs s0, Multi m)
     const int buf_bytes = s.buf_elems / 8;
     const int k1 = s.src_is_input ? s.k_leaf : s.k_int;  // quorum of the level-1 nodes
 
-    uint32_t cnt[NS][R][kPlanes];  // cnt[j - 2]: input count of the open level-j node, j = 2 .. D
+    // every node of the tree has at most F1 inputs (level-1 nodes exactly F1, the branching
+    // factor; higher levels at most that), so counts fit NP bit planes
+    constexpr int NP = planes_for(F1);
+    uint32_t cnt[NS][R][NP];  // cnt[j - 2]: input count of the open level-j node, j = 2 .. D
     uint32_t out[R];
 #pragma unroll
     for (int j = 0; j < NS; ++j)
 #pragma unroll
         for (int q = 0; q < R; ++q)
 #pragma unroll
-            for (int i = 0; i < kPlanes; ++i) cnt[j][q][i] = 0u;
+            for (int i = 0; i < NP; ++i) cnt[j][q][i] = 0u;
 #pragma unroll
     for (int q = 0; q < R; ++q) out[q] = 0u;
 
@@ -152,11 +159,11 @@ __global__ __launch_bounds__(1024) void k_group_bits(GroupArgs s0, Multi m)
                 for (int u = 0; u < F1; ++u)
 #pragma unroll
                     for (int q = 0; q < R; ++q) x[u][q] = lb[(c0 + u) * R + q];
-                uint32_t a[R][kPlanes];
+                uint32_t a[R][NP];
 #pragma unroll
                 for (int q = 0; q < R; ++q)
 #pragma unroll
-                    for (int i = 0; i < kPlanes; ++i) a[q][i] = 0u;
+                    for (int i = 0; i < NP; ++i) a[q][i] = 0u;
 #pragma unroll
                 for (int u = 0; u < F1; ++u)
 #pragma unroll
@@ -172,7 +179,7 @@ __global__ __launch_bounds__(1024) void k_group_bits(GroupArgs s0, Multi m)
                     if constexpr (D == 1) out[q] = y;
                     else bs_add(cnt[0][q], y);
                 }
-                close_bits_from<2, D, NS, R>(c, cnt, out, s.k_int);
+                close_bits_from<2, D, NS, R, NP>(c, cnt, out, s.k_int);
             }
         }
         buf ^= 1;
