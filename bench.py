@@ -80,8 +80,9 @@ def parse():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one plain 1 GiB device copy first (scale reference for HBM counters)")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default stage schedule")
-    ap.add_argument("--legs", default="batch,serve",
-                    help="extra measurements after the headline: batch (48 beams), serve (streaming loop)")
+    ap.add_argument("--legs", default="direct,batch,serve",
+                    help="extra measurements after the headline: direct (the same block without shared neurons), "
+                         "batch (48 beams), serve (streaming loop)")
     ap.add_argument("--serve-seconds", type=float, default=12.0, help="real-time length of each serving run")
     return ap.parse_args()
 
@@ -102,6 +103,33 @@ def cpu_baseline(spec, mode, n_sample):
                 sample=f"shared-pattern SND tree (C, FP64, 1 thread) over all {spec.dms.size} DMs x {n_sample} "
                        f"output samples of the same 1024-channel beam; {dt:.1f} s",
                 seconds=round(dt, 2)), np.asarray(y).shape
+
+
+def direct_leg(snd, torch, spec, x, pkw, dev, ref_out, reps=3):
+    """Comparison baseline on the same block: direct dedispersion, every DM row summing every
+    channel at its own delay, with no neuron shared between DMs (a plan with no materialised
+    level: SND_STAGE_NONE).  Float sums keep the tree's association, so the plane must equal
+    the shared-neuron plane bit for bit."""
+    p = snd.Plan(spec.freqs, spec.dms, spec.tsamp_s, spec.nsamp, stage_levels=0x80000000, **pkw)
+    p.upload(dev)
+    out = p.empty_output(dev)
+    ws = p.workspace(dev)
+    stream = torch.cuda.current_stream(dev)
+    p.execute(x, out=out, workspace=ws)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        p.execute(x, out=out, workspace=ws)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    info = p.info
+    a, b = out.float(), ref_out.float()
+    rel = float(torch.sqrt(torch.mean((a - b) ** 2)) / torch.sqrt(torch.mean(b ** 2)).clamp_min(1e-30))
+    return dict(method="direct (no shared neurons)", ms=round(ms, 3), value=p.ndm * p.n_out / (ms * 1e-3),
+                unit="DM-time samples/s", kernel=info["stage_kernel"][0], inputs_per_sample=info["stage_entries"][0],
+                identical_to_snd=bool(torch.equal(out, ref_out)), rel_rms_vs_snd=rel)
 
 
 def batch_leg(snd, synth, torch, dev, reps=3):
@@ -490,6 +518,14 @@ def main():
                                    workspace_gib=round(t["workspace_bytes"] / 2**30, 2)) for t in tuned]
     result["config"]["stage_levels"] = hex(stage_levels)
     legs = [l for l in args.legs.split(",") if l and l != "none"]
+    if "direct" in legs and plan.in_dtype == "bits":
+        result["direct"] = {"skipped": "bit input needs the materialised leaf level"}
+    elif "direct" in legs:
+        log("[bench] direct-dedispersion baseline on the same block")
+        ref = outs[(args.steps - 1) % 2]
+        result["direct"] = direct_leg(snd, torch, spec, x, pkw, dev, ref)
+        result["direct"]["snd_tree_ms"] = round(float(stage_ms.sum()), 3)
+        log(f"[bench] direct: {result['direct']['ms']} ms vs tree {result['direct']['snd_tree_ms']} ms")
     if legs:
         del x, outs, ws, detector, plan
         torch.cuda.empty_cache()
