@@ -247,3 +247,16 @@ def test_autotune_argument_errors(snd):
     d.chunk = 0
     assert L.snd_autotune(C.byref(d), c, 0, buf, 500, buf, 500, buf, 1 << 20, buf, 1 << 20, 1, C.byref(best),
                           None) == _capi.ERR_INVALID
+
+
+def test_bit_row_packing_layout():
+    """The tests' bit-row packing follows the BITS layout: bit i of word w is sample 32 w + i."""
+    from bitrows import pack_bits
+    rng = np.random.default_rng(3)
+    x = (rng.random((3, 301)) < 0.4).astype(np.uint8)
+    w = pack_bits(x).view(np.uint32)
+    assert w.shape == (3, 12)  # 301 samples -> 10 words, padded to a multiple of 4
+    for c in range(3):
+        for t in range(w.shape[1] * 32):
+            bit = (int(w[c, t // 32]) >> (t % 32)) & 1
+            assert bit == (x[c, t] if t < 301 else 0)

@@ -9,6 +9,7 @@ import numpy as np
 import pytest
 
 import synth
+from bitrows import pack_bits
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -51,6 +52,7 @@ BEAMS = [
     (64, 50, 200.0, 1000, 2, "graded", dict(cap=300), "u8"),
     (37, 17, 40.0, 613, 3, "float", dict(node_dtype="f16"), "f16"),
     (64, 64, 150.0, 800, 8, "binary", dict(k_leaf=2, k_int=2), "u8"),
+    (64, 40, 150.0, 900, 4, "binary", dict(k_leaf=1, k_int=2), "bits"),
 ]
 
 
@@ -77,6 +79,8 @@ def test_batch_matches_per_beam_and_oracle(snd, orc):
         want, _ = orc.snd_dedup(x, f, d, mode=mode, cluster=4, branching=B, **okw)
         plans.append(snd.Plan(f, dms, 0.138e-3, x.shape[1], mode=mode, branching=B, in_dtype=inp, **kw))
         xt = torch.from_numpy(np.ascontiguousarray(x)).cuda()
+        if inp == "bits":
+            xt = torch.from_numpy(pack_bits(x)).cuda()
         xs.append(snd.cast(xt, inp) if inp in ("bf16", "f16") else xt)
         wants.append(want)
         modes.append((mode, kw))

@@ -11,6 +11,7 @@ import numpy as np
 import pytest
 
 import synth
+from bitrows import pack_bits
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -51,17 +52,6 @@ def gpu_run(plan, x, stage_by_stage=False):
         y = plan.execute(xt)
     torch.cuda.synchronize()
     return to_np(y)
-
-
-def pack_bits(x):
-    """Spike rows [nchan][nsamp] (non-zero = spike) as bit rows: int32 [nchan][words], bit i
-    of word w = sample 32 w + i, words a multiple of 4."""
-    nchan, nsamp = x.shape
-    nw = (nsamp + 127) // 128 * 4
-    b = np.packbits(np.asarray(x) != 0, axis=1, bitorder="little")
-    out = np.zeros((nchan, nw * 4), dtype=np.uint8)
-    out[:, : b.shape[1]] = b
-    return out.view("<u4").view(np.int32)
 
 
 def rel_rms(a, b):
