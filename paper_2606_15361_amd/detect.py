@@ -68,21 +68,22 @@ class Detector:
         capi.check(capi.lib().snd_detect_launch(self.plan.handle, C.c_void_p(plane.data_ptr()), plane.stride(0),
                                                 C.byref(self.desc), C.c_void_p(self.ws.data_ptr()), self.ws.numel(),
                                                 C.c_void_p(stage.data_ptr()), nb, _stream_handle(stream, dev)))
+        st = torch.cuda.current_stream(dev) if stream is None else stream
         ev = torch.cuda.Event()
-        ev.record(torch.cuda.current_stream(dev) if stream is None else stream)
-        return (stage, ev, plane)
+        ev.record(st)
+        return (stage, ev, plane, st)
 
     def collect(self, ticket):
         """Candidates of a launched plane: waits for its read-back, then extracts them on the host
         (snd_detect_collect), while the device may already run later work.  Falls back to run()
         on the plane when the staged cells do not hold them all."""
-        stage, ev, plane = ticket
+        stage, ev, plane, st = ticket
         ev.synchronize()
         cnt, npx = C.c_int64(), C.c_int64()
         rc = capi.lib().snd_detect_collect(self.plan.handle, C.byref(self.desc), C.c_void_p(stage.data_ptr()),
                                            stage.numel(), self._buf, self._cap, C.byref(cnt), C.byref(npx))
         if rc == capi.ERR_CAPACITY and npx.value <= self.desc.max_pixels:
-            return self.run(plane)
+            return self.run(plane, stream=st)  # on the launch's stream: the workspace stays in order
         capi.check(rc)
         self.npixels = npx.value
         return self._candidates(cnt.value)
