@@ -21,7 +21,9 @@ What pins each function to something other than itself (tests/test_oracle_*.py):
 * bruteforce    -- DM 0 row = channel sum; conservation of the summed counts.
 * encode        -- fire rates against the normal tail probability.
 * matched_filter -- the printed noise-floor closed forms (0.8 and ~21), Gaussian noise
-                   statistics, optimal boxcar width, constant rows.
+                   statistics, optimal boxcar width, constant rows; per-row width counts reduce
+                   to the plain filter on the leading widths.
+* dm_width_counts -- hand-evaluated widths of the DM-scaled set for the Northern Cross band.
 * candidates    -- hand-built masks (row gaps 9 / 10, diagonal pairs) and scipy's closing and
                    labelling on padded planes.
 * fire_probability, cascade, binary_snr -- Table 1 values.
@@ -87,6 +89,10 @@ def _load():
         lib.orc_encode.restype = None
         lib.orc_matched_filter.argtypes = [C.c_int32, C.c_int64, C.c_int64, P, C.c_int32, P, C.c_double,
                                            P, P, P, P]
+        lib.orc_matched_filter_rows.argtypes = [C.c_int32, C.c_int64, C.c_int64, P, C.c_int32, P, P, C.c_double,
+                                                P, P, P, P]
+        lib.orc_dm_width_counts.argtypes = [C.c_int32, P, C.c_double, C.c_double, C.c_int32, P, C.c_int32, P,
+                                            C.c_int32, C.c_double, P]
         lib.orc_candidates.argtypes = [C.c_int64, C.c_int64, P, P, C.c_double, C.c_int32, C.c_int64,
                                        C.POINTER(_Cand), C.c_int64]
         lib.orc_candidates.restype = C.c_int64
@@ -208,8 +214,24 @@ def encode(z: np.ndarray, thresholds) -> np.ndarray:
     return out
 
 
-def matched_filter(y, widths, *, integer_plane: bool, sigma_min: float = 0.0):
-    """(snr, width_index, mu, sigma) for a DM-time plane y[ndm][nout]."""
+def dm_width_counts(freqs, dms, tsamp_s: float, widths, n_base: int, alpha: float, fref: float = 0.0) -> np.ndarray:
+    """int32 [ndm]: how many of the increasing widths each DM row uses under the DM-scaled width
+    set (base = the first n_base widths, the rest up to alpha * sweep / dt)."""
+    lib = _load()
+    f = np.ascontiguousarray(freqs, dtype=np.float64)
+    d = np.ascontiguousarray(dms, dtype=np.float64)
+    w = np.ascontiguousarray(widths, dtype=np.int32)
+    out = np.empty(d.size, dtype=np.int32)
+    rc = lib.orc_dm_width_counts(f.size, _ptr(f), tsamp_s, fref, d.size, _ptr(d), w.size, _ptr(w), int(n_base),
+                                 float(alpha), _ptr(out))
+    if rc:
+        raise ValueError("reference frequency below the highest channel frequency")
+    return out
+
+
+def matched_filter(y, widths, *, integer_plane: bool, sigma_min: float = 0.0, row_nw=None):
+    """(snr, width_index, mu, sigma) for a DM-time plane y[ndm][nout]; row_nw: per-row number of
+    leading widths used (None: all)."""
     lib = _load()
     yy = np.ascontiguousarray(y, dtype=np.float64)
     w = np.ascontiguousarray(widths, dtype=np.int32)
@@ -217,8 +239,10 @@ def matched_filter(y, widths, *, integer_plane: bool, sigma_min: float = 0.0):
     widx = np.empty(yy.shape, dtype=np.int32)
     mu = np.empty(yy.shape[0], dtype=np.float64)
     sg = np.empty(yy.shape[0], dtype=np.float64)
-    rc = lib.orc_matched_filter(int(integer_plane), yy.shape[0], yy.shape[1], _ptr(yy), w.size, _ptr(w), sigma_min,
-                                _ptr(snr), _ptr(widx), _ptr(mu), _ptr(sg))
+    rn = None if row_nw is None else np.ascontiguousarray(row_nw, dtype=np.int32)
+    rc = lib.orc_matched_filter_rows(int(integer_plane), yy.shape[0], yy.shape[1], _ptr(yy), w.size, _ptr(w),
+                                     None if rn is None else _ptr(rn), sigma_min, _ptr(snr), _ptr(widx), _ptr(mu),
+                                     _ptr(sg))
     if rc:
         raise ValueError("widths must be positive and strictly increasing")
     return snr, widx, mu, sg

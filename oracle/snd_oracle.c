@@ -434,6 +434,43 @@ void orc_encode(int64_t n, const float *z, int32_t nthr, const float *thr, uint8
 }
 
 /* ------------------------------------------------------------------------------------
+ * DM-scaled width set (Methods, "Matched filtering", the equation for W(d_k)): the widths of
+ * row k are the base set (the first n_base entries of the increasing width list) and every
+ * further width w with w <= alpha * tau_sweep(d_k) / dt, tau_sweep being the dispersive sweep
+ * across the band at d_k: the unrounded delay of the lowest channel frequency, evaluated
+ * exactly as the channel delays are.  Since the list increases, row k uses its first
+ * count[k] widths.  n_base <= 0 keeps every width in every row.
+ * ---------------------------------------------------------------------------------- */
+int orc_dm_width_counts(int32_t nchan, const double *freq, double tsamp_s, double fref, int32_t ndm,
+                        const double *dm, int32_t nw, const int32_t *widths, int32_t n_base, double alpha,
+                        int32_t *count)
+{
+    double fmax = freq[0], fmin = freq[0];
+    for (int32_t c = 1; c < nchan; ++c) {
+        if (freq[c] > fmax) fmax = freq[c];
+        if (freq[c] < fmin) fmin = freq[c];
+    }
+    double fr = fref > 0.0 ? fref : fmax;
+    if (fr < fmax) return -1;
+    double tms = tsamp_s * 1e3;
+    for (int32_t k = 0; k < ndm; ++k) {
+        if (n_base <= 0 || n_base >= nw) {
+            count[k] = nw;
+            continue;
+        }
+        double x = ORC_KDM * dm[k];
+        x = x * (1.0 / (fmin * fmin) - 1.0 / (fr * fr));
+        x = x / tms;  /* tau_sweep / dt in samples */
+        double lim = alpha * x;
+        int32_t n = n_base;
+        for (int32_t i = n_base; i < nw; ++i)
+            if ((double)widths[i] <= lim) n = i + 1;
+        count[k] = n;
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------------------
  * Boxcar matched filter (Methods, "Matched filtering"): per row the mean and population
  * standard deviation of the valid samples, an optional floor sigma_min on sigma, and for
  * every width W that fits, SNR(k,t,W) = (sum_{t'=t}^{t+W-1} y - mu W) / (sigma sqrt W).
@@ -444,9 +481,22 @@ void orc_encode(int64_t n, const float *z, int32_t nthr, const float *thr, uint8
  * sigma = sqrt(n*S2 - S1*S1)/n with each product and the difference rounded once (exact
  * for 8-bit planes, where every term is an integer below 2^53).
  * ---------------------------------------------------------------------------------- */
+int orc_matched_filter_rows(int32_t integer_plane, int64_t ndm, int64_t nout, const double *y, int32_t nw,
+                            const int32_t *widths, const int32_t *row_nw, double sigma_min, double *snr,
+                            int32_t *widx, double *mu_out, double *sigma_out);
+
 int orc_matched_filter(int32_t integer_plane, int64_t ndm, int64_t nout, const double *y, int32_t nw,
                        const int32_t *widths, double sigma_min, double *snr, int32_t *widx, double *mu_out,
                        double *sigma_out)
+{
+    return orc_matched_filter_rows(integer_plane, ndm, nout, y, nw, widths, NULL, sigma_min, snr, widx, mu_out,
+                                   sigma_out);
+}
+
+/* The same with row k restricted to its first row_nw[k] widths (row_nw NULL: all widths). */
+int orc_matched_filter_rows(int32_t integer_plane, int64_t ndm, int64_t nout, const double *y, int32_t nw,
+                            const int32_t *widths, const int32_t *row_nw, double sigma_min, double *snr,
+                            int32_t *widx, double *mu_out, double *sigma_out)
 {
     for (int32_t i = 0; i < nw; ++i)
         if (widths[i] < 1 || (i > 0 && widths[i] <= widths[i - 1])) return -1;
@@ -474,10 +524,11 @@ int orc_matched_filter(int32_t integer_plane, int64_t ndm, int64_t nout, const d
         if (sigma < sigma_min) sigma = sigma_min;
         if (mu_out) mu_out[k] = mu;
         if (sigma_out) sigma_out[k] = sigma;
+        const int32_t nwk = row_nw ? row_nw[k] : nw;
         for (int64_t t = 0; t < nout; ++t) {
             double best = 0.0;
             int32_t bi = -1;
-            for (int32_t i = 0; i < nw; ++i) {
+            for (int32_t i = 0; i < nwk; ++i) {
                 int32_t w = widths[i];
                 if (t + w > nout) break;
                 double s = 0.0;

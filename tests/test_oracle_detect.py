@@ -117,3 +117,37 @@ def test_binary_snr_prediction_limits(orc):
     assert orc.binary_snr(4, 0.5, 0.1) == pytest.approx(2 * orc.binary_snr(1, 0.5, 0.1))
     assert orc.binary_snr(16, 0.2, 0.2) == 0.0
     assert math.isclose(orc.binary_snr(1, 1.0, 0.5), 1.0)
+
+
+PAPER_WIDTHS = [1, 2, 4, 8, 16, 32, 64, 128, 256, 512, 1024]
+
+
+def test_dm_width_counts_northern_cross(orc):
+    # Methods, matched filtering, the DM-scaled width set with base {1, 2, 4, 8} and alpha = 0.1,
+    # evaluated by hand for the Northern Cross band (channel centres 416 - (c + 1/2) 16/1024 MHz,
+    # lowest 400.0078125, highest 415.9921875; dt = 0.138 ms):
+    #   sweep / dt = 4.148808e6 * d * (400.0078125^-2 - 415.9921875^-2) / 0.138 = 14.1619 * d
+    #   d = 0: 0 -> base only; d = 10: alpha * sweep = 14.16 -> base only; d = 25: 35.4 -> + 16, 32;
+    #   d = 50: 70.8 -> + 64; d = 100: 141.6 -> + 128; d = 200: 283.2 -> + 256; d = 400: 566.5
+    #   -> + 512; d = 2000: 2832 -> every width up to 1024
+    f = synth.channel_freqs(1024)
+    dms = [0.0, 10.0, 25.0, 50.0, 100.0, 200.0, 400.0, 2000.0]
+    got = orc.dm_width_counts(f, dms, 0.138e-3, PAPER_WIDTHS, 4, 0.1)
+    assert list(got) == [4, 4, 6, 7, 8, 9, 10, 11]
+    # the sweep at d = 2000 rounds to the band's largest channel delay, 28,324 samples
+    assert int(orc.delays(f, [2000.0], 0.138e-3).max()) == 28324
+    # no base given: every row keeps every width
+    assert list(orc.dm_width_counts(f, dms, 0.138e-3, PAPER_WIDTHS, 0, 0.1)) == [11] * 8
+
+
+@pytest.mark.parametrize("integer_plane", [True, False])
+def test_row_width_counts_reduce_to_the_plain_filter(orc, integer_plane):
+    rng = synth.make_rng(41)
+    y = rng.integers(0, 5, (6, 700)).astype(np.float64) if integer_plane else rng.standard_normal((6, 700))
+    y[2, 300:340] += 3.0
+    counts = np.array([1, 3, 5, 7, 2, 7], dtype=np.int32)
+    snr, widx, mu, sg = orc.matched_filter(y, PAPER_WIDTHS[:7], integer_plane=integer_plane, row_nw=counts)
+    for k, n in enumerate(counts):
+        s1, w1, m1, g1 = orc.matched_filter(y[k:k + 1], PAPER_WIDTHS[:n], integer_plane=integer_plane)
+        assert np.array_equal(snr[k], s1[0]) and np.array_equal(widx[k], w1[0])
+        assert mu[k] == m1[0] and sg[k] == g1[0]
