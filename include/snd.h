@@ -230,8 +230,14 @@ typedef struct {
     double threshold;       /* > 0, compared with the FP64 S/N */
     double sigma_min;       /* >= 0; the paper floors sigma of binary planes (0.15-0.20) */
     int32_t n_min;          /* >= 1; the paper uses 10 */
-    int32_t reserved;       /* must be zero */
+    int32_t n_base_widths;  /* 0 (or nwidths): every row uses every width.  Else a DM-scaled set
+                               (Methods, "Matched filtering", W(d_k)): row k uses the first
+                               n_base_widths widths and every further width w <= width_alpha *
+                               tau_sweep(d_k) / tsamp, tau_sweep being the unrounded delay of
+                               the lowest channel frequency at d_k (evaluated as the channel
+                               delays are); the paper uses {1,2,4,8} + {16..1024}, alpha 0.1 */
     int64_t max_pixels;     /* capacity of the device list of thresholded cells, >= 1 */
+    double width_alpha;     /* >= 0, used when n_base_widths > 0 */
 } snd_detect_desc;
 
 typedef struct {

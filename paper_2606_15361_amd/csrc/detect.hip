@@ -31,6 +31,8 @@ constexpr int kSnrTile = 4096;
 constexpr int kThreads = 256;
 
 template <typename T> struct IsInt { static constexpr bool value = true; };
+template <typename P> struct BoundNever { __device__ static P value() { return (P)2147483647; } };
+template <> struct BoundNever<double> { __device__ static double value() { return __builtin_inf(); } };
 template <> struct IsInt<float> { static constexpr bool value = false; };
 
 // Row sums with 16-byte loads: a scalar head up to the first 16-byte boundary of the row, then
@@ -158,7 +160,9 @@ __global__ __launch_bounds__(kThreads) void k_snr(const T *plane, int64_t pitch,
     const int64_t t0 = (int64_t)blockIdx.x * kSnrTile;
     const T *row = plane + (int64_t)k * pitch + t0;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const int wmax = a.w[a.nw - 1];
+    // widths of this row: the first nwk of the list (all of them unless a DM-scaled set)
+    const int nwk = a.row_nw ? a.row_nw[k] : a.nw;
+    const int wmax = a.w[nwk - 1];
     // elements t0 .. t0 + L - 1 are needed (and exist): L = min(tile + wmax - 1, n - t0)
     int64_t L64 = (int64_t)kSnrTile + wmax - 1;
     if (L64 > n - t0) L64 = n - t0;
@@ -256,7 +260,7 @@ __global__ __launch_bounds__(kThreads) void k_snr(const T *plane, int64_t pitch,
     auto exact = [&](int i, int64_t t, double &best, int &bi) {
         best = 0.0;
         bi = -1;
-        for (int w = 0; w < a.nw; ++w) {
+        for (int w = 0; w < nwk; ++w) {
             const int W = a.w[w];
             if (t + W > n) break;
             double val = 0.0;
@@ -291,7 +295,9 @@ __global__ __launch_bounds__(kThreads) void k_snr(const T *plane, int64_t pitch,
     if constexpr (NW > 0) {
 #pragma unroll
         for (int w = 0; w < NW; ++w) {
-            rthr[w] = sthr[w];
+            // widths beyond the row's set get a bound no sum reaches (their prefix reads stay
+            // inside the prefix array; the values there are not this row's and are never used)
+            rthr[w] = w < nwk ? sthr[w] : BoundNever<P>::value();
             rw[w] = a.w[w];
         }
     }
@@ -313,7 +319,7 @@ __global__ __launch_bounds__(kThreads) void k_snr(const T *plane, int64_t pitch,
 #pragma unroll
             for (int w = 0; w < RW; ++w) maybe |= (P)(pre[i + rw[w]] - p0) >= rthr[w];
         } else {
-            for (int w = 0; w < a.nw; ++w) {
+            for (int w = 0; w < nwk; ++w) {
                 if (t + a.w[w] > n) break;
                 maybe |= (P)(pre[i + a.w[w]] - p0) >= sthr[w];
             }

@@ -34,8 +34,13 @@ snd_status check_desc(const snd::PlanImpl &P, const snd_detect_desc *d)
         }
     }
     if (!(d->threshold > 0.0) || !(d->sigma_min >= 0.0) || d->closing_radius < 0 || d->closing_radius > 64 ||
-        d->n_min < 1 || d->max_pixels < 1 || d->reserved != 0) {
+        d->n_min < 1 || d->max_pixels < 1) {
         snd::set_error("threshold must be > 0, sigma_min >= 0, 0 <= closing_radius <= 64, n_min >= 1, max_pixels >= 1");
+        return SND_ERR_INVALID;
+    }
+    if (d->n_base_widths < 0 || d->n_base_widths > d->nwidths || !(d->width_alpha >= 0.0) ||
+        !std::isfinite(d->width_alpha)) {
+        snd::set_error("n_base_widths must be in 0..nwidths and width_alpha finite and >= 0");
         return SND_ERR_INVALID;
     }
     if (P.ndm > 65535) { snd::set_error("detect supports at most 65535 DM rows"); return SND_ERR_UNSUPPORTED; }
@@ -43,9 +48,57 @@ snd_status check_desc(const snd::PlanImpl &P, const snd_detect_desc *d)
     return SND_OK;
 }
 
+// Workspace: header (cell counter) | row statistics | thresholded cells | per-row width counts
+int64_t pixels_offset(const snd::PlanImpl &P) { return kHeader + round_up((int64_t)P.ndm * 16, 256); }
+
+int64_t row_nw_offset(const snd::PlanImpl &P, const snd_detect_desc *d)
+{
+    return round_up(pixels_offset(P) + d->max_pixels * (int64_t)sizeof(snd::Pixel), 256);
+}
+
 int64_t workspace_bytes_for(const snd::PlanImpl &P, const snd_detect_desc *d)
 {
-    return kHeader + round_up((int64_t)P.ndm * 16, 256) + d->max_pixels * (int64_t)sizeof(snd::Pixel);
+    return row_nw_offset(P, d) + round_up((int64_t)P.ndm * 4, 256);
+}
+
+// DM-scaled width set: the number of leading widths each row uses (Methods, "Matched
+// filtering", W(d_k)), from the unrounded sweep across the band at d_k.
+void row_width_counts(const snd::PlanImpl &P, const snd_detect_desc *d, std::vector<int32_t> &nw)
+{
+    nw.assign((size_t)P.ndm, d->nwidths);
+    if (d->n_base_widths <= 0) return;
+    double fmin = P.freq[0];
+    for (double f : P.freq) fmin = std::min(fmin, f);
+    const double tms = P.desc.tsamp_s * 1e3;
+    for (int k = 0; k < P.ndm; ++k) {
+        double x = snd::kDM * P.dm[(size_t)k];
+        x = x * (1.0 / (fmin * fmin) - 1.0 / (P.fref * P.fref));
+        x = x / tms;
+        const double lim = d->width_alpha * x;
+        int32_t n = d->n_base_widths;
+        for (int i = d->n_base_widths; i < d->nwidths; ++i)
+            if ((double)d->widths[i] <= lim) n = i + 1;
+        nw[(size_t)k] = n;
+    }
+}
+
+// Per-row width counts into the workspace (only for a DM-scaled set); the pageable source is
+// consumed when the copy call returns.
+snd_status upload_row_nw(const snd::PlanImpl &P, const snd_detect_desc *d, uint8_t *ws, snd::SnrArgs &a,
+                         hipStream_t st)
+{
+    a.row_nw = nullptr;
+    if (d->n_base_widths <= 0) return SND_OK;
+    std::vector<int32_t> nw;
+    row_width_counts(P, d, nw);
+    int32_t *dst = reinterpret_cast<int32_t *>(ws + row_nw_offset(P, d));
+    hipError_t e = hipMemcpyAsync(dst, nw.data(), nw.size() * sizeof(int32_t), hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) {
+        snd::set_error(std::string("hipMemcpyAsync(row widths): ") + hipGetErrorString(e));
+        return SND_ERR_HIP;
+    }
+    a.row_nw = dst;
+    return SND_OK;
 }
 
 void fill_args(const snd_detect_desc *d, snd::SnrArgs &a)
@@ -278,6 +331,8 @@ snd_status snd_snr_plane(snd_plan plan, const void *d_plane, int64_t plane_pitch
     a.widx = d_widx;
     a.widx_pitch = widx_pitch;
     double *stats = reinterpret_cast<double *>(static_cast<uint8_t *>(d_workspace) + kHeader);
+    s = upload_row_nw(P, desc, static_cast<uint8_t *>(d_workspace), a, (hipStream_t)stream);
+    if (s != SND_OK) return s;
     int e = snd::launch_detect(P.out_dtype, d_plane, plane_pitch, P.ndm, P.n_out, desc->sigma_min, stats, a, stream);
     if (e) { snd::set_error(std::string("detect launch: ") + hipGetErrorString((hipError_t)e)); return SND_ERR_HIP; }
     return SND_OK;
@@ -302,10 +357,12 @@ snd_status snd_detect_launch(snd_plan plan, const void *d_plane, int64_t plane_p
     snd::SnrArgs a;
     fill_args(desc, a);
     a.counter = reinterpret_cast<unsigned int *>(ws);
-    a.pixels = reinterpret_cast<snd::Pixel *>(ws + kHeader + round_up((int64_t)P.ndm * 16, 256));
+    a.pixels = reinterpret_cast<snd::Pixel *>(ws + pixels_offset(P));
     a.max_pixels = desc->max_pixels;
     double *stats = reinterpret_cast<double *>(ws + kHeader);
     hipStream_t st = (hipStream_t)stream;
+    s = upload_row_nw(P, desc, ws, a, st);
+    if (s != SND_OK) return s;
     int e = snd::launch_detect(P.out_dtype, d_plane, plane_pitch, P.ndm, P.n_out, desc->sigma_min, stats, a, stream);
     if (e) { snd::set_error(std::string("detect launch: ") + hipGetErrorString((hipError_t)e)); return SND_ERR_HIP; }
     uint8_t *hs = static_cast<uint8_t *>(h_stage);
@@ -363,10 +420,12 @@ snd_status snd_detect(snd_plan plan, const void *d_plane, int64_t plane_pitch, c
     snd::SnrArgs a;
     fill_args(desc, a);
     a.counter = reinterpret_cast<unsigned int *>(ws);
-    a.pixels = reinterpret_cast<snd::Pixel *>(ws + kHeader + round_up((int64_t)P.ndm * 16, 256));
+    a.pixels = reinterpret_cast<snd::Pixel *>(ws + pixels_offset(P));
     a.max_pixels = desc->max_pixels;
     double *stats = reinterpret_cast<double *>(ws + kHeader);
     hipStream_t st = (hipStream_t)stream;
+    s = upload_row_nw(P, desc, ws, a, st);
+    if (s != SND_OK) return s;
     int e = snd::launch_detect(P.out_dtype, d_plane, plane_pitch, P.ndm, P.n_out, desc->sigma_min, stats, a, stream);
     if (e) { snd::set_error(std::string("detect launch: ") + hipGetErrorString((hipError_t)e)); return SND_ERR_HIP; }
     unsigned int count = 0;

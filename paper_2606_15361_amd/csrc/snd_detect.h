@@ -26,6 +26,7 @@ struct SnrArgs {
     int32_t w[kMaxWidths];
     double sqrtw[kMaxWidths];
     int32_t nw;
+    const int32_t *row_nw;  // per-row number of leading widths used (null: nw for every row)
     double threshold;
     // plane output (when snr != nullptr)
     float *snr;

@@ -14,7 +14,11 @@ class Detector:
     """Boxcar S/N and candidate extraction for the DM-time planes of one plan."""
 
     def __init__(self, plan, widths=(1, 2, 4, 8, 16, 32, 64), threshold: float = 7.0, sigma_min: float = 0.0,
-                 closing_radius: int = 4, n_min: int = 10, max_pixels: int = 1 << 20, device="cuda"):
+                 closing_radius: int = 4, n_min: int = 10, max_pixels: int = 1 << 20, device="cuda",
+                 n_base_widths: int = 0, width_alpha: float = 0.0):
+        """n_base_widths > 0 selects the DM-scaled width set: each row uses the first
+        n_base_widths widths and the further ones up to width_alpha times its dispersive sweep
+        (the paper: widths 1..1024 in powers of two, n_base_widths 4, width_alpha 0.1)."""
         import torch
         self.plan = plan
         self._w = np.ascontiguousarray(widths, dtype=np.int32)
@@ -25,7 +29,8 @@ class Detector:
         d.sigma_min = sigma_min
         d.closing_radius = closing_radius
         d.n_min = n_min
-        d.reserved = 0
+        d.n_base_widths = n_base_widths
+        d.width_alpha = width_alpha
         d.max_pixels = max_pixels
         self.desc = d
         nb = C.c_int64()

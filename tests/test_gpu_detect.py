@@ -187,3 +187,43 @@ def test_config2_pulse_recovery_float(snd, orc):
         assert abs(float(o_snr[0].max()) - best["snr"]) <= 0.01 * best["snr"]
         checked += 1
     assert checked == 3
+
+
+PAPER_WIDTHS = [1, 2, 4, 8, 16, 32, 64, 128, 256, 512, 1024]
+
+
+@pytest.mark.parametrize("integer_plane", [True, False])
+def test_dm_scaled_width_set(snd, orc, integer_plane):
+    # the paper's width set: {1, 2, 4, 8} in every row, 16..1024 up to 0.1 x the row's sweep
+    f = synth.channel_freqs(1024)
+    dms = np.array([0.0, 10.0, 25.0, 50.0, 100.0, 200.0, 400.0, 2000.0])
+    n = 5000
+    dmax = int(orc.delays(f, dms, 0.138e-3).max())
+    p = snd.Plan(f, dms, 0.138e-3, dmax + n, mode="graded" if integer_plane else "float", branching=4)
+    assert p.n_out == n
+    rng = synth.make_rng(77)
+    if integer_plane:
+        plane = rng.integers(0, 6, (dms.size, n)).astype(np.uint8)
+        plane[6, 1000:1400] = 5  # a wide pulse: only rows with the wide widths catch it whole
+        plane[2, 3000:3030] = 5
+    else:
+        plane = rng.standard_normal((dms.size, n)).astype(np.float32)
+        plane[6, 1000:1400] += 1.0
+        plane[2, 3000:3030] += 3.0
+    counts = orc.dm_width_counts(f, dms, 0.138e-3, PAPER_WIDTHS, 4, 0.1)
+    assert list(counts) == [4, 4, 6, 7, 8, 9, 10, 11]
+    det = snd.Detector(p, PAPER_WIDTHS, threshold=6.0, n_base_widths=4, width_alpha=0.1)
+    dev = torch.from_numpy(plane).cuda()
+    snr, widx = det.snr_plane(dev)
+    o_snr, o_widx, _, _ = orc.matched_filter(plane.astype(np.float64), PAPER_WIDTHS, integer_plane=integer_plane,
+                                             row_nw=counts)
+    w = widx.cpu().numpy().astype(np.int32)
+    if integer_plane:
+        assert np.array_equal(snr.cpu().numpy(), o_snr.astype(np.float32)) and np.array_equal(w, o_widx)
+    else:
+        assert np.max(np.abs(snr.cpu().numpy() - o_snr)) <= 1e-4 * max(1.0, np.abs(o_snr).max())
+    assert np.all(w < counts[:, None])  # no row uses a width outside its set
+    got = det.run(dev)
+    want = orc.candidates(o_snr, o_widx, 6.0, radius=4, n_min=10)
+    assert [(c["k"], c["t"], c["npix"]) for c in got] == [(c["k"], c["t"], c["npix"]) for c in want]
+    assert any(c["k"] == 6 for c in got)
