@@ -24,6 +24,9 @@ What pins each function to something other than itself (tests/test_oracle_*.py):
                    statistics, optimal boxcar width, constant rows; per-row width counts reduce
                    to the plain filter on the leading widths.
 * dm_width_counts -- hand-evaluated widths of the DM-scaled set for the Northern Cross band.
+* scrunch_factors -- the printed Northern Cross band edges (289 / 578 / 1157 / 2313).
+* scrunch        -- identity at S = 1, constant rows, conservation of the summed samples.
+* merge_candidates -- hand-built candidate lists.
 * candidates    -- hand-built masks (row gaps 9 / 10, diagonal pairs) and scipy's closing and
                    labelling on padded planes.
 * fire_probability, cascade, binary_snr -- Table 1 values.
@@ -290,3 +293,57 @@ def cascade(p0: float, fanins, k_leaf: int, k_int: int) -> list:
 def binary_snr(width: float, p_sig: float, p_noise: float) -> float:
     """Predicted boxcar S/N of a Bernoulli root output (Eq. snr_A)."""
     return math.sqrt(width) * (p_sig - p_noise) / math.sqrt(p_noise * (1.0 - p_noise))
+
+
+# --------------------------------------------------------------------------------------
+# Multi-rate extension (Methods, "Multi-rate extension").
+# --------------------------------------------------------------------------------------
+K_DM = 4.148808e6  # MHz^2 ms per pc cm^-3 (as in the C part)
+
+
+def scrunch_factors(freqs, dms, tsamp_s: float, s_max: int = 16) -> np.ndarray:
+    """int32 [ndm]: the scrunch factor of each trial DM (Eq. scrunch): the largest power of two
+    S <= s_max with S * dt <= tau_smear(d) = K_DM d df / fc^3 (1 when even S = 2 fails).  fc is
+    the band centre (mean of the highest and lowest channel frequencies) and df the channel
+    spacing; tau_smear and dt in ms, FP64."""
+    f = np.asarray(freqs, dtype=np.float64)
+    d = np.asarray(dms, dtype=np.float64)
+    fc = 0.5 * (f.max() + f.min())
+    df = (f.max() - f.min()) / (f.size - 1) if f.size > 1 else 0.0
+    dt = tsamp_s * 1e3
+    out = np.ones(d.size, dtype=np.int32)
+    for i, dm in enumerate(d):
+        tau = K_DM * dm * df / (fc * fc * fc)
+        s = 1
+        while 2 * s <= s_max and 2 * s * dt <= tau:
+            s *= 2
+        out[i] = s
+    return out
+
+
+def scrunch(z, s: int) -> np.ndarray:
+    """float32 [nchan][n // s]: each output sample sums s consecutive input samples, in order, in
+    FP32, and scales by the FP32 value of 1/sqrt(s), so that unit-variance input stays unit
+    variance.  FP32 on purpose: the spike encoder thresholds the result, and both sides must
+    take that decision on the same values."""
+    z = np.asarray(z, dtype=np.float32)
+    n = z.shape[1] // s
+    acc = z[:, 0:n * s:s].copy()
+    for j in range(1, s):
+        acc = (acc + z[:, j:n * s:s]).astype(np.float32)
+    return (acc * np.float32(1.0 / math.sqrt(s))).astype(np.float32)
+
+
+def merge_candidates(cands, dm_tol: float = 20.0, t_tol_ms: float = 200.0) -> list:
+    """Cross-band merge of candidates (dicts with dm, t_ms, snr): in decreasing S/N (ties: lower
+    DM, then earlier time) a candidate within |dDM| <= dm_tol and |dt| <= t_tol_ms of an already
+    kept candidate is absorbed by it, otherwise it is kept.  Returns the kept ones ordered by
+    (t_ms, dm)."""
+    order = sorted(range(len(cands)), key=lambda i: (-cands[i]["snr"], cands[i]["dm"], cands[i]["t_ms"]))
+    kept = []
+    for i in order:
+        c = cands[i]
+        if any(abs(c["dm"] - q["dm"]) <= dm_tol and abs(c["t_ms"] - q["t_ms"]) <= t_tol_ms for q in kept):
+            continue
+        kept.append(c)
+    return sorted(kept, key=lambda c: (c["t_ms"], c["dm"]))
