@@ -293,6 +293,48 @@ snd_status snd_detect_collect(snd_plan plan, const snd_detect_desc *desc, const 
                               snd_candidate *h_out, int64_t cap, int64_t *h_count, int64_t *h_npixels);
 
 /* ---------------------------------------------------------------------------------------
+ * Multi-rate extension (Methods, "Multi-rate extension").  The DM range is split into bands
+ * by scrunch factor; each band runs its own plan (tsamp * S, nsamp / S samples, its DMs) on a
+ * time-scrunched copy of the filterbank, re-encoded for binary and graded modes, and the
+ * bands' candidates are merged in (DM, time).
+ * --------------------------------------------------------------------------------------- */
+
+/* Scrunch factor of each trial DM (Eq. scrunch): the largest power of two S <= s_max with
+ * S * tsamp <= tau_smear(d) = K_DM * d * df / fc^3, 1 when S = 2 already fails; fc = mean of the
+ * highest and lowest channel frequencies, df = channel spacing (highest - lowest) / (nchan - 1)
+ * (0 for one channel), all in FP64.  h_factor: host int32[ndm].  s_max: 1..1024. */
+snd_status snd_scrunch_factors(int32_t nchan, const double *freq_mhz, double tsamp_s, int32_t ndm, const double *dm,
+                               int32_t s_max, int32_t *h_factor);
+
+/* Time scrunch of a z-scored filterbank: d_out[c][t] = (sum_{j<s} d_z[c][s t + j]) * r for
+ * t < nsamp / s, the sum taken in order in FP32 and r the FP32 value of 1 / sqrt(s) (unit
+ * variance is kept, so encoder thresholds keep their meaning).  d_z [nchan][z_pitch] and d_out
+ * [nchan][out_pitch] float32 device arrays; 1 <= s <= 1024; nothing is done (OK) when
+ * nsamp < s.  Asynchronous on stream. */
+snd_status snd_scrunch(const float *d_z, int64_t z_pitch, int32_t nchan, int64_t nsamp, int32_t s, float *d_out,
+                       int64_t out_pitch, void *stream);
+
+/* One candidate of one band, for the cross-band merge. */
+typedef struct {
+    double dm;        /* trial DM */
+    double t_ms;      /* arrival time at the top of the band, ms from the block start */
+    double snr;       /* S/N of the peak cell */
+    int32_t band;     /* band index (caller's) */
+    int32_t dm_index; /* row in the caller's full DM list */
+    int32_t width;    /* boxcar width, band samples */
+    int32_t reserved; /* ignored */
+    int64_t t;        /* first sample of the peak boxcar, band samples */
+    int64_t npix;     /* pixels of the band island */
+} snd_band_candidate;
+
+/* Cross-band merge (host): in decreasing S/N (ties: lower DM, then earlier time) a candidate
+ * within |dDM| <= dm_tol and |dt| <= t_tol_ms of an already kept candidate is absorbed,
+ * otherwise kept (the paper: 20 pc cm^-3, 200 ms; full ties keep input order).  Writes the kept
+ * ones, ordered by (t_ms, dm), to h_out (room for n) and their number to *h_count. */
+snd_status snd_merge_candidates(int64_t n, const snd_band_candidate *h_in, double dm_tol, double t_tol_ms,
+                                snd_band_candidate *h_out, int64_t *h_count);
+
+/* ---------------------------------------------------------------------------------------
  * Batched execution.
  *
  * Several beams, each with its own uploaded plan (DM grids, lengths, modes and storage types

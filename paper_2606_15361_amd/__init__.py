@@ -11,6 +11,7 @@ from .plan import Plan, autotune, encode, encode_bits, cast  # noqa: F401
 from .detect import Detector  # noqa: F401
 from .stream import Stream, history_bytes  # noqa: F401
 from .batch import Batch, records_bytes  # noqa: F401
+from .multirate import MultiRate, scrunch, scrunch_factors, merge_candidates  # noqa: F401
 
-__all__ = ["Plan", "autotune", "Detector", "Stream", "Batch", "history_bytes", "records_bytes", "encode", "encode_bits", "cast", "SndError",
-           "LIB_PATH"]
+__all__ = ["Plan", "autotune", "Detector", "Stream", "Batch", "history_bytes", "records_bytes", "encode", "encode_bits",
+           "cast", "MultiRate", "scrunch", "scrunch_factors", "merge_candidates", "SndError", "LIB_PATH"]

@@ -59,6 +59,12 @@ class DetectDesc(C.Structure):
                 ("n_base_widths", C.c_int32), ("max_pixels", C.c_int64), ("width_alpha", C.c_double)]
 
 
+class BandCandidate(C.Structure):
+    _fields_ = [("dm", C.c_double), ("t_ms", C.c_double), ("snr", C.c_double), ("band", C.c_int32),
+                ("dm_index", C.c_int32), ("width", C.c_int32), ("reserved", C.c_int32), ("t", C.c_int64),
+                ("npix", C.c_int64)]
+
+
 class Candidate(C.Structure):
     _fields_ = [("dm_index", C.c_int32), ("width", C.c_int32), ("t", C.c_int64), ("snr", C.c_double),
                 ("dm", C.c_double), ("npix", C.c_int64)]
@@ -108,6 +114,9 @@ def lib() -> C.CDLL:
         "snd_encode": ([P, I64, I32, I32, I64, P, I32, P, I64, P], I32),
         "snd_encode_bits": ([P, I64, I32, I32, I64, C.c_float, P, I64, P], I32),
         "snd_cast": ([P, I64, I64, I64, P, I64, I32, P], I32),
+        "snd_scrunch_factors": ([I32, P, C.c_double, I32, P, I32, P], I32),
+        "snd_scrunch": ([P, I64, I32, I64, I32, P, I64, P], I32),
+        "snd_merge_candidates": ([I64, P, C.c_double, C.c_double, P, C.POINTER(I64)], I32),
         "snd_last_error": ([], C.c_char_p),
         "snd_version": ([], C.c_char_p),
     }

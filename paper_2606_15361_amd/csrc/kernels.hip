@@ -218,6 +218,20 @@ __global__ __launch_bounds__(256) void k_encode_bits_tm(const float *z, int64_t 
     }
 }
 
+// Time scrunch: each thread sums s consecutive samples of one channel in order (FP32, no
+// contraction) and scales by r.
+__global__ __launch_bounds__(256) void k_scrunch(const float *z, int64_t zp, int64_t nout, int s, float r, float *out,
+                                                 int64_t op)
+{
+    const int c = blockIdx.y;
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (t >= nout) return;
+    const float *p = z + (int64_t)c * zp + t * s;
+    float acc = p[0];
+    for (int j = 1; j < s; ++j) acc = acc + p[j];
+    out[(int64_t)c * op + t] = acc * r;
+}
+
 template <typename TO>
 __global__ __launch_bounds__(256) void k_cast(const float *src, int64_t sp, int64_t cols, TO *dst, int64_t dp)
 {
@@ -271,6 +285,14 @@ int launch_encode_bits(const float *z, int64_t zp, int time_major, int nchan, in
         dim3 grid((uint32_t)((nsamp + 255) / 256), (uint32_t)nchan);
         hipLaunchKernelGGL(k_encode_bits_cm, grid, dim3(256), 0, st, z, zp, nsamp, thr, out, ow);
     }
+    return (int)hipGetLastError();
+}
+
+int launch_scrunch(const float *z, int64_t zp, int nchan, int64_t nout, int s, float r, float *out, int64_t op,
+                   void *stream)
+{
+    dim3 grid((uint32_t)((nout + 255) / 256), (uint32_t)nchan);
+    hipLaunchKernelGGL(k_scrunch, grid, dim3(256), 0, (hipStream_t)stream, z, zp, nout, s, r, out, op);
     return (int)hipGetLastError();
 }
 

@@ -260,3 +260,22 @@ def test_bit_row_packing_layout():
         for t in range(w.shape[1] * 32):
             bit = (int(w[c, t // 32]) >> (t % 32)) & 1
             assert bit == (x[c, t] if t < 301 else 0)
+
+
+def test_multirate_host_logic_matches_the_oracle(snd, orc):
+    """Scrunch factors and the cross-band merge are host code: compared with the oracle here."""
+    f = synth.channel_freqs(1024)
+    dms = np.concatenate([np.linspace(0, 3000, 801), [289.0, 289.5, 578.0, 578.5, 1157.0, 2313.5]])
+    for s_max in (1, 2, 16):
+        assert np.array_equal(snd.scrunch_factors(f, dms, 0.138e-3, s_max), orc.scrunch_factors(f, dms, 0.138e-3, s_max))
+    f64 = synth.channel_freqs(64)
+    assert np.array_equal(snd.scrunch_factors(f64, dms[:200], 0.138e-3), orc.scrunch_factors(f64, dms[:200], 0.138e-3))
+    rng = np.random.default_rng(8)
+    for trial in range(20):
+        n = int(rng.integers(0, 40))
+        cands = [dict(dm=float(rng.integers(0, 200)), t_ms=float(rng.integers(0, 2000)),
+                      snr=float(rng.integers(6, 12)), band=0, k=i, width=1, t=0, npix=1) for i in range(n)]
+        got = snd.merge_candidates(cands)
+        want = orc.merge_candidates(cands)
+        assert [(g["dm"], g["t_ms"], g["snr"], g["k"]) for g in got] == [(w["dm"], w["t_ms"], w["snr"], w["k"])
+                                                                         for w in want]
