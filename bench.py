@@ -80,9 +80,9 @@ def parse():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one plain 1 GiB device copy first (scale reference for HBM counters)")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default stage schedule")
-    ap.add_argument("--legs", default="direct,batch,serve",
+    ap.add_argument("--legs", default="direct,multirate,batch,serve",
                     help="extra measurements after the headline: direct (the same block without shared neurons), "
-                         "batch (48 beams), serve (streaming loop)")
+                         "multirate (scrunch bands), batch (48 beams), serve (streaming loop)")
     ap.add_argument("--serve-seconds", type=float, default=12.0, help="real-time length of each serving run")
     return ap.parse_args()
 
@@ -130,6 +130,29 @@ def direct_leg(snd, torch, spec, x, pkw, dev, ref_out, reps=3):
     return dict(method="direct (no shared neurons)", ms=round(ms, 3), value=p.ndm * p.n_out / (ms * 1e-3),
                 unit="DM-time samples/s", kernel=info["stage_kernel"][0], inputs_per_sample=info["stage_entries"][0],
                 identical_to_snd=bool(torch.equal(out, ref_out)), rel_rms_vs_snd=rel)
+
+
+def multirate_leg(snd, torch, spec, zt, mode, dev, reps=3):
+    """The same block through the multi-rate pipeline: DM bands by scrunch factor (S = 1..16),
+    one plan per band on a scrunched, re-encoded copy, detection per band, cross-band merge."""
+    thr = {"float": None, "graded": [1.0, 2.0, 3.0, 4.0], "binary": [2.0]}[mode]
+    kw = dict(k_leaf=2, k_int=1) if mode == "binary" else {}
+    t = time.perf_counter()
+    mr = snd.MultiRate(spec.freqs, spec.dms, spec.tsamp_s, spec.nsamp, mode=mode, thresholds=thr,
+                       widths=spec.widths, threshold=7.0, branching=spec.branching, device=dev, **kw)
+    build_s = time.perf_counter() - t
+    merged, _ = mr.run(zt)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(reps):
+        merged, per_band = mr.run(zt)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t) * 1e3 / reps
+    bands = [dict(s=b["s"], dms=int(b["idx"].size), n_out=b["plan"].n_out, candidates=len(pb))
+             for b, pb in zip(mr.bands, per_band)]
+    return dict(method="multi-rate (scrunch bands, per-band trees, merged candidates)", mode=mode,
+                ms_per_block=round(ms, 3), plan_build_s=round(build_s, 2), bands=bands, candidates=len(merged),
+                note="includes scrunch, encode, trees, detection of every band and the merge; synchronous")
 
 
 def batch_leg(snd, synth, torch, dev, reps=3):
@@ -526,6 +549,16 @@ def main():
         result["direct"] = direct_leg(snd, torch, spec, x, pkw, dev, ref)
         result["direct"]["snd_tree_ms"] = round(float(stage_ms.sum()), 3)
         log(f"[bench] direct: {result['direct']['ms']} ms vs tree {result['direct']['snd_tree_ms']} ms")
+    if "multirate" in legs:
+        log("[bench] multi-rate pipeline on the same block")
+        del outs, ws, detector
+        torch.cuda.empty_cache()
+        zt = torch.from_numpy(z).to(dev)
+        result["multirate"] = multirate_leg(snd, torch, spec, zt, mode, dev)
+        result["multirate"]["single_rate_ms_per_block"] = round(ms_step, 3)
+        log(f"[bench] multirate: {result['multirate']['ms_per_block']} ms per block")
+        del zt
+        outs = ws = detector = None
     if legs:
         del x, outs, ws, detector, plan
         torch.cuda.empty_cache()
