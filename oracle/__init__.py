@@ -27,6 +27,8 @@ What pins each function to something other than itself (tests/test_oracle_*.py):
 * scrunch_factors -- the printed Northern Cross band edges (289 / 578 / 1157 / 2313).
 * scrunch        -- identity at S = 1, constant rows, conservation of the summed samples.
 * merge_candidates -- hand-built candidate lists.
+* sigma_clip_stats, normalize -- a hand-evaluated clipped outlier; no clipping reduces to the
+                   plain mean and standard deviation; the normal tail rate after normalising.
 * candidates    -- hand-built masks (row gaps 9 / 10, diagonal pairs) and scipy's closing and
                    labelling on padded planes.
 * fire_probability, cascade, binary_snr -- Table 1 values.
@@ -347,3 +349,31 @@ def merge_candidates(cands, dm_tol: float = 20.0, t_tol_ms: float = 200.0) -> li
             continue
         kept.append(c)
     return sorted(kept, key=lambda c: (c["t_ms"], c["dm"]))
+
+
+# --------------------------------------------------------------------------------------
+# Front end (Methods, "Input encoding"): two-pass sigma-clip normalisation of raw power.
+# --------------------------------------------------------------------------------------
+def sigma_clip_stats(p, clip: float = 5.0) -> np.ndarray:
+    """float64 [nchan][2] (mu, sigma) per channel: mean and population standard deviation of
+    the raw power, then of the power clipped to [mu0 - clip sigma0, mu0 + clip sigma0] (each
+    value outside moved to the nearer bound), in FP64."""
+    x = np.asarray(p, dtype=np.float64)
+    out = np.empty((x.shape[0], 2), dtype=np.float64)
+    for c in range(x.shape[0]):
+        row = x[c]
+        mu0 = row.mean()
+        s0 = math.sqrt(((row - mu0) ** 2).mean())
+        clipped = np.minimum(np.maximum(row, mu0 - clip * s0), mu0 + clip * s0)
+        mu = clipped.mean()
+        out[c, 0] = mu
+        out[c, 1] = math.sqrt(((clipped - mu) ** 2).mean())
+    return out
+
+
+def normalize(p, stats) -> np.ndarray:
+    """float32 z = (P - mu) / sigma per channel, the quotient taken in FP64 and rounded once
+    (the encoder then compares it with its thresholds in FP32, as the library does)."""
+    x = np.asarray(p, dtype=np.float64)
+    st = np.asarray(stats, dtype=np.float64)
+    return ((x - st[:, 0:1]) / st[:, 1:2]).astype(np.float32)
