@@ -201,6 +201,21 @@ snd_status snd_encode(const float *d_z, int64_t z_pitch, int32_t time_major, int
 snd_status snd_encode_bits(const float *d_z, int64_t z_pitch, int32_t time_major, int32_t nchan, int64_t nsamp,
                            float threshold, uint32_t *d_out, int64_t out_pitch, void *stream);
 
+/*
+ * Front end (Methods, "Input encoding"): two-pass sigma-clip normalisation of raw power.
+ * snd_channel_stats writes d_stats[2c] = mu_c and d_stats[2c+1] = sigma_c (device float64
+ * [nchan][2]): the mean and population standard deviation of channel c's nsamp raw samples,
+ * then of the same samples clipped to [mu0 - clip*sigma0, mu0 + clip*sigma0] (values outside
+ * moved to the nearer bound), all in FP64.  snd_normalize writes d_z[c][t] = (P - mu_c) /
+ * sigma_c, the quotient in FP64 rounded once to float32 (the encoders then threshold z in FP32).
+ * d_p [nchan][p_pitch] and d_z [nchan][z_pitch] float32, channel-major; clip > 0.
+ * Asynchronous on stream.
+ */
+snd_status snd_channel_stats(const float *d_p, int64_t p_pitch, int32_t nchan, int64_t nsamp, double clip,
+                             double *d_stats, void *stream);
+snd_status snd_normalize(const float *d_p, int64_t p_pitch, int32_t nchan, int64_t nsamp, const double *d_stats,
+                         float *d_z, int64_t z_pitch, void *stream);
+
 /* Float32 -> BF16 or F16 cast with round-to-nearest-even (input staging for the reduced-
  * precision float mode).  d_src [rows][src_pitch] float32, d_dst [rows][dst_pitch] of
  * dst_dtype.  Asynchronous on stream. */

@@ -7,11 +7,11 @@ PyTorch only provides device memory and HIP streams.
 """
 
 from ._capi import SndError, LIB_PATH  # noqa: F401
-from .plan import Plan, autotune, encode, encode_bits, cast  # noqa: F401
+from .plan import Plan, autotune, encode, encode_bits, cast, channel_stats, normalize  # noqa: F401
 from .detect import Detector  # noqa: F401
 from .stream import Stream, history_bytes  # noqa: F401
 from .batch import Batch, records_bytes  # noqa: F401
 from .multirate import MultiRate, scrunch, scrunch_factors, merge_candidates  # noqa: F401
 
 __all__ = ["Plan", "autotune", "Detector", "Stream", "Batch", "history_bytes", "records_bytes", "encode", "encode_bits",
-           "cast", "MultiRate", "scrunch", "scrunch_factors", "merge_candidates", "SndError", "LIB_PATH"]
+           "cast", "channel_stats", "normalize", "MultiRate", "scrunch", "scrunch_factors", "merge_candidates", "SndError", "LIB_PATH"]

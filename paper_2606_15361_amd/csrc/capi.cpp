@@ -309,6 +309,28 @@ snd_status snd_encode_bits(const float *d_z, int64_t z_pitch, int32_t time_major
     return SND_OK;
 }
 
+snd_status snd_channel_stats(const float *d_p, int64_t p_pitch, int32_t nchan, int64_t nsamp, double clip,
+                             double *d_stats, void *stream)
+{
+    if (!d_p || !d_stats) return fail(SND_ERR_INVALID, "null pointer");
+    if (nchan < 1 || nsamp < 1 || p_pitch < nsamp || !(clip > 0.0) || !std::isfinite(clip))
+        return fail(SND_ERR_INVALID, "bad nchan, nsamp, pitch or clip");
+    int e = snd::launch_chanstats(d_p, p_pitch, nchan, nsamp, clip, d_stats, stream);
+    if (e) return hip_fail(e, "channel statistics launch");
+    return SND_OK;
+}
+
+snd_status snd_normalize(const float *d_p, int64_t p_pitch, int32_t nchan, int64_t nsamp, const double *d_stats,
+                         float *d_z, int64_t z_pitch, void *stream)
+{
+    if (!d_p || !d_stats || !d_z) return fail(SND_ERR_INVALID, "null pointer");
+    if (nchan < 1 || nchan > 65535 || nsamp < 1 || p_pitch < nsamp || z_pitch < nsamp)
+        return fail(SND_ERR_INVALID, "bad nchan, nsamp or pitch");
+    int e = snd::launch_normalize(d_p, p_pitch, nchan, nsamp, d_stats, d_z, z_pitch, stream);
+    if (e) return hip_fail(e, "normalize launch");
+    return SND_OK;
+}
+
 snd_status snd_cast(const float *d_src, int64_t src_pitch, int64_t rows, int64_t cols, void *d_dst, int64_t dst_pitch,
                     int32_t dst_dtype, void *stream)
 {

@@ -232,6 +232,73 @@ __global__ __launch_bounds__(256) void k_scrunch(const float *z, int64_t zp, int
     out[(int64_t)c * op + t] = acc * r;
 }
 
+// Sigma-clip statistics of one channel per workgroup: a first FP64 pass about the channel's
+// first sample gives mu0 and sigma0, a second pass the same statistics of the clipped values
+// (about the clip range's centre, mu0).  Loads are coalesced across the workgroup.
+__device__ inline void block_sum2(double &a, double &b, double (*sh)[256], int tid)
+{
+    sh[0][tid] = a;
+    sh[1][tid] = b;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (tid < w) {
+            sh[0][tid] += sh[0][tid + w];
+            sh[1][tid] += sh[1][tid + w];
+        }
+        __syncthreads();
+    }
+    a = sh[0][0];
+    b = sh[1][0];
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(256) void k_chanstats(const float *p, int64_t pp, int64_t n, double clip, double *stats)
+{
+    __shared__ double sh[2][256];
+    const int c = blockIdx.x, tid = threadIdx.x;
+    const float *row = p + (int64_t)c * pp;
+    const double shift = (double)row[0];
+    double a = 0.0, b = 0.0;
+    for (int64_t t = tid; t < n; t += 256) {
+        const double d = (double)row[t] - shift;
+        a += d;
+        b += d * d;
+    }
+    block_sum2(a, b, sh, tid);
+    const double dn = (double)n;
+    const double m1 = a / dn;
+    const double mu0 = shift + m1;
+    const double v0 = b / dn - m1 * m1;
+    const double s0 = v0 > 0.0 ? sqrt(v0) : 0.0;
+    const double lo = mu0 - clip * s0, hi = mu0 + clip * s0;
+    a = 0.0;
+    b = 0.0;
+    for (int64_t t = tid; t < n; t += 256) {
+        double v = (double)row[t];
+        v = v < lo ? lo : (v > hi ? hi : v);
+        const double d = v - mu0;
+        a += d;
+        b += d * d;
+    }
+    block_sum2(a, b, sh, tid);
+    if (tid == 0) {
+        const double m = a / dn;
+        const double v = b / dn - m * m;
+        stats[2 * c] = mu0 + m;
+        stats[2 * c + 1] = v > 0.0 ? sqrt(v) : 0.0;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_normalize(const float *p, int64_t pp, int64_t n, const double *stats,
+                                                   float *z, int64_t zp)
+{
+    const int c = blockIdx.y;
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (t >= n) return;
+    const double mu = stats[2 * c], sg = stats[2 * c + 1];
+    z[(int64_t)c * zp + t] = (float)(((double)p[(int64_t)c * pp + t] - mu) / sg);
+}
+
 template <typename TO>
 __global__ __launch_bounds__(256) void k_cast(const float *src, int64_t sp, int64_t cols, TO *dst, int64_t dp)
 {
@@ -293,6 +360,20 @@ int launch_scrunch(const float *z, int64_t zp, int nchan, int64_t nout, int s, f
 {
     dim3 grid((uint32_t)((nout + 255) / 256), (uint32_t)nchan);
     hipLaunchKernelGGL(k_scrunch, grid, dim3(256), 0, (hipStream_t)stream, z, zp, nout, s, r, out, op);
+    return (int)hipGetLastError();
+}
+
+int launch_chanstats(const float *p, int64_t pp, int nchan, int64_t n, double clip, double *stats, void *stream)
+{
+    hipLaunchKernelGGL(k_chanstats, dim3((uint32_t)nchan), dim3(256), 0, (hipStream_t)stream, p, pp, n, clip, stats);
+    return (int)hipGetLastError();
+}
+
+int launch_normalize(const float *p, int64_t pp, int nchan, int64_t n, const double *stats, float *z, int64_t zp,
+                     void *stream)
+{
+    dim3 grid((uint32_t)((n + 255) / 256), (uint32_t)nchan);
+    hipLaunchKernelGGL(k_normalize, grid, dim3(256), 0, (hipStream_t)stream, p, pp, n, stats, z, zp);
     return (int)hipGetLastError();
 }
 

@@ -251,6 +251,33 @@ def encode_bits(z, threshold: float, time_major: bool = False, out=None, stream=
     return out
 
 
+def channel_stats(p, clip: float = 5.0, stream=None):
+    """Two-pass sigma-clip statistics of raw power p [nchan][nsamp] (float32, on the GPU):
+    float64 [nchan][2] of (mu, sigma) per channel (snd_channel_stats)."""
+    import torch
+    if p.dtype != torch.float32 or p.stride(1) != 1:
+        raise TypeError("p must be float32 with unit inner stride")
+    st = torch.empty((p.shape[0], 2), dtype=torch.float64, device=p.device)
+    capi.check(capi.lib().snd_channel_stats(C.c_void_p(p.data_ptr()), p.stride(0), p.shape[0], p.shape[1],
+                                            float(clip), C.c_void_p(st.data_ptr()), _stream_handle(stream, p.device)))
+    return st
+
+
+def normalize(p, stats, out=None, stream=None):
+    """z = (P - mu) / sigma per channel as float32 (snd_normalize)."""
+    import torch
+    if p.dtype != torch.float32 or p.stride(1) != 1:
+        raise TypeError("p must be float32 with unit inner stride")
+    if stats.dtype != torch.float64 or not stats.is_contiguous() or stats.shape != (p.shape[0], 2):
+        raise ValueError("stats must be contiguous float64 [nchan][2]")
+    if out is None:
+        out = torch.empty(p.shape, dtype=torch.float32, device=p.device)
+    capi.check(capi.lib().snd_normalize(C.c_void_p(p.data_ptr()), p.stride(0), p.shape[0], p.shape[1],
+                                        C.c_void_p(stats.data_ptr()), C.c_void_p(out.data_ptr()), out.stride(0),
+                                        _stream_handle(stream, p.device)))
+    return out
+
+
 def cast(x, dtype: str, stream=None):
     """float32 [rows][cols] -> bf16/f16 with round-to-nearest-even, on the GPU."""
     import torch
