@@ -109,7 +109,7 @@ constexpr int kGroupMaxSpan = 256;   // offset spread of one staged window (wind
 constexpr int kGroupSlotsPerWave = 8;  // staged windows per wave per batch
 constexpr int kAnchorTile = 512;     // reference samples per anchored sub-tile (8 per lane)
 constexpr int kAnchorMaxTile = 2048;  // largest anchored window per workgroup
-constexpr int kAnchorWaves = 8;      // waves per anchored workgroup
+constexpr int kAnchorWaves = 16;     // waves per anchored workgroup
 constexpr int kAnchorLdsBytes = 65536;
 constexpr int kAnchorLdsTarget = 40960;  // larger windows only while four workgroups fit a CU
 constexpr int kAnchorBitsW = 4;                         // bit input: words per lane
