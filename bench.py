@@ -29,13 +29,19 @@ KERNEL_SYMBOL = {"generic": "k_stage", "group_lds": "k_group", "anchored": "k_an
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic.json")
 
 
+# sources that decide what the tree kernels do: device code, the headers it includes, the plan
+# builder (tables, windows, batches) and the launch path; the other host files (detection's
+# host part, streaming, batching, tuning, multi-rate, validation) do not change their traffic
+DIGEST_CPP = ("plan.cpp", "capi.cpp")
+
+
 def source_digest():
-    """Digest of the library sources: counter readings are only valid for the code they were taken on."""
+    """Digest of the sources the counter readings depend on: they are only valid for that code."""
     import hashlib
     h = hashlib.sha256()
     for d in ("paper_2606_15361_amd/csrc", "include"):
         for name in sorted(os.listdir(os.path.join(ROOT, d))):
-            if name.endswith((".hip", ".h", ".cpp")):
+            if name.endswith((".hip", ".h")) or name in DIGEST_CPP:
                 with open(os.path.join(ROOT, d, name), "rb") as f:
                     h.update(name.encode() + b"\0" + f.read())
     return h.hexdigest()[:16]
@@ -132,6 +138,24 @@ def direct_leg(snd, torch, spec, x, pkw, dev, ref_out, reps=3):
                 identical_to_snd=bool(torch.equal(out, ref_out)), rel_rms_vs_snd=rel)
 
 
+def completeness(snd, spec, cands, n_out):
+    """Injected pulses of the block recovered by the candidates: greedy one-to-one matching in
+    decreasing S/N with |dDM| <= 10 and |dt| <= 0.5 W_eff (snd_match_injections).  cands:
+    dicts with dm, snr and the peak boxcar's first sample t and width in native samples
+    (t_centre = t + (width - 1) / 2).  Only pulses arriving inside the n_out valid samples
+    count."""
+    tms = spec.tsamp_s * 1e3
+    pulses = [p for p in spec.pulses if 0.0 <= p.t0 < n_out]
+    if not pulses:
+        return None
+    weff = snd.effective_width(spec.freqs, spec.tsamp_s, [p.dm for p in pulses], [p.width_ms for p in pulses])
+    match, n = snd.match_injections([c["dm"] for c in cands], [(c["t"] + 0.5 * (c["width"] - 1)) * tms for c in cands],
+                                    [c["snr"] for c in cands], [p.dm for p in pulses], [p.t0 * tms for p in pulses],
+                                    weff, 10.0, 0.5)
+    return dict(injected=len(pulses), matched=n, completeness=round(n / len(pulses), 4), candidates=len(cands),
+                rule="greedy one-to-one in decreasing S/N; |dDM| <= 10, |dt| <= 0.5 W_eff")
+
+
 def multirate_leg(snd, torch, spec, zt, mode, dev, reps=3):
     """The same block through the multi-rate pipeline: DM bands by scrunch factor (S = 1..16),
     one plan per band on a scrunched, re-encoded copy, detection per band, cross-band merge."""
@@ -150,8 +174,13 @@ def multirate_leg(snd, torch, spec, zt, mode, dev, reps=3):
     ms = (time.perf_counter() - t) * 1e3 / reps
     bands = [dict(s=b["s"], dms=int(b["idx"].size), n_out=b["plan"].n_out, candidates=len(pb))
              for b, pb in zip(mr.bands, per_band)]
+    # merged candidates in native samples: band sample t of scrunch s starts at native s t
+    native = [dict(dm=c["dm"], snr=c["snr"], t=c["t"] * mr.bands[c["band"]]["s"],
+                   width=c["width"] * mr.bands[c["band"]]["s"]) for c in merged]
+    n_out = min(b["plan"].n_out * b["s"] for b in mr.bands)
     return dict(method="multi-rate (scrunch bands, per-band trees, merged candidates)", mode=mode,
                 ms_per_block=round(ms, 3), plan_build_s=round(build_s, 2), bands=bands, candidates=len(merged),
+                detection=completeness(snd, spec, native, n_out),
                 note="includes scrunch, encode, trees, detection of every band and the merge; synchronous")
 
 
@@ -464,13 +493,16 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     ncand = 0
+    last = None
     for k in range(args.steps):
         events[k][0].record(stream)
         c, pending = step(k, events[k], pending)
         if c is not None:
-            ncand = len(c)
+            last = c
     if pending is not None:
-        ncand = len(detector.collect(pending))
+        last = detector.collect(pending)
+    if last is not None:
+        ncand = len(last)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     stage_ms = np.zeros(nst)
@@ -532,6 +564,7 @@ def main():
         "stage_alg_gb": [round(b / 1e9, 3) for b in info["stage_alg_bytes"]],
         "detect_ms": round(det_ms, 4),
         "candidates": ncand,
+        "detection": completeness(snd, spec, last, plan.n_out) if last is not None else None,
         "thresholded_cells": detector.npixels if detector is not None else 0,
         "plan": {"neurons": info["n_neurons"], "synapses": info["n_synapses"],
                  "workspace_gib": round(info["workspace_bytes"] / 2**30, 3)},

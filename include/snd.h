@@ -350,6 +350,34 @@ snd_status snd_merge_candidates(int64_t n, const snd_band_candidate *h_in, doubl
                                 snd_band_candidate *h_out, int64_t *h_count);
 
 /* ---------------------------------------------------------------------------------------
+ * Validation against injected pulses (Methods, "Validation methodology").  Host only.
+ * --------------------------------------------------------------------------------------- */
+
+/* Effective width of injected pulses at their DMs, in ms: the intrinsic width, the
+ * dispersive smearing inside one channel and the sampling time added in quadrature,
+ * sqrt(w^2 + tau^2 + dt^2), with tau = K_DM d df / fc^3 as in Eq. scrunch (fc the band
+ * centre, the mean of the highest and lowest channel frequency; df the channel spacing).
+ * The paper names this width without a formula; this is the reading used here.
+ * freq_mhz [nchan] host, > 0; dm [n] >= 0 and w_int_ms [n] >= 0 host; h_weff_ms [n] host
+ * output.  SND_ERR_INVALID on bad arguments (nothing written). */
+snd_status snd_effective_width(int32_t nchan, const double *freq_mhz, double tsamp_s, int64_t n, const double *dm,
+                               const double *w_int_ms, double *h_weff_ms);
+
+/* Greedy one-to-one matching of candidates to injections.  Candidates are taken in
+ * decreasing S/N (equal S/N: input order).  Each takes the unmatched injection j with
+ * |dm - inj_dm[j]| <= dm_tol and |t_ms - inj_t_ms[j]| <= t_frac * inj_weff_ms[j] that is
+ * nearest in time (ties: nearer in DM, then the lower index), or none.  The paper uses
+ * dm_tol = 10 pc cm^-3 and t_frac = 0.5.  Candidate arrays [n_cand] and injection arrays
+ * [n_inj] are host, finite; a candidate's time is the one the caller compares with the
+ * injection's (e.g. the centre of its peak boxcar at the top of the band).  Writes h_match
+ * [n_inj] (host): the matched candidate's index, or -1; and *h_nmatched, the number of
+ * matched injections (completeness = *h_nmatched / n_inj).  SND_ERR_INVALID on bad
+ * arguments, with h_match unspecified. */
+snd_status snd_match_injections(int64_t n_cand, const double *cand_dm, const double *cand_t_ms, const double *cand_snr,
+                                int64_t n_inj, const double *inj_dm, const double *inj_t_ms, const double *inj_weff_ms,
+                                double dm_tol, double t_frac, int32_t *h_match, int64_t *h_nmatched);
+
+/* ---------------------------------------------------------------------------------------
  * Batched execution.
  *
  * Several beams, each with its own uploaded plan (DM grids, lengths, modes and storage types

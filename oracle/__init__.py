@@ -29,6 +29,11 @@ What pins each function to something other than itself (tests/test_oracle_*.py):
 * merge_candidates -- hand-built candidate lists.
 * sigma_clip_stats, normalize -- a hand-evaluated clipped outlier; no clipping reduces to the
                    plain mean and standard deviation; the normal tail rate after normalising.
+* effective_width -- the printed scrunch band edges (the smearing term equals S dt there),
+                   DM 0 and zero-width special cases, a 3-4-5 right triangle.
+* match_injections -- hand-worked cases (tests/golden/injection_match.txt); all-admissible
+                   windows match min(candidates, injections); a one-to-one structure reduces to
+                   scipy's linear assignment.
 * candidates    -- hand-built masks (row gaps 9 / 10, diagonal pairs) and scipy's closing and
                    labelling on padded planes.
 * fire_probability, cascade, binary_snr -- Table 1 values.
@@ -377,3 +382,51 @@ def normalize(p, stats) -> np.ndarray:
     x = np.asarray(p, dtype=np.float64)
     st = np.asarray(stats, dtype=np.float64)
     return ((x - st[:, 0:1]) / st[:, 1:2]).astype(np.float32)
+
+
+# --------------------------------------------------------------------------------------
+# Validation against injected pulses (Methods, "Validation methodology").
+# --------------------------------------------------------------------------------------
+def effective_width(freqs, tsamp_s: float, dms, w_int_ms) -> np.ndarray:
+    """float64 [n]: effective width in ms of pulses of intrinsic width w_int_ms at DM dms.
+    The paper names the width at the injection DM without a formula; read here as the
+    intrinsic width, the smearing inside one channel (Eq. scrunch: K_DM d df / fc^3 with fc the
+    band centre and df the channel spacing) and the sampling time added in quadrature."""
+    f = np.asarray(freqs, dtype=np.float64)
+    fc = 0.5 * (f.max() + f.min())
+    df = (f.max() - f.min()) / (f.size - 1) if f.size > 1 else 0.0
+    dt = tsamp_s * 1e3
+    out = []
+    for d, w in zip(np.asarray(dms, dtype=np.float64).ravel(), np.asarray(w_int_ms, dtype=np.float64).ravel()):
+        tau = K_DM * d * df / fc ** 3
+        out.append(math.sqrt(w * w + tau * tau + dt * dt))
+    return np.array(out, dtype=np.float64)
+
+
+def match_injections(cands, injections, dm_tol: float = 10.0, t_frac: float = 0.5):
+    """Greedy one-to-one matching (Methods, "Validation methodology").  cands: dicts with dm,
+    t_ms, snr; injections: dicts with dm, t_ms, w_eff_ms.  Candidates go in decreasing S/N
+    (equal S/N: list order); each takes, among the injections not yet matched whose DM is
+    within dm_tol and whose time is within t_frac * w_eff_ms, the one nearest in time (then
+    nearest in DM, then first in the list).  Returns (list: matched candidate index per
+    injection or -1, number of injections matched); completeness is the number over the
+    injection count."""
+    order = sorted(range(len(cands)), key=lambda i: -cands[i]["snr"])  # sorted() is stable
+    match = [-1] * len(injections)
+    for i in order:
+        c = cands[i]
+        best = None
+        for j, q in enumerate(injections):
+            if match[j] >= 0:
+                continue
+            ddm = abs(c["dm"] - q["dm"])
+            dt = abs(c["t_ms"] - q["t_ms"])
+            if ddm > dm_tol or dt > t_frac * q["w_eff_ms"]:
+                continue
+            key = (dt, ddm, j)
+            if best is None or key < best:
+                best = key
+        if best is not None:
+            match[best[2]] = i
+    return match, sum(1 for m in match if m >= 0)
+

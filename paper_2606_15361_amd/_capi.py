@@ -119,6 +119,8 @@ def lib() -> C.CDLL:
         "snd_scrunch_factors": ([I32, P, C.c_double, I32, P, I32, P], I32),
         "snd_scrunch": ([P, I64, I32, I64, I32, P, I64, P], I32),
         "snd_merge_candidates": ([I64, P, C.c_double, C.c_double, P, C.POINTER(I64)], I32),
+        "snd_effective_width": ([I32, P, C.c_double, I64, P, P, P], I32),
+        "snd_match_injections": ([I64, P, P, P, I64, P, P, P, C.c_double, C.c_double, P, C.POINTER(I64)], I32),
         "snd_last_error": ([], C.c_char_p),
         "snd_version": ([], C.c_char_p),
     }

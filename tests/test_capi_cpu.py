@@ -279,3 +279,36 @@ def test_multirate_host_logic_matches_the_oracle(snd, orc):
         want = orc.merge_candidates(cands)
         assert [(g["dm"], g["t_ms"], g["snr"], g["k"]) for g in got] == [(w["dm"], w["t_ms"], w["snr"], w["k"])
                                                                          for w in want]
+
+
+def test_validation_host_logic_matches_the_oracle(snd, orc):
+    """Effective widths and injection matching are host code: compared with the oracle here,
+    on the hand-worked cases and on random ones with ties in S/N, time and DM."""
+    import json
+    f = synth.channel_freqs(1024)
+    dms = np.linspace(0, 3000, 301)
+    ws = np.linspace(0.1, 20, 301)
+    assert np.allclose(snd.effective_width(f, 0.138e-3, dms, ws), orc.effective_width(f, 0.138e-3, dms, ws),
+                       rtol=1e-15, atol=0.0)
+    g = json.load(open(os.path.join(ROOT, "tests", "golden", "injection_match.json")))
+    for case in g["cases"]:
+        c = np.array(case["candidates"], dtype=np.float64).reshape(-1, 3)
+        q = np.array(case["injections"], dtype=np.float64).reshape(-1, 3)
+        match, n = snd.match_injections(c[:, 0], c[:, 1], c[:, 2], q[:, 0], q[:, 1], q[:, 2], g["dm_tol"], g["t_frac"])
+        assert list(match) == case["expected"], case["name"]
+    rng = np.random.default_rng(12)
+    for trial in range(40):
+        nc, ni = int(rng.integers(0, 30)), int(rng.integers(0, 12))
+        # coarse values so that ties and bounds occur
+        c = np.stack([rng.integers(0, 40, nc) * 1.0, rng.integers(0, 20, nc) * 0.5, rng.integers(6, 10, nc) * 1.0], 1)
+        q = np.stack([rng.integers(0, 40, ni) * 1.0, rng.integers(0, 20, ni) * 0.5, rng.integers(0, 8, ni) * 1.0], 1)
+        match, n = snd.match_injections(c[:, 0], c[:, 1], c[:, 2], q[:, 0], q[:, 1], q[:, 2], 5.0, 0.5)
+        want, wn = orc.match_injections([dict(dm=a, t_ms=b, snr=s) for a, b, s in c],
+                                        [dict(dm=a, t_ms=b, w_eff_ms=w) for a, b, w in q], 5.0, 0.5)
+        assert list(match) == want and n == wn
+    with pytest.raises(snd.SndError):
+        snd.match_injections([1.0], [1.0], [float("nan")], [1.0], [1.0], [1.0])
+    with pytest.raises(snd.SndError):
+        snd.match_injections([1.0], [1.0], [7.0], [1.0], [1.0], [-1.0])
+    with pytest.raises(snd.SndError):
+        snd.effective_width(f, 0.138e-3, [-1.0], [1.0])

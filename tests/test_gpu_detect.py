@@ -187,6 +187,21 @@ def test_config2_pulse_recovery_float(snd, orc):
         assert abs(float(o_snr[0].max()) - best["snr"]) <= 0.01 * best["snr"]
         checked += 1
     assert checked == 3
+    # completeness under the paper's matching rule (|dDM| <= 10, |dt| <= 0.5 W_eff, greedy in
+    # decreasing S/N): the library's host matching agrees with the oracle's on these candidates,
+    # and the three brightest pulses are matched
+    tms = spec.tsamp_s * 1e3
+    pulses = [q for q in spec.pulses if 0 <= q.t0 < p.n_out]
+    weff = snd.effective_width(spec.freqs, spec.tsamp_s, [q.dm for q in pulses], [q.width_ms for q in pulses])
+    ct = [(c["t"] + 0.5 * (c["width"] - 1)) * tms for c in cands]
+    match, n = snd.match_injections([c["dm"] for c in cands], ct, [c["snr"] for c in cands], [q.dm for q in pulses],
+                                    [q.t0 * tms for q in pulses], weff)
+    want, wn = orc.match_injections([dict(dm=c["dm"], t_ms=t, snr=c["snr"]) for c, t in zip(cands, ct)],
+                                    [dict(dm=q.dm, t_ms=q.t0 * tms, w_eff_ms=w) for q, w in zip(pulses, weff)])
+    assert list(match) == want and n == wn
+    for j in sorted(range(len(pulses)), key=lambda j: -pulses[j].snr)[:3]:
+        assert match[j] >= 0, (pulses[j], weff[j])
+    _say(f"config2 float: {n} of {len(pulses)} injected pulses matched")
 
 
 PAPER_WIDTHS = [1, 2, 4, 8, 16, 32, 64, 128, 256, 512, 1024]
