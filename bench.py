@@ -573,6 +573,23 @@ def main():
         result["autotune"] = [dict(stage_levels=hex(t["stage_levels"]), ms=round(t["ms"], 3),
                                    workspace_gib=round(t["workspace_bytes"] / 2**30, 2)) for t in tuned]
     result["config"]["stage_levels"] = hex(stage_levels)
+    if detector is not None:
+        # the matched filter's sigma options on the last plane: the standard deviation (the
+        # default above) and the median absolute deviation; synchronous runs, host part included
+        plane = outs[(args.steps - 1) % 2]
+        opt = {}
+        for name in ("std", "mad"):
+            d2 = snd.Detector(plan, widths=spec.widths, threshold=7.0, device=dev, sigma=name)
+            c2 = d2.run(plane)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            for _ in range(3):
+                c2 = d2.run(plane)
+            torch.cuda.synchronize()
+            opt[name] = dict(ms=round((time.perf_counter() - t) * 1e3 / 3, 3), candidates=len(c2),
+                             detection=completeness(snd, spec, c2, plan.n_out))
+            del d2
+        result["detect_sigma"] = opt
     legs = [l for l in args.legs.split(",") if l and l != "none"]
     if "direct" in legs and plan.in_dtype == "bits":
         result["direct"] = {"skipped": "bit input needs the materialised leaf level"}

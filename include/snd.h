@@ -253,6 +253,14 @@ typedef struct {
                                delays are); the paper uses {1,2,4,8} + {16..1024}, alpha 0.1 */
     int64_t max_pixels;     /* capacity of the device list of thresholded cells, >= 1 */
     double width_alpha;     /* >= 0, used when n_base_widths > 0 */
+    int32_t sigma_estimator; /* 0: sigma_k is the row's standard deviation (Methods, "Matched
+                                filtering").  1: sigma_k = MAD_k / Phi^-1(3/4), MAD_k the lower
+                                median of |y_k(t) - m_k| and m_k the row's lower median (rank
+                                floor((n_out - 1) / 2)), the deviation taken in the plane's own
+                                arithmetic (FP32 for float planes); the robust per-row MAD the
+                                paper mentions for bounded (graded) planes.  mu_k stays the mean
+                                and sigma_min still floors sigma_k. */
+    int32_t reserved;        /* set to 0 */
 } snd_detect_desc;
 
 typedef struct {

@@ -34,6 +34,9 @@ What pins each function to something other than itself (tests/test_oracle_*.py):
 * match_injections -- hand-worked cases (tests/golden/injection_match.txt); all-admissible
                    windows match min(candidates, injections); a one-to-one structure reduces to
                    scipy's linear assignment.
+* mad_sigma     -- hand-evaluated rows (odd and even lengths, an outlier), the scale against
+                   scipy's normal quantile, Gaussian rows (MAD sigma ~ the standard deviation),
+                   robustness to a bright burst.
 * candidates    -- hand-built masks (row gaps 9 / 10, diagonal pairs) and scipy's closing and
                    labelling on padded planes.
 * fire_probability, cascade, binary_snr -- Table 1 values.
@@ -101,6 +104,8 @@ def _load():
                                            P, P, P, P]
         lib.orc_matched_filter_rows.argtypes = [C.c_int32, C.c_int64, C.c_int64, P, C.c_int32, P, P, C.c_double,
                                                 P, P, P, P]
+        lib.orc_matched_filter_sigma.argtypes = [C.c_int32, C.c_int64, C.c_int64, P, C.c_int32, P, P, P,
+                                                 C.c_double, P, P, P, P]
         lib.orc_dm_width_counts.argtypes = [C.c_int32, P, C.c_double, C.c_double, C.c_int32, P, C.c_int32, P,
                                             C.c_int32, C.c_double, P]
         lib.orc_candidates.argtypes = [C.c_int64, C.c_int64, P, P, C.c_double, C.c_int32, C.c_int64,
@@ -239,9 +244,10 @@ def dm_width_counts(freqs, dms, tsamp_s: float, widths, n_base: int, alpha: floa
     return out
 
 
-def matched_filter(y, widths, *, integer_plane: bool, sigma_min: float = 0.0, row_nw=None):
+def matched_filter(y, widths, *, integer_plane: bool, sigma_min: float = 0.0, row_nw=None, sigma_rows=None):
     """(snr, width_index, mu, sigma) for a DM-time plane y[ndm][nout]; row_nw: per-row number of
-    leading widths used (None: all)."""
+    leading widths used (None: all); sigma_rows: per-row sigma to use instead of the standard
+    deviation (e.g. mad_sigma), floored by sigma_min like it."""
     lib = _load()
     yy = np.ascontiguousarray(y, dtype=np.float64)
     w = np.ascontiguousarray(widths, dtype=np.int32)
@@ -250,12 +256,35 @@ def matched_filter(y, widths, *, integer_plane: bool, sigma_min: float = 0.0, ro
     mu = np.empty(yy.shape[0], dtype=np.float64)
     sg = np.empty(yy.shape[0], dtype=np.float64)
     rn = None if row_nw is None else np.ascontiguousarray(row_nw, dtype=np.int32)
-    rc = lib.orc_matched_filter_rows(int(integer_plane), yy.shape[0], yy.shape[1], _ptr(yy), w.size, _ptr(w),
-                                     None if rn is None else _ptr(rn), sigma_min, _ptr(snr), _ptr(widx), _ptr(mu),
-                                     _ptr(sg))
+    si = None if sigma_rows is None else np.ascontiguousarray(sigma_rows, dtype=np.float64)
+    rc = lib.orc_matched_filter_sigma(int(integer_plane), yy.shape[0], yy.shape[1], _ptr(yy), w.size, _ptr(w),
+                                      None if rn is None else _ptr(rn), None if si is None else _ptr(si), sigma_min,
+                                      _ptr(snr), _ptr(widx), _ptr(mu), _ptr(sg))
     if rc:
         raise ValueError("widths must be positive and strictly increasing")
     return snr, widx, mu, sg
+
+
+# 1 / Phi^-1(3/4): scales a median absolute deviation to the standard deviation of Gaussian
+# noise (the correctly rounded double of 1.48260221850560186...)
+MAD_SCALE = 1.4826022185056018
+
+
+def mad_sigma(y) -> np.ndarray:
+    """float64 [ndm]: per-row robust sigma, MAD_SCALE times the median absolute deviation (the
+    per-row MAD the paper names for graded planes, Methods "Tree activation modes", as an
+    alternative sigma for the matched filter).  Both medians are lower medians (element
+    floor((n - 1) / 2) of the sorted row); the deviation |y - m| is taken in the plane's own
+    type (integers exactly; float32 planes in float32 arithmetic)."""
+    y = np.asarray(y)
+    out = np.empty(y.shape[0], dtype=np.float64)
+    for k in range(y.shape[0]):
+        row = y[k].astype(np.int64) if np.issubdtype(y.dtype, np.integer) else y[k]
+        r = (row.size - 1) // 2
+        m = np.sort(row)[r]
+        d = np.abs(row - m)  # int64 or float32 arithmetic, as the row's type
+        out[k] = MAD_SCALE * float(np.sort(d)[r])
+    return out
 
 
 def candidates(snr, widx, theta: float, radius: int = 4, n_min: int = 10):

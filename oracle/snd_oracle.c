@@ -481,9 +481,17 @@ int orc_dm_width_counts(int32_t nchan, const double *freq, double tsamp_s, doubl
  * sigma = sqrt(n*S2 - S1*S1)/n with each product and the difference rounded once (exact
  * for 8-bit planes, where every term is an integer below 2^53).
  * ---------------------------------------------------------------------------------- */
+int orc_matched_filter_sigma(int32_t integer_plane, int64_t ndm, int64_t nout, const double *y, int32_t nw,
+                             const int32_t *widths, const int32_t *row_nw, const double *sigma_in, double sigma_min,
+                             double *snr, int32_t *widx, double *mu_out, double *sigma_out);
+
 int orc_matched_filter_rows(int32_t integer_plane, int64_t ndm, int64_t nout, const double *y, int32_t nw,
                             const int32_t *widths, const int32_t *row_nw, double sigma_min, double *snr,
-                            int32_t *widx, double *mu_out, double *sigma_out);
+                            int32_t *widx, double *mu_out, double *sigma_out)
+{
+    return orc_matched_filter_sigma(integer_plane, ndm, nout, y, nw, widths, row_nw, NULL, sigma_min, snr, widx,
+                                    mu_out, sigma_out);
+}
 
 int orc_matched_filter(int32_t integer_plane, int64_t ndm, int64_t nout, const double *y, int32_t nw,
                        const int32_t *widths, double sigma_min, double *snr, int32_t *widx, double *mu_out,
@@ -493,10 +501,12 @@ int orc_matched_filter(int32_t integer_plane, int64_t ndm, int64_t nout, const d
                                    sigma_out);
 }
 
-/* The same with row k restricted to its first row_nw[k] widths (row_nw NULL: all widths). */
-int orc_matched_filter_rows(int32_t integer_plane, int64_t ndm, int64_t nout, const double *y, int32_t nw,
-                            const int32_t *widths, const int32_t *row_nw, double sigma_min, double *snr,
-                            int32_t *widx, double *mu_out, double *sigma_out)
+/* The same with row k restricted to its first row_nw[k] widths (row_nw NULL: all widths), and
+ * sigma of row k given as sigma_in[k] instead of the standard deviation (sigma_in NULL: the
+ * standard deviation); the floor sigma_min applies either way. */
+int orc_matched_filter_sigma(int32_t integer_plane, int64_t ndm, int64_t nout, const double *y, int32_t nw,
+                             const int32_t *widths, const int32_t *row_nw, const double *sigma_in, double sigma_min,
+                             double *snr, int32_t *widx, double *mu_out, double *sigma_out)
 {
     for (int32_t i = 0; i < nw; ++i)
         if (widths[i] < 1 || (i > 0 && widths[i] <= widths[i - 1])) return -1;
@@ -521,6 +531,7 @@ int orc_matched_filter_rows(int32_t integer_plane, int64_t ndm, int64_t nout, co
             for (int64_t t = 0; t < nout; ++t) q += (row[t] - mu) * (row[t] - mu);
             sigma = sqrt(q / (double)nout);
         }
+        if (sigma_in) sigma = sigma_in[k];
         if (sigma < sigma_min) sigma = sigma_min;
         if (mu_out) mu_out[k] = mu;
         if (sigma_out) sigma_out[k] = sigma;

@@ -370,15 +370,113 @@ __global__ __launch_bounds__(kThreads) void k_snr(const T *plane, int64_t pitch,
     }
 }
 
+// Robust row sigma, the MAD option of the matched filter: sigma = kMadScale * MAD, MAD the lower
+// median of |y - m| over the row's valid samples and m the row's lower median (rank
+// floor((n - 1) / 2) of the sorted values; kMadScale = 1 / Phi^-1(3/4) makes it the standard
+// deviation of Gaussian noise).  Both medians are exact: a radix select over an order-preserving
+// integer key of the values, 8 bits per pass over the row, with one histogram per wave in LDS.
+// The deviation is taken in the plane's own arithmetic: exact for integer planes, one FP32
+// subtraction for float planes.  The floor sigma_min applies as for the standard deviation.
+constexpr double kMadScale = 1.4826022185056018;
+
+template <typename T> struct MadKeys;
+template <> struct MadKeys<uint8_t> {
+    static constexpr int kBits = 8;
+    __device__ static uint32_t key(uint8_t v) { return v; }
+    __device__ static uint8_t value(uint32_t k) { return (uint8_t)k; }
+    __device__ static uint32_t dev_key(uint8_t v, uint8_t m) { return v > m ? (uint32_t)(v - m) : (uint32_t)(m - v); }
+    __device__ static double dev_value(uint32_t k) { return (double)k; }
+};
+template <> struct MadKeys<uint16_t> {
+    static constexpr int kBits = 16;
+    __device__ static uint32_t key(uint16_t v) { return v; }
+    __device__ static uint16_t value(uint32_t k) { return (uint16_t)k; }
+    __device__ static uint32_t dev_key(uint16_t v, uint16_t m) { return v > m ? (uint32_t)(v - m) : (uint32_t)(m - v); }
+    __device__ static double dev_value(uint32_t k) { return (double)k; }
+};
+template <> struct MadKeys<float> {
+    static constexpr int kBits = 32;
+    // IEEE order as unsigned order: negative values reversed below the positive ones
+    __device__ static uint32_t key(float v)
+    {
+        const uint32_t u = __float_as_uint(v);
+        return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+    }
+    __device__ static float value(uint32_t k) { return __uint_as_float((k & 0x80000000u) ? (k & 0x7fffffffu) : ~k); }
+    __device__ static uint32_t dev_key(float v, float m) { return key(__builtin_fabsf(v - m)); }
+    __device__ static double dev_value(uint32_t k) { return (double)value(k); }
+};
+
+// Key of rank `rank` (0-based, in increasing order) among key(y) over the row.
+template <typename T, int BITS, typename K>
+__device__ uint32_t radix_select(const T *row, int64_t n, int64_t rank, K key, uint32_t (*hist)[256],
+                                 uint32_t *s_digit, long long *s_rank)
+{
+    const int tid = threadIdx.x, wave = tid >> 6;
+    uint32_t prefix = 0;
+    for (int shift = BITS - 8; shift >= 0; shift -= 8) {
+        for (int i = tid; i < (kThreads / 64) * 256; i += kThreads) (&hist[0][0])[i] = 0u;
+        __syncthreads();
+        const int hs = shift + 8;  // keys that agree with the prefix above this digit take part
+        row_fold(row, n, tid, [&](T v, int) {
+            const uint32_t k = key(v);
+            if ((uint32_t)((uint64_t)(k ^ prefix) >> hs) == 0u) atomicAdd(&hist[wave][(k >> shift) & 255u], 1u);
+        });
+        __syncthreads();
+        if (tid < 256) {
+            uint32_t c = 0;
+#pragma unroll
+            for (int w = 0; w < kThreads / 64; ++w) c += hist[w][tid];
+            hist[0][tid] = c;
+        }
+        __syncthreads();
+        if (tid == 0) {  // the digit whose bin holds the rank; the taking part outnumber it
+            long long r = rank;
+            uint32_t b = 0;
+            for (; b < 255u && r >= (long long)hist[0][b]; ++b) r -= hist[0][b];
+            *s_digit = b;
+            *s_rank = r;
+        }
+        __syncthreads();
+        prefix |= *s_digit << shift;
+        rank = *s_rank;
+        __syncthreads();  // everyone has read the digit before the histogram is cleared
+    }
+    return prefix;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_rowmad(const T *plane, int64_t pitch, int64_t n, double sigma_min,
+                                                       double *stats)
+{
+    __shared__ uint32_t hist[kThreads / 64][256];
+    __shared__ uint32_t s_digit;
+    __shared__ long long s_rank;
+    const int64_t k = blockIdx.x;
+    const T *row = plane + k * pitch;
+    const int64_t r = (n - 1) / 2;
+    using MK = MadKeys<T>;
+    const T m = MK::value(radix_select<T, MK::kBits>(row, n, r, [](T v) { return MK::key(v); }, hist, &s_digit, &s_rank));
+    const uint32_t d = radix_select<T, MK::kBits>(row, n, r, [m](T v) { return MK::dev_key(v, m); }, hist, &s_digit,
+                                                  &s_rank);
+    if (threadIdx.x == 0) {
+        double sg = kMadScale * MK::dev_value(d);
+        if (sg < sigma_min) sg = sigma_min;
+        stats[2 * k + 1] = sg;
+    }
+}
+
 __global__ void k_zero_counter(unsigned int *c) { *c = 0u; }
 
 template <typename T>
-int launch_typed(const void *plane, int64_t pitch, int ndm, int64_t n, double sigma_min, double *stats,
-                 const SnrArgs &a, hipStream_t st)
+int launch_typed(const void *plane, int64_t pitch, int ndm, int64_t n, double sigma_min, int sigma_mad,
+                 double *stats, const SnrArgs &a, hipStream_t st)
 {
     const T *p = static_cast<const T *>(plane);
     if (!a.snr) hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(1), 0, st, a.counter);
     hipLaunchKernelGGL((k_rowstats<T>), dim3((uint32_t)ndm), dim3(kThreads), 0, st, p, pitch, n, sigma_min, stats);
+    if (sigma_mad)  // sigma from the median absolute deviation instead (the mean stays)
+        hipLaunchKernelGGL((k_rowmad<T>), dim3((uint32_t)ndm), dim3(kThreads), 0, st, p, pitch, n, sigma_min, stats);
     dim3 grid((uint32_t)((n + kSnrTile - 1) / kSnrTile), (uint32_t)ndm);
     switch (a.nw) {
 #define SND_NW(N) case N: hipLaunchKernelGGL((k_snr<T, N>), grid, dim3(kThreads), 0, st, p, pitch, n, stats, a); break;
@@ -392,13 +490,13 @@ int launch_typed(const void *plane, int64_t pitch, int ndm, int64_t n, double si
 }  // namespace
 
 int launch_detect(int plane_dtype, const void *plane, int64_t pitch, int ndm, int64_t n, double sigma_min,
-                  double *stats, const SnrArgs &a, void *stream)
+                  int sigma_mad, double *stats, const SnrArgs &a, void *stream)
 {
     hipStream_t st = (hipStream_t)stream;
     switch (plane_dtype) {
-    case SND_DT_U8: return launch_typed<uint8_t>(plane, pitch, ndm, n, sigma_min, stats, a, st);
-    case SND_DT_U16: return launch_typed<uint16_t>(plane, pitch, ndm, n, sigma_min, stats, a, st);
-    case SND_DT_F32: return launch_typed<float>(plane, pitch, ndm, n, sigma_min, stats, a, st);
+    case SND_DT_U8: return launch_typed<uint8_t>(plane, pitch, ndm, n, sigma_min, sigma_mad, stats, a, st);
+    case SND_DT_U16: return launch_typed<uint16_t>(plane, pitch, ndm, n, sigma_min, sigma_mad, stats, a, st);
+    case SND_DT_F32: return launch_typed<float>(plane, pitch, ndm, n, sigma_min, sigma_mad, stats, a, st);
     }
     return (int)hipErrorInvalidValue;
 }

@@ -38,6 +38,10 @@ snd_status check_desc(const snd::PlanImpl &P, const snd_detect_desc *d)
         snd::set_error("threshold must be > 0, sigma_min >= 0, 0 <= closing_radius <= 64, n_min >= 1, max_pixels >= 1");
         return SND_ERR_INVALID;
     }
+    if (d->sigma_estimator != 0 && d->sigma_estimator != 1) {
+        snd::set_error("sigma_estimator must be 0 (standard deviation) or 1 (median absolute deviation)");
+        return SND_ERR_INVALID;
+    }
     if (d->n_base_widths < 0 || d->n_base_widths > d->nwidths || !(d->width_alpha >= 0.0) ||
         !std::isfinite(d->width_alpha)) {
         snd::set_error("n_base_widths must be in 0..nwidths and width_alpha finite and >= 0");
@@ -333,7 +337,8 @@ snd_status snd_snr_plane(snd_plan plan, const void *d_plane, int64_t plane_pitch
     double *stats = reinterpret_cast<double *>(static_cast<uint8_t *>(d_workspace) + kHeader);
     s = upload_row_nw(P, desc, static_cast<uint8_t *>(d_workspace), a, (hipStream_t)stream);
     if (s != SND_OK) return s;
-    int e = snd::launch_detect(P.out_dtype, d_plane, plane_pitch, P.ndm, P.n_out, desc->sigma_min, stats, a, stream);
+    int e = snd::launch_detect(P.out_dtype, d_plane, plane_pitch, P.ndm, P.n_out, desc->sigma_min, desc->sigma_estimator,
+                                 stats, a, stream);
     if (e) { snd::set_error(std::string("detect launch: ") + hipGetErrorString((hipError_t)e)); return SND_ERR_HIP; }
     return SND_OK;
 }
@@ -363,7 +368,8 @@ snd_status snd_detect_launch(snd_plan plan, const void *d_plane, int64_t plane_p
     hipStream_t st = (hipStream_t)stream;
     s = upload_row_nw(P, desc, ws, a, st);
     if (s != SND_OK) return s;
-    int e = snd::launch_detect(P.out_dtype, d_plane, plane_pitch, P.ndm, P.n_out, desc->sigma_min, stats, a, stream);
+    int e = snd::launch_detect(P.out_dtype, d_plane, plane_pitch, P.ndm, P.n_out, desc->sigma_min, desc->sigma_estimator,
+                                 stats, a, stream);
     if (e) { snd::set_error(std::string("detect launch: ") + hipGetErrorString((hipError_t)e)); return SND_ERR_HIP; }
     uint8_t *hs = static_cast<uint8_t *>(h_stage);
     hipError_t he = hipMemcpyAsync(hs, a.counter, sizeof(unsigned int), hipMemcpyDeviceToHost, st);
@@ -426,7 +432,8 @@ snd_status snd_detect(snd_plan plan, const void *d_plane, int64_t plane_pitch, c
     hipStream_t st = (hipStream_t)stream;
     s = upload_row_nw(P, desc, ws, a, st);
     if (s != SND_OK) return s;
-    int e = snd::launch_detect(P.out_dtype, d_plane, plane_pitch, P.ndm, P.n_out, desc->sigma_min, stats, a, stream);
+    int e = snd::launch_detect(P.out_dtype, d_plane, plane_pitch, P.ndm, P.n_out, desc->sigma_min, desc->sigma_estimator,
+                                 stats, a, stream);
     if (e) { snd::set_error(std::string("detect launch: ") + hipGetErrorString((hipError_t)e)); return SND_ERR_HIP; }
     unsigned int count = 0;
     hipError_t he = hipMemcpyAsync(&count, a.counter, sizeof(count), hipMemcpyDeviceToHost, st);

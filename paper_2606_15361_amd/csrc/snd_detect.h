@@ -40,6 +40,6 @@ struct SnrArgs {
 };
 
 int launch_detect(int plane_dtype, const void *plane, int64_t pitch, int ndm, int64_t n, double sigma_min,
-                  double *stats, const SnrArgs &a, void *stream);
+                  int sigma_mad, double *stats, const SnrArgs &a, void *stream);
 
 }  // namespace snd

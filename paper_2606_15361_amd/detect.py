@@ -15,10 +15,11 @@ class Detector:
 
     def __init__(self, plan, widths=(1, 2, 4, 8, 16, 32, 64), threshold: float = 7.0, sigma_min: float = 0.0,
                  closing_radius: int = 4, n_min: int = 10, max_pixels: int = 1 << 20, device="cuda",
-                 n_base_widths: int = 0, width_alpha: float = 0.0):
+                 n_base_widths: int = 0, width_alpha: float = 0.0, sigma: str = "std"):
         """n_base_widths > 0 selects the DM-scaled width set: each row uses the first
         n_base_widths widths and the further ones up to width_alpha times its dispersive sweep
-        (the paper: widths 1..1024 in powers of two, n_base_widths 4, width_alpha 0.1)."""
+        (the paper: widths 1..1024 in powers of two, n_base_widths 4, width_alpha 0.1).
+        sigma: "std" (row standard deviation) or "mad" (median absolute deviation, scaled)."""
         import torch
         self.plan = plan
         self._w = np.ascontiguousarray(widths, dtype=np.int32)
@@ -31,6 +32,9 @@ class Detector:
         d.n_min = n_min
         d.n_base_widths = n_base_widths
         d.width_alpha = width_alpha
+        if sigma not in ("std", "mad"):
+            raise ValueError('sigma must be "std" or "mad"')
+        d.sigma_estimator = 1 if sigma == "mad" else 0
         d.max_pixels = max_pixels
         self.desc = d
         nb = C.c_int64()

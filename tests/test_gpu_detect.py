@@ -242,3 +242,62 @@ def test_dm_scaled_width_set(snd, orc, integer_plane):
     want = orc.candidates(o_snr, o_widx, 6.0, radius=4, n_min=10)
     assert [(c["k"], c["t"], c["npix"]) for c in got] == [(c["k"], c["t"], c["npix"]) for c in want]
     assert any(c["k"] == 6 for c in got)
+
+
+@pytest.mark.parametrize("mode,hi,cap", [("graded", 255, 255), ("graded", 9, 255), ("binary", 1, 255),
+                                         ("graded", 3000, 4000)])
+def test_mad_sigma_integer_planes_bit_exact(snd, orc, mode, hi, cap):
+    # sigma from the median absolute deviation: exact medians on both sides, so the row
+    # statistics, the S/N plane and the candidates are bit-exact
+    rng = synth.make_rng(11 + hi)
+    ndm, n = 29, 4001 + hi % 7
+    dt = np.uint16 if cap > 255 else np.uint8
+    if mode == "binary":
+        plane = (rng.random((ndm, n)) < 0.03).astype(dt)
+        plane[6:9, 1500:1540] = 1
+        smin, theta = 0.2, 6.0
+    else:
+        plane = rng.integers(0, hi + 1, (ndm, n)).astype(dt)
+        plane[12:15, 2500:2530] = hi
+        plane[20, :80] = hi  # a burst that inflates the standard deviation, not the MAD
+        smin, theta = 0.0, 5.0
+    plane[4] = 2 if mode == "graded" else 0  # constant row: MAD 0
+    p = snd.Plan(synth.channel_freqs(4), np.zeros(ndm), 0.138e-3, n, mode=mode, branching=2, cap=cap)
+    _say(f"MAD detect mode={mode} hi={hi} cap={cap} plane dtype={p.info['out_dtype']}")
+    dev = torch.from_numpy(plane).cuda()
+    det = snd.Detector(p, WIDTHS, threshold=theta, sigma_min=smin, sigma="mad")
+    snr, widx = det.snr_plane(dev)
+    mu, sg = det.row_stats()
+    o_sig = orc.mad_sigma(plane)
+    o_snr, o_widx, o_mu, o_sg = orc.matched_filter(plane.astype(np.float64), WIDTHS, integer_plane=True,
+                                                   sigma_min=smin, sigma_rows=o_sig)
+    assert np.array_equal(mu.cpu().numpy(), o_mu) and np.array_equal(sg.cpu().numpy(), o_sg)
+    assert np.array_equal(snr.cpu().numpy(), o_snr.astype(np.float32))
+    assert np.array_equal(widx.cpu().numpy().astype(np.int32), o_widx)
+    _cands_equal(det.run(dev), orc.candidates(o_snr, o_widx, theta))
+
+
+def test_mad_sigma_float_plane(snd, orc):
+    # float planes: the deviation is one FP32 subtraction on both sides, so sigma is bit-exact;
+    # the S/N is within the float tolerance of the oracle's FP64 evaluation
+    rng = synth.make_rng(17)
+    ndm, n = 21, 6003
+    plane = (rng.standard_normal((ndm, n)) * rng.uniform(0.5, 30.0, (ndm, 1)) + rng.uniform(-5, 5, (ndm, 1)))
+    plane = plane.astype(np.float32)
+    plane[9:11, 4000:4010] += 40.0
+    plane[15, :150] += 500.0  # burst
+    plane[3] = 0.0
+    plane[3, ::2] = -0.0  # signed zeros: MAD 0, sigma 0, S/N 0
+    plane[18, :] = np.float32(1e-3)
+    plane[18, ::3] = np.float32(-2e30)  # a third of the row far below: the median stays 1e-3
+    p = _plan_for(snd, ndm, n, "float")
+    dev = torch.from_numpy(plane).cuda()
+    det = snd.Detector(p, WIDTHS, threshold=6.0, sigma="mad")
+    snr, widx = det.snr_plane(dev)
+    mu, sg = det.row_stats()
+    o_sig = orc.mad_sigma(plane)
+    assert np.array_equal(sg.cpu().numpy(), o_sig)
+    assert o_sig[3] == 0.0 and o_sig[18] == 0.0  # rows 3 and 18: MAD 0, so S/N 0 throughout
+    o_snr, o_widx, _, _ = orc.matched_filter(plane.astype(np.float64), WIDTHS, integer_plane=False, sigma_rows=o_sig)
+    s = snr.cpu().numpy()
+    assert np.max(np.abs(s - o_snr)) <= 1e-4 * max(1.0, np.abs(o_snr).max())

@@ -151,3 +151,32 @@ def test_row_width_counts_reduce_to_the_plain_filter(orc, integer_plane):
         s1, w1, m1, g1 = orc.matched_filter(y[k:k + 1], PAPER_WIDTHS[:n], integer_plane=integer_plane)
         assert np.array_equal(snr[k], s1[0]) and np.array_equal(widx[k], w1[0])
         assert mu[k] == m1[0] and sg[k] == g1[0]
+
+
+def test_mad_sigma_pins(orc):
+    """Robust sigma from the median absolute deviation (lower medians)."""
+    from scipy.stats import norm
+    # the scale is 1 / Phi^-1(3/4), from scipy's normal quantile
+    assert orc.MAD_SCALE == pytest.approx(1.0 / norm.ppf(0.75), rel=2e-16)
+    # odd length: median 3, deviations 2 1 0 1 97, their lower median 1
+    assert orc.mad_sigma(np.array([[1, 2, 3, 4, 100]], np.uint8))[0] == orc.MAD_SCALE
+    # even length: lower median 2 (not 2.5), deviations 1 0 1 8, lower median 1
+    assert orc.mad_sigma(np.array([[1.0, 2.0, 3.0, 10.0]], np.float32))[0] == orc.MAD_SCALE
+    assert orc.mad_sigma(np.array([[10, 3, 2, 1]], np.uint16))[0] == orc.MAD_SCALE
+    # a constant row has MAD 0; a row of two values has the smaller deviation 0
+    assert orc.mad_sigma(np.full((1, 7), 5, np.uint8))[0] == 0.0
+    # Gaussian rows: the MAD sigma estimates the standard deviation
+    rng = np.random.default_rng(3)
+    g = (rng.standard_normal((3, 200001)) * np.array([[0.5], [2.0], [7.0]])).astype(np.float32)
+    assert np.allclose(orc.mad_sigma(g), [0.5, 2.0, 7.0], rtol=0.01)
+    # a bright burst in 2 % of the samples inflates the standard deviation, not the MAD sigma
+    b = g[1].copy()
+    b[:4000] += 60.0
+    _, _, _, sd = orc.matched_filter(b[None, :].astype(np.float64), [1], integer_plane=False)
+    assert sd[0] > 4.0
+    assert orc.mad_sigma(b[None, :])[0] == pytest.approx(2.0, rel=0.05)
+    # the matched filter takes the given sigma, floored by sigma_min
+    row = np.array([[0, 0, 1, 0, 0, 3, 0, 0]], np.float64)
+    snr, _, mu, sg = orc.matched_filter(row, [1], integer_plane=True, sigma_rows=[0.25], sigma_min=0.5)
+    assert sg[0] == 0.5 and mu[0] == 0.5
+    assert snr[0, 5] == pytest.approx((3 - 0.5) / 0.5)
