@@ -86,7 +86,7 @@ def parse():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one plain 1 GiB device copy first (scale reference for HBM counters)")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default stage schedule")
-    ap.add_argument("--legs", default="direct,multirate,batch,serve",
+    ap.add_argument("--legs", default="direct,multirate,frontend,batch,serve",
                     help="extra measurements after the headline: direct (the same block without shared neurons), "
                          "multirate (scrunch bands), batch (48 beams), serve (streaming loop)")
     ap.add_argument("--serve-seconds", type=float, default=12.0, help="real-time length of each serving run")
@@ -182,6 +182,50 @@ def multirate_leg(snd, torch, spec, zt, mode, dev, reps=3):
                 ms_per_block=round(ms, 3), plan_build_s=round(build_s, 2), bands=bands, candidates=len(merged),
                 detection=completeness(snd, spec, native, n_out),
                 note="includes scrunch, encode, trees, detection of every band and the merge; synchronous")
+
+
+def frontend_leg(snd, torch, spec, dev, reps=3):
+    """The on-device front end on one raw-power block of the same shape: two-pass sigma-clip
+    statistics, normalisation, windowed MAD channel flagging (8192-sample windows, 5 MADs),
+    zero-DM subtraction (gamma 5) and the delta encoder to bits (1.5 sigma).  Raw power is
+    synthetic: exponential (chi-squared, 2 degrees of freedom) with per-channel gain and offset,
+    one hot channel and broadband bursts."""
+    import numpy as np
+    rng = np.random.default_rng(99)
+    nchan, n = spec.freqs.size, spec.nsamp
+    p = rng.standard_exponential((nchan, n), dtype=np.float32)
+    p *= rng.uniform(0.5, 3.0, (nchan, 1)).astype(np.float32)
+    p += rng.uniform(0.0, 10.0, (nchan, 1)).astype(np.float32)
+    p[100, : n // 4] *= 8.0
+    p[:, ::20011] += 5.0
+    pt = torch.from_numpy(p).to(dev)
+    del p
+    z = torch.empty_like(pt)
+    bits = torch.empty((nchan, (n + 31) // 32), dtype=torch.int32, device=dev)
+    cnt = torch.zeros(1, dtype=torch.int32, device=dev)
+    names = ("channel_stats", "normalize", "flag_channels", "zero_dm", "encode_bits")
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(len(names) + 1)]
+    ms = np.zeros(len(names))
+    for r in range(reps + 1):
+        ev[0].record()
+        st = snd.channel_stats(pt, 5.0)
+        ev[1].record()
+        snd.normalize(pt, st, out=z)
+        ev[2].record()
+        flags = snd.flag_channels(z, 8192, 5.0)
+        ev[3].record()
+        snd.zero_dm(z, 5.0, count=cnt)
+        ev[4].record()
+        snd.encode_bits(z, 1.5, out=bits)
+        ev[5].record()
+        torch.cuda.synchronize()
+        if r:  # the first pass warms up
+            ms += [ev[i].elapsed_time(ev[i + 1]) for i in range(len(names))]
+    ms /= reps
+    nflag = int(flags.sum().item())
+    return dict(method="front end on raw power", workload=f"{nchan} ch x {n} samples float32 raw power (synthetic)",
+                ms={k: round(float(v), 3) for k, v in zip(names, ms)}, total_ms=round(float(ms.sum()), 3),
+                flagged_channel_windows=nflag, zero_dm_samples_per_block=int(cnt.item()) // (reps + 1))
 
 
 def batch_leg(snd, synth, torch, dev, reps=3):
@@ -611,6 +655,11 @@ def main():
         outs = ws = detector = None
     if legs:
         del x, outs, ws, detector, plan
+        torch.cuda.empty_cache()
+    if "frontend" in legs:
+        log("[bench] front end on raw power")
+        result["frontend"] = frontend_leg(snd, torch, spec, dev)
+        log(f"[bench] front end: {result['frontend']['total_ms']} ms per block")
         torch.cuda.empty_cache()
     if "batch" in legs:
         log("[bench] batched leg: 48 beams")

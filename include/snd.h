@@ -216,6 +216,37 @@ snd_status snd_channel_stats(const float *d_p, int64_t p_pitch, int32_t nchan, i
 snd_status snd_normalize(const float *d_p, int64_t p_pitch, int32_t nchan, int64_t nsamp, const double *d_stats,
                          float *d_z, int64_t z_pitch, void *stream);
 
+/*
+ * Zero-DM subtraction (Results, "False-positive rate": optional zero-DM subtraction; Table S1:
+ * gamma_zdm = 5).  On a z-scored filterbank d_z [nchan][z_pitch] (float32, channel-major, in
+ * place): for every sample t, S(t) = sum_c z_c(t) in FP64 over the channels in order; where the
+ * zero-DM S/N |S(t)| / sqrt(nchan) exceeds gamma, every channel gets z_c(t) <- z_c(t) - S(t) /
+ * nchan, computed in FP64 and rounded once to float32.  The paper gives the threshold only; this
+ * conditional form is the reading used here.  d_count (optional device int32, added to, not
+ * cleared) counts the samples changed.  gamma >= 0.  Asynchronous on stream.
+ */
+snd_status snd_zero_dm(float *d_z, int64_t z_pitch, int32_t nchan, int64_t nsamp, double gamma, int32_t *d_count,
+                       void *stream);
+
+/*
+ * Windowed channel flagging by median absolute deviation (Results, "False-positive rate").  On
+ * a z-scored filterbank d_z [nchan][z_pitch] (float32, channel-major, in place), in windows of
+ * `window` samples (the last one may be shorter): s_c = the population standard deviation of
+ * channel c over the window, m = the lower median of the s_c over the channels (rank
+ * floor((nchan - 1) / 2)), MAD = the lower median of |s_c - m|; channel c is flagged in the
+ * window when |s_c - m| > k * (MAD / Phi^-1(3/4)), and its samples there are set to 0 (the
+ * normalised mean: no spikes, no float contribution).  Each of the two FP64 sums behind s_c
+ * (the samples, then the squared deviations from their mean) is taken as 64 interleaved
+ * partial sums, partial j adding samples j, j + 64, ... of the window in order, and the
+ * partials are added in order of j.  The paper names the method without parameters; window
+ * and k are the caller's.  d_sigma (device float64 [nwin][nchan], nwin = ceil(nsamp / window),
+ * caller-owned) receives the s_c; d_flags (optional device uint8 [nwin][flags_pitch]) 1 for
+ * flagged (window, channel) pairs, 0 otherwise.  1 <= nchan <= 8192; window >= 1; nwin <=
+ * 65535; k >= 0.  Asynchronous on stream.
+ */
+snd_status snd_flag_channels(float *d_z, int64_t z_pitch, int32_t nchan, int64_t nsamp, int64_t window, double k,
+                             double *d_sigma, uint8_t *d_flags, int64_t flags_pitch, void *stream);
+
 /* Float32 -> BF16 or F16 cast with round-to-nearest-even (input staging for the reduced-
  * precision float mode).  d_src [rows][src_pitch] float32, d_dst [rows][dst_pitch] of
  * dst_dtype.  Asynchronous on stream. */

@@ -37,6 +37,10 @@ What pins each function to something other than itself (tests/test_oracle_*.py):
 * mad_sigma     -- hand-evaluated rows (odd and even lengths, an outlier), the scale against
                    scipy's normal quantile, Gaussian rows (MAD sigma ~ the standard deviation),
                    robustness to a bright burst.
+* zero_dm       -- a broadband spike removed exactly, narrow-band and sub-threshold ones kept,
+                   the threshold's closed form on a constant block.
+* flag_channels -- a hot channel flagged in its window only, a dead (constant) channel, a
+                   clean Gaussian block left alone, a hand-evaluated 5-channel window.
 * candidates    -- hand-built masks (row gaps 9 / 10, diagonal pairs) and scipy's closing and
                    labelling on padded planes.
 * fire_probability, cascade, binary_snr -- Table 1 values.
@@ -104,6 +108,9 @@ def _load():
                                            P, P, P, P]
         lib.orc_matched_filter_rows.argtypes = [C.c_int32, C.c_int64, C.c_int64, P, C.c_int32, P, P, C.c_double,
                                                 P, P, P, P]
+        lib.orc_zero_dm.argtypes = [C.c_int32, C.c_int64, P, C.c_double]
+        lib.orc_zero_dm.restype = C.c_int64
+        lib.orc_flag_channels.argtypes = [C.c_int32, C.c_int64, P, C.c_int64, C.c_double, C.c_double, P, P]
         lib.orc_matched_filter_sigma.argtypes = [C.c_int32, C.c_int64, C.c_int64, P, C.c_int32, P, P, P,
                                                  C.c_double, P, P, P, P]
         lib.orc_dm_width_counts.argtypes = [C.c_int32, P, C.c_double, C.c_double, C.c_int32, P, C.c_int32, P,
@@ -458,4 +465,27 @@ def match_injections(cands, injections, dm_tol: float = 10.0, t_frac: float = 0.
         if best is not None:
             match[best[2]] = i
     return match, sum(1 for m in match if m >= 0)
+
+
+def zero_dm(z, gamma: float = 5.0):
+    """(filtered copy, samples changed): zero-DM subtraction of a z-scored float32 filterbank
+    [nchan][n] where the zero-DM S/N exceeds gamma (orc_zero_dm)."""
+    lib = _load()
+    x = np.array(z, dtype=np.float32, order="C", copy=True)
+    n = lib.orc_zero_dm(x.shape[0], x.shape[1], _ptr(x), float(gamma))
+    return x, int(n)
+
+
+def flag_channels(z, window: int, k: float = 5.0, return_sigma: bool = False):
+    """(flagged copy, uint8 flags [nwin][nchan][, float64 sigmas [nwin][nchan]]): windowed MAD
+    channel flagging of a z-scored float32 filterbank (orc_flag_channels), scale MAD_SCALE."""
+    lib = _load()
+    x = np.array(z, dtype=np.float32, order="C", copy=True)
+    nwin = (x.shape[1] + window - 1) // window
+    flags = np.zeros((nwin, x.shape[0]), dtype=np.uint8)
+    sig = np.zeros((nwin, x.shape[0]), dtype=np.float64)
+    if lib.orc_flag_channels(x.shape[0], x.shape[1], _ptr(x), int(window), float(k), MAD_SCALE, _ptr(flags),
+                             _ptr(sig)):
+        raise MemoryError("oracle channel flagging")
+    return (x, flags, sig) if return_sigma else (x, flags)
 

@@ -661,3 +661,96 @@ int64_t orc_candidates(int64_t ndm, int64_t nout, const double *snr, const int32
     free(all); free(seen); free(stack); free(a); free(b);
     return nkept;
 }
+
+/* ------------------------------------------------------------------------------------
+ * Front-end RFI steps (Results, "False-positive rate": windowed MAD channel flagging and
+ * optional zero-DM subtraction; Table S1: gamma_zdm).  z is a z-scored filterbank
+ * [nchan][n] of float32, changed in place.
+ *
+ * Zero-DM: S(t) = sum over channels in order (FP64); where |S(t)| / sqrt(nchan) > gamma every
+ * channel becomes (float)(z - S(t) / nchan).  Returns the number of samples changed.
+ * ---------------------------------------------------------------------------------- */
+int64_t orc_zero_dm(int32_t nchan, int64_t n, float *z, double gamma)
+{
+    int64_t changed = 0;
+    for (int64_t t = 0; t < n; ++t) {
+        double s = 0.0;
+        for (int32_t c = 0; c < nchan; ++c) s += (double)z[(int64_t)c * n + t];
+        if (fabs(s) / sqrt((double)nchan) > gamma) {
+            double mean = s / (double)nchan;
+            for (int32_t c = 0; c < nchan; ++c) z[(int64_t)c * n + t] = (float)((double)z[(int64_t)c * n + t] - mean);
+            ++changed;
+        }
+    }
+    return changed;
+}
+
+static int cmp_double(const void *a, const void *b)
+{
+    double x = *(const double *)a, y = *(const double *)b;
+    return (x > y) - (x < y);
+}
+
+/* Lower median: element floor((n - 1) / 2) of the sorted values. */
+static double lower_median(const double *v, int32_t n, double *scratch)
+{
+    memcpy(scratch, v, (size_t)n * sizeof(double));
+    qsort(scratch, (size_t)n, sizeof(double), cmp_double);
+    return scratch[(n - 1) / 2];
+}
+
+/* A sum of v[0..len) taken as 64 interleaved partial sums (partial j adds v[j], v[j + 64], ...
+ * in order), the partials then added in order of j: the summation order fixed for the
+ * per-window channel statistics below. */
+static double interleaved_sum(const float *v, int64_t len, double shift, int squared)
+{
+    double part[64];
+    for (int j = 0; j < 64; ++j) {
+        double a = 0.0;
+        for (int64_t t = j; t < len; t += 64) {
+            double x = (double)v[t] - shift;
+            a += squared ? x * x : x;
+        }
+        part[j] = a;
+    }
+    double s = 0.0;
+    for (int j = 0; j < 64; ++j) s += part[j];
+    return s;
+}
+
+/* Channel flagging: per window of w samples (the last may be shorter), s_c = population
+ * standard deviation of channel c over the window (the mean, then the mean squared deviation,
+ * each FP64 sum in the interleaved order above); m = lower median of s, mad = lower median of
+ * |s_c - m|; channel c is flagged when |s_c - m| > k * (mad_scale * mad) and its window samples
+ * are set to 0.  flags [nwin][nchan] receives 1 / 0, sigma_out [nwin][nchan] the s_c (may be
+ * NULL).  Returns 0, or -1 when memory runs out. */
+int orc_flag_channels(int32_t nchan, int64_t n, float *z, int64_t w, double k, double mad_scale, uint8_t *flags,
+                      double *sigma_out)
+{
+    double *s = malloc((size_t)nchan * sizeof(double)), *d = malloc((size_t)nchan * sizeof(double));
+    double *tmp = malloc((size_t)nchan * sizeof(double));
+    if (!s || !d || !tmp) { free(s); free(d); free(tmp); return -1; }
+    int64_t nwin = (n + w - 1) / w;
+    for (int64_t b = 0; b < nwin; ++b) {
+        int64_t t0 = b * w, len = n - t0 < w ? n - t0 : w;
+        for (int32_t c = 0; c < nchan; ++c) {
+            const float *row = z + (int64_t)c * n + t0;
+            double mu = interleaved_sum(row, len, 0.0, 0) / (double)len;
+            s[c] = sqrt(interleaved_sum(row, len, mu, 1) / (double)len);
+            if (sigma_out) sigma_out[b * nchan + c] = s[c];
+        }
+        double m = lower_median(s, nchan, tmp);
+        for (int32_t c = 0; c < nchan; ++c) d[c] = fabs(s[c] - m);
+        double thr = k * (mad_scale * lower_median(d, nchan, tmp));
+        for (int32_t c = 0; c < nchan; ++c) {
+            int f = d[c] > thr;
+            flags[b * nchan + c] = (uint8_t)f;
+            if (f)
+                for (int64_t t = 0; t < len; ++t) z[(int64_t)c * n + t0 + t] = 0.0f;
+        }
+    }
+    free(s);
+    free(d);
+    free(tmp);
+    return 0;
+}

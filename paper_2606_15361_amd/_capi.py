@@ -117,6 +117,8 @@ def lib() -> C.CDLL:
         "snd_cast": ([P, I64, I64, I64, P, I64, I32, P], I32),
         "snd_channel_stats": ([P, I64, I32, I64, C.c_double, P, P], I32),
         "snd_normalize": ([P, I64, I32, I64, P, P, I64, P], I32),
+        "snd_zero_dm": ([P, I64, I32, I64, C.c_double, P, P], I32),
+        "snd_flag_channels": ([P, I64, I32, I64, I64, C.c_double, P, P, I64, P], I32),
         "snd_scrunch_factors": ([I32, P, C.c_double, I32, P, I32, P], I32),
         "snd_scrunch": ([P, I64, I32, I64, I32, P, I64, P], I32),
         "snd_merge_candidates": ([I64, P, C.c_double, C.c_double, P, C.POINTER(I64)], I32),

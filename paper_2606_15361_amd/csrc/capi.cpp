@@ -331,6 +331,33 @@ snd_status snd_normalize(const float *d_p, int64_t p_pitch, int32_t nchan, int64
     return SND_OK;
 }
 
+snd_status snd_zero_dm(float *d_z, int64_t z_pitch, int32_t nchan, int64_t nsamp, double gamma, int32_t *d_count,
+                       void *stream)
+{
+    if (!d_z) return fail(SND_ERR_INVALID, "null pointer");
+    if (nchan < 1 || nsamp < 1 || z_pitch < nsamp || nsamp > (int64_t)0xffffffff * 256 || !(gamma >= 0.0) ||
+        !std::isfinite(gamma))
+        return fail(SND_ERR_INVALID, "bad nchan, nsamp, pitch or gamma");
+    int e = snd::launch_zero_dm(d_z, z_pitch, nchan, nsamp, gamma, d_count, stream);
+    if (e) return hip_fail(e, "zero-DM launch");
+    return SND_OK;
+}
+
+snd_status snd_flag_channels(float *d_z, int64_t z_pitch, int32_t nchan, int64_t nsamp, int64_t window, double k,
+                             double *d_sigma, uint8_t *d_flags, int64_t flags_pitch, void *stream)
+{
+    if (!d_z || !d_sigma) return fail(SND_ERR_INVALID, "null pointer");
+    if (nchan < 1 || nchan > 8192 || nsamp < 1 || z_pitch < nsamp || window < 1 || !(k >= 0.0) || !std::isfinite(k))
+        return fail(SND_ERR_INVALID, "1 <= nchan <= 8192, nsamp >= 1, pitch >= nsamp, window >= 1, finite k >= 0 needed");
+    const int64_t nwin = (nsamp + window - 1) / window;
+    if (nwin > 0x7fffffff) return fail(SND_ERR_INVALID, "too many windows");
+    if (d_flags && flags_pitch < nchan) return fail(SND_ERR_INVALID, "flags_pitch < nchan");
+    if (nwin > 65535) return fail(SND_ERR_INVALID, "at most 65535 windows");
+    int e = snd::launch_flag_channels(d_z, z_pitch, nchan, nsamp, window, k, d_sigma, d_flags, flags_pitch, stream);
+    if (e) return hip_fail(e, "channel flagging launch");
+    return SND_OK;
+}
+
 snd_status snd_cast(const float *d_src, int64_t src_pitch, int64_t rows, int64_t cols, void *d_dst, int64_t dst_pitch,
                     int32_t dst_dtype, void *stream)
 {

@@ -299,6 +299,109 @@ __global__ __launch_bounds__(256) void k_normalize(const float *p, int64_t pp, i
     z[(int64_t)c * zp + t] = (float)(((double)p[(int64_t)c * pp + t] - mu) / sg);
 }
 
+// Zero-DM subtraction: one thread per sample t sums the channels in order in FP64 (the
+// threads of a wave read consecutive samples of a channel row); when the zero-DM S/N
+// |sum| / sqrt(nchan) exceeds gamma, the channel mean sum / nchan is subtracted from every
+// channel, each result rounded once to FP32.
+__global__ __launch_bounds__(256) void k_zero_dm(float *z, int64_t zp, int nchan, int64_t n, double gamma,
+                                                 int32_t *count)
+{
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (t >= n) return;
+    double s = 0.0;
+    for (int c = 0; c < nchan; ++c) s += (double)z[(int64_t)c * zp + t];
+    if (__builtin_fabs(s) / __builtin_sqrt((double)nchan) > gamma) {
+        const double mean = s / (double)nchan;
+        for (int c = 0; c < nchan; ++c) z[(int64_t)c * zp + t] = (float)((double)z[(int64_t)c * zp + t] - mean);
+        if (count) atomicAdd(count, 1);
+    }
+}
+
+// Index of the element of rank r (0-based, increasing; equal values ordered by index) among
+// v[0..n) in LDS: each thread ranks its elements against all others.
+__device__ inline void lds_rank_select(const double *v, int n, int r, int *out)
+{
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const double x = v[i];
+        int below = 0;
+        for (int j = 0; j < n; ++j) below += (v[j] < x) || (v[j] == x && j < i);
+        if (below == r) *out = i;
+    }
+}
+
+// Windowed channel flagging by median absolute deviation, in two kernels.
+// k_chan_window_sigma: one wave per (channel, window of w samples): s = the population standard
+//   deviation over the window, each of its two FP64 sums (samples, then squared deviations from
+//   the mean) taken as 64 interleaved partial sums -- lane j sums samples j, j + 64, ... in
+//   order -- added in lane order.  Writes sigma[window][channel].
+// k_flag_window: one workgroup per window: m = the lower median of the window's s over the
+//   channels, MAD = the lower median of |s_c - m|; channel c is flagged when |s_c - m| >
+//   k * (kMad * MAD), kMad = 1 / Phi^-1(3/4), and its samples in the window are set to 0.
+constexpr double kFlagMadScale = 1.4826022185056018;
+
+__device__ inline double wave_sum_in_lane_order(double v, double *lds64)
+{
+    const int lane = threadIdx.x & 63;
+    lds64[lane] = v;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    double s = 0.0;
+    for (int j = 0; j < 64; ++j) s += lds64[j];
+    __builtin_amdgcn_wave_barrier();
+    return s;
+}
+
+__global__ __launch_bounds__(256) void k_chan_window_sigma(const float *z, int64_t zp, int nchan, int64_t n,
+                                                           int64_t w, double *sigma)
+{
+    __shared__ double part[4][64];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int c = blockIdx.x * 4 + wave;
+    const int64_t b = blockIdx.y;
+    if (c >= nchan) return;  // whole waves
+    const int64_t t0 = b * w;
+    const int64_t len = n - t0 < w ? n - t0 : w;
+    const float *row = z + (int64_t)c * zp + t0;
+    double a = 0.0;
+    for (int64_t t = lane; t < len; t += 64) a += (double)row[t];
+    const double mu = wave_sum_in_lane_order(a, part[wave]) / (double)len;
+    double q = 0.0;
+    for (int64_t t = lane; t < len; t += 64) q += ((double)row[t] - mu) * ((double)row[t] - mu);
+    const double qs = wave_sum_in_lane_order(q, part[wave]);
+    if (lane == 0) sigma[b * nchan + c] = __builtin_sqrt(qs / (double)len);
+}
+
+
+__global__ __launch_bounds__(1024) void k_flag_window(float *z, int64_t zp, int nchan, int64_t n, int64_t w,
+                                                      double k, const double *sigma, uint8_t *flags, int64_t fp)
+{
+    extern __shared__ double sv[];  // [2 * nchan]: the window's sigmas, then their deviations
+    __shared__ int s_idx;
+    const int64_t b = blockIdx.x;
+    const int64_t t0 = b * w;
+    const int64_t len = n - t0 < w ? n - t0 : w;
+    for (int c = threadIdx.x; c < nchan; c += blockDim.x) sv[c] = sigma[b * nchan + c];
+    __syncthreads();
+    const int r = (nchan - 1) / 2;
+    lds_rank_select(sv, nchan, r, &s_idx);
+    __syncthreads();
+    const double m = sv[s_idx];
+    for (int c = threadIdx.x; c < nchan; c += blockDim.x) sv[nchan + c] = __builtin_fabs(sv[c] - m);
+    __syncthreads();
+    lds_rank_select(sv + nchan, nchan, r, &s_idx);
+    __syncthreads();
+    const double thr = k * (kFlagMadScale * sv[nchan + s_idx]);
+    for (int c = 0; c < nchan; ++c) {  // uniform: every thread sees the same flag
+        const bool f = sv[nchan + c] > thr;
+        if (threadIdx.x == 0 && flags) flags[b * fp + c] = f ? 1 : 0;
+        if (f) {
+            float *row = z + (int64_t)c * zp + t0;
+            for (int64_t t = threadIdx.x; t < len; t += blockDim.x) row[t] = 0.0f;
+        }
+    }
+}
+
 template <typename TO>
 __global__ __launch_bounds__(256) void k_cast(const float *src, int64_t sp, int64_t cols, TO *dst, int64_t dp)
 {
@@ -366,6 +469,24 @@ int launch_scrunch(const float *z, int64_t zp, int nchan, int64_t nout, int s, f
 int launch_chanstats(const float *p, int64_t pp, int nchan, int64_t n, double clip, double *stats, void *stream)
 {
     hipLaunchKernelGGL(k_chanstats, dim3((uint32_t)nchan), dim3(256), 0, (hipStream_t)stream, p, pp, n, clip, stats);
+    return (int)hipGetLastError();
+}
+
+int launch_zero_dm(float *z, int64_t zp, int nchan, int64_t n, double gamma, int32_t *count, void *stream)
+{
+    const int64_t nb = (n + 255) / 256;
+    hipLaunchKernelGGL(k_zero_dm, dim3((uint32_t)nb), dim3(256), 0, (hipStream_t)stream, z, zp, nchan, n, gamma, count);
+    return (int)hipGetLastError();
+}
+
+int launch_flag_channels(float *z, int64_t zp, int nchan, int64_t n, int64_t w, double k, double *sigma,
+                         uint8_t *flags, int64_t fp, void *stream)
+{
+    const int64_t nwin = (n + w - 1) / w;
+    hipLaunchKernelGGL(k_chan_window_sigma, dim3((uint32_t)((nchan + 3) / 4), (uint32_t)nwin), dim3(256), 0,
+                       (hipStream_t)stream, z, zp, nchan, n, w, sigma);
+    hipLaunchKernelGGL(k_flag_window, dim3((uint32_t)nwin), dim3(1024), (size_t)(2 * nchan) * sizeof(double),
+                       (hipStream_t)stream, z, zp, nchan, n, w, k, sigma, flags, fp);
     return (int)hipGetLastError();
 }
 

@@ -256,6 +256,9 @@ int launch_encode(const float *z, int64_t z_pitch, int time_major, int nchan, in
 int launch_encode_bits(const float *z, int64_t z_pitch, int time_major, int nchan, int64_t nsamp, float thr,
                        uint32_t *out, int64_t out_words, void *stream);
 int launch_chanstats(const float *p, int64_t p_pitch, int nchan, int64_t n, double clip, double *stats, void *stream);
+int launch_zero_dm(float *z, int64_t zp, int nchan, int64_t n, double gamma, int32_t *count, void *stream);
+int launch_flag_channels(float *z, int64_t zp, int nchan, int64_t n, int64_t w, double k, double *sigma,
+                         uint8_t *flags, int64_t fp, void *stream);
 int launch_normalize(const float *p, int64_t p_pitch, int nchan, int64_t n, const double *stats, float *z,
                      int64_t z_pitch, void *stream);
 int launch_cast(const float *src, int64_t src_pitch, int64_t rows, int64_t cols, void *dst, int64_t dst_pitch,

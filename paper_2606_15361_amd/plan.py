@@ -278,6 +278,37 @@ def normalize(p, stats, out=None, stream=None):
     return out
 
 
+def zero_dm(z, gamma: float = 5.0, count=None, stream=None):
+    """Zero-DM subtraction in place on a z-scored float32 filterbank [nchan][nsamp] (snd_zero_dm);
+    count: optional int32 device tensor of one element, incremented by the samples changed."""
+    import torch
+    if z.dtype != torch.float32 or z.stride(1) != 1:
+        raise TypeError("z must be float32 with unit inner stride")
+    if count is not None and (count.dtype != torch.int32 or count.device != z.device):
+        raise TypeError("count must be an int32 tensor on z's device")
+    capi.check(capi.lib().snd_zero_dm(C.c_void_p(z.data_ptr()), z.stride(0), z.shape[0], z.shape[1], float(gamma),
+                                      None if count is None else C.c_void_p(count.data_ptr()),
+                                      _stream_handle(stream, z.device)))
+    return z
+
+
+def flag_channels(z, window: int, k: float = 5.0, stream=None, return_sigma: bool = False):
+    """Windowed MAD channel flagging in place on a z-scored float32 filterbank [nchan][nsamp]
+    (snd_flag_channels); returns the uint8 flags [nwin][nchan] (and the float64 per-window
+    channel sigmas [nwin][nchan] with return_sigma)."""
+    import torch
+    if z.dtype != torch.float32 or z.stride(1) != 1:
+        raise TypeError("z must be float32 with unit inner stride")
+    nwin = (z.shape[1] + window - 1) // window
+    flags = torch.empty((nwin, z.shape[0]), dtype=torch.uint8, device=z.device)
+    sigma = torch.empty((nwin, z.shape[0]), dtype=torch.float64, device=z.device)
+    capi.check(capi.lib().snd_flag_channels(C.c_void_p(z.data_ptr()), z.stride(0), z.shape[0], z.shape[1],
+                                            int(window), float(k), C.c_void_p(sigma.data_ptr()),
+                                            C.c_void_p(flags.data_ptr()), flags.stride(0),
+                                            _stream_handle(stream, z.device)))
+    return (flags, sigma) if return_sigma else flags
+
+
 def cast(x, dtype: str, stream=None):
     """float32 [rows][cols] -> bf16/f16 with round-to-nearest-even, on the GPU."""
     import torch

@@ -45,3 +45,29 @@ def test_sigma_clip_normalise_and_encode(snd, orc):
     # with the GPU's own statistics the normalised values agree to FP64 rounding
     z2 = snd.normalize(pt[sel].contiguous(), st[sel].contiguous()).cpu().numpy()
     assert np.max(np.abs(z2 - zw)) <= 1e-5
+
+
+@pytest.mark.parametrize("nchan,n,window", [(96, 20011, 4096), (1024, 16384, 8192), (7, 1000, 1000)])
+def test_flagging_and_zero_dm_bit_exact(snd, orc, nchan, n, window):
+    # windowed MAD channel flagging, then zero-DM subtraction, on a z-scored block with RFI:
+    # both sides sum in the same order in FP64, so flags, changed samples and values agree
+    # bit for bit
+    rng = synth.make_rng(nchan + window)
+    z = rng.standard_normal((nchan, n)).astype(np.float32)
+    z[nchan // 3, : min(n, window)] *= 12.0            # hot channel in the first window
+    z[nchan // 2, :] = 0.0                              # dead channel
+    z[:, n // 2] += 8.0 / np.sqrt(nchan) * 3.0          # broadband spikes (zero-DM S/N ~ 24)
+    z[:, n // 3: n // 3 + 5] += 2.0
+    z[1, 17] += 40.0                                    # narrow-band spike
+    zt = torch.from_numpy(z).cuda()
+    flags, sig = snd.flag_channels(zt, window, k=5.0, return_sigma=True)
+    want_z, want_f, want_s = orc.flag_channels(z, window, k=5.0, return_sigma=True)
+    assert np.array_equal(sig.cpu().numpy(), want_s)
+    assert np.array_equal(flags.cpu().numpy(), want_f)
+    assert np.array_equal(zt.cpu().numpy(), want_z)
+    assert want_f[0, nchan // 3] == 1 and np.all(want_f[:, nchan // 2] == 1)
+    cnt = torch.zeros(1, dtype=torch.int32, device="cuda")
+    snd.zero_dm(zt, 5.0, count=cnt)
+    want_z2, want_n = orc.zero_dm(want_z, 5.0)
+    assert int(cnt.item()) == want_n and want_n >= 1  # at least the strong broadband spike
+    assert np.array_equal(zt.cpu().numpy(), want_z2)

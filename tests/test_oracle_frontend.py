@@ -35,3 +35,55 @@ def test_normalised_fire_rate_is_the_normal_tail(orc):
     rate = float((z > np.float32(1.5)).mean())
     want = orc.fire_probability(1.5)  # 0.0668
     assert abs(rate - want) < 4 * math.sqrt(want * (1 - want) / z.size)
+
+
+def test_zero_dm_pins(orc):
+    rng = np.random.default_rng(21)
+    nchan, n = 64, 500
+    z = rng.standard_normal((nchan, n)).astype(np.float32)
+    # a broadband spike: +3 in every channel at t = 100, zero-DM S/N about 3 sqrt(64) = 24
+    z[:, 100] += 3.0
+    # a narrow-band spike of the same total power in one channel: S/N about 192/8 = 24 too, but
+    # the subtraction spreads it (it is broadband only in sum)
+    z[7, 300] += 192.0
+    # a weak broadband excursion: S/N about 0.5 * 8 = 4 < 5, kept
+    z[:, 400] += 0.5
+    out, changed = orc.zero_dm(z, 5.0)
+    zc = z.astype(np.float64)
+    snr = np.abs(zc.sum(0)) / 8.0
+    assert changed == int((snr > 5.0).sum())
+    # at t = 100 the added constant vanishes: the column equals the noise minus its own mean
+    noise = zc[:, 100] - 3.0
+    assert np.allclose(out[:, 100], noise - noise.mean(), atol=1e-5)
+    assert abs(out[:, 100].astype(np.float64).sum()) < 1e-4
+    # untouched columns are bit-identical
+    keep = snr <= 5.0
+    assert keep[400] and np.array_equal(out[:, keep], z[:, keep])
+    # closed form of the threshold: a constant block c has S/N |c| sqrt(nchan)
+    c = np.full((16, 4), 1.25, np.float32)  # 1.25 * 4 = 5: not above 5
+    assert orc.zero_dm(c, 5.0)[1] == 0
+    c2 = np.full((16, 4), 1.3, np.float32)
+    o2, k2 = orc.zero_dm(c2, 5.0)
+    assert k2 == 4 and np.all(o2 == 0.0)
+
+
+def test_flag_channels_pins(orc):
+    rng = np.random.default_rng(22)
+    nchan, n, w = 32, 3000, 1000
+    z = rng.standard_normal((nchan, n)).astype(np.float32)
+    z[5, 1000:2000] *= 10.0      # hot in window 1 only
+    z[9, :] = 0.25               # dead channel: sigma 0 in every window
+    out, flags = orc.flag_channels(z, w, k=5.0)
+    assert flags.shape == (3, nchan)
+    assert flags[1, 5] == 1 and flags[0, 5] == 0 and flags[2, 5] == 0
+    assert np.all(flags[:, 9] == 1)
+    assert flags.sum() == 4  # nothing else in a clean Gaussian block at 5 MADs
+    assert np.all(out[5, 1000:2000] == 0.0) and np.array_equal(out[5, :1000], z[5, :1000])
+    assert np.all(out[9] == 0.0)
+    # hand-evaluated window: channel standard deviations 1, 2, 3, 4 and 50 (values +-s, even
+    # length); m = 3, deviations 2 1 0 1 47, MAD = 1, scaled 1.4826: with k = 5 only the
+    # channel at 50 (47 > 7.41) is flagged; with k = 1 the channels at 1 and 50 (2 > 1.48)
+    s = np.array([1.0, 2.0, 3.0, 4.0, 50.0], np.float32)[:, None]
+    h = np.tile(np.array([1.0, -1.0], np.float32), (5, 4)) * s
+    assert list(orc.flag_channels(h, 8, k=5.0)[1][0]) == [0, 0, 0, 0, 1]
+    assert list(orc.flag_channels(h, 8, k=1.0)[1][0]) == [1, 0, 0, 0, 1]
