@@ -86,7 +86,7 @@ def parse():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one plain 1 GiB device copy first (scale reference for HBM counters)")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default stage schedule")
-    ap.add_argument("--legs", default="direct,multirate,frontend,batch,serve",
+    ap.add_argument("--legs", default="direct,fdmt,multirate,frontend,batch,serve",
                     help="extra measurements after the headline: direct (the same block without shared neurons), "
                          "multirate (scrunch bands), batch (48 beams), serve (streaming loop)")
     ap.add_argument("--serve-seconds", type=float, default=12.0, help="real-time length of each serving run")
@@ -182,6 +182,35 @@ def multirate_leg(snd, torch, spec, zt, mode, dev, reps=3):
                 ms_per_block=round(ms, 3), plan_build_s=round(build_s, 2), bands=bands, candidates=len(merged),
                 detection=completeness(snd, spec, native, n_out),
                 note="includes scrunch, encode, trees, detection of every band and the merge; synchronous")
+
+
+def fdmt_leg(snd, torch, spec, zt, tree_ms, reps=3):
+    """FDMT with the no-smear initialisation on the same float32 block, DM 0-2000: one row per
+    integer band sweep (28,353 rows against the tree's 4096 DMs)."""
+    bw = float(abs(spec.freqs[0] - spec.freqs[1]))
+    fd = snd.Fdmt(spec.freqs, bw, spec.tsamp_s, float(spec.dms.max()), spec.nsamp)
+    out = fd.execute(zt)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fd.execute(zt, out=out)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    # algorithmic bytes: every merge reads two source samples and writes one per output sample,
+    # over the rows of all merges
+    alg = fd.table_rows * spec.nsamp * 12
+    rows = fd.n_delays
+    value = rows * fd.n_out / (ms * 1e-3)
+    del out, fd
+    torch.cuda.empty_cache()
+    return dict(method="FDMT, no-smear initialisation (log2 1024 = 10 merges)", ms=round(ms, 3),
+                rows=rows, dm_step=round(float(spec.dms.max()) / (rows - 1), 5),
+                value=value, unit="DM-time samples/s", us_per_dm_row=round(ms * 1e3 / rows, 3),
+                snd_tree_ms=round(tree_ms, 3), snd_us_per_dm_row=round(tree_ms * 1e3 / spec.dms.size, 3),
+                alg_gb=round(alg / 1e9, 1), achieved_gbs=round(alg / (ms * 1e-3) / 1e9, 1),
+                hbm_frac=round(alg / (ms * 1e-3) / 8e12, 3))
 
 
 def frontend_leg(snd, torch, spec, dev, reps=3):
@@ -643,6 +672,11 @@ def main():
         result["direct"] = direct_leg(snd, torch, spec, x, pkw, dev, ref)
         result["direct"]["snd_tree_ms"] = round(float(stage_ms.sum()), 3)
         log(f"[bench] direct: {result['direct']['ms']} ms vs tree {result['direct']['snd_tree_ms']} ms")
+    if "fdmt" in legs and mode == "float" and plan.in_dtype == "f32":
+        log("[bench] FDMT baseline on the same block")
+        torch.cuda.empty_cache()
+        result["fdmt"] = fdmt_leg(snd, torch, spec, x, float(stage_ms.sum()))
+        log(f"[bench] FDMT: {result['fdmt']['ms']} ms for {result['fdmt']['rows']} rows")
     if "multirate" in legs:
         log("[bench] multi-rate pipeline on the same block")
         del outs, ws, detector

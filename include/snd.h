@@ -389,6 +389,41 @@ snd_status snd_merge_candidates(int64_t n, const snd_band_candidate *h_in, doubl
                                 snd_band_candidate *h_out, int64_t *h_count);
 
 /* ---------------------------------------------------------------------------------------
+ * FDMT baseline (Methods, "Classical dedispersion algorithms"), with the paper's no-smear
+ * initialisation: a comparison point for the SND tree on the same GPU.  FDMT merges adjacent
+ * sub-bands log2(nchan) times and outputs one row per integer band sweep delta = 0 .. D, D the
+ * sweep at dm_max rounded up; row delta stands for DM = delta * dm_per_delay.
+ *
+ * Channels are intervals of width chan_bw_mhz around freq_mhz[c] (host, strictly descending,
+ * lower edges > 0); nchan a power of two.  At each merge of a sub-band S into its upper half U
+ * and lower half L, S's delay delta splits as delta_U = round_half_even(delta * (f_mid^-2 -
+ * f_hi^-2) / (f_lo^-2 - f_hi^-2)) and delta_L = delta - delta_U (each clamped to the delays its
+ * half holds: ceil(D r / r_band) + 1 for a sweep span r = f_lo^-2 - f_hi^-2), and P_S[delta](t)
+ * = P_U[delta_U](t) + P_L[delta_L](t + delta_U), zero past nsamp; the time reference is each
+ * sub-band's upper edge.  No-smear initialisation: every initial delay row of a channel is the
+ * channel itself.  Sums in FP32.  Output row delta is valid for t < nsamp - D.
+ * --------------------------------------------------------------------------------------- */
+typedef struct snd_fdmt_s *snd_fdmt;
+
+/* Host tables for one shape.  SND_ERR_INVALID on bad arguments, or when the sweep at dm_max
+ * does not fit nsamp. */
+snd_status snd_fdmt_create(int32_t nchan, const double *freq_mhz, double chan_bw_mhz, double tsamp_s, double dm_max,
+                           int64_t nsamp, snd_fdmt *out);
+/* Output rows (D + 1), valid samples per row, device bytes of the tables and of the workspace
+ * (two buffers of the largest intermediate level), and the DM step per delay row.  Any output
+ * pointer may be NULL. */
+snd_status snd_fdmt_query(snd_fdmt p, int64_t *n_delays, int64_t *n_out, int64_t *table_bytes,
+                          int64_t *workspace_bytes, double *dm_per_delay);
+/* Copy the tables to caller-owned device memory (synchronises the stream); it must stay valid
+ * while the handle executes. */
+snd_status snd_fdmt_upload(snd_fdmt p, void *d_tables, int64_t bytes, void *stream);
+/* d_in float32 [nchan][in_pitch], d_out float32 [n_delays][out_pitch], pitches >= nsamp,
+ * d_ws >= workspace_bytes.  Asynchronous on stream; SND_ERR_STATE before upload. */
+snd_status snd_fdmt_execute(snd_fdmt p, const float *d_in, int64_t in_pitch, float *d_out, int64_t out_pitch,
+                            void *d_ws, int64_t ws_bytes, void *stream);
+snd_status snd_fdmt_destroy(snd_fdmt p);
+
+/* ---------------------------------------------------------------------------------------
  * Validation against injected pulses (Methods, "Validation methodology").  Host only.
  * --------------------------------------------------------------------------------------- */
 

@@ -41,6 +41,11 @@ What pins each function to something other than itself (tests/test_oracle_*.py):
                    the threshold's closed form on a constant block.
 * flag_channels -- a hot channel flagged in its window only, a dead (constant) channel, a
                    clean Gaussian block left alone, a hand-evaluated 5-channel window.
+* fdmt, fdmt_delays -- the recursion equals the direct sum over the channel delays traced down
+                   the split rule (two different computations); the zero-delay row is the channel
+                   sum; every traced delay stays within the merge count of the f^-2 law; the
+                   split of a sub-band's delay adds up; a spike track along traced delays sums
+                   to the channel count (no-smear initialisation: no spike is spread).
 * candidates    -- hand-built masks (row gaps 9 / 10, diagonal pairs) and scipy's closing and
                    labelling on padded planes.
 * fire_probability, cascade, binary_snr -- Table 1 values.
@@ -488,4 +493,99 @@ def flag_channels(z, window: int, k: float = 5.0, return_sigma: bool = False):
                              _ptr(sig)):
         raise MemoryError("oracle channel flagging")
     return (x, flags, sig) if return_sigma else (x, flags)
+
+
+# --------------------------------------------------------------------------------------
+# FDMT with the no-smear initialisation (Methods, "Classical dedispersion algorithms").
+# --------------------------------------------------------------------------------------
+def _fdmt_geometry(freqs, chan_bw_mhz: float, tsamp_s: float, dm_max: float):
+    """(span(c0, c1), D, ndel(c0, c1)) for channels given as intervals of width chan_bw_mhz
+    around descending centres: span is the f^-2 sweep span of channels [c0, c1) (lower edge of
+    the last, upper edge of the first), D the band sweep at dm_max in samples rounded up, ndel
+    the number of delays a sub-band holds."""
+    f = np.asarray(freqs, dtype=np.float64)
+    hi = f + 0.5 * chan_bw_mhz
+    lo = f - 0.5 * chan_bw_mhz
+
+    def span(c0, c1):
+        return 1.0 / (lo[c1 - 1] * lo[c1 - 1]) - 1.0 / (hi[c0] * hi[c0])
+
+    r_band = span(0, f.size)
+    D = int(math.ceil(K_DM * dm_max * r_band / (tsamp_s * 1e3)))
+
+    def ndel(c0, c1):
+        return min(int(math.ceil(D * span(c0, c1) / r_band)) + 1, D + 1)
+
+    return span, D, ndel
+
+
+def _fdmt_split(span, ndel, c0, w, d):
+    """Delay d of sub-band [c0, c0 + 2w) split over its upper half [c0, c0 + w) and lower half
+    [c0 + w, c0 + 2w), in proportion to their f^-2 spans (rounded half to even), each clamped
+    to the delays its half holds."""
+    du = min(int(np.rint(d * span(c0, c0 + w) / span(c0, c0 + 2 * w))), ndel(c0, c0 + w) - 1)
+    dl = min(d - du, ndel(c0 + w, c0 + 2 * w) - 1)
+    return du, dl
+
+
+def fdmt(x, freqs, chan_bw_mhz: float, tsamp_s: float, dm_max: float) -> np.ndarray:
+    """float64 [D + 1][n]: FDMT of x [nchan][n] (nchan a power of two) with the no-smear
+    initialisation: every initial delay row of a channel is the channel; merging adjacent
+    sub-bands, row d of a sub-band is row du of its upper half plus row dl of its lower half
+    read du samples later (zero past n), the time reference being each sub-band's upper edge.
+    Output row d is the band sweep of d samples."""
+    x = np.asarray(x, dtype=np.float64)
+    nchan, n = x.shape
+    span, D, ndel = _fdmt_geometry(freqs, chan_bw_mhz, tsamp_s, dm_max)
+    if D >= n:
+        raise ValueError("the band sweep at dm_max does not fit the block")
+    # sub-bands of the current width: arrays [ndel][n]
+    bands = [np.repeat(x[c][None, :], ndel(c, c + 1), axis=0) for c in range(nchan)]
+    w = 1
+    while w < nchan:
+        merged = []
+        for s in range(nchan // (2 * w)):
+            c0 = 2 * w * s
+            up, low = bands[2 * s], bands[2 * s + 1]
+            rows = np.zeros((ndel(c0, c0 + 2 * w), n))
+            for d in range(rows.shape[0]):
+                du, dl = _fdmt_split(span, ndel, c0, w, d)
+                rows[d] = up[du]
+                rows[d, : n - du] += low[dl, du:]
+            merged.append(rows)
+        bands = merged
+        w *= 2
+    return bands[0]
+
+
+def fdmt_delays(freqs, chan_bw_mhz: float, tsamp_s: float, dm_max: float, d: int) -> np.ndarray:
+    """int64 [nchan]: the sample delay at which FDMT's output row d reads each channel, found by
+    following the split rule from the whole band down to single channels (a channel of the
+    lower half is read later by the upper half's share of the delay)."""
+    f = np.asarray(freqs, dtype=np.float64)
+    span, D, ndel = _fdmt_geometry(f, chan_bw_mhz, tsamp_s, dm_max)
+    out = np.zeros(f.size, dtype=np.int64)
+
+    def walk(c0, width, dd, base):
+        if width == 1:
+            out[c0] = base
+            return
+        w = width // 2
+        du, dl = _fdmt_split(span, ndel, c0, w, dd)
+        walk(c0, w, du, base)
+        walk(c0 + w, w, dl, base + du)
+
+    walk(0, f.size, d, 0)
+    return out
+
+
+def fdmt_row(x, delays) -> np.ndarray:
+    """float64 [n]: sum over channels of x_c(t + delays[c]), zero past n (one FDMT output row
+    evaluated directly)."""
+    x = np.asarray(x, dtype=np.float64)
+    n = x.shape[1]
+    y = np.zeros(n)
+    for c, e in enumerate(np.asarray(delays, dtype=np.int64)):
+        y[: n - e] += x[c, e:]
+    return y
 

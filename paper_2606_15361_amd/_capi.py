@@ -123,6 +123,12 @@ def lib() -> C.CDLL:
         "snd_scrunch": ([P, I64, I32, I64, I32, P, I64, P], I32),
         "snd_merge_candidates": ([I64, P, C.c_double, C.c_double, P, C.POINTER(I64)], I32),
         "snd_effective_width": ([I32, P, C.c_double, I64, P, P, P], I32),
+        "snd_fdmt_create": ([I32, P, C.c_double, C.c_double, C.c_double, I64, C.POINTER(P)], I32),
+        "snd_fdmt_query": ([P, C.POINTER(I64), C.POINTER(I64), C.POINTER(I64), C.POINTER(I64),
+                            C.POINTER(C.c_double)], I32),
+        "snd_fdmt_upload": ([P, P, I64, P], I32),
+        "snd_fdmt_execute": ([P, P, I64, P, I64, P, I64, P], I32),
+        "snd_fdmt_destroy": ([P], I32),
         "snd_match_injections": ([I64, P, P, P, I64, P, P, P, C.c_double, C.c_double, P, C.POINTER(I64)], I32),
         "snd_last_error": ([], C.c_char_p),
         "snd_version": ([], C.c_char_p),

@@ -472,6 +472,37 @@ int launch_chanstats(const float *p, int64_t pp, int nchan, int64_t n, double cl
     return (int)hipGetLastError();
 }
 
+// One FDMT merge: output row r = source row U (tab[4r]) plus source row L (tab[4r + 1]) read
+// tab[4r + 2] samples later, zero past n.  A workgroup covers 2048 samples of a strided set of
+// rows; the table words are uniform (scalar loads).
+__global__ __launch_bounds__(256) void k_fdmt_merge(const float *src, int64_t sp, float *dst, int64_t dp,
+                                                    const int32_t *tab, int64_t rows, int64_t n)
+{
+    const int64_t t0 = (int64_t)blockIdx.x * 2048 + threadIdx.x;
+    for (int64_t r = blockIdx.y; r < rows; r += gridDim.y) {
+        const int64_t ru = tab[4 * r], rl = tab[4 * r + 1], du = tab[4 * r + 2];
+        const float *u = src + ru * sp;
+        const float *l = src + rl * sp + du;
+        float *o = dst + r * dp;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int64_t t = t0 + 256 * j;
+            if (t < n) o[t] = u[t] + (t + du < n ? l[t] : 0.0f);
+        }
+    }
+}
+
+int launch_fdmt_merge(const float *src, int64_t sp, float *dst, int64_t dp, const int32_t *tab, int64_t rows, int64_t n,
+                      void *stream)
+{
+    if (rows < 1) return 0;
+    const int64_t nx = (n + 2047) / 2048;
+    const int64_t ny = rows < 4096 ? rows : 4096;
+    hipLaunchKernelGGL(k_fdmt_merge, dim3((uint32_t)nx, (uint32_t)ny), dim3(256), 0, (hipStream_t)stream, src, sp,
+                       dst, dp, tab, rows, n);
+    return (int)hipGetLastError();
+}
+
 int launch_zero_dm(float *z, int64_t zp, int nchan, int64_t n, double gamma, int32_t *count, void *stream)
 {
     const int64_t nb = (n + 255) / 256;
