@@ -138,6 +138,37 @@ def direct_leg(snd, torch, spec, x, pkw, dev, ref_out, reps=3):
                 identical_to_snd=bool(torch.equal(out, ref_out)), rel_rms_vs_snd=rel)
 
 
+def subband_leg(snd, torch, spec, x, pkw, dev, ref_out, reps=3):
+    """Sub-band dedispersion on the same block, in its exact form: a two-level tree of 32
+    sub-bands of 32 channels (each sub-band's partial sums shared by the DMs with the same
+    delay pattern inside it) and one 32-input root per DM.  Float mode only: the tree is
+    linear there, so the plane equals the SND plane up to FP32 association."""
+    p = snd.Plan(spec.freqs, spec.dms, spec.tsamp_s, spec.nsamp, **dict(pkw, cluster=32, branching=32))
+    p.upload(dev)
+    out = p.empty_output(dev)
+    ws = p.workspace(dev)
+    stream = torch.cuda.current_stream(dev)
+    p.execute(x, out=out, workspace=ws)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        p.execute(x, out=out, workspace=ws)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    info = p.info
+    a, b = out.float(), ref_out.float()
+    rel = float(torch.sqrt(torch.mean((a - b) ** 2)) / torch.sqrt(torch.mean(b ** 2)).clamp_min(1e-30))
+    res = dict(method="sub-band (exact two-level tree: 32 sub-bands x 32 channels)", ms=round(ms, 3),
+               value=p.ndm * p.n_out / (ms * 1e-3), unit="DM-time samples/s", kernels=info["stage_kernel"],
+               sub_band_rows=info["stage_rows"][0], inputs_per_sample=sum(info["stage_entries"]),
+               rel_rms_vs_snd=rel)
+    del out, ws, p
+    torch.cuda.empty_cache()
+    return res
+
+
 def completeness(snd, spec, cands, n_out):
     """Injected pulses of the block recovered by the candidates: greedy one-to-one matching in
     decreasing S/N with |dDM| <= 10 and |dt| <= 0.5 W_eff (snd_match_injections).  cands:
@@ -672,6 +703,10 @@ def main():
         result["direct"] = direct_leg(snd, torch, spec, x, pkw, dev, ref)
         result["direct"]["snd_tree_ms"] = round(float(stage_ms.sum()), 3)
         log(f"[bench] direct: {result['direct']['ms']} ms vs tree {result['direct']['snd_tree_ms']} ms")
+        if mode == "float":
+            result["subband"] = subband_leg(snd, torch, spec, x, pkw, dev, ref)
+            result["subband"]["snd_tree_ms"] = round(float(stage_ms.sum()), 3)
+            log(f"[bench] sub-band: {result['subband']['ms']} ms")
     if "fdmt" in legs and mode == "float" and plan.in_dtype == "f32":
         log("[bench] FDMT baseline on the same block")
         torch.cuda.empty_cache()
