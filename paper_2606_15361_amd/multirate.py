@@ -60,7 +60,9 @@ class MultiRate:
     def __init__(self, freqs, dms, tsamp_s: float, nsamp: int, *, mode: str = "float", s_max: int = 16,
                  thresholds=None, widths=(1, 2, 4, 8, 16, 32, 64), threshold: float = 7.0, sigma_min: float = 0.0,
                  n_min: int = 10, dm_tol: float = 20.0, t_tol_ms: float = 200.0, device="cuda", bit_input=False,
-                 **plan_kw):
+                 detect_kw=None, **plan_kw):
+        """detect_kw: further Detector arguments for every band (e.g. n_base_widths and
+        width_alpha for the DM-scaled width set, sigma)."""
         self.freqs = np.ascontiguousarray(freqs, dtype=np.float64)
         self.dms = np.ascontiguousarray(dms, dtype=np.float64)
         self.tsamp_s, self.nsamp, self.mode = tsamp_s, int(nsamp), mode
@@ -79,7 +81,7 @@ class MultiRate:
             plan = Plan(self.freqs, self.dms[idx], tsamp_s * s, self.nsamp // s, mode=mode, **kw)
             plan.upload(device)
             det = Detector(plan, widths=widths, threshold=threshold, sigma_min=sigma_min, n_min=n_min,
-                           device=device)
+                           device=device, **(detect_kw or {}))
             self.bands.append(dict(s=s, idx=idx, plan=plan, det=det))
 
     def band_input(self, z, s: int):
