@@ -312,3 +312,45 @@ def test_validation_host_logic_matches_the_oracle(snd, orc):
         snd.match_injections([1.0], [1.0], [7.0], [1.0], [1.0], [-1.0])
     with pytest.raises(snd.SndError):
         snd.effective_width(f, 0.138e-3, [-1.0], [1.0])
+
+
+def test_new_entry_points_reject_bad_arguments(snd):
+    """Front-end, FDMT and detector-descriptor checks fail before any device call."""
+    from paper_2606_15361_amd import _capi
+    L = _capi.lib()
+    fake = C.c_void_p(0x1000)  # never dereferenced: every call below fails its argument checks
+    P = C.c_void_p
+    # zero-DM: null filterbank, pitch below nsamp, negative gamma
+    assert L.snd_zero_dm(None, 100, 4, 100, 5.0, None, None) == _capi.ERR_INVALID
+    assert L.snd_zero_dm(fake, 50, 4, 100, 5.0, None, None) == _capi.ERR_INVALID
+    assert L.snd_zero_dm(fake, 100, 4, 100, -1.0, None, None) == _capi.ERR_INVALID
+    # channel flagging: the sigma buffer is required; nchan, window, k and flags pitch checked
+    assert L.snd_flag_channels(fake, 100, 4, 100, 10, 5.0, None, None, 0, None) == _capi.ERR_INVALID
+    assert L.snd_flag_channels(fake, 100, 9000, 100, 10, 5.0, fake, None, 0, None) == _capi.ERR_INVALID
+    assert L.snd_flag_channels(fake, 100, 4, 100, 0, 5.0, fake, None, 0, None) == _capi.ERR_INVALID
+    assert L.snd_flag_channels(fake, 100, 4, 100, 10, -2.0, fake, None, 0, None) == _capi.ERR_INVALID
+    assert L.snd_flag_channels(fake, 100, 4, 100, 10, 5.0, fake, fake, 3, None) == _capi.ERR_INVALID
+    # FDMT: channel count a power of two, descending frequencies, the sweep inside the block
+    f = np.ascontiguousarray(synth.channel_freqs(64))
+    h = P()
+    assert L.snd_fdmt_create(48, f.ctypes.data_as(P), 0.25, 0.138e-3, 100.0, 4096, C.byref(h)) == _capi.ERR_INVALID
+    fa = np.ascontiguousarray(f[::-1])
+    assert L.snd_fdmt_create(64, fa.ctypes.data_as(P), 0.25, 0.138e-3, 100.0, 4096, C.byref(h)) == _capi.ERR_INVALID
+    assert L.snd_fdmt_create(64, f.ctypes.data_as(P), 0.25, 0.138e-3, 3000.0, 1000, C.byref(h)) == _capi.ERR_INVALID
+    assert L.snd_fdmt_create(64, f.ctypes.data_as(P), 0.25, 0.138e-3, 100.0, 4096, C.byref(h)) == _capi.OK
+    nd = C.c_int64()
+    assert L.snd_fdmt_query(h, C.byref(nd), None, None, None, None) == _capi.OK and nd.value > 1
+    # execute before upload is a state error, not a device call
+    assert L.snd_fdmt_execute(h, fake, 4096, fake, 4096, fake, 1 << 40, None) == _capi.ERR_STATE
+    assert L.snd_fdmt_destroy(h) == _capi.OK
+    # detector descriptor: sigma_estimator must be 0 or 1
+    p = snd.Plan(synth.channel_freqs(4), np.zeros(3), 0.138e-3, 100, mode="graded", branching=2)
+    w = np.array([1, 2], np.int32)
+    d = _capi.DetectDesc()
+    d.widths = w.ctypes.data_as(C.POINTER(C.c_int32))
+    d.nwidths, d.threshold, d.sigma_min, d.closing_radius, d.n_min, d.max_pixels = 2, 6.0, 0.0, 4, 10, 100
+    d.sigma_estimator = 2
+    nb = C.c_int64()
+    assert L.snd_detect_workspace(p.handle, C.byref(d), C.byref(nb)) == _capi.ERR_INVALID
+    d.sigma_estimator = 1
+    assert L.snd_detect_workspace(p.handle, C.byref(d), C.byref(nb)) == _capi.OK
