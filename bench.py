@@ -527,7 +527,9 @@ def serve_leg(snd, synth, torch, dev, seconds):
         for b in range(40):
             assert server.admit(b, kind(b))
         arr = {b: a for b, a in enumerate(synth.arrival_times(rng, 48, seconds + 5.0, period))}
-        joins = [(10.0 * (i + 1), 40 + i, kind(40 + i)) for i in range(int(seconds // 10))]
+        # beam i leaves at 10 (i + 1) s; the joining beam cycles through the 48 (after the 8 not
+        # yet started, the beams that left first come back)
+        joins = [(10.0 * (i + 1), (40 + i) % 48, kind((40 + i) % 48)) for i in range(int(seconds // 10))]
         leaves = [(10.0 * (i + 1), i) for i in range(int(seconds // 10))]
         log(f"[bench] serving ({form}) for {seconds:.0f} s")
         recs, adm = serve.run_schedule(server, arr, src, duration_s=seconds, joins=joins, leaves=leaves, log=log)
