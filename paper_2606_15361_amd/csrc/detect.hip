@@ -5,7 +5,7 @@
 //   Integer planes use exact 64-bit sums S1, S2 and sigma = sqrt(n*S2 - S1*S1)/n in one fixed
 //   FP64 expression; float planes use one FP64 pass about the row's first sample.  A floor
 //   sigma_min applies.
-// k_snr: one workgroup per (row, 4096-sample tile).  The tile plus the widest boxcar is
+// k_snr: one workgroup per (row, 2048-sample tile).  The tile plus the widest boxcar is
 //   staged in LDS as an inclusive prefix sum (int32 for integer planes: exact; FP64 for float
 //   planes), every sample then evaluates all widths with two LDS reads each:
 //   SNR(t, W) = (S_W(t) - mu W) / (sigma sqrt W), maximum over widths (first width on ties).
@@ -27,7 +27,7 @@ typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 template <typename T> using global_ptr = __attribute__((address_space(1))) T *;
 template <typename T> __device__ inline global_ptr<const T> as_global(const T *p) { return (global_ptr<const T>)p; }
 
-constexpr int kSnrTile = 4096;
+constexpr int kSnrTile = 2048;
 constexpr int kThreads = 256;
 
 template <typename T> struct IsInt { static constexpr bool value = true; };
@@ -150,7 +150,8 @@ __global__ __launch_bounds__(kThreads) void k_snr(const T *plane, int64_t pitch,
     using P = typename PrefixType<T>::type;
     constexpr int kMaxPer = (kSnrTile + kMaxWidth + kThreads - 1) / kThreads;  // elements per thread
     constexpr int kSlabs = kSnrTile / kThreads;                                // samples per thread
-    __shared__ P pre[kSnrTile + kMaxWidth + 1];
+    extern __shared__ __align__(16) unsigned char snr_dyn[];  // prefix sums: tile + widest width + 1
+    P *pre = reinterpret_cast<P *>(snr_dyn);
     __shared__ P wtot[kThreads / 64];
     __shared__ int slab_off[kSlabs][kThreads / 64];
     __shared__ unsigned int base_s;
@@ -478,11 +479,14 @@ int launch_typed(const void *plane, int64_t pitch, int ndm, int64_t n, double si
     if (sigma_mad)  // sigma from the median absolute deviation instead (the mean stays)
         hipLaunchKernelGGL((k_rowmad<T>), dim3((uint32_t)ndm), dim3(kThreads), 0, st, p, pitch, n, sigma_min, stats);
     dim3 grid((uint32_t)((n + kSnrTile - 1) / kSnrTile), (uint32_t)ndm);
+    // the prefix array holds the tile plus the widest boxcar of the list (every row's set is a
+    // leading part of the list)
+    const size_t lds = (size_t)(kSnrTile + a.w[a.nw - 1] + 1) * sizeof(typename PrefixType<T>::type);
     switch (a.nw) {
-#define SND_NW(N) case N: hipLaunchKernelGGL((k_snr<T, N>), grid, dim3(kThreads), 0, st, p, pitch, n, stats, a); break;
+#define SND_NW(N) case N: hipLaunchKernelGGL((k_snr<T, N>), grid, dim3(kThreads), lds, st, p, pitch, n, stats, a); break;
     SND_NW(1) SND_NW(2) SND_NW(3) SND_NW(4) SND_NW(5) SND_NW(6) SND_NW(7) SND_NW(8)
 #undef SND_NW
-    default: hipLaunchKernelGGL((k_snr<T, 0>), grid, dim3(kThreads), 0, st, p, pitch, n, stats, a); break;
+    default: hipLaunchKernelGGL((k_snr<T, 0>), grid, dim3(kThreads), lds, st, p, pitch, n, stats, a); break;
     }
     return (int)hipGetLastError();
 }
