@@ -763,6 +763,19 @@ def main():
                              detection=completeness(snd, spec, c2, plan.n_out))
             del d2
         result["detect_sigma"] = opt
+        # closing and labelling on the host (cells read back) or on the device (candidates only)
+        lab = {}
+        for where in ("host", "device"):
+            d2 = snd.Detector(plan, widths=spec.widths, threshold=7.0, device=dev, label=where)
+            c2 = d2.run(plane)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            for _ in range(3):
+                c2 = d2.run(plane)
+            torch.cuda.synchronize()
+            lab[where] = dict(ms=round((time.perf_counter() - t) * 1e3 / 3, 3), candidates=len(c2))
+            del d2
+        result["detect_label"] = lab
     legs = [l for l in args.legs.split(",") if l and l != "none"]
     if "direct" in legs and plan.in_dtype == "bits":
         result["direct"] = {"skipped": "bit input needs the materialised leaf level"}

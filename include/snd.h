@@ -291,7 +291,12 @@ typedef struct {
                                 arithmetic (FP32 for float planes); the robust per-row MAD the
                                 paper mentions for bounded (graded) planes.  mu_k stays the mean
                                 and sigma_min still floors sigma_k. */
-    int32_t reserved;        /* set to 0 */
+    int32_t label_on_device; /* 0: closing and labelling on the host (from the thresholded cells
+                                read back).  1: on the device as well, so that snd_detect reads
+                                back only the candidates; the workspace then grows by two
+                                bitmasks of the padded plane and per-run tables for max_pixels
+                                runs (SND_ERR_CAPACITY beyond that).  Same candidates either way.
+                                snd_detect_launch / snd_detect_collect label on the host. */
 } snd_detect_desc;
 
 typedef struct {

@@ -57,7 +57,7 @@ class DetectDesc(C.Structure):
     _fields_ = [("widths", C.POINTER(C.c_int32)), ("nwidths", C.c_int32), ("closing_radius", C.c_int32),
                 ("threshold", C.c_double), ("sigma_min", C.c_double), ("n_min", C.c_int32),
                 ("n_base_widths", C.c_int32), ("max_pixels", C.c_int64), ("width_alpha", C.c_double),
-                ("sigma_estimator", C.c_int32), ("reserved", C.c_int32)]
+                ("sigma_estimator", C.c_int32), ("label_on_device", C.c_int32)]
 
 
 class BandCandidate(C.Structure):

@@ -38,6 +38,14 @@ snd_status check_desc(const snd::PlanImpl &P, const snd_detect_desc *d)
         snd::set_error("threshold must be > 0, sigma_min >= 0, 0 <= closing_radius <= 64, n_min >= 1, max_pixels >= 1");
         return SND_ERR_INVALID;
     }
+    if (d->label_on_device != 0 && d->label_on_device != 1) {
+        snd::set_error("label_on_device must be 0 or 1");
+        return SND_ERR_INVALID;
+    }
+    if (d->label_on_device && d->max_pixels > 0x7fffffffLL) {
+        snd::set_error("labelling on the device takes at most 2^31 - 1 cells");
+        return SND_ERR_INVALID;
+    }
     if (d->sigma_estimator != 0 && d->sigma_estimator != 1) {
         snd::set_error("sigma_estimator must be 0 (standard deviation) or 1 (median absolute deviation)");
         return SND_ERR_INVALID;
@@ -60,9 +68,52 @@ int64_t row_nw_offset(const snd::PlanImpl &P, const snd_detect_desc *d)
     return round_up(pixels_offset(P) + d->max_pixels * (int64_t)sizeof(snd::Pixel), 256);
 }
 
-int64_t workspace_bytes_for(const snd::PlanImpl &P, const snd_detect_desc *d)
+int64_t host_workspace_end(const snd::PlanImpl &P, const snd_detect_desc *d)
 {
     return row_nw_offset(P, d) + round_up((int64_t)P.ndm * 4, 256);
+}
+
+// Labelling on the device: after the host part's regions, two bitmasks of the plane padded by
+// 2r, then per-row and per-run tables (runs up to max_pixels), then the candidate list.
+struct LabelLayout {
+    int64_t rows = 0, wd = 0, mask_a = 0, mask_b = 0, nruns = 0, run_ptr = 0, rs = 0, re = 0, rk = 0, parent = 0,
+            npix = 0, smax = 0, pkey = 0, pwidx = 0, ncand = 0, cand = 0, cand_npix = 0, end = 0;
+};
+
+LabelLayout label_layout(const snd::PlanImpl &P, const snd_detect_desc *d)
+{
+    LabelLayout L;
+    const int64_t r = d->closing_radius, m = d->max_pixels;
+    L.rows = P.ndm + 4 * r;
+    L.wd = (P.n_out + 4 * r + 63) / 64;
+    int64_t o = round_up(host_workspace_end(P, d), 256);
+    auto take = [&](int64_t bytes) {
+        const int64_t at = o;
+        o = round_up(o + bytes, 256);
+        return at;
+    };
+    L.mask_a = take(L.rows * L.wd * 8);
+    L.mask_b = take(L.rows * L.wd * 8);
+    L.nruns = take((int64_t)P.ndm * 4);
+    L.run_ptr = take(((int64_t)P.ndm + 1) * 4);
+    L.rs = take(m * 4);
+    L.re = take(m * 4);
+    L.rk = take(m * 4);
+    L.parent = take(m * 4);
+    L.npix = take(m * 8);
+    L.smax = take(m * 8);
+    L.pkey = take(m * 8);
+    L.pwidx = take(m * 4);
+    L.ncand = take(8);
+    L.cand = take(m * (int64_t)sizeof(snd::Pixel));
+    L.cand_npix = take(m * 8);
+    L.end = o;
+    return L;
+}
+
+int64_t workspace_bytes_for(const snd::PlanImpl &P, const snd_detect_desc *d)
+{
+    return d->label_on_device ? label_layout(P, d).end : host_workspace_end(P, d);
 }
 
 // DM-scaled width set: the number of leading widths each row uses (Methods, "Matched
@@ -302,6 +353,85 @@ snd_status candidates_from_pixels(std::vector<snd::Pixel> &px, const snd::PlanIm
     return SND_OK;
 }
 
+// Closing, labelling, island sizes and peaks on the device; only the candidates come back.
+snd_status label_device(const snd::PlanImpl &P, const snd_detect_desc *d, uint8_t *ws, const snd::SnrArgs &sa,
+                        snd_candidate *h_out, int64_t cap, int64_t *h_count, hipStream_t st)
+{
+    const LabelLayout L = label_layout(P, d);
+    snd::LabelArgs a{};
+    a.pixels = sa.pixels;
+    a.count = sa.counter;
+    a.max_pixels = d->max_pixels;
+    a.ndm = P.ndm;
+    a.n = P.n_out;
+    a.r = d->closing_radius;
+    a.rows = L.rows;
+    a.wd = L.wd;
+    a.mask_a = reinterpret_cast<uint64_t *>(ws + L.mask_a);
+    a.mask_b = reinterpret_cast<uint64_t *>(ws + L.mask_b);
+    a.nruns = reinterpret_cast<int32_t *>(ws + L.nruns);
+    a.run_ptr = reinterpret_cast<int32_t *>(ws + L.run_ptr);
+    a.rs = reinterpret_cast<int32_t *>(ws + L.rs);
+    a.re = reinterpret_cast<int32_t *>(ws + L.re);
+    a.rk = reinterpret_cast<int32_t *>(ws + L.rk);
+    a.parent = reinterpret_cast<int32_t *>(ws + L.parent);
+    a.npix = reinterpret_cast<unsigned long long *>(ws + L.npix);
+    a.smax = reinterpret_cast<unsigned long long *>(ws + L.smax);
+    a.pkey = reinterpret_cast<unsigned long long *>(ws + L.pkey);
+    a.pwidx = reinterpret_cast<int32_t *>(ws + L.pwidx);
+    a.max_runs = d->max_pixels;
+    a.n_min = d->n_min;
+    a.ncand = reinterpret_cast<unsigned int *>(ws + L.ncand);
+    a.cand = reinterpret_cast<snd::Pixel *>(ws + L.cand);
+    a.cand_npix = reinterpret_cast<int64_t *>(ws + L.cand_npix);
+    *h_count = 0;
+    auto hip_fail = [](hipError_t e, const char *what) {
+        snd::set_error(std::string(what) + ": " + hipGetErrorString(e));
+        return SND_ERR_HIP;
+    };
+    int e = snd::launch_label(a, st);
+    if (e) return hip_fail((hipError_t)e, "labelling launch");
+    int32_t total = 0;
+    hipError_t he = hipMemcpyAsync(&total, a.run_ptr + P.ndm, sizeof(total), hipMemcpyDeviceToHost, st);
+    if (he == hipSuccess) he = hipStreamSynchronize(st);
+    if (he != hipSuccess) return hip_fail(he, "labelling read-back");
+    if ((int64_t)total > a.max_runs) {  // the tables below hold max_pixels runs
+        snd::set_error("the closed mask has more runs than max_pixels");
+        return SND_ERR_CAPACITY;
+    }
+    e = snd::launch_label_finish(a, st);
+    if (e) return hip_fail((hipError_t)e, "labelling launch");
+    unsigned int nc = 0;
+    he = hipMemcpyAsync(&nc, a.ncand, sizeof(nc), hipMemcpyDeviceToHost, st);
+    if (he == hipSuccess) he = hipStreamSynchronize(st);
+    if (he != hipSuccess) return hip_fail(he, "labelling read-back");
+    std::vector<snd::Pixel> c(nc);
+    std::vector<int64_t> np(nc);
+    if (nc) {
+        he = hipMemcpyAsync(c.data(), a.cand, sizeof(snd::Pixel) * nc, hipMemcpyDeviceToHost, st);
+        if (he == hipSuccess) he = hipMemcpyAsync(np.data(), a.cand_npix, sizeof(int64_t) * nc, hipMemcpyDeviceToHost, st);
+        if (he == hipSuccess) he = hipStreamSynchronize(st);
+        if (he != hipSuccess) return hip_fail(he, "labelling read-back");
+    }
+    std::vector<snd_candidate> out(nc);
+    for (unsigned int i = 0; i < nc; ++i) {
+        snd_candidate &x = out[i];
+        x = snd_candidate{};
+        x.dm_index = c[i].k;
+        x.width = d->widths[c[i].widx];
+        x.t = c[i].t;
+        x.snr = c[i].snr;
+        x.dm = P.dm[(size_t)c[i].k];
+        x.npix = np[i];
+    }
+    std::sort(out.begin(), out.end(), [](const snd_candidate &x, const snd_candidate &y) {
+        return x.dm_index != y.dm_index ? x.dm_index < y.dm_index : x.t < y.t;
+    });
+    *h_count = (int64_t)out.size();
+    for (int64_t i = 0; i < cap && i < (int64_t)out.size(); ++i) h_out[i] = out[(size_t)i];
+    return SND_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -445,6 +575,7 @@ snd_status snd_detect(snd_plan plan, const void *d_plane, int64_t plane_pitch, c
         snd::set_error("more thresholded cells than max_pixels");
         return SND_ERR_CAPACITY;
     }
+    if (desc->label_on_device) return label_device(P, desc, ws, a, h_out, cap, h_count, st);
     std::vector<snd::Pixel> px(count);
     if (count) {
         // through a pinned staging buffer of this thread (grown on demand, kept until exit):

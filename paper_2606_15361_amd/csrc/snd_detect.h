@@ -42,4 +42,28 @@ struct SnrArgs {
 int launch_detect(int plane_dtype, const void *plane, int64_t pitch, int ndm, int64_t n, double sigma_min,
                   int sigma_mad, double *stats, const SnrArgs &a, void *stream);
 
+// Closing and labelling on the device (label.hip).  launch_label builds the closed mask and
+// counts its runs (run_ptr[ndm] = total); the caller checks the total against max_runs before
+// launch_label_finish emits one candidate per island of at least n_min cells.
+struct LabelArgs {
+    const Pixel *pixels;          // thresholded cells and their count (from the S/N kernel)
+    const unsigned int *count;
+    int64_t max_pixels;
+    int ndm;
+    int64_t n;                    // valid samples per row
+    int r;                        // closing radius
+    int64_t rows, wd;             // mask: ndm + 4r rows of wd 64-bit words (n + 4r columns)
+    uint64_t *mask_a, *mask_b;
+    int32_t *nruns, *run_ptr;     // [ndm], [ndm + 1]
+    int32_t *rs, *re, *rk, *parent;            // per run: first and last column, row, union-find
+    unsigned long long *npix, *smax, *pkey;    // per run (roots): size, peak S/N bits, peak (row, t)
+    int32_t *pwidx;
+    int64_t max_runs, n_min;
+    unsigned int *ncand;          // 8 bytes
+    Pixel *cand;                  // [max_runs]
+    int64_t *cand_npix;           // [max_runs]
+};
+int launch_label(const LabelArgs &a, void *stream);
+int launch_label_finish(const LabelArgs &a, void *stream);
+
 }  // namespace snd

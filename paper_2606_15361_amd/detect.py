@@ -15,11 +15,12 @@ class Detector:
 
     def __init__(self, plan, widths=(1, 2, 4, 8, 16, 32, 64), threshold: float = 7.0, sigma_min: float = 0.0,
                  closing_radius: int = 4, n_min: int = 10, max_pixels: int = 1 << 20, device="cuda",
-                 n_base_widths: int = 0, width_alpha: float = 0.0, sigma: str = "std"):
+                 n_base_widths: int = 0, width_alpha: float = 0.0, sigma: str = "std", label: str = "host"):
         """n_base_widths > 0 selects the DM-scaled width set: each row uses the first
         n_base_widths widths and the further ones up to width_alpha times its dispersive sweep
         (the paper: widths 1..1024 in powers of two, n_base_widths 4, width_alpha 0.1).
-        sigma: "std" (row standard deviation) or "mad" (median absolute deviation, scaled)."""
+        sigma: "std" (row standard deviation) or "mad" (median absolute deviation, scaled).
+        label: "host" or "device": where run() closes and labels the thresholded cells."""
         import torch
         self.plan = plan
         self._w = np.ascontiguousarray(widths, dtype=np.int32)
@@ -35,6 +36,9 @@ class Detector:
         if sigma not in ("std", "mad"):
             raise ValueError('sigma must be "std" or "mad"')
         d.sigma_estimator = 1 if sigma == "mad" else 0
+        if label not in ("host", "device"):
+            raise ValueError('label must be "host" or "device"')
+        d.label_on_device = 1 if label == "device" else 0
         d.max_pixels = max_pixels
         self.desc = d
         nb = C.c_int64()

@@ -301,3 +301,58 @@ def test_mad_sigma_float_plane(snd, orc):
     o_snr, o_widx, _, _ = orc.matched_filter(plane.astype(np.float64), WIDTHS, integer_plane=False, sigma_rows=o_sig)
     s = snr.cpu().numpy()
     assert np.max(np.abs(s - o_snr)) <= 1e-4 * max(1.0, np.abs(o_snr).max())
+
+
+@pytest.mark.parametrize("mode,hi", [("graded", 255), ("graded", 9), ("binary", 1), ("float", 0)])
+def test_label_on_device_matches_host_and_oracle(snd, orc, mode, hi):
+    # closing and labelling on the device: the same candidates as the host path and the oracle
+    rng = synth.make_rng(23 + hi)
+    ndm, n = 41, 5003
+    if mode == "binary":
+        plane = (rng.random((ndm, n)) < 0.02).astype(np.uint8)
+        plane[10:14, 1000:1030] = 1
+        plane[0:3, 0:40] = 1            # islands on the plane's edges
+        plane[ndm - 2:, n - 30:] = 1
+        smin, theta = 0.15, 6.0
+    elif mode == "graded":
+        plane = rng.integers(0, hi + 1, (ndm, n)).astype(np.uint8)
+        plane[20:23, 2000:2040] = hi
+        plane[0, :50] = hi
+        smin, theta = 0.0, 5.0
+    else:
+        plane = rng.standard_normal((ndm, n)).astype(np.float32)
+        plane[7:10, 3000:3008] += 4.0
+        plane[ndm - 1, n - 20:] += 5.0
+        smin, theta = 0.0, 4.0
+    p = _plan_for(snd, ndm, n, mode)
+    dev = torch.from_numpy(plane).cuda()
+    integer = mode != "float"
+    o_snr, o_widx, _, _ = orc.matched_filter(plane.astype(np.float64), WIDTHS, integer_plane=integer, sigma_min=smin)
+    for r, nmin in ((4, 10), (1, 1), (0, 1), (6, 3)):
+        _say(f"device labelling mode={mode} hi={hi} r={r} n_min={nmin}")
+        host = snd.Detector(p, WIDTHS, threshold=theta, sigma_min=smin, closing_radius=r, n_min=nmin).run(dev)
+        devc = snd.Detector(p, WIDTHS, threshold=theta, sigma_min=smin, closing_radius=r, n_min=nmin,
+                            label="device").run(dev)
+        assert [(c["k"], c["t"], c["widx"], c["npix"], c["snr"]) for c in devc] == \
+               [(c["k"], c["t"], c["widx"], c["npix"], c["snr"]) for c in host]
+        if integer:
+            _cands_equal(devc, orc.candidates(o_snr, o_widx, theta, radius=r, n_min=nmin))
+    # more closed runs than the run tables hold: a capacity error, not a fault
+    det = snd.Detector(p, WIDTHS, threshold=theta, sigma_min=smin, closing_radius=4, n_min=1, label="device",
+                       max_pixels=int((o_snr >= theta).sum()))
+    try:
+        det.run(dev)
+    except snd.SndError as e:
+        assert e.status == -5
+
+
+def test_label_on_device_full_size_float(snd, orc):
+    spec = synth.workload(2)
+    z = spec.filterbank()
+    p = snd.Plan(spec.freqs, spec.dms, spec.tsamp_s, spec.nsamp, mode="float", branching=4)
+    y = p.execute(torch.from_numpy(z).cuda())
+    host = snd.Detector(p, WIDTHS, threshold=7.0).run(y)
+    devc = snd.Detector(p, WIDTHS, threshold=7.0, label="device").run(y)
+    _say(f"full-size float: {len(host)} candidates on the host, {len(devc)} on the device")
+    assert [(c["k"], c["t"], c["widx"], c["npix"], c["snr"]) for c in devc] == \
+           [(c["k"], c["t"], c["widx"], c["npix"], c["snr"]) for c in host]
