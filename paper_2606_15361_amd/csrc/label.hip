@@ -100,47 +100,60 @@ __device__ inline uint64_t crop_word(const uint64_t *row, int64_t w, int pad, in
     return v;
 }
 
-// runs of plane row k: count (emit = false) or write (start, end, row) from base on
+// runs of plane row k, one wave per row, 64 consecutive words per step (one per lane): count
+// them (EMIT = false) or write them from run_ptr[k] on.  A run's start is a set bit whose left
+// neighbour is clear, its end a set bit whose right neighbour is clear; the i-th start and the
+// i-th end of a row belong to its i-th run, so starts and ends are placed by their own ranks.
 template <bool EMIT>
 __global__ void k_runs(const uint64_t *mask, int64_t wd, int ndm, int64_t n, int pad, int32_t *nruns,
                        const int32_t *run_ptr, int32_t *rs, int32_t *re, int32_t *rk, int64_t max_runs)
 {
-    const int k = blockIdx.x * kT + threadIdx.x;
-    if (k >= ndm) return;
+    const int lane = threadIdx.x & 63;
+    const int k = blockIdx.x * (kT / 64) + (threadIdx.x >> 6);
+    if (k >= ndm) return;  // whole waves
     const uint64_t *row = mask + ((int64_t)k + pad) * wd;
     const int64_t w0 = pad / 64, w1 = (pad + n + 63) / 64;
-    int32_t cnt = 0;
-    int64_t base = EMIT ? run_ptr[k] : 0;
-    uint64_t carry = 0;  // last bit of the previous word
-    int64_t start = -1;
-    for (int64_t w = w0; w < w1; ++w) {
-        const uint64_t v = crop_word(row, w, pad, n);
-        if (!EMIT) {
-            cnt += __popcll(v & ~((v << 1) | carry));
-        } else {
-            uint64_t s = v & ~((v << 1) | carry);   // run starts
-            uint64_t e = v & ~((v >> 1) | ((w + 1 < w1 ? crop_word(row, w + 1, pad, n) : 0ull) << 63));  // run ends
-            while (s | e) {
-                // bits in increasing column order; a start before (or at) an end of the same run
-                const int bs = s ? __builtin_ctzll(s) : 64, be = e ? __builtin_ctzll(e) : 64;
-                if (bs <= be && s) {
-                    start = 64 * w + bs - pad;
-                    s &= s - 1;
-                } else {
-                    const int64_t idx = base + cnt;
-                    if (idx < max_runs) {
-                        rs[idx] = (int32_t)start;
-                        re[idx] = (int32_t)(64 * w + be - pad);
-                        rk[idx] = k;
-                    }
-                    ++cnt;
-                    e &= e - 1;
-                }
+    const int64_t base = EMIT ? run_ptr[k] : 0;
+    int64_t ns = 0, ne = 0;       // starts and ends of the row before this step
+    uint64_t prev_last = 0;       // last word of the previous step (lane 63's)
+    for (int64_t wb = w0; wb < w1; wb += 64) {
+        const int64_t w = wb + lane;
+        const uint64_t v = w < w1 ? crop_word(row, w, pad, n) : 0ull;
+        // neighbouring words: lane - 1 (or the previous step's last) and lane + 1 (or the next
+        // step's first, read directly)
+        uint64_t left = __shfl_up(v, 1, 64);
+        if (lane == 0) left = prev_last;
+        uint64_t right = __shfl_down(v, 1, 64);
+        if (lane == 63) right = w + 1 < w1 ? crop_word(row, w + 1, pad, n) : 0ull;
+        const uint64_t s = v & ~((v << 1) | (left >> 63));
+        const uint64_t e = v & ~((v >> 1) | (right << 63));
+        const int cs = __popcll(s), ce = __popcll(e);
+        // inclusive scans of the per-lane counts
+        int is = cs, ie = ce;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const int us = __shfl_up(is, d, 64), ue = __shfl_up(ie, d, 64);
+            if (lane >= d) {
+                is += us;
+                ie += ue;
             }
         }
-        carry = v >> 63;
+        if (EMIT) {
+            int64_t r = base + ns + (is - cs);
+            for (uint64_t x = s; x; x &= x - 1, ++r)
+                if (r < max_runs) {
+                    rs[r] = (int32_t)(64 * w + __builtin_ctzll(x) - pad);
+                    rk[r] = k;
+                }
+            r = base + ne + (ie - ce);
+            for (uint64_t x = e; x; x &= x - 1, ++r)
+                if (r < max_runs) re[r] = (int32_t)(64 * w + __builtin_ctzll(x) - pad);
+        }
+        ns += __shfl(is, 63, 64);
+        ne += __shfl(ie, 63, 64);
+        prev_last = __shfl(v, 63, 64);
     }
-    if (!EMIT) nruns[k] = cnt;
+    if (!EMIT && lane == 0) nruns[k] = (int32_t)ns;
 }
 
 // exclusive prefix sum of nruns[0..ndm) into run_ptr[0..ndm], one workgroup
@@ -299,7 +312,8 @@ int launch_label(const LabelArgs &a, void *stream)
     hipLaunchKernelGGL((k_close_k<true>), dim3(nblocks(words)), dim3(kT), 0, st, a.mask_b, a.mask_a, a.rows, a.wd, a.r);
     hipLaunchKernelGGL((k_close_t<false>), dim3(nblocks(words)), dim3(kT), 0, st, a.mask_a, a.mask_b, a.rows, a.wd, a.r);
     hipLaunchKernelGGL((k_close_k<false>), dim3(nblocks(words)), dim3(kT), 0, st, a.mask_b, a.mask_a, a.rows, a.wd, a.r);
-    hipLaunchKernelGGL((k_runs<false>), dim3(nblocks(a.ndm)), dim3(kT), 0, st, a.mask_a, a.wd, a.ndm, a.n, pad, a.nruns,
+    const unsigned int nbr = (unsigned int)((a.ndm + kT / 64 - 1) / (kT / 64));  // one wave per row
+    hipLaunchKernelGGL((k_runs<false>), dim3(nbr), dim3(kT), 0, st, a.mask_a, a.wd, a.ndm, a.n, pad, a.nruns,
                        a.run_ptr, a.rs, a.re, a.rk, a.max_runs);
     hipLaunchKernelGGL(k_scan_runs, dim3(1), dim3(kT), 0, st, a.nruns, a.ndm, a.run_ptr);
     return (int)hipGetLastError();
@@ -310,7 +324,8 @@ int launch_label_finish(const LabelArgs &a, void *stream)
     hipStream_t st = (hipStream_t)stream;
     const int pad = 2 * a.r;
     const unsigned int nb = nblocks(a.max_runs);
-    hipLaunchKernelGGL((k_runs<true>), dim3(nblocks(a.ndm)), dim3(kT), 0, st, a.mask_a, a.wd, a.ndm, a.n, pad, a.nruns,
+    const unsigned int nbr = (unsigned int)((a.ndm + kT / 64 - 1) / (kT / 64));  // one wave per row
+    hipLaunchKernelGGL((k_runs<true>), dim3(nbr), dim3(kT), 0, st, a.mask_a, a.wd, a.ndm, a.n, pad, a.nruns,
                        a.run_ptr, a.rs, a.re, a.rk, a.max_runs);
     hipLaunchKernelGGL(k_iota32, dim3(nb), dim3(kT), 0, st, a.parent, a.max_runs);
     hipLaunchKernelGGL(k_fill64, dim3(nb), dim3(kT), 0, st, reinterpret_cast<uint64_t *>(a.npix), a.max_runs, 0ull);
