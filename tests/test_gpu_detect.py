@@ -356,3 +356,25 @@ def test_label_on_device_full_size_float(snd, orc):
     _say(f"full-size float: {len(host)} candidates on the host, {len(devc)} on the device")
     assert [(c["k"], c["t"], c["widx"], c["npix"], c["snr"]) for c in devc] == \
            [(c["k"], c["t"], c["widx"], c["npix"], c["snr"]) for c in host]
+
+
+def test_detect_edge_cases_both_labelling_paths(snd, orc):
+    # no cell above threshold, a single cell, and single-sample rows (MAD of one value is 0)
+    ndm, n = 9, 700
+    p = _plan_for(snd, ndm, n, "graded")
+    zero = torch.zeros((ndm, n), dtype=torch.uint8, device="cuda")
+    for where in ("host", "device"):
+        det = snd.Detector(p, WIDTHS, threshold=5.0, label=where)
+        assert det.run(zero) == [] and det.npixels == 0
+    one = np.zeros((ndm, n), np.uint8)
+    one[4, 350] = 200
+    dev = torch.from_numpy(one).cuda()
+    o_snr, o_widx, _, _ = orc.matched_filter(one.astype(np.float64), WIDTHS, integer_plane=True)
+    want = orc.candidates(o_snr, o_widx, 5.0, radius=4, n_min=1)
+    for where in ("host", "device"):
+        _cands_equal(snd.Detector(p, WIDTHS, threshold=5.0, n_min=1, label=where).run(dev), want)
+    p1 = _plan_for(snd, 3, 1, "graded")
+    d1 = snd.Detector(p1, [1], threshold=5.0, sigma="mad")
+    d1.run(torch.tensor([[3], [0], [9]], dtype=torch.uint8, device="cuda"))
+    mu, sg = d1.row_stats()
+    assert np.array_equal(sg.cpu().numpy(), [0.0, 0.0, 0.0]) and np.array_equal(mu.cpu().numpy(), [3.0, 0.0, 9.0])

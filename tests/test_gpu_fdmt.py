@@ -69,3 +69,13 @@ def test_fdmt_argument_errors(snd):
     f = synth.channel_freqs(64)
     with pytest.raises(snd.SndError):
         snd.Fdmt(f, 0.25, 0.138e-3, 3000.0, 1000)  # the sweep does not fit the block
+
+
+def test_fdmt_dm_zero_is_the_channel_sum(snd, orc):
+    f = synth.channel_freqs(16)
+    x = synth.make_rng(5).standard_normal((16, 777)).astype(np.float32)
+    fd = snd.Fdmt(f, 1.0, 0.138e-3, 0.0, 777)
+    assert fd.n_delays == 1 and fd.n_out == 777
+    y = fd.execute(torch.from_numpy(x).cuda()).cpu().numpy()
+    want = orc.fdmt(x, f, 1.0, 0.138e-3, 0.0)
+    assert np.allclose(y, want, rtol=0, atol=1e-5) and np.allclose(want[0], x.astype(np.float64).sum(0))
