@@ -68,7 +68,7 @@ def build(verbose: bool = False) -> str:
             sys.stderr.write(f"--- {src} ---\n{text}\n")
         raise RuntimeError("libsnd build failed: " + ", ".join(s for s, _ in failed))
     tmp = LIB + ".tmp"
-    cmd = [cc, "-shared", "-fPIC", "--offload-arch=gfx950", "-o", tmp] + objs
+    cmd = [cc, "-shared", "-fPIC", "--offload-arch=gfx950", "-o", tmp] + objs + ["-lrocprofiler-sdk-roctx"]
     subprocess.run(cmd, check=True)
     os.replace(tmp, LIB)
     return LIB

@@ -2,6 +2,7 @@
 // of candidate detection (Methods, "Candidate detection"): binary closing and 8-connected
 // labelling over the sparse set of thresholded cells returned by the device.
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <algorithm>
 #include <cmath>
@@ -539,9 +540,27 @@ snd_status snd_detect_collect(snd_plan plan, const snd_detect_desc *desc, const 
     return SND_OK;
 }
 
+static snd_status detect_impl(snd_plan plan, const void *d_plane, int64_t plane_pitch, const snd_detect_desc *desc,
+                       void *d_workspace, int64_t workspace_bytes, snd_candidate *h_out, int64_t cap, int64_t *h_count,
+                       int64_t *h_npixels, void *stream);
+
 snd_status snd_detect(snd_plan plan, const void *d_plane, int64_t plane_pitch, const snd_detect_desc *desc,
                       void *d_workspace, int64_t workspace_bytes, snd_candidate *h_out, int64_t cap, int64_t *h_count,
                       int64_t *h_npixels, void *stream)
+{
+    roctxRangePushA("snd detect");  // host timeline marker (rocprofv3 --marker-trace)
+    const snd_status s = detect_impl(plan, d_plane, plane_pitch, desc, d_workspace, workspace_bytes, h_out, cap,
+                                     h_count, h_npixels, stream);
+    roctxRangePop();
+    return s;
+}
+
+}  // extern "C"
+
+// the body of snd_detect (internal linkage: not part of the exported C API)
+static snd_status detect_impl(snd_plan plan, const void *d_plane, int64_t plane_pitch, const snd_detect_desc *desc,
+                       void *d_workspace, int64_t workspace_bytes, snd_candidate *h_out, int64_t cap, int64_t *h_count,
+                       int64_t *h_npixels, void *stream)
 {
     if (!plan || !d_plane || !d_workspace || !h_count || (cap > 0 && !h_out)) { snd::set_error("null argument"); return SND_ERR_INVALID; }
     const auto &P = plan->impl;
@@ -595,5 +614,3 @@ snd_status snd_detect(snd_plan plan, const void *d_plane, int64_t plane_pitch, c
     for (int64_t i = 0; i < cap && i < (int64_t)cands.size(); ++i) h_out[i] = cands[i];
     return SND_OK;
 }
-
-}  // extern "C"

@@ -27,6 +27,22 @@ def test_library_exports_every_declared_symbol(snd):
     assert not missing, missing
 
 
+def test_library_exports_no_undeclared_c_symbol(snd):
+    """Every unmangled function the library defines is one the header declares (internal
+    helpers have internal linkage or live in the C++ namespace)."""
+    import shutil
+    import subprocess
+    from paper_2606_15361_amd import _capi
+    if not shutil.which("nm"):
+        pytest.skip("nm not available")
+    names = set(_capi.declared_symbols(os.path.join(ROOT, "include", "snd.h")))
+    out = subprocess.run(["nm", "-D", "--defined-only", _capi.LIB_PATH], capture_output=True, text=True,
+                         check=True).stdout
+    funcs = {ln.split()[-1] for ln in out.splitlines() if len(ln.split()) == 3 and ln.split()[1] == "T"}
+    extra = sorted(n for n in funcs if not n.startswith("_Z") and n not in names)
+    assert not extra, extra
+
+
 @pytest.mark.parametrize("nchan,ndm,C_,B,dmax", [(64, 64, 4, 2, 300.0), (37, 29, 3, 3, 40.0), (24, 17, 5, 4, 30.0),
                                                  (9, 5, 4, 8, 10.0), (3, 4, 4, 2, 10.0), (1, 3, 1, 2, 50.0)])
 def test_plan_matches_oracle_counts(snd, orc, nchan, ndm, C_, B, dmax):
