@@ -50,7 +50,10 @@ __global__ __launch_bounds__(1024) void k_group_fast(GroupArgs s0, Multi m)
     TI *lds = reinterpret_cast<TI *>(smem);
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const uint32_t L = xcd_remap(bid, nblk);
+    // logical tile L = time tile * ngroups + DM group: each XCD takes an eighth of the DM groups
+    // of a time tile, and the XCDs work on the same time tiles, whose leaf windows the DM
+    // groups share
+    const uint32_t L = xcd_remap_chunked(bid, nblk, (uint32_t)(s.ngroups >= 8 ? s.ngroups / 8 : 1));
     const int g = (int)(L % (uint32_t)s.ngroups);
     const int t0 = (int)(L / (uint32_t)s.ngroups) * T;
     const int vt = s.n_out - t0 < T ? s.n_out - t0 : T;

@@ -112,6 +112,19 @@ __device__ inline uint32_t xcd_remap(uint32_t b, uint32_t nb)
     return x * q + (x < r ? x : r) + i;
 }
 
+// The same idea in chunks of 8 m workgroups: within each chunk XCD x takes the x-th run of m
+// consecutive logical tiles, so that all XCDs advance through the logical range together (the
+// data that the tiles of one chunk share stays in the Infinity Cache) while each XCD's tiles
+// are neighbours (they share lines in its L2).  The tail that does not fill a chunk keeps the
+// contiguous map above.  A bijection on [0, nb) for every m >= 1.
+__device__ inline uint32_t xcd_remap_chunked(uint32_t b, uint32_t nb, uint32_t m)
+{
+    const uint32_t C = 8u * m, full = nb / C * C;
+    if (b >= full) return full + xcd_remap(b - full, nb - full);
+    const uint32_t base = b / C * C, r = b - base;
+    return base + (r & 7u) * m + (r >> 3);
+}
+
 // The arguments and the workgroup index of this workgroup: those passed by value for a plain
 // launch, else those of the record whose workgroup range holds blockIdx.x (binary search over
 // the prefix table; every value is wave-uniform, so this is scalar work).
