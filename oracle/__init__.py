@@ -18,8 +18,12 @@ What pins each function to something other than itself (tests/test_oracle_*.py):
                    spike-count conservation; binary K = 1 and K = full fan-in reduce to
                    brute force; hand-worked binary cases (tests/golden); the cascade law on
                    Bernoulli spikes; the dedup tree equals the per-DM recursion in all modes.
+                   snd_points on its own, at sampled cells of ragged trees: float and graded
+                   against brute force, binary K = 1 against 1[brute force >= 1], binary
+                   quorums against the dedup tree.
 * bruteforce    -- DM 0 row = channel sum; conservation of the summed counts.
-* encode        -- fire rates against the normal tail probability.
+* encode        -- fire rates against the normal tail probability; samples exactly at a
+                   threshold do not fire, the next float above does (x = 1[z > theta]).
 * matched_filter -- the printed noise-floor closed forms (0.8 and ~21), Gaussian noise
                    statistics, optimal boxcar width, constant rows; per-row width counts reduce
                    to the plain filter on the leading widths.
@@ -31,7 +35,7 @@ What pins each function to something other than itself (tests/test_oracle_*.py):
                    plain mean and standard deviation; the normal tail rate after normalising.
 * effective_width -- the printed scrunch band edges (the smearing term equals S dt there),
                    DM 0 and zero-width special cases, a 3-4-5 right triangle.
-* match_injections -- hand-worked cases (tests/golden/injection_match.txt); all-admissible
+* match_injections -- hand-worked cases (tests/golden/injection_match.json); all-admissible
                    windows match min(candidates, injections); a one-to-one structure reduces to
                    scipy's linear assignment.
 * mad_sigma     -- hand-evaluated rows (odd and even lengths, an outlier), the scale against
@@ -40,7 +44,8 @@ What pins each function to something other than itself (tests/test_oracle_*.py):
 * zero_dm       -- a broadband spike removed exactly, narrow-band and sub-threshold ones kept,
                    the threshold's closed form on a constant block.
 * flag_channels -- a hot channel flagged in its window only, a dead (constant) channel, a
-                   clean Gaussian block left alone, a hand-evaluated 5-channel window.
+                   clean Gaussian block left alone, a hand-evaluated 5-channel window; the
+                   window sigmas equal numpy's population std (pairwise sums) to 1e-12.
 * fdmt, fdmt_delays -- the recursion equals the direct sum over the channel delays traced down
                    the split rule (two different computations); the zero-delay row is the channel
                    sum; every traced delay stays within the merge count of the f^-2 law; the

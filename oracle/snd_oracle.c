@@ -699,28 +699,22 @@ static double lower_median(const double *v, int32_t n, double *scratch)
     return scratch[(n - 1) / 2];
 }
 
-/* A sum of v[0..len) taken as 64 interleaved partial sums (partial j adds v[j], v[j + 64], ...
- * in order), the partials then added in order of j: the summation order fixed for the
- * per-window channel statistics below. */
-static double interleaved_sum(const float *v, int64_t len, double shift, int squared)
+/* Sum of v[0..len) (squared deviations from `shift` when `squared`), one FP64 accumulator
+ * taking the samples in time order: the plain definition of the sum, no partial sums. */
+static double window_sum(const float *v, int64_t len, double shift, int squared)
 {
-    double part[64];
-    for (int j = 0; j < 64; ++j) {
-        double a = 0.0;
-        for (int64_t t = j; t < len; t += 64) {
-            double x = (double)v[t] - shift;
-            a += squared ? x * x : x;
-        }
-        part[j] = a;
-    }
     double s = 0.0;
-    for (int j = 0; j < 64; ++j) s += part[j];
+    for (int64_t t = 0; t < len; ++t) {
+        double x = (double)v[t] - shift;
+        s += squared ? x * x : x;
+    }
     return s;
 }
 
-/* Channel flagging: per window of w samples (the last may be shorter), s_c = population
- * standard deviation of channel c over the window (the mean, then the mean squared deviation,
- * each FP64 sum in the interleaved order above); m = lower median of s, mad = lower median of
+/* Channel flagging (Results, "False-positive rate": windowed MAD channel flagging): per window
+ * of w samples (the last may be shorter), s_c = population standard deviation of channel c over
+ * the window (two passes: the mean, then the mean squared deviation from it, each a plain FP64
+ * sum in time order); m = lower median of s, mad = lower median of
  * |s_c - m|; channel c is flagged when |s_c - m| > k * (mad_scale * mad) and its window samples
  * are set to 0.  flags [nwin][nchan] receives 1 / 0, sigma_out [nwin][nchan] the s_c (may be
  * NULL).  Returns 0, or -1 when memory runs out. */
@@ -735,8 +729,8 @@ int orc_flag_channels(int32_t nchan, int64_t n, float *z, int64_t w, double k, d
         int64_t t0 = b * w, len = n - t0 < w ? n - t0 : w;
         for (int32_t c = 0; c < nchan; ++c) {
             const float *row = z + (int64_t)c * n + t0;
-            double mu = interleaved_sum(row, len, 0.0, 0) / (double)len;
-            s[c] = sqrt(interleaved_sum(row, len, mu, 1) / (double)len);
+            double mu = window_sum(row, len, 0.0, 0) / (double)len;
+            s[c] = sqrt(window_sum(row, len, mu, 1) / (double)len);
             if (sigma_out) sigma_out[b * nchan + c] = s[c];
         }
         double m = lower_median(s, nchan, tmp);

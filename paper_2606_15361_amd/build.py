@@ -17,7 +17,7 @@ LIB = os.path.join(HERE, "libsnd.so")
 BUILD = os.path.join(HERE, "_build")
 
 HIP_SOURCES = ["kernels.hip", "kernels_lds.hip", "kernels_fast_binary.hip", "kernels_fast_graded.hip",
-               "kernels_fast_float.hip", "kernels_bits.hip", "detect.hip", "stream.hip", "label.hip"]
+               "kernels_fast_float.hip", "kernels_bits.hip", "detect.hip", "label.hip"]
 CXX_SOURCES = ["plan.cpp", "capi.cpp", "detect_host.cpp", "stream_host.cpp", "batch_host.cpp", "tune_host.cpp",
                "multirate_host.cpp", "validate_host.cpp", "fdmt_host.cpp"]
 
@@ -44,7 +44,7 @@ def build(verbose: bool = False) -> str:
     for src in HIP_SOURCES + CXX_SOURCES:
         path = os.path.join(CSRC, src)
         if not os.path.exists(path):
-            continue
+            raise FileNotFoundError(f"libsnd source missing: {path}")
         obj = os.path.join(BUILD, src + ".o")
         if src.endswith(".hip"):
             cmd = [cc, "-x", "hip"] + COMMON + DEVICE + ["-c", path, "-o", obj]

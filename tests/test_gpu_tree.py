@@ -162,6 +162,25 @@ def test_encoder_bits_parity(snd, orc):
         assert np.array_equal(a, want) and np.array_equal(b, want)
 
 
+def test_encoders_at_exact_thresholds(snd, orc):
+    # samples exactly at a threshold do not fire (x = 1[z > theta]); the float just above does
+    rng = synth.make_rng(77)
+    thr = [0.75, 1.5, 2.0, 3.0]
+    t32 = np.array(thr, dtype=np.float32)
+    vals = np.concatenate([t32, np.nextafter(t32, np.float32(np.inf)), np.nextafter(t32, np.float32(-np.inf))])
+    z = rng.choice(vals, size=(5, 4100)).astype(np.float32)
+    zt = torch.from_numpy(z).cuda()
+    for th in ([2.0], [1.0, 2.0, 3.0, 4.0], [0.75, 1.5]):
+        _say(f"encode at exact thresholds {th}")
+        want = orc.encode(z, th)
+        assert np.array_equal(to_np(snd.encode(zt, th)), want)
+        assert np.array_equal(to_np(snd.encode(zt.t().contiguous(), th, time_major=True)), want)
+    for th in thr:
+        want = pack_bits(orc.encode(z, [th]))
+        assert np.array_equal(snd.encode_bits(zt, th).cpu().numpy(), want)
+        assert np.array_equal(snd.encode_bits(zt.t().contiguous(), th, time_major=True).cpu().numpy(), want)
+
+
 @pytest.mark.parametrize("kl,ki", [(2, 2), (2, 1)])
 def test_config1_binary_exact(snd, orc, kl, ki):
     spec = synth.workload(1)

@@ -87,3 +87,17 @@ def test_flag_channels_pins(orc):
     h = np.tile(np.array([1.0, -1.0], np.float32), (5, 4)) * s
     assert list(orc.flag_channels(h, 8, k=5.0)[1][0]) == [0, 0, 0, 0, 1]
     assert list(orc.flag_channels(h, 8, k=1.0)[1][0]) == [1, 0, 0, 0, 1]
+
+
+def test_flag_window_sigma_is_the_population_std(orc):
+    # the per-window channel sigma is the population standard deviation of the window's samples
+    # (two-pass FP64 sums in time order): numpy's own std, which sums pairwise, agrees to FP64
+    # rounding; the last window is ragged
+    rng = np.random.default_rng(23)
+    nchan, n, w = 9, 2500, 1000
+    z = (3.0 + rng.standard_normal((nchan, n)) * rng.uniform(0.5, 4.0, (nchan, 1))).astype(np.float32)
+    _, _, sig = orc.flag_channels(z, w, k=5.0, return_sigma=True)
+    assert sig.shape == (3, nchan)
+    for b in range(3):
+        want = z[:, b * w: (b + 1) * w].astype(np.float64).std(axis=1)
+        assert np.allclose(sig[b], want, rtol=1e-12, atol=0.0)

@@ -136,6 +136,54 @@ def test_dedup_equals_recursion_all_modes(orc):
             assert counts[-1][0] <= len(dms)
 
 
+@pytest.mark.parametrize("nchan,C,B", [(37, 3, 3), (24, 5, 4), (9, 4, 8), (64, 4, 2)])
+def test_points_pinned_to_bruteforce_and_dedup(orc, nchan, C, B):
+    # orc_snd_points (the checker used on full-size planes) at sampled (k, t) of ragged shapes:
+    # float and uncapped graded equal brute force, capped graded equals min(brute force, N),
+    # binary with K = 1 everywhere equals 1[brute force >= 1], and binary with a real quorum
+    # equals the shared-pattern tree (a separate computation) and the whole-plane recursion.
+    rng, f, dms = _random_case(nchan * 13 + B, nchan, 21, 800, shuffle=True)
+    d = orc.delays(f, dms, 0.138e-3)
+    nout = 800 - int(d.max())
+    ks = rng.integers(0, len(dms), 300)
+    ts = rng.integers(0, nout, 300)
+    ks[:3], ts[:3] = [0, len(dms) - 1, 1], [0, nout - 1, nout - 1]  # the plane's corners
+    xl = synth.random_levels(rng, nchan, 800, 6)
+    xs = synth.random_spikes(rng, nchan, 800, 0.25)
+    bf = orc.bruteforce(xl, d, mode="float")
+    bfs = orc.bruteforce(xs, d, mode="binary")
+    kw = dict(cluster=C, branching=B)
+    assert np.array_equal(orc.snd_points(xl, f, d, ks, ts, mode="float", **kw), bf[ks, ts])
+    assert np.array_equal(orc.snd_points(xl, f, d, ks, ts, mode="graded", cap=65535, **kw), bf[ks, ts])
+    assert np.array_equal(orc.snd_points(xl, f, d, ks, ts, mode="graded", cap=7, **kw), np.minimum(bf[ks, ts], 7))
+    one = orc.snd_points(xs, f, d, ks, ts, mode="binary", k_leaf=1, k_int=1, **kw)
+    assert np.array_equal(one, (bfs[ks, ts] >= 1).astype(float))
+    for kl, ki in ((2, 1), (2, 2), (1, 2)):
+        got = orc.snd_points(xs, f, d, ks, ts, mode="binary", k_leaf=kl, k_int=ki, **kw)
+        plane, _ = orc.snd_dedup(xs, f, d, mode="binary", k_leaf=kl, k_int=ki, **kw)
+        assert np.array_equal(got, plane[ks, ts])
+        rec = orc.snd_recursive(xs, f, d, mode="binary", k_leaf=kl, k_int=ki, **kw)
+        assert np.array_equal(got, rec[ks, ts])
+    with pytest.raises(ValueError):
+        orc.snd_points(xl, f, d, [0], [nout], mode="float", **kw)  # past the valid window
+
+
+def test_encoder_threshold_is_strict(orc):
+    # Methods, "Input encoding": a sample fires when it exceeds the threshold, x = 1[z > theta].
+    # A sample exactly at a threshold does not count; the next float above it does.
+    thr = [np.float32(0.75), np.float32(1.5), np.float32(2.0)]
+    for t in thr:
+        up = np.nextafter(t, np.float32(np.inf))
+        dn = np.nextafter(t, np.float32(-np.inf))
+        z = np.array([[dn, t, up]], dtype=np.float32)
+        assert orc.encode(z, [t]).tolist() == [[0, 0, 1]]
+    # multi-level: the level is the number of thresholds strictly exceeded
+    lv = [1.0, 2.0, 3.0, 4.0]
+    z = np.array([[0.0, 1.0, np.nextafter(np.float32(1.0), np.float32(2.0)), 2.0, 3.0, 3.5, 4.0, 4.0001, -5.0]],
+                 dtype=np.float32)
+    assert orc.encode(z, lv).tolist() == [[0, 0, 1, 1, 2, 3, 3, 4, 0]]
+
+
 def test_cascade_table1(orc):
     # Table 1: NC tree (C = 4, B = 8, B_root = 4), p0 = p(1.5 sigma); root noise fire rates
     # and the predicted worst-case S/N sqrt((1-p)/p) (Eq. snr_A with p_sig = 1, W = 1).
