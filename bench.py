@@ -15,6 +15,7 @@ import argparse
 import json
 import os
 import sys
+import tempfile
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
@@ -23,7 +24,10 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 METRIC = "dedispersed DM\u00d7time samples/s (1024 ch, 4096 DM) + %HBM peak; p99 chunk latency"
-LDS_PEAK_GBS = 256 * 128 * 2.4  # 256 CUs x 128 B/clk x 2.4 GHz
+# LDS read peak of gfx950: 256 CUs x 256 B/clk (CDNA4 doubled the per-CU LDS read rate of
+# CDNA3's 128 B/clk for 128-bit reads) x 2.4 GHz = 157.3 TB/s; a ds_read_b128 probe on the
+# part reaches 132 TB/s, 84 % of it
+LDS_PEAK_GBS = 256 * 256 * 2.4
 KERNEL_SYMBOL = {"generic": "k_stage", "group_lds": "k_group", "anchored": "k_anchored", "group_fast": "k_group_fast",
                  "group_bits": "k_group_bits", "anchored_bits": "k_anchored_bits"}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic.json")
@@ -82,7 +86,10 @@ def parse():
                     help="extract each block's candidates before the next block starts (no host/device overlap)")
     ap.add_argument("--generic-kernels", action="store_true", help="run every stage on the generic stage kernel")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=2048, help="output samples in the oracle's timed sample")
+    ap.add_argument("--cpu-sample", type=int, default=2048,
+                    help="output samples in the oracle's single-thread timed sample")
+    ap.add_argument("--cpu-sample-all", type=int, default=16384,
+                    help="output samples in the oracle's all-core timed sample")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one plain 1 GiB device copy first (scale reference for HBM counters)")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default stage schedule")
@@ -93,22 +100,80 @@ def parse():
     return ap.parse_args()
 
 
-def cpu_baseline(spec, mode, n_sample):
-    """The oracle's shared-pattern tree timed on the host on a bounded slice of the same beam."""
+def _host_cpu():
+    """(usable host cores, CPU model name)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return n, model
+
+
+def _cpu_slice(job):
+    """One worker's share of the all-core oracle run (a fresh interpreter: nothing of the GPU
+    process is inherited): the shared-pattern tree over one contiguous slice of DM rows, on the
+    input cut to that slice's own sweep plus the sample, so that every DM row yields the same
+    number of output samples.  Returns (output cells, seconds)."""
+    import numpy as np
+    import oracle
+    path, freqs, d, mode, branching, n_sample = job
+    x = np.load(path, mmap_mode="r")
+    n = int(d.max()) + n_sample
+    xs = np.ascontiguousarray(x[:, :n])
+    t = time.perf_counter()
+    y, _ = oracle.snd_dedup(xs, freqs, d, mode=mode, cluster=4, branching=branching, k_leaf=2, k_int=1, cap=255)
+    return int(y.shape[0] * y.shape[1]), time.perf_counter() - t
+
+
+def cpu_baseline(spec, mode, n_sample, n_sample_all):
+    """The oracle's shared-pattern tree timed on the host, on bounded slices of the same beam:
+    on one thread over every DM row, and on all usable host cores (up to 16, one process per
+    contiguous DM slice) over a longer slice."""
+    import multiprocessing as mp
     import numpy as np
     import oracle
     d = oracle.delays(spec.freqs, spec.dms, spec.tsamp_s)
-    nsamp = int(d.max()) + n_sample
-    z = spec.filterbank(nsamp)
+    n_long = max(n_sample, n_sample_all)
+    z = spec.filterbank(int(d.max()) + n_long)
     x = z if mode == "float" else oracle.encode(z, [1.0, 2.0, 3.0, 4.0] if mode == "graded" else [2.0])
+    kw = dict(mode=mode, cluster=4, branching=spec.branching, k_leaf=2, k_int=1, cap=255)
     t = time.perf_counter()
-    y, _ = oracle.snd_dedup(x, spec.freqs, d, mode=mode, cluster=4, branching=spec.branching,
-                            k_leaf=2, k_int=1, cap=255)
-    dt = time.perf_counter() - t
-    return dict(value=float(spec.dms.size * n_sample / dt), unit="DM-time samples/s", cores=1, kind="oracle",
-                sample=f"shared-pattern SND tree (C, FP64, 1 thread) over all {spec.dms.size} DMs x {n_sample} "
-                       f"output samples of the same 1024-channel beam; {dt:.1f} s",
-                seconds=round(dt, 2)), np.asarray(y).shape
+    y, _ = oracle.snd_dedup(x[:, :int(d.max()) + n_sample], spec.freqs, d, **kw)
+    dt1 = time.perf_counter() - t
+    v1 = float(spec.dms.size * n_sample / dt1)
+    ncpu, model = _host_cpu()
+    workers = max(1, min(16, ncpu))
+    bounds = np.linspace(0, spec.dms.size, workers + 1).astype(int)
+    with tempfile.TemporaryDirectory() as tmp:
+        path = os.path.join(tmp, "x.npy")
+        np.save(path, x)
+        jobs = [(path, spec.freqs, d[bounds[i]:bounds[i + 1]], mode, spec.branching, n_sample_all)
+                for i in range(workers)]
+        # fresh interpreters ("spawn"), so that no worker inherits the GPU process's state
+        with mp.get_context("spawn").Pool(workers) as pool:
+            pool.map(_cpu_slice, [(path, spec.freqs, d[:1], mode, spec.branching, 1)] * workers)  # warm imports
+            t = time.perf_counter()
+            res = pool.map(_cpu_slice, jobs)
+            dta = time.perf_counter() - t
+    cells = sum(c for c, _ in res)
+    va = float(cells / dta)
+    return dict(value=va, unit="DM-time samples/s", cores=workers, kind="oracle",
+                sample=f"shared-pattern SND tree (C, FP64) over all {spec.dms.size} DMs x {n_sample_all} output "
+                       f"samples of the same 1024-channel beam, one process per contiguous DM slice on {workers} "
+                       f"cores; {dta:.1f} s",
+                seconds=round(dta, 2), host_cpus=ncpu, cpu_model=model,
+                single_thread={"value": v1, "unit": "DM-time samples/s", "cores": 1,
+                               "sample": f"all {spec.dms.size} DMs x {n_sample} output samples, 1 thread; "
+                                         f"{dt1:.1f} s"}), np.asarray(y).shape
 
 
 def direct_leg(snd, torch, spec, x, pkw, dev, ref_out, reps=3):
@@ -513,7 +578,7 @@ def serve_leg(snd, synth, torch, dev, seconds):
     pf = snd.Plan(sf.freqs, sf.dms, sf.tsamp_s, None, mode="float", branching=4, chunk=T, in_dtype="bf16",
                   node_dtype="bf16")
     kinds = {"graded": (pg, [1.0, 2.0, 3.0, 4.0]), "bf16": (pf, None)}
-    budget = 22 * snd.history_bytes(pg) + 22 * snd.history_bytes(pf)
+    budget = 22 * snd.admission_bytes(pg) + 22 * snd.admission_bytes(pf)
     period = synth.chunk_period_s(T)
     src = _ChunkSource(snd, synth, torch, dev, 1024, T, 48, max(seconds, 30.0) + 30.0)
     kind = lambda b: "graded" if b % 2 == 0 else "bf16"
@@ -823,7 +888,7 @@ def main():
         result["serving"] = serve_leg(snd, synth, torch, dev, args.serve_seconds)
     if not args.no_cpu_baseline:
         log("[bench] timing the oracle on a bounded sample")
-        cb, _ = cpu_baseline(spec, mode, args.cpu_sample)
+        cb, _ = cpu_baseline(spec, mode, args.cpu_sample, args.cpu_sample_all)
         result["cpu_baseline"] = cb
     print(json.dumps(result), flush=True)
 

@@ -519,9 +519,9 @@ snd_status snd_autotune(const snd_plan_desc *desc, snd_tune_candidate *cands, in
  * plain snd_execute over the concatenated input.  Only the input is kept, not the neuron
  * rows: the first stage recomputes the short spread of each leaf row from the ring.
  *
- * The plan must be uploaded and its first stage must be the input-anchored kernel (the
- * default schedule; plans built with generic_kernels = 1 or without a materialised level
- * are rejected with UNSUPPORTED).
+ * The plan's first stage must be the input-anchored kernel (the default schedule; plans
+ * built with generic_kernels = 1 or without a materialised level are rejected with
+ * UNSUPPORTED), and its tables must be uploaded before the beam's first push (STATE).
  * --------------------------------------------------------------------------------------- */
 typedef struct snd_stream_s *snd_stream;
 
@@ -530,14 +530,21 @@ typedef struct snd_stream_s *snd_stream;
  * or float input). */
 snd_status snd_stream_history_bytes(snd_plan plan, int64_t *bytes);
 
-/* New stream that admits beams while the sum of their history bytes stays within
- * hbm_budget_bytes (> 0).  Host object only. */
+/* Device bytes a beam of this plan is charged against the stream's budget: its history ring
+ * (snd_stream_history_bytes) plus its share of a batched push's workspace (the plan's
+ * workspace_bytes rounded up to 256), so that the beams a budget admits can also be pushed
+ * together.  UNSUPPORTED for BITS input. */
+snd_status snd_stream_admission_bytes(snd_plan plan, int64_t *bytes);
+
+/* New stream that admits beams while the sum of their admission bytes
+ * (snd_stream_admission_bytes) stays within hbm_budget_bytes (> 0).  Host object only. */
 snd_status snd_stream_create(int64_t hbm_budget_bytes, snd_stream *out);
 snd_status snd_stream_destroy(snd_stream s);
 
 /* Admit beam_id (>= 0, not yet admitted) with plan and its history buffer d_history
  * (>= snd_stream_history_bytes bytes, 256-byte aligned, owned by the caller, kept until
- * evict).  CAPACITY (beam not admitted) when the budget would be exceeded.  The beam starts
+ * evict).  CAPACITY (beam not admitted) when the budget would be exceeded by the beam's
+ * snd_stream_admission_bytes.  Admission touches no device memory.  The beam starts
  * empty; its first push may carry any chunk index.  The plan must outlive the beam. */
 snd_status snd_stream_admit(snd_stream s, int32_t beam_id, snd_plan plan, void *d_history, int64_t bytes);
 
@@ -593,8 +600,11 @@ snd_status snd_stream_usage(snd_stream s, int64_t *budget, int64_t *used, int32_
 
 /* Checkpoint of one beam: a 64-byte header (state and ring shape) followed by the ring.
  * snd_stream_export_bytes gives the size; export copies to host memory and synchronises the
- * stream; import restores into an admitted beam whose plan has the same ring shape (INVALID
- * otherwise) and synchronises the stream. */
+ * stream; import restores into an admitted beam whose plan has the same ring shape and
+ * synchronises the stream.  Import rejects (INVALID, nothing restored) a header of another
+ * ring shape, a truncated buffer, and a state the beam cannot be in: either nothing received
+ * (emitted 0, next chunk -1), or S >= 1 samples received with emitted = max(0, S - max_delay)
+ * and next chunk >= 1. */
 snd_status snd_stream_export_bytes(snd_stream s, int32_t beam_id, int64_t *bytes);
 snd_status snd_stream_export(snd_stream s, int32_t beam_id, void *h_buf, int64_t bytes, void *stream);
 snd_status snd_stream_import(snd_stream s, int32_t beam_id, const void *h_buf, int64_t bytes, void *stream);

@@ -149,6 +149,7 @@ def lib() -> C.CDLL:
         "snd_batch_records_bytes": ([I32, PP, PI64, C.POINTER(I32)], I32),
         "snd_batch_execute": ([I32, PP, PP, PI64, PP, PI64, PP, PI64, PI64, P, I64, P, C.POINTER(I32)], I32),
         "snd_stream_history_bytes": ([P, PI64], I32),
+        "snd_stream_admission_bytes": ([P, PI64], I32),
         "snd_stream_create": ([I64, C.POINTER(P)], I32),
         "snd_stream_destroy": ([P], I32),
         "snd_stream_admit": ([P, I32, P, P, I64], I32),

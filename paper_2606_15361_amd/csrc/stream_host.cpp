@@ -62,13 +62,30 @@ struct Beam {
     int64_t received = 0;    // S
     int64_t emitted = 0;     // E
     int64_t next_chunk = -1; // -1: any index starts the history
+    int64_t charge = 0;      // bytes charged against the budget (admission_charge)
 };
+
+// The state a beam can be in: nothing received (any chunk index starts it), or S >= 1 samples
+// received with E = max(0, S - max_delay) outputs emitted and the next chunk index >= 1.
+bool valid_state(int64_t received, int64_t emitted, int64_t next_chunk, int64_t max_delay)
+{
+    if (received == 0) return emitted == 0 && next_chunk == -1;
+    return received > 0 && emitted == std::max<int64_t>(0, received - max_delay) && next_chunk >= 1;
+}
 
 struct Header {
     uint64_t magic;
     int64_t received, emitted, next_chunk, ring_len, pitch, es, nchan;
 };
 static_assert(sizeof(Header) == kHeaderBytes, "checkpoint header is 64 bytes");
+
+// Bytes of one beam's share of a batched push workspace.
+int64_t ws_share(const snd::PlanImpl &P) { return round_up(P.workspace_bytes, 256); }
+
+// Device bytes a beam is charged at admission: its input ring plus its share of the workspace
+// of a batched push, so that a budget that admits a set of beams also holds a batched push of
+// all of them.
+int64_t admission_charge(const snd::PlanImpl &P) { return ring_shape(P).bytes + ws_share(P); }
 
 }  // namespace
 
@@ -85,6 +102,14 @@ snd_status snd_stream_history_bytes(snd_plan plan, int64_t *bytes)
     if (!plan || !bytes) return fail(SND_ERR_INVALID, "null plan or output");
     if (plan->impl.desc.in_dtype == SND_DT_BITS) return fail(SND_ERR_UNSUPPORTED, "bit input is not streamed");
     *bytes = ring_shape(plan->impl).bytes;
+    return SND_OK;
+}
+
+snd_status snd_stream_admission_bytes(snd_plan plan, int64_t *bytes)
+{
+    if (!plan || !bytes) return fail(SND_ERR_INVALID, "null plan or output");
+    if (plan->impl.desc.in_dtype == SND_DT_BITS) return fail(SND_ERR_UNSUPPORTED, "bit input is not streamed");
+    *bytes = admission_charge(plan->impl);
     return SND_OK;
 }
 
@@ -119,17 +144,19 @@ snd_status snd_stream_admit(snd_stream s, int32_t beam_id, snd_plan plan, void *
     if (((uintptr_t)d_history & 255u) != 0) return fail(SND_ERR_INVALID, "history buffer must be 256-byte aligned");
     const RingShape r = ring_shape(P);
     if (bytes < r.bytes) return fail(SND_ERR_NOMEM, "history buffer smaller than snd_stream_history_bytes");
-    if (s->used + r.bytes > s->budget)
+    const int64_t charge = admission_charge(P);
+    if (s->used + charge > s->budget)
         return fail(SND_ERR_CAPACITY, "admission would exceed the stream's device-memory budget (" +
-                                          std::to_string(s->used) + " + " + std::to_string(r.bytes) + " > " +
+                                          std::to_string(s->used) + " + " + std::to_string(charge) +
+                                          " bytes of history ring and batched-push workspace > " +
                                           std::to_string(s->budget) + " bytes)");
-    if (!P.d_table) return fail(SND_ERR_STATE, "plan tables not uploaded");
     Beam b;
     b.plan = plan;
     b.ring = static_cast<uint8_t *>(d_history);
     b.shape = r;
+    b.charge = charge;
     s->beams[beam_id] = b;
-    s->used += r.bytes;
+    s->used += charge;
     return SND_OK;
 }
 
@@ -138,7 +165,7 @@ snd_status snd_stream_evict(snd_stream s, int32_t beam_id)
     if (!s) return fail(SND_ERR_INVALID, "null stream");
     auto it = s->beams.find(beam_id);
     if (it == s->beams.end()) return fail(SND_ERR_STATE, "beam not admitted");
-    s->used -= it->second.shape.bytes;
+    s->used -= it->second.charge;
     s->beams.erase(it);
     return SND_OK;
 }
@@ -146,9 +173,6 @@ snd_status snd_stream_evict(snd_stream s, int32_t beam_id)
 }  // extern "C"
 
 namespace {
-
-// Bytes of one beam's share of a batched push workspace.
-int64_t ws_share(const snd::PlanImpl &P) { return round_up(P.workspace_bytes, 256); }
 
 snd_status push_impl(snd_stream s, int32_t n, snd_stream_item *items, void *d_workspace, int64_t workspace_bytes,
                      void *d_records, int64_t records_bytes, bool batched, void *stream)
@@ -173,6 +197,15 @@ snd_status push_impl(snd_stream s, int32_t n, snd_stream_item *items, void *d_wo
         if (it.chunk_pitch < it.chunk_len) return fail(SND_ERR_INVALID, "item " + std::to_string(i) + ": chunk pitch");
         if (it.out_pitch < P.n_out) return fail(SND_ERR_INVALID, "item " + std::to_string(i) + ": output pitch < n_out");
         if (it.chunk_idx < 0) return fail(SND_ERR_INVALID, "item " + std::to_string(i) + ": negative chunk index");
+        if (!P.d_table) return fail(SND_ERR_STATE, "item " + std::to_string(i) + ": plan tables not uploaded");
+        {
+            // the outputs this chunk completes must fit the plan's output and workspace rows
+            const bool gap = b.next_chunk >= 0 && it.chunk_idx != b.next_chunk;
+            const int64_t S0 = gap ? 0 : b.received, E0 = gap ? 0 : b.emitted;
+            const int64_t n_run = std::max<int64_t>(0, S0 + it.chunk_len - P.max_delay) - E0;
+            if (n_run < 0 || n_run > P.n_out)
+                return fail(SND_ERR_STATE, "item " + std::to_string(i) + ": beam state inconsistent with its plan");
+        }
         ws_total += batched ? ws_share(P) : 0;
         if (!batched && P.workspace_bytes > 0 &&
             (!d_workspace || workspace_bytes < P.workspace_bytes || ((uintptr_t)d_workspace & 255u)))
@@ -345,8 +378,9 @@ snd_status snd_stream_import(snd_stream s, int32_t beam_id, const void *h_buf, i
         h.nchan != b.plan->impl.nchan)
         return fail(SND_ERR_INVALID, "checkpoint ring shape differs from the beam's plan");
     if (bytes < kHeaderBytes + b.shape.bytes) return fail(SND_ERR_INVALID, "checkpoint truncated");
-    if (h.received < 0 || h.emitted < 0 || h.emitted > h.received || h.next_chunk < -1)
-        return fail(SND_ERR_INVALID, "corrupt checkpoint state");
+    if (!valid_state(h.received, h.emitted, h.next_chunk, b.plan->impl.max_delay))
+        return fail(SND_ERR_INVALID, "corrupt checkpoint state (received, emitted and next chunk index do not "
+                                     "fit the beam's plan)");
     hipStream_t st = (hipStream_t)stream;
     hipError_t e = hipMemcpyAsync(b.ring, static_cast<const uint8_t *>(h_buf) + kHeaderBytes, (size_t)b.shape.bytes,
                                   hipMemcpyHostToDevice, st);

@@ -11,7 +11,7 @@ import time
 from . import _capi as capi
 from .detect import Detector
 from .plan import cast, encode
-from .stream import Stream, history_bytes
+from .stream import Stream, admission_bytes, history_bytes
 
 
 class Server:
@@ -37,8 +37,11 @@ class Server:
     def history_bytes(self, kind: str) -> int:
         return history_bytes(self.kinds[kind][0])
 
+    def admission_bytes(self, kind: str) -> int:
+        return admission_bytes(self.kinds[kind][0])
+
     def admit(self, beam: int, kind: str) -> bool:
-        """False when the budget cannot hold the beam's history."""
+        """False when the budget cannot hold the beam's history and workspace share."""
         plan = self.kinds[kind][0]
         try:
             self.stream.admit(beam, plan)

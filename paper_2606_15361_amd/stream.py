@@ -19,8 +19,17 @@ def history_bytes(plan: Plan) -> int:
     return int(b.value)
 
 
+def admission_bytes(plan: Plan) -> int:
+    """Device bytes a beam of this plan is charged against a stream's budget: its ring plus its
+    share of a batched push's workspace."""
+    b = C.c_int64()
+    capi.check(capi.lib().snd_stream_admission_bytes(plan.handle, C.byref(b)))
+    return int(b.value)
+
+
 class Stream:
-    """A set of beams sharing one device-memory budget for their histories."""
+    """A set of beams sharing one device-memory budget for their histories and the workspace of
+    a batched push of all of them."""
 
     def __init__(self, budget_bytes: int, device="cuda"):
         import torch

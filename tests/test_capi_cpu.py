@@ -187,25 +187,27 @@ def test_streaming_plan_and_admission_host_logic(snd):
     pf = snd.Plan(f, dms, 0.138e-3, None, mode="float", branching=2, chunk=1000, node_dtype="bf16", in_dtype="bf16")
     assert snd.history_bytes(pf) == 64 * ((2 * (pf.max_delay + 1000) + 255) // 256 * 256)
 
+    na = snd.admission_bytes(p)
     h = C.c_void_p()
     assert L.snd_stream_create(0, C.byref(h)) == _capi.ERR_INVALID
-    _capi.check(L.snd_stream_create(2 * nb + nb // 2, C.byref(h)))
+    _capi.check(L.snd_stream_create(2 * na + na // 2, C.byref(h)))
     fake = C.c_void_p(1 << 20)
     assert L.snd_stream_admit(h, 0, p.handle, C.c_void_p((1 << 20) + 8), nb) == _capi.ERR_INVALID  # misaligned
     assert L.snd_stream_admit(h, 0, p.handle, fake, nb - 1) == _capi.ERR_NOMEM
-    assert L.snd_stream_admit(h, 0, p.handle, fake, nb) == _capi.ERR_STATE  # tables not uploaded
-    assert "upload" in L.snd_last_error().decode()
     used = C.c_int64()
     _capi.check(L.snd_stream_usage(h, None, C.byref(used), None))
     assert used.value == 0
+    assert L.snd_stream_admit(h, 0, p.handle, fake, nb) == _capi.OK  # tables are needed only to push
     # a plan without the input-anchored first stage cannot stream
     g = snd.Plan(f, dms, 0.138e-3, None, mode="graded", branching=2, chunk=1000, generic_kernels=True)
     assert L.snd_stream_admit(h, 1, g.handle, fake, nb) == _capi.ERR_UNSUPPORTED
     # budget: the third beam of this size does not fit
-    big = C.c_int64(3 * nb)
-    assert L.snd_stream_admit(h, 2, p.handle, fake, big) in (_capi.ERR_STATE,)
+    assert L.snd_stream_admit(h, 2, p.handle, fake, 3 * nb) == _capi.OK
+    assert L.snd_stream_admit(h, 3, p.handle, fake, nb) == _capi.ERR_CAPACITY
+    _capi.check(L.snd_stream_usage(h, None, C.byref(used), None))
+    assert used.value == 2 * na
     small_budget = C.c_void_p()
-    _capi.check(L.snd_stream_create(nb - 1, C.byref(small_budget)))
+    _capi.check(L.snd_stream_create(na - 1, C.byref(small_budget)))
     assert L.snd_stream_admit(small_budget, 0, p.handle, fake, nb) == _capi.ERR_CAPACITY
     assert "budget" in L.snd_last_error().decode()
     # unknown beams
@@ -370,3 +372,83 @@ def test_new_entry_points_reject_bad_arguments(snd):
     assert L.snd_detect_workspace(p.handle, C.byref(d), C.byref(nb)) == _capi.ERR_INVALID
     d.sigma_estimator = 1
     assert L.snd_detect_workspace(p.handle, C.byref(d), C.byref(nb)) == _capi.OK
+
+
+def _fake_device_ptr():
+    # a 256-byte aligned address that admission records but never dereferences
+    return C.c_void_p(0x7F0000000000)
+
+
+def test_stream_admission_charges_ring_and_workspace(snd):
+    """Admission charges a beam's history ring plus its share of a batched push's workspace, so
+    a budget that admits a set of beams also holds a batched push of all of them (host-only
+    accounting: admission touches no device memory)."""
+    from paper_2606_15361_amd import _capi
+    spec = synth.workload(1)
+    p = snd.Plan(spec.freqs, spec.dms, spec.tsamp_s, None, mode="graded", branching=2, chunk=1024)
+    ring = snd.history_bytes(p)
+    ws = (p.info["workspace_bytes"] + 255) // 256 * 256
+    assert ws > 0 and snd.admission_bytes(p) == ring + ws
+    lib = _capi.lib()
+    for budget, want in ((ring + ws - 1, _capi.ERR_CAPACITY), (ring, _capi.ERR_CAPACITY), (ring + ws, _capi.OK)):
+        h = C.c_void_p()
+        assert lib.snd_stream_create(budget, C.byref(h)) == _capi.OK
+        assert lib.snd_stream_admit(h, 0, p.handle, _fake_device_ptr(), ring) == want
+        b, u, n = C.c_int64(), C.c_int64(), C.c_int32()
+        assert lib.snd_stream_usage(h, C.byref(b), C.byref(u), C.byref(n)) == _capi.OK
+        assert (u.value, n.value) == ((ring + ws, 1) if want == _capi.OK else (0, 0))
+        if want == _capi.OK:
+            assert lib.snd_stream_evict(h, 0) == _capi.OK
+            assert lib.snd_stream_usage(h, C.byref(b), C.byref(u), C.byref(n)) == _capi.OK and u.value == 0
+        lib.snd_stream_destroy(h)
+
+
+def test_stream_import_rejects_inconsistent_checkpoints(snd):
+    """A checkpoint header whose state the beam cannot be in is rejected before anything is
+    copied: emitted must be max(0, received - max_delay), and a beam with nothing received has
+    emitted 0 and next chunk -1.  A push on a plan whose tables were never uploaded is refused."""
+    from paper_2606_15361_amd import _capi
+    spec = synth.workload(1)
+    p = snd.Plan(spec.freqs, spec.dms, spec.tsamp_s, None, mode="graded", branching=2, chunk=1024)
+    lib = _capi.lib()
+    h = C.c_void_p()
+    assert lib.snd_stream_create(1 << 40, C.byref(h)) == _capi.OK
+    assert lib.snd_stream_admit(h, 7, p.handle, _fake_device_ptr(), snd.history_bytes(p)) == _capi.OK
+    nb = C.c_int64()
+    assert lib.snd_stream_export_bytes(h, 7, C.byref(nb)) == _capi.OK
+    ring = snd.history_bytes(p)
+    assert nb.value == 64 + ring
+    md = p.max_delay
+    ring_len = md + p.n_out
+    es, pitch = 1, (ring_len + 255) // 256 * 256
+    assert 64 * pitch == ring
+
+    def header(received, emitted, next_chunk, magic=0x31564548444e53, rl=ring_len):
+        buf = np.zeros(nb.value, dtype=np.uint8)
+        buf[:64] = np.frombuffer(np.array([magic, received, emitted, next_chunk, rl, pitch, es, 64],
+                                          dtype=np.int64).tobytes(), dtype=np.uint8)
+        return buf
+
+    bad = [header(10 * md, 0, 5),                  # received far above emitted: outputs past n_out
+           header(md + 100, 99, 5),                # emitted one short
+           header(md + 100, 101, 5),               # emitted one over
+           header(50, 0, -1),                      # samples received but no chunk index
+           header(0, 0, 3),                        # nothing received but an expected index
+           header(-5, 0, -1),
+           header(md + 100, 100, 0),
+           header(md + 100, 100, 5, magic=1),      # not a checkpoint
+           header(md + 100, 100, 5, rl=ring_len + 1)]  # another ring shape
+    for buf in bad:
+        rc = lib.snd_stream_import(h, 7, buf.ctypes.data_as(C.c_void_p), buf.size, None)
+        assert rc == _capi.ERR_INVALID, buf[:64].view(np.int64)
+    short = header(md + 100, 100, 5)[:100]
+    assert lib.snd_stream_import(h, 7, short.ctypes.data_as(C.c_void_p), short.size, None) == _capi.ERR_INVALID
+    r, nx, e = C.c_int64(), C.c_int64(), C.c_int64()
+    assert lib.snd_stream_beam_state(h, 7, C.byref(r), C.byref(nx), C.byref(e)) == _capi.OK
+    assert (r.value, nx.value, e.value) == (0, -1, 0)  # nothing restored
+    # a push before the plan's tables are uploaded: STATE, before any copy or launch
+    it = (_capi.StreamItem * 1)()
+    it[0].beam_id, it[0].chunk_idx, it[0].chunk_len, it[0].chunk_pitch = 7, 0, 1024, 1024
+    it[0].d_chunk, it[0].d_out, it[0].out_pitch = 0x7F0000100000, 0x7F0000200000, p.n_out
+    assert lib.snd_stream_push(h, 1, it, _fake_device_ptr(), 1 << 40, None) == _capi.ERR_STATE
+    lib.snd_stream_destroy(h)

@@ -26,7 +26,7 @@ def test_server_admission_detection_and_forms_agree(snd):
     pf = snd.Plan(spec.freqs, spec.dms, spec.tsamp_s, None, mode="float", branching=2, chunk=T, in_dtype="bf16",
                   node_dtype="bf16")
     kinds = {"graded": (pg, [1.0, 2.0, 3.0, 4.0]), "bf16": (pf, None)}
-    budget = 2 * snd.history_bytes(pg) + snd.history_bytes(pf)
+    budget = 2 * snd.admission_bytes(pg) + snd.admission_bytes(pf)
     total = 6 * T
     z = synth.noise_filterbank(synth.make_rng(5), 64, total)
     # a bright pulse at DM 150 whose sweep lies inside the fifth chunk's output window

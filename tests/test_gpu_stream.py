@@ -145,7 +145,8 @@ def test_stream_admission_by_budget_and_multi_beam_push(snd):
     pg = snd.Plan(spec.freqs, spec.dms, spec.tsamp_s, None, mode="graded", branching=2, chunk=1024)
     pf = snd.Plan(spec.freqs, spec.dms, spec.tsamp_s, None, mode="float", branching=2, chunk=1024,
                   in_dtype="bf16", node_dtype="bf16")
-    hg, hf = snd.history_bytes(pg), snd.history_bytes(pf)
+    hg, hf = snd.admission_bytes(pg), snd.admission_bytes(pf)
+    assert hg > snd.history_bytes(pg) and hf > snd.history_bytes(pf)  # ring + batched-push workspace share
     st = snd.Stream(2 * hg + hf)
     st.admit(0, pg)
     st.admit(1, pf)
