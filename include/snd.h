@@ -351,6 +351,21 @@ snd_status snd_detect_launch(snd_plan plan, const void *d_plane, int64_t plane_p
 snd_status snd_detect_collect(snd_plan plan, const snd_detect_desc *desc, const void *h_stage, int64_t stage_bytes,
                               snd_candidate *h_out, int64_t cap, int64_t *h_count, int64_t *h_npixels);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): snd_detect_launch with no workspace argument.  Its
+ * kernels use a fixed device array of SND_DETECT_NOALLOC_MAX_BYTES held by the library on each
+ * GPU it runs on until the process ends (looked up once per device on the first call there,
+ * on the stream's device, or the current device for the null stream).  The call itself
+ * allocates nothing.  Same arguments, outputs and errors as snd_detect_launch, collected with
+ * snd_detect_collect; NOMEM (nothing launched) when snd_detect_workspace exceeds the maximum,
+ * which holds e.g. 4096 DM rows with max_pixels up to 1.38 million.  Every call on one GPU
+ * shares that GPU's array: the cell counter is cleared by the launch itself, and calls that
+ * overlap on one GPU (other streams, other threads) race; order them, e.g. on one stream, and
+ * collect a launch before the next one's stream work runs. */
+#define SND_DETECT_NOALLOC_MAX_BYTES ((int64_t)32 << 20)
+snd_status snd_detect_launch_noalloc(snd_plan plan, const void *d_plane, int64_t plane_pitch,
+                                     const snd_detect_desc *desc, void *h_stage, int64_t stage_bytes, void *stream);
+
 /* ---------------------------------------------------------------------------------------
  * Multi-rate extension (Methods, "Multi-rate extension").  The DM range is split into bands
  * by scrunch factor; each band runs its own plan (tsamp * S, nsamp / S samples, its DMs) on a

@@ -20,6 +20,7 @@ DT_U8, DT_U16, DT_F32, DT_BF16, DT_F16, DT_BITS = 1, 2, 3, 4, 5, 6
 
 DETECT_STAGE_HEADER = 256  # SND_DETECT_STAGE_HEADER
 DETECT_CELL_BYTES = 24    # bytes per staged cell
+DETECT_NOALLOC_MAX_BYTES = 32 << 20  # SND_DETECT_NOALLOC_MAX_BYTES
 
 
 class SndError(RuntimeError):
@@ -140,6 +141,7 @@ def lib() -> C.CDLL:
         "snd_detect": ([P, P, I64, D, P, I64, C.POINTER(Candidate), I64, C.POINTER(I64), C.POINTER(I64), P], I32),
         "snd_detect_launch": ([P, P, I64, D, P, I64, P, I64, P], I32),
         "snd_detect_collect": ([P, D, P, I64, C.POINTER(Candidate), I64, C.POINTER(I64), C.POINTER(I64)], I32),
+        "snd_detect_launch_noalloc": ([P, P, I64, D, P, I64, P], I32),
     })
     PI64 = C.POINTER(I64)
     PP = C.POINTER(P)

@@ -452,3 +452,22 @@ def test_stream_import_rejects_inconsistent_checkpoints(snd):
     it[0].d_chunk, it[0].d_out, it[0].out_pitch = 0x7F0000100000, 0x7F0000200000, p.n_out
     assert lib.snd_stream_push(h, 1, it, _fake_device_ptr(), 1 << 40, None) == _capi.ERR_STATE
     lib.snd_stream_destroy(h)
+
+
+def test_noalloc_detect_rejects_workspaces_beyond_the_scratch(snd):
+    """snd_detect_launch_noalloc refuses, before touching any device, a descriptor whose
+    workspace exceeds its fixed device array."""
+    import numpy as np
+    from paper_2606_15361_amd import _capi as capi
+    spec = synth.workload(1)
+    plan = snd.Plan(spec.freqs, spec.dms, spec.tsamp_s, spec.nsamp, mode="float", branching=2)
+    w = np.array([1, 2, 4], dtype=np.int32)
+    desc = capi.DetectDesc()
+    desc.widths = w.ctypes.data_as(C.POINTER(C.c_int32))
+    desc.nwidths, desc.threshold, desc.closing_radius, desc.n_min = 3, 5.0, 4, 1
+    desc.max_pixels = 1 << 24
+    stage = (C.c_uint8 * 512)()
+    rc = capi.lib().snd_detect_launch_noalloc(plan.handle, C.c_void_p(1 << 20), plan.n_out, C.byref(desc),
+                                              C.cast(stage, C.c_void_p), 512, None)
+    assert rc == capi.ERR_NOMEM
+    assert b"static scratch" in capi.lib().snd_last_error()
