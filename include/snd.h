@@ -137,7 +137,8 @@ typedef struct {
     int32_t stage_kernel[SND_MAX_LEVELS];   /* kernel per stage: 0 generic, 1 LDS row groups,
                                                2 input-anchored, 3 LDS row groups specialised for
                                                regular level-1 nodes, 4 the same on bit rows,
-                                               5 input-anchored on bit input */
+                                               5 input-anchored on bit input, 6 LDS row groups
+                                               summing float-mode rows as one sum each */
     int64_t stage_staged[SND_MAX_LEVELS];   /* LDS row groups: source elements staged per time
                                                tile summed over groups (0 otherwise) */
     int64_t stage_batches[SND_MAX_LEVELS];  /* LDS row groups: batches summed over groups */

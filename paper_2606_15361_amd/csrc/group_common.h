@@ -67,10 +67,11 @@ __device__ inline int issue_batch(const_ptr<int32_t> batches, const_ptr<int32_t>
     return n_ins;
 }
 
-// Copy one window (descriptor as in issue_batch) of the tile into LDS.
+// Copy one window (descriptor as in issue_batch) of the tile into LDS; returns the number of
+// copy instructions issued.
 template <typename TI>
-__device__ inline void issue_window(int srow, int eoff, int lbyte, int hs, int lane, const unsigned char *srcb,
-                                    int64_t pitch_bytes, int t0, int vt, unsigned char *ldsb)
+__device__ inline int issue_window(int srow, int eoff, int lbyte, int hs, int lane, const unsigned char *srcb,
+                                   int64_t pitch_bytes, int t0, int vt, unsigned char *ldsb)
 {
     constexpr int ES = (int)sizeof(TI);
     // row and offsets are non-negative and a row pitch is below 4 GiB (checked on the host)
@@ -83,6 +84,7 @@ __device__ inline void issue_window(int srow, int eoff, int lbyte, int hs, int l
         __builtin_amdgcn_global_load_lds(gp + u0, (__attribute__((address_space(3))) void *)(lp + 16 * u0), 16, 0, 0);
     if (u0 < nu && u0 + lane < nu)
         __builtin_amdgcn_global_load_lds(gp + u0, (__attribute__((address_space(3))) void *)(lp + 16 * u0), 16, 0, 0);
+    return (nu + 63) >> 6;
 }
 
 // A batch's table words for one wave: its entry range and window range, and the descriptors
@@ -111,18 +113,21 @@ __device__ inline void load_batch_words(const_ptr<int32_t> batches, const_ptr<in
 }
 
 // issue_batch from preloaded words: the first two windows from w, any further ones loaded here.
+// Returns the number of copy instructions issued.
 template <typename TI>
-__device__ inline void issue_batch_words(const BatchWords &w, const_ptr<int32_t> instrs, int wave, int lane,
-                                         const unsigned char *srcb, int64_t pitch_bytes, int t0, int vt, TI *dst)
+__device__ inline int issue_batch_words(const BatchWords &w, const_ptr<int32_t> instrs, int wave, int lane,
+                                        const unsigned char *srcb, int64_t pitch_bytes, int t0, int vt, TI *dst)
 {
     unsigned char *ldsb = reinterpret_cast<unsigned char *>(dst);
-    int si = w.bz + wave;
+    int si = w.bz + wave, n = 0;
 #pragma unroll
     for (int j = 0; j < 2; ++j, si += kGroupRows)
-        if (si < w.bw) issue_window<TI>(w.d[j][0], w.d[j][1], w.d[j][2], w.d[j][3], lane, srcb, pitch_bytes, t0, vt, ldsb);
+        if (si < w.bw)
+            n += issue_window<TI>(w.d[j][0], w.d[j][1], w.d[j][2], w.d[j][3], lane, srcb, pitch_bytes, t0, vt, ldsb);
     for (; si < w.bw; si += kGroupRows)
-        issue_window<TI>(instrs[4 * si], instrs[4 * si + 1], instrs[4 * si + 2], instrs[4 * si + 3], lane, srcb,
-                         pitch_bytes, t0, vt, ldsb);
+        n += issue_window<TI>(instrs[4 * si], instrs[4 * si + 1], instrs[4 * si + 2], instrs[4 * si + 3], lane, srcb,
+                              pitch_bytes, t0, vt, ldsb);
+    return n;
 }
 
 // Workgroup barrier for the staged kernels.  Every wave has already waited for its own copies
@@ -138,6 +143,7 @@ __device__ inline void stage_barrier()
 }
 
 int launch_group_bits(const GroupArgs &a, int64_t n_out, int lds, void *stream, const Multi &m, int64_t nblocks);
+int launch_group_lin(const GroupArgs &a, int64_t n_out, int lds, void *stream, const Multi &m, int64_t nblocks);
 int launch_anchored_bits(const AnchorArgs &a, int64_t ntiles, int lds, void *stream, const Multi &m);
 int launch_group_fast_binary(int src_dt, int dst_dt, const GroupArgs &a, int64_t n_out, int lds, void *stream,
                              const Multi &m, int64_t nblocks);

@@ -104,8 +104,23 @@ bool valid_dtype_pair(int mode, int in_dt, int node_dt, int cap)
 // staged window per distinct source row of each entry.  Every row of the final stage walks the
 // same tree, so all rows have the same entry count and closing pattern.  Returns false (and
 // leaves the stage on the generic kernel) when one entry alone does not fit the LDS budget.
-bool build_group_lds(const PlanImpl &p, Stage &S, bool allow_fast)
+// Variants: kGroupGeneric (any tree), kGroupFast (regular level-1 nodes, compile-time depth),
+// kGroupLin (float mode: every row is one sum over its inputs, with no activation in between).
+enum { kGroupGeneric = 0, kGroupFast = 1, kGroupLin = 2 };
+bool build_group_lds(const PlanImpl &p, Stage &S, int variant)
 {
+    const bool allow_fast = variant == kGroupFast;
+    const bool lin = variant == kGroupLin;
+    // the linear kernel reads a materialised plane of f32 rows, whose pitch its copy table holds
+    int64_t src_pitch = 0;
+    if (lin) {
+        if (!(p.desc.mode == SND_MODE_FLOAT && S.src_dtype == SND_DT_F32 && S.dst_dtype == SND_DT_F32) ||
+            S.src_level < 0)
+            return false;
+        for (const Stage &Q : p.stages)
+            if (!Q.final_stage && Q.dst_level == S.src_level) src_pitch = Q.pitch;
+        if (src_pitch <= 0 || src_pitch % 4 != 0 || (S.src_rows * src_pitch) / 4 >= (int64_t(1) << 32)) return false;
+    }
     const int64_t rows = S.rows;
     if (rows < 1) return false;
     const int32_t ne = (int32_t)(S.row_ptr[1] - S.row_ptr[0]);
@@ -129,14 +144,17 @@ bool build_group_lds(const PlanImpl &p, Stage &S, bool allow_fast)
             !group_fast_types(p.desc.mode, S.src_dtype, S.dst_dtype))
             f1 = 0;
     }
+    if (lin) f1 = 0;
     const bool bits = S.src_dtype == SND_DT_BITS;
     if (bits && !f1) return false;  // bit rows: specialised kernel only
-    const int tile = bits ? kGroupTileBits : f1 ? kGroupTileFast : kGroupTile;
-    const int rpw = f1 ? kFastRows : 1;  // rows per wave
+    // samples a window holds beyond its span (its tile), and the tile step in time
+    const int tile = lin ? kLinCover : bits ? kGroupTileBits : f1 ? kGroupTileFast : kGroupTile;
+    const int tile_step = lin ? kLinTile : tile;
+    const int rpw = lin ? kLinRows : f1 ? kFastRows : 1;  // rows per wave
     const int gr = kGroupRows * rpw;     // rows per group
     const int unit = f1 ? f1 : 1;  // batches end on level-1 node boundaries
     const int eb = bits ? 1 : 8 * dtype_size(S.src_dtype);  // bits per element
-    const int64_t budget = (int64_t)(f1 ? kGroupFastLdsBytes : kGroupLdsBytes) * 8 / eb;
+    const int64_t budget = (int64_t)(lin ? kLinLdsBytes : f1 ? kGroupFastLdsBytes : kGroupLdsBytes) * 8 / eb;
     const int32_t epd = 128 / eb;  // elements per 16-byte copy unit
     // LDS elements of one window: its span plus one tile, from a 16-byte boundary, whole units
     // (bit rows: one more unit, since a lane reads the word after its 32 samples too)
@@ -166,9 +184,16 @@ bool build_group_lds(const PlanImpl &p, Stage &S, bool allow_fast)
     std::vector<int32_t> slot_of(gr);
     std::vector<Src> unit_srcs;
     std::vector<int32_t> unit_nsrc;
+    // linear kernel: copy chunks of the open batch
+    int32_t batch_chunks = 0;
+    auto lin_chunks = [&](const Src &s) {  // 64-unit copies of one window in a full tile
+        const int64_t units = ((int64_t)(s.lo % epd) + (s.hi - s.lo) + kLinTile + epd - 1) / epd;
+        return (int32_t)((units + 63) / 64);
+    };
     for (int64_t g = 0; g < ng; ++g) {
         int32_t e0 = 0, s0 = (int32_t)(slots.size() / 4);
         int64_t elems = 0;
+        batch_chunks = 0;
         for (int32_t eu = 0; eu < ne; eu += unit) {
         // windows of every input of this unit, then one decision where the batch ends
         unit_srcs.clear();
@@ -200,13 +225,23 @@ bool build_group_lds(const PlanImpl &p, Stage &S, bool allow_fast)
         for (const Src &s : unit_srcs) need += slot_elems(s.lo, s.hi - s.lo);
         if (need > budget || (int32_t)unit_srcs.size() > max_slots) return false;
         const int32_t nslot_batch = (int32_t)(slots.size() / 4) - s0;
-        if (elems + need > budget || nslot_batch + (int32_t)unit_srcs.size() > max_slots) {  // close the batch
+        bool lin_full = false;
+        int32_t unit_chunks = 0;
+        if (lin) {  // the batch's entries or the waves' copy chunks would overflow
+            for (const Src &s : unit_srcs) unit_chunks += lin_chunks(s);
+            if (unit_chunks > kGroupRows * kLinMaxChunks) return false;
+            lin_full = batch_chunks + unit_chunks > kGroupRows * kLinMaxChunks || eu - e0 >= kLinMaxBatchEntries;
+        }
+        if (elems + need > budget || nslot_batch + (int32_t)unit_srcs.size() > max_slots || lin_full) {
+            // close the batch
             batches.insert(batches.end(), {e0, eu, s0, (int32_t)(slots.size() / 4)});
             max_elems = std::max(max_elems, elems);
             e0 = eu;
             s0 = (int32_t)(slots.size() / 4);
             elems = 0;
+            batch_chunks = 0;
         }
+        batch_chunks += unit_chunks;
         size_t si0 = 0;
         for (int32_t e = eu; e < eu + unit; ++e) {
             const int32_t ns = unit_nsrc[(size_t)(e - eu)];
@@ -252,16 +287,75 @@ bool build_group_lds(const PlanImpl &p, Stage &S, bool allow_fast)
         const int32_t head = lo % epd;
         instrs.insert(instrs.end(), {srow, lo - head, (int32_t)((int64_t)(lofs - head) * eb / 8), head + span});
     }
+    std::vector<uint32_t> lin_tab, lin_smem;
+    if (lin) {
+        // linear kernel: per (batch, wave) the offset words of the wave's rows by phase, and the
+        // segment counts and copy chunks as scalar words
+        const int64_t nb_all = (int64_t)(batches.size() / 4);
+        lin_tab.assign((size_t)(nb_all * kGroupRows * kLinWords), 0u);
+        lin_smem.assign((size_t)(nb_all * kGroupRows * kLinSmemWords), 0u);
+        for (int64_t g = 0; g < ng; ++g) {
+            for (int32_t b = batch_ptr[(size_t)g]; b < batch_ptr[(size_t)g + 1]; ++b) {
+                const int32_t ex = batches[4 * (size_t)b], ey = batches[4 * (size_t)b + 1];
+                const int32_t bz = batches[4 * (size_t)b + 2], bw = batches[4 * (size_t)b + 3];
+                const int32_t n = ey - ex;
+                if (n > kLinMaxBatchEntries) return false;
+                for (int w = 0; w < kGroupRows; ++w) {
+                    uint32_t *words = &lin_tab[(size_t)((b * kGroupRows + w) * kLinWords)];
+                    for (int q = 0; q < kLinRows; ++q) {
+                        const int32_t r = grp_rows[(size_t)(g * gr + w * rpw + q)];
+                        uint32_t *o = words + q * n;
+                        int k = 0;
+                        for (int ph = 0; ph < 4; ++ph) {
+                            int cnt = 0;
+                            for (int32_t e = ex; e < ey && r >= 0; ++e) {
+                                const uint32_t el = ldsb_at(g, w * rpw + q, e) & kRowMask;
+                                if ((int)(el & 3u) != ph) continue;
+                                o[k++] = (el & ~3u) * 4u;
+                                ++cnt;
+                            }
+                            words[2 * n + q] |= (uint32_t)cnt << (8 * ph);
+                        }
+                    }
+                }
+                for (int w = 0; w < kGroupRows; ++w)
+                    lin_smem[(size_t)((b * kGroupRows + w) * kLinSmemWords + kLinSmemWords - 1)] = (uint32_t)n;
+                // copy chunks of the batch's windows for a full tile, dealt to the waves in turn
+                int32_t j = 0;
+                for (int32_t si = bz; si < bw; ++si) {
+                    const int32_t srow = slots[4 * (size_t)si], lo = slots[4 * (size_t)si + 1];
+                    const int32_t span = slots[4 * (size_t)si + 2], lofs = slots[4 * (size_t)si + 3];
+                    const int32_t head = lo % epd;
+                    const int64_t units = ((int64_t)head + span + kLinTile + epd - 1) / epd;
+                    const int64_t unit0 = ((int64_t)srow * src_pitch + lo - head) / epd;
+                    const int64_t lds0 = (int64_t)(lofs - head) * (eb / 8);
+                    for (int64_t u0 = 0; u0 < units; u0 += 64, ++j) {
+                        const int w = j % kGroupRows, c = j / kGroupRows;
+                        if (c >= kLinMaxChunks) return false;
+                        const int64_t nu = std::min<int64_t>(64, units - u0);
+                        uint32_t *sm = &lin_smem[(size_t)((b * kGroupRows + w) * kLinSmemWords)];
+                        sm[0] = (uint32_t)(c + 1);
+                        sm[kLinSmemWords - 1] = (uint32_t)(ey - ex);
+                        sm[1 + c] = (uint32_t)(unit0 + u0);
+                        sm[1 + kLinMaxChunks + c] = (uint32_t)(lds0 + 16 * u0);
+                        sm[1 + 2 * kLinMaxChunks + c] = (uint32_t)nu;
+                    }
+                }
+            }
+        }
+    }
     S.kernel = kKernelGroupLds;
     S.ngroups = ng;
     S.n_entries = ne;
     S.group_f1 = f1;
-    S.group_tile = tile;
+    S.group_tile = tile_step;
     S.group_rpw = rpw;
+    S.group_lin = lin;
     const int64_t buf_bytes = round_up(max_elems * eb / 8, 16);
     S.lds_buf_elems = (int32_t)(buf_bytes * 8 / eb);
     // general kernel: batches b+1, b+2 land while b is read; specialised kernel: b+1
-    S.lds_bytes = (int32_t)((f1 ? kFastBuffers : kGroupBuffers) * buf_bytes);
+    S.lds_bytes = (int32_t)(lin ? kLinBuffers * (buf_bytes + kLinWordBytes)
+                                : (f1 ? kFastBuffers : kGroupBuffers) * buf_bytes);
     S.grp_rows = std::move(grp_rows);
     S.batch_ptr = std::move(batch_ptr);
     S.batches = std::move(batches);
@@ -278,7 +372,10 @@ bool build_group_lds(const PlanImpl &p, Stage &S, bool allow_fast)
         S.node_closes.resize((size_t)(ne / f1));
         for (int32_t k = 0; k < ne / f1; ++k) S.node_closes[(size_t)k] = (int32_t)(S.ent[k * f1 + f1 - 1].rowc >> 24);
     }
+    if (lin) ldsb.clear();  // the linear kernel reads its own table
     S.ldsb = std::move(ldsb);
+    S.lin = std::move(lin_tab);
+    S.lin_smem = std::move(lin_smem);
     return true;
 }
 
@@ -622,7 +719,9 @@ snd_status build_plan(const snd_plan_desc &d, PlanImpl &p, std::string &err)
     for (Stage &S : p.stages) {
         S.kernel = kKernelGeneric;
         if (d.generic_kernels) continue;
-        if (S.final_stage && (build_group_lds(p, S, true) || (!bits && build_group_lds(p, S, false)))) continue;
+        if (S.final_stage && (build_group_lds(p, S, kGroupLin) || build_group_lds(p, S, kGroupFast) ||
+                              (!bits && build_group_lds(p, S, kGroupGeneric))))
+            continue;
         if (!S.final_stage && S.src_level < 0) build_anchored(p, S);
     }
     if (bits && (p.stages.size() != 2 || p.stages[0].kernel != kKernelAnchored ||
@@ -648,6 +747,8 @@ snd_status build_plan(const snd_plan_desc &d, PlanImpl &p, std::string &err)
         S.off_instrs = reserve((int64_t)S.instrs.size() * 4);
         S.off_ldsb = reserve((int64_t)S.ldsb.size() * 4);
         S.off_node_closes = reserve((int64_t)S.node_closes.size() * 4);
+        S.off_lin = reserve((int64_t)S.lin.size() * 4);
+        S.off_lin_smem = reserve((int64_t)S.lin_smem.size() * 4);
         S.off_nodes = reserve((int64_t)S.nodes.size() * 4);
         S.off_tiles = reserve((int64_t)S.tiles.size() * 4);
         S.off_row_lo = reserve((int64_t)S.row_lo.size() * 4);
@@ -666,6 +767,8 @@ snd_status build_plan(const snd_plan_desc &d, PlanImpl &p, std::string &err)
         put(S.off_instrs, S.instrs.data(), S.instrs.size() * 4);
         put(S.off_ldsb, S.ldsb.data(), S.ldsb.size() * 4);
         put(S.off_node_closes, S.node_closes.data(), S.node_closes.size() * 4);
+        put(S.off_lin, S.lin.data(), S.lin.size() * 4);
+        put(S.off_lin_smem, S.lin_smem.data(), S.lin_smem.size() * 4);
         put(S.off_nodes, S.nodes.data(), S.nodes.size() * 4);
         put(S.off_tiles, S.tiles.data(), S.tiles.size() * 4);
         put(S.off_row_lo, S.row_lo.data(), S.row_lo.size() * 4);
@@ -715,13 +818,15 @@ snd_status build_plan(const snd_plan_desc &d, PlanImpl &p, std::string &err)
         I.stage_alg_bytes[si] = S.alg_bytes;
         I.stage_rows[si] = S.rows;
         I.stage_entries[si] = (int64_t)S.ent.size();
-        I.stage_kernel[si] = S.kernel == kKernelAnchored && S.src_dtype == SND_DT_BITS ? 5
+        I.stage_kernel[si] = S.kernel == kKernelGroupLds && S.group_lin                    ? 6
+                             : S.kernel == kKernelAnchored && S.src_dtype == SND_DT_BITS ? 5
                              : S.kernel == kKernelGroupLds && S.src_dtype == SND_DT_BITS ? 4
                              : (S.kernel == kKernelGroupLds && S.group_f1 > 0) ? 3
                                                                                 : S.kernel;
         if (S.kernel == kKernelGroupLds) {
             int64_t staged = 0;
-            for (size_t i = 0; i < S.slots.size(); i += 4) staged += S.slots[i + 2] + S.group_tile;
+            const int64_t cover = S.group_lin ? kLinCover : S.group_tile;
+            for (size_t i = 0; i < S.slots.size(); i += 4) staged += S.slots[i + 2] + cover;
             I.stage_staged[si] = staged;
             I.stage_batches[si] = (int64_t)(S.batches.size() / 4);
             I.stage_windows[si] = (int64_t)(S.slots.size() / 4);

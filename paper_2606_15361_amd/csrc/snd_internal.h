@@ -65,8 +65,19 @@ struct Stage {
     std::vector<uint32_t> ldsb;     // [ngroups][kGroupRows][n_entries][rows per wave]: LDS element offset |
                                     // closes << 24 (general kernel) or LDS byte offset (specialised kernel)
     std::vector<int32_t> node_closes;  // specialised kernel: levels completed by each level-1 node
+    // Linear kernel (float mode: the final stage is one sum over its inputs, no activation).  Per
+    // (global batch index, wave): kLinWords offset words, copied to LDS with the batch: for each
+    // of the wave's two rows the LDS byte offsets of the 16-byte units holding the first sample of
+    // the batch's n inputs, ordered by the input's phase (offset mod 4), then one word per row
+    // with the number of inputs of each phase (four 8-bit counts); and kLinSmemWords words read
+    // as scalars: the number of copy chunks of the wave, then for its chunks (global -> LDS
+    // copies of up to 64 16-byte units) the source unit index from the plane start, the LDS byte
+    // offset and the unit count, and last the batch's number of inputs n.
+    bool group_lin = false;
+    std::vector<uint32_t> lin;
+    std::vector<uint32_t> lin_smem;
     int64_t off_grp_rows = 0, off_batch_ptr = 0, off_batches = 0, off_instrs = 0, off_ldsb = 0;
-    int64_t off_node_closes = 0;
+    int64_t off_node_closes = 0, off_lin = 0, off_lin_smem = 0;
 
     // kKernelAnchored: one workgroup per (node, window of anchor_tile reference samples).
     std::vector<int32_t> nodes;     // 6 ints per node: row begin, row end, channel begin, channel end, rho max,
@@ -94,6 +105,22 @@ constexpr int kGroupTileFast = 64 * kFastV;
 constexpr int kFastBuffers = 2;           // batch b + 1 lands while b is read
 constexpr int kGroupFastLdsBytes = 81920; // per buffer (two fill the 160 KB of LDS)
 constexpr int kGroupTileBits = 2048;  // bit rows: 32 samples (one word) per lane
+// Linear kernel: each wave sums kLinRows DM rows; lane i owns the 4-sample units at tile samples
+// 4i and kLinHalf + 4i, lanes 0..62 keep them, lane 63 only supplies lane 62's neighbour unit.
+constexpr int kLinRows = 2;
+constexpr int kLinHalf = 252;                  // samples per half tile (63 lanes x 4)
+constexpr int kLinTile = 2 * kLinHalf;         // output samples per workgroup tile
+constexpr int kLinCover = kLinTile + 4;        // staged samples per window beyond its span
+constexpr int kLinMaxBatchEntries = 31;        // 2 rows x 31 offsets + 2 count words fit 64 lanes
+constexpr int kLinWords = 64;                  // offset words per (batch, wave)
+constexpr int kLinMaxChunks = 7;               // copy chunks per (batch, wave)
+constexpr int kLinSmemWords = 24;              // chunk count, 7 units, 7 LDS offsets, 7 lengths, entries
+#ifndef SND_LIN_BUFFERS
+#define SND_LIN_BUFFERS 2
+#endif
+constexpr int kLinBuffers = SND_LIN_BUFFERS;    // LDS ring: batches b + 1 .. b + kLinBuffers - 1 land while b is read
+constexpr int kLinWordBytes = kGroupRows * kLinWords * 4;  // each buffer's copy of its batch's offset words
+constexpr int kLinLdsBytes = (163840 / kLinBuffers - kLinWordBytes) / 16 * 16;  // window bytes per buffer
 inline bool group_fast_types(int mode, int src_dt, int dst_dt)
 {
     if (mode == SND_MODE_BINARY) return (src_dt == SND_DT_U8 || src_dt == SND_DT_BITS) && dst_dt == SND_DT_U8;
@@ -215,6 +242,9 @@ struct GroupArgs {
     const int32_t *instrs;   // 4 ints per staged window (copy descriptor)
     const uint32_t *ldsb;
     const int32_t *node_closes;  // specialised kernel only
+    const uint32_t *lin_smem;    // linear kernel only
+    const uint32_t *lin;
+    int32_t lin_kernel;          // 1: linear kernel
     int32_t ngroups;
     int32_t n_entries;
     int32_t buf_elems;
@@ -265,9 +295,11 @@ int launch_cast(const float *src, int64_t src_pitch, int64_t rows, int64_t cols,
                 int dst_dtype, void *stream);
 
 // Compile-time shape of the kernel instance that runs stage S: the depth class, or, for the
-// specialised row-group kernel, 1000 * (inputs per level-1 node) + depth.
+// specialised row-group kernel, 1000 * (inputs per level-1 node) + depth; -1 for the linear
+// kernel.
 inline int stage_shape(const Stage &S)
 {
+    if (S.kernel == kKernelGroupLds && S.group_lin) return -1;
     if (S.kernel == kKernelGroupLds && S.group_f1 > 0) return 1000 * S.group_f1 + S.depth;
     return depth_bucket(S.depth);
 }

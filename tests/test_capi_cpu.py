@@ -71,14 +71,25 @@ def test_config2_plan_shape(snd):
     assert p.n_out == 102748
     assert p.info["n_stages"] == 2
     assert p.info["build_seconds"] < 3.0
-    assert p.info["stage_kernel"] == ["anchored", "group_fast"]
+    # float mode: every final-stage row is one sum, whatever the tree's shape
+    assert p.info["stage_kernel"] == ["anchored", "group_lin"]
     b8 = snd.Plan(spec.freqs, spec.dms, spec.tsamp_s, spec.nsamp, mode="float", branching=8)
-    assert b8.info["stage_kernel"] == ["anchored", "group_lds"]  # an 8-input node's windows exceed one batch
+    assert b8.info["stage_kernel"] == ["anchored", "group_lin"]
+    pg = snd.Plan(spec.freqs, spec.dms, spec.tsamp_s, spec.nsamp, mode="graded", branching=4)
+    assert pg.info["stage_kernel"] == ["anchored", "group_fast"]
+    g8 = snd.Plan(spec.freqs, spec.dms, spec.tsamp_s, spec.nsamp, mode="graded", branching=8)
+    assert g8.info["stage_kernel"] == ["anchored", "group_fast"]  # byte windows: an 8-input node fits a batch
+    h8 = snd.Plan(spec.freqs, spec.dms, spec.tsamp_s, spec.nsamp, mode="float", branching=8, node_dtype="bf16",
+                  in_dtype="bf16")
+    assert h8.info["stage_kernel"] == ["anchored", "group_fast"]  # 16-bit windows of an 8-input node fit too
     # a ragged tree (1000 channels: the last leaf and node groups are short) has irregular
-    # level-1 nodes and takes the general row-group kernel
-    rag = snd.Plan(synth.channel_freqs(1000), synth.dm_linear(512, 0, 500), spec.tsamp_s, 20000, mode="float",
+    # level-1 nodes and takes the general row-group kernel in the activated modes
+    rag = snd.Plan(synth.channel_freqs(1000), synth.dm_linear(512, 0, 500), spec.tsamp_s, 20000, mode="graded",
                    branching=4)
     assert rag.info["stage_kernel"] == ["anchored", "group_lds"]
+    ragf = snd.Plan(synth.channel_freqs(1000), synth.dm_linear(512, 0, 500), spec.tsamp_s, 20000, mode="float",
+                    branching=4)
+    assert ragf.info["stage_kernel"] == ["anchored", "group_lin"]
     g = snd.Plan(spec.freqs, spec.dms, spec.tsamp_s, spec.nsamp, mode="float", branching=4, generic_kernels=True)
     assert g.info["stage_kernel"] == ["generic", "generic"]
     every = snd.Plan(spec.freqs, spec.dms, spec.tsamp_s, 40000, mode="graded", branching=4, stage_levels=0b1111)

@@ -100,7 +100,8 @@ def test_parity_small(snd, orc, nchan, C_, B, mode, kw):
                      generic_kernels=generic, node_dtype=node, **kw)
         if not generic and sl == 0 and nlev > 1:
             assert p.info["stage_kernel"][0] == "anchored", p.info["stage_kernel"]
-            assert p.info["stage_kernel"][1] in ("group_lds", "group_fast", "group_bits"), p.info["stage_kernel"]
+            assert p.info["stage_kernel"][1] in ("group_lds", "group_fast", "group_bits", "group_lin"), \
+                p.info["stage_kernel"]
         y = gpu_run(p, x, stage_by_stage=(sl == 0))
         assert y.shape == want.shape
         if mode == "float":
@@ -123,7 +124,12 @@ def test_parity_small(snd, orc, nchan, C_, B, mode, kw):
             assert np.array_equal(y, want.astype(y.dtype))
             ys.append(y)
     for y in ys[1:]:
-        assert np.array_equal(y, ys[0])  # identical whatever levels are materialised
+        if mode == "float":
+            # float mode fixes no FP32 summation order: each schedule's plane is within the float
+            # tolerance of the others (every one already is of the FP64 oracle)
+            assert rel_rms(y, ys[0]) <= FP32_TOL
+        else:
+            assert np.array_equal(y, ys[0])  # identical whatever levels are materialised
 
 
 def test_float_small_integer_input_is_exact(snd, orc):
