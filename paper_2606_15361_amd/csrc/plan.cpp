@@ -148,8 +148,8 @@ bool build_group_lds(const PlanImpl &p, Stage &S, int variant)
     const bool bits = S.src_dtype == SND_DT_BITS;
     if (bits && !f1) return false;  // bit rows: specialised kernel only
     // samples a window holds beyond its span (its tile), and the tile step in time
-    const int tile = lin ? kLinCover : bits ? kGroupTileBits : f1 ? kGroupTileFast : kGroupTile;
-    const int tile_step = lin ? kLinTile : tile;
+    const int tile = lin ? kLinTile : bits ? kGroupTileBits : f1 ? kGroupTileFast : kGroupTile;
+    const int tile_step = tile;
     const int rpw = lin ? kLinRows : f1 ? kFastRows : 1;  // rows per wave
     const int gr = kGroupRows * rpw;     // rows per group
     const int unit = f1 ? f1 : 1;  // batches end on level-1 node boundaries
@@ -289,8 +289,8 @@ bool build_group_lds(const PlanImpl &p, Stage &S, int variant)
     }
     std::vector<uint32_t> lin_tab, lin_smem;
     if (lin) {
-        // linear kernel: per (batch, wave) the offset words of the wave's rows by phase, and the
-        // segment counts and copy chunks as scalar words
+        // linear kernel: per (batch, wave) the offset words of the wave's rows, and its copy
+        // chunks as scalar words
         const int64_t nb_all = (int64_t)(batches.size() / 4);
         lin_tab.assign((size_t)(nb_all * kGroupRows * kLinWords), 0u);
         lin_smem.assign((size_t)(nb_all * kGroupRows * kLinSmemWords), 0u);
@@ -304,18 +304,8 @@ bool build_group_lds(const PlanImpl &p, Stage &S, int variant)
                     uint32_t *words = &lin_tab[(size_t)((b * kGroupRows + w) * kLinWords)];
                     for (int q = 0; q < kLinRows; ++q) {
                         const int32_t r = grp_rows[(size_t)(g * gr + w * rpw + q)];
-                        uint32_t *o = words + q * n;
-                        int k = 0;
-                        for (int ph = 0; ph < 4; ++ph) {
-                            int cnt = 0;
-                            for (int32_t e = ex; e < ey && r >= 0; ++e) {
-                                const uint32_t el = ldsb_at(g, w * rpw + q, e) & kRowMask;
-                                if ((int)(el & 3u) != ph) continue;
-                                o[k++] = (el & ~3u) * 4u;
-                                ++cnt;
-                            }
-                            words[2 * n + q] |= (uint32_t)cnt << (8 * ph);
-                        }
+                        for (int32_t e = ex; e < ey && r >= 0; ++e)
+                            words[q * n + (e - ex)] = (ldsb_at(g, w * rpw + q, e) & kRowMask) * (uint32_t)(eb / 8);
                     }
                 }
                 for (int w = 0; w < kGroupRows; ++w)
@@ -825,8 +815,7 @@ snd_status build_plan(const snd_plan_desc &d, PlanImpl &p, std::string &err)
                                                                                 : S.kernel;
         if (S.kernel == kKernelGroupLds) {
             int64_t staged = 0;
-            const int64_t cover = S.group_lin ? kLinCover : S.group_tile;
-            for (size_t i = 0; i < S.slots.size(); i += 4) staged += S.slots[i + 2] + cover;
+            for (size_t i = 0; i < S.slots.size(); i += 4) staged += S.slots[i + 2] + S.group_tile;
             I.stage_staged[si] = staged;
             I.stage_batches[si] = (int64_t)(S.batches.size() / 4);
             I.stage_windows[si] = (int64_t)(S.slots.size() / 4);

@@ -66,13 +66,11 @@ struct Stage {
                                     // closes << 24 (general kernel) or LDS byte offset (specialised kernel)
     std::vector<int32_t> node_closes;  // specialised kernel: levels completed by each level-1 node
     // Linear kernel (float mode: the final stage is one sum over its inputs, no activation).  Per
-    // (global batch index, wave): kLinWords offset words, copied to LDS with the batch: for each
-    // of the wave's two rows the LDS byte offsets of the 16-byte units holding the first sample of
-    // the batch's n inputs, ordered by the input's phase (offset mod 4), then one word per row
-    // with the number of inputs of each phase (four 8-bit counts); and kLinSmemWords words read
-    // as scalars: the number of copy chunks of the wave, then for its chunks (global -> LDS
-    // copies of up to 64 16-byte units) the source unit index from the plane start, the LDS byte
-    // offset and the unit count, and last the batch's number of inputs n.
+    // (global batch index, wave): kLinWords offset words, copied to LDS with the batch: word
+    // q * n + i is the LDS byte offset of the first sample of input i of the wave's row q (n the
+    // batch's inputs); and kLinSmemWords words read as scalars: the number of copy chunks of the
+    // wave, then for its chunks (global -> LDS copies of up to 64 16-byte units) the source unit
+    // index from the plane start, the LDS byte offset and the unit count, and last n.
     bool group_lin = false;
     std::vector<uint32_t> lin;
     std::vector<uint32_t> lin_smem;
@@ -105,13 +103,11 @@ constexpr int kGroupTileFast = 64 * kFastV;
 constexpr int kFastBuffers = 2;           // batch b + 1 lands while b is read
 constexpr int kGroupFastLdsBytes = 81920; // per buffer (two fill the 160 KB of LDS)
 constexpr int kGroupTileBits = 2048;  // bit rows: 32 samples (one word) per lane
-// Linear kernel: each wave sums kLinRows DM rows; lane i owns the 4-sample units at tile samples
-// 4i and kLinHalf + 4i, lanes 0..62 keep them, lane 63 only supplies lane 62's neighbour unit.
-constexpr int kLinRows = 2;
-constexpr int kLinHalf = 252;                  // samples per half tile (63 lanes x 4)
-constexpr int kLinTile = 2 * kLinHalf;         // output samples per workgroup tile
-constexpr int kLinCover = kLinTile + 4;        // staged samples per window beyond its span
-constexpr int kLinMaxBatchEntries = 31;        // 2 rows x 31 offsets + 2 count words fit 64 lanes
+// Linear kernel: each wave sums kLinRows DM rows (128 DM-adjacent rows per workgroup share the
+// staged windows); lane i owns tile samples i + 64 v, v = 0 .. 7.
+constexpr int kLinRows = 8;
+constexpr int kLinTile = 512;                  // output samples per workgroup tile
+constexpr int kLinMaxBatchEntries = 64 / kLinRows;  // the wave's offset words fit 64 lanes
 constexpr int kLinWords = 64;                  // offset words per (batch, wave)
 constexpr int kLinMaxChunks = 7;               // copy chunks per (batch, wave)
 constexpr int kLinSmemWords = 24;              // chunk count, 7 units, 7 LDS offsets, 7 lengths, entries
