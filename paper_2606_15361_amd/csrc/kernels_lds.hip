@@ -368,8 +368,8 @@ int launch_group(int mode, int src_dt, int dst_dt, const GroupArgs &a, int64_t n
         return launch_group_bits(a, n_out, lds_bytes, stream, m, nblocks);
     }
     if (a.lin_kernel) {
-        if (mode != SND_MODE_FLOAT || src_dt != SND_DT_F32 || dst_dt != SND_DT_F32) return (int)hipErrorInvalidValue;
-        return launch_group_lin(a, n_out, lds_bytes, stream, m, nblocks);
+        if (mode != SND_MODE_FLOAT || dst_dt != SND_DT_F32) return (int)hipErrorInvalidValue;
+        return launch_group_lin(src_dt, a, n_out, lds_bytes, stream, m, nblocks);
     }
     if (a.f1 > 0) {
         if (mode == SND_MODE_BINARY)

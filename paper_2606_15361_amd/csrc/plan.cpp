@@ -111,15 +111,17 @@ bool build_group_lds(const PlanImpl &p, Stage &S, int variant)
 {
     const bool allow_fast = variant == kGroupFast;
     const bool lin = variant == kGroupLin;
-    // the linear kernel reads a materialised plane of f32 rows, whose pitch its copy table holds
+    // the linear kernel reads a materialised plane of f32, bf16 or f16 rows, whose pitch its copy
+    // table holds
     int64_t src_pitch = 0;
     if (lin) {
-        if (!(p.desc.mode == SND_MODE_FLOAT && S.src_dtype == SND_DT_F32 && S.dst_dtype == SND_DT_F32) ||
-            S.src_level < 0)
-            return false;
+        const bool ok_src = S.src_dtype == SND_DT_F32 || S.src_dtype == SND_DT_BF16 || S.src_dtype == SND_DT_F16;
+        if (!(p.desc.mode == SND_MODE_FLOAT && ok_src && S.dst_dtype == SND_DT_F32) || S.src_level < 0) return false;
         for (const Stage &Q : p.stages)
             if (!Q.final_stage && Q.dst_level == S.src_level) src_pitch = Q.pitch;
-        if (src_pitch <= 0 || src_pitch % 4 != 0 || (S.src_rows * src_pitch) / 4 >= (int64_t(1) << 32)) return false;
+        const int64_t epu = 16 / dtype_size(S.src_dtype);  // elements per 16-byte unit
+        if (src_pitch <= 0 || src_pitch % epu != 0 || (S.src_rows * src_pitch) / epu >= (int64_t(1) << 32))
+            return false;
     }
     const int64_t rows = S.rows;
     if (rows < 1) return false;
@@ -147,9 +149,10 @@ bool build_group_lds(const PlanImpl &p, Stage &S, int variant)
     if (lin) f1 = 0;
     const bool bits = S.src_dtype == SND_DT_BITS;
     if (bits && !f1) return false;  // bit rows: specialised kernel only
-    // samples a window holds beyond its span (its tile), and the tile step in time
-    const int tile = lin ? kLinTile : bits ? kGroupTileBits : f1 ? kGroupTileFast : kGroupTile;
-    const int tile_step = tile;
+    // samples a window holds beyond its span (its tile, plus one unit for the linear kernel on
+    // 16-bit rows), and the tile step in time
+    const int tile = lin ? lin_cover(S.src_dtype) : bits ? kGroupTileBits : f1 ? kGroupTileFast : kGroupTile;
+    const int tile_step = lin ? kLinTile : tile;
     const int rpw = lin ? kLinRows : f1 ? kFastRows : 1;  // rows per wave
     const int gr = kGroupRows * rpw;     // rows per group
     const int unit = f1 ? f1 : 1;  // batches end on level-1 node boundaries
@@ -187,7 +190,7 @@ bool build_group_lds(const PlanImpl &p, Stage &S, int variant)
     // linear kernel: copy chunks of the open batch
     int32_t batch_chunks = 0;
     auto lin_chunks = [&](const Src &s) {  // 64-unit copies of one window in a full tile
-        const int64_t units = ((int64_t)(s.lo % epd) + (s.hi - s.lo) + kLinTile + epd - 1) / epd;
+        const int64_t units = ((int64_t)(s.lo % epd) + (s.hi - s.lo) + tile + epd - 1) / epd;
         return (int32_t)((units + 63) / 64);
     };
     for (int64_t g = 0; g < ng; ++g) {
@@ -288,6 +291,7 @@ bool build_group_lds(const PlanImpl &p, Stage &S, int variant)
         instrs.insert(instrs.end(), {srow, lo - head, (int32_t)((int64_t)(lofs - head) * eb / 8), head + span});
     }
     std::vector<uint32_t> lin_tab, lin_smem;
+    static_assert(kLinMaxBatchEntries <= 15, "per-row input counts are packed in 4 bits");
     if (lin) {
         // linear kernel: per (batch, wave) the offset words of the wave's rows, and its copy
         // chunks as scalar words
@@ -302,21 +306,30 @@ bool build_group_lds(const PlanImpl &p, Stage &S, int variant)
                 if (n > kLinMaxBatchEntries) return false;
                 for (int w = 0; w < kGroupRows; ++w) {
                     uint32_t *words = &lin_tab[(size_t)((b * kGroupRows + w) * kLinWords)];
+                    uint32_t even = 0;  // 16-bit rows: inputs starting a dword first, counts per row
                     for (int q = 0; q < kLinRows; ++q) {
                         const int32_t r = grp_rows[(size_t)(g * gr + w * rpw + q)];
-                        for (int32_t e = ex; e < ey && r >= 0; ++e)
-                            words[q * n + (e - ex)] = (ldsb_at(g, w * rpw + q, e) & kRowMask) * (uint32_t)(eb / 8);
+                        int k = 0;
+                        for (int ph = 0; ph < (eb == 16 ? 2 : 1); ++ph) {
+                            for (int32_t e = ex; e < ey && r >= 0; ++e) {
+                                const uint32_t o = (ldsb_at(g, w * rpw + q, e) & kRowMask) * (uint32_t)(eb / 8);
+                                if (eb == 16 && (int)((o >> 1) & 1u) != ph) continue;
+                                words[q * n + k++] = o;
+                            }
+                            if (ph == 0) even |= (uint32_t)k << (4 * q);
+                        }
                     }
+                    uint32_t *sm = &lin_smem[(size_t)((b * kGroupRows + w) * kLinSmemWords)];
+                    sm[kLinSmemWords - 2] = even;
+                    sm[kLinSmemWords - 1] = (uint32_t)n;
                 }
-                for (int w = 0; w < kGroupRows; ++w)
-                    lin_smem[(size_t)((b * kGroupRows + w) * kLinSmemWords + kLinSmemWords - 1)] = (uint32_t)n;
                 // copy chunks of the batch's windows for a full tile, dealt to the waves in turn
                 int32_t j = 0;
                 for (int32_t si = bz; si < bw; ++si) {
                     const int32_t srow = slots[4 * (size_t)si], lo = slots[4 * (size_t)si + 1];
                     const int32_t span = slots[4 * (size_t)si + 2], lofs = slots[4 * (size_t)si + 3];
                     const int32_t head = lo % epd;
-                    const int64_t units = ((int64_t)head + span + kLinTile + epd - 1) / epd;
+                    const int64_t units = ((int64_t)head + span + tile + epd - 1) / epd;
                     const int64_t unit0 = ((int64_t)srow * src_pitch + lo - head) / epd;
                     const int64_t lds0 = (int64_t)(lofs - head) * (eb / 8);
                     for (int64_t u0 = 0; u0 < units; u0 += 64, ++j) {
@@ -325,7 +338,6 @@ bool build_group_lds(const PlanImpl &p, Stage &S, int variant)
                         const int64_t nu = std::min<int64_t>(64, units - u0);
                         uint32_t *sm = &lin_smem[(size_t)((b * kGroupRows + w) * kLinSmemWords)];
                         sm[0] = (uint32_t)(c + 1);
-                        sm[kLinSmemWords - 1] = (uint32_t)(ey - ex);
                         sm[1 + c] = (uint32_t)(unit0 + u0);
                         sm[1 + kLinMaxChunks + c] = (uint32_t)(lds0 + 16 * u0);
                         sm[1 + 2 * kLinMaxChunks + c] = (uint32_t)nu;

@@ -66,11 +66,13 @@ struct Stage {
                                     // closes << 24 (general kernel) or LDS byte offset (specialised kernel)
     std::vector<int32_t> node_closes;  // specialised kernel: levels completed by each level-1 node
     // Linear kernel (float mode: the final stage is one sum over its inputs, no activation).  Per
-    // (global batch index, wave): kLinWords offset words, copied to LDS with the batch: word
-    // q * n + i is the LDS byte offset of the first sample of input i of the wave's row q (n the
-    // batch's inputs); and kLinSmemWords words read as scalars: the number of copy chunks of the
-    // wave, then for its chunks (global -> LDS copies of up to 64 16-byte units) the source unit
-    // index from the plane start, the LDS byte offset and the unit count, and last n.
+    // (global batch index, wave): kLinWords offset words, copied to LDS with the batch: words
+    // q * n .. q * n + n - 1 are the LDS byte offsets of the first samples of the n inputs of the
+    // wave's row q (16-bit rows: those that start a dword first, each part in plan order); and
+    // kLinSmemWords words read as scalars: the number of copy chunks of the wave, then for its
+    // chunks (global -> LDS copies of up to 64 16-byte units) the source unit index from the
+    // plane start, the LDS byte offset and the unit count, then (16-bit rows) the count of each
+    // row's inputs that start a dword (4 bits per row), and last n.
     bool group_lin = false;
     std::vector<uint32_t> lin;
     std::vector<uint32_t> lin_smem;
@@ -104,13 +106,17 @@ constexpr int kFastBuffers = 2;           // batch b + 1 lands while b is read
 constexpr int kGroupFastLdsBytes = 81920; // per buffer (two fill the 160 KB of LDS)
 constexpr int kGroupTileBits = 2048;  // bit rows: 32 samples (one word) per lane
 // Linear kernel: each wave sums kLinRows DM rows (128 DM-adjacent rows per workgroup share the
-// staged windows); lane i owns tile samples i + 64 v, v = 0 .. 7.
+// staged windows) over tiles of 512 samples: f32 rows, lane i owns samples i + 64 v
+// (v = 0 .. 7); 16-bit rows, lane i owns the sample pairs 2 i + 128 v (v = 0 .. 3), and an input
+// that starts in the upper half of a dword reads one dword past the tile, so those windows
+// stage one 16-byte unit more.
 constexpr int kLinRows = 8;
 constexpr int kLinTile = 512;                  // output samples per workgroup tile
+inline int lin_cover(int src_dtype) { return src_dtype == SND_DT_F32 ? kLinTile : kLinTile + 8; }
 constexpr int kLinMaxBatchEntries = 64 / kLinRows;  // the wave's offset words fit 64 lanes
 constexpr int kLinWords = 64;                  // offset words per (batch, wave)
 constexpr int kLinMaxChunks = 7;               // copy chunks per (batch, wave)
-constexpr int kLinSmemWords = 24;              // chunk count, 7 units, 7 LDS offsets, 7 lengths, entries
+constexpr int kLinSmemWords = 24;              // chunk count, 7 units, 7 LDS offsets, 7 lengths, counts, n
 #ifndef SND_LIN_BUFFERS
 #define SND_LIN_BUFFERS 2
 #endif

@@ -81,7 +81,9 @@ def test_config2_plan_shape(snd):
     assert g8.info["stage_kernel"] == ["anchored", "group_fast"]  # byte windows: an 8-input node fits a batch
     h8 = snd.Plan(spec.freqs, spec.dms, spec.tsamp_s, spec.nsamp, mode="float", branching=8, node_dtype="bf16",
                   in_dtype="bf16")
-    assert h8.info["stage_kernel"] == ["anchored", "group_fast"]  # 16-bit windows of an 8-input node fit too
+    assert h8.info["stage_kernel"] == ["anchored", "group_lin"]  # 16-bit float rows are one sum too
+    h4 = snd.Plan(spec.freqs, spec.dms, spec.tsamp_s, spec.nsamp, mode="float", branching=4, node_dtype="f16")
+    assert h4.info["stage_kernel"] == ["anchored", "group_lin"]
     # a ragged tree (1000 channels: the last leaf and node groups are short) has irregular
     # level-1 nodes and takes the general row-group kernel in the activated modes
     rag = snd.Plan(synth.channel_freqs(1000), synth.dm_linear(512, 0, 500), spec.tsamp_s, 20000, mode="graded",

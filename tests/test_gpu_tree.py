@@ -144,6 +144,28 @@ def test_float_small_integer_input_is_exact(snd, orc):
     assert rel_rms(gpu_run(pn, x), wn) <= FP32_TOL
 
 
+@pytest.mark.parametrize("node,B", [("f32", 4), ("bf16", 4), ("f16", 4), ("bf16", 8), ("f16", 3)])
+def test_float_storage_small_integers_exact(snd, orc, node, B):
+    """Small-integer float input (levels -3..4): leaf sums (|v| <= 16) are exact in bf16 and f16
+    and the roots exact in FP32, so every storage type must reproduce the FP64 oracle bit for bit.  300 DMs
+    fill three 128-row groups of the one-sum final stage (the last one partly), and 2600 output
+    samples make five full 512-sample tiles and a ragged one; random DMs give inputs of both
+    dword phases on 16-bit rows."""
+    rng, f, dms, _ = _case(96, 300, 11 + B)
+    d = orc.delays(f, dms, 0.138e-3)
+    x = (synth.random_levels(rng, 96, int(d.max()) + 2600, 7).astype(np.float32) - 3.0)
+    want, _ = orc.snd_dedup(x, f, d, mode="float", cluster=4, branching=B)
+    p = snd.Plan(f, dms, 0.138e-3, x.shape[1], mode="float", branching=B, node_dtype=node)
+    assert p.info["stage_kernel"] == ["anchored", "group_lin"], p.info["stage_kernel"]
+    _say(f"small integers node={node} B={B} n_out={p.n_out}")
+    assert p.n_out == x.shape[1] - int(d.max())
+    y = gpu_run(p, x)
+    assert np.array_equal(y, want.astype(np.float32))
+    # the same leaf plane through the generic kernels
+    pg = snd.Plan(f, dms, 0.138e-3, x.shape[1], mode="float", branching=B, node_dtype=node, generic_kernels=True)
+    assert np.array_equal(gpu_run(pg, x), y)
+
+
 def test_encoder_parity(snd, orc):
     spec = synth.workload(1)
     z = spec.filterbank()
