@@ -30,7 +30,7 @@ METRIC = "dedispersed DM\u00d7time samples/s (1024 ch, 4096 DM) + %HBM peak; p99
 LDS_PEAK_GBS = 256 * 256 * 2.4
 KERNEL_SYMBOL = {"generic": "k_stage", "group_lds": "k_group", "anchored": "k_anchored", "group_fast": "k_group_fast",
                  "group_bits": "k_group_bits", "anchored_bits": "k_anchored_bits",
-                 "group_lin": "k_group_lin"}
+                 "group_lin": "k_group_lin", "group_pack": "k_group_pack"}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic.json")
 
 

@@ -138,7 +138,9 @@ typedef struct {
                                                2 input-anchored, 3 LDS row groups specialised for
                                                regular level-1 nodes, 4 the same on bit rows,
                                                5 input-anchored on bit input, 6 LDS row groups
-                                               summing float-mode rows as one sum each */
+                                               summing float-mode rows as one sum each, 7 LDS
+                                               row groups forming graded levels on packed
+                                               16-bit counts */
     int64_t stage_staged[SND_MAX_LEVELS];   /* LDS row groups: source elements staged per time
                                                tile summed over groups (0 otherwise) */
     int64_t stage_batches[SND_MAX_LEVELS];  /* LDS row groups: batches summed over groups */

@@ -18,7 +18,7 @@ BUILD = os.path.join(HERE, "_build")
 
 HIP_SOURCES = ["kernels.hip", "kernels_lds.hip", "kernels_fast_binary.hip", "kernels_fast_graded.hip",
                "kernels_fast_float.hip", "kernels_bits.hip", "detect.hip", "label.hip",
-               "detect_noalloc.hip", "group_lin.hip"]
+               "detect_noalloc.hip", "group_lin.hip", "group_pack.hip"]
 CXX_SOURCES = ["plan.cpp", "capi.cpp", "detect_host.cpp", "stream_host.cpp", "batch_host.cpp", "tune_host.cpp",
                "multirate_host.cpp", "validate_host.cpp", "fdmt_host.cpp"]
 

@@ -145,6 +145,7 @@ __device__ inline void stage_barrier()
 int launch_group_bits(const GroupArgs &a, int64_t n_out, int lds, void *stream, const Multi &m, int64_t nblocks);
 int launch_group_lin(int src_dt, const GroupArgs &a, int64_t n_out, int lds, void *stream, const Multi &m,
                      int64_t nblocks);
+int launch_group_pack(const GroupArgs &a, int64_t n_out, int lds, void *stream, const Multi &m, int64_t nblocks);
 int launch_anchored_bits(const AnchorArgs &a, int64_t ntiles, int lds, void *stream, const Multi &m);
 int launch_group_fast_binary(int src_dt, int dst_dt, const GroupArgs &a, int64_t n_out, int lds, void *stream,
                              const Multi &m, int64_t nblocks);

@@ -17,7 +17,7 @@
 // exact sum that differs from the tree's, within the float tolerance of the FP64 definition.
 #include <hip/hip_runtime.h>
 
-#include "group_common.h"
+#include "group_tab.h"
 
 namespace snd {
 
@@ -25,20 +25,39 @@ namespace {
 
 constexpr int R = kLinRows;
 
-// The sums of a wave live in a plain array of the kernel, `st`, which the policies below index
-// (a struct holding them ended up in scratch memory).
+// The policies below index the sums of a wave in a plain array of the pipeline (a struct
+// holding them ended up in scratch memory).
 //
 // f32 rows: st[q * V + v] is sample lane + 64 v of row q.
-struct LinF32 {
+// Interface shared with the linear 16-bit sums: input and output element types, rows per wave,
+// tile, words per (batch, wave), the batch's inputs n (and the 16-bit dword-phase counts) as
+// per-batch scalars.
+struct LinBase {
+    using A = float;
+    using TO = float;
+    static constexpr int kRows = R, kStep = kLinTile, kWords = kLinWords, kSmemWords = kLinSmemWords;
+    struct Carry {
+        int n;
+        uint32_t even;
+    };
+    static __device__ __forceinline__ Carry carry(const uint32_t (&blk)[kLinSmemWords])
+    {
+        return Carry{(int)blk[kLinSmemWords - 1], blk[kLinSmemWords - 2]};
+    }
+};
+
+struct LinF32 : LinBase {
     using TI = float;
-    static constexpr int kStep = kLinTile;
     static constexpr int V = kLinTile / 64;
     static constexpr int kState = R * V;
 
-    // the n inputs of every row of the wave from the batch at buf; vw: the wave's offset words
-    static __device__ __forceinline__ void add_batch(float (&st)[kState], const unsigned char *buf, int lane,
-                                                     uint32_t vw, int n, uint32_t)
+    // the n inputs of every row of the wave from the batch at buf; the lane's offset word at w
+    static __device__ __forceinline__ void add_batch(float (&st)[kState], const unsigned char *buf,
+                                                     const unsigned char *w, int lane, const Carry &c,
+                                                     const GroupArgs &)
     {
+        const uint32_t vw = *reinterpret_cast<const uint32_t *>(w);
+        const int n = c.n;
         const unsigned char *lane_base = buf + 4 * lane;
         for (int i = 0; i < n; ++i) {
 #pragma unroll
@@ -59,12 +78,12 @@ struct LinF32 {
         }
     }
     static __device__ __forceinline__ void store(const float (&st)[kState], int q, float *drow, int lane, int vt,
-                                                 float scale)
+                                                 const GroupArgs &s)
     {
         auto d = as_global(drow);
 #pragma unroll
         for (int v = 0; v < V; ++v)
-            if (lane + 64 * v < vt) d[lane + 64 * v] = st[q * V + v] * scale;
+            if (lane + 64 * v < vt) d[lane + 64 * v] = st[q * V + v] * s.scale;
     }
 };
 
@@ -74,9 +93,8 @@ struct LinF32 {
 // that dword and the lower half of the next (two reads per pair).  The plan lists each row's
 // inputs of the first kind first.
 template <bool F16>
-struct Lin16 {
+struct Lin16 : LinBase {
     using TI = uint16_t;
-    static constexpr int kStep = kLinTile;
     static constexpr int V = kLinTile / 128;
     static constexpr int LO = 0, HI = R * V, kState = 2 * R * V;
 
@@ -92,9 +110,13 @@ struct Lin16 {
     }
     // Row q's inputs that start a dword (the first even_q of its n words), then the others: two
     // loops per row without a branch per input, two inputs in flight.
-    static __device__ __forceinline__ void add_batch(float (&st)[kState], const unsigned char *buf, int lane,
-                                                     uint32_t vw, int n, uint32_t even)
+    static __device__ __forceinline__ void add_batch(float (&st)[kState], const unsigned char *buf,
+                                                     const unsigned char *w, int lane, const Carry &c,
+                                                     const GroupArgs &)
     {
+        const uint32_t vw = *reinterpret_cast<const uint32_t *>(w);
+        const int n = c.n;
+        const uint32_t even = c.even;
         const unsigned char *lane_base = buf + 4 * lane;
 #pragma unroll
         for (int q = 0; q < R; ++q) {
@@ -149,8 +171,9 @@ struct Lin16 {
         }
     }
     static __device__ __forceinline__ void store(const float (&st)[kState], int q, float *drow, int lane, int vt,
-                                                 float scale)
+                                                 const GroupArgs &s)
     {
+        const float scale = s.scale;
         auto d = as_global(drow);
         const bool vec = (reinterpret_cast<uintptr_t>(drow) & 7u) == 0;
 #pragma unroll
@@ -173,104 +196,7 @@ struct Lin16 {
 template <class Sum>
 __global__ __launch_bounds__(1024) void k_group_lin(GroupArgs s0, Multi m)
 {
-    using TI = typename Sum::TI;
-    constexpr int ES = (int)sizeof(TI);
-    GroupArgs s;
-    uint32_t bid, nblk;
-    select_record(s0, m, s, bid, nblk);
-    constexpr int T = Sum::kStep;
-    extern __shared__ __align__(16) unsigned char smem[];
-    const int tid = threadIdx.x, lane = tid & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    // logical tile = time tile * ngroups + DM group, dealt so that the XCDs share time tiles
-    const uint32_t L = xcd_remap_chunked(bid, nblk, (uint32_t)(s.ngroups >= 8 ? s.ngroups / 8 : 1));
-    const int g = (int)(L % (uint32_t)s.ngroups);
-    const int t0 = (int)(L / (uint32_t)s.ngroups) * T;
-    const int vt = s.n_out - t0 < T ? s.n_out - t0 : T;
-    int row[R];
-#pragma unroll
-    for (int q = 0; q < R; ++q)
-        row[q] = __builtin_amdgcn_readfirstlane(as_const(s.grp_rows)[(g * kGroupRows + wave) * R + q]);
-    const unsigned char *srcb = static_cast<const unsigned char *>(s.src);
-    const_ptr<int32_t> batches = as_const(s.batches);
-    const_ptr<int32_t> instrs = as_const(s.instrs);
-    const int64_t pitch_bytes = s.src_pitch * (int64_t)ES;
-    const int buf_bytes = s.buf_elems * ES;
-    static_assert(kLinBuffers == 2, "the table words below are loaded one batch ahead of a double buffer");
-    const int stride = buf_bytes + kLinWordBytes;  // bytes of one buffer: windows, then offset words
-    const bool full = vt == T;  // full tiles copy from the chunk table; the last tile by window
-
-    float st[Sum::kState];
-#pragma unroll
-    for (int i = 0; i < Sum::kState; ++i) st[i] = 0.0f;
-
-    const_ptr<uint32_t> smem_tab = as_const(s.lin_smem);
-    // this lane's 16-byte unit of the tile's first sample (t0 is a multiple of the unit's
-    // samples); chunk sources add their unit index
-    const uint4 *tile_src = reinterpret_cast<const uint4 *>(srcb) + (uint32_t)(t0 * ES) / 16u + lane;
-    // Copies of batch bb into buffer j: this wave's chunks of its windows (scalar words blk), or
-    // its windows one by one in the last tile, and the wave's offset words.
-    auto issue = [&](int bb, const uint32_t (&blk)[kLinSmemWords], int j) {
-        unsigned char *buf_base = smem + j * stride;
-        if (full) {
-            const int nch = (int)blk[0];
-#pragma unroll
-            for (int c = 0; c < kLinMaxChunks; ++c) {
-                if (c >= nch) break;
-                const uint4 *gp = tile_src + blk[1 + c];
-                auto lp = (__attribute__((address_space(3))) void *)(buf_base + blk[1 + kLinMaxChunks + c]);
-                if (lane < (int)blk[1 + 2 * kLinMaxChunks + c]) __builtin_amdgcn_global_load_lds(gp, lp, 16, 0, 0);
-            }
-        } else {
-            issue_batch<TI>(batches, instrs, bb, wave, lane, srcb, pitch_bytes, t0, vt,
-                            reinterpret_cast<TI *>(buf_base));
-        }
-        const uint32_t *wp = s.lin + ((int64_t)bb * kGroupRows + wave) * kLinWords + lane;
-        __builtin_amdgcn_global_load_lds(wp, (__attribute__((address_space(3))) void *)(buf_base + buf_bytes + 256 * wave),
-                                         4, 0, 0);
-    };
-    auto load_blk = [&](int bb, uint32_t (&blk)[kLinSmemWords]) {
-        const_ptr<uint32_t> p = smem_tab + ((int64_t)bb * kGroupRows + wave) * kLinSmemWords;
-#pragma unroll
-        for (int i = 0; i < kLinSmemWords; ++i) blk[i] = p[i];
-    };
-
-    const int b0 = as_const(s.batch_ptr)[g], b1 = as_const(s.batch_ptr)[g + 1];
-    uint32_t blk[kLinSmemWords];
-    int n_cur = 0;
-    uint32_t e_cur = 0;
-    if (b0 < b1) {
-        load_blk(b0, blk);
-        issue(b0, blk, 0);
-        n_cur = (int)blk[kLinSmemWords - 1];
-        e_cur = blk[kLinSmemWords - 2];
-    }
-    int slot = 0;
-    for (int b = b0; b < b1; ++b) {
-        // the scalar words of batch b + 1 load while this wave waits for its copies and the barrier
-        if (b + 1 < b1) load_blk(b + 1, blk);
-        __builtin_amdgcn_s_waitcnt(0x0f70);  // vmcnt(0): this wave's copies of batch b have landed
-        stage_barrier();  // everyone's have; everyone is done reading batch b - 1
-        int n_nxt = 0;
-        uint32_t e_nxt = 0;
-        if (b + 1 < b1) {  // into the buffer of batch b - 1
-            issue(b + 1, blk, slot ^ 1);
-            n_nxt = (int)blk[kLinSmemWords - 1];
-            e_nxt = blk[kLinSmemWords - 2];
-        }
-        const unsigned char *buf_base = smem + slot * stride;
-        const uint32_t vw = *reinterpret_cast<const uint32_t *>(buf_base + buf_bytes + 256 * wave + 4 * lane);
-        Sum::add_batch(st, buf_base, lane, vw, n_cur, e_cur);
-        n_cur = n_nxt;
-        e_cur = e_nxt;
-        slot ^= 1;
-    }
-
-#pragma unroll
-    for (int q = 0; q < R; ++q) {
-        if (row[q] < 0) continue;
-        Sum::store(st, q, static_cast<float *>(s.dst) + (int64_t)row[q] * s.dst_pitch + t0, lane, vt, s.scale);
-    }
+    group_tab_body<Sum>(s0, m);
 }
 
 namespace {

@@ -1,0 +1,173 @@
+// Final stage of a graded-mode plan on u8 rows with regular level-1 nodes (Methods, "Tree
+// activation modes": every node's output is the sum of its inputs clipped at the cap, at every
+// level up to the root).
+//
+// Staging is the table pipeline of the one-sum float kernel (group_tab.h).  Each wave computes
+// four DM rows (64 DM-adjacent rows per workgroup) over a tile of 512 samples; lane i owns
+// samples 4 i + 256 v (v = 0, 1).  An input at LDS byte offset o is read as the two aligned
+// dwords that hold its four samples for the lane (one ds_read2_b32), and one byte permute per
+// pair picks them out as two 16-bit counts: (samples 0, 2) and (samples 1, 3), whichever byte of
+// the dword the input starts at.  Level sums are then formed two samples per instruction with
+// 32-bit adds (fan-in x cap < 2^16, so the halves never carry into each other) and clipped with
+// a packed 16-bit minimum; levels 2 .. D close with compile-time control as the plan's closing
+// counts say.  Integer arithmetic in the tree's own order: the result is the tree's, bit for bit.
+#include <hip/hip_runtime.h>
+
+#include "group_tab.h"
+
+namespace snd {
+
+namespace {
+
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+
+__device__ inline uint32_t pk_min_u16(uint32_t a, uint32_t b)
+{
+    return __builtin_bit_cast(uint32_t, __builtin_elementwise_min(__builtin_bit_cast(u16x2, a),
+                                                                   __builtin_bit_cast(u16x2, b)));
+}
+
+// st[(j * R + q) * K + k]: j = 0 .. D - 2 the open partial sums of levels 2 .. D, j = D - 1 the
+// root; k = 2 v + h holds samples (h, h + 2) of the lane's four in block v.
+template <int F1, int D>
+struct PackGraded {
+    using TI = uint8_t;
+    using TO = uint8_t;
+    using A = uint32_t;
+    static constexpr int kRows = kPackRows, kStep = kLinTile, kWords = kPackWords, kSmemWords = kPackSmemWords;
+    static constexpr int R = kRows, V = kLinTile / 256, K = 2 * V;
+    static constexpr int OUT = D - 1;  // slot of the root
+    static constexpr int kState = D * R * K;
+    struct Carry {
+        uint32_t close0, close1;  // levels completed by each level-1 node, 4 bits per node
+        int n;
+    };
+    static __device__ __forceinline__ Carry carry(const uint32_t (&blk)[kPackSmemWords])
+    {
+        return Carry{blk[22], blk[23], (int)blk[kPackSmemWords - 1]};
+    }
+    static __device__ __forceinline__ A &at(A (&st)[kState], int j, int q, int k) { return st[(j * R + q) * K + k]; }
+
+    // close levels J .. D after a node that completes c levels (closing level j implies every
+    // level below it)
+    template <int J>
+    static __device__ __forceinline__ void close_from(A (&st)[kState], int c, uint32_t cap2)
+    {
+        if constexpr (J <= D) {
+            if (c >= J) {
+#pragma unroll
+                for (int q = 0; q < R; ++q)
+#pragma unroll
+                    for (int k = 0; k < K; ++k) {
+                        const uint32_t y = pk_min_u16(at(st, J - 2, q, k), cap2);
+                        at(st, J - 2, q, k) = 0;
+                        if constexpr (J == D) at(st, OUT, q, k) = y;
+                        else at(st, J - 1, q, k) += y;
+                    }
+                close_from<J + 1>(st, c, cap2);
+            }
+        }
+    }
+
+    // the level-1 nodes of one batch: for each, its F1 inputs per row, then the closes
+    static __device__ __forceinline__ void add_batch(A (&st)[kState], const unsigned char *buf, const unsigned char *w,
+                                                     int lane, const Carry &cr, const GroupArgs &s)
+    {
+        const uint4 w4 = *reinterpret_cast<const uint4 *>(w);  // component q: row q's input `lane`
+        const uint32_t wq[4] = {w4.x, w4.y, w4.z, w4.w};
+        const uint32_t cap2 = (uint32_t)s.cap * 0x00010001u;
+        const unsigned char *lane_base = buf + 4 * lane;
+        const int nn = cr.n / F1;
+        for (int j = 0; j < nn; ++j) {
+            const int c = (int)(((j < 8 ? cr.close0 : cr.close1) >> (4 * (j & 7))) & 15u);
+#pragma unroll
+            for (int q = 0; q < R; ++q) {
+                uint32_t a[K];
+#pragma unroll
+                for (int u = 0; u < F1; ++u) {
+                    const uint32_t o = (uint32_t)__builtin_amdgcn_readlane((int)wq[q], j * F1 + u);
+                    // byte selector of samples (0, 2) of the input from the dword pair; +0x00010001
+                    // gives samples (1, 3); 0x0c fills a zero byte
+                    const uint32_t sel = 0x0c020c00u + (o & 3u) * 0x00010001u;
+                    const uint32_t *p = reinterpret_cast<const uint32_t *>(lane_base + (o & ~3u));
+#pragma unroll
+                    for (int v = 0; v < V; ++v) {
+                        const uint32_t d0 = p[64 * v], d1 = p[64 * v + 1];
+                        const uint32_t e = __builtin_amdgcn_perm(d1, d0, sel);
+                        const uint32_t f = __builtin_amdgcn_perm(d1, d0, sel + 0x00010001u);
+                        if (u == 0) {
+                            a[2 * v] = e;
+                            a[2 * v + 1] = f;
+                        } else {
+                            a[2 * v] += e;
+                            a[2 * v + 1] += f;
+                        }
+                    }
+                }
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    const uint32_t y = pk_min_u16(a[k], cap2);
+                    if constexpr (D == 1) at(st, OUT, q, k) = y;
+                    else at(st, 0, q, k) += y;
+                }
+            }
+            close_from<2>(st, c, cap2);
+        }
+    }
+
+    // root counts (<= cap <= 255) back to bytes: (s0, s2) | (s1, s3) << 8
+    static __device__ __forceinline__ void store(const A (&st)[kState], int q, uint8_t *drow, int lane, int vt,
+                                                 const GroupArgs &)
+    {
+        auto d = as_global(drow);
+        const bool vec = (reinterpret_cast<uintptr_t>(drow) & 3u) == 0;
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            const uint32_t x = st[(OUT * R + q) * K + 2 * v] | (st[(OUT * R + q) * K + 2 * v + 1] << 8);
+            const int t = 4 * lane + 256 * v;
+            if (vec && t + 4 <= vt) {
+                *reinterpret_cast<__attribute__((address_space(1))) uint32_t *>(d + t) = x;
+            } else {
+#pragma unroll
+                for (int b = 0; b < 4; ++b)
+                    if (t + b < vt) d[t + b] = (uint8_t)(x >> (8 * b));
+            }
+        }
+    }
+};
+
+}  // namespace
+
+template <int F1, int D>
+__global__ __launch_bounds__(1024) void k_group_pack(GroupArgs s0, Multi m)
+{
+    group_tab_body<PackGraded<F1, D>>(s0, m);
+}
+
+namespace {
+
+template <int F1, int D>
+int launch_pack(const GroupArgs &a, int64_t n_out, int lds, void *stream, const Multi &m, int64_t nb_multi)
+{
+    const int64_t ntt = (n_out + kLinTile - 1) / kLinTile;
+    const int64_t nb = m.n > 0 ? nb_multi : (int64_t)a.ngroups * ntt;
+    if (nb <= 0) return 0;
+    if (nb > 0x7fffffffLL) return (int)hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_group_pack<F1, D>), dim3((uint32_t)nb), dim3(1024), lds, (hipStream_t)stream, a, m);
+    return (int)hipGetLastError();
+}
+
+}  // namespace
+
+// Every (inputs per level-1 node, depth) pair the plan builder admits for this kernel.
+int launch_group_pack(const GroupArgs &a, int64_t n_out, int lds, void *stream, const Multi &m, int64_t nblocks)
+{
+#define SND_PACK(F, DD) \
+    if (a.f1 == F && a.depth == DD) return launch_pack<F, DD>(a, n_out, lds, stream, m, nblocks);
+    SND_PACK(4, 1) SND_PACK(4, 2) SND_PACK(4, 3) SND_PACK(4, 4) SND_PACK(4, 5)
+    SND_PACK(8, 1) SND_PACK(8, 2) SND_PACK(8, 3) SND_PACK(8, 4)
+#undef SND_PACK
+    return (int)hipErrorInvalidValue;
+}
+
+}  // namespace snd

@@ -367,6 +367,10 @@ int launch_group(int mode, int src_dt, int dst_dt, const GroupArgs &a, int64_t n
         if (mode != SND_MODE_BINARY || dst_dt != SND_DT_U8 || a.f1 <= 0) return (int)hipErrorInvalidValue;
         return launch_group_bits(a, n_out, lds_bytes, stream, m, nblocks);
     }
+    if (a.lin_kernel == 2) {
+        if (mode != SND_MODE_GRADED || src_dt != SND_DT_U8 || dst_dt != SND_DT_U8) return (int)hipErrorInvalidValue;
+        return launch_group_pack(a, n_out, lds_bytes, stream, m, nblocks);
+    }
     if (a.lin_kernel) {
         if (mode != SND_MODE_FLOAT || dst_dt != SND_DT_F32) return (int)hipErrorInvalidValue;
         return launch_group_lin(src_dt, a, n_out, lds_bytes, stream, m, nblocks);

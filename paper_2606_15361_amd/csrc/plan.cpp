@@ -105,18 +105,27 @@ bool valid_dtype_pair(int mode, int in_dt, int node_dt, int cap)
 // same tree, so all rows have the same entry count and closing pattern.  Returns false (and
 // leaves the stage on the generic kernel) when one entry alone does not fit the LDS budget.
 // Variants: kGroupGeneric (any tree), kGroupFast (regular level-1 nodes, compile-time depth),
-// kGroupLin (float mode: every row is one sum over its inputs, with no activation in between).
-enum { kGroupGeneric = 0, kGroupFast = 1, kGroupLin = 2 };
+// kGroupLin (float mode: every row is one sum over its inputs, with no activation in between),
+// kGroupPack (graded mode on u8 rows with regular level-1 nodes of 4 or 8 inputs: the linear
+// kernel's staging, levels formed on pairs of 16-bit counts).
+enum { kGroupGeneric = 0, kGroupFast = 1, kGroupLin = 2, kGroupPack = 3 };
 bool build_group_lds(const PlanImpl &p, Stage &S, int variant)
 {
-    const bool allow_fast = variant == kGroupFast;
+    const bool allow_fast = variant == kGroupFast || variant == kGroupPack;
     const bool lin = variant == kGroupLin;
-    // the linear kernel reads a materialised plane of f32, bf16 or f16 rows, whose pitch its copy
-    // table holds
+    const bool pack = variant == kGroupPack;
+    const bool tab = lin || pack;  // kernels that copy by chunk tables and read offset words from LDS
+    // these kernels read a materialised plane of f32, bf16 or f16 rows (linear) or u8 rows
+    // (packed), whose pitch their copy table holds; the packed kernel's 16-bit counts hold any
+    // level sum (fan-in x cap < 2^16)
     int64_t src_pitch = 0;
-    if (lin) {
+    if (tab) {
         const bool ok_src = S.src_dtype == SND_DT_F32 || S.src_dtype == SND_DT_BF16 || S.src_dtype == SND_DT_F16;
-        if (!(p.desc.mode == SND_MODE_FLOAT && ok_src && S.dst_dtype == SND_DT_F32) || S.src_level < 0) return false;
+        if (lin && !(p.desc.mode == SND_MODE_FLOAT && ok_src && S.dst_dtype == SND_DT_F32)) return false;
+        if (pack && !(p.desc.mode == SND_MODE_GRADED && S.src_dtype == SND_DT_U8 && S.dst_dtype == SND_DT_U8 &&
+                      p.desc.cap <= 255 && (int64_t)p.desc.branching * p.desc.cap < 65536))
+            return false;
+        if (S.src_level < 0) return false;
         for (const Stage &Q : p.stages)
             if (!Q.final_stage && Q.dst_level == S.src_level) src_pitch = Q.pitch;
         const int64_t epu = 16 / dtype_size(S.src_dtype);  // elements per 16-byte unit
@@ -147,17 +156,26 @@ bool build_group_lds(const PlanImpl &p, Stage &S, int variant)
             f1 = 0;
     }
     if (lin) f1 = 0;
+    if (pack && !((f1 == 4 && S.depth <= 5) || (f1 == 8 && S.depth <= 4))) return false;
     const bool bits = S.src_dtype == SND_DT_BITS;
     if (bits && !f1) return false;  // bit rows: specialised kernel only
     // samples a window holds beyond its span (its tile, plus one unit for the linear kernel on
     // 16-bit rows), and the tile step in time
-    const int tile = lin ? lin_cover(S.src_dtype) : bits ? kGroupTileBits : f1 ? kGroupTileFast : kGroupTile;
-    const int tile_step = lin ? kLinTile : tile;
-    const int rpw = lin ? kLinRows : f1 ? kFastRows : 1;  // rows per wave
+    const int tile = lin    ? lin_cover(S.src_dtype)
+                     : pack ? kPackCover
+                     : bits ? kGroupTileBits
+                     : f1   ? kGroupTileFast
+                            : kGroupTile;
+    const int tile_step = tab ? kLinTile : tile;
+    const int rpw = lin ? kLinRows : pack ? kPackRows : f1 ? kFastRows : 1;  // rows per wave
+    const int max_entries = lin ? kLinMaxBatchEntries : kPackMaxBatchEntries;  // table kernels
+    const int n_words = lin ? kLinWords : kPackWords;
+    const int n_smem = lin ? kLinSmemWords : kPackSmemWords;
     const int gr = kGroupRows * rpw;     // rows per group
     const int unit = f1 ? f1 : 1;  // batches end on level-1 node boundaries
     const int eb = bits ? 1 : 8 * dtype_size(S.src_dtype);  // bits per element
-    const int64_t budget = (int64_t)(lin ? kLinLdsBytes : f1 ? kGroupFastLdsBytes : kGroupLdsBytes) * 8 / eb;
+    const int64_t budget =
+        (int64_t)(lin ? kLinLdsBytes : pack ? kPackLdsBytes : f1 ? kGroupFastLdsBytes : kGroupLdsBytes) * 8 / eb;
     const int32_t epd = 128 / eb;  // elements per 16-byte copy unit
     // LDS elements of one window: its span plus one tile, from a 16-byte boundary, whole units
     // (bit rows: one more unit, since a lane reads the word after its 32 samples too)
@@ -187,7 +205,7 @@ bool build_group_lds(const PlanImpl &p, Stage &S, int variant)
     std::vector<int32_t> slot_of(gr);
     std::vector<Src> unit_srcs;
     std::vector<int32_t> unit_nsrc;
-    // linear kernel: copy chunks of the open batch
+    // table kernels: copy chunks of the open batch
     int32_t batch_chunks = 0;
     auto lin_chunks = [&](const Src &s) {  // 64-unit copies of one window in a full tile
         const int64_t units = ((int64_t)(s.lo % epd) + (s.hi - s.lo) + tile + epd - 1) / epd;
@@ -230,10 +248,10 @@ bool build_group_lds(const PlanImpl &p, Stage &S, int variant)
         const int32_t nslot_batch = (int32_t)(slots.size() / 4) - s0;
         bool lin_full = false;
         int32_t unit_chunks = 0;
-        if (lin) {  // the batch's entries or the waves' copy chunks would overflow
+        if (tab) {  // the batch's entries or the waves' copy chunks would overflow
             for (const Src &s : unit_srcs) unit_chunks += lin_chunks(s);
             if (unit_chunks > kGroupRows * kLinMaxChunks) return false;
-            lin_full = batch_chunks + unit_chunks > kGroupRows * kLinMaxChunks || eu - e0 >= kLinMaxBatchEntries;
+            lin_full = batch_chunks + unit_chunks > kGroupRows * kLinMaxChunks || eu - e0 + unit > max_entries;
         }
         if (elems + need > budget || nslot_batch + (int32_t)unit_srcs.size() > max_slots || lin_full) {
             // close the batch
@@ -292,20 +310,35 @@ bool build_group_lds(const PlanImpl &p, Stage &S, int variant)
     }
     std::vector<uint32_t> lin_tab, lin_smem;
     static_assert(kLinMaxBatchEntries <= 15, "per-row input counts are packed in 4 bits");
-    if (lin) {
-        // linear kernel: per (batch, wave) the offset words of the wave's rows, and its copy
-        // chunks as scalar words
+    static_assert(kPackMaxBatchEntries / 4 <= 16 && kPackRows <= 4, "packed kernel: two closes words, 16-byte words");
+    if (tab) {
+        // per (batch, wave) the offset words of the wave's rows, and its copy chunks as scalar words
         const int64_t nb_all = (int64_t)(batches.size() / 4);
-        lin_tab.assign((size_t)(nb_all * kGroupRows * kLinWords), 0u);
-        lin_smem.assign((size_t)(nb_all * kGroupRows * kLinSmemWords), 0u);
+        lin_tab.assign((size_t)(nb_all * kGroupRows * n_words), 0u);
+        lin_smem.assign((size_t)(nb_all * kGroupRows * n_smem), 0u);
         for (int64_t g = 0; g < ng; ++g) {
             for (int32_t b = batch_ptr[(size_t)g]; b < batch_ptr[(size_t)g + 1]; ++b) {
                 const int32_t ex = batches[4 * (size_t)b], ey = batches[4 * (size_t)b + 1];
                 const int32_t bz = batches[4 * (size_t)b + 2], bw = batches[4 * (size_t)b + 3];
                 const int32_t n = ey - ex;
-                if (n > kLinMaxBatchEntries) return false;
+                if (n > max_entries) return false;
                 for (int w = 0; w < kGroupRows; ++w) {
-                    uint32_t *words = &lin_tab[(size_t)((b * kGroupRows + w) * kLinWords)];
+                    uint32_t *words = &lin_tab[(size_t)((b * kGroupRows + w) * n_words)];
+                    uint32_t *sm = &lin_smem[(size_t)((b * kGroupRows + w) * n_smem)];
+                    if (pack) {  // lane i, component q: input i of row q; then each node's closes
+                        for (int q = 0; q < kPackRows; ++q) {
+                            const int32_t r = grp_rows[(size_t)(g * gr + w * rpw + q)];
+                            for (int32_t e = ex; e < ey && r >= 0; ++e)
+                                words[4 * (e - ex) + q] = ldsb_at(g, w * rpw + q, e) & kRowMask;
+                        }
+                        for (int32_t k = 0; k < n / f1; ++k) {
+                            const uint32_t c = S.ent[ex + k * f1 + f1 - 1].rowc >> 24;
+                            if (c > 15) return false;
+                            sm[22 + k / 8] |= c << (4 * (k % 8));
+                        }
+                        sm[n_smem - 1] = (uint32_t)n;
+                        continue;
+                    }
                     uint32_t even = 0;  // 16-bit rows: inputs starting a dword first, counts per row
                     for (int q = 0; q < kLinRows; ++q) {
                         const int32_t r = grp_rows[(size_t)(g * gr + w * rpw + q)];
@@ -319,9 +352,8 @@ bool build_group_lds(const PlanImpl &p, Stage &S, int variant)
                             if (ph == 0) even |= (uint32_t)k << (4 * q);
                         }
                     }
-                    uint32_t *sm = &lin_smem[(size_t)((b * kGroupRows + w) * kLinSmemWords)];
-                    sm[kLinSmemWords - 2] = even;
-                    sm[kLinSmemWords - 1] = (uint32_t)n;
+                    sm[n_smem - 2] = even;
+                    sm[n_smem - 1] = (uint32_t)n;
                 }
                 // copy chunks of the batch's windows for a full tile, dealt to the waves in turn
                 int32_t j = 0;
@@ -336,7 +368,7 @@ bool build_group_lds(const PlanImpl &p, Stage &S, int variant)
                         const int w = j % kGroupRows, c = j / kGroupRows;
                         if (c >= kLinMaxChunks) return false;
                         const int64_t nu = std::min<int64_t>(64, units - u0);
-                        uint32_t *sm = &lin_smem[(size_t)((b * kGroupRows + w) * kLinSmemWords)];
+                        uint32_t *sm = &lin_smem[(size_t)((b * kGroupRows + w) * n_smem)];
                         sm[0] = (uint32_t)(c + 1);
                         sm[1 + c] = (uint32_t)(unit0 + u0);
                         sm[1 + kLinMaxChunks + c] = (uint32_t)(lds0 + 16 * u0);
@@ -353,11 +385,13 @@ bool build_group_lds(const PlanImpl &p, Stage &S, int variant)
     S.group_tile = tile_step;
     S.group_rpw = rpw;
     S.group_lin = lin;
+    S.group_pack = pack;
     const int64_t buf_bytes = round_up(max_elems * eb / 8, 16);
     S.lds_buf_elems = (int32_t)(buf_bytes * 8 / eb);
-    // general kernel: batches b+1, b+2 land while b is read; specialised kernel: b+1
-    S.lds_bytes = (int32_t)(lin ? kLinBuffers * (buf_bytes + kLinWordBytes)
-                                : (f1 ? kFastBuffers : kGroupBuffers) * buf_bytes);
+    // general kernel: batches b+1, b+2 land while b is read; the others: b+1
+    S.lds_bytes = (int32_t)(lin    ? kLinBuffers * (buf_bytes + kLinWordBytes)
+                            : pack ? 2 * (buf_bytes + kPackWordBytes)
+                                   : (f1 ? kFastBuffers : kGroupBuffers) * buf_bytes);
     S.grp_rows = std::move(grp_rows);
     S.batch_ptr = std::move(batch_ptr);
     S.batches = std::move(batches);
@@ -374,7 +408,7 @@ bool build_group_lds(const PlanImpl &p, Stage &S, int variant)
         S.node_closes.resize((size_t)(ne / f1));
         for (int32_t k = 0; k < ne / f1; ++k) S.node_closes[(size_t)k] = (int32_t)(S.ent[k * f1 + f1 - 1].rowc >> 24);
     }
-    if (lin) ldsb.clear();  // the linear kernel reads its own table
+    if (tab) ldsb.clear();  // the table kernels read their own tables
     S.ldsb = std::move(ldsb);
     S.lin = std::move(lin_tab);
     S.lin_smem = std::move(lin_smem);
@@ -721,8 +755,8 @@ snd_status build_plan(const snd_plan_desc &d, PlanImpl &p, std::string &err)
     for (Stage &S : p.stages) {
         S.kernel = kKernelGeneric;
         if (d.generic_kernels) continue;
-        if (S.final_stage && (build_group_lds(p, S, kGroupLin) || build_group_lds(p, S, kGroupFast) ||
-                              (!bits && build_group_lds(p, S, kGroupGeneric))))
+        if (S.final_stage && (build_group_lds(p, S, kGroupLin) || build_group_lds(p, S, kGroupPack) ||
+                              build_group_lds(p, S, kGroupFast) || (!bits && build_group_lds(p, S, kGroupGeneric))))
             continue;
         if (!S.final_stage && S.src_level < 0) build_anchored(p, S);
     }
@@ -820,7 +854,8 @@ snd_status build_plan(const snd_plan_desc &d, PlanImpl &p, std::string &err)
         I.stage_alg_bytes[si] = S.alg_bytes;
         I.stage_rows[si] = S.rows;
         I.stage_entries[si] = (int64_t)S.ent.size();
-        I.stage_kernel[si] = S.kernel == kKernelGroupLds && S.group_lin                    ? 6
+        I.stage_kernel[si] = S.kernel == kKernelGroupLds && S.group_pack                   ? 7
+                             : S.kernel == kKernelGroupLds && S.group_lin                  ? 6
                              : S.kernel == kKernelAnchored && S.src_dtype == SND_DT_BITS ? 5
                              : S.kernel == kKernelGroupLds && S.src_dtype == SND_DT_BITS ? 4
                              : (S.kernel == kKernelGroupLds && S.group_f1 > 0) ? 3

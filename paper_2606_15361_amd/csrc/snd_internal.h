@@ -72,8 +72,10 @@ struct Stage {
     // kLinSmemWords words read as scalars: the number of copy chunks of the wave, then for its
     // chunks (global -> LDS copies of up to 64 16-byte units) the source unit index from the
     // plane start, the LDS byte offset and the unit count, then (16-bit rows) the count of each
-    // row's inputs that start a dword (4 bits per row), and last n.
+    // row's inputs that start a dword (4 bits per row), and last n.  The packed kernel keeps its
+    // tables (kPackWords and kPackSmemWords per batch and wave) in the same two vectors.
     bool group_lin = false;
+    bool group_pack = false;
     std::vector<uint32_t> lin;
     std::vector<uint32_t> lin_smem;
     int64_t off_grp_rows = 0, off_batch_ptr = 0, off_batches = 0, off_instrs = 0, off_ldsb = 0;
@@ -117,12 +119,23 @@ constexpr int kLinMaxBatchEntries = 64 / kLinRows;  // the wave's offset words f
 constexpr int kLinWords = 64;                  // offset words per (batch, wave)
 constexpr int kLinMaxChunks = 7;               // copy chunks per (batch, wave)
 constexpr int kLinSmemWords = 24;              // chunk count, 7 units, 7 LDS offsets, 7 lengths, counts, n
-#ifndef SND_LIN_BUFFERS
-#define SND_LIN_BUFFERS 2
-#endif
-constexpr int kLinBuffers = SND_LIN_BUFFERS;    // LDS ring: batches b + 1 .. b + kLinBuffers - 1 land while b is read
+constexpr int kLinBuffers = 2;                 // batch b + 1 lands while b is read
 constexpr int kLinWordBytes = kGroupRows * kLinWords * 4;  // each buffer's copy of its batch's offset words
 constexpr int kLinLdsBytes = (163840 / kLinBuffers - kLinWordBytes) / 16 * 16;  // window bytes per buffer
+// Packed kernel (graded mode on u8 rows, regular level-1 nodes of 4 or 8 inputs): the staging
+// and copy tables of the linear kernel; each wave computes kPackRows DM rows (64-row groups),
+// lane i owns samples 4 i + 256 v (v = 0, 1) as two pairs of 16-bit counts, and reads each
+// input as two aligned dwords (its first four samples may start in either), so windows stage
+// one 16-byte unit beyond the tile.  Offset words: lane i, component q of a 16-byte word holds
+// input i of row q.  Scalar words: those of the linear kernel, then the levels each level-1
+// node of the batch completes (4 bits per node, two words), then n.
+constexpr int kPackRows = 4;
+constexpr int kPackCover = kLinTile + 16;
+constexpr int kPackMaxBatchEntries = 64;
+constexpr int kPackWords = 256;                // offset words per (batch, wave)
+constexpr int kPackSmemWords = 25;
+constexpr int kPackWordBytes = kGroupRows * kPackWords * 4;
+constexpr int kPackLdsBytes = (163840 / 2 - kPackWordBytes) / 16 * 16;
 inline bool group_fast_types(int mode, int src_dt, int dst_dt)
 {
     if (mode == SND_MODE_BINARY) return (src_dt == SND_DT_U8 || src_dt == SND_DT_BITS) && dst_dt == SND_DT_U8;
@@ -246,7 +259,7 @@ struct GroupArgs {
     const int32_t *node_closes;  // specialised kernel only
     const uint32_t *lin_smem;    // linear kernel only
     const uint32_t *lin;
-    int32_t lin_kernel;          // 1: linear kernel
+    int32_t lin_kernel;          // 1: linear kernel, 2: packed kernel
     int32_t ngroups;
     int32_t n_entries;
     int32_t buf_elems;
@@ -298,10 +311,11 @@ int launch_cast(const float *src, int64_t src_pitch, int64_t rows, int64_t cols,
 
 // Compile-time shape of the kernel instance that runs stage S: the depth class, or, for the
 // specialised row-group kernel, 1000 * (inputs per level-1 node) + depth; -1 for the linear
-// kernel.
+// kernel; minus the specialised shape for the packed kernel.
 inline int stage_shape(const Stage &S)
 {
     if (S.kernel == kKernelGroupLds && S.group_lin) return -1;
+    if (S.kernel == kKernelGroupLds && S.group_pack) return -(1000 * S.group_f1 + S.depth);
     if (S.kernel == kKernelGroupLds && S.group_f1 > 0) return 1000 * S.group_f1 + S.depth;
     return depth_bucket(S.depth);
 }

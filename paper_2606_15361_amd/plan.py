@@ -140,7 +140,7 @@ class Plan:
             stage_alg_bytes=list(info.stage_alg_bytes[:ns]), stage_rows=list(info.stage_rows[:ns]),
             stage_entries=list(info.stage_entries[:ns]), build_seconds=info.build_seconds,
             stage_kernel=[("generic", "group_lds", "anchored", "group_fast", "group_bits", "anchored_bits",
-                           "group_lin")[k]
+                           "group_lin", "group_pack")[k]
                           for k in info.stage_kernel[:ns]],
             stage_staged=list(info.stage_staged[:ns]), stage_batches=list(info.stage_batches[:ns]),
             stage_windows=list(info.stage_windows[:ns]),

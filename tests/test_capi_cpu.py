@@ -75,10 +75,17 @@ def test_config2_plan_shape(snd):
     assert p.info["stage_kernel"] == ["anchored", "group_lin"]
     b8 = snd.Plan(spec.freqs, spec.dms, spec.tsamp_s, spec.nsamp, mode="float", branching=8)
     assert b8.info["stage_kernel"] == ["anchored", "group_lin"]
+    # graded u8 rows with level-1 nodes of 4 or 8 inputs: levels on packed 16-bit counts
     pg = snd.Plan(spec.freqs, spec.dms, spec.tsamp_s, spec.nsamp, mode="graded", branching=4)
-    assert pg.info["stage_kernel"] == ["anchored", "group_fast"]
+    assert pg.info["stage_kernel"] == ["anchored", "group_pack"]
     g8 = snd.Plan(spec.freqs, spec.dms, spec.tsamp_s, spec.nsamp, mode="graded", branching=8)
-    assert g8.info["stage_kernel"] == ["anchored", "group_fast"]  # byte windows: an 8-input node fits a batch
+    assert g8.info["stage_kernel"] == ["anchored", "group_pack"]
+    g2 = snd.Plan(spec.freqs, spec.dms, spec.tsamp_s, spec.nsamp, mode="graded", branching=2)
+    assert g2.info["stage_kernel"] == ["anchored", "group_fast"]
+    g16 = snd.Plan(spec.freqs, spec.dms, spec.tsamp_s, spec.nsamp, mode="graded", branching=4, cap=4095)
+    assert g16.node_dtype == "u16" and g16.info["stage_kernel"] == ["anchored", "group_fast"]
+    pb = snd.Plan(spec.freqs, spec.dms, spec.tsamp_s, spec.nsamp, mode="binary", branching=4, node_dtype="u8")
+    assert pb.info["stage_kernel"] == ["anchored", "group_fast"]
     h8 = snd.Plan(spec.freqs, spec.dms, spec.tsamp_s, spec.nsamp, mode="float", branching=8, node_dtype="bf16",
                   in_dtype="bf16")
     assert h8.info["stage_kernel"] == ["anchored", "group_lin"]  # 16-bit float rows are one sum too

@@ -166,6 +166,26 @@ def test_float_storage_small_integers_exact(snd, orc, node, B):
     assert np.array_equal(gpu_run(pg, x), y)
 
 
+@pytest.mark.parametrize("nchan,B,cap,levels", [(1024, 4, 255, 4), (1024, 4, 3, 4), (256, 8, 255, 4),
+                                                (512, 8, 7, 6), (64, 4, 2, 2)])
+def test_graded_packed_levels_exact(snd, orc, nchan, B, cap, levels):
+    """Graded u8 rows with level-1 nodes of 4 or 8 inputs run the packed kernel (two 16-bit
+    counts per dword); small caps clip at every level.  Bit-exact against the oracle and the
+    generic kernels, over 300 DMs (five 64-row groups, the last partial) and a ragged sixth
+    512-sample tile."""
+    rng, f, dms, _ = _case(nchan, 300, 17 + B + cap)
+    d = orc.delays(f, dms, 0.138e-3)
+    x = synth.random_levels(rng, nchan, int(d.max()) + 2600, levels)
+    want, _ = orc.snd_dedup(x, f, d, mode="graded", cluster=4, branching=B, cap=cap)
+    p = snd.Plan(f, dms, 0.138e-3, x.shape[1], mode="graded", branching=B, cap=cap)
+    assert p.info["stage_kernel"] == ["anchored", "group_pack"], p.info["stage_kernel"]
+    _say(f"packed graded nchan={nchan} B={B} cap={cap} n_out={p.n_out}")
+    y = gpu_run(p, x)
+    assert np.array_equal(y, want.astype(y.dtype))
+    pg = snd.Plan(f, dms, 0.138e-3, x.shape[1], mode="graded", branching=B, cap=cap, generic_kernels=True)
+    assert np.array_equal(gpu_run(pg, x), y)
+
+
 def test_encoder_parity(snd, orc):
     spec = synth.workload(1)
     z = spec.filterbank()
