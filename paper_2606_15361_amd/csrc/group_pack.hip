@@ -38,6 +38,7 @@ struct PackGraded {
     static constexpr int R = kRows, V = kLinTile / 256, K = 2 * V;
     static constexpr int OUT = D - 1;  // slot of the root
     static constexpr int kState = D * R * K;
+    static_assert(F1 >= 3, "three-input adds");
     struct Carry {
         uint32_t close0, close1;  // levels completed by each level-1 node, 4 bits per node
         int n;
@@ -69,6 +70,25 @@ struct PackGraded {
         }
     }
 
+    // the dword pairs holding the lane's samples of the F1 inputs of level-1 node j of one row
+    // (offset words w), and per input the byte selector of its samples (0, 2); +0x00010001
+    // gives samples (1, 3), and 0x0c fills a zero byte
+    static __device__ __forceinline__ void load_row(uint32_t (&d)[F1][V][2], uint32_t (&sel)[F1], uint32_t w,
+                                                    const unsigned char *lane_base, int j)
+    {
+#pragma unroll
+        for (int u = 0; u < F1; ++u) {
+            const uint32_t o = (uint32_t)__builtin_amdgcn_readlane((int)w, j * F1 + u);
+            sel[u] = 0x0c020c00u + (o & 3u) * 0x00010001u;
+            const uint32_t *p = reinterpret_cast<const uint32_t *>(lane_base + (o & ~3u));
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                d[u][v][0] = p[64 * v];
+                d[u][v][1] = p[64 * v + 1];
+            }
+        }
+    }
+
     // the level-1 nodes of one batch: for each, its F1 inputs per row, then the closes
     static __device__ __forceinline__ void add_batch(A (&st)[kState], const unsigned char *buf, const unsigned char *w,
                                                      int lane, const Carry &cr, const GroupArgs &s)
@@ -82,28 +102,23 @@ struct PackGraded {
             const int c = (int)(((j < 8 ? cr.close0 : cr.close1) >> (4 * (j & 7))) & 15u);
 #pragma unroll
             for (int q = 0; q < R; ++q) {
+                uint32_t d[F1][V][2], sel[F1];
+                load_row(d, sel, wq[q], lane_base, j);
+                // the node's sum of F1 permuted inputs, three at a time (v_add3_u32)
                 uint32_t a[K];
 #pragma unroll
-                for (int u = 0; u < F1; ++u) {
-                    const uint32_t o = (uint32_t)__builtin_amdgcn_readlane((int)wq[q], j * F1 + u);
-                    // byte selector of samples (0, 2) of the input from the dword pair; +0x00010001
-                    // gives samples (1, 3); 0x0c fills a zero byte
-                    const uint32_t sel = 0x0c020c00u + (o & 3u) * 0x00010001u;
-                    const uint32_t *p = reinterpret_cast<const uint32_t *>(lane_base + (o & ~3u));
+                for (int v = 0; v < V; ++v)
 #pragma unroll
-                    for (int v = 0; v < V; ++v) {
-                        const uint32_t d0 = p[64 * v], d1 = p[64 * v + 1];
-                        const uint32_t e = __builtin_amdgcn_perm(d1, d0, sel);
-                        const uint32_t f = __builtin_amdgcn_perm(d1, d0, sel + 0x00010001u);
-                        if (u == 0) {
-                            a[2 * v] = e;
-                            a[2 * v + 1] = f;
-                        } else {
-                            a[2 * v] += e;
-                            a[2 * v + 1] += f;
-                        }
+                    for (int h = 0; h < 2; ++h) {
+                        uint32_t x[F1];
+#pragma unroll
+                        for (int u = 0; u < F1; ++u)
+                            x[u] = __builtin_amdgcn_perm(d[u][v][1], d[u][v][0], sel[u] + (h ? 0x00010001u : 0u));
+                        uint32_t acc = x[0] + x[1] + x[2];
+#pragma unroll
+                        for (int u = 3; u < F1; u += 2) acc = u + 1 < F1 ? acc + x[u] + x[u + 1] : acc + x[u];
+                        a[2 * v + h] = acc;
                     }
-                }
 #pragma unroll
                 for (int k = 0; k < K; ++k) {
                     const uint32_t y = pk_min_u16(a[k], cap2);

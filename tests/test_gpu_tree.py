@@ -167,7 +167,8 @@ def test_float_storage_small_integers_exact(snd, orc, node, B):
 
 
 @pytest.mark.parametrize("nchan,B,cap,levels", [(1024, 4, 255, 4), (1024, 4, 3, 4), (256, 8, 255, 4),
-                                                (512, 8, 7, 6), (64, 4, 2, 2)])
+                                                (512, 8, 7, 6), (64, 4, 2, 2), (4096, 4, 15, 4),
+                                                (4096, 8, 255, 4)])
 def test_graded_packed_levels_exact(snd, orc, nchan, B, cap, levels):
     """Graded u8 rows with level-1 nodes of 4 or 8 inputs run the packed kernel (two 16-bit
     counts per dword); small caps clip at every level.  Bit-exact against the oracle and the
