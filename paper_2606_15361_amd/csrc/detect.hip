@@ -5,7 +5,7 @@
 //   Integer planes use exact 64-bit sums S1, S2 and sigma = sqrt(n*S2 - S1*S1)/n in one fixed
 //   FP64 expression; float planes use one FP64 pass about the row's first sample.  A floor
 //   sigma_min applies.
-// k_snr: one workgroup per (row, 2048-sample tile).  The tile plus the widest boxcar is
+// k_snr: one workgroup per (row, tile of 8192 samples for integer planes, 2048 for float).  The tile plus the widest boxcar is
 //   staged in LDS as an inclusive prefix sum (int32 for integer planes: exact; FP64 for float
 //   planes), every sample then evaluates all widths with two LDS reads each:
 //   SNR(t, W) = (S_W(t) - mu W) / (sigma sqrt W), maximum over widths (first width on ties).
@@ -16,6 +16,7 @@
 //   quotient.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 
 #include "snd_detect.h"
@@ -27,13 +28,17 @@ typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 template <typename T> using global_ptr = __attribute__((address_space(1))) T *;
 template <typename T> __device__ inline global_ptr<const T> as_global(const T *p) { return (global_ptr<const T>)p; }
 
-constexpr int kSnrTile = 2048;
 constexpr int kThreads = 256;
 
 template <typename T> struct IsInt { static constexpr bool value = true; };
 template <typename P> struct BoundNever { __device__ static P value() { return (P)2147483647; } };
 template <> struct BoundNever<double> { __device__ static double value() { return __builtin_inf(); } };
 template <> struct IsInt<float> { static constexpr bool value = false; };
+// Samples of one row per S/N workgroup: integer planes carry a 4-byte prefix per sample and
+// little arithmetic per byte read, so their tiles are longer (fewer workgroups, a smaller share
+// of re-read halo; 4096 keeps seven workgroups on a CU, 8192 and 2048 measured slower); float
+// planes carry an 8-byte prefix.
+template <typename T> constexpr int snr_tile() { return IsInt<T>::value ? 4096 : 2048; }
 
 // Row sums with 16-byte loads: a scalar head up to the first 16-byte boundary of the row, then
 // 16-byte vectors (four in flight per thread), then a scalar tail.  f(x, j) folds one sample;
@@ -148,8 +153,10 @@ __global__ __launch_bounds__(kThreads) void k_snr(const T *plane, int64_t pitch,
                                                   SnrArgs a)
 {
     using P = typename PrefixType<T>::type;
+    constexpr int kSnrTile = snr_tile<T>();
     constexpr int kMaxPer = (kSnrTile + kMaxWidth + kThreads - 1) / kThreads;  // elements per thread
     constexpr int kSlabs = kSnrTile / kThreads;                                // samples per thread
+    static_assert(kSlabs <= 32, "one flag bit per slab");
     extern __shared__ __align__(16) unsigned char snr_dyn[];  // prefix sums: tile + widest width + 1
     P *pre = reinterpret_cast<P *>(snr_dyn);
     __shared__ P wtot[kThreads / 64];
@@ -172,7 +179,11 @@ __global__ __launch_bounds__(kThreads) void k_snr(const T *plane, int64_t pitch,
     // four samples (at most kMaxPer, since kMaxPer is itself a multiple of four)
     static_assert(kMaxPer % 4 == 0, "vector chunks");
     const bool vec4 = !IsInt<T>::value && sizeof(T) == 4 && ((uintptr_t)row & 15u) == 0;
-    const int per = vec4 ? (L + 4 * kThreads - 1) / (4 * kThreads) * 4 : (L + kThreads - 1) / kThreads;
+    // integer tiles: every thread takes kMaxPer elements, those past L read as zero (the prefix
+    // array is sized for kThreads * kMaxPer entries), so that no access depends on L
+    const int per = IsInt<T>::value ? kMaxPer
+                    : vec4          ? (L + 4 * kThreads - 1) / (4 * kThreads) * 4
+                                    : (L + kThreads - 1) / kThreads;
     const int beg = tid * per;
     // prefix sums: per-thread chunk totals, wave scan, wave totals through LDS.  Integer
     // tiles are first read with coalesced loads into LDS (in the prefix array's storage, which
@@ -183,12 +194,22 @@ __global__ __launch_bounds__(kThreads) void k_snr(const T *plane, int64_t pitch,
         T *raw = reinterpret_cast<T *>(pre);
         static_assert(sizeof(T) <= sizeof(P), "the staged tile fits the prefix array");
         const auto grow = as_global(row);
-        for (int j = tid; j < L; j += kThreads) raw[j] = grow[j];
+        // 16-byte loads where the tile starts on a 16-byte boundary (rows of 64-sample pitch do)
+        constexpr int E = 16 / (int)sizeof(T);
+        int j0 = 0;
+        if (((uintptr_t)row & 15u) == 0) {
+            const auto g4 = as_global(reinterpret_cast<const u32x4 *>(row));
+            u32x4 *r4 = reinterpret_cast<u32x4 *>(raw);
+            for (int j = tid; j < L / E; j += kThreads) r4[j] = g4[j];
+            j0 = L / E * E;
+        }
+        for (int j = j0 + tid; j < L; j += kThreads) raw[j] = grow[j];
         __syncthreads();
 #pragma unroll
         for (int i = 0; i < kMaxPer; ++i) {
             const int j = beg + i;
-            v[i] = (i < per && j < L) ? (P)raw[j] : (P)0;
+            const P x = (P)raw[j];
+            v[i] = j < L ? x : (P)0;
             run += v[i];
         }
     } else if (vec4) {
@@ -231,12 +252,20 @@ __global__ __launch_bounds__(kThreads) void k_snr(const T *plane, int64_t pitch,
     P acc = inc - run;
     for (int w = 0; w < wv; ++w) acc += wtot[w];
     if (tid == 0) pre[0] = 0;
+    if constexpr (IsInt<T>::value) {
 #pragma unroll
-    for (int i = 0; i < kMaxPer; ++i) {
-        const int j = beg + i;
-        if (i < per && j < L) {
+        for (int i = 0; i < kMaxPer; ++i) {
             acc += v[i];
-            pre[j + 1] = acc;
+            pre[beg + i + 1] = acc;
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < kMaxPer; ++i) {
+            const int j = beg + i;
+            if (i < per && j < L) {
+                acc += v[i];
+                pre[j + 1] = acc;
+            }
         }
     }
     const double mu = stats[2 * k], sg = stats[2 * k + 1];
@@ -305,12 +334,24 @@ __global__ __launch_bounds__(kThreads) void k_snr(const T *plane, int64_t pitch,
     // every width fits every sample of the tile: no end-of-row tests
     const bool interior = t0 + kSnrTile + wmax - 1 <= n;
     uint32_t flags = 0;
-    double bs[kSlabs];
-    int bw[kSlabs];
+    if (NW > 0 && interior && sg > 0.0) {  // straight-line bound tests; the exact quotient is rare
+#pragma unroll
+        for (int j = 0; j < kSlabs; ++j) {
+            const int i = tid + kThreads * j;
+            const P p0 = pre[i];
+            bool maybe = false;
+#pragma unroll
+            for (int w = 0; w < RW; ++w) maybe |= (P)(pre[i + rw[w]] - p0) >= rthr[w];
+            if (maybe) {
+                double best;
+                int bi;
+                exact(i, t0 + i, best, bi);
+                if (bi >= 0 && best >= a.threshold) flags |= 1u << j;
+            }
+        }
+    } else {
 #pragma unroll
     for (int j = 0; j < kSlabs; ++j) {
-        bs[j] = 0.0;
-        bw[j] = 0;
         const int i = tid + kThreads * j;
         const int64_t t = t0 + i;
         if (t >= n || !(sg > 0.0)) continue;
@@ -329,11 +370,8 @@ __global__ __launch_bounds__(kThreads) void k_snr(const T *plane, int64_t pitch,
         double best;
         int bi;
         exact(i, t, best, bi);
-        if (bi >= 0 && best >= a.threshold) {
-            flags |= 1u << j;
-            bs[j] = best;
-            bw[j] = bi;
-        }
+        if (bi >= 0 && best >= a.threshold) flags |= 1u << j;
+    }
     }
     // ordered output: the block's cells in increasing t (slab by slab, thread by thread)
     uint64_t masks[kSlabs];
@@ -360,11 +398,16 @@ __global__ __launch_bounds__(kThreads) void k_snr(const T *plane, int64_t pitch,
         if (!((flags >> j) & 1u)) continue;
         const int64_t pos = (int64_t)base_s + slab_off[j][wv] + __popcll(masks[j] & below);
         if (pos < a.max_pixels) {
+            // the flagged cells are few: their exact maximum is taken again rather than kept
+            const int i = tid + kThreads * j;
+            double best;
+            int bi;
+            exact(i, t0 + i, best, bi);
             Pixel px;
             px.k = k;
-            px.t = (int32_t)(t0 + tid + kThreads * j);
-            px.snr = bs[j];
-            px.widx = bw[j];
+            px.t = (int32_t)(t0 + i);
+            px.snr = best;
+            px.widx = bi;
             px.pad = 0;
             a.pixels[pos] = px;
         }
@@ -478,10 +521,14 @@ int launch_typed(const void *plane, int64_t pitch, int ndm, int64_t n, double si
     hipLaunchKernelGGL((k_rowstats<T>), dim3((uint32_t)ndm), dim3(kThreads), 0, st, p, pitch, n, sigma_min, stats);
     if (sigma_mad)  // sigma from the median absolute deviation instead (the mean stays)
         hipLaunchKernelGGL((k_rowmad<T>), dim3((uint32_t)ndm), dim3(kThreads), 0, st, p, pitch, n, sigma_min, stats);
+    constexpr int kSnrTile = snr_tile<T>();
     dim3 grid((uint32_t)((n + kSnrTile - 1) / kSnrTile), (uint32_t)ndm);
     // the prefix array holds the tile plus the widest boxcar of the list (every row's set is a
     // leading part of the list)
-    const size_t lds = (size_t)(kSnrTile + a.w[a.nw - 1] + 1) * sizeof(typename PrefixType<T>::type);
+    // (integer planes: at least one entry per element of the threads' fixed chunks)
+    constexpr int64_t kChunks = IsInt<T>::value ? (int64_t)kThreads * ((kSnrTile + kMaxWidth + kThreads - 1) / kThreads) + 1 : 0;
+    const int64_t entries = std::max<int64_t>(kSnrTile + a.w[a.nw - 1] + 1, kChunks);
+    const size_t lds = (size_t)entries * sizeof(typename PrefixType<T>::type);
     switch (a.nw) {
 #define SND_NW(N) case N: hipLaunchKernelGGL((k_snr<T, N>), grid, dim3(kThreads), lds, st, p, pitch, n, stats, a); break;
     SND_NW(1) SND_NW(2) SND_NW(3) SND_NW(4) SND_NW(5) SND_NW(6) SND_NW(7) SND_NW(8)
