@@ -94,9 +94,10 @@ def parse():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one plain 1 GiB device copy first (scale reference for HBM counters)")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default stage schedule")
-    ap.add_argument("--legs", default="direct,fdmt,multirate,frontend,batch,serve",
+    ap.add_argument("--legs", default="direct,fdmt,multirate,trees,frontend,batch,serve",
                     help="extra measurements after the headline: direct (the same block without shared neurons), "
-                         "multirate (scrunch bands), batch (48 beams), serve (streaming loop)")
+                         "multirate (scrunch bands), trees (every mode and storage, B = 4 and 8), batch (48 beams), "
+                         "serve (streaming loop and load sweep)")
     ap.add_argument("--serve-seconds", type=float, default=12.0, help="real-time length of each serving run")
     return ap.parse_args()
 
@@ -202,6 +203,52 @@ def direct_leg(snd, torch, spec, x, pkw, dev, ref_out, reps=3):
     return dict(method="direct (no shared neurons)", ms=round(ms, 3), value=p.ndm * p.n_out / (ms * 1e-3),
                 unit="DM-time samples/s", kernel=info["stage_kernel"][0], inputs_per_sample=info["stage_entries"][0],
                 identical_to_snd=bool(torch.equal(out, ref_out)), rel_rms_vs_snd=rel)
+
+
+def trees_leg(snd, torch, spec, zt, dev, reps=3):
+    """The tree alone (every stage, no detection) on the same block for each mode and storage,
+    with the default branching B = 4 and the paper's own tree (Table S1: C = 4, B = 8, a
+    4-input root): milliseconds per block, the final stage's kernel and its share."""
+    rows = []
+    variants = [("float", "f32", 4), ("float", "f32", 8), ("float", "bf16", 4), ("float", "bf16", 8),
+                ("graded", "u8", 4), ("graded", "u8", 8), ("binary", "bits", 4), ("binary", "bits", 8)]
+    for mode, node, B in variants:
+        if mode == "float":
+            x = zt if node == "f32" else snd.cast(zt, node)
+            in_dtype = None if node == "f32" else node
+        elif mode == "graded":
+            x, in_dtype = snd.encode(zt, [1.0, 2.0, 3.0, 4.0]), None
+        else:
+            x, in_dtype = snd.encode_bits(zt, 2.0), "bits"
+        p = snd.Plan(spec.freqs, spec.dms, spec.tsamp_s, spec.nsamp, mode=mode, branching=B, cluster=spec.cluster,
+                     k_leaf=2, k_int=1, cap=255, node_dtype=node, in_dtype=in_dtype)
+        p.upload(dev)
+        out = p.empty_output(dev)
+        ws = p.workspace(dev)
+        stream = torch.cuda.current_stream(dev)
+        p.execute(x, out=out, workspace=ws)
+        torch.cuda.synchronize()
+        ns = p.info["n_stages"]
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(ns + 1)]
+        tot = [0.0] * ns
+        for _ in range(reps):
+            ev[0].record(stream)
+            for st in range(ns):
+                p.execute(x, out=out, workspace=ws, stage=st)
+                ev[st + 1].record(stream)
+            torch.cuda.synchronize()
+            for st in range(ns):
+                tot[st] += ev[st].elapsed_time(ev[st + 1]) / reps
+        ms = sum(tot)
+        rows.append(dict(mode=mode, storage=node, branching=B, ms=round(ms, 3),
+                         stage_ms=[round(t, 3) for t in tot], kernels=p.info["stage_kernel"],
+                         value=p.ndm * p.n_out / (ms * 1e-3), neurons=p.info["n_neurons"],
+                         synapses=p.info["n_synapses"]))
+        log(f"[bench] tree {mode}/{node} B={B}: {ms:.3f} ms {p.info['stage_kernel']}")
+        del p, out, ws, x
+        torch.cuda.empty_cache()
+    return dict(workload="the same 1024 ch x 2^17 block, 4096 DMs 0-2000, C = 4", unit="DM-time samples/s",
+                rows=rows)
 
 
 def subband_leg(snd, torch, spec, x, pkw, dev, ref_out, reps=3):
@@ -625,6 +672,35 @@ def serve_leg(snd, synth, torch, dev, seconds):
         out[form]["saturated_dm_time_samples_per_s"] = produced * pg.ndm / dt
         del server
         torch.cuda.empty_cache()
+    # offered load: the same 40 beams with their arrival period compressed f times; a form
+    # sustains load f while its p99 latency stays within the chunk's real-time duration
+    sweep = {}
+    for form in ("batched_stream", "plain_per_beam"):
+        rows = []
+        for f in (1, 5, 10, 15, 20, 22, 24, 26):
+            server = (serve.Server(kinds, budget, batched=True, device=dev) if form == "batched_stream"
+                      else _PlainServer(snd, torch, kinds, dev))
+            for b in range(40):
+                assert server.admit(b, kind(b))
+            rng = synth.make_rng(synth.seed_for(5, 11))
+            dur = 6.0
+            arr = {b: a for b, a in enumerate(synth.arrival_times(rng, 40, dur + 1.0, period / f))}
+            recs, _ = serve.run_schedule(server, arr, src, duration_s=dur, warm_chunks=5)
+            lat = np.array([r["latency"] for r in recs if r["counted"]])
+            offered = 40 * f / period
+            rows.append(dict(load=f, offered_chunks_per_s=round(offered, 1), chunks=len(recs),
+                             served_chunks_per_s=round(len(recs) / dur, 1),
+                             p50_ms=round(float(np.percentile(lat, 50)) * 1e3, 3) if lat.size else None,
+                             p99_ms=round(float(np.percentile(lat, 99)) * 1e3, 3) if lat.size else None))
+            log(f"[bench] serving sweep {form} load {f}x: {rows[-1]}")
+            del server
+            torch.cuda.empty_cache()
+        ok = [r["load"] for r in rows if r["p99_ms"] is not None and r["p99_ms"] < period * 1e3
+              and r["served_chunks_per_s"] >= 0.98 * r["offered_chunks_per_s"]]
+        sweep[form] = dict(rows=rows, max_sustained_load=max(ok) if ok else None)
+    sweep["note"] = ("40 beams, arrival period 1.1305 s / load, 6 s per point; latency = arrival to candidates "
+                     "on the host; sustained = p99 below 1130.5 ms and at least 98 % of the offered chunks served")
+    out["load_sweep"] = sweep
     out["workload"] = ("48 beams x 1024 ch, 8192-sample chunks (1.1305 s), arrivals period x U(0.8,1.2); half graded "
                        "u8 / half bf16 float; 4096 DMs to 2000; B=4; history budget ~44 beams; 40 at start, one "
                        "leaves and one joins every 10 s")
@@ -872,6 +948,12 @@ def main():
         outs = ws = detector = None
     if legs:
         del x, outs, ws, detector, plan
+        torch.cuda.empty_cache()
+    if "trees" in legs:
+        log("[bench] trees: every mode and storage, B = 4 and B = 8")
+        zt = torch.from_numpy(z).to(dev)
+        result["trees"] = trees_leg(snd, torch, spec, zt, dev)
+        del zt
         torch.cuda.empty_cache()
     if "completeness" in legs:
         log("[bench] completeness curve: synthetic injections, multi-rate pipeline")

@@ -20,11 +20,12 @@ class Server:
     plan's input storage type."""
 
     def __init__(self, kinds: dict, budget_bytes: int, *, widths=(1, 2, 4, 8, 16, 32, 64), threshold=7.0,
-                 n_min=10, batched=True, device="cuda"):
+                 n_min=10, batched=True, device="cuda", stage_cells=1 << 15):
         import torch
         self.device = torch.device(device)
         self.kinds = kinds
         self.batched = batched
+        self.stage_cells = stage_cells  # thresholded cells read back per chunk (more: run again)
         self.stream = Stream(budget_bytes, device)
         self.det = {k: Detector(p, widths=widths, threshold=threshold, n_min=n_min, device=device)
                     for k, (p, _) in kinds.items()}
@@ -75,12 +76,17 @@ class Server:
             x = encode(z, thr) if thr is not None else (z if plan.in_dtype == "f32" else cast(z, plan.in_dtype))
             items.append((beam, idx, x, self.out[beam]))
         res = self.stream.push(items, workspace=self.ws, batched=self.batched)
-        done = []
+        # every complete chunk's detection is enqueued first (kernels and the read-back of its
+        # thresholded cells, on the push's stream), then the host extracts the candidates of
+        # each in turn while the device works through the rest
+        tickets = []
         for (beam, idx, _, out), (t0, n, status) in zip(items, res):
             kind = self.kind_of[beam]
-            cands = self.det[kind].run(out) if n == self.kinds[kind][0].n_out else None
-            done.append((beam, idx, t0, n, cands))
-        return done
+            full = n == self.kinds[kind][0].n_out
+            tickets.append((beam, idx, t0, n, kind, self.det[kind].launch(out, stage_cells=self.stage_cells)
+                            if full else None))
+        return [(beam, idx, t0, n, None if tk is None else self.det[kind].collect(tk))
+                for beam, idx, t0, n, kind, tk in tickets]
 
 
 def run_schedule(server: Server, arrivals, make_chunk, *, duration_s: float, joins=(), leaves=(), warm_chunks=5,
