@@ -510,8 +510,39 @@ def batch_leg(snd, synth, torch, dev, reps=3):
     ms_batch = timed(lambda: batch.execute(xs, outs))
     ms_single = timed(lambda: [p.execute(x, out=o, workspace=w)
                                for p, x, o, w in zip(plans, xs, outs, batch.workspaces)])
+    # tuned against default: launch shapes tuned once per beam class (mode, storage) on its first
+    # beam (cached on disk), applied to every beam of the class, the batch timed again
+    tw = snd.tune_word
+    shapes = [0, tw(xcd_groups=1), tw(xcd_groups=2), tw(xcd_groups=16), tw(lds_quarters_off=1),
+              tw(lds_quarters_off=2), tw(leaf_window=1024), tw(leaf_window=512)]
+    classes = {}
+    for i, p in enumerate(plans):
+        classes.setdefault((p.mode, p.node_dtype), []).append(i)
+    tuned_rows, best_tune = [], {}
+    for key, idx in classes.items():
+        s_, p0 = specs[idx[0]], plans[idx[0]]
+        kw = dict(mode=s_.mode, branching=4, k_leaf=s_.k_leaf, k_int=s_.k_int, node_dtype=p0.node_dtype,
+                  in_dtype=p0.in_dtype)
+        best, recs, hit = snd.autotune_cached(s_.freqs, s_.dms, s_.tsamp_s, xs[idx[0]], [(0, 0, t) for t in shapes],
+                                              nsamp=s_.nsamp, reps=2, **kw)
+        best_tune[key] = best[2]
+        ok = [r["ms"] for r in recs if r["ms"] > 0]
+        tuned_rows.append(dict(mode=key[0], storage=key[1], beams=len(idx), default_ms=round(recs[0]["ms"], 3),
+                               tuned_ms=round(min(ok), 3), tune=snd.tune_fields(best[2]), cache_hit=hit))
+        log(f"[bench] batch class {key}: default {recs[0]['ms']:.3f} ms, tuned {min(ok):.3f} ms "
+            f"{snd.tune_fields(best[2])}")
+    del batch
+    torch.cuda.empty_cache()
+    plans_t = []
+    for s_, p in zip(specs, plans):
+        plans_t.append(snd.Plan(s_.freqs, s_.dms, s_.tsamp_s, s_.nsamp, mode=s_.mode, branching=4, k_leaf=s_.k_leaf,
+                                k_int=s_.k_int, node_dtype=p.node_dtype, in_dtype=p.in_dtype,
+                                tune=best_tune[(p.mode, p.node_dtype)]))
+    batch = snd.Batch(plans_t, dev)
+    ms_tuned = timed(lambda: batch.execute(xs, outs))
     res = dict(workload="48 beams x 1024 ch x 2^16 samples; DM grids 1024-4096 trials to 500-2000; "
                         "modes binary/graded/float (f32/bf16/f16); B=4; synthetic N(0,1) encoded on the device",
+               ms_batched_tuned=round(ms_tuned, 3), tuned_classes=tuned_rows,
                beams=48, grids=batch.n_launches, plan_build_s=round(t_plan, 2),
                dm_time_samples=int(samples), ms_batched=round(ms_batch, 3), ms_per_beam_launches=round(ms_single, 3),
                value_batched=samples / (ms_batch * 1e-3), value_per_beam=samples / (ms_single * 1e-3),
@@ -751,15 +782,24 @@ def main():
     pkw = dict(mode=mode, branching=spec.branching, cluster=spec.cluster, k_leaf=2, k_int=1, cap=255,
                node_dtype=node, in_dtype=in_dtype, generic_kernels=args.generic_kernels)
     tuned = None
+    tune = 0
     stage_levels = args.stage_levels
     if not args.no_autotune and not args.stage_levels and not args.generic_kernels:
         # measured choice of the stage schedule: leaves only, level 2 only, leaves and level 2
-        cands = [(0, 0), (0b0100, 0), (0b0101, 0)]
-        best, tuned = snd.autotune(spec.freqs, spec.dms, spec.tsamp_s, x, cands, reps=1, nsamp=spec.nsamp, **pkw)
-        stage_levels = cands[best][0]
-        log(f"[bench] autotune: {[(hex(t['stage_levels']), round(t['ms'], 2)) for t in tuned]} -> {stage_levels:#x}")
+        # and of the launch shapes (snd_plan_desc.tune); the choice is cached on disk per GPU
+        # architecture, mode, storage and tree shape
+        tw = snd.tune_word
+        cands = [(0, 0, 0), (0b0100, 0, 0), (0b0101, 0, 0), (0, 0, tw(xcd_groups=1)), (0, 0, tw(xcd_groups=2)),
+                 (0, 0, tw(xcd_groups=16)), (0, 0, tw(lds_quarters_off=1)), (0, 0, tw(leaf_window=1024))]
+        best, tuned, hit = snd.autotune_cached(spec.freqs, spec.dms, spec.tsamp_s, x, cands, reps=1, nsamp=spec.nsamp,
+                                               **pkw)
+        stage_levels, tune = best[0], best[2]
+        for t in tuned:
+            t["tune"] = snd.tune_fields(t["tune"])
+        log(f"[bench] autotune ({'cached' if hit else 'timed'}): "
+            f"{[(hex(t['stage_levels']), round(t['ms'], 2)) for t in tuned]} -> {stage_levels:#x}, tune {tune:#x}")
         torch.cuda.empty_cache()
-    plan = snd.Plan(spec.freqs, spec.dms, spec.tsamp_s, spec.nsamp, stage_levels=stage_levels, **pkw)
+    plan = snd.Plan(spec.freqs, spec.dms, spec.tsamp_s, spec.nsamp, stage_levels=stage_levels, tune=tune, **pkw)
     info = plan.info
     log(f"[bench] plan: {info['n_neurons']} neurons, {info['n_synapses']} synapses, stages {info['stage_rows']}, "
         f"workspace {info['workspace_bytes'] / 2**30:.2f} GiB, built in {info['build_seconds']:.2f} s")
@@ -885,9 +925,11 @@ def main():
                  "workspace_gib": round(info["workspace_bytes"] / 2**30, 3)},
     }
     if tuned is not None:
-        result["autotune"] = [dict(stage_levels=hex(t["stage_levels"]), ms=round(t["ms"], 3),
-                                   workspace_gib=round(t["workspace_bytes"] / 2**30, 2)) for t in tuned]
+        result["autotune"] = dict(cached=hit, candidates=[
+            dict(stage_levels=hex(t["stage_levels"]), tune=t["tune"], ms=round(t["ms"], 3),
+                 workspace_gib=round(t["workspace_bytes"] / 2**30, 2)) for t in tuned])
     result["config"]["stage_levels"] = hex(stage_levels)
+    result["config"]["tune"] = hex(tune)
     if detector is not None:
         # the matched filter's sigma options on the last plane: the standard deviation (the
         # default above) and the median absolute deviation; synchronous runs, host part included

@@ -108,7 +108,18 @@ typedef struct {
                                 LDS-staged kernels (same results; for cross-checks) */
     int32_t chunk;           /* > 0: streaming plan for chunks of up to `chunk` samples; nsamp is
                                 then max_delay + chunk, so that n_out = chunk */
-    int32_t reserved[6];     /* must be zero */
+    uint32_t tune;           /* launch-shape choices (0 = the library's defaults; the output is
+                                identical for every value, only speed and memory differ):
+                                bits 0-3  leaf-stage window of reference samples per workgroup:
+                                          0 auto (the largest of 2048, 1024, 512 whose staging
+                                          keeps four workgroups on a CU), 1..4 = 512, 1024, 2048,
+                                          4096 (UNSUPPORTED when it exceeds the LDS);
+                                bits 4-7  final-stage workgroups dealt per XCD and time tile:
+                                          0 auto (an eighth of the DM groups), k = 1..7: 2^(k-1);
+                                bits 8-11 final-stage LDS batch budget: 0 the whole buffer,
+                                          1 three quarters, 2 half, 3 a quarter.
+                                Other bits must be zero. */
+    int32_t reserved[5];     /* must be zero */
 } snd_plan_desc;
 
 typedef struct snd_plan_s *snd_plan;
@@ -503,17 +514,20 @@ snd_status snd_batch_execute(int32_t nbeams, const snd_plan *plans, const void *
  * Schedule autotuner.
  *
  * A candidate is a stage schedule (which tree levels are written to device memory, see
- * snd_plan_desc.stage_levels) and a time chunk (0 = the whole block in one run, else runs of
- * `chunk` output samples, which bounds the workspace).  Every candidate computes the same
+ * snd_plan_desc.stage_levels), a time chunk (0 = the whole block in one run, else runs of
+ * `chunk` output samples, which bounds the workspace) and launch shapes (snd_plan_desc.tune).  Every candidate computes the same
  * output; they differ in speed and memory.  For each candidate the library builds its plan,
  * uploads the tables to d_tables and times `reps` passes over the block d_in -> d_out with HIP
  * events on `stream` (after one untimed pass).  A candidate whose tables or workspace exceed
- * table_bytes / workspace_bytes is skipped (ms = -1).  *h_best receives the index of the
+ * table_bytes / workspace_bytes, or whose launch shapes the plan cannot take (UNSUPPORTED), is
+ * skipped (ms = -1).  *h_best receives the index of the
  * fastest.  Synchronises the stream.  NOMEM when no candidate fits.
  * --------------------------------------------------------------------------------------- */
 typedef struct {
     uint32_t stage_levels;     /* in: schedule (as in snd_plan_desc) */
     int32_t chunk;             /* in: output samples per run, 0 = whole block */
+    uint32_t tune;             /* in: launch shapes (as snd_plan_desc.tune) */
+    int32_t pad;               /* ignored */
     double ms;                 /* out: mean milliseconds per pass, -1 when skipped */
     int64_t workspace_bytes;   /* out: the candidate's workspace */
     int64_t table_bytes;       /* out: the candidate's tables */

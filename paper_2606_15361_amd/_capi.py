@@ -36,7 +36,7 @@ class PlanDesc(C.Structure):
         ("branching", C.c_int32), ("cluster", C.c_int32), ("mode", C.c_int32), ("k_leaf", C.c_int32),
         ("k_int", C.c_int32), ("cap", C.c_int32), ("in_dtype", C.c_int32), ("node_dtype", C.c_int32),
         ("root_norm", C.c_int32), ("nsamp", C.c_int64), ("stage_levels", C.c_uint32),
-        ("generic_kernels", C.c_int32), ("chunk", C.c_int32), ("reserved", C.c_int32 * 6),
+        ("generic_kernels", C.c_int32), ("chunk", C.c_int32), ("tune", C.c_uint32), ("reserved", C.c_int32 * 5),
     ]
 
 
@@ -79,7 +79,8 @@ class StreamItem(C.Structure):
 
 
 class TuneCandidate(C.Structure):
-    _fields_ = [("stage_levels", C.c_uint32), ("chunk", C.c_int32), ("ms", C.c_double),
+    _fields_ = [("stage_levels", C.c_uint32), ("chunk", C.c_int32), ("tune", C.c_uint32), ("pad", C.c_int32),
+                ("ms", C.c_double),
                 ("workspace_bytes", C.c_int64), ("table_bytes", C.c_int64)]
 
 

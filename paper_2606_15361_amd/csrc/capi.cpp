@@ -175,6 +175,7 @@ Prepared prepare_stage(const PlanImpl &P, size_t si, const Run &run, const void 
         g.lin_smem = reinterpret_cast<const uint32_t *>(tb + S.off_lin_smem);
         g.lin = reinterpret_cast<const uint32_t *>(tb + S.off_lin);
         g.lin_kernel = S.group_lin ? 1 : S.group_pack ? 2 : 0;
+        g.xcd_chunk = S.xcd_chunk;
         g.ngroups = (int32_t)S.ngroups;
         g.n_entries = S.n_entries;
         g.buf_elems = S.lds_buf_elems;

@@ -53,7 +53,7 @@ __global__ __launch_bounds__(1024) void k_group_fast(GroupArgs s0, Multi m)
     // logical tile L = time tile * ngroups + DM group: each XCD takes an eighth of the DM groups
     // of a time tile, and the XCDs work on the same time tiles, whose leaf windows the DM
     // groups share
-    const uint32_t L = xcd_remap_chunked(bid, nblk, (uint32_t)(s.ngroups >= 8 ? s.ngroups / 8 : 1));
+    const uint32_t L = xcd_remap_chunked(bid, nblk, (uint32_t)s.xcd_chunk);
     const int g = (int)(L % (uint32_t)s.ngroups);
     const int t0 = (int)(L / (uint32_t)s.ngroups) * T;
     const int vt = s.n_out - t0 < T ? s.n_out - t0 : T;

@@ -13,8 +13,9 @@
 //    dword and the lower half of the next one (a second read); the branch on that is uniform.
 //    Samples are widened to FP32 exactly before they are added.
 //
-// Each row is summed in FP32 in the order the plan lists its inputs: an association of the
-// exact sum that differs from the tree's, within the float tolerance of the FP64 definition.
+// Each row is summed in FP32 in the order the plan lists its inputs (16-bit rows: batch by batch,
+// each batch's inputs that start a dword before the others): an association of the exact sum
+// that differs from the tree's, within the float tolerance of the FP64 definition.
 #include <hip/hip_runtime.h>
 
 #include "group_tab.h"

@@ -32,7 +32,7 @@ __device__ __forceinline__ void group_tab_body(const GroupArgs &s0, const Multi 
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     // logical tile = time tile * ngroups + DM group, dealt so that the XCDs share time tiles
-    const uint32_t L = xcd_remap_chunked(bid, nblk, (uint32_t)(s.ngroups >= 8 ? s.ngroups / 8 : 1));
+    const uint32_t L = xcd_remap_chunked(bid, nblk, (uint32_t)s.xcd_chunk);
     const int g = (int)(L % (uint32_t)s.ngroups);
     const int t0 = (int)(L / (uint32_t)s.ngroups) * T;
     const int vt = s.n_out - t0 < T ? s.n_out - t0 : T;

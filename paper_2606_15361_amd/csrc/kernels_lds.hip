@@ -39,7 +39,7 @@ __global__ __launch_bounds__(1024) void k_group(GroupArgs s0, Multi m)
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     // time tile * ngroups + DM group, dealt so that the XCDs share time tiles (as k_group_fast)
-    const uint32_t L = xcd_remap_chunked(bid, nblk, (uint32_t)(s.ngroups >= 8 ? s.ngroups / 8 : 1));
+    const uint32_t L = xcd_remap_chunked(bid, nblk, (uint32_t)s.xcd_chunk);
     const int g = (int)(L % (uint32_t)s.ngroups);
     const int t0 = (int)(L / (uint32_t)s.ngroups) * kGroupTile;
     const int vt = s.n_out - t0 < kGroupTile ? s.n_out - t0 : kGroupTile;

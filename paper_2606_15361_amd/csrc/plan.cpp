@@ -174,8 +174,9 @@ bool build_group_lds(const PlanImpl &p, Stage &S, int variant)
     const int gr = kGroupRows * rpw;     // rows per group
     const int unit = f1 ? f1 : 1;  // batches end on level-1 node boundaries
     const int eb = bits ? 1 : 8 * dtype_size(S.src_dtype);  // bits per element
-    const int64_t budget =
-        (int64_t)(lin ? kLinLdsBytes : pack ? kPackLdsBytes : f1 ? kGroupFastLdsBytes : kGroupLdsBytes) * 8 / eb;
+    // LDS bytes per batch buffer, less the share the caller's tune word gives up
+    const int64_t full_budget = lin ? kLinLdsBytes : pack ? kPackLdsBytes : f1 ? kGroupFastLdsBytes : kGroupLdsBytes;
+    const int64_t budget = full_budget * (4 - (int64_t)((p.desc.tune >> 8) & 15u)) / 4 * 8 / eb;
     const int32_t epd = 128 / eb;  // elements per 16-byte copy unit
     // LDS elements of one window: its span plus one tile, from a 16-byte boundary, whole units
     // (bit rows: one more unit, since a lane reads the word after its 32 samples too)
@@ -380,6 +381,10 @@ bool build_group_lds(const PlanImpl &p, Stage &S, int variant)
     }
     S.kernel = kKernelGroupLds;
     S.ngroups = ng;
+    {  // workgroups dealt per XCD and time tile: an eighth of the groups, or the tune word's
+        const uint32_t x = (p.desc.tune >> 4) & 15u;
+        S.xcd_chunk = x ? (1 << (x - 1)) : (ng >= 8 ? (int32_t)(ng / 8) : 1);
+    }
     S.n_entries = ne;
     S.group_f1 = f1;
     S.group_tile = tile_step;
@@ -449,9 +454,13 @@ bool build_anchored(const PlanImpl &p, Stage &S)
     }
     // bit input: leaf level only, tiles of kAnchorTileBits from 64-aligned row anchors
     int tile = bits ? kAnchorTileBits : kAnchorTile;
-    if (!bits)
+    const int forced = (int)(p.desc.tune & 15u);  // a window chosen by the caller (tuning)
+    if (!bits && forced) {
+        tile = kAnchorTile << (forced - 1);
+    } else if (!bits) {
         for (int t = kAnchorMaxTile; t > kAnchorTile; t /= 2)
             if ((chan_max * t + worst) * es <= kAnchorLdsTarget) { tile = t; break; }
+    }
     std::vector<int32_t> nodes, tiles;
     int64_t lds_max = 0;
     for (const NodeSpan &n : ns) {
@@ -486,8 +495,12 @@ snd_status build_plan(const snd_plan_desc &d, PlanImpl &p, std::string &err)
         err = "nchan, ndm, nsamp (or chunk) must be >= 1, tsamp_s > 0 and freq/dm non-null";
         return SND_ERR_INVALID;
     }
-    for (int i = 0; i < 6; ++i)
+    for (int i = 0; i < 5; ++i)
         if (d.reserved[i]) { err = "reserved descriptor fields must be zero"; return SND_ERR_INVALID; }
+    if ((d.tune & ~0xfffu) || (d.tune & 15u) > 4 || ((d.tune >> 4) & 15u) > 7 || ((d.tune >> 8) & 15u) > 3) {
+        err = "unknown tune bits";
+        return SND_ERR_INVALID;
+    }
     if (d.branching < 2 || d.cluster < 1) { err = "branching must be >= 2 and cluster >= 1"; return SND_ERR_INVALID; }
     if (d.mode < SND_MODE_BINARY || d.mode > SND_MODE_FLOAT) { err = "unknown mode"; return SND_ERR_INVALID; }
     if (d.mode == SND_MODE_BINARY && (d.k_leaf < 1 || d.k_int < 1)) {
@@ -758,7 +771,10 @@ snd_status build_plan(const snd_plan_desc &d, PlanImpl &p, std::string &err)
         if (S.final_stage && (build_group_lds(p, S, kGroupLin) || build_group_lds(p, S, kGroupPack) ||
                               build_group_lds(p, S, kGroupFast) || (!bits && build_group_lds(p, S, kGroupGeneric))))
             continue;
-        if (!S.final_stage && S.src_level < 0) build_anchored(p, S);
+        if (!S.final_stage && S.src_level < 0 && !build_anchored(p, S) && (d.tune & 15u)) {
+            err = "the requested leaf-stage window does not fit the LDS";
+            return SND_ERR_UNSUPPORTED;
+        }
     }
     if (bits && (p.stages.size() != 2 || p.stages[0].kernel != kKernelAnchored ||
                  p.stages[1].kernel != kKernelGroupLds)) {

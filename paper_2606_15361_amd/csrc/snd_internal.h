@@ -53,6 +53,7 @@ struct Stage {
     int32_t lds_buf_elems = 0;      // elements per LDS buffer (group kernel)
     int32_t group_f1 = 0;           // inputs per level-1 node when regular (specialised kernel), else 0
     int32_t group_tile = 0;         // time samples per workgroup
+    int32_t xcd_chunk = 1;          // DM groups of one time tile dealt to each XCD in turn
     int32_t group_rpw = 1;          // rows per wave (kFastRows for the specialised kernel)
     std::vector<int32_t> grp_rows;  // [ngroups * kGroupRows * rows per wave], -1 = padding
     std::vector<int32_t> batch_ptr; // [ngroups + 1] into batches
@@ -260,6 +261,7 @@ struct GroupArgs {
     const uint32_t *lin_smem;    // linear kernel only
     const uint32_t *lin;
     int32_t lin_kernel;          // 1: linear kernel, 2: packed kernel
+    int32_t xcd_chunk;           // DM groups of one time tile dealt to each XCD in turn
     int32_t ngroups;
     int32_t n_entries;
     int32_t buf_elems;

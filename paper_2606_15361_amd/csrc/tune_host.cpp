@@ -63,9 +63,11 @@ snd_status snd_autotune(const snd_plan_desc *desc, snd_tune_candidate *cands, in
         snd_plan_desc d = *desc;
         d.stage_levels = c.stage_levels;
         d.chunk = c.chunk > 0 ? c.chunk : 0;
+        d.tune = c.tune;
         snd::PlanImpl P;
         std::string err;
         snd_status s = snd::build_plan(d, P, err);
+        if (s == SND_ERR_UNSUPPORTED) continue;  // e.g. a leaf window the LDS cannot hold: skipped
         if (s != SND_OK) {
             ret = tfail(s, "candidate " + std::to_string(i) + ": " + err);
             break;

@@ -40,7 +40,7 @@ def _stream_handle(stream, device):
 
 def make_desc(freqs, dms, tsamp_s, nsamp, *, mode="float", branching=4, cluster=4, k_leaf=2, k_int=2, cap=255,
               in_dtype=None, node_dtype=None, root_norm=False, fref=0.0, stage_levels=0, generic_kernels=False,
-              chunk=0):
+              chunk=0, tune=0):
     """snd_plan_desc for these parameters; also returns the frequency and DM arrays it points to
     (keep them alive while the descriptor is used) and the resolved storage types."""
     freq = np.ascontiguousarray(freqs, dtype=np.float64)
@@ -64,19 +64,47 @@ def make_desc(freqs, dms, tsamp_s, nsamp, *, mode="float", branching=4, cluster=
     d.chunk = int(chunk)
     d.stage_levels = int(stage_levels)
     d.generic_kernels = int(generic_kernels)
+    d.tune = int(tune)
     return d, freq, dm, in_dtype, node_dtype
 
 
+def tune_word(leaf_window: int = 0, xcd_groups: int = 0, lds_quarters_off: int = 0) -> int:
+    """snd_plan_desc.tune from its fields: leaf-stage window (0 auto, else 512, 1024, 2048 or
+    4096 samples), final-stage DM groups dealt per XCD and time tile (0 auto, else a power of two
+    up to 64), and quarters of the final stage's LDS batch buffer left unused (0..3)."""
+    w = {0: 0, 512: 1, 1024: 2, 2048: 3, 4096: 4}[int(leaf_window)]
+    x = 0 if not xcd_groups else int(xcd_groups).bit_length()
+    if xcd_groups and (1 << (x - 1)) != xcd_groups or x > 7:
+        raise ValueError("xcd_groups must be 0 or a power of two up to 64")
+    if not 0 <= lds_quarters_off <= 3:
+        raise ValueError("lds_quarters_off must be 0..3")
+    return w | (x << 4) | (int(lds_quarters_off) << 8)
+
+
+def tune_fields(tune: int) -> dict:
+    """The fields of a tune word (see tune_word)."""
+    w, x, q = tune & 15, (tune >> 4) & 15, (tune >> 8) & 15
+    return dict(leaf_window=0 if not w else 512 << (w - 1), xcd_groups=0 if not x else 1 << (x - 1),
+                lds_quarters_off=q)
+
+
 def autotune(freqs, dms, tsamp_s, x, candidates, *, reps=2, out=None, stream=None, nsamp=None, **plan_kw):
-    """Time every (stage_levels, chunk) candidate on the block x [nchan][nsamp] with snd_autotune
-    (nsamp defaults to the samples a row of x holds).
-    Returns (index of the fastest, [dict(stage_levels, chunk, ms, workspace_bytes, table_bytes)]).
-    Buffers are sized for the largest candidate that is probed host-side first."""
+    """Time every candidate on the block x [nchan][nsamp] with snd_autotune (nsamp defaults to
+    the samples a row of x holds).  A candidate is (stage_levels, chunk) or (stage_levels, chunk,
+    tune).  Returns (index of the fastest, [dict(stage_levels, chunk, tune, ms, workspace_bytes,
+    table_bytes)]); a skipped candidate has ms -1.  Buffers are sized for the largest candidate
+    that is probed host-side first."""
     import torch
+    cands = [tuple(c) + (0,) * (3 - len(c)) for c in candidates]
     in_dt = plan_kw.get("in_dtype") or ""
     nsamp = int(nsamp or row_samples(x, in_dt))
-    probes = [Plan(freqs, dms, tsamp_s, None if c else nsamp, stage_levels=s, chunk=c, **plan_kw)
-              for s, c in candidates]
+    probes = []
+    for s, c, t in cands:
+        try:
+            probes.append(Plan(freqs, dms, tsamp_s, None if c else nsamp, stage_levels=s, chunk=c, tune=t, **plan_kw))
+        except capi.SndError as e:
+            if e.status != capi.ERR_UNSUPPORTED:
+                raise
     wsb = max(p.info["workspace_bytes"] for p in probes)
     tb = max(p.info["table_bytes"] for p in probes)
     n_out = nsamp - probes[0].max_delay
@@ -87,16 +115,66 @@ def autotune(freqs, dms, tsamp_s, x, candidates, *, reps=2, out=None, stream=Non
         out = torch.empty((probes[0].ndm, n_out), dtype=probes[0].out_dtype, device=dev)
     del probes
     d, _f, _d, _, _ = make_desc(freqs, dms, tsamp_s, nsamp, stage_levels=0, chunk=0, **plan_kw)
-    arr = (capi.TuneCandidate * len(candidates))()
-    for i, (s, c) in enumerate(candidates):
-        arr[i].stage_levels, arr[i].chunk = int(s), int(c)
+    arr = (capi.TuneCandidate * len(cands))()
+    for i, (s, c, t) in enumerate(cands):
+        arr[i].stage_levels, arr[i].chunk, arr[i].tune = int(s), int(c), int(t)
     best = C.c_int32()
-    capi.check(capi.lib().snd_autotune(C.byref(d), arr, len(candidates), C.c_void_p(x.data_ptr()), row_pitch(x, in_dt),
+    capi.check(capi.lib().snd_autotune(C.byref(d), arr, len(cands), C.c_void_p(x.data_ptr()), row_pitch(x, in_dt),
                                        C.c_void_p(out.data_ptr()), out.stride(0), C.c_void_p(ws.data_ptr()),
                                        ws.numel(), C.c_void_p(tables.data_ptr()), tables.numel(), int(reps),
                                        C.byref(best), _stream_handle(stream, dev)))
-    return best.value, [dict(stage_levels=a.stage_levels, chunk=a.chunk, ms=a.ms, workspace_bytes=a.workspace_bytes,
-                             table_bytes=a.table_bytes) for a in arr]
+    return best.value, [dict(stage_levels=a.stage_levels, chunk=a.chunk, tune=a.tune, ms=a.ms,
+                             workspace_bytes=a.workspace_bytes, table_bytes=a.table_bytes) for a in arr]
+
+
+def tune_cache_path() -> str:
+    """File of the autotune cache: $SND_TUNE_CACHE, else ~/.cache/snd/tune.json."""
+    import os
+    return os.environ.get("SND_TUNE_CACHE") or os.path.join(os.path.expanduser("~"), ".cache", "snd", "tune.json")
+
+
+def tune_key(freqs, dms, tsamp_s, nsamp, device, **plan_kw) -> str:
+    """Cache key of a tuning problem: GPU architecture, mode, storage types, branching, cluster,
+    the tree's shape (nodes and shared neurons per level), DM rows and output samples."""
+    import torch
+    kw = {k: v for k, v in plan_kw.items() if k not in ("stage_levels", "chunk", "tune")}
+    p = Plan(freqs, dms, tsamp_s, nsamp, **kw)
+    arch = torch.cuda.get_device_properties(device).gcnArchName.split(":")[0]
+    return "|".join(str(v) for v in (arch, p.mode, p.in_dtype, p.node_dtype, p.params["branching"],
+                                        p.params["cluster"], p.params["cap"] if p.mode == "graded" else "-",
+                                        ",".join(map(str, p.info["nodes_per_level"])),
+                                        ",".join(map(str, p.info["neurons_per_level"])), p.ndm, p.n_out))
+
+
+def autotune_cached(freqs, dms, tsamp_s, x, candidates, *, nsamp=None, cache_path=None, reps=2, **plan_kw):
+    """autotune() with an on-disk cache keyed by tune_key(): a stored choice for the same key and
+    candidate list is returned without timing.  Returns (best candidate as a tuple, records, hit)."""
+    import json
+    import os
+    path = cache_path or tune_cache_path()
+    in_dt = plan_kw.get("in_dtype") or ""
+    nsamp = int(nsamp or row_samples(x, in_dt))
+    key = tune_key(freqs, dms, tsamp_s, nsamp, x.device, **plan_kw)
+    cands = [list(tuple(c) + (0,) * (3 - len(c))) for c in candidates]
+    try:
+        with open(path) as f:
+            db = json.load(f)
+    except (OSError, ValueError):
+        db = {}
+    ent = db.get(key)
+    if ent is not None and ent.get("candidates") == cands:
+        return tuple(ent["best"]), ent["records"], True
+    best, recs = autotune(freqs, dms, tsamp_s, x, [tuple(c) for c in cands], reps=reps, nsamp=nsamp, **plan_kw)
+    db[key] = dict(candidates=cands, best=cands[best], records=recs)
+    try:
+        os.makedirs(os.path.dirname(path) or ".", exist_ok=True)
+        tmp = path + ".tmp"
+        with open(tmp, "w") as f:
+            json.dump(db, f, indent=1)
+        os.replace(tmp, path)
+    except OSError:
+        pass  # a read-only cache location: the result is still returned
+    return tuple(cands[best]), recs, False
 
 
 class Plan:
@@ -105,9 +183,10 @@ class Plan:
     def __init__(self, freqs, dms, tsamp_s: float, nsamp: int | None, *, mode: str = "float", branching: int = 4,
                  cluster: int = 4, k_leaf: int = 2, k_int: int = 2, cap: int = 255, in_dtype: str | None = None,
                  node_dtype: str | None = None, root_norm: bool = False, fref: float = 0.0, stage_levels: int = 0,
-                 generic_kernels: bool = False, chunk: int = 0):
+                 generic_kernels: bool = False, chunk: int = 0, tune: int = 0):
         """nsamp: input samples per execute; or chunk > 0 (nsamp None): a streaming plan whose
-        n_out is `chunk` and whose nsamp is max_delay + chunk."""
+        n_out is `chunk` and whose nsamp is max_delay + chunk.  tune: launch shapes
+        (snd_plan_desc.tune; 0 = defaults, see tune_word)."""
         L = capi.lib()
         # binary mode stores tree rows as bits unless asked otherwise; trees and schedules that
         # bit rows do not support (irregular level-1 nodes, other stage schedules) use bytes
@@ -115,7 +194,8 @@ class Plan:
         d, self._freq, self._dm, in_dtype, node_dtype = make_desc(
             freqs, dms, tsamp_s, nsamp, mode=mode, branching=branching, cluster=cluster, k_leaf=k_leaf, k_int=k_int,
             cap=cap, in_dtype=in_dtype, node_dtype=node_dtype, root_norm=root_norm, fref=fref,
-            stage_levels=stage_levels, generic_kernels=generic_kernels, chunk=chunk)
+            stage_levels=stage_levels, generic_kernels=generic_kernels, chunk=chunk, tune=tune)
+        self.tune = int(tune)
         h = C.c_void_p()
         rc = L.snd_plan_create(C.byref(d), C.byref(h))
         if rc == capi.ERR_UNSUPPORTED and auto_bits:

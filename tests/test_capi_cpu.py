@@ -491,3 +491,30 @@ def test_noalloc_detect_rejects_workspaces_beyond_the_scratch(snd):
                                               C.cast(stage, C.c_void_p), 512, None)
     assert rc == capi.ERR_NOMEM
     assert b"static scratch" in capi.lib().snd_last_error()
+
+
+def test_tune_word_plans(snd):
+    """Launch-shape choices (snd_plan_desc.tune): every field builds a plan of the same kernels
+    and counts; a smaller LDS batch budget makes more batches; unknown bits and a leaf window
+    the LDS cannot hold are refused."""
+    from paper_2606_15361_amd import SndError, tune_word, tune_fields
+    spec = synth.workload(2)
+    base = snd.Plan(spec.freqs, spec.dms, spec.tsamp_s, spec.nsamp, mode="graded", branching=4)
+    for kw in (dict(xcd_groups=1), dict(xcd_groups=64), dict(lds_quarters_off=2), dict(leaf_window=512),
+               dict(leaf_window=1024, xcd_groups=4, lds_quarters_off=1)):
+        t = tune_word(**kw)
+        assert {k: v for k, v in tune_fields(t).items() if v} == {k: v for k, v in kw.items() if v}
+        p = snd.Plan(spec.freqs, spec.dms, spec.tsamp_s, spec.nsamp, mode="graded", branching=4, tune=t)
+        assert p.info["stage_kernel"] == base.info["stage_kernel"]
+        assert p.info["neurons_per_level"] == base.info["neurons_per_level"] and p.n_out == base.n_out
+        if kw.get("lds_quarters_off"):
+            assert p.info["stage_batches"][1] > base.info["stage_batches"][1]
+    with pytest.raises(SndError) as e:
+        snd.Plan(spec.freqs, spec.dms, spec.tsamp_s, spec.nsamp, mode="graded", branching=4, tune=1 << 12)
+    assert e.value.status == -1
+    with pytest.raises(SndError) as e:  # 4 channels x (4096 + spread) f32 samples exceed 64 KB
+        snd.Plan(spec.freqs, spec.dms, spec.tsamp_s, spec.nsamp, mode="float", branching=4,
+                 tune=tune_word(leaf_window=4096))
+    assert e.value.status == -2
+    with pytest.raises(ValueError):
+        tune_word(xcd_groups=3)

@@ -187,6 +187,39 @@ def test_graded_packed_levels_exact(snd, orc, nchan, B, cap, levels):
     assert np.array_equal(gpu_run(pg, x), y)
 
 
+@pytest.mark.parametrize("mode,node", [("float", "f32"), ("float", "bf16"), ("graded", "u8"), ("binary", "bits"),
+                                       ("binary", "u8")])
+def test_tune_variants_identical(snd, orc, mode, node):
+    """Every launch shape of snd_plan_desc.tune (leaf window, XCD dealing, LDS batch budget)
+    computes the same plane bit for bit, equal to the oracle's (float: within FP32 tolerance; f32
+    rows bit for bit while the final stage keeps its kernel)."""
+    rng, f, dms, _ = _case(256, 300, 23)
+    d = orc.delays(f, dms, 0.138e-3)
+    x = _inputs(rng, mode, 256, int(d.max()) + 3000)
+    kw = dict(k_leaf=2, k_int=1) if mode == "binary" else {}
+    want, _ = orc.snd_dedup(x, f, d, mode=mode, cluster=4, branching=4, **kw)
+    tw = snd.tune_word
+    base = snd.Plan(f, dms, 0.138e-3, x.shape[1], mode=mode, branching=4, node_dtype=node, **kw)
+    y0 = gpu_run(base, x)
+    if mode == "float":
+        assert rel_rms(y0, want) <= (FP32_TOL if node == "f32" else REDUCED_TOL)
+    else:
+        assert np.array_equal(y0, want.astype(y0.dtype))
+    for t in (tw(xcd_groups=1), tw(xcd_groups=2), tw(xcd_groups=16), tw(lds_quarters_off=1), tw(lds_quarters_off=3),
+              tw(leaf_window=512), tw(leaf_window=1024), tw(leaf_window=2048, xcd_groups=4, lds_quarters_off=2)):
+        _say(f"tune mode={mode} node={node} tune={t:#x}")
+        p = snd.Plan(f, dms, 0.138e-3, x.shape[1], mode=mode, branching=4, node_dtype=node, tune=t, **kw)
+        y = gpu_run(p, x)
+        if mode == "float" and (node != "f32" or p.info["stage_kernel"] != base.info["stage_kernel"]):
+            # the one-sum kernel on 16-bit rows adds each batch's inputs grouped by dword phase,
+            # so other batch boundaries associate differently; and a budget too small for its
+            # batches moves the stage to a kernel that sums in the tree's association: the same
+            # plane within FP32 rounding
+            assert rel_rms(y, y0) <= FP32_TOL, snd.tune_fields(t)
+        else:
+            assert np.array_equal(y, y0), snd.tune_fields(t)
+
+
 def test_encoder_parity(snd, orc):
     spec = synth.workload(1)
     z = spec.filterbank()
