@@ -131,9 +131,12 @@ def test_batch_time_chunks_equal_whole_run(snd, orc):
     assert np.array_equal(to_np(out), want)
 
 
-def test_batch_48_beams_workload(snd):
+def test_batch_48_beams_workload(snd, orc):
     """The 48-beam workload (uneven DM grids and lengths, mixed modes and storage) in one
-    batch; a sample of beams is checked against one execute per beam."""
+    batch; a sample of beams is checked against one execute per beam, and at 400 sampled
+    (DM, time) cells each against the oracle's recursion on the same input (integer modes
+    exactly; float f32 within 1e-5 and bf16 / f16 storage within 1e-2 rel-RMS of the FP64
+    values)."""
     specs = [synth.batch_beam(b) for b in range(48)]
     plans, xs = [], []
     for s in specs:
@@ -161,6 +164,19 @@ def test_batch_48_beams_workload(snd):
         ref = plans[b].execute(xs[b], workspace=batch.workspaces[b])
         torch.cuda.synchronize()
         assert torch.equal(y, ref), b
+        s, p = specs[b], plans[b]
+        d = orc.delays(s.freqs, s.dms, s.tsamp_s)
+        xh = xs[b].float().cpu().numpy() if s.mode == "float" else xs[b].cpu().numpy()
+        r = synth.make_rng(1000 + b)
+        ks, ts = r.integers(0, p.ndm, 400), r.integers(0, p.n_out, 400)
+        want = orc.snd_points(xh, s.freqs, d, ks, ts, mode=s.mode, cluster=4, branching=4, k_leaf=s.k_leaf,
+                              k_int=s.k_int)
+        got = to_np(y)[ks, ts]
+        _say(f"beam {b} {s.mode}/{p.node_dtype}: {p.ndm} DMs x {p.n_out} samples vs the oracle")
+        if s.mode == "float":
+            assert rel_rms(got, want) <= (1e-5 if p.node_dtype == "f32" else 1e-2), b
+        else:
+            assert np.array_equal(got, want.astype(got.dtype)), b
 
 
 def test_autotune_times_candidates_with_identical_results(snd):

@@ -208,9 +208,10 @@ def test_stream_checkpoint_restores_beam(snd):
         c.restore(0, ck)  # ring shape differs
 
 
-def test_stream_full_size_graded_chunk(snd):
-    """1024 channels, 4096 DMs to 2000, 8192-sample chunks: the streamed output of the first
-    complete chunks equals the plain execute on the same samples."""
+def test_stream_full_size_graded_chunk(snd, orc):
+    """1024 channels, 4096 DMs to 2000, 8192-sample chunks (the serving beams' shape): the
+    streamed output of the first complete chunks equals the plain execute on the same samples,
+    and the oracle's recursion at 600 sampled (DM, time) cells, bit for bit."""
     spec = synth.workload(2)
     plan = snd.Plan(spec.freqs, spec.dms, spec.tsamp_s, None, mode="graded", branching=4, chunk=8192)
     assert plan.info["stage_kernel"][0] == "anchored"
@@ -227,6 +228,11 @@ def test_stream_full_size_graded_chunk(snd):
     assert y.shape[1] == N - plan.max_delay
     plain = snd.Plan(spec.freqs, spec.dms, spec.tsamp_s, N, mode="graded", branching=4)
     assert np.array_equal(y, to_np(plain.execute(x)))
+    d = orc.delays(spec.freqs, spec.dms, spec.tsamp_s)
+    r = synth.make_rng(77)
+    ks, ts = r.integers(0, plan.ndm, 600), r.integers(0, y.shape[1], 600)
+    want = orc.snd_points(x.cpu().numpy(), spec.freqs, d, ks, ts, mode="graded", cluster=4, branching=4)
+    assert np.array_equal(y[ks, ts], want.astype(y.dtype))
 
 
 def test_batched_push_equals_per_beam_push(snd):
