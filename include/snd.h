@@ -365,6 +365,33 @@ snd_status snd_detect_launch(snd_plan plan, const void *d_plane, int64_t plane_p
 snd_status snd_detect_collect(snd_plan plan, const snd_detect_desc *desc, const void *h_stage, int64_t stage_bytes,
                               snd_candidate *h_out, int64_t cap, int64_t *h_count, int64_t *h_npixels);
 
+/*
+ * Batched detection: the planes of n beams (each with its own plan: DM list, n_out, DM-scaled
+ * width counts, output dtype) in shared grids -- one row-statistics and one S/N launch per plane
+ * dtype for all beams, one cell counter and list, one read-back -- instead of one detection
+ * per beam.  Same candidates as snd_detect per beam.  The descriptor is shared; the standard-
+ * deviation sigma and host labelling only (sigma_estimator 1 or label_on_device 1:
+ * UNSUPPORTED).  max_pixels bounds the cells of all beams together.
+ *
+ * snd_detect_batch_workspace: device bytes for these plans (256-byte aligned buffer).
+ * snd_detect_batch_launch: enqueue on stream the detection of d_planes[i] [ndm_i][pitches[i]]
+ * (plan i's output dtype) and the read-back of the cell count and of up to
+ * SND_DETECT_STAGE_CELLS(stage_bytes) cells into h_stage (page-locked for an asynchronous copy;
+ * first 4 bytes: the count), then return.
+ * snd_detect_batch_collect: once that work has completed, the candidates of each beam from the
+ * staged cells, on the host: beam i's at h_out + i * cap_per_beam (up to cap_per_beam), their
+ * number in h_counts[i] and its thresholded cells in h_npixels[i] (host arrays of n).  CAPACITY
+ * (no candidates) when the cells exceed max_pixels or the staged cells: run snd_detect per beam.
+ * The plans, descriptor and n must be those of the launch.
+ */
+snd_status snd_detect_batch_workspace(int32_t n, const snd_plan *plans, const snd_detect_desc *desc, int64_t *bytes);
+snd_status snd_detect_batch_launch(int32_t n, const snd_plan *plans, const void *const *d_planes, const int64_t *pitches,
+                                   const snd_detect_desc *desc, void *d_workspace, int64_t workspace_bytes,
+                                   void *h_stage, int64_t stage_bytes, void *stream);
+snd_status snd_detect_batch_collect(int32_t n, const snd_plan *plans, const snd_detect_desc *desc, const void *h_stage,
+                                    int64_t stage_bytes, snd_candidate *h_out, int64_t cap_per_beam, int64_t *h_counts,
+                                    int64_t *h_npixels);
+
 /* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
  * loops, harnesses that forbid hipMalloc): snd_detect_launch with no workspace argument.  Its
  * kernels use a fixed device array of SND_DETECT_NOALLOC_MAX_BYTES held by the library on each

@@ -142,6 +142,9 @@ def lib() -> C.CDLL:
         "snd_detect": ([P, P, I64, D, P, I64, C.POINTER(Candidate), I64, C.POINTER(I64), C.POINTER(I64), P], I32),
         "snd_detect_launch": ([P, P, I64, D, P, I64, P, I64, P], I32),
         "snd_detect_collect": ([P, D, P, I64, C.POINTER(Candidate), I64, C.POINTER(I64), C.POINTER(I64)], I32),
+        "snd_detect_batch_workspace": ([I32, P, D, C.POINTER(I64)], I32),
+        "snd_detect_batch_launch": ([I32, P, P, P, D, P, I64, P, I64, P], I32),
+        "snd_detect_batch_collect": ([I32, P, D, P, I64, C.POINTER(Candidate), I64, P, P], I32),
         "snd_detect_launch_noalloc": ([P, P, I64, D, P, I64, P], I32),
     })
     PI64 = C.POINTER(I64)

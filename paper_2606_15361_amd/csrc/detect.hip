@@ -73,12 +73,39 @@ __device__ inline void row_fold(const T *row, int64_t n, int tid, F &&f)
     for (int64_t t = head + nv * E + tid; t < n; t += kThreads) f(row[t], 0);
 }
 
-template <typename T>
-__global__ __launch_bounds__(kThreads) void k_rowstats(const T *plane, int64_t pitch, int64_t n, double sigma_min,
-                                                       double *stats)
+// Row k of a launch: a row of the single plane, or (BATCH) batch row row0 + k of the plane
+// whose row range holds it (a scan of the table: every value is wave-uniform, so scalar work).
+template <bool BATCH, typename T>
+__device__ inline void locate_row(const T *plane, int64_t pitch, int64_t n, const int32_t *row_nw, const DetBeam *beams,
+                                  int nbeams, int row0, int k_launch, const T *&row, int64_t &nr, const int32_t *&nw,
+                                  int &k, int &kl)
 {
-    const int k = blockIdx.x;
-    const T *row = plane + (int64_t)k * pitch;
+    k = row0 + k_launch;
+    if constexpr (!BATCH) {
+        row = plane + (int64_t)k * pitch;
+        nr = n;
+        nw = row_nw;
+        kl = k;
+        return;
+    }
+    int i = 0;
+    while (i + 1 < nbeams && k >= beams[i + 1].row_base) ++i;
+    const DetBeam b = beams[i];
+    kl = k - b.row_base;
+    row = static_cast<const T *>(b.plane) + (int64_t)kl * b.pitch;
+    nr = b.n;
+    nw = b.row_nw;
+}
+
+template <typename T, bool BATCH>
+__global__ __launch_bounds__(kThreads) void k_rowstats(const T *plane, int64_t pitch, int64_t n_, double sigma_min,
+                                                       double *stats, const DetBeam *beams, int nbeams, int row0)
+{
+    const T *row;
+    int64_t n;
+    const int32_t *nw_unused;
+    int k, kl;
+    locate_row<BATCH>(plane, pitch, n_, nullptr, beams, nbeams, row0, (int)blockIdx.x, row, n, nw_unused, k, kl);
     const int tid = threadIdx.x;
     if constexpr (IsInt<T>::value) {
         __shared__ unsigned long long s1[kThreads], s2[kThreads];
@@ -147,9 +174,9 @@ __global__ __launch_bounds__(kThreads) void k_rowstats(const T *plane, int64_t p
 }
 
 // NW > 0: exactly NW widths, known at compile time (per-row constants stay in registers);
-// NW == 0: any number of widths.
-template <typename T, int NW>
-__global__ __launch_bounds__(kThreads) void k_snr(const T *plane, int64_t pitch, int64_t n, const double *stats,
+// NW == 0: any number of widths.  BATCH: rows of several planes (SnrArgs::beams).
+template <typename T, int NW, bool BATCH>
+__global__ __launch_bounds__(kThreads) void k_snr(const T *plane, int64_t pitch, int64_t n_, const double *stats,
                                                   SnrArgs a)
 {
     using P = typename PrefixType<T>::type;
@@ -164,12 +191,19 @@ __global__ __launch_bounds__(kThreads) void k_snr(const T *plane, int64_t pitch,
     __shared__ unsigned int base_s;
     __shared__ double muw[kMaxWidths], den[kMaxWidths];  // per-row constants
     __shared__ P sthr[kMaxWidths];                       // per-row boxcar-sum bounds
-    const int k = blockIdx.y;
+    const T *rowk;
+    int64_t n;
+    const int32_t *row_nw;
+    int k, kl;
+    locate_row<BATCH>(plane, pitch, n_, a.row_nw, a.beams, a.nbeams, a.row0, (int)blockIdx.y, rowk, n, row_nw, k, kl);
     const int64_t t0 = (int64_t)blockIdx.x * kSnrTile;
-    const T *row = plane + (int64_t)k * pitch + t0;
+    if constexpr (BATCH) {
+        if (t0 >= n) return;  // a shorter plane of the batch (uniform: before any barrier)
+    }
+    const T *row = rowk + t0;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     // widths of this row: the first nwk of the list (all of them unless a DM-scaled set)
-    const int nwk = a.row_nw ? a.row_nw[k] : a.nw;
+    const int nwk = row_nw ? row_nw[kl] : a.nw;
     const int wmax = a.w[nwk - 1];
     // elements t0 .. t0 + L - 1 are needed (and exist): L = min(tile + wmax - 1, n - t0)
     int64_t L64 = (int64_t)kSnrTile + wmax - 1;
@@ -512,17 +546,40 @@ __global__ __launch_bounds__(kThreads) void k_rowmad(const T *plane, int64_t pit
 
 __global__ void k_zero_counter(unsigned int *c) { *c = 0u; }
 
+template <typename T, bool BATCH>
+int launch_snr_grid(dim3 grid, const T *p, int64_t pitch, int64_t n, double *stats, const SnrArgs &a, hipStream_t st);
+
 template <typename T>
 int launch_typed(const void *plane, int64_t pitch, int ndm, int64_t n, double sigma_min, int sigma_mad,
                  double *stats, const SnrArgs &a, hipStream_t st)
 {
     const T *p = static_cast<const T *>(plane);
     if (!a.snr) hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(1), 0, st, a.counter);
-    hipLaunchKernelGGL((k_rowstats<T>), dim3((uint32_t)ndm), dim3(kThreads), 0, st, p, pitch, n, sigma_min, stats);
+    hipLaunchKernelGGL((k_rowstats<T, false>), dim3((uint32_t)ndm), dim3(kThreads), 0, st, p, pitch, n, sigma_min,
+                       stats, (const DetBeam *)nullptr, 0, 0);
     if (sigma_mad)  // sigma from the median absolute deviation instead (the mean stays)
         hipLaunchKernelGGL((k_rowmad<T>), dim3((uint32_t)ndm), dim3(kThreads), 0, st, p, pitch, n, sigma_min, stats);
     constexpr int kSnrTile = snr_tile<T>();
     dim3 grid((uint32_t)((n + kSnrTile - 1) / kSnrTile), (uint32_t)ndm);
+    return launch_snr_grid<T, false>(grid, p, pitch, n, stats, a, st);
+}
+
+// Batched: statistics and S/N of batch rows a.row0 .. a.row0 + nrows - 1; the grid spans the
+// longest plane, the tiles past a shorter plane's end return at once.
+template <typename T>
+int launch_typed_batch(int nrows, int64_t n_max, double sigma_min, double *stats, const SnrArgs &a, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_rowstats<T, true>), dim3((uint32_t)nrows), dim3(kThreads), 0, st, (const T *)nullptr,
+                       (int64_t)0, (int64_t)0, sigma_min, stats, a.beams, a.nbeams, a.row0);
+    constexpr int kSnrTile = snr_tile<T>();
+    dim3 grid((uint32_t)((n_max + kSnrTile - 1) / kSnrTile), (uint32_t)nrows);
+    return launch_snr_grid<T, true>(grid, (const T *)nullptr, 0, 0, stats, a, st);
+}
+
+template <typename T, bool BATCH>
+int launch_snr_grid(dim3 grid, const T *p, int64_t pitch, int64_t n, double *stats, const SnrArgs &a, hipStream_t st)
+{
+    constexpr int kSnrTile = snr_tile<T>();
     // the prefix array holds the tile plus the widest boxcar of the list (every row's set is a
     // leading part of the list)
     // (integer planes: at least one entry per element of the threads' fixed chunks)
@@ -530,10 +587,10 @@ int launch_typed(const void *plane, int64_t pitch, int ndm, int64_t n, double si
     const int64_t entries = std::max<int64_t>(kSnrTile + a.w[a.nw - 1] + 1, kChunks);
     const size_t lds = (size_t)entries * sizeof(typename PrefixType<T>::type);
     switch (a.nw) {
-#define SND_NW(N) case N: hipLaunchKernelGGL((k_snr<T, N>), grid, dim3(kThreads), lds, st, p, pitch, n, stats, a); break;
+#define SND_NW(N) case N: hipLaunchKernelGGL((k_snr<T, N, BATCH>), grid, dim3(kThreads), lds, st, p, pitch, n, stats, a); break;
     SND_NW(1) SND_NW(2) SND_NW(3) SND_NW(4) SND_NW(5) SND_NW(6) SND_NW(7) SND_NW(8)
 #undef SND_NW
-    default: hipLaunchKernelGGL((k_snr<T, 0>), grid, dim3(kThreads), lds, st, p, pitch, n, stats, a); break;
+    default: hipLaunchKernelGGL((k_snr<T, 0, BATCH>), grid, dim3(kThreads), lds, st, p, pitch, n, stats, a); break;
     }
     return (int)hipGetLastError();
 }
@@ -548,6 +605,24 @@ int launch_detect(int plane_dtype, const void *plane, int64_t pitch, int ndm, in
     case SND_DT_U8: return launch_typed<uint8_t>(plane, pitch, ndm, n, sigma_min, sigma_mad, stats, a, st);
     case SND_DT_U16: return launch_typed<uint16_t>(plane, pitch, ndm, n, sigma_min, sigma_mad, stats, a, st);
     case SND_DT_F32: return launch_typed<float>(plane, pitch, ndm, n, sigma_min, sigma_mad, stats, a, st);
+    }
+    return (int)hipErrorInvalidValue;
+}
+
+int launch_zero_counter(unsigned int *counter, void *stream)
+{
+    hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(1), 0, (hipStream_t)stream, counter);
+    return (int)hipGetLastError();
+}
+
+int launch_detect_batch(int plane_dtype, int nrows, int64_t n_max, double sigma_min, double *stats, const SnrArgs &a,
+                        void *stream)
+{
+    hipStream_t st = (hipStream_t)stream;
+    switch (plane_dtype) {
+    case SND_DT_U8: return launch_typed_batch<uint8_t>(nrows, n_max, sigma_min, stats, a, st);
+    case SND_DT_U16: return launch_typed_batch<uint16_t>(nrows, n_max, sigma_min, stats, a, st);
+    case SND_DT_F32: return launch_typed_batch<float>(nrows, n_max, sigma_min, stats, a, st);
     }
     return (int)hipErrorInvalidValue;
 }

@@ -540,6 +540,192 @@ snd_status snd_detect_collect(snd_plan plan, const snd_detect_desc *desc, const 
     return SND_OK;
 }
 
+// ---- batched detection ----
+// Beams in batch-row order: grouped by plane dtype (u8, u16, f32), the caller's order within a
+// group; each group is one launch of each kernel.  Workspace: header (cell counter) | row
+// statistics of every batch row | cells | per-row width counts | the beams' table.
+struct BatchLayout {
+    std::vector<int32_t> order;     // beam indices in batch-row order
+    std::vector<int32_t> row_base;  // per beam (caller's index)
+    int64_t rows = 0;
+    int64_t stats = 0, pixels = 0, row_nw = 0, table = 0, end = 0;
+};
+
+static snd_status batch_layout(int32_t n, const snd_plan *plans, const snd_detect_desc *desc, BatchLayout &L)
+{
+    if (n < 1 || !plans) { snd::set_error("no beams"); return SND_ERR_INVALID; }
+    for (int32_t i = 0; i < n; ++i) {
+        if (!plans[i]) { snd::set_error("null plan"); return SND_ERR_INVALID; }
+        const snd_status s = check_desc(plans[i]->impl, desc);
+        if (s != SND_OK) return s;
+    }
+    if (desc->sigma_estimator != 0 || desc->label_on_device != 0) {
+        snd::set_error("batched detection takes the standard-deviation sigma and host labelling");
+        return SND_ERR_UNSUPPORTED;
+    }
+    L.row_base.assign((size_t)n, 0);
+    L.order.clear();
+    for (int dt : {SND_DT_U8, SND_DT_U16, SND_DT_F32})
+        for (int32_t i = 0; i < n; ++i)
+            if (plans[i]->impl.out_dtype == dt) {
+                L.order.push_back(i);
+                L.row_base[(size_t)i] = (int32_t)L.rows;
+                L.rows += plans[i]->impl.ndm;
+                if (L.rows > 0x7fffffffLL) { snd::set_error("too many rows in one batch"); return SND_ERR_UNSUPPORTED; }
+            }
+    if ((int32_t)L.order.size() != n) { snd::set_error("unsupported plane dtype"); return SND_ERR_UNSUPPORTED; }
+    L.stats = kHeader;
+    L.pixels = round_up(L.stats + L.rows * 16, 256);
+    L.row_nw = round_up(L.pixels + desc->max_pixels * (int64_t)sizeof(snd::Pixel), 256);
+    L.table = round_up(L.row_nw + L.rows * 4, 256);
+    L.end = round_up(L.table + (int64_t)n * (int64_t)sizeof(snd::DetBeam), 256);
+    return SND_OK;
+}
+
+extern "C" {
+
+snd_status snd_detect_batch_workspace(int32_t n, const snd_plan *plans, const snd_detect_desc *desc, int64_t *bytes)
+{
+    if (!bytes) { snd::set_error("null argument"); return SND_ERR_INVALID; }
+    BatchLayout L;
+    const snd_status s = batch_layout(n, plans, desc, L);
+    if (s != SND_OK) return s;
+    *bytes = L.end;
+    return SND_OK;
+}
+
+snd_status snd_detect_batch_launch(int32_t n, const snd_plan *plans, const void *const *d_planes, const int64_t *pitches,
+                                   const snd_detect_desc *desc, void *d_workspace, int64_t workspace_bytes,
+                                   void *h_stage, int64_t stage_bytes, void *stream)
+{
+    if (!d_planes || !pitches || !d_workspace || !h_stage) { snd::set_error("null argument"); return SND_ERR_INVALID; }
+    if (stage_bytes < SND_DETECT_STAGE_HEADER) { snd::set_error("stage buffer smaller than its header"); return SND_ERR_INVALID; }
+    BatchLayout L;
+    snd_status s = batch_layout(n, plans, desc, L);
+    if (s != SND_OK) return s;
+    if (workspace_bytes < L.end || ((uintptr_t)d_workspace & 255u)) {
+        snd::set_error("batched detect workspace too small or not 256-byte aligned");
+        return SND_ERR_NOMEM;
+    }
+    for (int32_t i = 0; i < n; ++i)
+        if (!d_planes[i] || pitches[i] < plans[i]->impl.n_out) {
+            snd::set_error("null plane or plane pitch smaller than n_out");
+            return SND_ERR_INVALID;
+        }
+    uint8_t *ws = static_cast<uint8_t *>(d_workspace);
+    hipStream_t st = (hipStream_t)stream;
+    // per-row width counts (DM-scaled set) and the beams' table, one copy each (the pageable
+    // sources are consumed when the copy calls return)
+    std::vector<int32_t> nw_all;
+    std::vector<snd::DetBeam> table((size_t)n);
+    const bool scaled = desc->n_base_widths > 0;
+    if (scaled) nw_all.resize((size_t)L.rows);
+    for (size_t j = 0; j < L.order.size(); ++j) {
+        const int32_t i = L.order[j];
+        const auto &P = plans[i]->impl;
+        const int32_t base = L.row_base[(size_t)i];
+        if (scaled) {
+            std::vector<int32_t> nw;
+            row_width_counts(P, desc, nw);
+            std::copy(nw.begin(), nw.end(), nw_all.begin() + base);
+        }
+        snd::DetBeam &b = table[j];
+        b.plane = d_planes[i];
+        b.pitch = pitches[i];
+        b.n = P.n_out;
+        b.row_nw = scaled ? reinterpret_cast<const int32_t *>(ws + L.row_nw) + base : nullptr;
+        b.row_base = base;
+        b.ndm = P.ndm;
+    }
+    hipError_t he = hipSuccess;
+    if (scaled) he = hipMemcpyAsync(ws + L.row_nw, nw_all.data(), nw_all.size() * 4, hipMemcpyHostToDevice, st);
+    if (he == hipSuccess)
+        he = hipMemcpyAsync(ws + L.table, table.data(), table.size() * sizeof(snd::DetBeam), hipMemcpyHostToDevice, st);
+    if (he != hipSuccess) { snd::set_error(std::string("batched detect tables: ") + hipGetErrorString(he)); return SND_ERR_HIP; }
+    snd::SnrArgs a;
+    fill_args(desc, a);
+    a.counter = reinterpret_cast<unsigned int *>(ws);
+    a.pixels = reinterpret_cast<snd::Pixel *>(ws + L.pixels);
+    a.max_pixels = desc->max_pixels;
+    double *stats = reinterpret_cast<double *>(ws + L.stats);
+    int e = snd::launch_zero_counter(a.counter, stream);
+    // one launch per plane dtype over that group's rows
+    for (size_t j0 = 0; j0 < L.order.size() && !e;) {
+        const int dt = plans[L.order[j0]]->impl.out_dtype;
+        size_t j1 = j0;
+        int64_t nrows = 0, n_max = 0;
+        while (j1 < L.order.size() && plans[L.order[j1]]->impl.out_dtype == dt) {
+            nrows += plans[L.order[j1]]->impl.ndm;
+            n_max = std::max<int64_t>(n_max, plans[L.order[j1]]->impl.n_out);
+            ++j1;
+        }
+        a.beams = reinterpret_cast<const snd::DetBeam *>(ws + L.table) + j0;
+        a.nbeams = (int32_t)(j1 - j0);
+        a.row0 = table[j0].row_base;
+        e = snd::launch_detect_batch(dt, (int)nrows, n_max, desc->sigma_min, stats, a, stream);
+        j0 = j1;
+    }
+    if (e) { snd::set_error(std::string("batched detect launch: ") + hipGetErrorString((hipError_t)e)); return SND_ERR_HIP; }
+    uint8_t *hs = static_cast<uint8_t *>(h_stage);
+    he = hipMemcpyAsync(hs, a.counter, sizeof(unsigned int), hipMemcpyDeviceToHost, st);
+    const int64_t ncells = std::min<int64_t>(SND_DETECT_STAGE_CELLS(stage_bytes), desc->max_pixels);
+    if (he == hipSuccess && ncells > 0)
+        he = hipMemcpyAsync(hs + SND_DETECT_STAGE_HEADER, a.pixels, (size_t)ncells * sizeof(snd::Pixel),
+                            hipMemcpyDeviceToHost, st);
+    if (he != hipSuccess) { snd::set_error(std::string("batched detect read-back: ") + hipGetErrorString(he)); return SND_ERR_HIP; }
+    return SND_OK;
+}
+
+snd_status snd_detect_batch_collect(int32_t n, const snd_plan *plans, const snd_detect_desc *desc, const void *h_stage,
+                                    int64_t stage_bytes, snd_candidate *h_out, int64_t cap_per_beam, int64_t *h_counts,
+                                    int64_t *h_npixels)
+{
+    if (!h_stage || !h_counts || !h_npixels || cap_per_beam < 0 || (cap_per_beam > 0 && !h_out)) {
+        snd::set_error("null argument");
+        return SND_ERR_INVALID;
+    }
+    if (stage_bytes < SND_DETECT_STAGE_HEADER) { snd::set_error("stage buffer smaller than its header"); return SND_ERR_INVALID; }
+    BatchLayout L;
+    snd_status s = batch_layout(n, plans, desc, L);
+    if (s != SND_OK) return s;
+    for (int32_t i = 0; i < n; ++i) h_counts[i] = h_npixels[i] = 0;
+    const uint8_t *hs = static_cast<const uint8_t *>(h_stage);
+    unsigned int count = 0;
+    std::memcpy(&count, hs, sizeof(count));
+    const int64_t ncells = std::min<int64_t>(SND_DETECT_STAGE_CELLS(stage_bytes), desc->max_pixels);
+    if ((int64_t)count > desc->max_pixels || (int64_t)count > ncells) {
+        snd::set_error("more thresholded cells than max_pixels or than the stage buffer holds");
+        return SND_ERR_CAPACITY;
+    }
+    // cells by beam (batch row -> beam through the row ranges), rows back to each plan's own
+    std::vector<std::vector<snd::Pixel>> px((size_t)n);
+    for (unsigned int c = 0; c < count; ++c) {
+        snd::Pixel q;
+        std::memcpy(&q, hs + SND_DETECT_STAGE_HEADER + (size_t)c * sizeof(snd::Pixel), sizeof(q));
+        size_t lo = 0, hi = L.order.size();  // last beam (batch-row order) whose base <= q.k
+        while (hi - lo > 1) {
+            const size_t mid = (lo + hi) / 2;
+            if (L.row_base[(size_t)L.order[mid]] <= q.k) lo = mid;
+            else hi = mid;
+        }
+        const int32_t i = L.order[lo];
+        q.k -= L.row_base[(size_t)i];
+        if (q.k < 0 || q.k >= plans[i]->impl.ndm) { snd::set_error("staged cell outside the batch"); return SND_ERR_INVALID; }
+        px[(size_t)i].push_back(q);
+    }
+    std::vector<snd_candidate> cands;
+    for (int32_t i = 0; i < n; ++i) {
+        h_npixels[i] = (int64_t)px[(size_t)i].size();
+        s = candidates_from_pixels(px[(size_t)i], plans[i]->impl, desc, cands);
+        if (s != SND_OK) return s;
+        h_counts[i] = (int64_t)cands.size();
+        for (int64_t c = 0; c < cap_per_beam && c < (int64_t)cands.size(); ++c) h_out[i * cap_per_beam + c] = cands[(size_t)c];
+    }
+    return SND_OK;
+}
+
+}  // extern "C"
+
 static snd_status detect_impl(snd_plan plan, const void *d_plane, int64_t plane_pitch, const snd_detect_desc *desc,
                        void *d_workspace, int64_t workspace_bytes, snd_candidate *h_out, int64_t cap, int64_t *h_count,
                        int64_t *h_npixels, void *stream);

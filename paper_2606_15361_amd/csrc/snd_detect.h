@@ -22,6 +22,17 @@ struct Pixel {
 template <typename T> struct PrefixType { using type = int32_t; };
 template <> struct PrefixType<float> { using type = double; };
 
+// One plane of a batched detection: its rows are rows row_base .. row_base + ndm - 1 of the
+// batch (statistics, cells and width counts are indexed by batch row).
+struct DetBeam {
+    const void *plane;
+    int64_t pitch;
+    int64_t n;              // valid samples per row
+    const int32_t *row_nw;  // per-row width counts of this plane (null: every width)
+    int32_t row_base;
+    int32_t ndm;
+};
+
 struct SnrArgs {
     int32_t w[kMaxWidths];
     double sqrtw[kMaxWidths];
@@ -37,10 +48,20 @@ struct SnrArgs {
     unsigned int *counter;
     Pixel *pixels;
     int64_t max_pixels;
+    // batched detection (beams != null): the launch covers batch rows row0 .. row0 + gridDim.y - 1
+    // of the nbeams planes in `beams` (device table); plane, pitch and n of the launch are unused
+    const DetBeam *beams;
+    int32_t nbeams;
+    int32_t row0;
 };
 
 int launch_detect(int plane_dtype, const void *plane, int64_t pitch, int ndm, int64_t n, double sigma_min,
                   int sigma_mad, double *stats, const SnrArgs &a, void *stream);
+// Batched: rows a.row0 .. a.row0 + nrows - 1 of the planes in a.beams (all of plane_dtype), whose
+// longest row has n_max samples.  The standard-deviation sigma only.
+int launch_detect_batch(int plane_dtype, int nrows, int64_t n_max, double sigma_min, double *stats, const SnrArgs &a,
+                        void *stream);
+int launch_zero_counter(unsigned int *counter, void *stream);
 
 // Closing and labelling on the device (label.hip).  launch_label builds the closed mask and
 // counts its runs (run_ptr[ndm] = total); the caller checks the total against max_runs before

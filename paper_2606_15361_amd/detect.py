@@ -118,3 +118,86 @@ class Detector:
             out.append(dict(k=c.dm_index, t=c.t, width=c.width, widx=self.widths.index(c.width), snr=c.snr,
                             dm=c.dm, npix=c.npix))
         return out
+
+
+class BatchDetector:
+    """Detection of the planes of several beams in shared grids (snd_detect_batch_*): one
+    statistics and one S/N launch per plane dtype for all of them and one read-back, the same
+    candidates as a Detector per beam.  Standard-deviation sigma and host labelling."""
+
+    def __init__(self, widths=(1, 2, 4, 8, 16, 32, 64), threshold: float = 7.0, sigma_min: float = 0.0,
+                 closing_radius: int = 4, n_min: int = 10, max_pixels: int = 1 << 20, device="cuda",
+                 n_base_widths: int = 0, width_alpha: float = 0.0):
+        import torch
+        self._w = np.ascontiguousarray(widths, dtype=np.int32)
+        d = capi.DetectDesc()
+        d.widths = self._w.ctypes.data_as(C.POINTER(C.c_int32))
+        d.nwidths = self._w.size
+        d.threshold = threshold
+        d.sigma_min = sigma_min
+        d.closing_radius = closing_radius
+        d.n_min = n_min
+        d.n_base_widths = n_base_widths
+        d.width_alpha = width_alpha
+        d.max_pixels = max_pixels
+        self.desc = d
+        self.device = torch.device(device)
+        self.widths = [int(w) for w in self._w]
+        self.ws = None
+        self.cap = 1 << 12  # candidates kept per beam
+        self.npixels = []
+
+    def launch(self, plans, planes, stage_cells: int = 1 << 18, stream=None):
+        """Enqueue the detection of planes[i] (of plans[i]) and the read-back of up to stage_cells
+        cells of all of them; returns a ticket for collect().  The workspace is reused in stream
+        order; the planes must stay unchanged until collect() returns."""
+        import torch
+        n = len(plans)
+        ph = (C.c_void_p * n)(*[p.handle for p in plans])
+        nb = C.c_int64()
+        capi.check(capi.lib().snd_detect_batch_workspace(n, ph, C.byref(self.desc), C.byref(nb)))
+        if self.ws is None or self.ws.numel() < nb.value:
+            self.ws = torch.empty(nb.value, dtype=torch.uint8, device=self.device)
+        dp = (C.c_void_p * n)(*[y.data_ptr() for y in planes])
+        pit = (C.c_int64 * n)(*[y.stride(0) for y in planes])
+        sb = capi.DETECT_STAGE_HEADER + capi.DETECT_CELL_BYTES * int(stage_cells)
+        stage = torch.empty(sb, dtype=torch.uint8, pin_memory=True)
+        capi.check(capi.lib().snd_detect_batch_launch(n, ph, dp, pit, C.byref(self.desc),
+                                                      C.c_void_p(self.ws.data_ptr()), self.ws.numel(),
+                                                      C.c_void_p(stage.data_ptr()), sb,
+                                                      _stream_handle(stream, self.device)))
+        st = torch.cuda.current_stream(self.device) if stream is None else stream
+        ev = torch.cuda.Event()
+        ev.record(st)
+        return (list(plans), list(planes), ph, stage, ev, st)
+
+    def collect(self, ticket):
+        """Candidates of each launched beam (a list of lists of dicts, as Detector.run); falls back
+        to one Detector run per beam when the staged cells do not hold them all."""
+        plans, planes, ph, stage, ev, st = ticket
+        ev.synchronize()
+        n = len(plans)
+        buf = (capi.Candidate * (n * self.cap))()
+        cnt, npx = (C.c_int64 * n)(), (C.c_int64 * n)()
+        rc = capi.lib().snd_detect_batch_collect(n, ph, C.byref(self.desc), C.c_void_p(stage.data_ptr()),
+                                                 stage.numel(), buf, self.cap, cnt, npx)
+        if rc == capi.ERR_CAPACITY:
+            out = []
+            for p, y in zip(plans, planes):
+                d = Detector(p, widths=self.widths, threshold=self.desc.threshold, sigma_min=self.desc.sigma_min,
+                             closing_radius=self.desc.closing_radius, n_min=self.desc.n_min,
+                             max_pixels=self.desc.max_pixels, device=self.device,
+                             n_base_widths=self.desc.n_base_widths, width_alpha=self.desc.width_alpha)
+                out.append(d.run(y, stream=st))
+            return out
+        capi.check(rc)
+        self.npixels = [int(v) for v in npx]
+        out = []
+        for i in range(n):
+            rows = []
+            for j in range(min(int(cnt[i]), self.cap)):
+                c = buf[i * self.cap + j]
+                rows.append(dict(k=c.dm_index, t=c.t, width=c.width, widx=self.widths.index(c.width), snr=c.snr,
+                                 dm=c.dm, npix=c.npix))
+            out.append(rows)
+        return out

@@ -9,7 +9,7 @@ from __future__ import annotations
 import time
 
 from . import _capi as capi
-from .detect import Detector
+from .detect import BatchDetector, Detector
 from .plan import cast, encode
 from .stream import Stream, admission_bytes, history_bytes
 
@@ -29,6 +29,8 @@ class Server:
         self.stream = Stream(budget_bytes, device)
         self.det = {k: Detector(p, widths=widths, threshold=threshold, n_min=n_min, device=device)
                     for k, (p, _) in kinds.items()}
+        # the batched form detects all complete chunks of a push in shared grids
+        self.bdet = BatchDetector(widths=widths, threshold=threshold, n_min=n_min, device=device) if batched else None
         self.kind_of, self.out = {}, {}
         self.ws = None
         if not batched:
@@ -76,6 +78,18 @@ class Server:
             x = encode(z, thr) if thr is not None else (z if plan.in_dtype == "f32" else cast(z, plan.in_dtype))
             items.append((beam, idx, x, self.out[beam]))
         res = self.stream.push(items, workspace=self.ws, batched=self.batched)
+        if self.batched:
+            # the complete chunks of every beam in one batched detection: shared grids, one
+            # read-back, candidates extracted per beam on the host
+            full = [i for i, ((beam, _, _, _), (t0, n, st)) in enumerate(zip(items, res))
+                    if n == self.kinds[self.kind_of[beam]][0].n_out]
+            found = {}
+            if full:
+                tk = self.bdet.launch([self.kinds[self.kind_of[items[i][0]]][0] for i in full],
+                                      [items[i][3] for i in full], stage_cells=self.stage_cells * len(full))
+                found = dict(zip(full, self.bdet.collect(tk)))
+            return [(beam, idx, t0, n, found.get(i)) for i, ((beam, idx, _, _), (t0, n, _)) in
+                    enumerate(zip(items, res))]
         # every complete chunk's detection is enqueued first (kernels and the read-back of its
         # thresholded cells, on the push's stream), then the host extracts the candidates of
         # each in turn while the device works through the rest

@@ -378,3 +378,37 @@ def test_detect_edge_cases_both_labelling_paths(snd, orc):
     d1.run(torch.tensor([[3], [0], [9]], dtype=torch.uint8, device="cuda"))
     mu, sg = d1.row_stats()
     assert np.array_equal(sg.cpu().numpy(), [0.0, 0.0, 0.0]) and np.array_equal(mu.cpu().numpy(), [3.0, 0.0, 9.0])
+
+
+@pytest.mark.parametrize("scaled", [False, True])
+def test_batched_detection_equals_per_beam(snd, orc, scaled):
+    """snd_detect_batch_*: planes of four beams with different plans (graded u8, float f32,
+    binary u8, graded u16; different DM grids and lengths) detected in shared grids give each
+    beam the candidates and cell counts of its own detection."""
+    beams = [("graded", dict(cap=255), 64, 120, 60.0, 9000), ("float", {}, 96, 200, 80.0, 12000),
+             ("binary", dict(k_leaf=2, k_int=1), 64, 77, 40.0, 7000), ("graded", dict(cap=4095), 128, 150, 100.0, 8000)]
+    rng = synth.make_rng(404)
+    plans, planes = [], []
+    for mode, kw, nchan, ndm, dmax, nsamp in beams:
+        f = synth.channel_freqs(nchan)
+        dms = np.sort(rng.uniform(0, dmax, ndm))
+        z = synth.noise_filterbank(rng, nchan, nsamp)
+        synth.inject_pulses(z, f, 0.138e-3, [synth.Pulse(dm=dmax * 0.6, t0=nsamp / 3.0, width_ms=2.0, snr=60.0)])
+        x = z if mode == "float" else orc.encode(z, [1.0, 2.0, 3.0, 4.0] if mode == "graded" else [2.0])
+        p = snd.Plan(f, dms, 0.138e-3, nsamp, mode=mode, branching=4, **kw)
+        planes.append(p.execute(torch.from_numpy(np.ascontiguousarray(x)).cuda()))
+        plans.append(p)
+    torch.cuda.synchronize()
+    kw = dict(widths=(1, 2, 4, 8, 16, 32), threshold=6.0, sigma_min=0.15, n_min=3)
+    if scaled:
+        kw.update(n_base_widths=2, width_alpha=0.1)
+    bd = snd.BatchDetector(**kw)
+    got = bd.collect(bd.launch(plans, planes, stage_cells=1 << 16))
+    total = 0
+    for i, (p, y) in enumerate(zip(plans, planes)):
+        d = snd.Detector(p, **kw)
+        want = d.run(y)
+        assert got[i] == want, i
+        assert bd.npixels[i] == d.npixels, i
+        total += len(want)
+    assert total > 0
