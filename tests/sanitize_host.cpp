@@ -183,6 +183,7 @@ static void detection()
     std::vector<snd_candidate> out(256);
     int64_t nc = 0, npx = 0;
     CHECK(snd_detect_collect(p, &d, stage.data(), bytes, out.data(), (int64_t)out.size(), &nc, &npx));
+    const int64_t nc_single = nc;
     if (nc < 1 || npx != (int64_t)cells.size()) {
         std::fprintf(stderr, "collect: %lld candidates from %lld cells\n", (long long)nc, (long long)npx);
         std::exit(1);
@@ -192,6 +193,30 @@ static void detection()
     std::memcpy(stage.data(), &over, 4);
     EXPECT(snd_detect_collect(p, &d, stage.data(), bytes, out.data(), (int64_t)out.size(), &nc, &npx),
            SND_ERR_CAPACITY);
+
+    // batched: the same cells as the first beam's (the float plan's), whose rows follow the
+    // graded plan's in batch-row order (u8 planes first); nothing in the graded beam
+    const Shape g{48, 30, 50.0, 4000, SND_MODE_GRADED, 4, 4, 255, SND_DT_U8, SND_DT_U8, 0, 0, 0, 0};
+    const std::vector<double> fg = band(g.nchan), dg = grid(g.ndm, g.dm_hi);
+    snd_plan pg = nullptr;
+    CHECK(make(g, fg, dg, &pg));
+    const snd_plan both[2] = {p, pg};
+    int64_t wsb = 0;
+    CHECK(snd_detect_batch_workspace(2, both, &d, &wsb));
+    std::vector<Cell> shifted = cells;
+    for (Cell &c : shifted) c.k += g.ndm;
+    std::memcpy(stage.data(), &count, 4);
+    std::memcpy(stage.data() + SND_DETECT_STAGE_HEADER, shifted.data(), shifted.size() * sizeof(Cell));
+    std::vector<snd_candidate> bout(2 * 128);
+    int64_t cnts[2], npxs[2];
+    CHECK(snd_detect_batch_collect(2, both, &d, stage.data(), bytes, bout.data(), 128, cnts, npxs));
+    if (cnts[1] != 0 || npxs[1] != 0 || cnts[0] != nc_single || npxs[0] != (int64_t)cells.size()) {
+        std::fprintf(stderr, "batched collect: %lld/%lld candidates\n", (long long)cnts[0], (long long)cnts[1]);
+        std::exit(1);
+    }
+    d.sigma_estimator = 1;  // the median-absolute-deviation sigma is single-plane only
+    EXPECT(snd_detect_batch_workspace(2, both, &d, &wsb), SND_ERR_UNSUPPORTED);
+    CHECK(snd_plan_destroy(pg));
     CHECK(snd_plan_destroy(p));
 }
 
