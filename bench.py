@@ -282,6 +282,59 @@ def subband_leg(snd, torch, spec, x, pkw, dev, ref_out, reps=3):
     return res
 
 
+def subband_approx_leg(snd, torch, spec, x, dev, ref_out, nsub=32, coarse_step=8, reps=3):
+    import numpy as np
+    """Approximate (coarse-DM) sub-band dedispersion on the same float block: SND plans per
+    sub-band over every coarse_step-th DM, then one combine kernel for the fine DMs.  Cheaper
+    than the exact tree, at the cost of each sub-band's internal sweep taken at the coarse DM:
+    its error against the SND plane is reported with its time."""
+    sb = snd.SubbandApprox(spec.freqs, spec.dms, spec.tsamp_s, spec.nsamp, nsub=nsub, coarse_step=coarse_step,
+                           device=dev)
+    out = sb.empty_output()
+    stream = torch.cuda.current_stream(dev)
+    sb.execute(x, out=out)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        sb.execute(x, out=out)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    n = min(sb.n_out, ref_out.shape[1])
+    a, b = out[:, :n].float(), ref_out[:, :n].float()
+    rel = float(torch.sqrt(torch.mean((a - b) ** 2)) / torch.sqrt(torch.mean(b ** 2)).clamp_min(1e-30))
+
+    # sensitivity: boxcar S/N of each injected pulse at its nearest trial DM in both planes
+    def pulse_snr(plane, k, t0):
+        row = plane[k, :n].double()
+        sd = float(row.std())
+        lo, hi = max(0, t0 - 64), min(n, t0 + 128)
+        c = torch.cat([torch.zeros(1, dtype=row.dtype, device=row.device), torch.cumsum(row[lo:hi] - row.mean(), 0)])
+        best = 0.0
+        for w in (1, 2, 4, 8, 16, 32, 64):
+            if hi - lo > w:
+                best = max(best, float((c[w:] - c[:-w]).max()) / (sd * w ** 0.5))
+        return best
+    ratios = []
+    for pl in spec.pulses:
+        k = int(np.argmin(np.abs(spec.dms - pl.dm)))
+        t0 = int(round(pl.t0))
+        if t0 + 128 < n:
+            s_snd = pulse_snr(b, k, t0)
+            if s_snd > 0:
+                ratios.append(pulse_snr(a, k, t0) / s_snd)
+    res = dict(method=f"approximate sub-band ({nsub} sub-bands, every {coarse_step}th DM coarse)", ms=round(ms, 3),
+               value=sb.ndm * sb.n_out / (ms * 1e-3), unit="DM-time samples/s", coarse_dms=int(sb.coarse.size),
+               n_out=sb.n_out, rel_rms_vs_snd=rel,
+               pulse_snr_ratio_vs_snd=dict(mean=round(float(np.mean(ratios)), 3) if ratios else None,
+                                           min=round(float(np.min(ratios)), 3) if ratios else None,
+                                           pulses=len(ratios)))
+    del sb, out
+    torch.cuda.empty_cache()
+    return res
+
+
 def completeness(snd, spec, cands, n_out):
     """Injected pulses of the block recovered by the candidates: greedy one-to-one matching in
     decreasing S/N with |dDM| <= 10 and |dt| <= 0.5 W_eff (snd_match_injections).  cands:
@@ -973,6 +1026,10 @@ def main():
             result["subband"] = subband_leg(snd, torch, spec, x, pkw, dev, ref)
             result["subband"]["snd_tree_ms"] = round(float(stage_ms.sum()), 3)
             log(f"[bench] sub-band: {result['subband']['ms']} ms")
+            result["subband_approx"] = subband_approx_leg(snd, torch, spec, x, dev, ref)
+            result["subband_approx"]["snd_tree_ms"] = round(float(stage_ms.sum()), 3)
+            log(f"[bench] approximate sub-band: {result['subband_approx']['ms']} ms, "
+                f"pulse S/N vs SND {result['subband_approx']['pulse_snr_ratio_vs_snd']}")
     if "fdmt" in legs and mode == "float" and plan.in_dtype == "f32":
         log("[bench] FDMT baseline on the same block")
         torch.cuda.empty_cache()

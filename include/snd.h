@@ -485,6 +485,29 @@ snd_status snd_fdmt_execute(snd_fdmt p, const float *d_in, int64_t in_pitch, flo
 snd_status snd_fdmt_destroy(snd_fdmt p);
 
 /* ---------------------------------------------------------------------------------------
+ * Approximate (coarse-DM) sub-band dedispersion, a comparison baseline on the same GPU
+ * (Methods, "Classical dedispersion algorithms": the hierarchical methods SND is set against).
+ * The band is cut into sub-bands of adjacent channels.  Step one is an SND plan per sub-band
+ * over a coarse DM grid (every channel at its delay relative to the band's top frequency):
+ *     R_s[j](t) = sum_{c in s} x_c(t + delta_c(D_j)).
+ * Step two, this call: every fine DM d_k takes the coarse row j = coarse_row[k] of each sub-band
+ * and shifts it by the extra sweep of the sub-band's top channel c_s between D_j and d_k:
+ *     y_k(t) = sum_s R_s[j](t + offsets[k][s]),   offsets[k][s] = delta_{c_s}(d_k) - delta_{c_s}(D_j),
+ * exact when D_j = d_k, otherwise with each sub-band's internal sweep taken at D_j.
+ * d_planes: host array of nsub device pointers, plane s float32 [ncoarse][pitches[s]] with
+ * n_valid[s] valid samples per row; coarse_row [ndm] (0..ncoarse-1) and offsets [ndm][nsub]
+ * (>= 0) host arrays, uploaded by the call into d_workspace (>= snd_subband_workspace_bytes,
+ * 256-byte aligned); d_out float32 [ndm][out_pitch], n_out samples per row, each summed in FP32
+ * in sub-band order.  INVALID when a read would pass a plane's valid samples.  Asynchronous on
+ * stream.
+ * --------------------------------------------------------------------------------------- */
+snd_status snd_subband_workspace_bytes(int32_t ndm, int32_t nsub, int64_t *bytes);
+snd_status snd_subband_combine(int32_t ndm, int32_t nsub, const float *const *d_planes, const int64_t *pitches,
+                               const int64_t *n_valid, int32_t ncoarse, const int32_t *coarse_row,
+                               const int32_t *offsets, float *d_out, int64_t out_pitch, int64_t n_out,
+                               void *d_workspace, int64_t workspace_bytes, void *stream);
+
+/* ---------------------------------------------------------------------------------------
  * Validation against injected pulses (Methods, "Validation methodology").  Host only.
  * --------------------------------------------------------------------------------------- */
 

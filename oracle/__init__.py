@@ -236,6 +236,37 @@ def bruteforce(x, delay, *, mode="float") -> np.ndarray:
     return y
 
 
+def subband_approx(x, freqs, dms, tsamp_s: float, nsub: int, coarse_step: int) -> np.ndarray:
+    """Approximate (coarse-DM) sub-band dedispersion, written out in FP64 (Methods, "Classical
+    dedispersion algorithms": the hierarchical baselines).  Sub-bands are runs of nchan / nsub
+    channels in the given order; the coarse grid is every coarse_step-th of the sorted distinct
+    DMs; fine DM d_k takes the largest coarse DM D_j <= d_k.  With delta the integer delays
+    relative to the top frequency (delays()) and c_s the top channel of sub-band s:
+        y_k(t) = sum_s sum_{c in s} x_c(t + delta_c(D_j) + delta_{c_s}(d_k) - delta_{c_s}(D_j)),
+    for t below the smallest number of samples every term has.  Returns float64 [ndm][n_out].
+    Plain loops over DMs and channels: for small cases."""
+    x = np.asarray(x, dtype=np.float64)
+    f = np.asarray(freqs, dtype=np.float64)
+    d = np.asarray(dms, dtype=np.float64)
+    nchan, nsamp = x.shape
+    m = nchan // nsub
+    coarse = np.unique(d)[::coarse_step]
+    j = np.searchsorted(coarse, d, side="right") - 1
+    dF, dC = delays(f, d, tsamp_s), delays(f, coarse, tsamp_s)
+    tops = [s * m + int(np.argmax(f[s * m:(s + 1) * m])) for s in range(nsub)]
+    shift = np.empty((d.size, nchan), dtype=np.int64)  # total read offset of each (DM, channel)
+    for s in range(nsub):
+        extra = dF[:, tops[s]].astype(np.int64) - dC[j, tops[s]]
+        for c in range(s * m, (s + 1) * m):
+            shift[:, c] = dC[j, c] + extra
+    n_out = nsamp - int(shift.max())
+    y = np.zeros((d.size, n_out))
+    for k in range(d.size):
+        for c in range(nchan):
+            y[k] += x[c, shift[k, c]:shift[k, c] + n_out]
+    return y
+
+
 def encode(z: np.ndarray, thresholds) -> np.ndarray:
     """uint8 level = number of thresholds exceeded (z > theta), compared in float32."""
     lib = _load()

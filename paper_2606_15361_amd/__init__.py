@@ -14,7 +14,8 @@ from .batch import Batch, records_bytes  # noqa: F401
 from .multirate import MultiRate, scrunch, scrunch_factors, merge_candidates  # noqa: F401
 from .validate import effective_width, match_injections  # noqa: F401
 from .fdmt import Fdmt  # noqa: F401
+from .subband import SubbandApprox  # noqa: F401
 
 __all__ = ["Plan", "autotune", "autotune_cached", "tune_word", "tune_fields", "Detector", "BatchDetector", "Stream", "Batch", "history_bytes", "admission_bytes", "records_bytes", "encode", "encode_bits",
            "cast", "channel_stats", "normalize", "zero_dm", "flag_channels", "MultiRate", "scrunch", "scrunch_factors", "merge_candidates",
-           "effective_width", "match_injections", "Fdmt", "SndError", "LIB_PATH"]
+           "effective_width", "match_injections", "Fdmt", "SubbandApprox", "SndError", "LIB_PATH"]

@@ -131,6 +131,8 @@ def lib() -> C.CDLL:
         "snd_fdmt_upload": ([P, P, I64, P], I32),
         "snd_fdmt_execute": ([P, P, I64, P, I64, P, I64, P], I32),
         "snd_fdmt_destroy": ([P], I32),
+        "snd_subband_workspace_bytes": ([I32, I32, C.POINTER(I64)], I32),
+        "snd_subband_combine": ([I32, I32, P, P, P, I32, P, P, P, I64, I64, P, I64, P], I32),
         "snd_match_injections": ([I64, P, P, P, I64, P, P, P, C.c_double, C.c_double, P, C.POINTER(I64)], I32),
         "snd_last_error": ([], C.c_char_p),
         "snd_version": ([], C.c_char_p),

@@ -20,7 +20,7 @@ HIP_SOURCES = ["kernels.hip", "kernels_lds.hip", "kernels_fast_binary.hip", "ker
                "kernels_fast_float.hip", "kernels_bits.hip", "detect.hip", "label.hip",
                "detect_noalloc.hip", "group_lin.hip", "group_pack.hip"]
 CXX_SOURCES = ["plan.cpp", "capi.cpp", "detect_host.cpp", "stream_host.cpp", "batch_host.cpp", "tune_host.cpp",
-               "multirate_host.cpp", "validate_host.cpp", "fdmt_host.cpp"]
+               "multirate_host.cpp", "validate_host.cpp", "fdmt_host.cpp", "subband_host.cpp"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function", "-ffp-contract=off",
           "-I" + os.path.join(ROOT, "include"), "-I" + CSRC]

@@ -503,6 +503,41 @@ int launch_fdmt_merge(const float *src, int64_t sp, float *dst, int64_t dp, cons
     return (int)hipGetLastError();
 }
 
+// Approximate sub-band dedispersion, second step: out row k = sum over sub-bands s of row
+// coarse[k] of sub-band plane s, read offs[k * nsub + s] samples later, in FP32 in sub-band
+// order.  A workgroup covers 1024 samples of one row, 4 per lane (coalesced reads of each plane
+// row); the table words are uniform (scalar loads).
+__global__ __launch_bounds__(256) void k_subband_combine(const float *const *planes, const int64_t *pitches,
+                                                         const int32_t *coarse, const int32_t *offs, int nsub,
+                                                         float *out, int64_t op, int64_t n)
+{
+    const int k = blockIdx.y;
+    const int64_t t0 = (int64_t)blockIdx.x * 1024 + threadIdx.x;
+    const int j = coarse[k];
+    float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    for (int s = 0; s < nsub; ++s) {
+        const float *row = planes[s] + (int64_t)j * pitches[s] + offs[(int64_t)k * nsub + s];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int64_t t = t0 + 256 * i;
+            if (t < n) acc[i] += row[t];
+        }
+    }
+    float *o = out + (int64_t)k * op;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+        if (t0 + 256 * i < n) o[t0 + 256 * i] = acc[i];
+}
+
+int launch_subband_combine(const float *const *planes, const int64_t *pitches, const int32_t *coarse,
+                           const int32_t *offs, int nsub, int ndm, float *out, int64_t op, int64_t n, void *stream)
+{
+    if (ndm < 1 || n < 1) return 0;
+    hipLaunchKernelGGL(k_subband_combine, dim3((uint32_t)((n + 1023) / 1024), (uint32_t)ndm), dim3(256), 0,
+                       (hipStream_t)stream, planes, pitches, coarse, offs, nsub, out, op, n);
+    return (int)hipGetLastError();
+}
+
 int launch_zero_dm(float *z, int64_t zp, int nchan, int64_t n, double gamma, int32_t *count, void *stream)
 {
     const int64_t nb = (n + 255) / 256;

@@ -70,3 +70,32 @@ def test_no_smear_spike_track_sums_every_channel(orc):
         y = orc.fdmt(x, f, bw, 0.138e-3, dm)
         assert y[d, 100] == 32.0
         assert y.max() == 32.0
+
+
+def test_subband_approx_pins():
+    """Approximate sub-band dedispersion: with every DM on the coarse grid it is brute-force
+    dedispersion; otherwise the rows whose DM lies on the coarse grid still are, and the others
+    differ only through the sub-bands' internal sweeps (bounded by the pulse smear)."""
+    import oracle as orc
+    rng = synth.make_rng(515)
+    f = synth.channel_freqs(32)
+    dms = np.sort(rng.uniform(0, 80.0, 40))
+    d = orc.delays(f, dms, 0.138e-3)
+    x = rng.standard_normal((32, int(d.max()) + 400))
+    exact = orc.bruteforce(x, d)
+    y1 = orc.subband_approx(x, f, dms, 0.138e-3, nsub=4, coarse_step=1)
+    assert y1.shape == exact.shape and np.allclose(y1, exact, rtol=0, atol=1e-12)
+    y4 = orc.subband_approx(x, f, dms, 0.138e-3, nsub=4, coarse_step=4)
+    on_grid = np.isin(dms, np.unique(dms)[::4])
+    n = min(y4.shape[1], exact.shape[1])
+    assert np.allclose(y4[on_grid, :n], exact[on_grid, :n], rtol=0, atol=1e-12)
+    assert not np.allclose(y4[~on_grid, :n], exact[~on_grid, :n])
+    # a delta pulse: every sub-band's channels meet at the same time only on the coarse grid;
+    # off the grid the channels of a sub-band land within its internal sweep difference
+    z = np.zeros((32, int(d.max()) + 400))
+    t0 = 150
+    k = int(np.flatnonzero(~on_grid)[0])
+    for c in range(32):
+        z[c, t0 + d[k, c]] = 1.0
+    yz = orc.subband_approx(z, f, dms, 0.138e-3, nsub=4, coarse_step=4)
+    assert yz[k].sum() == 32.0 and yz[k].max() < 32.0
