@@ -90,8 +90,7 @@ typedef struct {
     int32_t in_dtype;        /* input samples: U8 for binary/graded (binary: non-zero = spike);
                                 F32, BF16 or F16 for float.  Binary also takes BITS input (rows of
                                 bits, in_pitch in bits and a multiple of 32), which needs
-                                node_dtype BITS, cluster <= 15 and a plain (chunk = 0) plan;
-                                UNSUPPORTED otherwise */
+                                node_dtype BITS and cluster <= 15; UNSUPPORTED otherwise */
     int32_t node_dtype;      /* storage of materialised tree rows: BITS or U8 for binary; U8
                                 (cap <= 255) or U16 for graded; F32, BF16 or F16 for float (FP32
                                 accumulate).  BITS needs the default schedule (leaf level
@@ -608,14 +607,14 @@ snd_status snd_autotune(const snd_plan_desc *desc, snd_tune_candidate *cands, in
 typedef struct snd_stream_s *snd_stream;
 
 /* Device bytes of one beam's history for this plan (ring of nchan x (max_delay + n_out)
- * input samples, rows padded to 256 bytes).  UNSUPPORTED for BITS input (streams take byte
- * or float input). */
+ * input samples, rows padded to 256 bytes).  BITS input keeps one bit per sample, the ring
+ * length rounded up to a whole number of 32-bit words. */
 snd_status snd_stream_history_bytes(snd_plan plan, int64_t *bytes);
 
 /* Device bytes a beam of this plan is charged against the stream's budget: its history ring
  * (snd_stream_history_bytes) plus its share of a batched push's workspace (the plan's
  * workspace_bytes rounded up to 256), so that the beams a budget admits can also be pushed
- * together.  UNSUPPORTED for BITS input. */
+ * together. */
 snd_status snd_stream_admission_bytes(snd_plan plan, int64_t *bytes);
 
 /* New stream that admits beams while the sum of their admission bytes
@@ -635,7 +634,9 @@ snd_status snd_stream_evict(snd_stream s, int32_t beam_id);
 
 /* One chunk of one beam in a push.  Inputs: beam_id, chunk_idx (must follow the beam's
  * previous chunk index by one), chunk_len (1 .. n_out of the beam's plan), d_chunk
- * [nchan][chunk_pitch] in the plan's input dtype, d_out [ndm][out_pitch] in the plan's output
+ * [nchan][chunk_pitch] in the plan's input dtype (BITS: chunk_len and chunk_pitch counted in
+ * bits, the pitch a multiple of 32 and d_chunk 4-byte aligned; bit i of word w of a row is
+ * sample 32 w + i of the chunk, as snd_encode_bits writes), d_out [ndm][out_pitch] in the plan's output
  * dtype with out_pitch >= n_out.  Outputs: out_t0 = output time of column 0 of d_out,
  * out_n = output samples written (0 while the first max_delay samples fill the history),
  * status = SND_OK or SND_ERR_GAP. */

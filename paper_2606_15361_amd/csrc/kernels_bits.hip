@@ -240,12 +240,25 @@ __global__ __launch_bounds__(256) void k_anchored_bits(AnchorArgs s0, Multi m)
     const int64_t wp = s.src_pitch >> 5;  // words per input row
     const int64_t w0 = tau0 >> 5;         // first staged word
     const int ntot = (c1 - c0) * nw;
+    // a ring (streaming): sample i of the run sits at ring bit (ring_start + i) mod ring_len,
+    // ring_len a whole number of words, so the run's word k is a funnel shift of ring words
+    // q, q + 1 (mod the ring) with q = ring_start / 32 + k
+    const int64_t rw = s.ring_len >> 5, q0 = s.ring_start >> 5;
+    const uint32_t rb = (uint32_t)(s.ring_start & 31);
     for (int j = tid; j < ntot; j += 256) {
         const int c = j / nw, k = j - c * nw;
         const int64_t sb = 32 * (w0 + k);  // first sample of the word
         uint32_t v = 0u;
         if (sb < s.src_len) {
-            v = src[(int64_t)(c0 + c) * wp + w0 + k];
+            const auto row = src + (int64_t)(c0 + c) * wp;
+            if (rw > 0) {
+                int64_t q = q0 + w0 + k;
+                q = q >= rw ? q % rw : q;
+                const int64_t q1 = q + 1 == rw ? 0 : q + 1;
+                v = rb ? __builtin_amdgcn_alignbit(row[q1], row[q], rb) : row[q];
+            } else {
+                v = row[w0 + k];
+            }
             const int64_t left = s.src_len - sb;
             if (left < 32) v &= (1u << left) - 1u;
         }
@@ -293,12 +306,51 @@ int launch_bits_shape(const GroupArgs &a, int64_t n_out, int lds, hipStream_t st
     return (int)hipGetLastError();
 }
 
+// A streamed bit chunk into its beam's ring: L bits of chunk row c (from bit 0) go to ring bit
+// positions pos, pos + 1, ... of row c, wrapping at R (a whole number of words).  One thread per
+// ring word touched (the positions [pos, min(pos + L, R)) and then [0, pos + L - R)); each word
+// keeps its bits outside that range.  Bit by bit: a chunk is a few thousand bits per row.
+__global__ __launch_bounds__(256) void k_ring_put_bits(const uint32_t *chunk, int64_t cw, uint32_t *ring, int64_t rwp,
+                                                       int64_t R, int64_t pos, int64_t L)
+{
+    const int c = blockIdx.y;
+    const int64_t e0 = pos + L < R ? pos + L : R;  // first segment [pos, e0), source bits from 0
+    const int64_t e1 = pos + L - R;                // second segment [0, e1) when > 0, from R - pos
+    const int64_t n0 = (e0 - 1) / 32 - pos / 32 + 1, n1 = e1 > 0 ? (e1 - 1) / 32 + 1 : 0;
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n0 + n1) return;
+    const int64_t a = i < n0 ? pos : 0, b = i < n0 ? e0 : e1, so = i < n0 ? 0 : R - pos;
+    const int64_t w = i < n0 ? pos / 32 + i : i - n0;
+    const uint32_t *src = chunk + (int64_t)c * cw;
+    uint32_t v = ring[(int64_t)c * rwp + w];
+    for (int k = 0; k < 32; ++k) {
+        const int64_t p = 32 * w + k;
+        if (p < a || p >= b) continue;
+        const int64_t sbit = so + (p - a);
+        const uint32_t bit = (src[sbit >> 5] >> (sbit & 31)) & 1u;
+        v = (v & ~(1u << k)) | (bit << k);
+    }
+    ring[(int64_t)c * rwp + w] = v;
+}
+
 }  // namespace
+
+int launch_ring_put_bits(const uint32_t *chunk, int64_t chunk_words, uint32_t *ring, int64_t ring_words, int64_t R,
+                         int64_t pos, int64_t L, int nchan, void *stream)
+{
+    if (L < 1 || nchan < 1) return 0;
+    if ((R & 31) != 0 || pos < 0 || pos >= R || L > R || 32 * chunk_words < L || 32 * ring_words < R)
+        return (int)hipErrorInvalidValue;
+    const int64_t words = L / 32 + 2;  // ring words one chunk can touch, at most
+    hipLaunchKernelGGL(k_ring_put_bits, dim3((uint32_t)((words + 255) / 256), (uint32_t)nchan), dim3(256), 0,
+                       (hipStream_t)stream, chunk, chunk_words, ring, ring_words, R, pos, L);
+    return (int)hipGetLastError();
+}
 
 int launch_anchored_bits(const AnchorArgs &a, int64_t ntiles, int lds, void *stream, const Multi &m)
 {
     if (ntiles <= 0) return 0;
-    if (ntiles > 0x7fffffffLL || a.depth != 1 || a.ring_len != 0) return (int)hipErrorInvalidValue;
+    if (ntiles > 0x7fffffffLL || a.depth != 1 || (a.ring_len & 31) != 0) return (int)hipErrorInvalidValue;
     hipLaunchKernelGGL((k_anchored_bits<kAnchorBitsW>), dim3((uint32_t)ntiles), dim3(256), lds, (hipStream_t)stream, a,
                        m);
     return (int)hipGetLastError();

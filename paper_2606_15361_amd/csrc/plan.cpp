@@ -512,8 +512,8 @@ snd_status build_plan(const snd_plan_desc &d, PlanImpl &p, std::string &err)
         err = "unsupported input/node dtype for this mode";
         return SND_ERR_UNSUPPORTED;
     }
-    if (d.in_dtype == SND_DT_BITS && (d.chunk > 0 || d.cluster > 15)) {
-        err = "bit input needs a plain (chunk = 0) plan and cluster <= 15";
+    if (d.in_dtype == SND_DT_BITS && d.cluster > 15) {
+        err = "bit input needs cluster <= 15";
         return SND_ERR_UNSUPPORTED;
     }
     p.desc = d;

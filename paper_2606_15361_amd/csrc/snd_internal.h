@@ -310,6 +310,10 @@ int launch_normalize(const float *p, int64_t p_pitch, int nchan, int64_t n, cons
                      int64_t z_pitch, void *stream);
 int launch_cast(const float *src, int64_t src_pitch, int64_t rows, int64_t cols, void *dst, int64_t dst_pitch,
                 int dst_dtype, void *stream);
+// Bit rows: copy L bits of each of nchan chunk rows (from bit 0) into a ring of R bits per row
+// (R a multiple of 32) at ring bit position pos, wrapping at R; the ring's other bits keep.
+int launch_ring_put_bits(const uint32_t *chunk, int64_t chunk_words, uint32_t *ring, int64_t ring_words, int64_t R,
+                         int64_t pos, int64_t L, int nchan, void *stream);
 
 // Compile-time shape of the kernel instance that runs stage S: the depth class, or, for the
 // specialised row-group kernel, 1000 * (inputs per level-1 node) + depth; -1 for the linear

@@ -41,13 +41,22 @@ int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 struct RingShape {
     int64_t ring_len;  // R
     int64_t pitch;     // elements per ring row
-    int64_t es;        // bytes per element
+    int64_t es;        // bytes per element; 0 for bit input (one bit per sample)
     int64_t bytes;
 };
 
+// Bit input keeps one bit per sample: R is a whole number of 32-bit words, so that ring
+// positions wrap at a word boundary, and rows are padded to 256 bytes.
 RingShape ring_shape(const snd::PlanImpl &P)
 {
     RingShape r{};
+    if (P.desc.in_dtype == SND_DT_BITS) {
+        r.es = 0;
+        r.ring_len = round_up(P.max_delay + P.n_out, 32);
+        r.pitch = round_up(r.ring_len, 2048);
+        r.bytes = (int64_t)P.nchan * r.pitch / 8;
+        return r;
+    }
     r.es = snd::dtype_size(P.desc.in_dtype);
     r.ring_len = P.max_delay + P.n_out;
     r.pitch = round_up(r.ring_len * r.es, 256) / r.es;
@@ -100,7 +109,6 @@ extern "C" {
 snd_status snd_stream_history_bytes(snd_plan plan, int64_t *bytes)
 {
     if (!plan || !bytes) return fail(SND_ERR_INVALID, "null plan or output");
-    if (plan->impl.desc.in_dtype == SND_DT_BITS) return fail(SND_ERR_UNSUPPORTED, "bit input is not streamed");
     *bytes = ring_shape(plan->impl).bytes;
     return SND_OK;
 }
@@ -108,7 +116,6 @@ snd_status snd_stream_history_bytes(snd_plan plan, int64_t *bytes)
 snd_status snd_stream_admission_bytes(snd_plan plan, int64_t *bytes)
 {
     if (!plan || !bytes) return fail(SND_ERR_INVALID, "null plan or output");
-    if (plan->impl.desc.in_dtype == SND_DT_BITS) return fail(SND_ERR_UNSUPPORTED, "bit input is not streamed");
     *bytes = admission_charge(plan->impl);
     return SND_OK;
 }
@@ -137,7 +144,6 @@ snd_status snd_stream_admit(snd_stream s, int32_t beam_id, snd_plan plan, void *
     if (beam_id < 0) return fail(SND_ERR_INVALID, "beam id must be >= 0");
     if (s->beams.count(beam_id)) return fail(SND_ERR_INVALID, "beam already admitted");
     const snd::PlanImpl &P = plan->impl;
-    if (P.desc.in_dtype == SND_DT_BITS) return fail(SND_ERR_UNSUPPORTED, "bit input is not streamed");
     if (P.stages.empty() || P.stages[0].kernel != snd::kKernelAnchored || P.stages[0].final_stage)
         return fail(SND_ERR_UNSUPPORTED,
                     "streaming needs a plan whose first stage is the input-anchored kernel (default schedule)");
@@ -195,6 +201,8 @@ snd_status push_impl(snd_stream s, int32_t n, snd_stream_item *items, void *d_wo
         if (it.chunk_len < 1 || it.chunk_len > P.n_out)
             return fail(SND_ERR_INVALID, "item " + std::to_string(i) + ": chunk_len must be in 1..n_out of the plan");
         if (it.chunk_pitch < it.chunk_len) return fail(SND_ERR_INVALID, "item " + std::to_string(i) + ": chunk pitch");
+        if (P.desc.in_dtype == SND_DT_BITS && (it.chunk_pitch % 32 || ((uintptr_t)it.d_chunk & 3u)))
+            return fail(SND_ERR_INVALID, "item " + std::to_string(i) + ": bit chunks need whole 32-bit words per row");
         if (it.out_pitch < P.n_out) return fail(SND_ERR_INVALID, "item " + std::to_string(i) + ": output pitch < n_out");
         if (it.chunk_idx < 0) return fail(SND_ERR_INVALID, "item " + std::to_string(i) + ": negative chunk index");
         if (!P.d_table) return fail(SND_ERR_STATE, "item " + std::to_string(i) + ": plan tables not uploaded");
@@ -245,13 +253,21 @@ snd_status push_impl(snd_stream s, int32_t n, snd_stream_item *items, void *d_wo
         const int64_t c0 = b.received % r.ring_len;
         const int64_t n1 = std::min(L, r.ring_len - c0);
         const uint8_t *src = static_cast<const uint8_t *>(it.d_chunk);
-        hipError_t e = hipMemcpy2DAsync(b.ring + c0 * r.es, (size_t)(r.pitch * r.es), src,
-                                        (size_t)(it.chunk_pitch * r.es), (size_t)(n1 * r.es), (size_t)P.nchan,
-                                        hipMemcpyDeviceToDevice, st);
-        if (e == hipSuccess && n1 < L)
-            e = hipMemcpy2DAsync(b.ring, (size_t)(r.pitch * r.es), src + n1 * r.es, (size_t)(it.chunk_pitch * r.es),
-                                 (size_t)((L - n1) * r.es), (size_t)P.nchan, hipMemcpyDeviceToDevice, st);
-        if (e != hipSuccess) return hip_fail(e, "hipMemcpy2DAsync(chunk into history)");
+        hipError_t e = hipSuccess;
+        if (r.es == 0) {  // bit rows: a kernel merges the chunk's bits into the ring's words
+            const int rc = snd::launch_ring_put_bits(static_cast<const uint32_t *>(it.d_chunk), it.chunk_pitch / 32,
+                                                     reinterpret_cast<uint32_t *>(b.ring), r.pitch / 32, r.ring_len,
+                                                     c0, L, P.nchan, st);
+            e = (hipError_t)rc;
+        } else {
+            e = hipMemcpy2DAsync(b.ring + c0 * r.es, (size_t)(r.pitch * r.es), src, (size_t)(it.chunk_pitch * r.es),
+                                 (size_t)(n1 * r.es), (size_t)P.nchan, hipMemcpyDeviceToDevice, st);
+            if (e == hipSuccess && n1 < L)
+                e = hipMemcpy2DAsync(b.ring, (size_t)(r.pitch * r.es), src + n1 * r.es,
+                                     (size_t)(it.chunk_pitch * r.es), (size_t)((L - n1) * r.es), (size_t)P.nchan,
+                                     hipMemcpyDeviceToDevice, st);
+        }
+        if (e != hipSuccess) return hip_fail(e, "chunk into history");
         const int64_t S1 = b.received + L;
         const int64_t E1 = std::max<int64_t>(0, S1 - P.max_delay);
         const int64_t n_run = E1 - b.emitted;

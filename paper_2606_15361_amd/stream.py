@@ -77,7 +77,8 @@ class Stream:
         return w.value, r.value
 
     def push(self, items, workspace=None, stream=None, batched=False):
-        """items: sequence of (beam_id, chunk_idx, chunk [nchan][L] tensor, out [ndm][>= n_out] tensor).
+        """items: sequence of (beam_id, chunk_idx, chunk [nchan][L] tensor, out [ndm][>= n_out] tensor);
+        bit-input beams take (beam_id, chunk_idx, chunk int32 [nchan][words] of bit rows, out, L bits).
         Returns [(out_t0, out_n, status)] per item; a chunk-index gap resets that beam (status
         ERR_GAP) and is not raised; every other failure raises SndError.  batched=True runs the
         beams' stages in shared grids (snd_stream_push_batched); its workspace and record
@@ -85,15 +86,20 @@ class Stream:
         n = len(items)
         arr = (capi.StreamItem * max(1, n))()
         ws_need = 0
-        for i, (bid, idx, chunk, out) in enumerate(items):
+        for i, item in enumerate(items):
+            bid, idx, chunk, out = item[:4]
             plan = self._beams[int(bid)][0]
             if chunk.dim() != 2 or chunk.shape[0] != plan.nchan or chunk.stride(1) != 1:
                 raise ValueError("chunk must be [nchan][L] with unit time stride")
+            bits = plan.in_dtype == "bits"
+            if bits and len(item) != 5:
+                raise ValueError("a bit-input beam's item carries its chunk length in bits")
             if out.dim() != 2 or out.shape[0] != plan.ndm or out.stride(1) != 1 or out.dtype != plan.out_dtype:
                 raise ValueError("output must be [ndm][>= n_out] of the plan's output dtype")
             it = arr[i]
-            it.beam_id, it.chunk_idx, it.chunk_len = int(bid), int(idx), int(chunk.shape[1])
-            it.d_chunk, it.chunk_pitch = chunk.data_ptr(), chunk.stride(0)
+            it.beam_id, it.chunk_idx = int(bid), int(idx)
+            it.chunk_len = int(item[4]) if bits else int(chunk.shape[1])
+            it.d_chunk, it.chunk_pitch = chunk.data_ptr(), chunk.stride(0) * (32 if bits else 1)
             it.d_out, it.out_pitch = out.data_ptr(), out.stride(0)
             ws_need = max(ws_need, plan.info["workspace_bytes"])
         if batched:

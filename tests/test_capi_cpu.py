@@ -141,7 +141,7 @@ def test_plan_validation_errors(snd):
 
 
 def test_bit_input_plans(snd):
-    """Bit input: leaf stage on bit rows, bit-row final stage, not streamed."""
+    """Bit input: leaf stage on bit rows, bit-row final stage; streamed through a ring of bits."""
     from paper_2606_15361_amd import SndError, _capi
     f = synth.channel_freqs(64)
     dms = synth.dm_linear(40, 0, 60)
@@ -152,10 +152,14 @@ def test_bit_input_plans(snd):
     # same tree; the input read is 1/8 of the byte input's
     assert p.info["n_neurons"] == u.info["n_neurons"] and p.info["stage_entries"] == u.info["stage_entries"]
     assert u.info["stage_alg_bytes"][0] - p.info["stage_alg_bytes"][0] == 64 * 2000 - 64 * 2000 // 8
+    # a stream keeps one bit per sample: ring of whole words, rows padded to 256 bytes
+    q = snd.Plan(f, dms, 0.138e-3, None, mode="binary", branching=4, in_dtype="bits", chunk=512)
     nb = C.c_int64()
-    assert _capi.lib().snd_stream_history_bytes(p.handle, C.byref(nb)) == _capi.ERR_UNSUPPORTED
+    _capi.check(_capi.lib().snd_stream_history_bytes(q.handle, C.byref(nb)))
+    ring = -(-(q.info["max_delay"] + q.n_out) // 32) * 32
+    assert nb.value == 64 * (-(-ring // 2048) * 2048) // 8
     with pytest.raises(SndError) as ei:
-        snd.Plan(f, dms, 0.138e-3, None, mode="binary", branching=4, in_dtype="bits", chunk=512)
+        snd.Plan(f, dms, 0.138e-3, 2000, mode="binary", branching=4, in_dtype="bits", cluster=16)
     assert ei.value.status == _capi.ERR_UNSUPPORTED
     # bit input pitch must be whole words; encoder pitch likewise
     buf = (C.c_uint8 * 256)()

@@ -281,3 +281,61 @@ def test_batched_push_equals_per_beam_push(snd):
             if n:
                 assert torch.equal(oa[i][:, :n], ob[i][:, :n]), (step, i)
     assert gaps == 1
+
+
+def test_stream_bit_input_any_chunks(snd, orc):
+    """Binary beams fed rows of bits: each chunk (any length, any bit offset in the ring) is
+    merged into a ring of bits, and the output equals the plain execute on the whole bit
+    input and the oracle, through per-beam and batched pushes and a checkpoint restore."""
+    from bitrows import pack_bits
+    spec = synth.workload(1)
+    rng = synth.make_rng(5151)
+    chunk = 1000
+    plan = snd.Plan(spec.freqs, spec.dms, spec.tsamp_s, None, mode="binary", branching=4, chunk=chunk,
+                    in_dtype="bits", node_dtype="bits", k_leaf=2, k_int=1)
+    assert plan.info["stage_kernel"][0] == "anchored_bits"
+    total = plan.max_delay + 5 * chunk + 357
+    x = orc.encode(spec.filterbank(total), [2.0])
+    d = orc.delays(spec.freqs, spec.dms, spec.tsamp_s)
+    want, _ = orc.snd_dedup(x, spec.freqs, d, mode="binary", cluster=4, branching=4, k_leaf=2, k_int=1)
+    plain_plan = snd.Plan(spec.freqs, spec.dms, spec.tsamp_s, total, mode="binary", branching=4, in_dtype="bits",
+                          node_dtype="bits", k_leaf=2, k_int=1)
+    plain = to_np(plain_plan.execute(torch.from_numpy(pack_bits(x)).cuda()))
+    assert np.array_equal(plain, want.astype(plain.dtype))
+    lengths = chunk_lengths(rng, total, chunk)
+    _say(f"bit stream chunks={len(lengths)} total={total} max_delay={plan.max_delay}")
+    a, b = snd.Stream(1 << 34), snd.Stream(1 << 34)
+    a.admit(0, plan)
+    b.admit(0, plan)
+    ws = plan.workspace("cuda")
+    oa, ob = plan.empty_output("cuda"), plan.empty_output("cuda")
+    ya, yb, yc = [], [], []
+    c = oc = None
+    pos = 0
+    half = len(lengths) // 2
+    for i, L in enumerate(lengths):
+        xb = torch.from_numpy(pack_bits(x[:, pos:pos + L])).cuda()
+        (t0, n, s1), = a.push([(0, i, xb, oa, L)], workspace=ws)
+        (u0, m, s2), = b.push([(0, i, xb, ob, L)], batched=True)
+        assert (t0, n, s1) == (u0, m, s2) and s1 == 0
+        if c is not None:
+            (v0, k, s3), = c.push([(0, i, xb, oc, L)], workspace=ws)
+            assert (v0, k, s3) == (t0, n, s1)
+        torch.cuda.synchronize()
+        if n:
+            ya.append(to_np(oa[:, :n]))
+            yb.append(to_np(ob[:, :n]))
+            if c is not None:
+                yc.append(to_np(oc[:, :n]))
+        pos += L
+        if i == half:  # checkpoint the beam into a new stream, which then runs alongside
+            c = snd.Stream(1 << 34)
+            c.admit(0, plan)
+            c.restore(0, a.export(0))
+            oc = plan.empty_output("cuda")
+    y = np.concatenate(ya, axis=1)
+    assert np.array_equal(y, plain)
+    assert np.array_equal(np.concatenate(yb, axis=1), plain)
+    tail = np.concatenate(yc, axis=1)
+    assert np.array_equal(tail, plain[:, plain.shape[1] - tail.shape[1]:])
+    assert a.state(0) == dict(received=total, next_chunk=len(lengths), emitted=total - plan.max_delay)
