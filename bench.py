@@ -283,11 +283,11 @@ def subband_leg(snd, torch, spec, x, pkw, dev, ref_out, reps=3):
 
 
 def subband_approx_leg(snd, torch, spec, x, dev, ref_out, nsub=32, coarse_step=8, reps=3):
-    import numpy as np
     """Approximate (coarse-DM) sub-band dedispersion on the same float block: SND plans per
     sub-band over every coarse_step-th DM, then one combine kernel for the fine DMs.  Cheaper
     than the exact tree, at the cost of each sub-band's internal sweep taken at the coarse DM:
     its error against the SND plane is reported with its time."""
+    import numpy as np
     sb = snd.SubbandApprox(spec.freqs, spec.dms, spec.tsamp_s, spec.nsamp, nsub=nsub, coarse_step=coarse_step,
                            device=dev)
     out = sb.empty_output()

@@ -13,11 +13,15 @@
 //   threshold are appended to a global pixel list, each workgroup's cells as one segment in
 //   increasing t.  For the list, a per-width bound on the boxcar sum (in the prefix type)
 //   skips the cells that cannot reach the threshold; every cell that can takes the exact
-//   quotient.
+//   quotient.  u8 planes whose widths are 1 and even widths up to 256 (every boxcar sum below
+//   2^16) take the bound tests on two cells per 32-bit lane: the prefix is kept modulo 2^16 in
+//   16-bit halves (differences stay exact), one dword read brings the prefix at t + W and
+//   t + 1 + W, and packed 16-bit subtractions test both cells.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cstdint>
+#include <type_traits>
 
 #include "snd_detect.h"
 
@@ -173,6 +177,244 @@ __global__ __launch_bounds__(kThreads) void k_rowstats(const T *plane, int64_t p
     }
 }
 
+// Per-row constants of S/N(t, W) = (S_W(t) - mu W) / (sigma sqrt W), for threads tid < nw:
+// mu W, sigma sqrt W and the bound on the boxcar sum below which a cell cannot reach the
+// threshold at width W.
+template <typename P>
+__device__ inline void row_constants(int tid, const SnrArgs &a, double mu, double sg, double *muw, double *den,
+                                     P *sthr, bool is_int)
+{
+    if (tid >= a.nw) return;
+    muw[tid] = __dmul_rn(mu, (double)a.w[tid]);
+    den[tid] = __dmul_rn(sg, a.sqrtw[tid]);
+    // S/N >= Theta needs S >= mu W + Theta sigma sqrt W up to the rounding of the exact
+    // quotient (relative 1e-16); the bound takes a relative margin of 1e-9 below that
+    const double b = muw[tid] + a.threshold * den[tid];
+    const double thr = b - 1e-9 * (fabs(muw[tid]) + a.threshold * den[tid]);
+    if (is_int) {  // integer sums: the largest integer at or below the bound
+        sthr[tid] = thr <= -2147483648.0 ? (P)(-2147483647 - 1) : thr >= 2147483647.0 ? (P)2147483647 : (P)floor(thr);
+    } else {
+        sthr[tid] = (P)thr;
+    }
+}
+
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+__device__ inline uint32_t pk_sub(uint32_t x, uint32_t y)  // two 16-bit differences modulo 2^16
+{
+    return __builtin_bit_cast(uint32_t, __builtin_bit_cast(u16x2, x) - __builtin_bit_cast(u16x2, y));
+}
+__device__ inline uint32_t pk_sub_sat(uint32_t x, uint32_t y)  // two max(x - y, 0)
+{
+    return __builtin_bit_cast(uint32_t,
+                              __builtin_elementwise_sub_sat(__builtin_bit_cast(u16x2, x), __builtin_bit_cast(u16x2, y)));
+}
+// (p mod 2^16, (p + x) mod 2^16) from p and a word whose byte 2 holds x (other bytes zero)
+__device__ inline uint32_t pair_word(uint32_t p, uint32_t x_hi)
+{
+    return __builtin_amdgcn_perm(p, p, 0x01000100u) + x_hi;
+}
+
+// Where the u8 plane's staged bytes sit in the S/N workgroup's dynamic LDS on the paired path:
+// after the 16-bit prefix of tile + 256 entries (the widest boxcar of the path) and some slack.
+constexpr int kPairRawOff = 9216;
+
+// The paired path applies to a u8 list whose first width is 1 and whose other widths are even
+// and at most 256 (every boxcar sum of u8 samples is then below 2^16).
+template <int NW>
+__device__ inline bool pairs_usable(const SnrArgs &a)
+{
+    if (a.w[0] != 1 || a.w[NW - 1] > 256) return false;
+#pragma unroll
+    for (int w = 1; w < NW; ++w)
+        if (a.w[w] & 1) return false;
+    return true;
+}
+
+// Compaction on the paired path for one interior tile of a u8 row with sigma > 0: every width
+// fits every cell of the tile.  The cells whose bound test passes take the exact quotient, as
+// on the general path; the output is the same list.
+template <int NW>
+__device__ void snr_pairs(const uint8_t *row, int k, int64_t t0, int nwk, int wmax, double mu, double sg,
+                          const SnrArgs &a, unsigned char *dyn, int32_t *wtot, int (*slab_off)[kThreads / 64],
+                          unsigned int &base_s, double *muw, double *den, int32_t *sthr)
+{
+    __shared__ uint64_t smask[snr_tile<uint8_t>() / 2 / kThreads][kThreads / 64][2];
+    constexpr int kTile = snr_tile<uint8_t>();
+    constexpr int kPairs = kTile / 2 / kThreads;  // pairs of cells per thread
+    static_assert(kTile == 16 * kThreads, "sixteen staged bytes per thread");
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    uint16_t *pre16 = reinterpret_cast<uint16_t *>(dyn);  // pre16[j] = P(j) mod 2^16
+    uint8_t *raw = dyn + kPairRawOff;
+    const int L = kTile + wmax - 1;  // staged samples (interior tile)
+    {
+        const auto g4 = as_global(reinterpret_cast<const u32x4 *>(row));
+        u32x4 *r4 = reinterpret_cast<u32x4 *>(raw);
+        int j0 = 0;
+        if (((uintptr_t)row & 15u) == 0) {
+            for (int j = tid; j < L / 16; j += kThreads) r4[j] = g4[j];
+            j0 = L / 16 * 16;
+        }
+        const auto grow = as_global(row);
+        for (int j = j0 + tid; j < L; j += kThreads) raw[j] = grow[j];
+    }
+    row_constants(tid, a, mu, sg, muw, den, sthr, true);
+    __syncthreads();
+    // thread t: samples 16 t .. 16 t + 15; wave 0 also the halo samples 4096 + 4 lane .. + 3
+    // (those past L feed prefix entries no width of the row reads)
+    const u32x4 q = *reinterpret_cast<const u32x4 *>(raw + 16 * tid);
+    constexpr uint32_t kOnes = 0x01010101u;
+    uint32_t tot = __builtin_amdgcn_udot4(q.x, kOnes, 0u, false);
+    tot = __builtin_amdgcn_udot4(q.y, kOnes, tot, false);
+    tot = __builtin_amdgcn_udot4(q.z, kOnes, tot, false);
+    tot = __builtin_amdgcn_udot4(q.w, kOnes, tot, false);
+    uint32_t hq = 0u, htot = 0u;
+    if (wv == 0) {
+        hq = *reinterpret_cast<const uint32_t *>(raw + kTile + 4 * lane);
+        htot = __builtin_amdgcn_udot4(hq, kOnes, 0u, false);
+    }
+    uint32_t inc = tot;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t u = __shfl_up(inc, d, 64);
+        if (lane >= d) inc += u;
+    }
+    if (lane == 63) wtot[wv] = (int32_t)inc;
+    __syncthreads();
+    uint32_t B = inc - tot;
+    for (int w = 0; w < wv; ++w) B += (uint32_t)wtot[w];
+    uint32_t words[8];
+    const uint32_t qd[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        const uint32_t d = qd[m];
+        words[2 * m] = pair_word(B, __builtin_amdgcn_perm(0u, d, 0x0c000c0cu));      // P(4m), P(4m + 1)
+        const uint32_t B2 = __builtin_amdgcn_udot4(d, 0x00000101u, B, false);
+        words[2 * m + 1] = pair_word(B2, __builtin_amdgcn_perm(0u, d, 0x0c020c0cu));  // P(4m + 2), P(4m + 3)
+        B = __builtin_amdgcn_udot4(d, kOnes, B, false);
+    }
+    u32x4 *p4 = reinterpret_cast<u32x4 *>(pre16 + 16 * tid);
+    p4[0] = u32x4{words[0], words[1], words[2], words[3]};
+    p4[1] = u32x4{words[4], words[5], words[6], words[7]};
+    if (wv == 0) {  // P(4096 + 4 lane + i), i = 0..3
+        uint32_t hinc = htot;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const uint32_t u = __shfl_up(hinc, d, 64);
+            if (lane >= d) hinc += u;
+        }
+        const uint32_t Bh = (uint32_t)wtot[0] + (uint32_t)wtot[1] + (uint32_t)wtot[2] + (uint32_t)wtot[3] + hinc - htot;
+        const uint32_t w0 = pair_word(Bh, __builtin_amdgcn_perm(0u, hq, 0x0c000c0cu));
+        const uint32_t w1 = pair_word(__builtin_amdgcn_udot4(hq, 0x00000101u, Bh, false),
+                                      __builtin_amdgcn_perm(0u, hq, 0x0c020c0cu));
+        uint32_t *h2 = reinterpret_cast<uint32_t *>(pre16 + kTile + 4 * lane);
+        h2[0] = w0;
+        h2[1] = w1;
+    }
+    __syncthreads();
+    // per-width thresholds as two 16-bit copies of sthr - 1: a cell's sum S passes when
+    // max(S - (sthr - 1), 0) > 0; widths past the row's set never pass; a bound at or below
+    // zero passes every cell
+    uint32_t th[NW];
+    int hw[NW];
+    uint32_t m0 = 0u;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+        hw[w] = w == 0 ? 1 : (a.w[w] >> 1);
+        const int32_t s = sthr[w];
+        uint32_t t = 0xFFFFu;
+        if (w < nwk) {
+            if (s <= 0) m0 = 0xFFFFFFFFu;
+            else t = (uint32_t)min(s - 1, 65535);
+        }
+        th[w] = t * 0x00010001u;
+    }
+    const uint32_t *dw = reinterpret_cast<const uint32_t *>(pre16);
+    auto exact16 = [&](int i, double &best, int &bi) {
+        best = 0.0;
+        bi = -1;
+        for (int w = 0; w < nwk; ++w) {
+            const int W = a.w[w];
+            const double s = (double)(uint16_t)(pre16[i + W] - pre16[i]);
+            const double val = __dsub_rn(s, muw[w]) / den[w];
+            if (bi < 0 || val > best) {
+                best = val;
+                bi = w;
+            }
+        }
+    };
+    // straight-line bound tests: bit j of `maybe` marks pair j when either of its cells passes
+    uint32_t maybe = 0;
+#pragma unroll
+    for (int j = 0; j < kPairs; ++j) {
+        const int qp = tid + kThreads * j;
+        const uint32_t d0 = dw[qp];
+        uint32_t m = m0 | pk_sub_sat(pk_sub(__builtin_amdgcn_alignbit(dw[qp + 1], d0, 16), d0), th[0]);
+#pragma unroll
+        for (int w = 1; w < NW; ++w) m |= pk_sub_sat(pk_sub(dw[qp + hw[w]], d0), th[w]);
+        maybe |= (m ? 1u : 0u) << j;
+    }
+    // the marked pairs (few) take the exact quotient on both cells; bit 2 j + h of `flags`:
+    // cell 2 (tid + 256 j) + h reaches the threshold
+    uint32_t flags = 0;
+    while (maybe) {
+        const int j = __builtin_ctz(maybe);
+        maybe &= maybe - 1u;
+#pragma unroll 1
+        for (int h = 0; h < 2; ++h) {
+            double best;
+            int bi;
+            exact16(2 * (tid + kThreads * j) + h, best, bi);
+            if (bi >= 0 && best >= a.threshold) flags |= 1u << (2 * j + h);
+        }
+    }
+    // ordered output: pairs in increasing t (slab j, then thread), the even cell first; each
+    // wave's ballots of its even and odd cells per slab go through LDS for the output loop
+#pragma unroll
+    for (int j = 0; j < kPairs; ++j) {
+        const uint64_t b0 = __ballot((flags >> (2 * j)) & 1u), b1 = __ballot((flags >> (2 * j + 1)) & 1u);
+        if (lane == 0) {
+            slab_off[j][wv] = __popcll(b0) + __popcll(b1);
+            smask[j][wv][0] = b0;
+            smask[j][wv][1] = b1;
+        }
+    }
+    __syncthreads();
+    if (tid == 0) {
+        int tsum = 0;
+        for (int j = 0; j < kPairs; ++j)
+            for (int w = 0; w < kThreads / 64; ++w) {
+                const int c = slab_off[j][w];
+                slab_off[j][w] = tsum;
+                tsum += c;
+            }
+        base_s = tsum ? atomicAdd(a.counter, (unsigned int)tsum) : 0u;
+    }
+    __syncthreads();
+    const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
+    uint32_t f = flags;
+    while (f) {
+        const int b = __builtin_ctz(f);
+        f &= f - 1u;
+        const int j = b >> 1, h = b & 1;
+        const int64_t pos = (int64_t)base_s + slab_off[j][wv] + __popcll(smask[j][wv][0] & below) +
+                            __popcll(smask[j][wv][1] & below) + (h ? ((flags >> (2 * j)) & 1u) : 0u);
+        if (pos < a.max_pixels) {
+            // the flagged cells are few: their exact maximum is taken again rather than kept
+            const int i = 2 * (tid + kThreads * j) + h;
+            double best;
+            int bi;
+            exact16(i, best, bi);
+            Pixel px;
+            px.k = k;
+            px.t = (int32_t)(t0 + i);
+            px.snr = best;
+            px.widx = bi;
+            px.pad = 0;
+            a.pixels[pos] = px;
+        }
+    }
+}
+
 // NW > 0: exactly NW widths, known at compile time (per-row constants stay in registers);
 // NW == 0: any number of widths.  BATCH: rows of several planes (SnrArgs::beams).
 template <typename T, int NW, bool BATCH>
@@ -209,6 +451,14 @@ __global__ __launch_bounds__(kThreads) void k_snr(const T *plane, int64_t pitch,
     int64_t L64 = (int64_t)kSnrTile + wmax - 1;
     if (L64 > n - t0) L64 = n - t0;
     const int L = (int)L64;
+    if constexpr (std::is_same<T, uint8_t>::value && NW >= 2) {
+        const double mu = stats[2 * k], sg = stats[2 * k + 1];
+        // uniform over the workgroup: the list, the row's sigma and the tile's place in the row
+        if (!a.snr && sg > 0.0 && t0 + kSnrTile + wmax - 1 <= n && pairs_usable<NW>(a)) {
+            snr_pairs<NW>(row, k, t0, nwk, wmax, mu, sg, a, snr_dyn, wtot, slab_off, base_s, muw, den, sthr);
+            return;
+        }
+    }
     // float tiles on a 16-byte boundary are read as 16-byte vectors: chunks of a multiple of
     // four samples (at most kMaxPer, since kMaxPer is itself a multiple of four)
     static_assert(kMaxPer % 4 == 0, "vector chunks");
@@ -304,21 +554,7 @@ __global__ __launch_bounds__(kThreads) void k_snr(const T *plane, int64_t pitch,
     }
     const double mu = stats[2 * k], sg = stats[2 * k + 1];
     // per-row constants of S/N(t, W) = (S_W(t) - mu W) / (sigma sqrt W)
-    if (tid < a.nw) {
-        muw[tid] = __dmul_rn(mu, (double)a.w[tid]);
-        den[tid] = __dmul_rn(sg, a.sqrtw[tid]);
-        // S/N >= Theta needs S >= mu W + Theta sigma sqrt W up to the rounding of the exact
-        // quotient (relative 1e-16); the bound takes a relative margin of 1e-9 below that
-        const double b = muw[tid] + a.threshold * den[tid];
-        const double thr = b - 1e-9 * (fabs(muw[tid]) + a.threshold * den[tid]);
-        if constexpr (IsInt<T>::value) {  // integer sums: the largest integer at or below the bound
-            sthr[tid] = thr <= -2147483648.0 ? (P)(-2147483647 - 1)
-                        : thr >= 2147483647.0 ? (P)2147483647
-                                              : (P)floor(thr);
-        } else {
-            sthr[tid] = thr;
-        }
-    }
+    row_constants(tid, a, mu, sg, muw, den, sthr, IsInt<T>::value);
     __syncthreads();
     // the exact maximum over widths of sample i (first width on ties)
     auto exact = [&](int i, int64_t t, double &best, int &bi) {

@@ -75,6 +75,44 @@ def test_integer_plane_bit_exact(snd, orc, mode, hi, seed):
         assert det.npixels == int((o_snr >= theta).sum())
 
 
+@pytest.mark.parametrize("mode,hi,widths,theta,sigma_min", [
+    ("graded", 255, WIDTHS, 5.0, 0.0),
+    ("graded", 9, [1, 2, 8, 32, 128, 256], 5.0, 0.0),
+    ("graded", 255, [1, 2, 4, 8, 16, 32, 64, 256], 4.5, 0.0),
+    ("binary", 1, WIDTHS, 2.0, 0.15),        # bounds at or below zero: every cell is tested exactly
+    ("graded", 255, [1, 3, 5, 7], 4.0, 0.0),  # odd widths: the general path
+    ("graded", 255, [2, 4, 8], 4.0, 0.0),     # first width not 1: the general path
+])
+def test_integer_plane_multi_tile_bit_exact(snd, orc, mode, hi, widths, theta, sigma_min):
+    """u8 planes several S/N tiles long with a ragged last tile: the paired 16-bit bound tests
+    (widths 1 and even widths up to 256) and the general path give the oracle's S/N plane, cell
+    count and candidates."""
+    rng = synth.make_rng(hi + len(widths))
+    ndm, n = 19, 3 * 4096 + 777
+    if mode == "binary":
+        plane = (rng.random((ndm, n)) < 0.03).astype(np.uint8)
+        plane[4:7, 5000:5040] = 1
+        plane[8] = 0  # an all-zero row: sigma floored
+    else:
+        plane = rng.integers(0, hi + 1, (ndm, n)).astype(np.uint8)
+        plane[11:13, 8190:8300] = hi  # a pulse across a tile boundary
+        plane[2, 4096 - 20:4096 + 20] = hi
+    plane[5] = 1 if mode == "binary" else 3  # constant row
+    p = _plan_for(snd, ndm, n, mode)
+    dev = torch.from_numpy(plane).cuda()
+    _say(f"multi-tile integer detect mode={mode} hi={hi} widths={widths} theta={theta}")
+    det = snd.Detector(p, widths, threshold=theta, sigma_min=sigma_min, closing_radius=1, n_min=1)
+    o_snr, o_widx, o_mu, o_sg = orc.matched_filter(plane.astype(np.float64), widths, integer_plane=True,
+                                                   sigma_min=sigma_min)
+    snr, widx = det.snr_plane(dev)
+    assert np.array_equal(snr.cpu().numpy(), o_snr.astype(np.float32))
+    assert np.array_equal(widx.cpu().numpy().astype(np.int32), o_widx)
+    got = det.run(dev)
+    want = orc.candidates(o_snr, o_widx, theta, radius=1, n_min=1)
+    _cands_equal(got, want)
+    assert det.npixels == int((o_snr >= theta).sum()) > 0
+
+
 def test_float_plane_within_tolerance(snd, orc):
     rng = synth.make_rng(8)
     ndm, n = 24, 5000
