@@ -214,10 +214,6 @@ __device__ inline uint32_t pair_word(uint32_t p, uint32_t x_hi)
     return __builtin_amdgcn_perm(p, p, 0x01000100u) + x_hi;
 }
 
-// Where the u8 plane's staged bytes sit in the S/N workgroup's dynamic LDS on the paired path:
-// after the 16-bit prefix of tile + 256 entries (the widest boxcar of the path) and some slack.
-constexpr int kPairRawOff = 9216;
-
 // The paired path applies to a u8 list whose first width is 1 and whose other widths are even
 // and at most 256 (every boxcar sum of u8 samples is then below 2^16).
 template <int NW>
@@ -230,11 +226,12 @@ __device__ inline bool pairs_usable(const SnrArgs &a)
     return true;
 }
 
-// Compaction on the paired path for one interior tile of a u8 row with sigma > 0: every width
-// fits every cell of the tile.  The cells whose bound test passes take the exact quotient, as
-// on the general path; the output is the same list.
+// Compaction on the paired path for one interior tile of a u8 row (16-byte aligned): every
+// width fits every cell of the tile.  The tile's bytes are loaded into registers before the
+// row's statistics, so that the two loads overlap.  The cells whose bound test passes take the
+// exact quotient, as on the general path; the output is the same list (none when sigma is 0).
 template <int NW>
-__device__ void snr_pairs(const uint8_t *row, int k, int64_t t0, int nwk, int wmax, double mu, double sg,
+__device__ void snr_pairs(const uint8_t *row, int k, int64_t t0, int nwk, int wmax, const double *stats,
                           const SnrArgs &a, unsigned char *dyn, int32_t *wtot, int (*slab_off)[kThreads / 64],
                           unsigned int &base_s, double *muw, double *den, int32_t *sthr)
 {
@@ -244,34 +241,26 @@ __device__ void snr_pairs(const uint8_t *row, int k, int64_t t0, int nwk, int wm
     static_assert(kTile == 16 * kThreads, "sixteen staged bytes per thread");
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     uint16_t *pre16 = reinterpret_cast<uint16_t *>(dyn);  // pre16[j] = P(j) mod 2^16
-    uint8_t *raw = dyn + kPairRawOff;
-    const int L = kTile + wmax - 1;  // staged samples (interior tile)
-    {
-        const auto g4 = as_global(reinterpret_cast<const u32x4 *>(row));
-        u32x4 *r4 = reinterpret_cast<u32x4 *>(raw);
-        int j0 = 0;
-        if (((uintptr_t)row & 15u) == 0) {
-            for (int j = tid; j < L / 16; j += kThreads) r4[j] = g4[j];
-            j0 = L / 16 * 16;
-        }
-        const auto grow = as_global(row);
-        for (int j = j0 + tid; j < L; j += kThreads) raw[j] = grow[j];
+    // thread t: samples 16 t .. 16 t + 15 (one 16-byte load); wave 0 also the halo samples
+    // 4096 + 4 lane .. + 3 that exist in the tile's window (L = 4096 + wmax - 1 samples; the
+    // others read as zero and feed prefix entries no width of the row reads)
+    const u32x4 q = as_global(reinterpret_cast<const u32x4 *>(row))[tid];
+    uint32_t hq = 0u;
+    if (wv == 0) {
+        const auto grow = as_global(row + kTile);
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+            if (4 * lane + b < wmax - 1) hq |= (uint32_t)grow[4 * lane + b] << (8 * b);
     }
+    const double mu = stats[2 * k], sg = stats[2 * k + 1];
+    if (!(sg > 0.0)) return;  // uniform: no cell of the row has a non-zero S/N
     row_constants(tid, a, mu, sg, muw, den, sthr, true);
-    __syncthreads();
-    // thread t: samples 16 t .. 16 t + 15; wave 0 also the halo samples 4096 + 4 lane .. + 3
-    // (those past L feed prefix entries no width of the row reads)
-    const u32x4 q = *reinterpret_cast<const u32x4 *>(raw + 16 * tid);
     constexpr uint32_t kOnes = 0x01010101u;
     uint32_t tot = __builtin_amdgcn_udot4(q.x, kOnes, 0u, false);
     tot = __builtin_amdgcn_udot4(q.y, kOnes, tot, false);
     tot = __builtin_amdgcn_udot4(q.z, kOnes, tot, false);
     tot = __builtin_amdgcn_udot4(q.w, kOnes, tot, false);
-    uint32_t hq = 0u, htot = 0u;
-    if (wv == 0) {
-        hq = *reinterpret_cast<const uint32_t *>(raw + kTile + 4 * lane);
-        htot = __builtin_amdgcn_udot4(hq, kOnes, 0u, false);
-    }
+    const uint32_t htot = __builtin_amdgcn_udot4(hq, kOnes, 0u, false);
     uint32_t inc = tot;
 #pragma unroll
     for (int d = 1; d < 64; d <<= 1) {
@@ -452,10 +441,9 @@ __global__ __launch_bounds__(kThreads) void k_snr(const T *plane, int64_t pitch,
     if (L64 > n - t0) L64 = n - t0;
     const int L = (int)L64;
     if constexpr (std::is_same<T, uint8_t>::value && NW >= 2) {
-        const double mu = stats[2 * k], sg = stats[2 * k + 1];
-        // uniform over the workgroup: the list, the row's sigma and the tile's place in the row
-        if (!a.snr && sg > 0.0 && t0 + kSnrTile + wmax - 1 <= n && pairs_usable<NW>(a)) {
-            snr_pairs<NW>(row, k, t0, nwk, wmax, mu, sg, a, snr_dyn, wtot, slab_off, base_s, muw, den, sthr);
+        // uniform over the workgroup: the list, the tile's place in the row and its alignment
+        if (!a.snr && t0 + kSnrTile + wmax - 1 <= n && ((uintptr_t)row & 15u) == 0 && pairs_usable<NW>(a)) {
+            snr_pairs<NW>(row, k, t0, nwk, wmax, stats, a, snr_dyn, wtot, slab_off, base_s, muw, den, sthr);
             return;
         }
     }
@@ -463,8 +451,8 @@ __global__ __launch_bounds__(kThreads) void k_snr(const T *plane, int64_t pitch,
     // four samples (at most kMaxPer, since kMaxPer is itself a multiple of four)
     static_assert(kMaxPer % 4 == 0, "vector chunks");
     const bool vec4 = !IsInt<T>::value && sizeof(T) == 4 && ((uintptr_t)row & 15u) == 0;
-    // integer tiles: every thread takes kMaxPer elements, those past L read as zero (the prefix
-    // array is sized for kThreads * kMaxPer entries), so that no access depends on L
+    // integer tiles: every thread takes kMaxPer elements, those past L read as zero (the staged
+    // bytes fit the prefix array for any L), and only prefix entries up to L are written
     const int per = IsInt<T>::value ? kMaxPer
                     : vec4          ? (L + 4 * kThreads - 1) / (4 * kThreads) * 4
                                     : (L + kThreads - 1) / kThreads;
@@ -540,7 +528,7 @@ __global__ __launch_bounds__(kThreads) void k_snr(const T *plane, int64_t pitch,
 #pragma unroll
         for (int i = 0; i < kMaxPer; ++i) {
             acc += v[i];
-            pre[beg + i + 1] = acc;
+            if (beg + i < L) pre[beg + i + 1] = acc;  // entries 1 .. L (the array holds tile + wmax + 1)
         }
     } else {
 #pragma unroll
@@ -817,10 +805,12 @@ int launch_snr_grid(dim3 grid, const T *p, int64_t pitch, int64_t n, double *sta
 {
     constexpr int kSnrTile = snr_tile<T>();
     // the prefix array holds the tile plus the widest boxcar of the list (every row's set is a
-    // leading part of the list)
-    // (integer planes: at least one entry per element of the threads' fixed chunks)
-    constexpr int64_t kChunks = IsInt<T>::value ? (int64_t)kThreads * ((kSnrTile + kMaxWidth + kThreads - 1) / kThreads) + 1 : 0;
-    const int64_t entries = std::max<int64_t>(kSnrTile + a.w[a.nw - 1] + 1, kChunks);
+    // leading part of the list); integer tiles are first staged in its storage, at most
+    // kThreads * kMaxPer samples of sizeof(T) <= 2 bytes each
+    constexpr int64_t kStageBytes = IsInt<T>::value ? (int64_t)kThreads * ((kSnrTile + kMaxWidth + kThreads - 1) / kThreads) * 2 : 0;
+    const int64_t entries = std::max<int64_t>(kSnrTile + a.w[a.nw - 1] + 1,
+                                              (kStageBytes + (int64_t)sizeof(typename PrefixType<T>::type) - 1) /
+                                                  (int64_t)sizeof(typename PrefixType<T>::type));
     const size_t lds = (size_t)entries * sizeof(typename PrefixType<T>::type);
     switch (a.nw) {
 #define SND_NW(N) case N: hipLaunchKernelGGL((k_snr<T, N, BATCH>), grid, dim3(kThreads), lds, st, p, pitch, n, stats, a); break;
