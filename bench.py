@@ -530,7 +530,7 @@ def batch_leg(snd, synth, torch, dev, reps=3):
     t = time.perf_counter()
     plans = []
     for s_ in specs:
-        inp = s_.node_dtype if s_.mode == "float" else "u8"
+        inp = s_.node_dtype if s_.mode != "graded" else "u8"  # float storage, binary bit rows, graded bytes
         plans.append(snd.Plan(s_.freqs, s_.dms, s_.tsamp_s, s_.nsamp, mode=s_.mode, branching=4, k_leaf=s_.k_leaf,
                               k_int=s_.k_int, node_dtype=s_.node_dtype, in_dtype=inp))
     t_plan = time.perf_counter() - t
@@ -541,6 +541,8 @@ def batch_leg(snd, synth, torch, dev, reps=3):
         z = torch.randn(s_.nchan, s_.nsamp, device=dev, generator=gen)
         if s_.mode == "float":
             xs.append(z if p.in_dtype == "f32" else snd.cast(z, p.in_dtype))
+        elif p.in_dtype == "bits":
+            xs.append(snd.encode_bits(z, s_.enc_thresholds[0]))
         else:
             xs.append(snd.encode(z, list(s_.enc_thresholds)))
         del z
@@ -594,7 +596,8 @@ def batch_leg(snd, synth, torch, dev, reps=3):
     batch = snd.Batch(plans_t, dev)
     ms_tuned = timed(lambda: batch.execute(xs, outs))
     res = dict(workload="48 beams x 1024 ch x 2^16 samples; DM grids 1024-4096 trials to 500-2000; "
-                        "modes binary/graded/float (f32/bf16/f16); B=4; synthetic N(0,1) encoded on the device",
+                        "modes binary (bit rows) / graded (u8) / float (f32/bf16/f16); B=4; synthetic N(0,1) "
+                        "encoded on the device",
                ms_batched_tuned=round(ms_tuned, 3), tuned_classes=tuned_rows,
                beams=48, grids=batch.n_launches, plan_build_s=round(t_plan, 2),
                dm_time_samples=int(samples), ms_batched=round(ms_batch, 3), ms_per_beam_launches=round(ms_single, 3),

@@ -43,7 +43,7 @@ class WorkloadSpec:
     widths: tuple = (1, 2, 4, 8, 16, 32, 64)
     tsamp_s: float = TSAMP_S
     beam: int = 0
-    node_dtype: str = "f32"        # float mode storage: f32 | bf16 | f16
+    node_dtype: str = "f32"        # tree storage: f32 | bf16 | f16 (float), u8 (graded), bits (binary)
     pulses: list = dataclasses.field(default_factory=list)
 
     @property
@@ -92,11 +92,12 @@ def _config3(nsamp: int = 65536, mode: str = "graded", branching: int = 4) -> Wo
 
 
 def batch_beam(beam: int, nsamp: int = 65536, nchan: int = 1024) -> WorkloadSpec:
-    """One beam of the 48-beam batched workload: uneven DM grids, rotating modes and float storage."""
+    """One beam of the 48-beam batched workload: uneven DM grids, rotating modes and float storage;
+    binary beams carry bit rows (one bit per spike, input and tree), graded beams u8."""
     ndm = 1024 + (3072 * beam) // 47
     dmax = 500.0 + 1500.0 * ((29 * beam) % 48) / 47.0
     mode = ("binary", "graded", "float")[beam % 3]
-    node = ("f32", "bf16", "f16")[(beam // 3) % 3] if mode == "float" else ("u8")
+    node = ("f32", "bf16", "f16")[(beam // 3) % 3] if mode == "float" else ("bits" if mode == "binary" else "u8")
     thr = {"binary": (2.0,), "graded": (1.0, 2.0, 3.0, 4.0), "float": ()}[mode]
     spec = WorkloadSpec(name=f"batch_beam{beam}", config=4, nchan=nchan, nsamp=nsamp,
                         dms=dm_linear(ndm, 0.0, dmax), branching=4, cluster=4, mode=mode,

@@ -140,16 +140,22 @@ def test_batch_48_beams_workload(snd, orc):
     specs = [synth.batch_beam(b) for b in range(48)]
     plans, xs = [], []
     for s in specs:
-        inp = s.node_dtype if s.mode == "float" else "u8"
+        inp = s.node_dtype if s.mode != "graded" else "u8"  # float storage, binary bit rows, graded bytes
         plans.append(snd.Plan(s.freqs, s.dms, s.tsamp_s, s.nsamp, mode=s.mode, branching=4, k_leaf=s.k_leaf,
                               k_int=s.k_int, node_dtype=s.node_dtype, in_dtype=inp))
     rng = synth.make_rng(48)
-    for s, p in zip(specs, plans):
+    checked = (0, 1, 2, 17, 29, 47)
+    spikes = {}  # byte spikes of the checked bit-input beams, for the oracle
+    for b, (s, p) in enumerate(zip(specs, plans)):
         # device-side noise stands in for each beam's filterbank here (the parity of the
         # encoded path is covered elsewhere); drawing on the device keeps the test fast
         z = torch.randn(s.nchan, s.nsamp, device="cuda", generator=None)
         if s.mode == "float":
             xs.append(z if p.in_dtype == "f32" else snd.cast(z, p.in_dtype))
+        elif p.in_dtype == "bits":
+            xs.append(snd.encode_bits(z, s.enc_thresholds[0]))
+            if b in checked:
+                spikes[b] = snd.encode(z, list(s.enc_thresholds)).cpu().numpy()
         else:
             xs.append(snd.encode(z, list(s.enc_thresholds)))
         del z
@@ -159,14 +165,14 @@ def test_batch_48_beams_workload(snd, orc):
     torch.cuda.synchronize()
     _say(f"48 beams in {nl} grids")
     assert nl <= 12
-    for b in (0, 1, 2, 17, 29, 47):
+    for b in checked:
         y = outs[b].clone()
         ref = plans[b].execute(xs[b], workspace=batch.workspaces[b])
         torch.cuda.synchronize()
         assert torch.equal(y, ref), b
         s, p = specs[b], plans[b]
         d = orc.delays(s.freqs, s.dms, s.tsamp_s)
-        xh = xs[b].float().cpu().numpy() if s.mode == "float" else xs[b].cpu().numpy()
+        xh = xs[b].float().cpu().numpy() if s.mode == "float" else spikes[b] if b in spikes else xs[b].cpu().numpy()
         r = synth.make_rng(1000 + b)
         ks, ts = r.integers(0, p.ndm, 400), r.integers(0, p.n_out, 400)
         want = orc.snd_points(xh, s.freqs, d, ks, ts, mode=s.mode, cluster=4, branching=4, k_leaf=s.k_leaf,
