@@ -36,8 +36,10 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic.json")
 
 # sources that decide what the tree kernels do: device code, the headers it includes, the plan
 # builder (tables, windows, batches) and the launch path; the other host files (detection's
-# host part, streaming, batching, tuning, multi-rate, validation) do not change their traffic
+# host part, streaming, batching, tuning, multi-rate, validation) and the detection kernels,
+# which the tree kernels do not include, do not change their traffic
 DIGEST_CPP = ("plan.cpp", "capi.cpp")
+DIGEST_SKIP = ("detect.hip", "detect_noalloc.hip", "label.hip", "snd_detect.h")
 
 
 def source_digest():
@@ -46,7 +48,7 @@ def source_digest():
     h = hashlib.sha256()
     for d in ("paper_2606_15361_amd/csrc", "include"):
         for name in sorted(os.listdir(os.path.join(ROOT, d))):
-            if name.endswith((".hip", ".h")) or name in DIGEST_CPP:
+            if (name.endswith((".hip", ".h")) and name not in DIGEST_SKIP) or name in DIGEST_CPP:
                 with open(os.path.join(ROOT, d, name), "rb") as f:
                     h.update(name.encode() + b"\0" + f.read())
     return h.hexdigest()[:16]

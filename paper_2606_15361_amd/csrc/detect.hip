@@ -214,6 +214,20 @@ __device__ inline uint32_t pair_word(uint32_t p, uint32_t x_hi)
     return __builtin_amdgcn_perm(p, p, 0x01000100u) + x_hi;
 }
 
+// Inclusive sum over the 64 lanes of a wave with DPP moves: within each row of 16 lanes by
+// shifts of 1, 2, 4 and 8 (lanes shifted in from outside the row add zero), then lane 15's total
+// into rows 1 and 3, then lane 31's into rows 2 and 3.
+__device__ inline uint32_t wave_inclusive_sum(uint32_t x)
+{
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xf, 0xf, false);  // row_shr:1
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xf, 0xf, false);  // row_shr:2
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xf, 0xf, false);  // row_shr:4
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xf, 0xf, false);  // row_shr:8
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xa, 0xf, false);  // row_bcast:15
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xc, 0xf, false);  // row_bcast:31
+    return x;
+}
+
 // The paired path applies to a u8 list whose first width is 1 and whose other widths are even
 // and at most 256 (every boxcar sum of u8 samples is then below 2^16).
 template <int NW>
@@ -255,18 +269,26 @@ __device__ void snr_pairs(const uint8_t *row, int k, int64_t t0, int nwk, int wm
     const double mu = stats[2 * k], sg = stats[2 * k + 1];
     if (!(sg > 0.0)) return;  // uniform: no cell of the row has a non-zero S/N
     row_constants(tid, a, mu, sg, muw, den, sthr, true);
+    // per-width thresholds as two 16-bit copies of sthr - 1: a cell's sum S passes when
+    // max(S - (sthr - 1), 0) > 0; widths past the row's set never pass; a bound at or below
+    // zero passes every cell (flag word all ones)
+    __shared__ uint2 thw[NW];
+    if (tid < NW) {
+        const int32_t sb = sthr[tid];
+        uint32_t t = 0xFFFFu, all = 0u;
+        if (tid < nwk) {
+            if (sb <= 0) all = 0xFFFFFFFFu;
+            else t = (uint32_t)min(sb - 1, 65535);
+        }
+        thw[tid] = uint2{t * 0x00010001u, all};
+    }
     constexpr uint32_t kOnes = 0x01010101u;
     uint32_t tot = __builtin_amdgcn_udot4(q.x, kOnes, 0u, false);
     tot = __builtin_amdgcn_udot4(q.y, kOnes, tot, false);
     tot = __builtin_amdgcn_udot4(q.z, kOnes, tot, false);
     tot = __builtin_amdgcn_udot4(q.w, kOnes, tot, false);
     const uint32_t htot = __builtin_amdgcn_udot4(hq, kOnes, 0u, false);
-    uint32_t inc = tot;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const uint32_t u = __shfl_up(inc, d, 64);
-        if (lane >= d) inc += u;
-    }
+    const uint32_t inc = wave_inclusive_sum(tot);
     if (lane == 63) wtot[wv] = (int32_t)inc;
     __syncthreads();
     uint32_t B = inc - tot;
@@ -285,12 +307,7 @@ __device__ void snr_pairs(const uint8_t *row, int k, int64_t t0, int nwk, int wm
     p4[0] = u32x4{words[0], words[1], words[2], words[3]};
     p4[1] = u32x4{words[4], words[5], words[6], words[7]};
     if (wv == 0) {  // P(4096 + 4 lane + i), i = 0..3
-        uint32_t hinc = htot;
-#pragma unroll
-        for (int d = 1; d < 64; d <<= 1) {
-            const uint32_t u = __shfl_up(hinc, d, 64);
-            if (lane >= d) hinc += u;
-        }
+        const uint32_t hinc = wave_inclusive_sum(htot);
         const uint32_t Bh = (uint32_t)wtot[0] + (uint32_t)wtot[1] + (uint32_t)wtot[2] + (uint32_t)wtot[3] + hinc - htot;
         const uint32_t w0 = pair_word(Bh, __builtin_amdgcn_perm(0u, hq, 0x0c000c0cu));
         const uint32_t w1 = pair_word(__builtin_amdgcn_udot4(hq, 0x00000101u, Bh, false),
@@ -300,22 +317,15 @@ __device__ void snr_pairs(const uint8_t *row, int k, int64_t t0, int nwk, int wm
         h2[1] = w1;
     }
     __syncthreads();
-    // per-width thresholds as two 16-bit copies of sthr - 1: a cell's sum S passes when
-    // max(S - (sthr - 1), 0) > 0; widths past the row's set never pass; a bound at or below
-    // zero passes every cell
     uint32_t th[NW];
     int hw[NW];
     uint32_t m0 = 0u;
 #pragma unroll
     for (int w = 0; w < NW; ++w) {
         hw[w] = w == 0 ? 1 : (a.w[w] >> 1);
-        const int32_t s = sthr[w];
-        uint32_t t = 0xFFFFu;
-        if (w < nwk) {
-            if (s <= 0) m0 = 0xFFFFFFFFu;
-            else t = (uint32_t)min(s - 1, 65535);
-        }
-        th[w] = t * 0x00010001u;
+        const uint2 t = thw[w];
+        th[w] = t.x;
+        m0 |= t.y;
     }
     const uint32_t *dw = reinterpret_cast<const uint32_t *>(pre16);
     auto exact16 = [&](int i, double &best, int &bi) {
@@ -331,8 +341,9 @@ __device__ void snr_pairs(const uint8_t *row, int k, int64_t t0, int nwk, int wm
             }
         }
     };
-    // straight-line bound tests: bit j of `maybe` marks pair j when either of its cells passes
-    uint32_t maybe = 0;
+    // straight-line bound tests; mk[j]: the wave's lanes whose pair j has a cell that passes
+    uint64_t mk[kPairs];
+    uint64_t any = 0;
 #pragma unroll
     for (int j = 0; j < kPairs; ++j) {
         const int qp = tid + kThreads * j;
@@ -340,10 +351,16 @@ __device__ void snr_pairs(const uint8_t *row, int k, int64_t t0, int nwk, int wm
         uint32_t m = m0 | pk_sub_sat(pk_sub(__builtin_amdgcn_alignbit(dw[qp + 1], d0, 16), d0), th[0]);
 #pragma unroll
         for (int w = 1; w < NW; ++w) m |= pk_sub_sat(pk_sub(dw[qp + hw[w]], d0), th[w]);
-        maybe |= (m ? 1u : 0u) << j;
+        mk[j] = __ballot(m != 0u);
+        any |= mk[j];
     }
     // the marked pairs (few) take the exact quotient on both cells; bit 2 j + h of `flags`:
     // cell 2 (tid + 256 j) + h reaches the threshold
+    uint32_t maybe = 0;
+    if (any) {  // uniform over the wave
+#pragma unroll
+        for (int j = 0; j < kPairs; ++j) maybe |= (uint32_t)((mk[j] >> lane) & 1u) << j;
+    }
     uint32_t flags = 0;
     while (maybe) {
         const int j = __builtin_ctz(maybe);
