@@ -228,6 +228,27 @@ __device__ inline uint32_t wave_inclusive_sum(uint32_t x)
     return x;
 }
 
+// The same scan for FP64 values (each DPP move carries the two halves of a value).
+template <int CTRL, int ROW_MASK>
+__device__ inline double dpp_f64(double x)
+{
+    const uint64_t b = __builtin_bit_cast(uint64_t, x);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, CTRL, ROW_MASK, 0xf, false);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), CTRL, ROW_MASK, 0xf, false);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+__device__ inline double wave_inclusive_sum(double x)
+{
+    x += dpp_f64<0x111, 0xf>(x);
+    x += dpp_f64<0x112, 0xf>(x);
+    x += dpp_f64<0x114, 0xf>(x);
+    x += dpp_f64<0x118, 0xf>(x);
+    x += dpp_f64<0x142, 0xa>(x);
+    x += dpp_f64<0x143, 0xc>(x);
+    return x;
+}
+__device__ inline int32_t wave_inclusive_sum(int32_t x) { return (int32_t)wave_inclusive_sum((uint32_t)x); }
+
 // The paired path applies to a u8 list whose first width is 1 and whose other widths are even
 // and at most 256 (every boxcar sum of u8 samples is then below 2^16).
 template <int NW>
@@ -530,12 +551,7 @@ __global__ __launch_bounds__(kThreads) void k_snr(const T *plane, int64_t pitch,
             run += v[i];
         }
     }
-    P inc = run;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const P u = __shfl_up(inc, d, 64);
-        if (lane >= d) inc += u;
-    }
+    const P inc = wave_inclusive_sum(run);
     if (lane == 63) wtot[wv] = inc;
     __syncthreads();
     P acc = inc - run;
