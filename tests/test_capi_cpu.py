@@ -161,6 +161,24 @@ def test_bit_input_plans(snd):
     with pytest.raises(SndError) as ei:
         snd.Plan(f, dms, 0.138e-3, 2000, mode="binary", branching=4, in_dtype="bits", cluster=16)
     assert ei.value.status == _capi.ERR_UNSUPPORTED
+    # pushes of bit chunks: lengths and pitches in bits, whole 32-bit words per row, 4-byte
+    # aligned rows; checked before any device work (admission records the buffer only)
+    L = _capi.lib()
+    h = C.c_void_p()
+    _capi.check(L.snd_stream_create(1 << 34, C.byref(h)))
+    _capi.check(L.snd_stream_admit(h, 3, q.handle, C.c_void_p(1 << 20), nb.value))
+    item = _capi.StreamItem()
+    item.beam_id, item.chunk_idx, item.chunk_len = 3, 0, 300
+    item.d_chunk, item.chunk_pitch = 1 << 24, 320
+    item.d_out, item.out_pitch = 1 << 28, q.n_out
+    rc = L.snd_stream_push(h, 1, C.byref(item), None, 0, None)
+    assert rc == _capi.ERR_STATE  # the arguments pass; the plan's tables are not uploaded
+    for pitch, ptr in ((300, 1 << 24), (330, 1 << 24), (320, (1 << 24) + 2)):
+        item.chunk_pitch, item.d_chunk = pitch, ptr
+        assert L.snd_stream_push(h, 1, C.byref(item), None, 0, None) == _capi.ERR_INVALID, (pitch, ptr)
+    item.chunk_pitch, item.d_chunk, item.chunk_len = 1024, 1 << 24, q.n_out + 1
+    assert L.snd_stream_push(h, 1, C.byref(item), None, 0, None) == _capi.ERR_INVALID  # longer than n_out
+    L.snd_stream_destroy(h)
     # bit input pitch must be whole words; encoder pitch likewise
     buf = (C.c_uint8 * 256)()
     rc = _capi.lib().snd_encode_bits(C.cast(buf, C.c_void_p), 100, 0, 1, 100, C.c_float(1.0),
