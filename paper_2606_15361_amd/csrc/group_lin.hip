@@ -11,11 +11,18 @@
 //  * bf16 / f16 rows: lane i owns the sample pairs (2 i + 128 v, 2 i + 1 + 128 v), one dword.
 //    An input whose first sample sits in the upper half of a dword takes the upper half of that
 //    dword and the lower half of the next one (a second read); the branch on that is uniform.
-//    Samples are widened to FP32 exactly before they are added.
+//    f16 samples are widened to FP32 exactly before they are added.  bf16 inputs go in twos: one
+//    byte permute puts the two inputs' samples of one output sample into one dword, and one
+//    v_dot2_f32_bf16 with weights (1, 1) adds both to the FP32 sum (one instruction per sample
+//    instead of a widening and an add).  Only samples of the output being formed enter a dot.
 //
 // Each row is summed in FP32 in the order the plan lists its inputs (16-bit rows: batch by batch,
 // each batch's inputs that start a dword before the others): an association of the exact sum
-// that differs from the tree's, within the float tolerance of the FP64 definition.
+// that differs from the tree's, within the float tolerance of the FP64 definition.  A bf16 dot
+// does not round like FP32 adds: measured on gfx950, its error stays below 1.5 x 2^-23 times the
+// sum of its three terms' magnitudes (against 2^-24 times the result for an add), with a slight
+// bias toward -infinity.  A row of n inputs is therefore within n 2^-23 sum|x| of the exact sum,
+// the bound the parity tests check element by element.
 #include <hip/hip_runtime.h>
 
 #include "group_tab.h"
@@ -109,6 +116,16 @@ struct Lin16 : LinBase {
         if constexpr (F16) return (float)__builtin_bit_cast(_Float16, (uint16_t)(d >> 16));
         else return __uint_as_float(d & 0xffff0000u);
     }
+    // byte selectors of v_perm_b32 (a, b): the lower halves of b and a, or their upper halves
+    static constexpr uint32_t kLoLo = 0x05040100u, kHiHi = 0x07060302u;
+    // acc + the two bf16 samples that the selector picks from a and b (weights one2 = (1, 1))
+    static __device__ __forceinline__ float add2(float acc, uint32_t a, uint32_t b, uint32_t sel, uint32_t one2)
+    {
+        typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+        const uint32_t pr = __builtin_amdgcn_perm(a, b, sel);
+        return __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2, pr), __builtin_bit_cast(bf16x2, one2), acc,
+                                               false);
+    }
     // Row q's inputs that start a dword (the first even_q of its n words), then the others: two
     // loops per row without a branch per input, two inputs in flight.
     static __device__ __forceinline__ void add_batch(float (&st)[kState], const unsigned char *buf,
@@ -118,6 +135,10 @@ struct Lin16 : LinBase {
         const uint32_t vw = *reinterpret_cast<const uint32_t *>(w);
         const int n = c.n;
         const uint32_t even = c.even;
+        // (1.0, 1.0) in bf16, materialised in a scalar register so that the compiler cannot encode
+        // it as an inline constant (which the hardware would apply to one half only)
+        uint32_t one2;
+        asm volatile("s_mov_b32 %0, 0x3f803f80" : "=s"(one2));
         const unsigned char *lane_base = buf + 4 * lane;
 #pragma unroll
         for (int q = 0; q < R; ++q) {
@@ -132,13 +153,21 @@ struct Lin16 : LinBase {
 #pragma unroll
                     for (int v = 0; v < V; ++v) x[u][v] = p[64 * v];
                 }
+                if constexpr (F16) {
 #pragma unroll
-                for (int u = 0; u < 2; ++u)
+                    for (int u = 0; u < 2; ++u)
+#pragma unroll
+                        for (int v = 0; v < V; ++v) {
+                            st[LO + q * V + v] += lower(x[u][v]);
+                            st[HI + q * V + v] += upper(x[u][v]);
+                        }
+                } else {
 #pragma unroll
                     for (int v = 0; v < V; ++v) {
-                        st[LO + q * V + v] += lower(x[u][v]);
-                        st[HI + q * V + v] += upper(x[u][v]);
+                        st[LO + q * V + v] = add2(st[LO + q * V + v], x[1][v], x[0][v], kLoLo, one2);
+                        st[HI + q * V + v] = add2(st[HI + q * V + v], x[1][v], x[0][v], kHiHi, one2);
                     }
+                }
             }
             if (k < ke) {
                 const uint32_t o = (uint32_t)__builtin_amdgcn_readlane((int)vw, k);
@@ -154,6 +183,26 @@ struct Lin16 : LinBase {
                 ++k;
             }
             // first sample in the upper half: that half of the dword, then the lower half of the next
+            if constexpr (!F16) {
+                for (; k + 2 <= k1; k += 2) {
+                    uint32_t x[2][V], y[2][V];
+#pragma unroll
+                    for (int u = 0; u < 2; ++u) {
+                        const uint32_t o = (uint32_t)__builtin_amdgcn_readlane((int)vw, k + u);
+                        const uint32_t *p = reinterpret_cast<const uint32_t *>(lane_base + (o & ~3u));
+#pragma unroll
+                        for (int v = 0; v < V; ++v) {
+                            x[u][v] = p[64 * v];
+                            y[u][v] = p[64 * v + 1];
+                        }
+                    }
+#pragma unroll
+                    for (int v = 0; v < V; ++v) {
+                        st[LO + q * V + v] = add2(st[LO + q * V + v], x[1][v], x[0][v], kHiHi, one2);
+                        st[HI + q * V + v] = add2(st[HI + q * V + v], y[1][v], y[0][v], kLoLo, one2);
+                    }
+                }
+            }
             for (; k < k1; ++k) {
                 const uint32_t o = (uint32_t)__builtin_amdgcn_readlane((int)vw, k);
                 const uint32_t *p = reinterpret_cast<const uint32_t *>(lane_base + (o & ~3u));

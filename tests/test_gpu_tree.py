@@ -166,6 +166,35 @@ def test_float_storage_small_integers_exact(snd, orc, node, B):
     assert np.array_equal(gpu_run(pg, x), y)
 
 
+@pytest.mark.parametrize("node", ["f32", "bf16", "f16"])
+def test_float_rows_sum_error_bound(snd, orc, node):
+    """Element-wise bound on the final stage's FP32 arithmetic.  One channel of every cluster of
+    four carries values +-m 2^e (m < 256, e in -10..7), the others zero, so every leaf is exact in
+    bf16 and f16 storage while the 128-input roots span 2^29 in magnitude and round.  Whatever the
+    association, n roundings of at most one unit in the last place (round to nearest: half of
+    one; the bf16 kernel's paired dots: one) keep |y - exact| <= n 2^-23 sum|x| with n = 128
+    inputs per root; a dropped or foreign sample, or a non-sample half in a dot, breaks it.  300
+    DMs and 2600 output samples: three 128-row groups, five full tiles and a ragged one."""
+    rng, f, dms, _ = _case(512, 300, 71)
+    d = orc.delays(f, dms, 0.138e-3)
+    nsamp = int(d.max()) + 2600
+    m = rng.integers(1, 256, (512, nsamp)).astype(np.float64)
+    e = rng.integers(-10, 8, (512, nsamp)).astype(np.float64)
+    x = (np.where(rng.random((512, nsamp)) < 0.5, -1.0, 1.0) * m * np.exp2(e)).astype(np.float32)
+    x[np.arange(512) % 4 != 0] = 0.0
+    want, _ = orc.snd_dedup(x, f, d, mode="float", cluster=4, branching=4)
+    absum, _ = orc.snd_dedup(np.abs(x), f, d, mode="float", cluster=4, branching=4)
+    p = snd.Plan(f, dms, 0.138e-3, nsamp, mode="float", branching=4, node_dtype=node)
+    assert p.info["stage_kernel"] == ["anchored", "group_lin"], p.info["stage_kernel"]
+    _say(f"float rows error bound node={node} n_out={p.n_out}")
+    y = gpu_run(p, x).astype(np.float64)
+    err = np.abs(y - want)
+    bound = 128 * 2.0 ** -23 * absum
+    assert np.all(np.isfinite(y))
+    assert np.all(err <= bound), (float(np.max(err / np.maximum(bound, 1e-300))), np.argwhere(err > bound)[:5])
+    assert np.any(err > 0)  # the roots do round
+
+
 @pytest.mark.parametrize("nchan,B,cap,levels", [(1024, 4, 255, 4), (1024, 4, 3, 4), (256, 8, 255, 4),
                                                 (512, 8, 7, 6), (64, 4, 2, 2), (4096, 4, 15, 4),
                                                 (4096, 8, 255, 4)])
