@@ -125,7 +125,7 @@ snd_status check_exec(snd_plan plan, const void *d_in, int64_t in_pitch, void *d
 namespace snd {
 
 Prepared prepare_stage(const PlanImpl &P, size_t si, const Run &run, const void *d_in, int64_t in_pitch, void *d_out,
-                       int64_t out_pitch, void *d_workspace)
+                       int64_t out_pitch, void *d_workspace, bool bound)
 {
     const int32_t len_cut = (int32_t)(P.n_out - run.n_run);
     const uint8_t *tb = static_cast<const uint8_t *>(P.d_table);
@@ -187,6 +187,8 @@ Prepared prepare_stage(const PlanImpl &P, size_t si, const Run &run, const void 
         g.k_int = P.desc.k_int;
         g.cap = P.desc.cap;
         g.scale = scale;
+        if (bound && S.group_pack && si == 1 && P.bound_off >= 0)
+            g.bound = reinterpret_cast<const uint32_t *>(ws + P.bound_off) + P.bound_n;
         pr.n_run = run.n_run;
         pr.shape = stage_shape(S);
         const int64_t tile = S.group_tile;
@@ -216,6 +218,7 @@ Prepared prepare_stage(const PlanImpl &P, size_t si, const Run &run, const void 
         g.n_run = (int32_t)run.n_run;
         g.len_cut = len_cut;
         g.tile = S.anchor_tile;
+        if (bound && si == 0 && P.bound_off >= 0) g.bound_slots = reinterpret_cast<uint32_t *>(ws + P.bound_off);
         pr.shape = stage_shape(S);
         pr.nblocks = S.ntiles;
         return pr;
@@ -248,6 +251,10 @@ snd_status launch_prepared(const Prepared &pr, void *stream, const Multi &m, int
     } else if (pr.kind == kKernelAnchored) {
         e = launch_anchored(pr.mode, pr.src_dt, pr.dst_dt, pr.an, m.n > 0 ? nblocks : pr.nblocks, pr.lds, stream, m);
         what = "stage launch (input-anchored)";
+        if (!e && pr.an.bound_slots && m.n == 0) {
+            e = launch_bound_reduce(pr.an.bound_slots, pr.nblocks, stream);
+            what = "leaf bound reduction";
+        }
     } else {
         e = launch_stage(pr.mode, pr.src_dt, pr.dst_dt, pr.st, pr.max_len, stream, m, nblocks);
     }
@@ -262,7 +269,7 @@ snd_status run_stage(PlanImpl &P, size_t si, const Run &run, const void *d_in, i
     static const char *kStageNames[] = {"snd stage 0", "snd stage 1", "snd stage 2", "snd stage 3",
                                         "snd stage 4", "snd stage 5", "snd stage 6", "snd stage 7"};
     roctxRangePushA(si < 8 ? kStageNames[si] : "snd stage");
-    const Prepared pr = prepare_stage(P, si, run, d_in, in_pitch, d_out, out_pitch, d_workspace);
+    const Prepared pr = prepare_stage(P, si, run, d_in, in_pitch, d_out, out_pitch, d_workspace, true);
     const snd_status s = launch_prepared(pr, stream, Multi{nullptr, nullptr, 0}, 0);
     roctxRangePop();
     return s;

@@ -11,6 +11,13 @@
 // 32-bit adds (fan-in x cap < 2^16, so the halves never carry into each other) and clipped with
 // a packed 16-bit minimum; levels 2 .. D close with compile-time control as the plan's closing
 // counts say.  Integer arithmetic in the tree's own order: the result is the tree's, bit for bit.
+//
+// When the stage that wrote the input plane reports its largest value m and F1 m < 256, a
+// level-1 node's sums fit a byte per sample: each input's four samples are aligned into one
+// dword (v_alignbyte_b32, whatever its byte phase), the F1 dwords are added as four bytes at
+// once, and only the node's sum is split into 16-bit counts for the clip.  A sample position
+// that holds no valid output (past the last tile's valid length) may carry out of its byte, but
+// only into higher positions, which hold none either.
 #include <hip/hip_runtime.h>
 
 #include "group_tab.h"
@@ -28,8 +35,9 @@ __device__ inline uint32_t pk_min_u16(uint32_t a, uint32_t b)
 }
 
 // st[(j * R + q) * K + k]: j = 0 .. D - 2 the open partial sums of levels 2 .. D, j = D - 1 the
-// root; k = 2 v + h holds samples (h, h + 2) of the lane's four in block v.
-template <int F1, int D>
+// root; k = 2 v + h holds samples (h, h + 2) of the lane's four in block v.  BYTES: level-1 sums
+// as four bytes per dword (the input plane's bound allows it).
+template <int F1, int D, bool BYTES>
 struct PackGraded {
     using TI = uint8_t;
     using TO = uint8_t;
@@ -89,6 +97,23 @@ struct PackGraded {
         }
     }
 
+    // the same dword pairs, and per input its byte phase
+    static __device__ __forceinline__ void load_row_bytes(uint32_t (&d)[F1][V][2], uint32_t (&ph)[F1], uint32_t w,
+                                                          const unsigned char *lane_base, int j)
+    {
+#pragma unroll
+        for (int u = 0; u < F1; ++u) {
+            const uint32_t o = (uint32_t)__builtin_amdgcn_readlane((int)w, j * F1 + u);
+            ph[u] = o & 3u;
+            const uint32_t *p = reinterpret_cast<const uint32_t *>(lane_base + (o & ~3u));
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                d[u][v][0] = p[64 * v];
+                d[u][v][1] = p[64 * v + 1];
+            }
+        }
+    }
+
     // the level-1 nodes of one batch: for each, its F1 inputs per row, then the closes
     static __device__ __forceinline__ void add_batch(A (&st)[kState], const unsigned char *buf, const unsigned char *w,
                                                      int lane, const Carry &cr, const GroupArgs &s)
@@ -98,6 +123,37 @@ struct PackGraded {
         const uint32_t cap2 = (uint32_t)s.cap * 0x00010001u;
         const unsigned char *lane_base = buf + 4 * lane;
         const int nn = cr.n / F1;
+        if constexpr (BYTES) {
+            for (int j = 0; j < nn; ++j) {
+                const int c = (int)(((j < 8 ? cr.close0 : cr.close1) >> (4 * (j & 7))) & 15u);
+#pragma unroll
+                for (int q = 0; q < R; ++q) {
+                    uint32_t d[F1][V][2], ph[F1];
+                    load_row_bytes(d, ph, wq[q], lane_base, j);
+                    uint32_t a[K];
+#pragma unroll
+                    for (int v = 0; v < V; ++v) {
+                        uint32_t x[F1];
+#pragma unroll
+                        for (int u = 0; u < F1; ++u) x[u] = __builtin_amdgcn_alignbyte(d[u][v][1], d[u][v][0], ph[u]);
+                        // four byte sums below 256 each: no carries between valid samples
+                        uint32_t acc = x[0] + x[1] + x[2];
+#pragma unroll
+                        for (int u = 3; u < F1; u += 2) acc = u + 1 < F1 ? acc + x[u] + x[u + 1] : acc + x[u];
+                        a[2 * v] = __builtin_amdgcn_perm(0u, acc, 0x0c020c00u);      // samples (0, 2)
+                        a[2 * v + 1] = __builtin_amdgcn_perm(0u, acc, 0x0c030c01u);  // samples (1, 3)
+                    }
+#pragma unroll
+                    for (int k = 0; k < K; ++k) {
+                        const uint32_t y = pk_min_u16(a[k], cap2);
+                        if constexpr (D == 1) at(st, OUT, q, k) = y;
+                        else at(st, 0, q, k) += y;
+                    }
+                }
+                close_from<2>(st, c, cap2);
+            }
+            return;
+        }
         for (int j = 0; j < nn; ++j) {
             const int c = (int)(((j < 8 ? cr.close0 : cr.close1) >> (4 * (j & 7))) & 15u);
 #pragma unroll
@@ -156,7 +212,12 @@ struct PackGraded {
 template <int F1, int D>
 __global__ __launch_bounds__(1024) void k_group_pack(GroupArgs s0, Multi m)
 {
-    group_tab_body<PackGraded<F1, D>>(s0, m);
+    // the bound is known for single launches only (batched records carry none); the two bodies
+    // are separate so that neither holds the other's registers
+    if (m.n == 0 && s0.bound && (uint32_t)F1 * as_const(s0.bound)[0] <= 255u)
+        group_tab_body<PackGraded<F1, D, true>>(s0, m);
+    else
+        group_tab_body<PackGraded<F1, D, false>>(s0, m);
 }
 
 namespace {

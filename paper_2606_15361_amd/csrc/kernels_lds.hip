@@ -151,7 +151,13 @@ __global__ __launch_bounds__(64 * kAnchorWaves) void k_anchored(AnchorArgs s0, M
     const int r0 = __builtin_amdgcn_readfirstlane(nd[0]), r1 = __builtin_amdgcn_readfirstlane(nd[1]);
     const int c0 = __builtin_amdgcn_readfirstlane(nd[2]), c1 = __builtin_amdgcn_readfirstlane(nd[3]);
     const int rho_max = __builtin_amdgcn_readfirstlane(nd[4]);
-    if (tau0 >= nd[5] + s.n_run) return;  // past every row of the node in this run (uniform per block)
+    // graded u8 rows: the largest value this workgroup computes, for the packed final stage
+    constexpr bool kBound = MODE == SND_MODE_GRADED && std::is_same<TO, uint8_t>::value;
+    uint32_t vmax = 0;
+    if (tau0 >= nd[5] + s.n_run) {  // past every row of the node in this run (uniform per block)
+        if (kBound && s.bound_slots && tid == 0) s.bound_slots[bid] = 0;
+        return;
+    }
     const_ptr<int32_t> row_lo = as_const(s.row_lo), row_len = as_const(s.row_len);
     const_ptr<uint32_t> row_ptr = as_const(s.row_ptr);
     const_ptr<uint32_t> ent = as_const(reinterpret_cast<const uint32_t *>(s.ent));  // (rowc, off) word pairs
@@ -212,6 +218,7 @@ __global__ __launch_bounds__(64 * kAnchorWaves) void k_anchored(AnchorArgs s0, M
 #pragma unroll
                     for (int u = 1; u < EU; ++u) a += val[u][v];
                     out[v] = activate<MODE>(a, 1, 1, s.k_leaf, s.k_int, s.cap);
+                    if constexpr (kBound) vmax = max(vmax, (uint32_t)out[v]);
                 }
                 const auto dst = as_global(static_cast<TO *>(s.dst)) + (int64_t)r * s.dst_pitch + i0 + lane;
                 if constexpr (MODE == SND_MODE_FLOAT) {
@@ -295,6 +302,7 @@ __global__ __launch_bounds__(64 * kAnchorWaves) void k_anchored(AnchorArgs s0, M
 #pragma unroll
                 for (int v = 0; v < V; ++v) {
                     const int i = i0 + lane + 64 * v;
+                    if constexpr (kBound) vmax = max(vmax, (uint32_t)out[v]);
                     if (i >= 0 && i < len) {
                         if constexpr (MODE == SND_MODE_FLOAT) Store<TO>::put(dst + 64 * v, out[v] * s.scale);
                         else Store<TO>::put(dst + 64 * v, out[v]);
@@ -302,6 +310,48 @@ __global__ __launch_bounds__(64 * kAnchorWaves) void k_anchored(AnchorArgs s0, M
                 }
             }
         }
+    }
+    if constexpr (kBound) {
+        if (s.bound_slots) {  // uniform: every thread of the block gets here
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) vmax = max(vmax, (uint32_t)__shfl_xor((int)vmax, o, 64));
+            // the staged window's first words, once every wave is done reading it (no static LDS,
+            // which would cost the stage a resident workgroup per CU at its LDS target)
+            uint32_t *wave_max = reinterpret_cast<uint32_t *>(smem);
+            __syncthreads();
+            if (lane == 0) wave_max[wave] = vmax;
+            __syncthreads();
+            if (tid == 0) {
+                uint32_t m = 0;
+                for (int w = 0; w < kAnchorWaves; ++w) m = max(m, wave_max[w]);
+                s.bound_slots[bid] = m;
+            }
+        }
+    }
+}
+
+// The largest of n per-workgroup words into slots[n]: one workgroup of 1024 threads, four
+// independent loads in flight per thread.
+__global__ __launch_bounds__(1024) void k_bound_reduce(uint32_t *slots, int64_t n)
+{
+    __shared__ uint32_t wave_max[16];
+    const auto src = as_global(static_cast<const uint32_t *>(slots));
+    uint32_t m[4] = {0, 0, 0, 0};
+    int64_t i = threadIdx.x;
+    for (; i + 3 * 1024 < n; i += 4 * 1024) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) m[u] = max(m[u], src[i + 1024 * u]);
+    }
+    for (; i < n; i += 1024) m[0] = max(m[0], src[i]);
+    uint32_t r = max(max(m[0], m[1]), max(m[2], m[3]));
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) r = max(r, (uint32_t)__shfl_xor((int)r, o, 64));
+    if ((threadIdx.x & 63) == 0) wave_max[threadIdx.x >> 6] = r;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t t = 0;
+        for (int w = 0; w < 16; ++w) t = max(t, wave_max[w]);
+        slots[n] = t;
     }
 }
 
@@ -399,6 +449,13 @@ int launch_anchored(int mode, int src_dt, int dst_dt, const AnchorArgs &a, int64
         return launch_anchored_typed<SND_MODE_BINARY, uint8_t, bits_t>(a, ntiles, lds_bytes, (hipStream_t)stream, m);
     }
     return dispatch_types(mode, src_dt, dst_dt, AnchorLauncher{a, ntiles, lds_bytes, m}, (hipStream_t)stream);
+}
+
+int launch_bound_reduce(uint32_t *slots, int64_t n, void *stream)
+{
+    if (!slots || n <= 0) return (int)hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_bound_reduce, dim3(1), dim3(1024), 0, (hipStream_t)stream, slots, n);
+    return (int)hipGetLastError();
 }
 
 }  // namespace snd

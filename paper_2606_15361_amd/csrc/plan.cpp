@@ -831,6 +831,17 @@ snd_status build_plan(const snd_plan_desc &d, PlanImpl &p, std::string &err)
         S.ws_off = ws;
         ws = round_up(ws + dtype_bytes(S.dst_dtype, S.rows * S.pitch), 256);
     }
+    // a graded u8 leaf plane read by the packed final stage: one bound word per leaf workgroup
+    // and the reduced one after them
+    p.bound_off = -1;
+    p.bound_n = 0;
+    if (p.stages.size() == 2 && p.stages[0].kernel == kKernelAnchored && p.stages[0].dst_dtype == SND_DT_U8 &&
+        p.desc.mode == SND_MODE_GRADED && p.stages[1].kernel == kKernelGroupLds && p.stages[1].group_pack &&
+        p.stages[0].ntiles > 0) {
+        p.bound_off = ws;
+        p.bound_n = p.stages[0].ntiles;
+        ws = round_up(ws + 4 * (p.bound_n + 1), 256);
+    }
     p.workspace_bytes = ws;
 
     // ---------------- info ----------------

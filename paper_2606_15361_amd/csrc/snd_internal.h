@@ -185,6 +185,10 @@ struct PlanImpl {
     std::vector<Stage> stages;
     std::vector<uint8_t> table;  // host image of the device tables
     int64_t workspace_bytes = 0;
+    // graded plans of an input-anchored leaf stage and a packed final stage: workspace offset of
+    // the leaf stage's per-workgroup bound words and their count (bound word after them); -1: none
+    int64_t bound_off = -1;
+    int64_t bound_n = 0;
     int out_dtype = SND_DT_F32;
     void *d_table = nullptr;
     snd_plan_info info{};
@@ -271,6 +275,9 @@ struct GroupArgs {
     int32_t src_is_input;
     int32_t k_leaf, k_int, cap;
     float scale;
+    // packed graded kernel: the largest value of its input plane, written by the stage that
+    // produced it (k_bound_reduce); nullptr: no bound known, the kernel takes its general path
+    const uint32_t *bound;
 };
 int launch_group(int mode, int src_dtype, int dst_dtype, const GroupArgs &a, int64_t n_out, int lds_bytes, void *stream,
                  const Multi &m = Multi{nullptr, nullptr, 0}, int64_t nblocks = 0);
@@ -295,9 +302,14 @@ struct AnchorArgs {
     int32_t n_run;    // output samples of this run (<= n_out)
     int32_t len_cut;  // n_out - n_run: samples dropped from the end of every row
     int32_t tile;     // reference samples per workgroup window (a multiple of kAnchorTile)
+    // graded u8 output: one word per workgroup receives the largest value it computed, and
+    // the word after the last the largest of them all (k_bound_reduce); nullptr: not tracked
+    uint32_t *bound_slots;
 };
 int launch_anchored(int mode, int src_dtype, int dst_dtype, const AnchorArgs &a, int64_t ntiles, int lds_bytes,
                     void *stream, const Multi &m = Multi{nullptr, nullptr, 0});
+// max of the n per-workgroup words at slots into slots[n] (one workgroup)
+int launch_bound_reduce(uint32_t *slots, int64_t n, void *stream);
 int launch_encode(const float *z, int64_t z_pitch, int time_major, int nchan, int64_t nsamp, const float *thr,
                   int nthr, uint8_t *out, int64_t out_pitch, void *stream);
 int launch_encode_bits(const float *z, int64_t z_pitch, int time_major, int nchan, int64_t nsamp, float thr,
@@ -340,8 +352,10 @@ struct Prepared {
     GroupArgs gr;
     AnchorArgs an;
 };
+// bound: track the leaf plane's largest value for the packed graded final stage (single
+// launches only; batched records leave it off and their final stage takes its general path)
 Prepared prepare_stage(const PlanImpl &P, size_t si, const Run &run, const void *d_in, int64_t in_pitch, void *d_out,
-                       int64_t out_pitch, void *d_workspace);
+                       int64_t out_pitch, void *d_workspace, bool bound = false);
 snd_status launch_prepared(const Prepared &pr, void *stream, const Multi &m, int64_t nblocks);
 
 // One beam of a batched execution: its plan, run and buffers.

@@ -216,6 +216,39 @@ def test_graded_packed_levels_exact(snd, orc, nchan, B, cap, levels):
     assert np.array_equal(gpu_run(pg, x), y)
 
 
+@pytest.mark.parametrize("B,top,cap", [(4, 63, 255), (4, 64, 255), (4, 63, 100), (8, 31, 255), (8, 32, 60)])
+def test_graded_packed_byte_sums_at_the_bound(snd, orc, B, top, cap):
+    """The packed kernel adds a level-1 node's inputs as four bytes per dword when the leaf
+    stage's largest value m has F1 m < 256 (F1 = B here), and as 16-bit counts otherwise.  The
+    first F1 clusters carry leaves of exactly `top` over most of the block, so their level-1 node
+    reaches F1 top: 252 or 248 on the byte path, 256 on the other.  The workspace starts filled
+    with 0xFF, so row padding past the valid length holds the largest bytes.  Bit-exact against
+    the oracle and the generic kernels, with a ragged last tile."""
+    rng, f, dms, _ = _case(256, 300, 29 + B + top)
+    d = orc.delays(f, dms, 0.138e-3)
+    nsamp = int(d.max()) + 2600
+    hi = (top - 3) // 4 if B == 4 else (top - 3) // 4 // 2 * 2
+    x = synth.random_levels(rng, 256, nsamp, min(hi, 15))
+    q, r = divmod(top, 4)  # channel values of one cluster summing to top
+    per_cluster = [q + (1 if k < r else 0) for k in range(4)]
+    for c in range(4 * B):
+        x[c, 50:nsamp - 50] = per_cluster[c % 4]
+    want, _ = orc.snd_dedup(x, f, d, mode="graded", cluster=4, branching=B, cap=cap)
+    p = snd.Plan(f, dms, 0.138e-3, nsamp, mode="graded", branching=B, cap=cap)
+    assert p.info["stage_kernel"] == ["anchored", "group_pack"], p.info["stage_kernel"]
+    _say(f"packed byte sums B={B} top={top} cap={cap} n_out={p.n_out}")
+    xt = torch.from_numpy(np.ascontiguousarray(x)).cuda()
+    ws = p.workspace(xt.device)
+    ws.fill_(255)
+    out = p.empty_output(xt.device)
+    p.execute(xt, out=out, workspace=ws)
+    torch.cuda.synchronize()
+    y = to_np(out)
+    assert np.array_equal(y, want.astype(y.dtype))
+    pg = snd.Plan(f, dms, 0.138e-3, nsamp, mode="graded", branching=B, cap=cap, generic_kernels=True)
+    assert np.array_equal(gpu_run(pg, x), y)
+
+
 @pytest.mark.parametrize("mode,node", [("float", "f32"), ("float", "bf16"), ("graded", "u8"), ("binary", "bits"),
                                        ("binary", "u8")])
 def test_tune_variants_identical(snd, orc, mode, node):
