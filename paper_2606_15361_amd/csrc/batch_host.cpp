@@ -82,7 +82,7 @@ snd_status run_batch(const std::vector<Job> &jobs, void *d_records, int64_t reco
             if (w >= j.P->stages.size()) continue;
             if (j.run.n_run <= 0) continue;
             cls[class_key(*j.P, w)].push_back(
-                prepare_stage(*j.P, w, j.run, j.in, j.in_pitch, j.out, j.out_pitch, j.ws));
+                prepare_stage(*j.P, w, j.run, j.in, j.in_pitch, j.out, j.out_pitch, j.ws, true));
         }
         for (auto &kv : cls) {
             std::vector<Prepared> &v = kv.second;
@@ -123,6 +123,16 @@ snd_status run_batch(const std::vector<Job> &jobs, void *d_records, int64_t reco
                 snd_status s = launch_prepared(merged, stream, m, total);
                 if (s != SND_OK) return s;
                 ++nl;
+                // leaf grids of graded beams: each record's largest leaf value for its final stage
+                bool bound = false;
+                for (const Prepared &p : v) bound = bound || (kind == kKernelAnchored && p.an.bound_slots);
+                if (bound) {
+                    const int e = launch_bound_reduce_records(m, stream);
+                    if (e) {
+                        set_error(std::string("leaf bound reduction: ") + hipGetErrorString((hipError_t)e));
+                        return SND_ERR_HIP;
+                    }
+                }
             }
             rec += bytes;
         }

@@ -212,12 +212,15 @@ struct PackGraded {
 template <int F1, int D>
 __global__ __launch_bounds__(1024) void k_group_pack(GroupArgs s0, Multi m)
 {
-    // the bound is known for single launches only (batched records carry none); the two bodies
-    // are separate so that neither holds the other's registers
-    if (m.n == 0 && s0.bound && (uint32_t)F1 * as_const(s0.bound)[0] <= 255u)
-        group_tab_body<PackGraded<F1, D, true>>(s0, m);
+    GroupArgs s;
+    uint32_t bid, nblk;
+    select_record(s0, m, s, bid, nblk);
+    // per record (uniform per workgroup); the two bodies are separate so that neither holds the
+    // other's registers
+    if (s.bound && (uint32_t)F1 * as_const(s.bound)[0] <= 255u)
+        group_tab_run<PackGraded<F1, D, true>>(s, bid, nblk);
     else
-        group_tab_body<PackGraded<F1, D, false>>(s0, m);
+        group_tab_run<PackGraded<F1, D, false>>(s, bid, nblk);
 }
 
 namespace {

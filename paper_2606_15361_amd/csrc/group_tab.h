@@ -16,8 +16,9 @@
 
 namespace snd {
 
+// The pipeline for workgroup bid of nblk over the arguments s (its record, already selected).
 template <class Sum>
-__device__ __forceinline__ void group_tab_body(const GroupArgs &s0, const Multi &m)
+__device__ __forceinline__ void group_tab_run(const GroupArgs &s, uint32_t bid, uint32_t nblk)
 {
     using TI = typename Sum::TI;
     using A = typename Sum::A;
@@ -25,9 +26,6 @@ __device__ __forceinline__ void group_tab_body(const GroupArgs &s0, const Multi 
     constexpr int R = Sum::kRows, T = Sum::kStep, NW = Sum::kWords, NSM = Sum::kSmemWords;
     constexpr int WPL = NW / 64;  // offset words per lane
     static_assert(WPL == 1 || WPL == 4, "one global_load_lds of 4 or 16 bytes per lane");
-    GroupArgs s;
-    uint32_t bid, nblk;
-    select_record(s0, m, s, bid, nblk);
     extern __shared__ __align__(16) unsigned char smem[];
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -113,6 +111,15 @@ __device__ __forceinline__ void group_tab_body(const GroupArgs &s0, const Multi 
         if (row[q] < 0) continue;
         Sum::store(st, q, static_cast<typename Sum::TO *>(s.dst) + (int64_t)row[q] * s.dst_pitch + t0, lane, vt, s);
     }
+}
+
+template <class Sum>
+__device__ __forceinline__ void group_tab_body(const GroupArgs &s0, const Multi &m)
+{
+    GroupArgs s;
+    uint32_t bid, nblk;
+    select_record(s0, m, s, bid, nblk);
+    group_tab_run<Sum>(s, bid, nblk);
 }
 
 }  // namespace snd

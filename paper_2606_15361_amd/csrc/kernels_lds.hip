@@ -332,7 +332,7 @@ __global__ __launch_bounds__(64 * kAnchorWaves) void k_anchored(AnchorArgs s0, M
 
 // The largest of n per-workgroup words into slots[n]: one workgroup of 1024 threads, four
 // independent loads in flight per thread.
-__global__ __launch_bounds__(1024) void k_bound_reduce(uint32_t *slots, int64_t n)
+__device__ __forceinline__ void bound_reduce(uint32_t *slots, int64_t n)
 {
     __shared__ uint32_t wave_max[16];
     const auto src = as_global(static_cast<const uint32_t *>(slots));
@@ -353,6 +353,21 @@ __global__ __launch_bounds__(1024) void k_bound_reduce(uint32_t *slots, int64_t 
         for (int w = 0; w < 16; ++w) t = max(t, wave_max[w]);
         slots[n] = t;
     }
+}
+
+__global__ __launch_bounds__(1024) void k_bound_reduce(uint32_t *slots, int64_t n) { bound_reduce(slots, n); }
+
+// Batched leaf grids: workgroup r reduces the words of record r (its workgroup count from the
+// prefix table), when the record tracks them.
+__global__ __launch_bounds__(1024) void k_bound_reduce_records(Multi m)
+{
+    const int r = (int)blockIdx.x;
+    const_ptr<int32_t> pre = as_const(m.prefix);
+    const int64_t n = pre[r + 1] - pre[r];
+    const auto *rec = static_cast<const AnchorArgs *>(m.recs) + r;
+    uint32_t *slots = rec->bound_slots;
+    if (!slots || n <= 0) return;
+    bound_reduce(slots, n);
 }
 
 template <int MODE, typename TI, typename TO>
@@ -455,6 +470,13 @@ int launch_bound_reduce(uint32_t *slots, int64_t n, void *stream)
 {
     if (!slots || n <= 0) return (int)hipErrorInvalidValue;
     hipLaunchKernelGGL(k_bound_reduce, dim3(1), dim3(1024), 0, (hipStream_t)stream, slots, n);
+    return (int)hipGetLastError();
+}
+
+int launch_bound_reduce_records(const Multi &m, void *stream)
+{
+    if (m.n <= 0) return 0;
+    hipLaunchKernelGGL(k_bound_reduce_records, dim3((uint32_t)m.n), dim3(1024), 0, (hipStream_t)stream, m);
     return (int)hipGetLastError();
 }
 

@@ -310,6 +310,8 @@ int launch_anchored(int mode, int src_dtype, int dst_dtype, const AnchorArgs &a,
                     void *stream, const Multi &m = Multi{nullptr, nullptr, 0});
 // max of the n per-workgroup words at slots into slots[n] (one workgroup)
 int launch_bound_reduce(uint32_t *slots, int64_t n, void *stream);
+// the same for every record of a batched leaf grid that tracks its words (one workgroup each)
+int launch_bound_reduce_records(const Multi &m, void *stream);
 int launch_encode(const float *z, int64_t z_pitch, int time_major, int nchan, int64_t nsamp, const float *thr,
                   int nthr, uint8_t *out, int64_t out_pitch, void *stream);
 int launch_encode_bits(const float *z, int64_t z_pitch, int time_major, int nchan, int64_t nsamp, float thr,
@@ -352,8 +354,8 @@ struct Prepared {
     GroupArgs gr;
     AnchorArgs an;
 };
-// bound: track the leaf plane's largest value for the packed graded final stage (single
-// launches only; batched records leave it off and their final stage takes its general path)
+// bound: track the leaf plane's largest value for the packed graded final stage (a batched leaf
+// grid is followed by launch_bound_reduce_records, a single leaf launch by launch_bound_reduce)
 Prepared prepare_stage(const PlanImpl &P, size_t si, const Run &run, const void *d_in, int64_t in_pitch, void *d_out,
                        int64_t out_pitch, void *d_workspace, bool bound = false);
 snd_status launch_prepared(const Prepared &pr, void *stream, const Multi &m, int64_t nblocks);

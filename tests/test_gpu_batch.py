@@ -110,6 +110,46 @@ def test_batch_matches_per_beam_and_oracle(snd, orc):
     assert all(np.array_equal(to_np(o), to_np(p.execute(x))) for p, x, o in zip(plans, xs, outs))
 
 
+def test_batch_graded_records_choose_their_level1_sums(snd, orc):
+    """Graded beams of one batched grid whose packed final stage runs level-1 sums as bytes or as
+    16-bit counts, each record by its own leaf maximum: leaves of at most 16 and exactly 63 (byte
+    path at B = 4) beside leaves of 64 (16-bit path), with time-chunked runs and every workspace
+    filled with 0xFF.  Bit-exact against the oracle and one execute per beam."""
+    cases = [(16, 255, None), (63, 255, None), (64, 255, None), (63, 90, 1500)]
+    plans, xs, wants, n_run = [], [], [], []
+    for i, (top, cap, nr) in enumerate(cases):
+        rng = synth.make_rng(900 + i)
+        f = synth.channel_freqs(256)
+        dms = np.sort(rng.uniform(0, 40.0, 200 + 37 * i))
+        d = orc.delays(f, dms, 0.138e-3)
+        nsamp = int(d.max()) + 2300 + 111 * i
+        x = synth.random_levels(rng, 256, nsamp, 4)
+        if top > 16:
+            q, r = divmod(top, 4)
+            for c in range(16):
+                x[c, 40:nsamp - 40] = q + (1 if c % 4 < r else 0)
+        want, _ = orc.snd_dedup(x, f, d, mode="graded", cluster=4, branching=4, cap=cap)
+        p = snd.Plan(f, dms, 0.138e-3, nsamp, mode="graded", branching=4, cap=cap)
+        assert p.info["stage_kernel"] == ["anchored", "group_pack"], p.info["stage_kernel"]
+        plans.append(p)
+        xs.append(torch.from_numpy(np.ascontiguousarray(x)).cuda())
+        wants.append(want)
+        n_run.append(p.n_out if nr is None else nr)
+    batch = snd.Batch(plans)
+    for w in batch.workspaces:
+        w.fill_(255)
+    outs = [p.empty_output("cuda") for p in plans]
+    for o in outs:
+        o.zero_()
+    nl = batch.execute(xs, outs, n_run=n_run)
+    torch.cuda.synchronize()
+    _say(f"graded batch of {len(plans)} beams in {nl} grids")
+    for i, (p, x, o, want, nr) in enumerate(zip(plans, xs, outs, wants, n_run)):
+        y = to_np(o)[:, :nr]
+        assert np.array_equal(y, want[:, :nr].astype(y.dtype)), i
+        assert np.array_equal(y, to_np(p.execute(x))[:, :nr]), i
+
+
 def test_batch_time_chunks_equal_whole_run(snd, orc):
     """A long beam cut into time chunks of a chunk plan (pointer offsets + n_run) reproduces
     the plain execute of the whole block."""
