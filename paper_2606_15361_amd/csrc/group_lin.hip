@@ -11,7 +11,9 @@
 //  * bf16 / f16 rows: lane i owns the sample pairs (2 i + 128 v, 2 i + 1 + 128 v), one dword.
 //    An input whose first sample sits in the upper half of a dword takes the upper half of that
 //    dword and the lower half of the next one (a second read); the branch on that is uniform.
-//    f16 samples are widened to FP32 exactly before they are added.  bf16 inputs go in twos: one
+//    f16 samples are added by v_fma_mix_f32 with a multiplier of 1.0 (the f16 half widened
+//    exactly, the product exact, one rounding: the FP32 add of the widened sample, in one
+//    instruction).  bf16 inputs go in twos: one
 //    byte permute puts the two inputs' samples of one output sample into one dword, and one
 //    v_dot2_f32_bf16 with weights (1, 1) adds both to the FP32 sum (one instruction per sample
 //    instead of a widening and an add).  Only samples of the output being formed enter a dot.
@@ -116,6 +118,31 @@ struct Lin16 : LinBase {
         if constexpr (F16) return (float)__builtin_bit_cast(_Float16, (uint16_t)(d >> 16));
         else return __uint_as_float(d & 0xffff0000u);
     }
+    // f16: acc + the lower or upper half of d, widened, as one FP32 add (v_fma_mix_f32 with a
+    // multiplier of 1.0 in a scalar register)
+    static __device__ __forceinline__ float mix_lo(float acc, uint32_t d, uint32_t one)
+    {
+        float r;
+        asm("v_fma_mix_f32 %0, %1, %2, %3 op_sel_hi:[1,0,0]" : "=v"(r) : "v"(d), "s"(one), "v"(acc));
+        return r;
+    }
+    static __device__ __forceinline__ float mix_hi(float acc, uint32_t d, uint32_t one)
+    {
+        float r;
+        asm("v_fma_mix_f32 %0, %1, %2, %3 op_sel:[1,0,0] op_sel_hi:[1,0,0]" : "=v"(r) : "v"(d), "s"(one), "v"(acc));
+        return r;
+    }
+    // acc + lower(d) / upper(d): one instruction for f16, widening and add for bf16
+    static __device__ __forceinline__ float add_lo(float acc, uint32_t d, uint32_t one)
+    {
+        if constexpr (F16) return mix_lo(acc, d, one);
+        else return acc + lower(d);
+    }
+    static __device__ __forceinline__ float add_hi(float acc, uint32_t d, uint32_t one)
+    {
+        if constexpr (F16) return mix_hi(acc, d, one);
+        else return acc + upper(d);
+    }
     // byte selectors of v_perm_b32 (a, b): the lower halves of b and a, or their upper halves
     static constexpr uint32_t kLoLo = 0x05040100u, kHiHi = 0x07060302u;
     // acc + the two bf16 samples that the selector picks from a and b (weights one2 = (1, 1))
@@ -136,9 +163,10 @@ struct Lin16 : LinBase {
         const int n = c.n;
         const uint32_t even = c.even;
         // (1.0, 1.0) in bf16, materialised in a scalar register so that the compiler cannot encode
-        // it as an inline constant (which the hardware would apply to one half only)
+        // it as an inline constant (which the hardware would apply to one half only); 1.0f for f16
         uint32_t one2;
-        asm volatile("s_mov_b32 %0, 0x3f803f80" : "=s"(one2));
+        if constexpr (F16) asm volatile("s_mov_b32 %0, 0x3f800000" : "=s"(one2));
+        else asm volatile("s_mov_b32 %0, 0x3f803f80" : "=s"(one2));
         const unsigned char *lane_base = buf + 4 * lane;
 #pragma unroll
         for (int q = 0; q < R; ++q) {
@@ -158,8 +186,8 @@ struct Lin16 : LinBase {
                     for (int u = 0; u < 2; ++u)
 #pragma unroll
                         for (int v = 0; v < V; ++v) {
-                            st[LO + q * V + v] += lower(x[u][v]);
-                            st[HI + q * V + v] += upper(x[u][v]);
+                            st[LO + q * V + v] = add_lo(st[LO + q * V + v], x[u][v], one2);
+                            st[HI + q * V + v] = add_hi(st[HI + q * V + v], x[u][v], one2);
                         }
                 } else {
 #pragma unroll
@@ -177,8 +205,8 @@ struct Lin16 : LinBase {
                 for (int v = 0; v < V; ++v) x[v] = p[64 * v];
 #pragma unroll
                 for (int v = 0; v < V; ++v) {
-                    st[LO + q * V + v] += lower(x[v]);
-                    st[HI + q * V + v] += upper(x[v]);
+                    st[LO + q * V + v] = add_lo(st[LO + q * V + v], x[v], one2);
+                    st[HI + q * V + v] = add_hi(st[HI + q * V + v], x[v], one2);
                 }
                 ++k;
             }
@@ -214,8 +242,8 @@ struct Lin16 : LinBase {
                 }
 #pragma unroll
                 for (int v = 0; v < V; ++v) {
-                    st[LO + q * V + v] += upper(x[v]);
-                    st[HI + q * V + v] += lower(y[v]);
+                    st[LO + q * V + v] = add_hi(st[LO + q * V + v], x[v], one2);
+                    st[HI + q * V + v] = add_lo(st[HI + q * V + v], y[v], one2);
                 }
             }
         }
