@@ -189,7 +189,11 @@ snd_status snd_execute(snd_plan plan, const void *d_in, int64_t in_pitch, void *
  * One stage of snd_execute (0 <= stage < n_stages), for callers that time or interleave the
  * stages: stage 0 reads d_in, every later stage reads the workspace written by the stage
  * before it, the last stage writes d_out.  Running stages 0 .. n_stages-1 in order on one
- * stream is exactly snd_execute.  Same arguments and errors as snd_execute.
+ * stream is exactly snd_execute.  Same arguments and errors as snd_execute.  Besides the node
+ * rows, the workspace carries what a stage records for the next: for graded plans whose final
+ * stage is the packed kernel (stage_kernel 7), stage 0 writes the largest leaf value there, and
+ * the final stage picks its level-1 arithmetic from it, so a final stage must follow the
+ * stage 0 that wrote its workspace (as in snd_execute).
  */
 snd_status snd_execute_stage(snd_plan plan, int32_t stage, const void *d_in, int64_t in_pitch, void *d_out,
                              int64_t out_pitch, void *d_workspace, int64_t workspace_bytes, void *stream);
