@@ -942,6 +942,8 @@ def main():
     es = {"f32": 4, "bf16": 2, "f16": 2, "u8": 1, "u16": 2, "bits": 0.125}[info["stage_src_dtype"][dom]]
     lds_alg = info["stage_entries"][dom] * plan.n_out * es
     whole_alg = sum(info["stage_alg_bytes"])
+    node_es = {"f32": 4, "bf16": 2, "f16": 2, "u8": 1, "u16": 2, "bits": 0.125}[node]
+    level_bytes = int(info["n_neurons"] * node_es * 2 * plan.n_out)
     # the type the tree arithmetic runs in: float storage types accumulate in FP32; binary bit
     # rows are evaluated with bitwise logic on 1-bit samples
     dtype_name = {"float": "f32" if node == "f32" else node, "graded": node, "binary": "u1" if node == "bits" else "u8"}[mode]
@@ -973,6 +975,12 @@ def main():
         "tree_hbm": {"alg_bytes": whole_alg, "ms": round(float(stage_ms.sum()), 4),
                      "achieved": whole_alg / (stage_ms.sum() * 1e-3) / 1e9,
                      "frac": whole_alg / (stage_ms.sum() * 1e-3) / 1e9 / HBM_PEAK_GBS},
+        # the level-by-level count (every neuron of every level written once and read once per
+        # output sample, in the node storage type), against which a 60 %-of-peak time is quoted;
+        # the fused tree keeps levels 1 .. root in registers and moves far fewer bytes
+        "level_model": {"bytes": level_bytes, "ms_at_60pct_peak": round(level_bytes / (0.6 * HBM_PEAK_GBS * 1e9) * 1e3, 3),
+                        "tree_ms": round(float(stage_ms.sum()), 4),
+                        "effective_gbs": level_bytes / (stage_ms.sum() * 1e-3) / 1e9},
         "stage_ms": [round(v, 4) for v in stage_ms],
         "stage_alg_gb": [round(b / 1e9, 3) for b in info["stage_alg_bytes"]],
         "detect_ms": round(det_ms, 4),
