@@ -4,9 +4,10 @@
 //
 // Staging is that of the other row-group kernels: 16 waves of 1024 threads, leaf windows copied
 // global -> LDS in double-buffered batches, full tiles by 64-unit chunks listed in the plan.  Each
-// wave sums eight DM rows, so 128 DM-adjacent rows share the staged windows.  Every read is a
-// dword at o + 4 i + 256 v for an input at LDS byte offset o (lane i, v = 0 .. 3 or 7), which
-// pairs into stride-64 reads of two dwords and needs 4-byte alignment only:
+// wave sums four DM rows over a tile of 1024 samples, so 64 DM-adjacent rows share the staged
+// windows.  Every read is a dword at o + 4 i + 256 v for an input at LDS byte offset o (lane i,
+// v = 0 .. 7 or 15), which pairs into stride-64 reads of two dwords and needs 4-byte alignment
+// only:
 //  * f32 rows: lane i owns samples i + 64 v, one per dword, and every input takes one path.
 //  * bf16 / f16 rows: lane i owns the sample pairs (2 i + 128 v, 2 i + 1 + 128 v), one dword.
 //    An input whose first sample sits in the upper half of a dword takes the upper half of that

@@ -42,8 +42,8 @@ struct PackGraded {
     using TI = uint8_t;
     using TO = uint8_t;
     using A = uint32_t;
-    static constexpr int kRows = kPackRows, kStep = kLinTile, kWords = kPackWords, kSmemWords = kPackSmemWords;
-    static constexpr int R = kRows, V = kLinTile / 256, K = 2 * V;
+    static constexpr int kRows = kPackRows, kStep = kPackTile, kWords = kPackWords, kSmemWords = kPackSmemWords;
+    static constexpr int R = kRows, V = kPackTile / 256, K = 2 * V;
     static constexpr int OUT = D - 1;  // slot of the root
     static constexpr int kState = D * R * K;
     static_assert(F1 >= 3, "three-input adds");
@@ -228,7 +228,7 @@ namespace {
 template <int F1, int D>
 int launch_pack(const GroupArgs &a, int64_t n_out, int lds, void *stream, const Multi &m, int64_t nb_multi)
 {
-    const int64_t ntt = (n_out + kLinTile - 1) / kLinTile;
+    const int64_t ntt = (n_out + kPackTile - 1) / kPackTile;
     const int64_t nb = m.n > 0 ? nb_multi : (int64_t)a.ngroups * ntt;
     if (nb <= 0) return 0;
     if (nb > 0x7fffffffLL) return (int)hipErrorInvalidValue;

@@ -166,7 +166,7 @@ bool build_group_lds(const PlanImpl &p, Stage &S, int variant)
                      : bits ? kGroupTileBits
                      : f1   ? kGroupTileFast
                             : kGroupTile;
-    const int tile_step = tab ? kLinTile : tile;
+    const int tile_step = lin ? kLinTile : pack ? kPackTile : tile;
     const int rpw = lin ? kLinRows : pack ? kPackRows : f1 ? kFastRows : 1;  // rows per wave
     const int max_entries = lin ? kLinMaxBatchEntries : kPackMaxBatchEntries;  // table kernels
     const int n_words = lin ? kLinWords : kPackWords;

@@ -108,15 +108,17 @@ constexpr int kGroupTileFast = 64 * kFastV;
 constexpr int kFastBuffers = 2;           // batch b + 1 lands while b is read
 constexpr int kGroupFastLdsBytes = 81920; // per buffer (two fill the 160 KB of LDS)
 constexpr int kGroupTileBits = 2048;  // bit rows: 32 samples (one word) per lane
-// Linear kernel: each wave sums kLinRows DM rows (128 DM-adjacent rows per workgroup share the
-// staged windows) over tiles of 512 samples: f32 rows, lane i owns samples i + 64 v
-// (v = 0 .. 7); 16-bit rows, lane i owns the sample pairs 2 i + 128 v (v = 0 .. 3), and an input
+// Linear kernel: each wave sums kLinRows DM rows (64 DM-adjacent rows per workgroup share the
+// staged windows) over tiles of 1024 samples: f32 rows, lane i owns samples i + 64 v
+// (v = 0 .. 15); 16-bit rows, lane i owns the sample pairs 2 i + 128 v (v = 0 .. 7), and an input
 // that starts in the upper half of a dword reads one dword past the tile, so those windows
 // stage one 16-byte unit more.
-constexpr int kLinRows = 8;
-constexpr int kLinTile = 512;                  // output samples per workgroup tile
+constexpr int kLinRows = 4;
+constexpr int kLinTile = 1024;                 // output samples per workgroup tile
 inline int lin_cover(int src_dtype) { return src_dtype == SND_DT_F32 ? kLinTile : kLinTile + 8; }
-constexpr int kLinMaxBatchEntries = 64 / kLinRows;  // the wave's offset words fit 64 lanes
+// inputs per row and batch: the wave's offset words fit 64 lanes, and the 16-bit kernels pack
+// each row's count of inputs of one dword phase in 4 bits
+constexpr int kLinMaxBatchEntries = 64 / kLinRows < 15 ? 64 / kLinRows : 15;
 constexpr int kLinWords = 64;                  // offset words per (batch, wave)
 constexpr int kLinMaxChunks = 7;               // copy chunks per (batch, wave)
 constexpr int kLinSmemWords = 24;              // chunk count, 7 units, 7 LDS offsets, 7 lengths, counts, n
@@ -124,14 +126,16 @@ constexpr int kLinBuffers = 2;                 // batch b + 1 lands while b is r
 constexpr int kLinWordBytes = kGroupRows * kLinWords * 4;  // each buffer's copy of its batch's offset words
 constexpr int kLinLdsBytes = (163840 / kLinBuffers - kLinWordBytes) / 16 * 16;  // window bytes per buffer
 // Packed kernel (graded mode on u8 rows, regular level-1 nodes of 4 or 8 inputs): the staging
-// and copy tables of the linear kernel; each wave computes kPackRows DM rows (64-row groups),
-// lane i owns samples 4 i + 256 v (v = 0, 1) as two pairs of 16-bit counts, and reads each
+// and copy tables of the linear kernel; each wave computes kPackRows DM rows (64-row groups)
+// over tiles of kPackTile samples, lane i owns samples 4 i + 256 v (v = 0, 1) as two pairs of
+// 16-bit counts (a 1024-sample tile would need twice the open level sums), and reads each
 // input as two aligned dwords (its first four samples may start in either), so windows stage
 // one 16-byte unit beyond the tile.  Offset words: lane i, component q of a 16-byte word holds
 // input i of row q.  Scalar words: those of the linear kernel, then the levels each level-1
 // node of the batch completes (4 bits per node, two words), then n.
 constexpr int kPackRows = 4;
-constexpr int kPackCover = kLinTile + 16;
+constexpr int kPackTile = 512;
+constexpr int kPackCover = kPackTile + 16;
 constexpr int kPackMaxBatchEntries = 64;
 constexpr int kPackWords = 256;                // offset words per (batch, wave)
 constexpr int kPackSmemWords = 25;

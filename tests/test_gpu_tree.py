@@ -148,8 +148,8 @@ def test_float_small_integer_input_is_exact(snd, orc):
 def test_float_storage_small_integers_exact(snd, orc, node, B):
     """Small-integer float input (levels -3..4): leaf sums (|v| <= 16) are exact in bf16 and f16
     and the roots exact in FP32, so every storage type must reproduce the FP64 oracle bit for bit.  300 DMs
-    fill three 128-row groups of the one-sum final stage (the last one partly), and 2600 output
-    samples make five full 512-sample tiles and a ragged one; random DMs give inputs of both
+    fill five 64-row groups of the one-sum final stage (the last one partly), and 2600 output
+    samples make two full 1024-sample tiles and a ragged one; random DMs give inputs of both
     dword phases on 16-bit rows."""
     rng, f, dms, _ = _case(96, 300, 11 + B)
     d = orc.delays(f, dms, 0.138e-3)
@@ -174,7 +174,7 @@ def test_float_rows_sum_error_bound(snd, orc, node):
     association, n roundings of at most one unit in the last place (round to nearest: half of
     one; the bf16 kernel's paired dots: one) keep |y - exact| <= n 2^-23 sum|x| with n = 128
     inputs per root; a dropped or foreign sample, or a non-sample half in a dot, breaks it.  300
-    DMs and 2600 output samples: three 128-row groups, five full tiles and a ragged one."""
+    DMs and 2600 output samples: five 64-row groups, two full 1024-sample tiles and a ragged one."""
     rng, f, dms, _ = _case(512, 300, 71)
     d = orc.delays(f, dms, 0.138e-3)
     nsamp = int(d.max()) + 2600
