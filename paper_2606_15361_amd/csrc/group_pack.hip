@@ -3,8 +3,9 @@
 // level up to the root).
 //
 // Staging is the table pipeline of the one-sum float kernel (group_tab.h).  Each wave computes
-// four DM rows (64 DM-adjacent rows per workgroup) over a tile of 512 samples; lane i owns
-// samples 4 i + 256 v (v = 0, 1).  An input at LDS byte offset o is read as the two aligned
+// two DM rows over a tile of 1024 samples (32 DM-adjacent rows per workgroup) where the open
+// level sums of the shape allow (four inputs per level-1 node, depth <= 4), else four rows over
+// 512 samples; lane i owns samples 4 i + 256 v.  An input at LDS byte offset o is read as the two aligned
 // dwords that hold its four samples for the lane (one ds_read2_b32), and one byte permute per
 // pair picks them out as two 16-bit counts: (samples 0, 2) and (samples 1, 3), whichever byte of
 // the dword the input starts at.  Level sums are then formed two samples per instruction with
@@ -42,8 +43,9 @@ struct PackGraded {
     using TI = uint8_t;
     using TO = uint8_t;
     using A = uint32_t;
-    static constexpr int kRows = kPackRows, kStep = kPackTile, kWords = kPackWords, kSmemWords = kPackSmemWords;
-    static constexpr int R = kRows, V = kPackTile / 256, K = 2 * V;
+    static constexpr int kRows = pack_rows(F1, D), kStep = pack_tile(F1, D), kWords = kPackWords,
+                         kSmemWords = kPackSmemWords;
+    static constexpr int R = kRows, V = kStep / 256, K = 2 * V;
     static constexpr int OUT = D - 1;  // slot of the root
     static constexpr int kState = D * R * K;
     static_assert(F1 >= 3, "three-input adds");
@@ -228,7 +230,7 @@ namespace {
 template <int F1, int D>
 int launch_pack(const GroupArgs &a, int64_t n_out, int lds, void *stream, const Multi &m, int64_t nb_multi)
 {
-    const int64_t ntt = (n_out + kPackTile - 1) / kPackTile;
+    const int64_t ntt = (n_out + pack_tile(F1, D) - 1) / pack_tile(F1, D);
     const int64_t nb = m.n > 0 ? nb_multi : (int64_t)a.ngroups * ntt;
     if (nb <= 0) return 0;
     if (nb > 0x7fffffffLL) return (int)hipErrorInvalidValue;

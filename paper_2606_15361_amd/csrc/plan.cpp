@@ -162,12 +162,12 @@ bool build_group_lds(const PlanImpl &p, Stage &S, int variant)
     // samples a window holds beyond its span (its tile, plus one unit for the linear kernel on
     // 16-bit rows), and the tile step in time
     const int tile = lin    ? lin_cover(S.src_dtype)
-                     : pack ? kPackCover
+                     : pack ? pack_tile(f1, S.depth) + 16
                      : bits ? kGroupTileBits
                      : f1   ? kGroupTileFast
                             : kGroupTile;
-    const int tile_step = lin ? kLinTile : pack ? kPackTile : tile;
-    const int rpw = lin ? kLinRows : pack ? kPackRows : f1 ? kFastRows : 1;  // rows per wave
+    const int tile_step = lin ? kLinTile : pack ? pack_tile(f1, S.depth) : tile;
+    const int rpw = lin ? kLinRows : pack ? pack_rows(f1, S.depth) : f1 ? kFastRows : 1;  // rows per wave
     const int max_entries = lin ? kLinMaxBatchEntries : kPackMaxBatchEntries;  // table kernels
     const int n_words = lin ? kLinWords : kPackWords;
     const int n_smem = lin ? kLinSmemWords : kPackSmemWords;
@@ -311,7 +311,7 @@ bool build_group_lds(const PlanImpl &p, Stage &S, int variant)
     }
     std::vector<uint32_t> lin_tab, lin_smem;
     static_assert(kLinMaxBatchEntries <= 15, "per-row input counts are packed in 4 bits");
-    static_assert(kPackMaxBatchEntries / 4 <= 16 && kPackRows <= 4, "packed kernel: two closes words, 16-byte words");
+    static_assert(kPackMaxBatchEntries / 4 <= 16 && kPackRowsMax <= 4, "packed kernel: two closes words, 16-byte words");
     if (tab) {
         // per (batch, wave) the offset words of the wave's rows, and its copy chunks as scalar words
         const int64_t nb_all = (int64_t)(batches.size() / 4);
@@ -327,7 +327,7 @@ bool build_group_lds(const PlanImpl &p, Stage &S, int variant)
                     uint32_t *words = &lin_tab[(size_t)((b * kGroupRows + w) * n_words)];
                     uint32_t *sm = &lin_smem[(size_t)((b * kGroupRows + w) * n_smem)];
                     if (pack) {  // lane i, component q: input i of row q; then each node's closes
-                        for (int q = 0; q < kPackRows; ++q) {
+                        for (int q = 0; q < rpw; ++q) {
                             const int32_t r = grp_rows[(size_t)(g * gr + w * rpw + q)];
                             for (int32_t e = ex; e < ey && r >= 0; ++e)
                                 words[4 * (e - ex) + q] = ldsb_at(g, w * rpw + q, e) & kRowMask;

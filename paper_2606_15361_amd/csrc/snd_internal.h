@@ -126,16 +126,17 @@ constexpr int kLinBuffers = 2;                 // batch b + 1 lands while b is r
 constexpr int kLinWordBytes = kGroupRows * kLinWords * 4;  // each buffer's copy of its batch's offset words
 constexpr int kLinLdsBytes = (163840 / kLinBuffers - kLinWordBytes) / 16 * 16;  // window bytes per buffer
 // Packed kernel (graded mode on u8 rows, regular level-1 nodes of 4 or 8 inputs): the staging
-// and copy tables of the linear kernel; each wave computes kPackRows DM rows (64-row groups)
-// over tiles of kPackTile samples, lane i owns samples 4 i + 256 v (v = 0, 1) as two pairs of
-// 16-bit counts (a 1024-sample tile would need twice the open level sums), and reads each
-// input as two aligned dwords (its first four samples may start in either), so windows stage
-// one 16-byte unit beyond the tile.  Offset words: lane i, component q of a 16-byte word holds
-// input i of row q.  Scalar words: those of the linear kernel, then the levels each level-1
-// node of the batch completes (4 bits per node, two words), then n.
-constexpr int kPackRows = 4;
-constexpr int kPackTile = 512;
-constexpr int kPackCover = kPackTile + 16;
+// and copy tables of the linear kernel; each wave computes pack_rows DM rows over tiles of
+// pack_tile samples: two rows over 1024 samples where the open level sums of the shape fit the
+// registers (four inputs per level-1 node, depth <= 4: 32-row groups), four rows over 512
+// samples otherwise (64-row groups).  Lane i owns samples 4 i + 256 v as two pairs of 16-bit
+// counts, and reads each input as two aligned dwords (its first four samples may start in
+// either), so windows stage one 16-byte unit beyond the tile.  Offset words: lane i, component
+// q of a 16-byte word holds input i of row q.  Scalar words: those of the linear kernel, then
+// the levels each level-1 node of the batch completes (4 bits per node, two words), then n.
+constexpr int pack_rows(int f1, int depth) { return f1 == 4 && depth <= 4 ? 2 : 4; }
+constexpr int pack_tile(int f1, int depth) { return pack_rows(f1, depth) == 2 ? 1024 : 512; }
+constexpr int kPackRowsMax = 4;
 constexpr int kPackMaxBatchEntries = 64;
 constexpr int kPackWords = 256;                // offset words per (batch, wave)
 constexpr int kPackSmemWords = 25;

@@ -201,8 +201,9 @@ def test_float_rows_sum_error_bound(snd, orc, node):
 def test_graded_packed_levels_exact(snd, orc, nchan, B, cap, levels):
     """Graded u8 rows with level-1 nodes of 4 or 8 inputs run the packed kernel (two 16-bit
     counts per dword); small caps clip at every level.  Bit-exact against the oracle and the
-    generic kernels, over 300 DMs (five 64-row groups, the last partial) and a ragged sixth
-    512-sample tile."""
+    generic kernels, over 300 DMs (32-row groups over 1024-sample tiles at four inputs per node
+    and depth <= 4, else 64-row groups over 512 samples; the last group partial in both) and
+    2600 output samples (a ragged last tile in both)."""
     rng, f, dms, _ = _case(nchan, 300, 17 + B + cap)
     d = orc.delays(f, dms, 0.138e-3)
     x = synth.random_levels(rng, nchan, int(d.max()) + 2600, levels)
