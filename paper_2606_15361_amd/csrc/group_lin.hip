@@ -4,10 +4,10 @@
 //
 // Staging is that of the other row-group kernels: 16 waves of 1024 threads, leaf windows copied
 // global -> LDS in double-buffered batches, full tiles by 64-unit chunks listed in the plan.  Each
-// wave sums four DM rows over a tile of 1024 samples, so 64 DM-adjacent rows share the staged
-// windows.  Every read is a dword at o + 4 i + 256 v for an input at LDS byte offset o (lane i,
-// v = 0 .. 7 or 15), which pairs into stride-64 reads of two dwords and needs 4-byte alignment
-// only:
+// wave sums eight DM rows over a tile of 512 samples (f32 rows: 128 DM-adjacent rows share the
+// staged windows) or four rows over 1024 samples (16-bit rows: 64-row groups).  Every read is a
+// dword at o + 4 i + 256 v for an input at LDS byte offset o (lane i, v = 0 .. 7), which pairs
+// into stride-64 reads of two dwords and needs 4-byte alignment only:
 //  * f32 rows: lane i owns samples i + 64 v, one per dword, and every input takes one path.
 //  * bf16 / f16 rows: lane i owns the sample pairs (2 i + 128 v, 2 i + 1 + 128 v), one dword.
 //    An input whose first sample sits in the upper half of a dword takes the upper half of that
@@ -34,19 +34,17 @@ namespace snd {
 
 namespace {
 
-constexpr int R = kLinRows;
-
 // The policies below index the sums of a wave in a plain array of the pipeline (a struct
 // holding them ended up in scratch memory).
 //
 // f32 rows: st[q * V + v] is sample lane + 64 v of row q.
-// Interface shared with the linear 16-bit sums: input and output element types, rows per wave,
-// tile, words per (batch, wave), the batch's inputs n (and the 16-bit dword-phase counts) as
-// per-batch scalars.
+// Interface shared with the linear 16-bit sums: output element types, words per (batch, wave),
+// the batch's inputs n (and the 16-bit dword-phase counts) as per-batch scalars; each policy
+// sets its rows per wave and tile.
 struct LinBase {
     using A = float;
     using TO = float;
-    static constexpr int kRows = R, kStep = kLinTile, kWords = kLinWords, kSmemWords = kLinSmemWords;
+    static constexpr int kWords = kLinWords, kSmemWords = kLinSmemWords;
     struct Carry {
         int n;
         uint32_t even;
@@ -59,7 +57,8 @@ struct LinBase {
 
 struct LinF32 : LinBase {
     using TI = float;
-    static constexpr int V = kLinTile / 64;
+    static constexpr int R = lin_rows(SND_DT_F32), kRows = R, kStep = lin_tile(SND_DT_F32);
+    static constexpr int V = kStep / 64;
     static constexpr int kState = R * V;
 
     // the n inputs of every row of the wave from the batch at buf; the lane's offset word at w
@@ -106,7 +105,8 @@ struct LinF32 : LinBase {
 template <bool F16>
 struct Lin16 : LinBase {
     using TI = uint16_t;
-    static constexpr int V = kLinTile / 128;
+    static constexpr int R = lin_rows(SND_DT_BF16), kRows = R, kStep = lin_tile(SND_DT_BF16);
+    static constexpr int V = kStep / 128;
     static constexpr int LO = 0, HI = R * V, kState = 2 * R * V;
 
     static __device__ inline float lower(uint32_t d)

@@ -166,9 +166,9 @@ bool build_group_lds(const PlanImpl &p, Stage &S, int variant)
                      : bits ? kGroupTileBits
                      : f1   ? kGroupTileFast
                             : kGroupTile;
-    const int tile_step = lin ? kLinTile : pack ? pack_tile(f1, S.depth) : tile;
-    const int rpw = lin ? kLinRows : pack ? pack_rows(f1, S.depth) : f1 ? kFastRows : 1;  // rows per wave
-    const int max_entries = lin ? kLinMaxBatchEntries : kPackMaxBatchEntries;  // table kernels
+    const int tile_step = lin ? lin_tile(S.src_dtype) : pack ? pack_tile(f1, S.depth) : tile;
+    const int rpw = lin ? lin_rows(S.src_dtype) : pack ? pack_rows(f1, S.depth) : f1 ? kFastRows : 1;  // rows per wave
+    const int max_entries = lin ? lin_max_batch_entries(S.src_dtype) : kPackMaxBatchEntries;  // table kernels
     const int n_words = lin ? kLinWords : kPackWords;
     const int n_smem = lin ? kLinSmemWords : kPackSmemWords;
     const int gr = kGroupRows * rpw;     // rows per group
@@ -310,7 +310,9 @@ bool build_group_lds(const PlanImpl &p, Stage &S, int variant)
         instrs.insert(instrs.end(), {srow, lo - head, (int32_t)((int64_t)(lofs - head) * eb / 8), head + span});
     }
     std::vector<uint32_t> lin_tab, lin_smem;
-    static_assert(kLinMaxBatchEntries <= 15, "per-row input counts are packed in 4 bits");
+    static_assert(lin_max_batch_entries(SND_DT_F32) <= 15 && lin_max_batch_entries(SND_DT_BF16) <= 15 &&
+                      lin_rows(SND_DT_BF16) * 4 <= 32,
+                  "per-row input counts are packed in 4 bits, one word per wave");
     static_assert(kPackMaxBatchEntries / 4 <= 16 && kPackRowsMax <= 4, "packed kernel: two closes words, 16-byte words");
     if (tab) {
         // per (batch, wave) the offset words of the wave's rows, and its copy chunks as scalar words
@@ -341,7 +343,7 @@ bool build_group_lds(const PlanImpl &p, Stage &S, int variant)
                         continue;
                     }
                     uint32_t even = 0;  // 16-bit rows: inputs starting a dword first, counts per row
-                    for (int q = 0; q < kLinRows; ++q) {
+                    for (int q = 0; q < rpw; ++q) {
                         const int32_t r = grp_rows[(size_t)(g * gr + w * rpw + q)];
                         int k = 0;
                         for (int ph = 0; ph < (eb == 16 ? 2 : 1); ++ph) {

@@ -108,17 +108,19 @@ constexpr int kGroupTileFast = 64 * kFastV;
 constexpr int kFastBuffers = 2;           // batch b + 1 lands while b is read
 constexpr int kGroupFastLdsBytes = 81920; // per buffer (two fill the 160 KB of LDS)
 constexpr int kGroupTileBits = 2048;  // bit rows: 32 samples (one word) per lane
-// Linear kernel: each wave sums kLinRows DM rows (64 DM-adjacent rows per workgroup share the
-// staged windows) over tiles of 1024 samples: f32 rows, lane i owns samples i + 64 v
-// (v = 0 .. 15); 16-bit rows, lane i owns the sample pairs 2 i + 128 v (v = 0 .. 7), and an input
-// that starts in the upper half of a dword reads one dword past the tile, so those windows
-// stage one 16-byte unit more.
-constexpr int kLinRows = 4;
-constexpr int kLinTile = 1024;                 // output samples per workgroup tile
-inline int lin_cover(int src_dtype) { return src_dtype == SND_DT_F32 ? kLinTile : kLinTile + 8; }
+// Linear kernel shape per row storage.  f32 rows: eight DM rows per wave (128 DM-adjacent rows
+// per workgroup share the staged windows) over tiles of 512 samples, lane i owning samples
+// i + 64 v (v = 0 .. 7).  16-bit rows: four rows per wave (64-row groups) over tiles of 1024
+// samples, lane i owning the sample pairs 2 i + 128 v (v = 0 .. 7); an input that starts in the
+// upper half of a dword reads one dword past the tile, so those windows stage one 16-byte unit
+// more.  (The 16-bit sums are bound by instruction issue, which the longer tile eases; f32 rows
+// are bound by LDS reads, and the larger groups stage fewer bytes per output.)
+constexpr int lin_rows(int src_dtype) { return src_dtype == SND_DT_F32 ? 8 : 4; }
+constexpr int lin_tile(int src_dtype) { return src_dtype == SND_DT_F32 ? 512 : 1024; }
+inline int lin_cover(int src_dtype) { return src_dtype == SND_DT_F32 ? lin_tile(src_dtype) : lin_tile(src_dtype) + 8; }
 // inputs per row and batch: the wave's offset words fit 64 lanes, and the 16-bit kernels pack
 // each row's count of inputs of one dword phase in 4 bits
-constexpr int kLinMaxBatchEntries = 64 / kLinRows < 15 ? 64 / kLinRows : 15;
+constexpr int lin_max_batch_entries(int src_dtype) { return 64 / lin_rows(src_dtype) < 15 ? 64 / lin_rows(src_dtype) : 15; }
 constexpr int kLinWords = 64;                  // offset words per (batch, wave)
 constexpr int kLinMaxChunks = 7;               // copy chunks per (batch, wave)
 constexpr int kLinSmemWords = 24;              // chunk count, 7 units, 7 LDS offsets, 7 lengths, counts, n
