@@ -195,10 +195,17 @@ __global__ __launch_bounds__(64 * kAnchorWaves) void k_anchored(AnchorArgs s0, M
         if constexpr (MAXD == 1 && !std::is_same<TO, bits_t>::value) if (ee - eb == (uint32_t)EU) {
             // one-level rows of EU inputs (the leaf level of clusters of four channels): table
             // words once per row, stores without per-sample tests inside the row
+            // rows of 1- or 2-byte elements: lane i owns the PK consecutive samples PK i + j
+            // + 64 PK w (j < PK) of a sub-tile, so that each store writes a whole dword
+            constexpr int PK = sizeof(TO) < 4 ? 4 / (int)sizeof(TO) : 1;
+            static_assert(V % PK == 0, "whole dwords per lane");
             const TI *p[EU];
 #pragma unroll
             for (int u = 0; u < EU; ++u)
-                p[u] = lds - lo + lane + ((int)(ent[2 * (eb + u)] & kRowMask) - c0) * wst + (int32_t)ent[2 * (eb + u) + 1];
+                p[u] = lds - lo + PK * lane + ((int)(ent[2 * (eb + u)] & kRowMask) - c0) * wst +
+                       (int32_t)ent[2 * (eb + u) + 1];
+            // sample slot v of the lane: offset PK lane + off(v) in the sub-tile
+            auto off = [](int v) { return (v % PK) + 64 * PK * (v / PK); };
             for (int sub = 0; sub < T; sub += ST) {
                 const int i0 = tau0 + sub - lo;  // output index at the sub-tile start
                 if (i0 >= len || i0 + ST <= 0) continue;
@@ -207,7 +214,7 @@ __global__ __launch_bounds__(64 * kAnchorWaves) void k_anchored(AnchorArgs s0, M
                 for (int u = 0; u < EU; ++u)
 #pragma unroll
                     for (int v = 0; v < V; ++v) {
-                        A y = (A)Load<TI>::get(p[u] + sub + 64 * v);
+                        A y = (A)Load<TI>::get(p[u] + sub + off(v));
                         if constexpr (MODE == SND_MODE_BINARY) y = y != 0;
                         val[u][v] = y;
                     }
@@ -220,19 +227,33 @@ __global__ __launch_bounds__(64 * kAnchorWaves) void k_anchored(AnchorArgs s0, M
                     out[v] = activate<MODE>(a, 1, 1, s.k_leaf, s.k_int, s.cap);
                     if constexpr (kBound) vmax = max(vmax, (uint32_t)out[v]);
                 }
-                const auto dst = as_global(static_cast<TO *>(s.dst)) + (int64_t)r * s.dst_pitch + i0 + lane;
+                const auto dst = as_global(static_cast<TO *>(s.dst)) + (int64_t)r * s.dst_pitch + i0 + PK * lane;
                 if constexpr (MODE == SND_MODE_FLOAT) {
 #pragma unroll
                     for (int v = 0; v < V; ++v) out[v] *= s.scale;
                 }
-                if (i0 >= 0 && i0 + ST <= len) {  // uniform: the whole sub-tile is inside the row
+                // uniform: the whole sub-tile is inside the row (and, for packed stores, starts
+                // on a dword)
+                if (i0 >= 0 && i0 + ST <= len && (PK == 1 || ((uintptr_t)(dst - PK * lane) & 3u) == 0)) {
+                    if constexpr (PK == 1) {
 #pragma unroll
-                    for (int v = 0; v < V; ++v) Store<TO>::put(dst + 64 * v, out[v]);
+                        for (int v = 0; v < V; ++v) Store<TO>::put(dst + 64 * v, out[v]);
+                    } else {
+                        auto d32 = reinterpret_cast<global_ptr<uint32_t>>(dst);
+#pragma unroll
+                        for (int w = 0; w < V / PK; ++w) {
+                            uint32_t word = 0;
+#pragma unroll
+                            for (int j = 0; j < PK; ++j)
+                                word |= store_bits<TO>(out[PK * w + j]) << (8 * (int)sizeof(TO) * j);
+                            d32[64 * w] = word;  // samples 64 PK w + PK lane .. + PK - 1
+                        }
+                    }
                 } else {
 #pragma unroll
                     for (int v = 0; v < V; ++v) {
-                        const int i = i0 + lane + 64 * v;
-                        if (i >= 0 && i < len) Store<TO>::put(dst + 64 * v, out[v]);
+                        const int i = i0 + PK * lane + off(v);
+                        if (i >= 0 && i < len) Store<TO>::put(dst + off(v), out[v]);
                     }
                 }
             }

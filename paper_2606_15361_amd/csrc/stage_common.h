@@ -66,6 +66,16 @@ template <> struct Store<f16_t> {
     template <typename P, typename A> __device__ static void put(P p, A v) { p->v = (_Float16)(float)v; }
 };
 
+// The storage bits of one element as Store<T>::put writes them, for packed stores.
+template <typename T, typename A> __device__ inline uint32_t store_bits(A v);
+template <> __device__ inline uint32_t store_bits<uint8_t, int>(int v) { return (uint32_t)(uint8_t)v; }
+template <> __device__ inline uint32_t store_bits<uint16_t, int>(int v) { return (uint32_t)(uint16_t)v; }
+template <> __device__ inline uint32_t store_bits<bf16_t, float>(float v) { return f32_to_bf16_rne(v); }
+template <> __device__ inline uint32_t store_bits<f16_t, float>(float v)
+{
+    return (uint32_t)__builtin_bit_cast(uint16_t, (_Float16)v);
+}
+
 template <int MODE> struct Acc { using type = int; };
 template <> struct Acc<SND_MODE_FLOAT> { using type = float; };
 
